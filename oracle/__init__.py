@@ -1,0 +1,25 @@
+"""CPU FP64 oracle for the adaptive Hessian-sketch ridge solver.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously correct
+restatement of what the paper (Lacotte & Pilanci, "Effective Dimension Adaptive
+Sketching Methods for Faster Regularized Least-Squares Optimization", NeurIPS
+2020) computes.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it.  The GPU library never
+routes through it, and it shares no code with the GPU library.
+
+Modules
+-------
+philox  : Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
+          stream map used to draw the sketches' randomness.
+sketch  : SRHT (dense Walsh-Hadamard, no fast transform) and Gaussian embeddings
+          (Section 1; Appendix C.2 "SRHT matrices").
+ridge   : the problem (eq. EqnMain), its direct solution, gradient, error metric
+          and effective dimension (Section 1.1 "Notations").
+ihs     : algorithmic parameters (Theorems 1-2, Definitions 3.1-3.2), the
+          sketched Hessian and its Woodbury inverse (proof of Theorem 7), the
+          sketched Newton decrement (Lemma 1) and Algorithm 1.
+mlp     : FP64 reference of the small MLP used by the learned starting-m form.
+
+Parity status: every function is pinned by a ``-m "not gpu"`` test except those
+whose docstring says "parity unpinned".
+"""

@@ -1,0 +1,12 @@
+"""Seeded synthetic ridge problems shared by the tests, the smoke run and the bench.
+
+This module holds no arithmetic of the solver: it only draws inputs.  Shapes and
+spectra follow the paper's synthetic experiments (Appendix A.1: exponential and
+polynomial singular-value decays): A = G diag(sigma) V^T with G i.i.d.
+N(0, 1/n) and V Haar-distributed, b = A x_pl + c * xi.
+"""
+from .problems import (Problem, make_problem, spectrum, config_c1, config_c2,
+                       make_problem_torch)
+
+__all__ = ["Problem", "make_problem", "spectrum", "config_c1", "config_c2",
+           "make_problem_torch"]

@@ -1,0 +1,97 @@
+"""Generators for A = G diag(sigma) V^T and b = A x_pl + c xi.
+
+numpy (PCG64) on the host for problems that fit comfortably in host memory;
+torch on a device for the multi-GiB ones.  V is Haar: the Q factor of a Gaussian
+matrix with the signs of diag(R) folded in (F. Mezzadri, "How to generate random
+matrices from the classical compact groups", Notices AMS 2007).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    A: np.ndarray          # (n, d), row-major
+    b: np.ndarray          # (n,)
+    x_pl: np.ndarray       # planted vector
+    sigma: np.ndarray      # nominal singular values
+    nu2: float
+    name: str = ""
+
+
+def spectrum(kind, d, rate=None):
+    """Nominal singular values.
+
+    kind: "geom"  sigma_i = rate^i,        i = 0..d-1
+          "poly"  sigma_i = i^-rate,       i = 1..d
+          "exp"   sigma_i = exp(-i/rate),  i = 1..d
+    """
+    if kind == "geom":
+        return rate ** np.arange(d, dtype=np.float64)
+    if kind == "poly":
+        return np.arange(1, d + 1, dtype=np.float64) ** (-rate)
+    if kind == "exp":
+        return np.exp(-np.arange(1, d + 1, dtype=np.float64) / rate)
+    raise ValueError(kind)
+
+
+def haar_orthogonal(rng, d):
+    Z = rng.standard_normal((d, d))
+    Q, R = np.linalg.qr(Z)
+    return Q * np.sign(np.diag(R))[None, :]
+
+
+def make_problem(n, d, sigma, nu2, noise, seed, dtype=np.float32, name="",
+                 planted_scale=1.0):
+    """A = G diag(sigma) V^T, G ~ N(0, 1/n); b = A x_pl + noise * xi."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, d)) / np.sqrt(n)
+    V = haar_orthogonal(rng, d)
+    A64 = (G * sigma[None, :]) @ V.T
+    x_pl = rng.standard_normal(d) * planted_scale
+    xi = rng.standard_normal(n)
+    A = np.ascontiguousarray(A64.astype(dtype))
+    b64 = A.astype(np.float64) @ x_pl + noise * xi
+    b = b64.astype(dtype)
+    return Problem(A=A, b=b, x_pl=x_pl, sigma=sigma, nu2=float(nu2), name=name)
+
+
+def config_c1(seed=0):
+    """1024 x 64 FP64, sigma_i = 0.9^i (i = 0..63), nu^2 = 1e-2, noise 0.01."""
+    return make_problem(1024, 64, spectrum("geom", 64, 0.9), 1e-2, 0.01, seed,
+                        dtype=np.float64, name="c1_1024x64_f64")
+
+
+def config_c2(nu2=1e-2, seed=0, n=65536, d=1024):
+    """65536 x 1024 FP32, sigma_i = 1/i, noise 0.1; nu^2 in {1e-2, 1e-4}."""
+    return make_problem(n, d, spectrum("poly", d, 1.0), nu2, 0.1, seed,
+                        dtype=np.float32, name=f"c2_{n}x{d}_f32_nu2_{nu2:g}")
+
+
+def make_problem_torch(n, d, sigma, noise, seed, device, dtype=None, row_block=1 << 16):
+    """Device-side generator for large problems (returns torch tensors A, b).
+
+    G is drawn in row blocks with a seeded torch generator on ``device``.
+    """
+    import torch
+    dtype = dtype or torch.float32
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    Z = torch.randn(d, d, generator=gen, device=device, dtype=torch.float64)
+    Q, R = torch.linalg.qr(Z)
+    V = Q * torch.sign(torch.diagonal(R))[None, :]
+    sig = torch.as_tensor(sigma, device=device, dtype=torch.float64)
+    M = (sig[:, None] * V.T).to(torch.float32)            # diag(sigma) V^T
+    x_pl = torch.randn(d, generator=gen, device=device, dtype=torch.float64)
+    A = torch.empty(n, d, device=device, dtype=dtype)
+    b = torch.empty(n, device=device, dtype=dtype)
+    for r0 in range(0, n, row_block):
+        r1 = min(n, r0 + row_block)
+        G = torch.randn(r1 - r0, d, generator=gen, device=device, dtype=torch.float32)
+        G.mul_(1.0 / np.sqrt(n))
+        blk = (G @ M).to(dtype)
+        A[r0:r1] = blk
+        xi = torch.randn(r1 - r0, generator=gen, device=device, dtype=torch.float64)
+        b[r0:r1] = (blk.to(torch.float64) @ x_pl + noise * xi).to(dtype)
+    return A, b, x_pl
