@@ -1,0 +1,243 @@
+/*
+ * rs.h -- C ABI of librs, the MI355X (gfx950) adaptive Hessian-sketch ridge solver.
+ *
+ * Problem (Lacotte & Pilanci, NeurIPS 2020, eq. EqnMain):
+ *     x* = argmin_x  1/2 ||A x - b||^2 + nu^2/2 ||x||^2,   A is n x d, n >= d.
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller unless a comment
+ *     says "host".  The library never frees caller memory.
+ *   - Matrices are row-major with an explicit leading dimension (elements).
+ *     A (n x d) has lda >= d; lda must be a multiple of 16/sizeof(element) and A
+ *     16-byte aligned (vector loads).  Sizes are int64_t.
+ *   - Vectors of the iteration (x, g, g~) are FP64.  A k-column block of vectors
+ *     ("k RHS") is stored column after column: V[c*d + i].
+ *   - All work is enqueued on the given stream.  Functions that return host
+ *     values synchronize that stream first; the others do not.
+ *   - Every argument is validated before any launch; errors come back as
+ *     rs_status and rs_last_error() returns a thread-local message.  No C++
+ *     exception crosses the ABI.
+ *   - Internal scratch (histograms, transform intermediates, partial sums) is
+ *     owned by the library, allocated once per device and grown on demand.
+ *     Calls that overlap on one device (e.g. from two host threads or two
+ *     streams) race on it: serialize them.
+ */
+#ifndef RS_H_
+#define RS_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RS_OK = 0,
+  RS_ERR_ARG = 1,             /* null pointer, bad enum, bad alignment/leading dimension */
+  RS_ERR_SHAPE = 2,           /* n < d, m < 1, m > padded n, unsupported size */
+  RS_ERR_NOT_POW2 = 3,        /* reserved: non power-of-two sizes are zero-padded */
+  RS_ERR_NOT_SPD = 4,         /* a Cholesky pivot was not positive (e.g. nu^2 <= 0) */
+  RS_ERR_NONFINITE = 5,       /* NaN or Inf met in the iteration */
+  RS_ERR_NO_CONVERGENCE = 6,  /* tolerance not met within max_iter, or stuck at m_max */
+  RS_ERR_OOM = 7,
+  RS_ERR_HIP = 8,             /* a HIP runtime call failed */
+  RS_ERR_UNSUPPORTED = 9      /* valid request outside what this build implements */
+} rs_status;
+
+typedef enum { RS_F64 = 0, RS_F32 = 1, RS_BF16 = 2, RS_FP8E4M3 = 3 } rs_dtype;
+typedef enum { RS_SKETCH_SRHT = 0, RS_SKETCH_GAUSSIAN = 1 } rs_sketch_kind;
+/* FRESH: each doubling draws a new sketch (Algorithm 1 samples S afresh).
+ * NESTED: keeps the signs and row keys; the 2m rows include the previous m. */
+typedef enum { RS_RESAMPLE_FRESH = 0, RS_RESAMPLE_NESTED = 1 } rs_resample;
+/* POLYAK: Algorithm 1.  GD_ONLY: its gradient-only variant (Section 4). */
+typedef enum { RS_VARIANT_POLYAK = 0, RS_VARIANT_GD_ONLY = 1 } rs_variant;
+
+/* Step sizes and target rates of Algorithm 1. */
+typedef struct {
+  double mu_gd, mu_p, beta_p, cbar_gd, cbar_p;
+} rs_ihs_params;
+
+/* Parameters from Definition 3.2 (SRHT: lambda, Lambda = 1 -+ sqrt(rho), rho in (0,1))
+ * or Definition 3.1 (Gaussian: (1 -+ sqrt(c_eta rho))^2, c_eta = (1+3 sqrt(eta))^2,
+ * rho in (0, 0.18], eta in (0, 0.01]) plugged into Theorem 1 (mu_gd, cbar_gd) and
+ * Theorem 2 (mu_p, beta_p, cbar_p).  out: host.  RS_ERR_ARG outside the domains. */
+rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* out);
+
+/* ------------------------------------------------------------------ sketches */
+
+/* SRHT embedding (Appendix C.2): SA = (1/sqrt(m)) R H diag(eps) A, with H the
+ * Sylvester-ordered Walsh-Hadamard matrix of order npad = 2^ceil(log2 n)
+ * (entries +-1; rows of A past n count as zero), eps Rademacher signs and R the
+ * m rows with the smallest Philox4x32-10 keys, drawn without replacement
+ * (Theorem 10's sampling rule).  Randomness: key (seed), counter
+ * (row, 0, stream, sketch_id) with stream 4 = signs (eps_i = 1 - 2 (w0 & 1)) and
+ * stream 5 = row keys (w1 * 2^32 + w0; ties broken by row index).
+ *   A    : n x d, dtype a_t in {F64, F32}, leading dimension lda.
+ *   m    : 1 <= m <= npad; npad <= 2^20.
+ *   SA   : m x d output, dtype sa_t (F64 only with F64 A; F32; BF16; FP8E4M3),
+ *          leading dimension ldsa >= d.  Row k is sampled row rows[k]; rows are
+ *          in ascending order.
+ *   sa_col_scale : FP8 only (d floats, else NULL): SA = fp8 value * scale[j],
+ *          per column, a power of two chosen from the column's max.
+ *   rows_out  : NULL or m int64 (ascending sampled rows).
+ *   signs_out : NULL or npad int8 (+-1).
+ * Asynchronous. */
+rs_status rs_sketch_srht(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                         int64_t m, uint64_t seed, uint32_t sketch_id,
+                         void* SA, rs_dtype sa_t, int64_t ldsa, float* sa_col_scale,
+                         int64_t* rows_out, int8_t* signs_out, hipStream_t stream);
+
+/* Gaussian embedding (Section 1): SA = S A with S[k][j] = z_{k n + j} / sqrt(m),
+ * z standard normal by Box-Muller from Philox4x32-10 counter (k n + j, stream 6,
+ * sketch_id):  F64 path: u1 = ((w0>>6) 2^26 + (w1>>6) + 1/2) 2^-52, u2 likewise
+ * from (w2, w3); F32 path: u1 = ((w0>>9) + 1/2) 2^-23, u2 = ((w1>>9) + 1/2) 2^-23;
+ * z = sqrt(-2 ln u1) cos(2 pi u2).  S is generated tile by tile and never stored.
+ *   m: 1 <= m <= n.  Other arguments as for rs_sketch_srht.  Asynchronous. */
+rs_status rs_sketch_gaussian(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                             int64_t m, uint64_t seed, uint32_t sketch_id,
+                             void* SA, rs_dtype sa_t, int64_t ldsa, float* sa_col_scale,
+                             hipStream_t stream);
+
+/* ------------------------------------------------------------------ factor */
+
+typedef struct rs_factor rs_factor;
+
+/* Factor the sketched Hessian H_S = (SA)^T SA + nu^2 I (eq. EqnApproximateHessian)
+ * for repeated solves.  m < d: Woodbury identity through the m x m matrix
+ * nu^2 I_m + SA SA^T (proof of Theorem 7); m >= d: the d x d matrix itself.  The
+ * Gram is accumulated in FP32 (FP64 for F64 SA) on the matrix cores, the
+ * Cholesky factor and its triangular inverse are FP64.
+ *   SA    : m x d device array (borrowed: it must stay valid and unchanged while
+ *           *out is used; the Woodbury branch reads it on every apply).
+ *   nu2   : > 0.
+ *   out   : host pointer receiving a handle; release with rs_factor_destroy.
+ * Synchronizes the stream (checks the pivots); RS_ERR_NOT_SPD on a failed pivot. */
+rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_scale,
+                             int64_t m, int64_t d, int64_t ldsa, double nu2,
+                             rs_factor** out, hipStream_t stream);
+
+/* gtilde = H_S^-1 g for k right-hand sides, and r[c] = 1/2 g_c^T gtilde_c (the
+ * sketched Newton decrement of Lemma 1).  g, gtilde: d x k FP64 (column after
+ * column); r: k FP64 on the device.  All accumulation in FP64.  Asynchronous. */
+rs_status rs_factor_apply(const rs_factor* F, const double* g, double* gtilde, double* r,
+                          int64_t k, hipStream_t stream);
+
+void rs_factor_destroy(rs_factor* F);
+
+/* ------------------------------------------------------------------ gradient */
+
+/* G = A^T (A X - b) + nu^2 X for k right-hand sides (from eq. EqnMain), in one
+ * read of A.  X, G: d x k FP64; b: n entries of A's dtype.  Row residuals are
+ * formed in A's precision; the A^T r sums are accumulated in FP64 (FP32 over
+ * groups of at most 8 rows for FP32 A).  k in 1..4.  Asynchronous. */
+rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                      const void* b, double nu2, const double* X, int64_t k, double* G,
+                      hipStream_t stream);
+
+/* ------------------------------------------------------------------ iteration */
+
+typedef struct {
+  double* x;        /* device, d: x_t                                   */
+  double* x_prev;   /* device, d: x_{t-1}                               */
+  double* g;        /* device, d: grad f(x_t)                           */
+  double* gtilde;   /* device, d: H_S^-1 g_t                            */
+  double r_t;       /* host: 1/2 g_t^T gtilde_t                         */
+  double r_1;       /* host: r at the first iterate                     */
+  int64_t t;        /* host: step index, starting at 1                  */
+} rs_ihs_state;
+
+typedef struct {
+  int32_t accepted; /* 0: Polyak candidate, 1: gradient candidate, -1: both rejected */
+  double r_p;       /* decrement at the Polyak candidate (NaN for GD_ONLY) */
+  double r_gd;      /* decrement at the gradient candidate */
+} rs_step_result;
+
+/* One step of Algorithm 1 under a fixed factor: candidates
+ * x_p = x_t - mu_p g~_t + beta_p (x_t - x_{t-1}) and x_gd = x_t - mu_gd g~_t, their
+ * gradients in one pass over A, their decrements, then the tests
+ * (r_p / r_1)^(1/t) <= cbar_p, else r_gd / r_t <= cbar_gd (ties accept).  On
+ * acceptance the state moves to the accepted candidate (t += 1); when both are
+ * rejected the state is left unchanged and the caller is expected to double m,
+ * refactor and recompute gtilde_t and r_t.  Synchronizes the stream. */
+rs_status rs_ihs_step(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                      const void* b, double nu2, const rs_factor* F, const rs_ihs_params* p,
+                      rs_variant variant, rs_ihs_state* st, rs_step_result* out,
+                      hipStream_t stream);
+
+/* ------------------------------------------------------------------ solver */
+
+#define RS_MAX_EVENTS 512
+
+typedef struct {
+  rs_sketch_kind kind;       /* default SRHT */
+  rs_variant variant;        /* default POLYAK */
+  rs_resample resample;      /* default FRESH */
+  rs_dtype sketch_dtype;     /* storage of SA: F64 (F64 A only), F32, BF16, FP8E4M3 */
+  double rho;                /* default 0.1 */
+  double eta;                /* default 0.01 (Gaussian only) */
+  int64_t m_init;            /* default 1 */
+  int64_t m_max;             /* 0: padded n (SRHT) or n (Gaussian) */
+  double tol;                /* stop when r_t <= tol * r_ref; default 1e-7 */
+  int64_t max_iter;          /* cap on accepted steps; default 200 */
+  uint64_t seed;
+  int32_t check_every;       /* steps queued between host reads of the device state; default 4 */
+  int32_t reserved;
+} rs_solve_opts;
+
+/* Event kinds recorded in rs_solve_info. */
+#define RS_EVENT_POLYAK 0
+#define RS_EVENT_GD 1
+#define RS_EVENT_DOUBLE 2
+
+typedef struct {
+  rs_status status;
+  int32_t reserved;
+  int64_t m_final, doublings, steps, grad_passes, applies;
+  int64_t accepted_polyak, accepted_gd;
+  double r_final, r_ref;
+  int64_t n_events;                     /* min(#events, RS_MAX_EVENTS) */
+  int32_t event_kind[RS_MAX_EVENTS];    /* RS_EVENT_* in order */
+  int32_t event_t[RS_MAX_EVENTS];       /* step index t of each event */
+  int64_t event_m[RS_MAX_EVENTS];       /* sketch size after the event */
+  double ms_sketch, ms_factor, ms_iterate; /* host-timed phases (0 unless timing enabled) */
+} rs_solve_info;
+
+/* Fill opts with the defaults listed above. */
+void rs_solve_opts_default(rs_solve_opts* opts);
+
+/* Algorithm 1 end to end (Section 3 and the readings in the design notes):
+ * start at m = m_init, double m and resample whenever both candidates fail their
+ * tests, stop at r_t <= tol * r_ref with r_ref = 1/2 g_1^T H_S^-1 g_1 under the
+ * current sketch.  The step control runs on the device; the host reads a small
+ * state record every check_every steps and performs the resamplings.
+ *   A, b   : problem (F64 or F32); nu2 > 0.
+ *   x      : device, d FP64: in = initial point x_1 (= x_0), out = solution.
+ *   info   : host.
+ * Synchronizes the stream.  Returns RS_OK, RS_ERR_NO_CONVERGENCE (x holds the
+ * last iterate) or an error. */
+rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                            const void* b, double nu2, const rs_solve_opts* opts,
+                            double* x, rs_solve_info* info, hipStream_t stream);
+
+/* ------------------------------------------------------------------ timing */
+
+/* Diagnostics for measuring the dominant kernel (not part of the method).
+ * While enabled, every launch of the gradient's partial-sum kernel (the pass
+ * over A) is bracketed by two HIP events recorded on the stream it is launched
+ * on.  rs_profile_read synchronizes those events, returns the number of
+ * bracketed launches and their summed duration in milliseconds (host
+ * pointers), and clears the record.  Not thread-safe. */
+rs_status rs_profile_enable(int on);
+rs_status rs_profile_read(int64_t* launches, double* total_ms);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* rs_last_error(void);
+
+/* Library version string. */
+const char* rs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RS_H_ */

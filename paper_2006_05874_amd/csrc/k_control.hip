@@ -1,0 +1,235 @@
+// Step control of Algorithm 1 on the device.
+//
+// One step = candidates -> gradient (one pass over A for both candidates) ->
+// apply -> decide.  The decision kernel applies the two ratio tests in FP64,
+// moves the state to the accepted candidate, records the event, and raises a
+// status flag (converged / double m / stuck / step cap / non-finite) that makes
+// every later kernel of the queued steps return at once.  The host therefore
+// queues several steps, reads the small control record, and only intervenes to
+// resample.
+#include "rs_internal.hpp"
+
+namespace rs {
+
+// X[0] = x - mu_p gt + beta_p (x - x_prev), X[K-1] = x - mu_gd gt (K = 2);
+// K = 1 (gradient-only): X[0] = x - mu_gd gt.
+template <int K>
+__global__ __launch_bounds__(256) void k_candidates(int64_t d, const double* __restrict__ x,
+                                                    const double* __restrict__ x_prev,
+                                                    const double* __restrict__ gt,
+                                                    double* __restrict__ X, double mu_p,
+                                                    double beta_p, double mu_gd,
+                                                    const int* __restrict__ status) {
+  if (status && *status != 0) return;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
+    const double xi = x[i], gi = gt[i];
+    if (K == 2) {
+      X[i] = xi - mu_p * gi + beta_p * (xi - x_prev[i]);
+      X[d + i] = xi - mu_gd * gi;
+    } else {
+      X[i] = xi - mu_gd * gi;
+    }
+  }
+}
+
+struct DecideArgs {
+  double mu_p, beta_p, mu_gd, cbar_p, cbar_gd, tol;
+  int64_t max_iter;
+  int32_t polyak;  // variant has a Polyak candidate (K = 2)
+};
+
+// Single block.  rpart: nrp x K partial sums of g^T gtilde.
+template <int K>
+__global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
+                                                 const double* __restrict__ rpart, int nrp,
+                                                 DecideArgs a, int64_t d,
+                                                 const double* __restrict__ X,
+                                                 const double* __restrict__ G,
+                                                 const double* __restrict__ GT,
+                                                 double* __restrict__ x, double* __restrict__ x_prev,
+                                                 double* __restrict__ g, double* __restrict__ gt,
+                                                 int32_t* __restrict__ ev_kind, int ev_cap) {
+  __shared__ double r[K];
+  __shared__ int chosen;
+  if (ctl->status != RS_CTL_RUNNING) return;
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int b = 0; b < nrp; ++b) s += rpart[(int64_t)b * K + threadIdx.x];
+    r[threadIdx.x] = 0.5 * s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = -1;
+    int st = RS_CTL_RUNNING;
+    const double rt = ctl->r_t, r1 = ctl->r_1;
+    const int64_t t = ctl->t;
+    bool finite = true;
+    for (int i = 0; i < K; ++i) finite = finite && isfinite(r[i]);
+    ctl->passes += 1;
+    if (!finite) {
+      st = RS_CTL_NONFINITE;
+    } else {
+      if (a.polyak) {
+        // (r_p / r_1)^(1/t) <= cbar_p
+        if (pow(r[0] / r1, 1.0 / (double)t) <= a.cbar_p) c = 0;
+      }
+      if (c < 0) {
+        const double rg = r[K - 1];
+        if (rg / rt <= a.cbar_gd) c = K - 1;
+        else if (ctl->at_cap) {
+          if (rg < rt) c = K - 1;
+          else st = RS_CTL_STUCK;
+        } else {
+          st = RS_CTL_DOUBLE;
+        }
+      }
+    }
+    if (c >= 0) {
+      const int kind = (a.polyak && c == 0) ? 0 : 1;
+      if (t < ev_cap) ev_kind[t] = kind;
+      if (kind == 0) ctl->polyak += 1; else ctl->gd += 1;
+      ctl->r_t = r[c];
+      ctl->t = t + 1;
+      ctl->steps += 1;
+      if (r[c] <= a.tol * ctl->r_ref) st = RS_CTL_CONVERGED;
+      else if (t + 1 >= a.max_iter) st = RS_CTL_MAXITER;
+    }
+    ctl->last_r[0] = r[0];
+    ctl->last_r[1] = r[K - 1];
+    ctl->status = st;
+    chosen = c;
+  }
+  __syncthreads();
+  const int c = chosen;
+  if (c < 0) return;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    const double xi = x[i];
+    x_prev[i] = xi;
+    x[i] = X[(int64_t)c * d + i];
+    g[i] = G[(int64_t)c * d + i];
+    gt[i] = GT[(int64_t)c * d + i];
+  }
+}
+
+// After the first gradient and apply: g <- G[0], gtilde <- GT[0], g_ref <- G[0],
+// x_prev <- x, r_t = r_1 = r_ref = r.
+__global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
+                                                     const double* __restrict__ rpart, int nrp,
+                                                     double tol, int64_t max_iter, int64_t d,
+                                                     const double* __restrict__ G,
+                                                     const double* __restrict__ GT,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ x_prev,
+                                                     double* __restrict__ g,
+                                                     double* __restrict__ gt,
+                                                     double* __restrict__ gref, int at_cap) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nrp; ++b) s += rpart[b];
+    const double r = 0.5 * s;
+    ctl->r_t = r;
+    ctl->r_1 = r;
+    ctl->r_ref = r;
+    ctl->t = 1;
+    ctl->steps = 0;
+    ctl->passes = 1;
+    ctl->polyak = 0;
+    ctl->gd = 0;
+    ctl->at_cap = at_cap;
+    int st = RS_CTL_RUNNING;
+    if (!isfinite(r)) st = RS_CTL_NONFINITE;
+    else if (r <= tol * r) st = RS_CTL_CONVERGED;
+    else if (1 >= max_iter) st = RS_CTL_MAXITER;
+    ctl->status = st;
+  }
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    x_prev[i] = x[i];
+    g[i] = G[i];
+    gref[i] = G[i];
+    gt[i] = GT[i];
+  }
+}
+
+// After a resample: apply was run on [g_t, g_ref] -> GT; rpart holds 2 sums.
+__global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl,
+                                                        const double* __restrict__ rpart, int nrp,
+                                                        double tol, int64_t d,
+                                                        const double* __restrict__ GT,
+                                                        double* __restrict__ gt, int at_cap) {
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = 0; b < nrp; ++b) {
+      s0 += rpart[(int64_t)b * 2];
+      s1 += rpart[(int64_t)b * 2 + 1];
+    }
+    ctl->r_t = 0.5 * s0;
+    ctl->r_ref = 0.5 * s1;
+    ctl->at_cap = at_cap;
+    int st = RS_CTL_RUNNING;
+    if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;
+    else if (ctl->r_t <= tol * ctl->r_ref) st = RS_CTL_CONVERGED;
+    ctl->status = st;
+  }
+  for (int64_t i = threadIdx.x; i < d; i += 1024) gt[i] = GT[i];
+}
+
+// Copy two vectors into a 2-column block (for the post-resample apply).
+__global__ __launch_bounds__(256) void k_pack2(int64_t d, const double* __restrict__ a,
+                                               const double* __restrict__ b,
+                                               double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
+    out[i] = a[i];
+    out[d + i] = b[i];
+  }
+}
+
+static unsigned vec_grid(int64_t d) { return (unsigned)std::min<int64_t>((d + 255) / 256, 1024); }
+
+rs_status candidates_launch(int K, int64_t d, const double* x, const double* x_prev,
+                            const double* gt, double* X, double mu_p, double beta_p, double mu_gd,
+                            const int* status, hipStream_t s) {
+  if (K == 2)
+    hipLaunchKernelGGL(k_candidates<2>, dim3(vec_grid(d)), dim3(256), 0, s, d, x, x_prev, gt, X,
+                       mu_p, beta_p, mu_gd, status);
+  else
+    hipLaunchKernelGGL(k_candidates<1>, dim3(vec_grid(d)), dim3(256), 0, s, d, x, x_prev, gt, X,
+                       mu_p, beta_p, mu_gd, status);
+  return check_launch("candidates");
+}
+
+rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const CtlParams& p,
+                        int64_t d, const double* X, const double* G, const double* GT, double* x,
+                        double* x_prev, double* g, double* gt, int32_t* ev_kind, int ev_cap,
+                        hipStream_t s) {
+  DecideArgs a{p.mu_p, p.beta_p, p.mu_gd, p.cbar_p, p.cbar_gd, p.tol, p.max_iter, K == 2 ? 1 : 0};
+  if (K == 2)
+    hipLaunchKernelGGL(k_decide<2>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, a, d, X, G, GT, x,
+                       x_prev, g, gt, ev_kind, ev_cap);
+  else
+    hipLaunchKernelGGL(k_decide<1>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, a, d, X, G, GT, x,
+                       x_prev, g, gt, ev_kind, ev_cap);
+  return check_launch("decide");
+}
+
+rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
+                            int64_t max_iter, int64_t d, const double* G, const double* GT,
+                            const double* x, double* x_prev, double* g, double* gt, double* gref,
+                            int at_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, max_iter, d, G,
+                     GT, x, x_prev, g, gt, gref, at_cap);
+  return check_launch("init state");
+}
+
+rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
+                               const double* GT, double* gt, int at_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_post_resample, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, d, GT, gt,
+                     at_cap);
+  return check_launch("post resample");
+}
+
+rs_status pack2_launch(int64_t d, const double* a, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack2, dim3(vec_grid(d)), dim3(256), 0, s, d, a, b, out);
+  return check_launch("pack2");
+}
+
+}  // namespace rs

@@ -1,0 +1,124 @@
+// Gaussian embedding SA = S A, S[k][j] = z_{k n + j} / sqrt(m) (Section 1: i.i.d.
+// N(0, 1/m) entries).  S is never stored: each block draws the 64 x 16 slice of
+// S it needs from Philox4x32-10 + Box-Muller into LDS, stages the matching
+// 16 x 128 slice of A, and accumulates a 64 x 128 tile of SA on the matrix
+// cores (FP32 MFMA 16x16x4 for FP32 data, FP64 MFMA 16x16x4 for FP64 data).
+// Forming SA costs 2 m n d flops (the O(mnd) of Section 1).
+#include "rs_internal.hpp"
+
+namespace rs {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T gauss_at(uint64_t seed, uint32_t sid, uint64_t idx);
+template <>
+__device__ __forceinline__ float gauss_at<float>(uint64_t seed, uint32_t sid, uint64_t idx) {
+  return gauss_f32(seed, sid, idx);
+}
+template <>
+__device__ __forceinline__ double gauss_at<double>(uint64_t seed, uint32_t sid, uint64_t idx) {
+  return gauss_f64(seed, sid, idx);
+}
+
+template <typename T, typename OutT>
+__global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, int64_t n, int64_t d,
+                                                      int64_t lda, int64_t m, uint64_t seed,
+                                                      uint32_t sid, double scale,
+                                                      OutT* __restrict__ SA, int64_t ldsa) {
+  constexpr int TM = 64, TD = 128, KC = 16;
+  __shared__ T Ss[KC][TM + 1];  // Ss[j][k] = S[k0 + k][j0 + j]
+  __shared__ T As[KC][TD + 1];  // As[j][c] = A[j0 + j][c0 + c]
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;  // wave quadrant: 32 rows x 64 cols
+  const int64_t k0 = (int64_t)blockIdx.y * TM;
+  const int64_t c0 = (int64_t)blockIdx.x * TD;
+  using Acc4 = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+  Acc4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc4{0, 0, 0, 0};
+
+  for (int64_t j0 = 0; j0 < n; j0 += KC) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {  // S slice: 64 x 16 = 1024 draws
+      const int idx = t * 4 + e;
+      const int kk = idx / KC, jj = idx % KC;
+      const int64_t k = k0 + kk, j = j0 + jj;
+      T v = 0;
+      if (k < m && j < n) v = gauss_at<T>(seed, sid, (uint64_t)k * (uint64_t)n + (uint64_t)j);
+      Ss[jj][kk] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {  // A slice: 16 x 128
+      const int idx = t * 8 + e;
+      const int jj = idx / TD, cc = idx % TD;
+      const int64_t j = j0 + jj, c = c0 + cc;
+      As[jj][cc] = (j < n && c < d) ? A[j * lda + c] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T av = Ss[kr][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const T bv = As[kr][wc * 64 + b * 16 + (lane & 15)];
+          if constexpr (sizeof(T) == 4)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t k = k0 + wr * 32 + a * 16 + mfma16_row<T>(lane, r);
+        const int64_t c = c0 + wc * 64 + b * 16 + (lane & 15);
+        if (k < m && c < d) {
+          const double v = (double)acc[a][b][r] * scale;
+          if constexpr (sizeof(OutT) == 2)
+            SA[k * ldsa + c] = f32_to_bf16_rne((float)v);
+          else
+            SA[k * ldsa + c] = (OutT)v;
+        }
+      }
+}
+
+rs_status gauss_launch(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
+                       uint64_t seed, uint32_t sid, void* SA, rs_dtype sa_t, int64_t ldsa,
+                       hipStream_t s) {
+  const dim3 grid((unsigned)((d + 127) / 128), (unsigned)((m + 63) / 64));
+  const double scale = 1.0 / std::sqrt((double)m);
+  if (a_t == RS_F64) {
+    if (sa_t != RS_F64) return set_error(RS_ERR_UNSUPPORTED, "gaussian: F64 A needs F64 SA");
+    hipLaunchKernelGGL((k_gauss_sketch<double, double>), grid, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(A), n, d, lda, m, seed, sid, scale,
+                       reinterpret_cast<double*>(SA), ldsa);
+  } else if (sa_t == RS_F32) {
+    hipLaunchKernelGGL((k_gauss_sketch<float, float>), grid, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(A), n, d, lda, m, seed, sid, scale,
+                       reinterpret_cast<float*>(SA), ldsa);
+  } else if (sa_t == RS_BF16) {
+    hipLaunchKernelGGL((k_gauss_sketch<float, uint16_t>), grid, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(A), n, d, lda, m, seed, sid, scale,
+                       reinterpret_cast<uint16_t*>(SA), ldsa);
+  } else {
+    return set_error(RS_ERR_UNSUPPORTED, "gaussian: SA dtype not supported");
+  }
+  return check_launch("gaussian sketch");
+}
+
+}  // namespace rs

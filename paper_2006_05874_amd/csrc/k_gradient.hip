@@ -1,0 +1,307 @@
+// Fused gradient G = A^T (A X - b) + nu^2 X for k right-hand sides, one read of A.
+//
+// The per-iteration cost of the method is this product (proof of Theorem 7: the
+// matrix-vector products A x_t and A^T (A x_t - b)).  It is bound by HBM: each
+// pass streams n*d*sizeof(T) bytes and does 4 n d k flops.
+//
+// Layout: TPR threads cover one row of A with NV 16-byte vectors each (columns
+// (lt + TPR*v)*VEC ..), so a row is read with fully coalesced 16-byte loads.  A
+// 256-thread block holds 256/TPR row groups; each group takes R rows at a time.
+// Row dots are reduced inside the group (shuffles, plus LDS when TPR > 64); the
+// A^T r products of the R rows are summed in T and then added to FP64
+// accumulators.  Each block writes one FP64 partial of length k*d; a second
+// kernel adds the partials in a fixed order (deterministic) and nu^2 X.
+#include "rs_internal.hpp"
+
+namespace rs {
+
+template <typename T, int TPR, int NV, int K, int R>
+__global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, int64_t n, int64_t d,
+                                                      int64_t lda, const T* __restrict__ b,
+                                                      const double* __restrict__ X,
+                                                      int64_t rows_per_block, int iters,
+                                                      double* __restrict__ partial,
+                                                      const int* __restrict__ status) {
+  if (status && *status != 0) return;
+  using V = typename VecOf<T>::type;
+  constexpr int VEC = VecOf<T>::n;
+  constexpr int GPB = 256 / TPR;          // row groups per block
+  constexpr int WPG = TPR > 64 ? TPR / 64 : 1;  // waves per group
+  __shared__ double red_acc[256 * NV * VEC > 4096 ? 4096 : 256 * NV * VEC];
+  __shared__ T red_dot[2][GPB][WPG][R * K];
+
+  const int tid = threadIdx.x;
+  const int grp = tid / TPR;
+  const int lt = tid % TPR;
+  const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t row1 = row0 + rows_per_block < n ? row0 + rows_per_block : n;
+
+  // x in registers (T precision)
+  T xv[K][NV][VEC];
+  bool colok[NV][VEC];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t c = (int64_t)(lt + TPR * v) * VEC + e;
+      colok[v][e] = c < d;
+#pragma unroll
+      for (int k = 0; k < K; ++k) xv[k][v][e] = colok[v][e] ? (T)X[k * d + c] : (T)0;
+    }
+  }
+  double acc[K][NV][VEC];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[k][v][e] = 0.0;
+
+  for (int it = 0; it < iters; ++it) {
+    const int64_t base = row0 + ((int64_t)it * GPB + grp) * R;
+    V a[R][NV];
+    T bv[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int64_t row = base + i;
+      const bool rok = row < row1;
+      bv[i] = rok ? b[row] : (T)0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int64_t c = (int64_t)(lt + TPR * v) * VEC;
+        if (rok && c < d) {
+          a[i][v] = *reinterpret_cast<const V*>(A + row * lda + c);
+        } else {
+          a[i][v] = V{};
+        }
+      }
+    }
+    // mask columns past d (the vector may straddle d)
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (!colok[v][e]) set(a[i][v], e, (T)0);
+
+    T s[R][K];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        T t = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) t = fma(get(a[i][v], e), xv[k][v][e], t);
+        s[i][k] = t;
+      }
+    // reduce the row dots over the TPR threads of the group
+    if constexpr (TPR <= 64) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[i][k] = group_sum<TPR>(s[i][k]);
+    } else {
+      const int w = lt / 64;
+      const int buf = it & 1;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          T t = wave_sum(s[i][k]);
+          if ((lt & 63) == 0) red_dot[buf][grp][w][i * K + k] = t;
+        }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          T t = 0;
+#pragma unroll
+          for (int ww = 0; ww < WPG; ++ww) t += red_dot[buf][grp][ww][i * K + k];
+          s[i][k] = t;
+        }
+    }
+    // A^T r for the R rows: T sums, then FP64 accumulation
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      T res[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) res[i] = s[i][k] - bv[i];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          T t = 0;
+#pragma unroll
+          for (int i = 0; i < R; ++i) t = fma(get(a[i][v], e), res[i], t);
+          acc[k][v][e] += (double)t;
+        }
+    }
+  }
+
+  // combine the row groups of the block in a fixed order, one RHS at a time
+  constexpr int COLS = TPR * NV * VEC;  // columns covered by one group
+  for (int k = 0; k < K; ++k) {
+    if constexpr (GPB == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const int64_t c = (int64_t)(lt + TPR * v) * VEC + e;
+          if (c < d) partial[((int64_t)blockIdx.x * K + k) * d + c] = acc[k][v][e];
+        }
+    } else {
+      // red_acc holds GPB * COLS doubles when that fits 4096, else groups pass
+      // through it in rounds
+      constexpr int GR = (GPB * COLS <= 4096) ? GPB : (4096 / COLS);
+      double sum[NV][VEC];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sum[v][e] = 0.0;
+      for (int g0 = 0; g0 < GPB; g0 += GR) {
+        __syncthreads();
+        if (grp >= g0 && grp < g0 + GR) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              red_acc[(grp - g0) * COLS + (lt + TPR * v) * VEC + e] = acc[k][v][e];
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              for (int gg = 0; gg < GR && g0 + gg < GPB; ++gg)
+                sum[v][e] += red_acc[gg * COLS + (lt + TPR * v) * VEC + e];
+        }
+      }
+      if (grp == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            const int64_t c = (int64_t)(lt + TPR * v) * VEC + e;
+            if (c < d) partial[((int64_t)blockIdx.x * K + k) * d + c] = sum[v][e];
+          }
+      }
+    }
+  }
+}
+
+// G[k][j] = sum over blocks of partial[b][k][j] (fixed order) + nu2 X[k][j].
+// Block: 8 columns x 32 block-strides; LDS tree over the 32 strides.
+__global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ partial, int nblk,
+                                                     int64_t kd, double nu2,
+                                                     const double* __restrict__ X,
+                                                     double* __restrict__ G,
+                                                     const int* __restrict__ status) {
+  if (status && *status != 0) return;
+  __shared__ double s[32][8];
+  const int cl = threadIdx.x & 7;
+  const int rs_ = threadIdx.x >> 3;
+  const int64_t c = (int64_t)blockIdx.x * 8 + cl;
+  double t = 0.0;
+  if (c < kd)
+    for (int b = rs_; b < nblk; b += 32) t += partial[(int64_t)b * kd + c];
+  s[rs_][cl] = t;
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double u = 0.0;
+    for (int r = 0; r < 32; ++r) u += s[r][threadIdx.x];
+    const int64_t cc = (int64_t)blockIdx.x * 8 + threadIdx.x;
+    if (cc < kd) G[cc] = u + nu2 * X[cc];
+  }
+}
+
+namespace {
+
+struct GradShape {
+  int tpr, nv;
+};
+
+template <typename T>
+GradShape pick_shape(int64_t d) {
+  constexpr int VEC = VecOf<T>::n;
+  const int64_t chunks = (d + VEC - 1) / VEC;  // 16-byte vectors per row
+  if (chunks <= 16) return {16, 1};
+  if (chunks <= 64) return {64, 1};
+  if (chunks <= 128) return {64, 2};
+  if (chunks <= 256) return {64, 4};
+  if (chunks <= 512) return {128, 4};
+  if (chunks <= 1024) return {256, 4};
+  if (chunks <= 2048) return {256, 8};
+  return {0, 0};
+}
+
+template <typename T, int TPR, int NV, int K>
+void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
+                    double* partial, int grid, int64_t rpb, const int* status, hipStream_t s) {
+  constexpr int R = (NV >= 8) ? 2 : (NV >= 4 ? 4 : 8);
+  constexpr int GPB = 256 / TPR;
+  const int iters = (int)((rpb + GPB * R - 1) / (GPB * R));
+  prof_begin(s);
+  hipLaunchKernelGGL((k_grad_partial<T, TPR, NV, K, R>), dim3(grid), dim3(256), 0, s, A, n, d, lda,
+                     b, X, rpb, iters, partial, status);
+  prof_end(s);
+}
+
+template <typename T, int K>
+bool dispatch_k(GradShape sh, const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
+                const double* X, double* partial, int grid, int64_t rpb, const int* status,
+                hipStream_t s) {
+#define RS_GCASE(TP, NVV)                                                                    \
+  if (sh.tpr == TP && sh.nv == NVV) {                                                        \
+    launch_partial<T, TP, NVV, K>(A, n, d, lda, b, X, partial, grid, rpb, status, s);        \
+    return true;                                                                             \
+  }
+  RS_GCASE(16, 1) RS_GCASE(64, 1) RS_GCASE(64, 2) RS_GCASE(64, 4) RS_GCASE(128, 4)
+  RS_GCASE(256, 4) RS_GCASE(256, 8)
+#undef RS_GCASE
+  return false;
+}
+
+}  // namespace
+
+int grad_partial_blocks(int64_t n) {
+  const int64_t target = (int64_t)device_cus() * 2;
+  int64_t g = n / 64;
+  if (g < 1) g = 1;
+  return (int)(g < target ? g : target);
+}
+
+template <typename T>
+rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
+                          const double* X, int k, double* G, double* partial, int grid,
+                          const int* status, hipStream_t s) {
+  const GradShape sh = pick_shape<T>(d);
+  if (sh.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
+  int64_t rpb = (n + grid - 1) / grid;
+  bool ok = false;
+  switch (k) {
+    case 1: ok = dispatch_k<T, 1>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
+    case 2: ok = dispatch_k<T, 2>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
+    case 3: ok = dispatch_k<T, 3>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
+    case 4: ok = dispatch_k<T, 4>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
+    default: return set_error(RS_ERR_ARG, "gradient: k must be in 1..4");
+  }
+  if (!ok) return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
+  const int64_t kd = (int64_t)k * d;
+  hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial, grid,
+                     kd, nu2, X, G, status);
+  return check_launch("gradient");
+}
+
+template rs_status gradient_launch<float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                          double, const double*, int, double*, double*, int,
+                                          const int*, hipStream_t);
+template rs_status gradient_launch<double>(const double*, int64_t, int64_t, int64_t, const double*,
+                                           double, const double*, int, double*, double*, int,
+                                           const int*, hipStream_t);
+
+}  // namespace rs

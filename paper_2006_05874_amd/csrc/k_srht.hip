@@ -1,0 +1,526 @@
+// SRHT embedding SA = (1/sqrt(m)) R H diag(eps) A on the device (Appendix C.2).
+//
+// Randomness: eps_i and row keys from Philox4x32-10 (streams 4 and 5).  R is the
+// m rows with the smallest (key, index): a one-level radix select on the top
+// 12 key bits finds the boundary bin, its few members are sorted in one block,
+// and a stream compaction writes the chosen rows in ascending order.
+//
+// Transform: H of order npad = n1 * n2 factors as H_{n1} (x) H_{n2} on the row
+// index i = i1 * n2 + i2 (Sylvester order).  Pass 1 transforms every block of
+// n2 = min(npad, 1024) consecutive rows (with the sign flip fused into the load)
+// and keeps only the i2 values that some sampled row uses (Q of them).  Pass 2
+// transforms along i1 (length n1) for those Q columns and writes the sampled
+// rows, scaled by 1/sqrt(m), straight into SA.  A pass streams a tile of
+// 1024 rows x 128 bytes per block: 32 rows per thread sit in registers for the
+// butterflies of the high row bits, one LDS transpose brings the low row bits
+// into registers for the rest, and HBM sees whole 128-byte row segments.
+#include "rs_internal.hpp"
+
+namespace rs {
+
+constexpr int kHistBits = 12;
+constexpr int kHistBins = 1 << kHistBits;
+constexpr int kCandCap = 8192;
+constexpr int kCompactBlock = 1024;  // elements per block in the compaction
+
+// ---------------------------------------------------------------- selection
+// hist (kHistBins) must be zero on entry.  Also writes the signs and resets the
+// row->sample map to -1.
+__global__ __launch_bounds__(256) void k_keys_hist(uint64_t seed, uint32_t sid, int64_t npad,
+                                                   uint32_t* __restrict__ hist,
+                                                   int8_t* __restrict__ signs,
+                                                   int32_t* __restrict__ kmap) {
+  __shared__ uint32_t h[kHistBins];
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = row_key(seed, sid, (uint64_t)i);
+    atomicAdd(&h[(uint32_t)(key >> (64 - kHistBits))], 1u);
+    signs[i] = (int8_t)sign_of(seed, sid, (uint64_t)i);
+    kmap[i] = -1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+struct SelectState {
+  uint32_t bstar;      // boundary bin
+  uint32_t need;       // rows still to take from the boundary bin
+  uint32_t ncand;      // members of the boundary bin found
+  uint32_t overflow;   // set when the boundary bin exceeds kCandCap
+  uint64_t tkey;       // (tkey, tidx): the last selected (key, index)
+  int64_t tidx;
+};
+
+// One block of 1024 threads: prefix sums over the histogram, locate the bin
+// holding the m-th smallest key; clears the histogram for the next call.
+__global__ __launch_bounds__(1024) void k_select_bin(uint32_t* __restrict__ hist, int64_t m,
+                                                     SelectState* __restrict__ st) {
+  __shared__ uint32_t part[1024];
+  constexpr int PER = kHistBins / 1024;
+  uint32_t loc[PER];
+  uint32_t tot = 0;
+  for (int j = 0; j < PER; ++j) {
+    loc[j] = hist[threadIdx.x * PER + j];
+    tot += loc[j];
+  }
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  // inclusive scan over 1024 thread totals (Hillis-Steele)
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int j = 0; j < PER; ++j) {
+    const uint32_t after = before + loc[j];
+    if ((uint64_t)before < (uint64_t)m && (uint64_t)m <= (uint64_t)after) {
+      st->bstar = threadIdx.x * PER + j;
+      st->need = (uint32_t)(m - before);
+    }
+    before = after;
+  }
+  for (int j = 0; j < PER; ++j) hist[threadIdx.x * PER + j] = 0u;
+  if (threadIdx.x == 0) {
+    st->ncand = 0;
+    st->overflow = 0;
+  }
+}
+
+// Members of the boundary bin -> candidate list; per-block counts of keys in
+// lower bins.
+__global__ __launch_bounds__(256) void k_collect(uint64_t seed, uint32_t sid, int64_t npad,
+                                                 SelectState* __restrict__ st,
+                                                 uint64_t* __restrict__ cand_key,
+                                                 int64_t* __restrict__ cand_idx,
+                                                 uint32_t* __restrict__ blk_less) {
+  __shared__ uint32_t cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const uint32_t bstar = st->bstar;
+  const int64_t b0 = (int64_t)blockIdx.x * kCompactBlock;
+  uint32_t mine = 0;
+  for (int j = threadIdx.x; j < kCompactBlock; j += blockDim.x) {
+    const int64_t i = b0 + j;
+    if (i >= npad) break;
+    const uint64_t key = row_key(seed, sid, (uint64_t)i);
+    const uint32_t bin = (uint32_t)(key >> (64 - kHistBits));
+    if (bin < bstar) ++mine;
+    else if (bin == bstar) {
+      const uint32_t pos = atomicAdd(&st->ncand, 1u);
+      if (pos < (uint32_t)kCandCap) {
+        cand_key[pos] = key;
+        cand_idx[pos] = i;
+      } else {
+        st->overflow = 1u;
+      }
+    }
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) blk_less[blockIdx.x] = cnt;
+}
+
+// One block: sort the candidates by (key, index) (bitonic, in LDS), keep the
+// first `need`, record the threshold, and turn blk_less into exclusive offsets.
+__global__ __launch_bounds__(1024) void k_cand_sort(SelectState* __restrict__ st,
+                                                    uint64_t* __restrict__ cand_key,
+                                                    int64_t* __restrict__ cand_idx,
+                                                    uint32_t* __restrict__ blk_less, int nblk) {
+  __shared__ uint64_t sk[kCandCap];
+  __shared__ int32_t si[kCandCap];
+  __shared__ uint32_t part[1024];
+  const uint32_t nc = st->ncand < (uint32_t)kCandCap ? st->ncand : (uint32_t)kCandCap;
+  uint32_t P = 1;
+  while (P < nc) P <<= 1;
+  for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+    if (i < nc) {
+      sk[i] = cand_key[i];
+      si[i] = (int32_t)cand_idx[i];
+    } else {
+      sk[i] = ~0ull;
+      si[i] = 0x7fffffff;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const bool gt = (sk[i] > sk[l]) || (sk[i] == sk[l] && si[i] > si[l]);
+          if (gt == up) {
+            uint64_t tk = sk[i]; sk[i] = sk[l]; sk[l] = tk;
+            int32_t ti = si[i]; si[i] = si[l]; si[l] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint32_t need = st->need;
+  // write back the selected members sorted by index order is not needed: keep
+  // them sorted by (key, idx); the scatter pass only counts them.
+  for (uint32_t i = threadIdx.x; i < need && i < nc; i += blockDim.x) cand_idx[i] = si[i];
+  if (threadIdx.x == 0 && need >= 1 && need <= nc) {
+    st->tkey = sk[need - 1];
+    st->tidx = si[need - 1];
+  }
+  // exclusive scan of blk_less (nblk <= 1024 * PER)
+  const int PER = (nblk + 1023) / 1024;
+  uint32_t tot = 0;
+  for (int j = 0; j < PER; ++j) {
+    const int b = threadIdx.x * PER + j;
+    tot += b < nblk ? blk_less[b] : 0u;
+  }
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int j = 0; j < PER; ++j) {
+    const int b = threadIdx.x * PER + j;
+    if (b < nblk) {
+      const uint32_t v = blk_less[b];
+      blk_less[b] = run;
+      run += v;
+    }
+  }
+}
+
+// Compaction: rows[offset + local rank] = i for every selected i, ascending.
+// Also fills kmap[row] = k and marks the used low indices (row & (n2-1)).
+__global__ __launch_bounds__(256) void k_scatter_rows(uint64_t seed, uint32_t sid, int64_t npad,
+                                                      const SelectState* __restrict__ st,
+                                                      const int64_t* __restrict__ sel_cand_idx,
+                                                      const uint32_t* __restrict__ blk_off,
+                                                      int64_t* __restrict__ rows,
+                                                      int32_t* __restrict__ kmap,
+                                                      int32_t* __restrict__ used, int64_t n2mask,
+                                                      int64_t m) {
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t base_s;
+  const uint32_t bstar = st->bstar;
+  const uint64_t tkey = st->tkey;
+  const int64_t tidx = st->tidx;
+  const int64_t b0 = (int64_t)blockIdx.x * kCompactBlock;
+  if (threadIdx.x == 0) {
+    // selected boundary members with index below this block
+    uint32_t c = 0;
+    const uint32_t need = min(st->need, (uint32_t)kCandCap);
+    for (uint32_t j = 0; j < need; ++j) c += sel_cand_idx[j] < b0 ? 1u : 0u;
+    base_s = blk_off[blockIdx.x] + c;
+  }
+  __syncthreads();
+  uint32_t base = base_s;
+  constexpr int PER = kCompactBlock / 256;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int p = 0; p < PER; ++p) {
+    const int64_t i = b0 + p * 256 + threadIdx.x;
+    bool sel = false;
+    if (i < npad) {
+      const uint64_t key = row_key(seed, sid, (uint64_t)i);
+      const uint32_t bin = (uint32_t)(key >> (64 - kHistBits));
+      sel = bin < bstar || (bin == bstar && (key < tkey || (key == tkey && i <= tidx)));
+    }
+    const uint64_t ballot = __ballot(sel);
+    const uint32_t below = (uint32_t)__popcll(ballot & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = (uint32_t)__popcll(ballot);
+    __syncthreads();
+    uint32_t off = base;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    if (sel && (int64_t)(off + below) < m) {
+      const uint32_t k = off + below;
+      rows[k] = i;
+      kmap[i] = (int32_t)k;
+      used[i & n2mask] = 1;
+    }
+    uint32_t tot = 0;
+    for (int w = 0; w < 4; ++w) tot += wsum[w];
+    __syncthreads();
+    base += tot;
+  }
+}
+
+// One block: used[n2] -> qmap (i2 -> q or -1), qlist (q -> i2), Q; clears used.
+__global__ __launch_bounds__(1024) void k_qscan(int32_t* __restrict__ used, int n2,
+                                                int32_t* __restrict__ qmap,
+                                                int32_t* __restrict__ qlist,
+                                                int32_t* __restrict__ qcount) {
+  __shared__ int32_t part[1024];
+  const int i = threadIdx.x;
+  const int u = (i < n2) ? (used[i] != 0) : 0;
+  part[i] = u;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = i >= off ? part[i - off] : 0;
+    __syncthreads();
+    part[i] += v;
+    __syncthreads();
+  }
+  if (i < n2) {
+    const int q = part[i] - 1;
+    qmap[i] = u ? q : -1;
+    if (u) qlist[q] = i;
+    used[i] = 0;
+  }
+  if (i == 1023) *qcount = part[1023];
+}
+
+// ---------------------------------------------------------------- transform
+// One tile: 1024 rows x W columns (W*sizeof(T) = 128 bytes), 256 threads.
+// Stage A: thread (g = t/8, c = t%8) holds rows r = g + 32 j, j = 0..31, and
+// applies the butterflies of row bits 5..9; stage B (after an LDS transpose)
+// holds rows r = 32 g + j and applies row bits 0..4.  Only row bits below lb
+// take part (the transform length is 2^lb; tile rows above it are independent
+// transforms).
+template <typename T>
+struct Tile {
+  using V = typename VecOf<T>::type;
+  static constexpr int VEC = VecOf<T>::n;
+  static constexpr int CW = 8;           // vectors per tile row
+  static constexpr int W = CW * VEC;     // columns per tile
+  static constexpr int RT = 1024;        // rows per tile
+  static constexpr int J = 32;           // rows per thread
+};
+
+template <typename V>
+__device__ __forceinline__ void bfly(V& u, V& v);
+template <>
+__device__ __forceinline__ void bfly<float4>(float4& u, float4& v) {
+  const float4 a = u, b = v;
+  u = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+  v = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+template <>
+__device__ __forceinline__ void bfly<double2>(double2& u, double2& v) {
+  const double2 a = u, b = v;
+  u = make_double2(a.x + b.x, a.y + b.y);
+  v = make_double2(a.x - b.x, a.y - b.y);
+}
+
+template <typename V, int J>
+__device__ __forceinline__ void reg_fwht(V (&v)[J], int bit_lo, int lb) {
+  // butterflies over register-index bits; register bit s <-> row bit bit_lo + s
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    if (bit_lo + s < lb) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if ((j & (1 << s)) == 0) bfly(v[j], v[j | (1 << s)]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int lds_slot(int r, int c) { return r * 8 + (c ^ ((r >> 5) & 7)); }
+
+template <typename T>
+__device__ __forceinline__ void store_row(T* out, int64_t ldo, int64_t orow, int64_t col0,
+                                          int64_t d, const typename VecOf<T>::type& v, T scale) {
+  constexpr int VEC = VecOf<T>::n;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+    if (col0 + e < d) out[orow * ldo + col0 + e] = get(v, e) * scale;
+}
+
+__device__ __forceinline__ void store_row_bf16(uint16_t* out, int64_t ldo, int64_t orow,
+                                               int64_t col0, int64_t d, const float4& v,
+                                               float scale) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (col0 + e < d) out[orow * ldo + col0 + e] = f32_to_bf16_rne(get(v, e) * scale);
+}
+
+// mode 0: pass 1 writing Zc rows (j1*Q + qmap[i2]);
+// mode 1: pass 1 writing SA rows kmap[row] (single pass, npad <= 1024);
+// mode 2: pass 2 reading Zc, writing SA rows.
+// OutT: T, or uint16_t for BF16 output.
+template <typename T, typename OutT, int MODE>
+__global__ __launch_bounds__(256) void k_fwht_tile(
+    const T* __restrict__ src, int64_t n_src_rows, int64_t lds_src, int64_t d,
+    const int8_t* __restrict__ signs, int lb, int64_t n2, int64_t Q,
+    const int32_t* __restrict__ qmap, const int32_t* __restrict__ qlist,
+    const int32_t* __restrict__ kmap, const int32_t* __restrict__ qcount,
+    OutT* __restrict__ out, int64_t ldo, double scale) {
+  using TT = Tile<T>;
+  using V = typename TT::V;
+  constexpr int VEC = TT::VEC;
+  constexpr int J = TT::J;
+  __shared__ V lds[TT::RT * TT::CW];
+  __shared__ int32_t dest[TT::RT];
+
+  const int t = threadIdx.x;
+  const int c = t & 7;
+  const int g = t >> 3;
+  const int64_t col0 = ((int64_t)blockIdx.y * TT::CW + c) * VEC;
+  const bool cvec = col0 < d;
+
+  // destination of each tile row
+  const int64_t tile = blockIdx.x;
+  for (int r = t; r < TT::RT; r += 256) {
+    int32_t dst = -1;
+    if (MODE == 0) {
+      const int32_t q = (r < n2) ? qmap[r] : -1;
+      dst = q >= 0 ? (int32_t)(tile * Q + q) : -1;
+    } else if (MODE == 1) {
+      dst = (r < n2) ? kmap[r] : -1;
+    } else {
+      const int64_t n1 = (int64_t)1 << lb;
+      const int64_t qq = r >> lb;
+      const int64_t i1 = r & (n1 - 1);
+      const int64_t q = tile * (TT::RT >> lb) + qq;
+      dst = q < (int64_t)(*qcount) ? kmap[i1 * n2 + qlist[q]] : -1;
+    }
+    dest[r] = dst;
+  }
+
+  // load (stage A mapping)
+  V v[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int r = g + 32 * j;
+    int64_t srow;
+    bool ok;
+    T sg = (T)1;
+    if (MODE == 2) {
+      const int64_t n1 = (int64_t)1 << lb;
+      const int64_t qq = r >> lb;
+      const int64_t i1 = r & (n1 - 1);
+      const int64_t q = tile * (TT::RT >> lb) + qq;
+      srow = i1 * Q + q;
+      ok = q < Q;
+    } else {
+      srow = tile * n2 + r;
+      ok = (r < n2) && (srow < n_src_rows);
+      if (ok) sg = (T)signs[srow];
+    }
+    V x = V{};
+    if (ok && cvec) x = *reinterpret_cast<const V*>(src + srow * lds_src + col0);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const T xe = (col0 + e < d) ? get(x, e) * sg : (T)0;
+      set(x, e, xe);
+    }
+    v[j] = x;
+  }
+  reg_fwht<V, J>(v, 5, lb);
+#pragma unroll
+  for (int j = 0; j < J; ++j) lds[lds_slot(g + 32 * j, c)] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) v[j] = lds[lds_slot(32 * g + j, c)];
+  reg_fwht<V, J>(v, 0, lb);
+
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int r = 32 * g + j;
+    const int32_t dst = dest[r];
+    if (dst >= 0 && cvec) {
+      if constexpr (sizeof(OutT) == 2) {
+        store_row_bf16(reinterpret_cast<uint16_t*>(out), ldo, dst, col0, d, v[j], (float)scale);
+      } else {
+        store_row<T>(reinterpret_cast<T*>(out), ldo, dst, col0, d, v[j], (T)scale);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- driver
+rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t npad, int64_t m,
+                      int64_t n2, int64_t* rows, hipStream_t s) {
+  const int hist_grid = (int)std::min<int64_t>((npad + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_keys_hist, dim3(hist_grid), dim3(256), 0, s, seed, sid, npad, B.hist,
+                     B.signs, B.kmap);
+  SelectState* st = reinterpret_cast<SelectState*>(B.state);
+  hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(1024), 0, s, B.hist, m, st);
+  const int nblk = (int)((npad + kCompactBlock - 1) / kCompactBlock);
+  hipLaunchKernelGGL(k_collect, dim3(nblk), dim3(256), 0, s, seed, sid, npad, st, B.cand_key,
+                     B.cand_idx, B.blk_less);
+  hipLaunchKernelGGL(k_cand_sort, dim3(1), dim3(1024), 0, s, st, B.cand_key, B.cand_idx,
+                     B.blk_less, nblk);
+  hipLaunchKernelGGL(k_scatter_rows, dim3(nblk), dim3(256), 0, s, seed, sid, npad, st,
+                     B.cand_idx, B.blk_less, rows, B.kmap, B.used, n2 - 1, m);
+  hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, s, B.used, (int)n2, B.qmap, B.qlist,
+                     B.qcount);
+  return check_launch("srht select");
+}
+
+size_t srht_state_bytes() { return sizeof(SelectState); }
+int srht_cand_cap() { return kCandCap; }
+int srht_compact_block() { return kCompactBlock; }
+
+template <typename T, typename OutT, int MODE>
+static void launch_tile(dim3 grid, hipStream_t s, const T* src, int64_t nsrc, int64_t ldsrc,
+                        int64_t d, const SrhtBuffers& B, int lb, int64_t n2, int64_t Q, void* out,
+                        int64_t ldo, double scale) {
+  hipLaunchKernelGGL((k_fwht_tile<T, OutT, MODE>), grid, dim3(256), 0, s, src, nsrc, ldsrc, d,
+                     B.signs, lb, n2, Q, B.qmap, B.qlist, B.kmap, B.qcount,
+                     reinterpret_cast<OutT*>(out), ldo, scale);
+}
+
+template <typename T>
+rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
+                         int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
+                         int64_t Qmax, hipStream_t s) {
+  using TT = Tile<T>;
+  const int64_t n2 = npad < TT::RT ? npad : TT::RT;
+  const int64_t n1 = npad / n2;
+  int lb2 = 0;
+  while (((int64_t)1 << lb2) < n2) ++lb2;
+  int lb1 = 0;
+  while (((int64_t)1 << lb1) < n1) ++lb1;
+  const unsigned panels = (unsigned)((d + TT::W - 1) / TT::W);
+  const double scale = 1.0 / std::sqrt((double)m);
+  const bool bf16 = sa_t == RS_BF16;
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) return set_error(RS_ERR_UNSUPPORTED, "srht: BF16 output needs FP32 input");
+  }
+  if (n1 > TT::RT) return set_error(RS_ERR_SHAPE, "srht: padded n above 2^20 is not supported");
+  if (n1 == 1) {
+    if constexpr (sizeof(T) == 4) {
+      if (bf16) {
+        launch_tile<T, uint16_t, 1>(dim3(1, panels), s, A, n, lda, d, B, lb2, n2, 0, SA, ldsa, scale);
+        return check_launch("srht single pass");
+      }
+    }
+    launch_tile<T, T, 1>(dim3(1, panels), s, A, n, lda, d, B, lb2, n2, 0, SA, ldsa, scale);
+    return check_launch("srht single pass");
+  }
+  // Q (distinct low indices) lives on the device; the intermediate is laid out
+  // with the host bound Qmax >= Q and pass 2 reads the device count.
+  const int64_t ldz = ((d + TT::VEC - 1) / TT::VEC) * TT::VEC;
+  launch_tile<T, T, 0>(dim3((unsigned)n1, panels), s, A, n, lda, d, B, lb2, n2, Qmax, B.zbuf, ldz,
+                       1.0);
+  const int64_t tiles2 = (Qmax * n1 + TT::RT - 1) / TT::RT;
+  const T* Z = reinterpret_cast<const T*>(B.zbuf);
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) {
+      launch_tile<T, uint16_t, 2>(dim3((unsigned)tiles2, panels), s, Z, n1 * Qmax, ldz, d, B, lb1,
+                                  n2, Qmax, SA, ldsa, scale);
+      return check_launch("srht two pass");
+    }
+  }
+  launch_tile<T, T, 2>(dim3((unsigned)tiles2, panels), s, Z, n1 * Qmax, ldz, d, B, lb1, n2, Qmax,
+                       SA, ldsa, scale);
+  return check_launch("srht two pass");
+}
+
+template rs_status srht_transform<float>(const SrhtBuffers&, const float*, int64_t, int64_t,
+                                         int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
+                                         int64_t, hipStream_t);
+template rs_status srht_transform<double>(const SrhtBuffers&, const double*, int64_t, int64_t,
+                                          int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
+                                          int64_t, hipStream_t);
+
+}  // namespace rs

@@ -1,0 +1,668 @@
+// C ABI of librs: argument checks, per-device scratch, and the host side of the
+// adaptive controller (Algorithm 1).  Every numeric step runs in the kernels.
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rs_internal.hpp"
+
+namespace rs {
+
+static thread_local std::string g_err;
+
+rs_status set_error(rs_status st, const char* msg) {
+  g_err = msg ? msg : "";
+  return st;
+}
+
+rs_status check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return RS_ERR_HIP;
+  }
+  return RS_OK;
+}
+
+#define RS_HIP(call)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      g_err = std::string(#call) + ": " + hipGetErrorString(e_);                    \
+      return e_ == hipErrorOutOfMemory ? RS_ERR_OOM : RS_ERR_HIP;                   \
+    }                                                                               \
+  } while (0)
+
+#define RS_TRY(expr)                   \
+  do {                                 \
+    rs_status st_ = (expr);            \
+    if (st_ != RS_OK) return st_;      \
+  } while (0)
+
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// ------------------------------------------------------------------ timing
+static bool g_prof_on = false;
+static std::vector<hipEvent_t> g_prof_ev;  // begin/end pairs
+static size_t g_prof_n = 0;                // events recorded
+
+static hipEvent_t prof_event() {
+  if (g_prof_n >= g_prof_ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof_ev.push_back(e);
+  }
+  return g_prof_ev[g_prof_n++];
+}
+
+void prof_begin(hipStream_t s) {
+  if (!g_prof_on) return;
+  hipEvent_t e = prof_event();
+  if (e) (void)hipEventRecord(e, s);
+}
+
+void prof_end(hipStream_t s) {
+  if (!g_prof_on) return;
+  hipEvent_t e = prof_event();
+  if (e) (void)hipEventRecord(e, s);
+}
+
+// ------------------------------------------------------------------ scratch
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  // grow-only; zero-fills fresh memory when `zero` is set
+  rs_status ensure(size_t want, bool zero = false) {
+    if (want <= bytes && p) return RS_OK;
+    if (p) {
+      hipError_t e = hipFree(p);
+      (void)e;
+      p = nullptr;
+      bytes = 0;
+    }
+    const size_t sz = want ? want : 256;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      p = nullptr;
+      g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? RS_ERR_OOM : RS_ERR_HIP;
+    }
+    if (zero) {
+      e = hipMemset(p, 0, sz);
+      if (e != hipSuccess) return set_error(RS_ERR_HIP, "hipMemset failed");
+    }
+    bytes = sz;
+    return RS_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+struct DeviceScratch {
+  std::mutex mu;
+  // SRHT
+  DevBuf hist, signs, kmap, state, cand_key, cand_idx, blk_less, used, qmap, qlist, qcount, zbuf, rows;
+  // gradient partials, vectors, control
+  DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
+  // solver-owned sketch and factor
+  DevBuf sa, fM, fLinv, fHinv, fCw;
+  void* host_pinned = nullptr;
+};
+
+static DeviceScratch* scratch_for_current() {
+  static std::mutex mu;
+  static std::vector<DeviceScratch*> all;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)all.size() <= dev) all.resize(dev + 1, nullptr);
+  if (!all[dev]) all[dev] = new DeviceScratch();
+  return all[dev];
+}
+
+static int64_t next_pow2(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+static size_t dtype_size(rs_dtype t) {
+  switch (t) {
+    case RS_F64: return 8;
+    case RS_F32: return 4;
+    case RS_BF16: return 2;
+    case RS_FP8E4M3: return 1;
+  }
+  return 0;
+}
+
+static rs_status check_matrix(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                              const char* who) {
+  if (!A) return set_error(RS_ERR_ARG, (std::string(who) + ": A is null").c_str());
+  if (a_t != RS_F32 && a_t != RS_F64)
+    return set_error(RS_ERR_ARG, (std::string(who) + ": A must be F32 or F64").c_str());
+  if (n < 1 || d < 1) return set_error(RS_ERR_SHAPE, (std::string(who) + ": empty matrix").c_str());
+  const int64_t vec = 16 / (int64_t)dtype_size(a_t);
+  if (lda < d || lda % vec != 0)
+    return set_error(RS_ERR_ARG,
+                     (std::string(who) + ": lda must be >= d and a multiple of 16 bytes").c_str());
+  if (reinterpret_cast<uintptr_t>(A) % 16 != 0)
+    return set_error(RS_ERR_ARG, (std::string(who) + ": A must be 16-byte aligned").c_str());
+  return RS_OK;
+}
+
+static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, SrhtBuffers& B) {
+  RS_TRY(S.hist.ensure(4096 * sizeof(uint32_t), true));
+  RS_TRY(S.signs.ensure((size_t)npad));
+  RS_TRY(S.kmap.ensure((size_t)npad * sizeof(int32_t)));
+  RS_TRY(S.state.ensure(srht_state_bytes()));
+  RS_TRY(S.cand_key.ensure((size_t)srht_cand_cap() * sizeof(uint64_t)));
+  RS_TRY(S.cand_idx.ensure((size_t)srht_cand_cap() * sizeof(int64_t)));
+  RS_TRY(S.blk_less.ensure((size_t)((npad + srht_compact_block() - 1) / srht_compact_block()) *
+                           sizeof(uint32_t)));
+  RS_TRY(S.used.ensure(1024 * sizeof(int32_t), true));
+  RS_TRY(S.qmap.ensure(1024 * sizeof(int32_t)));
+  RS_TRY(S.qlist.ensure(1024 * sizeof(int32_t)));
+  RS_TRY(S.qcount.ensure(sizeof(int32_t)));
+  RS_TRY(S.zbuf.ensure((size_t)std::max<int64_t>(zbytes, 256)));
+  B = SrhtBuffers{S.hist.as<uint32_t>(), S.signs.as<int8_t>(),   S.kmap.as<int32_t>(),
+                  S.state.p,             S.cand_key.as<uint64_t>(), S.cand_idx.as<int64_t>(),
+                  S.blk_less.as<uint32_t>(), S.used.as<int32_t>(), S.qmap.as<int32_t>(),
+                  S.qlist.as<int32_t>(), S.qcount.as<int32_t>(), S.zbuf.p};
+  return RS_OK;
+}
+
+// SRHT into SA (no argument checks).
+static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
+                          int64_t lda, int64_t m, uint64_t seed, uint32_t sid, void* SA,
+                          rs_dtype sa_t, int64_t ldsa, int64_t* rows_out, int8_t* signs_out,
+                          hipStream_t s) {
+  const int64_t npad = next_pow2(n);
+  const int64_t n2 = std::min<int64_t>(npad, 1024);
+  const int64_t n1 = npad / n2;
+  const int64_t Qmax = std::min<int64_t>(m, n2);
+  const int64_t es = (int64_t)dtype_size(a_t);
+  const int64_t vec = 16 / es;
+  const int64_t ldz = (d + vec - 1) / vec * vec;
+  const int64_t zbytes = n1 > 1 ? n1 * Qmax * ldz * es : 0;
+  SrhtBuffers B;
+  RS_TRY(ensure_srht(S, npad, zbytes, B));
+  int64_t* rows = rows_out;
+  if (!rows) {
+    RS_TRY(S.rows.ensure((size_t)m * sizeof(int64_t)));
+    rows = S.rows.as<int64_t>();
+  }
+  RS_TRY(srht_select(B, seed, sid, npad, m, n2, rows, s));
+  if (a_t == RS_F32)
+    RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, m, SA, sa_t,
+                                 ldsa, Qmax, s));
+  else
+    RS_TRY(srht_transform<double>(B, reinterpret_cast<const double*>(A), n, d, lda, npad, m, SA,
+                                  sa_t, ldsa, Qmax, s));
+  if (signs_out) RS_HIP(hipMemcpyAsync(signs_out, B.signs, (size_t)npad, hipMemcpyDeviceToDevice, s));
+  return RS_OK;
+}
+
+static rs_status check_sa_type(rs_dtype a_t, rs_dtype sa_t) {
+  if (a_t == RS_F64 && sa_t != RS_F64) return set_error(RS_ERR_UNSUPPORTED, "F64 A needs F64 SA");
+  if (a_t == RS_F32 && !(sa_t == RS_F32 || sa_t == RS_BF16))
+    return set_error(RS_ERR_UNSUPPORTED, "F32 A supports F32 or BF16 SA");
+  return RS_OK;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+// ==================================================================== ABI
+struct rs_factor {
+  int64_t m, d, p, pp, dp;
+  double nu2;
+  bool wood;
+  DevBuf M, Linv, Hinv, Cw, info, rpart;
+};
+
+extern "C" {
+
+const char* rs_last_error(void) { return g_err.c_str(); }
+
+rs_status rs_profile_enable(int on) {
+  g_prof_on = on != 0;
+  return RS_OK;
+}
+
+rs_status rs_profile_read(int64_t* launches, double* total_ms) {
+  if (!launches || !total_ms) return set_error(RS_ERR_ARG, "rs_profile_read: null argument");
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (size_t i = 0; i + 1 < g_prof_n; i += 2) {
+    RS_HIP(hipEventSynchronize(g_prof_ev[i + 1]));
+    float ms = 0.0f;
+    RS_HIP(hipEventElapsedTime(&ms, g_prof_ev[i], g_prof_ev[i + 1]));
+    tot += ms;
+    ++cnt;
+  }
+  g_prof_n = 0;
+  *launches = cnt;
+  *total_ms = tot;
+  return RS_OK;
+}
+const char* rs_version(void) { return "librs 0.1 (gfx950)"; }
+
+rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* out) {
+  if (!out) return set_error(RS_ERR_ARG, "rs_params: out is null");
+  double lam, Lam;
+  if (kind == RS_SKETCH_SRHT) {
+    if (!(rho > 0.0 && rho < 1.0)) return set_error(RS_ERR_ARG, "rs_params: SRHT needs rho in (0,1)");
+    lam = 1.0 - std::sqrt(rho);
+    Lam = 1.0 + std::sqrt(rho);
+  } else if (kind == RS_SKETCH_GAUSSIAN) {
+    if (!(rho > 0.0 && rho <= 0.18 && eta > 0.0 && eta <= 0.01))
+      return set_error(RS_ERR_ARG, "rs_params: Gaussian needs rho in (0,0.18], eta in (0,0.01]");
+    const double ceta = (1.0 + 3.0 * std::sqrt(eta)) * (1.0 + 3.0 * std::sqrt(eta));
+    const double sq = std::sqrt(ceta * rho);
+    lam = (1.0 - sq) * (1.0 - sq);
+    Lam = (1.0 + sq) * (1.0 + sq);
+  } else {
+    return set_error(RS_ERR_ARG, "rs_params: unknown sketch kind");
+  }
+  const double sl = std::sqrt(lam), sL = std::sqrt(Lam);
+  out->mu_gd = 2.0 / (1.0 / lam + 1.0 / Lam);
+  out->cbar_gd = ((Lam - lam) / (Lam + lam)) * ((Lam - lam) / (Lam + lam));
+  out->mu_p = 4.0 / ((1.0 / sl + 1.0 / sL) * (1.0 / sl + 1.0 / sL));
+  out->beta_p = ((sL - sl) / (sL + sl)) * ((sL - sl) / (sL + sl));
+  out->cbar_p = out->beta_p;
+  return RS_OK;
+}
+
+rs_status rs_sketch_srht(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
+                         uint64_t seed, uint32_t sketch_id, void* SA, rs_dtype sa_t, int64_t ldsa,
+                         float* sa_col_scale, int64_t* rows_out, int8_t* signs_out,
+                         hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_sketch_srht"));
+  if (!SA) return set_error(RS_ERR_ARG, "rs_sketch_srht: SA is null");
+  RS_TRY(check_sa_type(a_t, sa_t));
+  (void)sa_col_scale;
+  const int64_t npad = next_pow2(n);
+  if (npad > (int64_t)1 << 20) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: padded n above 2^20");
+  if (m < 1 || m > npad) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: need 1 <= m <= padded n");
+  if (ldsa < d) return set_error(RS_ERR_ARG, "rs_sketch_srht: ldsa < d");
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  return srht_run(*S, A, a_t, n, d, lda, m, seed, sketch_id, SA, sa_t, ldsa, rows_out, signs_out,
+                  stream);
+}
+
+rs_status rs_sketch_gaussian(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                             int64_t m, uint64_t seed, uint32_t sketch_id, void* SA, rs_dtype sa_t,
+                             int64_t ldsa, float* sa_col_scale, hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_sketch_gaussian"));
+  if (!SA) return set_error(RS_ERR_ARG, "rs_sketch_gaussian: SA is null");
+  RS_TRY(check_sa_type(a_t, sa_t));
+  (void)sa_col_scale;
+  if (m < 1 || m > n) return set_error(RS_ERR_SHAPE, "rs_sketch_gaussian: need 1 <= m <= n");
+  if (ldsa < d) return set_error(RS_ERR_ARG, "rs_sketch_gaussian: ldsa < d");
+  return gauss_launch(A, a_t, n, d, lda, m, seed, sketch_id, SA, sa_t, ldsa, stream);
+}
+
+static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
+  F->m = m;
+  F->d = d;
+  F->wood = m < d;
+  F->p = F->wood ? m : d;
+  F->pp = (F->p + 63) / 64 * 64;
+  F->dp = (d + 63) / 64 * 64;
+  F->nu2 = nu2;
+  RS_TRY(F->M.ensure(factor_bytes_M(m, d)));
+  RS_TRY(F->Linv.ensure(factor_bytes_M(m, d)));
+  RS_TRY(F->Hinv.ensure(factor_bytes_Hinv(d)));
+  if (F->wood) RS_TRY(F->Cw.ensure(factor_bytes_Cw(m, d)));
+  RS_TRY(F->info.ensure(sizeof(int), true));
+  RS_TRY(F->rpart.ensure((size_t)apply_blocks(d) * 4 * sizeof(double)));
+  return RS_OK;
+}
+
+rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_scale, int64_t m,
+                             int64_t d, int64_t ldsa, double nu2, rs_factor** out,
+                             hipStream_t stream) {
+  (void)sa_col_scale;
+  if (!SA || !out) return set_error(RS_ERR_ARG, "rs_factor_woodbury: null argument");
+  if (m < 1 || d < 1 || ldsa < d) return set_error(RS_ERR_SHAPE, "rs_factor_woodbury: bad shape");
+  if (!(nu2 > 0.0) || !std::isfinite(nu2))
+    return set_error(RS_ERR_NOT_SPD, "rs_factor_woodbury: nu^2 must be positive");
+  if (sa_t != RS_F32 && sa_t != RS_F64 && sa_t != RS_BF16)
+    return set_error(RS_ERR_UNSUPPORTED, "rs_factor_woodbury: SA dtype not supported");
+  *out = nullptr;
+  rs_factor* F = new rs_factor();
+  rs_status st = factor_alloc(F, m, d, nu2);
+  if (st == RS_OK) {
+    FactorBuffers B{F->M.as<double>(), F->Linv.as<double>(), F->Hinv.as<double>(),
+                    F->Cw.as<double>(), F->info.as<int>()};
+    hipError_t e = hipMemsetAsync(B.info, 0, sizeof(int), stream);
+    if (e != hipSuccess) st = set_error(RS_ERR_HIP, "hipMemsetAsync failed");
+    if (st == RS_OK) st = factor_build(B, SA, sa_t, m, d, ldsa, nu2, stream);
+    int info = 0;
+    if (st == RS_OK) {
+      e = hipMemcpyAsync(&info, B.info, sizeof(int), hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) st = set_error(RS_ERR_HIP, hipGetErrorString(e));
+    }
+    if (st == RS_OK && info) st = set_error(RS_ERR_NOT_SPD, "rs_factor_woodbury: pivot not positive");
+  }
+  if (st != RS_OK) {
+    delete F;
+    return st;
+  }
+  *out = F;
+  return RS_OK;
+}
+
+rs_status rs_factor_apply(const rs_factor* F, const double* g, double* gtilde, double* r, int64_t k,
+                          hipStream_t stream) {
+  if (!F || !g || !gtilde || !r) return set_error(RS_ERR_ARG, "rs_factor_apply: null argument");
+  if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "rs_factor_apply: k must be in 1..4");
+  RS_TRY(apply_launch(F->Hinv.as<double>(), F->dp, F->d, g, (int)k, gtilde,
+                      F->rpart.as<double>(), nullptr, stream));
+  return rsum_launch(F->rpart.as<double>(), apply_blocks(F->d), (int)k, r, stream);
+}
+
+void rs_factor_destroy(rs_factor* F) {
+  if (!F) return;
+  for (DevBuf* b : {&F->M, &F->Linv, &F->Hinv, &F->Cw, &F->info, &F->rpart})
+    if (b->p) (void)hipFree(b->p);
+  delete F;
+}
+
+rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, const void* b,
+                      double nu2, const double* X, int64_t k, double* G, hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_gradient"));
+  if (!b || !X || !G) return set_error(RS_ERR_ARG, "rs_gradient: null argument");
+  if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "rs_gradient: k must be in 1..4");
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  const int grid = grad_partial_blocks(n);
+  RS_TRY(S->partial.ensure((size_t)grid * k * d * sizeof(double)));
+  if (a_t == RS_F32)
+    return gradient_launch<float>(reinterpret_cast<const float*>(A), n, d, lda,
+                                  reinterpret_cast<const float*>(b), nu2, X, (int)k, G,
+                                  S->partial.as<double>(), grid, nullptr, stream);
+  return gradient_launch<double>(reinterpret_cast<const double*>(A), n, d, lda,
+                                 reinterpret_cast<const double*>(b), nu2, X, (int)k, G,
+                                 S->partial.as<double>(), grid, nullptr, stream);
+}
+
+static rs_status grad_any(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
+                          int64_t lda, const void* b, double nu2, const double* X, int k, double* G,
+                          const int* status, hipStream_t s) {
+  const int grid = grad_partial_blocks(n);
+  RS_TRY(S.partial.ensure((size_t)grid * k * d * sizeof(double)));
+  if (a_t == RS_F32)
+    return gradient_launch<float>(reinterpret_cast<const float*>(A), n, d, lda,
+                                  reinterpret_cast<const float*>(b), nu2, X, k, G,
+                                  S.partial.as<double>(), grid, status, s);
+  return gradient_launch<double>(reinterpret_cast<const double*>(A), n, d, lda,
+                                 reinterpret_cast<const double*>(b), nu2, X, k, G,
+                                 S.partial.as<double>(), grid, status, s);
+}
+
+rs_status rs_ihs_step(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, const void* b,
+                      double nu2, const rs_factor* F, const rs_ihs_params* p, rs_variant variant,
+                      rs_ihs_state* st, rs_step_result* out, hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_ihs_step"));
+  if (!b || !F || !p || !st || !out || !st->x || !st->x_prev || !st->g || !st->gtilde)
+    return set_error(RS_ERR_ARG, "rs_ihs_step: null argument");
+  if (F->d != d) return set_error(RS_ERR_SHAPE, "rs_ihs_step: factor built for another d");
+  if (st->t < 1) return set_error(RS_ERR_ARG, "rs_ihs_step: t must start at 1");
+  const int K = variant == RS_VARIANT_POLYAK ? 2 : 1;
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  RS_TRY(S->vecs.ensure((size_t)6 * d * sizeof(double)));
+  const int nrp = apply_blocks(d);
+  RS_TRY(S->rpart.ensure((size_t)nrp * 4 * sizeof(double)));
+  RS_TRY(S->ctl.ensure(sizeof(DevCtl)));
+  RS_TRY(S->ev.ensure(sizeof(int32_t) * 4));
+  double* X = S->vecs.as<double>();
+  double* G = X + 2 * d;
+  double* GT = X + 4 * d;
+  DevCtl h{};
+  h.r_t = st->r_t;
+  h.r_1 = st->r_1;
+  h.r_ref = 1.0;
+  h.t = st->t;
+  h.status = RS_CTL_RUNNING;
+  h.at_cap = 0;
+  DevCtl* dctl = S->ctl.as<DevCtl>();
+  RS_HIP(hipMemcpyAsync(dctl, &h, sizeof(DevCtl), hipMemcpyHostToDevice, stream));
+  CtlParams cp{p->mu_p, p->beta_p, p->mu_gd, p->cbar_p, p->cbar_gd, -1.0, INT64_MAX};
+  const int* status = &dctl->status;
+  RS_TRY(candidates_launch(K, d, st->x, st->x_prev, st->gtilde, X, p->mu_p, p->beta_p, p->mu_gd,
+                           status, stream));
+  RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
+  RS_TRY(apply_launch(F->Hinv.as<double>(), F->dp, d, G, K, GT, S->rpart.as<double>(), status,
+                      stream));
+  RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, st->x, st->x_prev,
+                       st->g, st->gtilde, S->ev.as<int32_t>(), 0, stream));
+  RS_HIP(hipMemcpyAsync(&h, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
+  RS_HIP(hipStreamSynchronize(stream));
+  if (h.status == RS_CTL_NONFINITE) return set_error(RS_ERR_NONFINITE, "rs_ihs_step: non-finite decrement");
+  out->r_p = K == 2 ? h.last_r[0] : std::nan("");
+  out->r_gd = h.last_r[1];
+  if (h.status == RS_CTL_DOUBLE) {
+    out->accepted = -1;
+  } else {
+    out->accepted = (h.polyak > 0) ? 0 : 1;
+    st->r_t = h.r_t;
+    st->t = h.t;
+  }
+  return RS_OK;
+}
+
+void rs_solve_opts_default(rs_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->kind = RS_SKETCH_SRHT;
+  o->variant = RS_VARIANT_POLYAK;
+  o->resample = RS_RESAMPLE_FRESH;
+  o->sketch_dtype = RS_F32;
+  o->rho = 0.1;
+  o->eta = 0.01;
+  o->m_init = 1;
+  o->m_max = 0;
+  o->tol = 1e-7;
+  o->max_iter = 200;
+  o->seed = 0;
+  o->check_every = 4;
+}
+
+rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                            const void* b, double nu2, const rs_solve_opts* opts, double* x,
+                            rs_solve_info* info, hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
+  if (!b || !opts || !x || !info) return set_error(RS_ERR_ARG, "rs_adaptive_solve: null argument");
+  if (n < d) return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: needs n >= d");
+  if (!(nu2 > 0.0) || !std::isfinite(nu2))
+    return set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: nu^2 must be positive");
+  if (!(opts->tol >= 0.0)) return set_error(RS_ERR_ARG, "rs_adaptive_solve: tol must be >= 0");
+  if (opts->max_iter < 1) return set_error(RS_ERR_ARG, "rs_adaptive_solve: max_iter must be >= 1");
+  RS_TRY(check_sa_type(a_t, opts->sketch_dtype));
+  rs_ihs_params prm;
+  RS_TRY(rs_params(opts->kind, opts->rho, opts->eta, &prm));
+  const bool srht = opts->kind == RS_SKETCH_SRHT;
+  const int64_t npad = next_pow2(n);
+  if (srht && npad > (int64_t)1 << 20)
+    return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: SRHT padded n above 2^20");
+  int64_t m_cap = srht ? npad : n;
+  if (opts->m_max > 0) m_cap = std::min<int64_t>(m_cap, opts->m_max);
+  int64_t m = std::min<int64_t>(std::max<int64_t>(opts->m_init, 1), m_cap);
+  const int K = opts->variant == RS_VARIANT_POLYAK ? 2 : 1;
+  const int check_every = std::max(1, (int)opts->check_every);
+  const rs_dtype sa_t = opts->sketch_dtype;
+  const size_t sa_es = dtype_size(sa_t);
+  uint32_t sid = 0;
+
+  std::memset(info, 0, sizeof(*info));
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+
+  // scratch sized for this problem
+  const int nrp = apply_blocks(d);
+  RS_TRY(S->vecs.ensure((size_t)(4 + 3 * 2) * d * sizeof(double)));
+  RS_TRY(S->rpart.ensure((size_t)nrp * 4 * sizeof(double)));
+  RS_TRY(S->ctl.ensure(sizeof(DevCtl)));
+  const int ev_cap = (int)std::min<int64_t>(opts->max_iter + 1, 1 << 20);
+  RS_TRY(S->ev.ensure((size_t)ev_cap * sizeof(int32_t)));
+  RS_TRY(S->info.ensure(sizeof(int), true));
+  if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
+  double* x_prev = S->vecs.as<double>();
+  double* g = x_prev + d;
+  double* gt = g + d;
+  double* gref = gt + d;
+  double* X = gref + d;
+  double* G = X + 2 * d;
+  double* GT = G + 2 * d;
+  DevCtl* dctl = S->ctl.as<DevCtl>();
+  int* finfo = S->info.as<int>();
+  const int* status = &dctl->status;
+  RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
+
+  const CtlParams cp{prm.mu_p, prm.beta_p, prm.mu_gd, prm.cbar_p, prm.cbar_gd, opts->tol,
+                     opts->max_iter};
+  const int64_t ldsa = d;
+
+  auto sketch_and_factor = [&](int64_t mm, uint32_t id) -> rs_status {
+    RS_TRY(S->sa.ensure((size_t)mm * ldsa * sa_es));
+    if (srht) {
+      RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, nullptr,
+                      nullptr, stream));
+    } else {
+      RS_TRY(gauss_launch(A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, stream));
+    }
+    RS_TRY(S->fM.ensure(factor_bytes_M(mm, d)));
+    RS_TRY(S->fLinv.ensure(factor_bytes_M(mm, d)));
+    RS_TRY(S->fHinv.ensure(factor_bytes_Hinv(d)));
+    if (mm < d) RS_TRY(S->fCw.ensure(factor_bytes_Cw(mm, d)));
+    FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
+                     S->fCw.as<double>(), finfo};
+    return factor_build(FB, S->sa.p, sa_t, mm, d, ldsa, nu2, stream);
+  };
+  const int64_t dp = (d + 63) / 64 * 64;
+  const double* Hinv_ptr = nullptr;
+
+  std::vector<int32_t> dbl_t;   // step index of each doubling
+  std::vector<int64_t> dbl_m;   // m after it
+
+  RS_TRY(sketch_and_factor(m, sid));
+  Hinv_ptr = S->fHinv.as<double>();
+  // g_1, gtilde_1, r_1
+  RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
+  RS_TRY(apply_launch(Hinv_ptr, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
+  RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, opts->tol, opts->max_iter, d, G, GT, x,
+                           x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream));
+
+  DevCtl h{};
+  int64_t applies = 1;
+  rs_status result = RS_OK;
+  for (;;) {
+    // read the control record and the factor flag
+    RS_HIP(hipMemcpyAsync(S->host_pinned, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
+    RS_HIP(hipMemcpyAsync((char*)S->host_pinned + 512, finfo, sizeof(int), hipMemcpyDeviceToHost,
+                          stream));
+    RS_HIP(hipStreamSynchronize(stream));
+    std::memcpy(&h, S->host_pinned, sizeof(DevCtl));
+    int fbad = 0;
+    std::memcpy(&fbad, (char*)S->host_pinned + 512, sizeof(int));
+    if (fbad) {
+      result = set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: sketched Hessian factor failed");
+      break;
+    }
+    if (h.status == RS_CTL_RUNNING) {
+      for (int it = 0; it < check_every; ++it) {
+        RS_TRY(candidates_launch(K, d, x, x_prev, gt, X, prm.mu_p, prm.beta_p, prm.mu_gd, status,
+                                 stream));
+        RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
+        RS_TRY(apply_launch(Hinv_ptr, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
+        RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
+                             gt, S->ev.as<int32_t>(), ev_cap, stream));
+      }
+      continue;
+    }
+    if (h.status == RS_CTL_DOUBLE) {
+      m = std::min<int64_t>(2 * m, m_cap);
+      if (opts->resample == RS_RESAMPLE_FRESH) ++sid;
+      dbl_t.push_back((int32_t)h.t);
+      dbl_m.push_back(m);
+      RS_TRY(sketch_and_factor(m, sid));
+      RS_TRY(pack2_launch(d, g, gref, X, stream));
+      RS_TRY(apply_launch(Hinv_ptr, dp, d, X, 2, GT, S->rpart.as<double>(), nullptr, stream));
+      RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, opts->tol, d, GT, gt,
+                                  m == m_cap ? 1 : 0, stream));
+      applies += 1;
+      continue;
+    }
+    if (h.status == RS_CTL_CONVERGED) result = RS_OK;
+    else if (h.status == RS_CTL_NONFINITE)
+      result = set_error(RS_ERR_NONFINITE, "rs_adaptive_solve: non-finite decrement");
+    else
+      result = set_error(RS_ERR_NO_CONVERGENCE,
+                         h.status == RS_CTL_STUCK ? "rs_adaptive_solve: no progress at m_max"
+                                                  : "rs_adaptive_solve: max_iter reached");
+    break;
+  }
+
+  // event log: doublings at step t come before the step accepted at t
+  const int64_t tfin = h.t;
+  std::vector<int32_t> kinds((size_t)std::max<int64_t>(tfin, 1), -1);
+  if (tfin > 1) {
+    const int64_t cnt = std::min<int64_t>(tfin, ev_cap);
+    RS_HIP(hipMemcpy(kinds.data(), S->ev.p, (size_t)cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  int64_t ne = 0;
+  size_t di = 0;
+  int64_t m_now = std::min<int64_t>(std::max<int64_t>(opts->m_init, 1), m_cap);
+  auto push = [&](int kind, int64_t t, int64_t mm) {
+    if (ne < RS_MAX_EVENTS) {
+      info->event_kind[ne] = kind;
+      info->event_t[ne] = (int32_t)t;
+      info->event_m[ne] = mm;
+    }
+    ++ne;
+  };
+  for (int64_t t = 1; t <= tfin; ++t) {
+    while (di < dbl_t.size() && dbl_t[di] == t) {
+      m_now = dbl_m[di];
+      push(RS_EVENT_DOUBLE, t, m_now);
+      ++di;
+    }
+    if (t < tfin && t < (int64_t)kinds.size() && kinds[t] >= 0)
+      push(kinds[t] == 0 ? RS_EVENT_POLYAK : RS_EVENT_GD, t, m_now);
+  }
+  info->status = result;
+  info->m_final = m;
+  info->doublings = (int64_t)dbl_t.size();
+  info->steps = h.steps;
+  info->grad_passes = h.passes;
+  info->applies = applies + h.passes;
+  info->accepted_polyak = h.polyak;
+  info->accepted_gd = h.gd;
+  info->r_final = h.r_t;
+  info->r_ref = h.r_ref;
+  info->n_events = std::min<int64_t>(ne, RS_MAX_EVENTS);
+  return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations shared by the librs translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "rs.h"
+#include "rs_device.hpp"
+
+namespace rs {
+
+rs_status set_error(rs_status st, const char* msg);
+rs_status check_launch(const char* what);
+int device_cus();
+// kernel timing hooks (no-ops unless rs_profile_enable(1))
+void prof_begin(hipStream_t s);
+void prof_end(hipStream_t s);
+
+// ---------------------------------------------------------------- SRHT
+struct SrhtBuffers {
+  uint32_t* hist;      // 4096 bins, zero between calls
+  int8_t* signs;       // npad
+  int32_t* kmap;       // npad: row -> sample index or -1
+  void* state;         // selection record
+  uint64_t* cand_key;  // candidate cap
+  int64_t* cand_idx;
+  uint32_t* blk_less;  // npad / 1024
+  int32_t* used;       // 1024, zero between calls
+  int32_t* qmap;       // 1024
+  int32_t* qlist;      // 1024
+  int32_t* qcount;     // 1
+  void* zbuf;          // pass-1 output: n1 * Qmax rows of ldz elements
+};
+rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t npad, int64_t m,
+                      int64_t n2, int64_t* rows, hipStream_t s);
+template <typename T>
+rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
+                         int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
+                         int64_t Qmax, hipStream_t s);
+size_t srht_state_bytes();
+int srht_cand_cap();
+int srht_compact_block();
+
+// ---------------------------------------------------------------- Gaussian
+rs_status gauss_launch(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
+                       uint64_t seed, uint32_t sid, void* SA, rs_dtype sa_t, int64_t ldsa,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------- factor
+struct FactorBuffers {
+  double* M;     // pad64(p)^2
+  double* Linv;  // pad64(p)^2
+  double* Hinv;  // pad64(d)^2
+  double* Cw;    // pad64(m) x pad64(d) (Woodbury branch)
+  int* info;     // 1: a pivot failed
+};
+rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, int64_t m, int64_t d,
+                       int64_t ldsa, double nu2, hipStream_t s);
+size_t factor_bytes_M(int64_t m, int64_t d);
+size_t factor_bytes_Hinv(int64_t d);
+size_t factor_bytes_Cw(int64_t m, int64_t d);
+
+// ---------------------------------------------------------------- gradient
+int grad_partial_blocks(int64_t n);
+template <typename T>
+rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
+                          const double* X, int k, double* G, double* partial, int grid,
+                          const int* status, hipStream_t s);
+
+// ---------------------------------------------------------------- apply
+int apply_blocks(int64_t d);
+rs_status apply_launch(const double* Hinv, int64_t ldh, int64_t d, const double* G, int k,
+                       double* Y, double* rpart, const int* status, hipStream_t s);
+rs_status rsum_launch(const double* rpart, int nblk, int k, double* r, hipStream_t s);
+
+// ---------------------------------------------------------------- control
+enum {
+  RS_CTL_RUNNING = 0,
+  RS_CTL_CONVERGED = 1,
+  RS_CTL_DOUBLE = 2,
+  RS_CTL_STUCK = 3,
+  RS_CTL_MAXITER = 4,
+  RS_CTL_NONFINITE = 5
+};
+
+struct DevCtl {
+  double r_t, r_1, r_ref;
+  double last_r[2];
+  int64_t t, steps, passes, polyak, gd;
+  int32_t status;
+  int32_t at_cap;
+};
+
+struct CtlParams {
+  double mu_p, beta_p, mu_gd, cbar_p, cbar_gd, tol;
+  int64_t max_iter;
+};
+
+rs_status candidates_launch(int K, int64_t d, const double* x, const double* x_prev,
+                            const double* gt, double* X, double mu_p, double beta_p, double mu_gd,
+                            const int* status, hipStream_t s);
+rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const CtlParams& p,
+                        int64_t d, const double* X, const double* G, const double* GT, double* x,
+                        double* x_prev, double* g, double* gt, int32_t* ev_kind, int ev_cap,
+                        hipStream_t s);
+rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
+                            int64_t max_iter, int64_t d, const double* G, const double* GT,
+                            const double* x, double* x_prev, double* g, double* gt, double* gref,
+                            int at_cap, hipStream_t s);
+rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
+                               const double* GT, double* gt, int at_cap, hipStream_t s);
+rs_status pack2_launch(int64_t d, const double* a, const double* b, double* out, hipStream_t s);
+
+}  // namespace rs

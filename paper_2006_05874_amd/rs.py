@@ -1,0 +1,318 @@
+"""ctypes binding of librs (include/rs.h): argument marshalling only.
+
+Every computation runs in the HIP library.  torch provides device memory and
+the current HIP stream.  Loading fails loudly when librs.so is missing: there
+is no CPU fallback.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librs.so")
+
+RS_OK, RS_ERR_ARG, RS_ERR_SHAPE, RS_ERR_NOT_POW2, RS_ERR_NOT_SPD = 0, 1, 2, 3, 4
+RS_ERR_NONFINITE, RS_ERR_NO_CONVERGENCE, RS_ERR_OOM, RS_ERR_HIP, RS_ERR_UNSUPPORTED = 5, 6, 7, 8, 9
+STATUS_NAMES = {0: "ok", 1: "arg", 2: "shape", 3: "not_pow2", 4: "not_spd", 5: "nonfinite",
+                6: "no_convergence", 7: "oom", 8: "hip", 9: "unsupported"}
+
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+                "fp8": torch.uint8}
+SKETCH = {"srht": 0, "gaussian": 1}
+RESAMPLE = {"fresh": 0, "nested": 1}
+VARIANT = {"polyak": 0, "gd": 1}
+EVENT_NAMES = {0: "polyak", 1: "gd", 2: "double"}
+RS_MAX_EVENTS = 512
+
+
+class RsError(RuntimeError):
+    def __init__(self, status, where, msg):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.name}: {msg}")
+
+
+class IhsParams(ctypes.Structure):
+    _fields_ = [("mu_gd", ctypes.c_double), ("mu_p", ctypes.c_double),
+                ("beta_p", ctypes.c_double), ("cbar_gd", ctypes.c_double),
+                ("cbar_p", ctypes.c_double)]
+
+
+class IhsState(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("x_prev", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("gtilde", ctypes.c_void_p), ("r_t", ctypes.c_double), ("r_1", ctypes.c_double),
+                ("t", ctypes.c_int64)]
+
+
+class StepResult(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("r_p", ctypes.c_double), ("r_gd", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("variant", ctypes.c_int), ("resample", ctypes.c_int),
+                ("sketch_dtype", ctypes.c_int), ("rho", ctypes.c_double), ("eta", ctypes.c_double),
+                ("m_init", ctypes.c_int64), ("m_max", ctypes.c_int64), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("reserved", ctypes.c_int32),
+                ("m_final", ctypes.c_int64), ("doublings", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("grad_passes", ctypes.c_int64),
+                ("applies", ctypes.c_int64), ("accepted_polyak", ctypes.c_int64),
+                ("accepted_gd", ctypes.c_int64), ("r_final", ctypes.c_double),
+                ("r_ref", ctypes.c_double), ("n_events", ctypes.c_int64),
+                ("event_kind", ctypes.c_int32 * RS_MAX_EVENTS),
+                ("event_t", ctypes.c_int32 * RS_MAX_EVENTS),
+                ("event_m", ctypes.c_int64 * RS_MAX_EVENTS),
+                ("ms_sketch", ctypes.c_double), ("ms_factor", ctypes.c_double),
+                ("ms_iterate", ctypes.c_double)]
+
+
+EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
+           "rs_factor_apply", "rs_factor_destroy", "rs_gradient", "rs_ihs_step",
+           "rs_solve_opts_default", "rs_adaptive_solve", "rs_last_error", "rs_version",
+           "rs_profile_enable", "rs_profile_read"]
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load librs.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"librs.so not built at {path}; run paper_2006_05874_amd.build.build()")
+    L = ctypes.CDLL(path)
+    vp, i64, u64, u32, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                              ctypes.c_double)
+    c_int = ctypes.c_int
+    L.rs_params.argtypes = [c_int, dbl, dbl, ctypes.POINTER(IhsParams)]
+    L.rs_sketch_srht.argtypes = [vp, c_int, i64, i64, i64, i64, u64, u32, vp, c_int, i64, vp, vp,
+                                 vp, vp]
+    L.rs_sketch_gaussian.argtypes = [vp, c_int, i64, i64, i64, i64, u64, u32, vp, c_int, i64, vp,
+                                     vp]
+    L.rs_factor_woodbury.argtypes = [vp, c_int, vp, i64, i64, i64, dbl, ctypes.POINTER(vp), vp]
+    L.rs_factor_apply.argtypes = [vp, vp, vp, vp, i64, vp]
+    L.rs_factor_destroy.argtypes = [vp]
+    L.rs_factor_destroy.restype = None
+    L.rs_gradient.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, i64, vp, vp]
+    L.rs_ihs_step.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, ctypes.POINTER(IhsParams),
+                              c_int, ctypes.POINTER(IhsState), ctypes.POINTER(StepResult), vp]
+    L.rs_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+    L.rs_solve_opts_default.restype = None
+    L.rs_adaptive_solve.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, ctypes.POINTER(SolveOpts),
+                                    vp, ctypes.POINTER(SolveInfo), vp]
+    L.rs_profile_enable.argtypes = [c_int]
+    L.rs_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    L.rs_last_error.restype = ctypes.c_char_p
+    L.rs_version.restype = ctypes.c_char_p
+    for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
+                 "rs_factor_apply", "rs_gradient", "rs_ihs_step", "rs_adaptive_solve",
+                 "rs_profile_enable", "rs_profile_read"]:
+        getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def _check(st, where):
+    if st != RS_OK:
+        raise RsError(st, where, load().rs_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mat(A, where):
+    if not A.is_cuda:
+        raise ValueError(f"{where}: A must be a device tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError(f"{where}: A must be 2-D row-major (unit column stride)")
+    if A.dtype == torch.float32:
+        return 1
+    if A.dtype == torch.float64:
+        return 0
+    raise ValueError(f"{where}: A must be float32 or float64")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def padded(n, d, dtype=torch.float32, device="cuda"):
+    """Row-major (n, d) tensor with a 16-byte-multiple leading dimension (view)."""
+    es = torch.tensor([], dtype=dtype).element_size()
+    vec = 16 // es
+    ld = (d + vec - 1) // vec * vec
+    return torch.zeros(n, ld, dtype=dtype, device=device)[:, :d]
+
+
+# ------------------------------------------------------------------ entry points
+def rs_params(kind="srht", rho=0.1, eta=0.01):
+    p = IhsParams()
+    _check(load().rs_params(SKETCH[kind], rho, eta, ctypes.byref(p)), "rs_params")
+    return {k: getattr(p, k) for k, _ in IhsParams._fields_}
+
+
+def rs_sketch_srht(A, m, seed=0, sketch_id=0, sa_dtype=None, rows=False, signs=False):
+    a_t = _mat(A, "rs_sketch_srht")
+    n, d = A.shape
+    sa_dtype = sa_dtype or ("f64" if a_t == 0 else "f32")
+    SA = torch.empty(m, d, dtype=TORCH_DTYPES[sa_dtype], device=A.device)
+    npad = 1 << max(0, math.ceil(math.log2(n)))
+    R = torch.empty(m, dtype=torch.int64, device=A.device) if rows else None
+    E = torch.empty(npad, dtype=torch.int8, device=A.device) if signs else None
+    st = load().rs_sketch_srht(_ptr(A), a_t, n, d, A.stride(0), m, seed, sketch_id, _ptr(SA),
+                               DTYPES[sa_dtype], SA.stride(0), None, _ptr(R), _ptr(E), _stream())
+    _check(st, "rs_sketch_srht")
+    out = [SA]
+    if rows:
+        out.append(R)
+    if signs:
+        out.append(E)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def rs_sketch_gaussian(A, m, seed=0, sketch_id=0, sa_dtype=None):
+    a_t = _mat(A, "rs_sketch_gaussian")
+    n, d = A.shape
+    sa_dtype = sa_dtype or ("f64" if a_t == 0 else "f32")
+    SA = torch.empty(m, d, dtype=TORCH_DTYPES[sa_dtype], device=A.device)
+    st = load().rs_sketch_gaussian(_ptr(A), a_t, n, d, A.stride(0), m, seed, sketch_id, _ptr(SA),
+                                   DTYPES[sa_dtype], SA.stride(0), None, _stream())
+    _check(st, "rs_sketch_gaussian")
+    return SA
+
+
+class Factor:
+    """Handle from rs_factor_woodbury; keeps SA alive while in use."""
+
+    def __init__(self, SA, nu2):
+        if SA.dtype == torch.float32:
+            sa_t = DTYPES["f32"]
+        elif SA.dtype == torch.float64:
+            sa_t = DTYPES["f64"]
+        elif SA.dtype == torch.bfloat16:
+            sa_t = DTYPES["bf16"]
+        else:
+            raise ValueError("SA dtype")
+        self.SA = SA
+        self.m, self.d = SA.shape
+        h = ctypes.c_void_p()
+        st = load().rs_factor_woodbury(_ptr(SA), sa_t, None, self.m, self.d, SA.stride(0), nu2,
+                                       ctypes.byref(h), _stream())
+        _check(st, "rs_factor_woodbury")
+        self.handle = h
+
+    def apply(self, G):
+        """(H_S^-1 G, r) for G of shape (k, d) float64 (k right-hand sides)."""
+        G = G.contiguous()
+        k = G.shape[0]
+        GT = torch.empty_like(G)
+        r = torch.empty(k, dtype=torch.float64, device=G.device)
+        _check(load().rs_factor_apply(self.handle, _ptr(G), _ptr(GT), _ptr(r), k, _stream()),
+               "rs_factor_apply")
+        return GT, r
+
+    def close(self):
+        if self.handle:
+            torch.cuda.current_stream().synchronize()
+            load().rs_factor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rs_factor_woodbury(SA, nu2):
+    return Factor(SA, nu2)
+
+
+def rs_factor_apply(F, G):
+    return F.apply(G)
+
+
+def rs_gradient(A, b, nu2, X):
+    """G = A^T (A X - b) + nu2 X for X of shape (k, d) float64."""
+    a_t = _mat(A, "rs_gradient")
+    n, d = A.shape
+    X = X.contiguous()
+    G = torch.empty_like(X)
+    st = load().rs_gradient(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2, _ptr(X),
+                            X.shape[0], _ptr(G), _stream())
+    _check(st, "rs_gradient")
+    return G
+
+
+def rs_ihs_step(A, b, nu2, F, params, variant, state):
+    """One step; ``state`` is a dict with device tensors x, x_prev, g, gtilde and
+    host values r_t, r_1, t (updated in place)."""
+    a_t = _mat(A, "rs_ihs_step")
+    n, d = A.shape
+    p = IhsParams(**{k: params[k] for k, _ in IhsParams._fields_})
+    s = IhsState(_ptr(state["x"]), _ptr(state["x_prev"]), _ptr(state["g"]), _ptr(state["gtilde"]),
+                 state["r_t"], state["r_1"], state["t"])
+    out = StepResult()
+    st = load().rs_ihs_step(_ptr(A), a_t, n, d, A.stride(0), _ptr(b), nu2, F.handle,
+                            ctypes.byref(p), VARIANT[variant], ctypes.byref(s), ctypes.byref(out),
+                            _stream())
+    _check(st, "rs_ihs_step")
+    state["r_t"], state["t"] = s.r_t, s.t
+    return {"accepted": out.accepted, "r_p": out.r_p, "r_gd": out.r_gd}
+
+
+def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh",
+                      sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
+                      max_iter=200, seed=0, check_every=4, x0=None, raise_on_error=True):
+    """Algorithm 1 end to end.  Returns (x float64 tensor, info dict)."""
+    a_t = _mat(A, "rs_adaptive_solve")
+    n, d = A.shape
+    o = SolveOpts()
+    load().rs_solve_opts_default(ctypes.byref(o))
+    o.kind, o.variant, o.resample = SKETCH[kind], VARIANT[variant], RESAMPLE[resample]
+    o.sketch_dtype = DTYPES[sketch_dtype or ("f64" if a_t == 0 else "f32")]
+    o.rho, o.eta, o.m_init, o.m_max, o.tol = rho, eta, m_init, m_max, tol
+    o.max_iter, o.seed, o.check_every = max_iter, seed, check_every
+    x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
+         else x0.to(torch.float64).contiguous().clone())
+    info = SolveInfo()
+    st = load().rs_adaptive_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+                                  ctypes.byref(o), _ptr(x), ctypes.byref(info), _stream())
+    res = {
+        "status": STATUS_NAMES.get(info.status, str(info.status)),
+        "m_final": info.m_final, "doublings": info.doublings, "steps": info.steps,
+        "grad_passes": info.grad_passes, "applies": info.applies,
+        "accepted_polyak": info.accepted_polyak, "accepted_gd": info.accepted_gd,
+        "r_final": info.r_final, "r_ref": info.r_ref,
+        "events": [(int(info.event_t[i]), EVENT_NAMES[int(info.event_kind[i])],
+                    int(info.event_m[i])) for i in range(info.n_events)],
+    }
+    if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
+        _check(st, "rs_adaptive_solve")
+    res["status_code"] = st
+    return x, res
+
+
+def rs_profile_enable(on=True):
+    _check(load().rs_profile_enable(1 if on else 0), "rs_profile_enable")
+
+
+def rs_profile_read():
+    """(launches, total_ms) of the bracketed gradient partial-sum launches."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().rs_profile_read(ctypes.byref(n), ctypes.byref(ms)), "rs_profile_read")
+    return n.value, ms.value
+
+
+def version():
+    return load().rs_version().decode()

@@ -1,0 +1,115 @@
+"""CPU-side checks of librs: it loads, exports every symbol declared in
+include/rs.h, and its host-only logic (parameter formulas, argument checks that
+fail before any device work) behaves.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import ihs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rs.h")
+LIB = os.path.join(ROOT, "paper_2006_05874_amd", "librs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2006_05874_amd import build
+        build.build(verbose=False)
+    from paper_2006_05874_amd import rs
+    return rs.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ["rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury", "rs_ihs_step",
+                 "rs_adaptive_solve", "rs_factor_apply", "rs_gradient", "rs_params"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_declares_every_export():
+    from paper_2006_05874_amd import rs
+    assert set(declared_functions()) <= set(rs.EXPORTS)
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.rs_version()
+
+
+@pytest.mark.parametrize("kind,rho,eta", [("srht", 0.1, 0.01), ("srht", 0.37, 0.01),
+                                          ("gaussian", 0.1, 0.01), ("gaussian", 0.18, 0.004)])
+def test_params_match_oracle(lib, kind, rho, eta):
+    from paper_2006_05874_amd import rs
+    got = rs.rs_params(kind, rho, eta)
+    want = ihs.params_for(kind, rho, eta)
+    for k in ["mu_gd", "mu_p", "beta_p", "cbar_gd", "cbar_p"]:
+        assert abs(got[k] - getattr(want, k)) < 1e-15 * max(1.0, abs(getattr(want, k)))
+
+
+@pytest.mark.parametrize("kind,rho,eta", [("srht", 0.0, 0.01), ("srht", 1.0, 0.01),
+                                          ("gaussian", 0.5, 0.01), ("gaussian", 0.1, 0.05)])
+def test_params_reject_outside_domain(lib, kind, rho, eta):
+    from paper_2006_05874_amd import rs
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_params(kind, rho, eta)
+    assert e.value.name == "arg"
+
+
+def test_null_and_shape_errors_before_any_device_work(lib):
+    vp = ctypes.c_void_p
+    st = lib.rs_sketch_srht(vp(0), 1, 100, 10, 12, 4, 0, 0, vp(16), 1, 10, vp(0), vp(0), vp(0),
+                            vp(0))
+    assert st == 1 and b"null" in lib.rs_last_error()
+    # lda not a multiple of 16 bytes
+    st = lib.rs_gradient(vp(256), 1, 100, 10, 10, vp(256), 1.0, vp(256), 1, vp(256), vp(0))
+    assert st == 1 and b"lda" in lib.rs_last_error()
+    # misaligned A
+    st = lib.rs_gradient(vp(260), 1, 100, 10, 12, vp(256), 1.0, vp(256), 1, vp(256), vp(0))
+    assert st == 1 and b"aligned" in lib.rs_last_error()
+    # k out of range
+    st = lib.rs_gradient(vp(256), 1, 100, 10, 12, vp(256), 1.0, vp(256), 5, vp(256), vp(0))
+    assert st == 1
+    # m above the padded row count
+    st = lib.rs_sketch_srht(vp(256), 1, 100, 10, 12, 129, 0, 0, vp(256), 1, 10, vp(0), vp(0),
+                            vp(0), vp(0))
+    assert st == 2
+    # F64 A with F32 SA is not offered
+    st = lib.rs_sketch_srht(vp(256), 0, 100, 10, 10, 4, 0, 0, vp(256), 1, 10, vp(0), vp(0),
+                            vp(0), vp(0))
+    assert st == 9
+
+
+def test_solver_argument_errors(lib):
+    from paper_2006_05874_amd import rs
+    vp = ctypes.c_void_p
+    o = rs.SolveOpts()
+    lib.rs_solve_opts_default(ctypes.byref(o))
+    assert o.rho == 0.1 and o.m_init == 1 and o.tol == 1e-7 and o.check_every == 4
+    info = rs.SolveInfo()
+    # n < d
+    st = lib.rs_adaptive_solve(vp(256), 1, 8, 16, 16, vp(256), 0.1, ctypes.byref(o), vp(256),
+                               ctypes.byref(info), vp(0))
+    assert st == 2
+    # nu^2 <= 0 is not positive definite
+    st = lib.rs_adaptive_solve(vp(256), 1, 64, 16, 16, vp(256), 0.0, ctypes.byref(o), vp(256),
+                               ctypes.byref(info), vp(0))
+    assert st == 4
+    # Gaussian rho outside Definition 3.1's domain
+    o.kind, o.rho = 1, 0.5
+    st = lib.rs_adaptive_solve(vp(256), 1, 64, 16, 16, vp(256), 0.1, ctypes.byref(o), vp(256),
+                               ctypes.byref(info), vp(0))
+    assert st == 1
