@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default="polyak", choices=["polyak", "gd"])
     ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device-to-device copy first (a counter "
+                         "reference for HBM traffic measurements)")
     return ap.parse_args()
 
 
@@ -95,6 +98,13 @@ def main():
             out.append((nu2, x, info))
         return out
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

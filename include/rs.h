@@ -225,9 +225,12 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
 /* Diagnostics for measuring the dominant kernel (not part of the method).
  * While enabled, every launch of the gradient's partial-sum kernel (the pass
  * over A) is bracketed by two HIP events recorded on the stream it is launched
- * on.  rs_profile_read synchronizes those events, returns the number of
- * bracketed launches and their summed duration in milliseconds (host
- * pointers), and clears the record.  Not thread-safe. */
+ * on, and the kernel raises a device flag when it does its work (launches
+ * queued behind a raised status flag return at once and are not counted).
+ * rs_profile_read synchronizes the device, returns the number of launches that
+ * did their work and their summed duration in milliseconds (host pointers),
+ * and clears the record.  At most 65536 launches are recorded between reads.
+ * Not thread-safe. */
 rs_status rs_profile_enable(int on);
 rs_status rs_profile_read(int64_t* launches, double* total_ms);
 

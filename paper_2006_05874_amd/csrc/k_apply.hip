@@ -70,7 +70,7 @@ __global__ void k_rsum(const double* __restrict__ rpart, int nblk, int K, double
   }
 }
 
-constexpr int kApplyRPW = 4;
+constexpr int kApplyRPW = 2;
 
 int apply_blocks(int64_t d) { return (int)((d + 4 * kApplyRPW - 1) / (4 * kApplyRPW)); }
 

@@ -34,7 +34,7 @@ __device__ __forceinline__ float load_as<float, uint16_t>(uint16_t v) { return b
 
 template <typename TIn, typename TAcc, bool TN>
 __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64_t ld, int64_t p,
-                                              int64_t q, double nu2, double* __restrict__ C,
+                                              int64_t q, int64_t qchunk, TAcc* __restrict__ P,
                                               int64_t ldc) {
   // triangular tile index -> (I, J), J <= I
   const int64_t bid = blockIdx.x;
@@ -59,7 +59,9 @@ __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc4{0, 0, 0, 0};
 
-  for (int64_t l0 = 0; l0 < q; l0 += KC) {
+  const int64_t lbeg = (int64_t)blockIdx.y * qchunk;
+  const int64_t lend = lbeg + qchunk < q ? lbeg + qchunk : q;
+  for (int64_t l0 = lbeg; l0 < lend; l0 += KC) {
     // stage X(l0..l0+16, i0..i0+64) and X(l0.., j0..) : 1024 elements each
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64
       const int64_t l = l0 + kk;
       const int64_t ia = i0 + ii, ja = j0 + ii;
       TAcc va = 0, vb = 0;
-      if (l < q) {
+      if (l < lend) {
         if (ia < p) va = load_as<TAcc>(TN ? src[l * ld + ia] : src[ia * ld + l]);
         if (ja < p) vb = load_as<TAcc>(TN ? src[l * ld + ja] : src[ja * ld + l]);
       }
@@ -96,7 +98,9 @@ __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64
     }
     __syncthreads();
   }
-  // lane holds column lane % 16 of each 16x16 tile, rows per mfma16_row
+  // lane holds column lane % 16 of each 16x16 tile, rows per mfma16_row;
+  // partial Gram of this K range into slice blockIdx.y
+  TAcc* Ps = P + (int64_t)blockIdx.y * ldc * ldc;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -105,12 +109,29 @@ __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64
       for (int r = 0; r < 4; ++r) {
         const int64_t i = i0 + wr * 32 + a * 16 + mfma16_row<TAcc>(lane, r);
         const int64_t j = j0 + wc * 32 + b * 16 + (lane & 15);
-        double v = (double)acc[a][b][r];
-        if (i == j) v += nu2;
-        if (i >= p || j >= p) v = (i == j) ? 1.0 : 0.0;
-        C[i * ldc + j] = v;
-        if (I != J) C[j * ldc + i] = v;
+        Ps[i * ldc + j] = acc[a][b][r];
       }
+}
+
+// M = sum_s P[s] (fixed order, FP64) + nu2 I on the lower tiles; identity past p.
+template <typename TAcc>
+__global__ __launch_bounds__(256) void k_gram_reduce(const TAcc* __restrict__ P, int nsplit,
+                                                     int64_t p, double nu2,
+                                                     double* __restrict__ C, int64_t ldc) {
+  const int64_t bid = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= bid) ++I;
+  while (I * (I + 1) / 2 > bid) --I;
+  const int64_t J = bid - I * (I + 1) / 2;
+  const int64_t slice = ldc * ldc;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int64_t i = I * NB + e / NB, j = J * NB + e % NB;
+    double v = 0.0;
+    for (int sI = 0; sI < nsplit; ++sI) v += (double)P[sI * slice + i * ldc + j];
+    if (i == j) v += nu2;
+    if (i >= p || j >= p) v = (i == j) ? 1.0 : 0.0;
+    C[i * ldc + j] = v;
+  }
 }
 
 // ------------------------------------------------------------------ FP64 tiles
@@ -126,8 +147,11 @@ struct Opnd {
 };
 
 __device__ __forceinline__ double opnd_at(const Opnd& o, int64_t r, int64_t c) {
-  if (r >= o.rows || c >= o.cols) return 0.0;
-  return o.trans ? o.p[c * o.ld + r] : o.p[r * o.ld + c];
+  // clamped in-bounds address and a select: no branch around the load
+  const bool ok = r < o.rows && c < o.cols;
+  const int64_t rr = ok ? r : 0, cc = ok ? c : 0;
+  const double v = o.p[o.trans ? cc * o.ld + rr : rr * o.ld + cc];
+  return ok ? v : 0.0;
 }
 
 struct FOpnd {  // FP32 source, same addressing
@@ -137,8 +161,10 @@ struct FOpnd {  // FP32 source, same addressing
   bool trans;
 };
 __device__ __forceinline__ double opnd_at(const FOpnd& o, int64_t r, int64_t c) {
-  if (r >= o.rows || c >= o.cols) return 0.0;
-  return (double)(o.trans ? o.p[c * o.ld + r] : o.p[r * o.ld + c]);
+  const bool ok = r < o.rows && c < o.cols;
+  const int64_t rr = ok ? r : 0, cc = ok ? c : 0;
+  const double v = (double)o.p[o.trans ? cc * o.ld + rr : rr * o.ld + cc];
+  return ok ? v : 0.0;
 }
 struct HOpnd {  // BF16 source
   const uint16_t* p;
@@ -147,39 +173,65 @@ struct HOpnd {  // BF16 source
   bool trans;
 };
 __device__ __forceinline__ double opnd_at(const HOpnd& o, int64_t r, int64_t c) {
-  if (r >= o.rows || c >= o.cols) return 0.0;
-  return (double)bf16_to_f32(o.trans ? o.p[c * o.ld + r] : o.p[r * o.ld + c]);
+  const bool ok = r < o.rows && c < o.cols;
+  const int64_t rr = ok ? r : 0, cc = ok ? c : 0;
+  const double v = (double)bf16_to_f32(o.p[o.trans ? cc * o.ld + rr : rr * o.ld + cc]);
+  return ok ? v : 0.0;
+}
+
+// The next 32-deep chunk of both operands is loaded into registers while the
+// current one is multiplied from LDS (double-buffered, one barrier per chunk).
+constexpr int TKC = 32;
+struct TileLds {
+  double A[2][TKC][NB + 1];
+  double B[2][TKC][NB + 1];
+};
+
+template <typename OA, typename OB>
+__device__ __forceinline__ void tile_fetch(const OA& A, const OB& B, int64_t k0, double (&ra)[8],
+                                           double (&rb)[8]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int idx = t + 256 * e;                 // 0..2047
+    const int r = idx >> 5, kk = idx & 31;       // A: 64 rows x 32 k
+    ra[e] = opnd_at(A, r, k0 + kk);
+    const int kb = idx >> 6, cb = idx & 63;      // B: 32 k x 64 cols
+    rb[e] = opnd_at(B, k0 + kb, cb);
+  }
 }
 
 template <typename OA, typename OB>
-__device__ void tile_mm(double (&acc)[4][4], const OA& A, const OB& B, int64_t kd,
-                        double (*As)[NB + 1], double (*Bs)[NB + 1]) {
+__device__ void tile_mm(double (&acc)[4][4], const OA& A, const OB& B, int64_t kd, TileLds& L) {
   const int t = threadIdx.x;
   const int ty = t >> 4, tx = t & 15;
-  for (int64_t k0 = 0; k0 < kd; k0 += 16) {
+  double ra[8], rb[8];
+  tile_fetch(A, B, 0, ra, rb);
+  int buf = 0;
+  for (int64_t k0 = 0; k0 < kd; k0 += TKC) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = t * 4 + e;
-      const int r = idx >> 4, kk = idx & 15;     // A: 64 rows x 16 k
-      As[kk][r] = opnd_at(A, r, k0 + kk);
-      const int kb = idx >> 6, cb = idx & 63;    // B: 16 k x 64 cols
-      Bs[kb][cb] = opnd_at(B, k0 + kb, cb);
+    for (int e = 0; e < 8; ++e) {
+      const int idx = t + 256 * e;
+      L.A[buf][idx & 31][idx >> 5] = ra[e];
+      L.B[buf][idx >> 6][idx & 63] = rb[e];
     }
     __syncthreads();
+    if (k0 + TKC < kd) tile_fetch(A, B, k0 + TKC, ra, rb);
+#pragma unroll 8
+    for (int kk = 0; kk < TKC; ++kk) {
+      double av[4], bv[4];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+      for (int i = 0; i < 4; ++i) av[i] = L.A[buf][kk][ty * 4 + i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+      for (int j = 0; j < 4; ++j) bv[j] = L.B[buf][kk][tx * 4 + j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
     }
-    __syncthreads();
+    buf ^= 1;
   }
+  __syncthreads();
 }
 
 __device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
@@ -198,51 +250,151 @@ __device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
 //   update: M_ij -= L_ik L_jk^T (k < j <= i), Y_ij -= L_ik X_kj (i > k, j <= k).
 // Every step adds one 64^3 tile product to the critical path.
 
-// Diagonal tile k: factor in LDS (right-looking, one column per step), then
-// invert the 64x64 lower factor by forward substitution row by row.
+// 1/sqrt(x) in FP64: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// Diagonal tile k: factor and invert the 64 x 64 block in LDS, 16 columns at a
+// time.  For each 16-wide panel: one wave factors the 16 x 16 diagonal piece in
+// registers (lane i holds row i; column values move between lanes by shuffles)
+// and 16 of its lanes invert it column by column; then the whole block applies
+// the panel below it, the matching block row of the inverse, and the trailing
+// update.  X = L^-1 is carried along as the right-hand side of L X = I.
+template <int Q>
+__device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB + 1],
+                                           double (*dinv)[17], bool& bad) {
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  // A: factor the 16 x 16 block at (Q, Q)
+  if (w == 0) {
+    const int li = lane & 15;
+    double r[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) r[c] = a[Q + li][Q + c];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double piv = __shfl(r[j], j, 64);
+      bad |= !(piv > 0.0);
+      const double inv = rsqrt64(piv);
+      const double l = r[j] * inv;
+      r[j] = li > j ? l : (li == j ? piv * inv : r[j]);
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) {
+        const double lc = __shfl(l, c, 64);
+        if (li >= c) r[c] -= l * lc;
+      }
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[Q + lane][Q + c] = c <= lane ? r[c] : 0.0;
+    }
+  }
+  __syncthreads();
+  // B: lane c < 16 of wave 0 computes column c of the 16 x 16 inverse
+  if (w == 0 && lane < 16) {
+    const int c = lane;
+    double col[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = 0; l < i; ++l) acc -= a[Q + i][Q + l] * col[l];
+      col[i] = i >= c ? acc / a[Q + i][Q + i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dinv[i][c] = col[i];
+  }
+  __syncthreads();
+  // C: panel below (rows Q+16.., 16 columns) and block row Q.. of the inverse
+  constexpr int NPAN = (NB - Q - 16) * 16;
+  constexpr int NINV = 16 * (Q + 16);
+  constexpr int PER = (NPAN + NINV + 255) / 256;
+  double res[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + 256 * u;
+    double v = 0.0;
+    if (e < NPAN) {
+      const int r = Q + 16 + e / 16, c = e % 16;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) v += a[r][Q + l] * dinv[c][l];
+    } else if (e < NPAN + NINV) {
+      const int e2 = e - NPAN;
+      const int i = e2 / (Q + 16), c = e2 % (Q + 16);
+#pragma unroll
+      for (int l = 0; l < 16; ++l) v += dinv[i][l] * x[Q + l][c];
+    }
+    res[u] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + 256 * u;
+    if (e < NPAN) {
+      a[Q + 16 + e / 16][Q + e % 16] = res[u];
+    } else if (e < NPAN + NINV) {
+      const int e2 = e - NPAN;
+      x[Q + e2 / (Q + 16)][e2 % (Q + 16)] = res[u];
+    }
+  }
+  __syncthreads();
+  // D: trailing update of the lower part and of the rows of Y below the panel
+  constexpr int NR = NB - Q - 16;
+  constexpr int NUPD = NR * NR;
+  constexpr int NY = NR * (Q + 16);
+  if constexpr (NR > 0) for (int e = t; e < NUPD + NY; e += 256) {
+    if (e < NUPD) {
+      const int r = Q + 16 + e / NR, c = Q + 16 + e % NR;
+      if (c <= r) {
+        double v = a[r][c];
+#pragma unroll
+        for (int l = 0; l < 16; ++l) v -= a[r][Q + l] * a[c][Q + l];
+        a[r][c] = v;
+      }
+    } else {
+      const int e2 = e - NUPD;
+      const int r = Q + 16 + e2 / (Q + 16), c = e2 % (Q + 16);
+      double v = x[r][c];
+#pragma unroll
+      for (int l = 0; l < 16; ++l) v -= a[r][Q + l] * x[Q + l][c];
+      x[r][c] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Panels that lie entirely in the identity padding (index >= p) are skipped:
+// there L = I and X = I already, and the earlier panels leave them unchanged
+// because the padding has zero coupling to the valid indices.
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64_t ld, int k,
                                                    double* __restrict__ Linv,
-                                                   int* __restrict__ info) {
+                                                   int* __restrict__ info, int64_t p) {
   __shared__ double a[NB][NB + 1];
   __shared__ double x[NB][NB + 1];
-  __shared__ double dg[NB];
+  __shared__ double dinv[16][17];
   const int t = threadIdx.x;
   const int64_t o = (int64_t)k * NB;
   for (int idx = t; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, j = idx % NB;
+    const int i = idx >> 6, j = idx & 63;
     a[i][j] = M[(o + i) * ld + o + j];
-    x[i][j] = 0.0;
-  }
-  for (int j = 0; j < NB; ++j) {
-    __syncthreads();
-    const double piv = a[j][j];
-    const bool bad = !(piv > 0.0);
-    const double sq = bad ? __builtin_nan("") : sqrt(piv);
-    if (t == 0) {
-      dg[j] = sq;
-      if (bad) atomicExch(info, 1);
-    }
-    if (t > j && t < NB) a[t][j] = a[t][j] / sq;
-    __syncthreads();
-    const int rem = NB - 1 - j;
-    for (int idx = t; idx < rem * rem; idx += 256) {
-      const int i = j + 1 + idx / rem, l = j + 1 + idx % rem;
-      if (l <= i) a[i][l] -= a[i][j] * a[l][j];
-    }
+    x[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (t < NB) a[t][t] = dg[t];
-  __syncthreads();
-  for (int i = 0; i < NB; ++i) {
-    if (t <= i) {
-      double sm = (t == i) ? 1.0 : 0.0;
-      for (int l = t; l < i; ++l) sm -= a[i][l] * x[l][t];
-      x[i][t] = sm / a[i][i];
-    }
-    __syncthreads();
-  }
+  bool bad = false;
+  const int64_t valid = p - o;  // valid indices in this tile (>= 1)
+  diag_panel<0>(a, x, dinv, bad);
+  if (valid > 16) diag_panel<16>(a, x, dinv, bad);
+  if (valid > 32) diag_panel<32>(a, x, dinv, bad);
+  if (valid > 48) diag_panel<48>(a, x, dinv, bad);
+  if (bad) atomicExch(info, 1);
   for (int idx = t; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, j = idx % NB;
+    const int i = idx >> 6, j = idx & 63;
     M[(o + i) * ld + o + j] = j <= i ? a[i][j] : 0.0;
     Linv[(o + i) * ld + o + j] = j <= i ? x[i][j] : 0.0;
   }
@@ -252,8 +404,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
 // Blocks [nrest, nrest + k): X_kj = Linv_kk Y_kj in place, j = b - nrest.
 __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int64_t ld, int k,
                                                     int nrest, double* __restrict__ Linv) {
-  __shared__ double As[16][NB + 1];
-  __shared__ double Bs[16][NB + 1];
+  __shared__ TileLds tl;
   const int t = threadIdx.x;
   const int ty = t >> 4, tx = t & 15;
   const int64_t ok = (int64_t)k * NB;
@@ -265,13 +416,13 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int6
     const int64_t oi = ok + (int64_t)(blockIdx.x + 1) * NB;
     Opnd A{M + oi * ld + ok, ld, NB, NB, false};
     Opnd B{Linv + ok * ld + ok, ld, NB, NB, true};
-    tile_mm(acc, A, B, NB, As, Bs);
+    tile_mm(acc, A, B, NB, tl);
     dst = M + oi * ld + ok;
   } else {
     const int64_t oj = (int64_t)(blockIdx.x - nrest) * NB;
     Opnd A{Linv + ok * ld + ok, ld, NB, NB, false};
     Opnd B{Linv + ok * ld + oj, ld, NB, NB, false};
-    tile_mm(acc, A, B, NB, As, Bs);
+    tile_mm(acc, A, B, NB, tl);
     dst = Linv + ok * ld + oj;
   }
   // tile_mm ends with a barrier: every read of the destination tile is done
@@ -285,8 +436,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int6
 // Blocks [tri(nrest), + nrest*(k+1)): Y_ij -= L_ik X_kj for i > k, j <= k.
 __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int64_t ld, int k,
                                                      int nrest, double* __restrict__ Linv) {
-  __shared__ double As[16][NB + 1];
-  __shared__ double Bs[16][NB + 1];
+  __shared__ TileLds tl;
   const int64_t tri = (int64_t)nrest * (nrest + 1) / 2;
   const int64_t bid = blockIdx.x;
   const int64_t ok = (int64_t)k * NB;
@@ -301,7 +451,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
     const int64_t oi = (k + 1 + I) * NB, oj = (k + 1 + J) * NB;
     Opnd A{M + oi * ld + ok, ld, NB, NB, false};
     Opnd B{M + oj * ld + ok, ld, NB, NB, true};
-    tile_mm(acc, A, B, NB, As, Bs);
+    tile_mm(acc, A, B, NB, tl);
     dst = M + oi * ld + oj;
   } else {
     const int64_t r = bid - tri;
@@ -309,7 +459,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
     const int64_t oi = (k + 1 + I) * NB, oj = J * NB;
     Opnd A{M + oi * ld + ok, ld, NB, NB, false};
     Opnd B{Linv + ok * ld + oj, ld, NB, NB, false};
-    tile_mm(acc, A, B, NB, As, Bs);
+    tile_mm(acc, A, B, NB, tl);
     dst = Linv + oi * ld + oj;
   }
   const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
@@ -331,8 +481,7 @@ __global__ __launch_bounds__(256) void k_fill_identity(double* __restrict__ X, i
 // sum_{l >= I} Linv_lI^T Linv_lJ.
 __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, int64_t ld,
                                                int nblk, double* __restrict__ H, int64_t ldh) {
-  __shared__ double As[16][NB + 1];
-  __shared__ double Bs[16][NB + 1];
+  __shared__ TileLds tl;
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= bid) ++I;
@@ -344,7 +493,7 @@ __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, 
   const int64_t rows = (nblk - I) * NB;
   Opnd A{Linv + oI * ld + oI, ld, NB, rows, true};   // op(A) = (Linv[oI.., oI..])^T: 64 x rows
   Opnd B{Linv + oI * ld + oJ, ld, rows, NB, false};
-  tile_mm(acc, A, B, rows, As, Bs);
+  tile_mm(acc, A, B, rows, tl);
   const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -360,8 +509,7 @@ template <typename OSA>
 __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv, int64_t ld,
                                                 OSA SA, int64_t d, double* __restrict__ Cw,
                                                 int64_t ldc) {
-  __shared__ double As[16][NB + 1];
-  __shared__ double Bs[16][NB + 1];
+  __shared__ TileLds tl;
   const int64_t I = blockIdx.y, Jd = blockIdx.x;
   double acc[4][4];
   zero_acc(acc);
@@ -370,7 +518,7 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv,
   OSA B = SA;
   B.p = SA.p + oJ;
   B.cols = d - oJ;
-  tile_mm(acc, A, B, (I + 1) * NB, As, Bs);
+  tile_mm(acc, A, B, (I + 1) * NB, tl);
   const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -382,8 +530,7 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv,
 __global__ __launch_bounds__(256) void k_woodbury_inv(const double* __restrict__ Cw, int64_t ldc,
                                                       int64_t mpad, double inv_nu2, int64_t dp,
                                                       double* __restrict__ H, int64_t ldh) {
-  __shared__ double As[16][NB + 1];
-  __shared__ double Bs[16][NB + 1];
+  __shared__ TileLds tl;
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= bid) ++I;
@@ -394,7 +541,7 @@ __global__ __launch_bounds__(256) void k_woodbury_inv(const double* __restrict__
   const int64_t oI = I * NB, oJ = J * NB;
   Opnd A{Cw + oI, ldc, NB, mpad, true};
   Opnd B{Cw + oJ, ldc, mpad, NB, false};
-  tile_mm(acc, A, B, mpad, As, Bs);
+  tile_mm(acc, A, B, mpad, tl);
   const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -417,31 +564,42 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, in
   const int64_t pp = pad64(p);
   const int nblk = (int)(pp / NB);
   const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
-  // 1. Gram
+  // 1. Gram, split over the summed dimension so that the launch fills the chip
+  const int64_t q = wood ? d : m;
+  const int64_t cus = device_cus();
+  int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((2 * cus + tiles - 1) / tiles,
+                                                           (q + 255) / 256));
+  nsplit = std::min(nsplit, 16);
+  const int64_t qchunk = ((q + nsplit - 1) / nsplit + 15) / 16 * 16;
+  nsplit = (int)((q + qchunk - 1) / qchunk);
+  const dim3 gg((unsigned)tiles, (unsigned)nsplit);
+  const size_t esz = sa_t == RS_F64 ? 8 : 4;
+  if ((size_t)nsplit * pp * pp * esz > F.gram_bytes)
+    return set_error(RS_ERR_ARG, "factor: Gram scratch too small");
   if (sa_t == RS_F32) {
     const float* X = reinterpret_cast<const float*>(SA);
+    float* P = reinterpret_cast<float*>(F.gram);
     if (wood)
-      hipLaunchKernelGGL((k_gram<float, float, false>), dim3((unsigned)tiles), dim3(256), 0, s, X,
-                         ldsa, p, d, nu2, F.M, pp);
+      hipLaunchKernelGGL((k_gram<float, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
     else
-      hipLaunchKernelGGL((k_gram<float, float, true>), dim3((unsigned)tiles), dim3(256), 0, s, X,
-                         ldsa, p, m, nu2, F.M, pp);
+      hipLaunchKernelGGL((k_gram<float, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_F64) {
     const double* X = reinterpret_cast<const double*>(SA);
+    double* P = reinterpret_cast<double*>(F.gram);
     if (wood)
-      hipLaunchKernelGGL((k_gram<double, double, false>), dim3((unsigned)tiles), dim3(256), 0, s,
-                         X, ldsa, p, d, nu2, F.M, pp);
+      hipLaunchKernelGGL((k_gram<double, double, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
     else
-      hipLaunchKernelGGL((k_gram<double, double, true>), dim3((unsigned)tiles), dim3(256), 0, s,
-                         X, ldsa, p, m, nu2, F.M, pp);
+      hipLaunchKernelGGL((k_gram<double, double, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+    hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_BF16) {
     const uint16_t* X = reinterpret_cast<const uint16_t*>(SA);
+    float* P = reinterpret_cast<float*>(F.gram);
     if (wood)
-      hipLaunchKernelGGL((k_gram<uint16_t, float, false>), dim3((unsigned)tiles), dim3(256), 0, s,
-                         X, ldsa, p, d, nu2, F.M, pp);
+      hipLaunchKernelGGL((k_gram<uint16_t, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
     else
-      hipLaunchKernelGGL((k_gram<uint16_t, float, true>), dim3((unsigned)tiles), dim3(256), 0, s,
-                         X, ldsa, p, m, nu2, F.M, pp);
+      hipLaunchKernelGGL((k_gram<uint16_t, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else {
     return set_error(RS_ERR_UNSUPPORTED, "factor: SA dtype not supported");
   }
@@ -452,7 +610,7 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, in
     hipLaunchKernelGGL(k_fill_identity, dim3(g), dim3(256), 0, s, F.Linv, pp);
   }
   for (int k = 0; k < nblk; ++k) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, F.M, pp, k, F.Linv, F.info);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, F.M, pp, k, F.Linv, F.info, p);
     const int nrest = nblk - 1 - k;
     if (nrest + k > 0)
       hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(nrest + k)), dim3(256), 0, s, F.M, pp, k,
@@ -490,6 +648,11 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, in
 size_t factor_bytes_M(int64_t m, int64_t d) {
   const int64_t p = m < d ? m : d;
   return (size_t)pad64(p) * pad64(p) * sizeof(double);
+}
+size_t factor_bytes_gram(int64_t m, int64_t d, rs_dtype sa_t) {
+  const int64_t p = m < d ? m : d;
+  const int64_t pp = pad64(p);
+  return (size_t)16 * pp * pp * (sa_t == RS_F64 ? 8 : 4);
 }
 size_t factor_bytes_Hinv(int64_t d) { return (size_t)pad64(d) * pad64(d) * sizeof(double); }
 size_t factor_bytes_Cw(int64_t m, int64_t d) {

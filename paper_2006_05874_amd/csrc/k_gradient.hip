@@ -21,8 +21,10 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
                                                       const double* __restrict__ X,
                                                       int64_t rows_per_block, int iters,
                                                       double* __restrict__ partial,
-                                                      const int* __restrict__ status) {
+                                                      const int* __restrict__ status,
+                                                      int* __restrict__ ran) {
   if (status && *status != 0) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
   using V = typename VecOf<T>::type;
   constexpr int VEC = VecOf<T>::n;
   constexpr int GPB = 256 / TPR;          // row groups per block
@@ -36,7 +38,8 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
   const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t row1 = row0 + rows_per_block < n ? row0 + rows_per_block : n;
 
-  // x in registers (T precision)
+  // x in registers (T precision); loads are unconditional from clamped
+  // in-bounds addresses and masked afterwards, so they all stay in flight
   T xv[K][NV][VEC];
   bool colok[NV][VEC];
 #pragma unroll
@@ -45,8 +48,12 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
     for (int e = 0; e < VEC; ++e) {
       const int64_t c = (int64_t)(lt + TPR * v) * VEC + e;
       colok[v][e] = c < d;
+      const int64_t cc = c < d ? c : 0;
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv[k][v][e] = colok[v][e] ? (T)X[k * d + c] : (T)0;
+      for (int k = 0; k < K; ++k) {
+        const T xval = (T)X[k * d + cc];
+        xv[k][v][e] = colok[v][e] ? xval : (T)0;
+      }
     }
   }
   double acc[K][NV][VEC];
@@ -61,29 +68,32 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
     const int64_t base = row0 + ((int64_t)it * GPB + grp) * R;
     V a[R][NV];
     T bv[R];
+    bool rok[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int64_t row = base + i;
-      const bool rok = row < row1;
-      bv[i] = rok ? b[row] : (T)0;
+      rok[i] = row < row1;
+      const int64_t rowc = row < n ? row : n - 1;
+      bv[i] = b[rowc];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int64_t c = (int64_t)(lt + TPR * v) * VEC;
-        if (rok && c < d) {
-          a[i][v] = *reinterpret_cast<const V*>(A + row * lda + c);
-        } else {
-          a[i][v] = V{};
-        }
+        const int64_t cc = c < d ? c : 0;
+        a[i][v] = *reinterpret_cast<const V*>(A + rowc * lda + cc);
       }
     }
-    // mask columns past d (the vector may straddle d)
+    // mask rows past the block and columns past d (a vector may straddle d)
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+    for (int i = 0; i < R; ++i) {
+      bv[i] = rok[i] ? bv[i] : (T)0;
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (!colok[v][e]) set(a[i][v], e, (T)0);
+        for (int e = 0; e < VEC; ++e) {
+          const T val = get(a[i][v], e);
+          set(a[i][v], e, (rok[i] && colok[v][e]) ? val : (T)0);
+        }
+    }
 
     T s[R][K];
 #pragma unroll
@@ -245,9 +255,9 @@ void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, c
   constexpr int R = (NV >= 8) ? 2 : (NV >= 4 ? 4 : 8);
   constexpr int GPB = 256 / TPR;
   const int iters = (int)((rpb + GPB * R - 1) / (GPB * R));
-  prof_begin(s);
+  int* ran = prof_begin(s);
   hipLaunchKernelGGL((k_grad_partial<T, TPR, NV, K, R>), dim3(grid), dim3(256), 0, s, A, n, d, lda,
-                     b, X, rpb, iters, partial, status);
+                     b, X, rpb, iters, partial, status, ran);
   prof_end(s);
 }
 

@@ -366,33 +366,39 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
   const int64_t col0 = ((int64_t)blockIdx.y * TT::CW + c) * VEC;
   const bool cvec = col0 < d;
 
-  // destination of each tile row
+  // destination of each tile row (index loads clamped in bounds, then masked)
   const int64_t tile = blockIdx.x;
   for (int r = t; r < TT::RT; r += 256) {
     int32_t dst = -1;
     if (MODE == 0) {
-      const int32_t q = (r < n2) ? qmap[r] : -1;
-      dst = q >= 0 ? (int32_t)(tile * Q + q) : -1;
+      const int32_t q = qmap[r < n2 ? r : 0];
+      dst = (r < n2 && q >= 0) ? (int32_t)(tile * Q + q) : -1;
     } else if (MODE == 1) {
-      dst = (r < n2) ? kmap[r] : -1;
+      const int32_t kk = kmap[r < n2 ? r : 0];
+      dst = r < n2 ? kk : -1;
     } else {
       const int64_t n1 = (int64_t)1 << lb;
       const int64_t qq = r >> lb;
       const int64_t i1 = r & (n1 - 1);
       const int64_t q = tile * (TT::RT >> lb) + qq;
-      dst = q < (int64_t)(*qcount) ? kmap[i1 * n2 + qlist[q]] : -1;
+      const bool okq = q < (int64_t)(*qcount);
+      const int32_t i2 = qlist[okq ? q : 0];
+      const int32_t kk = kmap[okq ? i1 * n2 + i2 : 0];
+      dst = okq ? kk : -1;
     }
     dest[r] = dst;
   }
 
-  // load (stage A mapping)
+  // load (stage A mapping): every load is issued unconditionally from a clamped
+  // in-bounds address and masked afterwards, so all 32 stay in flight
   V v[J];
+  T sgn[J];
+  bool okr[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int r = g + 32 * j;
     int64_t srow;
     bool ok;
-    T sg = (T)1;
     if (MODE == 2) {
       const int64_t n1 = (int64_t)1 << lb;
       const int64_t qq = r >> lb;
@@ -403,16 +409,19 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     } else {
       srow = tile * n2 + r;
       ok = (r < n2) && (srow < n_src_rows);
-      if (ok) sg = (T)signs[srow];
     }
-    V x = V{};
-    if (ok && cvec) x = *reinterpret_cast<const V*>(src + srow * lds_src + col0);
+    const int64_t srowc = ok ? srow : 0;
+    okr[j] = ok && cvec;
+    v[j] = *reinterpret_cast<const V*>(src + srowc * lds_src + (cvec ? col0 : 0));
+    sgn[j] = (MODE == 2) ? (T)1 : (T)signs[srowc];
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-      const T xe = (col0 + e < d) ? get(x, e) * sg : (T)0;
-      set(x, e, xe);
+      const T xe = get(v[j], e) * sgn[j];
+      set(v[j], e, (okr[j] && col0 + e < d) ? xe : (T)0);
     }
-    v[j] = x;
   }
   reg_fwht<V, J>(v, 5, lb);
 #pragma unroll

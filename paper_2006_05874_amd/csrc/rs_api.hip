@@ -55,9 +55,14 @@ int device_cus() {
 }
 
 // ------------------------------------------------------------------ timing
+// Launches bracketed while profiling: event pairs plus a device flag per launch
+// that the kernel sets when it does its work (launches queued behind a raised
+// status flag return at once and are not counted).
 static bool g_prof_on = false;
 static std::vector<hipEvent_t> g_prof_ev;  // begin/end pairs
 static size_t g_prof_n = 0;                // events recorded
+static int* g_prof_ran = nullptr;          // device flags, one per launch
+static constexpr size_t kProfCap = 1 << 16;
 
 static hipEvent_t prof_event() {
   if (g_prof_n >= g_prof_ev.size()) {
@@ -68,14 +73,16 @@ static hipEvent_t prof_event() {
   return g_prof_ev[g_prof_n++];
 }
 
-void prof_begin(hipStream_t s) {
-  if (!g_prof_on) return;
+int* prof_begin(hipStream_t s) {
+  if (!g_prof_on || g_prof_n / 2 >= kProfCap) return nullptr;
+  const size_t slot = g_prof_n / 2;
   hipEvent_t e = prof_event();
   if (e) (void)hipEventRecord(e, s);
+  return g_prof_ran ? g_prof_ran + slot : nullptr;
 }
 
 void prof_end(hipStream_t s) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || g_prof_n % 2 == 0) return;
   hipEvent_t e = prof_event();
   if (e) (void)hipEventRecord(e, s);
 }
@@ -120,7 +127,7 @@ struct DeviceScratch {
   // gradient partials, vectors, control
   DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
   // solver-owned sketch and factor
-  DevBuf sa, fM, fLinv, fHinv, fCw;
+  DevBuf sa, fM, fLinv, fHinv, fCw, fGram;
   void* host_pinned = nullptr;
 };
 
@@ -234,14 +241,20 @@ struct rs_factor {
   int64_t m, d, p, pp, dp;
   double nu2;
   bool wood;
-  DevBuf M, Linv, Hinv, Cw, info, rpart;
+  DevBuf M, Linv, Hinv, Cw, info, rpart, gram;
+  rs_dtype sa_t;
 };
 
 extern "C" {
 
 const char* rs_last_error(void) { return g_err.c_str(); }
+const char* rs_version(void) { return "librs 0.1 (gfx950)"; }
 
 rs_status rs_profile_enable(int on) {
+  if (on && !g_prof_ran) {
+    RS_HIP(hipMalloc(&g_prof_ran, kProfCap * sizeof(int)));
+    RS_HIP(hipMemset(g_prof_ran, 0, kProfCap * sizeof(int)));
+  }
   g_prof_on = on != 0;
   return RS_OK;
 }
@@ -250,10 +263,18 @@ rs_status rs_profile_read(int64_t* launches, double* total_ms) {
   if (!launches || !total_ms) return set_error(RS_ERR_ARG, "rs_profile_read: null argument");
   double tot = 0.0;
   int64_t cnt = 0;
-  for (size_t i = 0; i + 1 < g_prof_n; i += 2) {
-    RS_HIP(hipEventSynchronize(g_prof_ev[i + 1]));
+  const size_t pairs = g_prof_n / 2;
+  std::vector<int> ran(pairs, 1);
+  if (g_prof_ran && pairs) {
+    RS_HIP(hipDeviceSynchronize());
+    RS_HIP(hipMemcpy(ran.data(), g_prof_ran, pairs * sizeof(int), hipMemcpyDeviceToHost));
+    RS_HIP(hipMemset(g_prof_ran, 0, kProfCap * sizeof(int)));
+  }
+  for (size_t i = 0; i < pairs; ++i) {
+    RS_HIP(hipEventSynchronize(g_prof_ev[2 * i + 1]));
+    if (!ran[i]) continue;
     float ms = 0.0f;
-    RS_HIP(hipEventElapsedTime(&ms, g_prof_ev[i], g_prof_ev[i + 1]));
+    RS_HIP(hipEventElapsedTime(&ms, g_prof_ev[2 * i], g_prof_ev[2 * i + 1]));
     tot += ms;
     ++cnt;
   }
@@ -262,7 +283,6 @@ rs_status rs_profile_read(int64_t* launches, double* total_ms) {
   *total_ms = tot;
   return RS_OK;
 }
-const char* rs_version(void) { return "librs 0.1 (gfx950)"; }
 
 rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* out) {
   if (!out) return set_error(RS_ERR_ARG, "rs_params: out is null");
@@ -334,6 +354,7 @@ static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
   if (F->wood) RS_TRY(F->Cw.ensure(factor_bytes_Cw(m, d)));
   RS_TRY(F->info.ensure(sizeof(int), true));
   RS_TRY(F->rpart.ensure((size_t)apply_blocks(d) * 4 * sizeof(double)));
+  RS_TRY(F->gram.ensure(factor_bytes_gram(m, d, F->sa_t)));
   return RS_OK;
 }
 
@@ -349,10 +370,11 @@ rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_
     return set_error(RS_ERR_UNSUPPORTED, "rs_factor_woodbury: SA dtype not supported");
   *out = nullptr;
   rs_factor* F = new rs_factor();
+  F->sa_t = sa_t;
   rs_status st = factor_alloc(F, m, d, nu2);
   if (st == RS_OK) {
     FactorBuffers B{F->M.as<double>(), F->Linv.as<double>(), F->Hinv.as<double>(),
-                    F->Cw.as<double>(), F->info.as<int>()};
+                    F->Cw.as<double>(), F->info.as<int>(), F->gram.p, F->gram.bytes};
     hipError_t e = hipMemsetAsync(B.info, 0, sizeof(int), stream);
     if (e != hipSuccess) st = set_error(RS_ERR_HIP, "hipMemsetAsync failed");
     if (st == RS_OK) st = factor_build(B, SA, sa_t, m, d, ldsa, nu2, stream);
@@ -383,7 +405,7 @@ rs_status rs_factor_apply(const rs_factor* F, const double* g, double* gtilde, d
 
 void rs_factor_destroy(rs_factor* F) {
   if (!F) return;
-  for (DevBuf* b : {&F->M, &F->Linv, &F->Hinv, &F->Cw, &F->info, &F->rpart})
+  for (DevBuf* b : {&F->M, &F->Linv, &F->Hinv, &F->Cw, &F->info, &F->rpart, &F->gram})
     if (b->p) (void)hipFree(b->p);
   delete F;
 }
@@ -556,8 +578,9 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
     RS_TRY(S->fLinv.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fHinv.ensure(factor_bytes_Hinv(d)));
     if (mm < d) RS_TRY(S->fCw.ensure(factor_bytes_Cw(mm, d)));
+    RS_TRY(S->fGram.ensure(factor_bytes_gram(mm, d, sa_t)));
     FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
-                     S->fCw.as<double>(), finfo};
+                     S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes};
     return factor_build(FB, S->sa.p, sa_t, mm, d, ldsa, nu2, stream);
   };
   const int64_t dp = (d + 63) / 64 * 64;

@@ -16,7 +16,7 @@ rs_status set_error(rs_status st, const char* msg);
 rs_status check_launch(const char* what);
 int device_cus();
 // kernel timing hooks (no-ops unless rs_profile_enable(1))
-void prof_begin(hipStream_t s);
+int* prof_begin(hipStream_t s);  // returns the launch's "did work" flag slot or null
 void prof_end(hipStream_t s);
 
 // ---------------------------------------------------------------- SRHT
@@ -56,11 +56,14 @@ struct FactorBuffers {
   double* Hinv;  // pad64(d)^2
   double* Cw;    // pad64(m) x pad64(d) (Woodbury branch)
   int* info;     // 1: a pivot failed
+  void* gram;    // split-K partial Grams
+  size_t gram_bytes;
 };
 rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, int64_t m, int64_t d,
                        int64_t ldsa, double nu2, hipStream_t s);
 size_t factor_bytes_M(int64_t m, int64_t d);
 size_t factor_bytes_Hinv(int64_t d);
+size_t factor_bytes_gram(int64_t m, int64_t d, rs_dtype sa_t);
 size_t factor_bytes_Cw(int64_t m, int64_t d);
 
 // ---------------------------------------------------------------- gradient
