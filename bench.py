@@ -12,6 +12,7 @@ Prints one JSON line (see the repository's design notes for the roofline and
 baseline definitions).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,29 @@ def parse():
                     help="run one plain 256 MiB device-to-device copy first (a counter "
                          "reference for HBM traffic measurements)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_partial_65536x1024_f32_traffic.txt")
+GRAD_SOURCES = [os.path.join(ROOT, "paper_2006_05874_amd", "csrc", f)
+                for f in ("k_gradient.hip", "rs_device.hpp")]
+
+
+def recorded_traffic():
+    """HBM bytes per gradient launch from the committed counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in GRAD_SOURCES)).hexdigest()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if ": " in line and not line.startswith("#"):
+            k, v = line.split(": ", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def blas_threads():
@@ -151,8 +175,11 @@ def main():
     alg_bytes = N * D * 4 + N * 4
     avg_ms = grad_ms / max(launches, 1)
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    traffic = recorded_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic else None,
+            "algorithmic_bytes": alg_bytes,
             "kernel": "k_grad_partial (A^T(AX-b) pass, 2 RHS)", "avg_launch_us": round(avg_ms * 1e3, 2),
             "launches": launches}
 

@@ -600,6 +600,9 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
   DevCtl h{};
   int64_t applies = 1;
   rs_status result = RS_OK;
+  // steps queued per host read: one right after a resample (the next step is
+  // often rejected again while m is small), check_every after accepted steps
+  int queue = 1;
   for (;;) {
     // read the control record and the factor flag
     RS_HIP(hipMemcpyAsync(S->host_pinned, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
@@ -614,7 +617,7 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
       break;
     }
     if (h.status == RS_CTL_RUNNING) {
-      for (int it = 0; it < check_every; ++it) {
+      for (int it = 0; it < queue; ++it) {
         RS_TRY(candidates_launch(K, d, x, x_prev, gt, X, prm.mu_p, prm.beta_p, prm.mu_gd, status,
                                  stream));
         RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
@@ -622,6 +625,7 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
         RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
                              gt, S->ev.as<int32_t>(), ev_cap, stream));
       }
+      queue = check_every;
       continue;
     }
     if (h.status == RS_CTL_DOUBLE) {
@@ -635,6 +639,7 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
       RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, opts->tol, d, GT, gt,
                                   m == m_cap ? 1 : 0, stream));
       applies += 1;
+      queue = 1;
       continue;
     }
     if (h.status == RS_CTL_CONVERGED) result = RS_OK;
