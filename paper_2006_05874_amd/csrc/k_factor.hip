@@ -31,11 +31,14 @@ template <typename TAcc, typename T>
 __device__ __forceinline__ TAcc load_as(T v) { return (TAcc)v; }
 template <>
 __device__ __forceinline__ float load_as<float, uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+template <>
+__device__ __forceinline__ float load_as<float, uint8_t>(uint8_t v) { return e4m3_to_f32(v); }
 
+// colscale (FP8 data only, else null): element (r, c) of SA is stored * scale[c].
 template <typename TIn, typename TAcc, bool TN>
 __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64_t ld, int64_t p,
                                               int64_t q, int64_t qchunk, TAcc* __restrict__ P,
-                                              int64_t ldc) {
+                                              int64_t ldc, const float* __restrict__ colscale) {
   // triangular tile index -> (I, J), J <= I
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
@@ -75,6 +78,16 @@ __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64
       if (l < lend) {
         if (ia < p) va = load_as<TAcc>(TN ? src[l * ld + ia] : src[ia * ld + l]);
         if (ja < p) vb = load_as<TAcc>(TN ? src[l * ld + ja] : src[ja * ld + l]);
+        if (colscale) {
+          if (TN) {
+            if (ia < p) va *= (TAcc)colscale[ia];
+            if (ja < p) vb *= (TAcc)colscale[ja];
+          } else {
+            const TAcc cs = (TAcc)colscale[l];
+            va *= cs;
+            vb *= cs;
+          }
+        }
       }
       As[kk][ii] = va;
       Bs[kk][ii] = vb;
@@ -110,6 +123,99 @@ __global__ __launch_bounds__(256) void k_gram(const TIn* __restrict__ src, int64
         const int64_t i = i0 + wr * 32 + a * 16 + mfma16_row<TAcc>(lane, r);
         const int64_t j = j0 + wc * 32 + b * 16 + (lane & 15);
         Ps[i * ldc + j] = acc[a][b][r];
+      }
+}
+
+// Low-precision TN Gram on the gfx950 K=32 matrix instructions:
+// C[i][j] = sum_l X[l][i] X[l][j] over a K range, X stored as BF16 (uint16) or
+// FP8 E4M3 (uint8, with per-column scales applied to the FP32 result).  A 64-row
+// chunk of X is staged transposed in LDS (Xs[i][l]) so that each lane reads its
+// 8 consecutive k values of the 16x16x32 operand layout (lane l: row l % 16,
+// k = 8 (l / 16) .. + 7) with one 16- or 8-byte LDS read.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_gram_lp_tn(const TIn* __restrict__ src, int64_t ld,
+                                                    int64_t p, int64_t q, int64_t qchunk,
+                                                    float* __restrict__ P, int64_t ldc,
+                                                    const float* __restrict__ colscale) {
+  const int64_t bid = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= bid) ++I;
+  while (I * (I + 1) / 2 > bid) --I;
+  const int64_t J = bid - I * (I + 1) / 2;
+  const int64_t i0 = I * NB, j0 = J * NB;
+  constexpr int KC = 64;
+  constexpr int PADK = KC + 16 / (int)sizeof(TIn);   // keeps rows 16-byte aligned
+  __shared__ __attribute__((aligned(16))) TIn As[NB][PADK];
+  __shared__ __attribute__((aligned(16))) TIn Bs[NB][PADK];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+  const int64_t lbeg = (int64_t)blockIdx.y * qchunk;
+  const int64_t lend = lbeg + qchunk < q ? lbeg + qchunk : q;
+  constexpr int EPV = 16 / (int)sizeof(TIn);  // elements per 16-byte vector
+  constexpr int VPR = NB / EPV;               // vectors per 64-wide row segment
+  for (int64_t l0 = lbeg; l0 < lend; l0 += KC) {
+    // stage: KC rows x 64 columns for each operand, 16-byte vectors
+    for (int v = t; v < KC * VPR; v += 256) {
+      const int kk = v / VPR, cv = v % VPR;
+      const int64_t l = l0 + kk;
+      const bool lok = l < lend;
+      const int64_t lc = lok ? l : lbeg;
+      uint4 va = *reinterpret_cast<const uint4*>(src + lc * ld + i0 + cv * EPV);
+      uint4 vb = *reinterpret_cast<const uint4*>(src + lc * ld + j0 + cv * EPV);
+      const TIn* ea = reinterpret_cast<const TIn*>(&va);
+      const TIn* eb = reinterpret_cast<const TIn*>(&vb);
+#pragma unroll
+      for (int e = 0; e < EPV; ++e) {
+        const int64_t ci = i0 + cv * EPV + e, cj = j0 + cv * EPV + e;
+        As[cv * EPV + e][kk] = (lok && ci < p) ? ea[e] : (TIn)0;
+        Bs[cv * EPV + e][kk] = (lok && cj < p) ? eb[e] : (TIn)0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k32 = 0; k32 < KC / 32; ++k32) {
+      const int kof = k32 * 32 + 8 * (lane >> 4);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int ia = wr * 32 + a * 16 + (lane & 15);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int jb = wc * 32 + b * 16 + (lane & 15);
+          if constexpr (sizeof(TIn) == 2) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[ia][kof]);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bs[jb][kof]);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[a][b], 0, 0, 0);
+          } else {
+            const long av = *reinterpret_cast<const long*>(&As[ia][kof]);
+            const long bv = *reinterpret_cast<const long*>(&Bs[jb][kof]);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc[a][b], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* Ps = P + (int64_t)blockIdx.y * ldc * ldc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wr * 32 + a * 16 + mfma16_row<float>(lane, r);
+        const int64_t j = j0 + wc * 32 + b * 16 + (lane & 15);
+        float v = acc[a][b][r];
+        if (colscale && i < p && j < p) v *= colscale[i] * colscale[j];
+        Ps[i * ldc + j] = v;
       }
 }
 
@@ -176,6 +282,22 @@ __device__ __forceinline__ double opnd_at(const HOpnd& o, int64_t r, int64_t c) 
   const bool ok = r < o.rows && c < o.cols;
   const int64_t rr = ok ? r : 0, cc = ok ? c : 0;
   const double v = (double)bf16_to_f32(o.p[o.trans ? cc * o.ld + rr : rr * o.ld + cc]);
+  return ok ? v : 0.0;
+}
+
+struct QOpnd {  // FP8 E4M3 source with per-column scales of the stored matrix
+  const uint8_t* p;
+  int64_t ld;
+  int64_t rows, cols;
+  bool trans;
+  const float* scale;  // indexed by the stored matrix's column
+};
+__device__ __forceinline__ double opnd_at(const QOpnd& o, int64_t r, int64_t c) {
+  const bool ok = r < o.rows && c < o.cols;
+  const int64_t rr = ok ? r : 0, cc = ok ? c : 0;
+  const int64_t sc = o.trans ? rr : cc;
+  const double v = (double)e4m3_to_f32(o.p[o.trans ? cc * o.ld + rr : rr * o.ld + cc]) *
+                   (double)o.scale[sc];
   return ok ? v : 0.0;
 }
 
@@ -504,6 +626,10 @@ __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, 
     }
 }
 
+template <typename O>
+__device__ __forceinline__ void shift_scale(O&, int64_t) {}
+__device__ __forceinline__ void shift_scale(QOpnd& o, int64_t off) { o.scale += off; }
+
 // C = Linv SA (m x d): tile (I over m, Jd over d): sum_{l <= I} Linv_Il SA_l.
 template <typename OSA>
 __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv, int64_t ld,
@@ -518,6 +644,7 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv,
   OSA B = SA;
   B.p = SA.p + oJ;
   B.cols = d - oJ;
+  shift_scale(B, oJ);
   tile_mm(acc, A, B, (I + 1) * NB, tl);
   const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
 #pragma unroll
@@ -557,8 +684,9 @@ __global__ __launch_bounds__(256) void k_woodbury_inv(const double* __restrict__
 // ------------------------------------------------------------------ driver
 static inline int64_t pad64(int64_t v) { return (v + NB - 1) / NB * NB; }
 
-rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, int64_t m, int64_t d,
-                       int64_t ldsa, double nu2, hipStream_t s) {
+rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                       const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
+                       hipStream_t s) {
   const bool wood = m < d;
   const int64_t p = wood ? m : d;
   const int64_t pp = pad64(p);
@@ -574,31 +702,55 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, in
   nsplit = (int)((q + qchunk - 1) / qchunk);
   const dim3 gg((unsigned)tiles, (unsigned)nsplit);
   const size_t esz = sa_t == RS_F64 ? 8 : 4;
+  // the low-precision TN kernel reads 16-byte vectors of 64-column segments: it
+  // needs 16-byte aligned rows and a padded width (columns up to pad64(d) exist)
+  const size_t lpes = sa_t == RS_BF16 ? 2 : 1;
+  const bool lp_ok = (sa_t == RS_BF16 || sa_t == RS_FP8E4M3) &&
+                     ((uintptr_t)SA % 16 == 0) && ((ldsa * lpes) % 16 == 0) && ldsa >= pp;
   if ((size_t)nsplit * pp * pp * esz > F.gram_bytes)
     return set_error(RS_ERR_ARG, "factor: Gram scratch too small");
   if (sa_t == RS_F32) {
     const float* X = reinterpret_cast<const float*>(SA);
     float* P = reinterpret_cast<float*>(F.gram);
     if (wood)
-      hipLaunchKernelGGL((k_gram<float, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+      hipLaunchKernelGGL((k_gram<float, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
-      hipLaunchKernelGGL((k_gram<float, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+      hipLaunchKernelGGL((k_gram<float, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_F64) {
     const double* X = reinterpret_cast<const double*>(SA);
     double* P = reinterpret_cast<double*>(F.gram);
     if (wood)
-      hipLaunchKernelGGL((k_gram<double, double, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+      hipLaunchKernelGGL((k_gram<double, double, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
-      hipLaunchKernelGGL((k_gram<double, double, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+      hipLaunchKernelGGL((k_gram<double, double, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
+  } else if (sa_t == RS_BF16 && !wood && lp_ok) {
+    float* P = reinterpret_cast<float*>(F.gram);
+    hipLaunchKernelGGL(k_gram_lp_tn<uint16_t>, gg, dim3(256), 0, s,
+                       reinterpret_cast<const uint16_t*>(SA), ldsa, p, q, qchunk, P, pp,
+                       (const float*)nullptr);
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
+  } else if (sa_t == RS_FP8E4M3 && !wood && lp_ok) {
+    float* P = reinterpret_cast<float*>(F.gram);
+    hipLaunchKernelGGL(k_gram_lp_tn<uint8_t>, gg, dim3(256), 0, s,
+                       reinterpret_cast<const uint8_t*>(SA), ldsa, p, q, qchunk, P, pp, colscale);
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_BF16) {
     const uint16_t* X = reinterpret_cast<const uint16_t*>(SA);
     float* P = reinterpret_cast<float*>(F.gram);
     if (wood)
-      hipLaunchKernelGGL((k_gram<uint16_t, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+      hipLaunchKernelGGL((k_gram<uint16_t, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
-      hipLaunchKernelGGL((k_gram<uint16_t, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+      hipLaunchKernelGGL((k_gram<uint16_t, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
+  } else if (sa_t == RS_FP8E4M3) {
+    const uint8_t* X = reinterpret_cast<const uint8_t*>(SA);
+    float* P = reinterpret_cast<float*>(F.gram);
+    if (wood)
+      hipLaunchKernelGGL((k_gram<uint8_t, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, colscale);
+    else
+      hipLaunchKernelGGL((k_gram<uint8_t, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, colscale);
     hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else {
     return set_error(RS_ERR_UNSUPPORTED, "factor: SA dtype not supported");
@@ -634,9 +786,12 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, in
     } else if (sa_t == RS_F64) {
       Opnd B{reinterpret_cast<const double*>(SA), ldsa, m, d, false};
       hipLaunchKernelGGL((k_whiten<Opnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
-    } else {
+    } else if (sa_t == RS_BF16) {
       HOpnd B{reinterpret_cast<const uint16_t*>(SA), ldsa, m, d, false};
       hipLaunchKernelGGL((k_whiten<HOpnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
+    } else {
+      QOpnd B{reinterpret_cast<const uint8_t*>(SA), ldsa, m, d, false, colscale};
+      hipLaunchKernelGGL((k_whiten<QOpnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
     }
     const int dblk = (int)(dp / NB);
     hipLaunchKernelGGL(k_woodbury_inv, dim3((unsigned)(dblk * (dblk + 1) / 2)), dim3(256), 0, s,

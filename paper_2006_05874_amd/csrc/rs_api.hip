@@ -128,6 +128,8 @@ struct DeviceScratch {
   DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
   // solver-owned sketch and factor
   DevBuf sa, fM, fLinv, fHinv, fCw, fGram;
+  // FP8 staging: FP32 sketch, column maxima, per-column scales
+  DevBuf sa_tmp, colmax, sa_scale;
   void* host_pinned = nullptr;
 };
 
@@ -197,8 +199,8 @@ static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, Srh
 // SRHT into SA (no argument checks).
 static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                           int64_t lda, int64_t m, uint64_t seed, uint32_t sid, void* SA,
-                          rs_dtype sa_t, int64_t ldsa, int64_t* rows_out, int8_t* signs_out,
-                          hipStream_t s) {
+                          rs_dtype sa_t, int64_t ldsa, float* scale_out, int64_t* rows_out,
+                          int8_t* signs_out, hipStream_t s) {
   const int64_t npad = next_pow2(n);
   const int64_t n2 = std::min<int64_t>(npad, 1024);
   const int64_t n1 = npad / n2;
@@ -215,7 +217,14 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
     rows = S.rows.as<int64_t>();
   }
   RS_TRY(srht_select(B, seed, sid, npad, m, n2, rows, s));
-  if (a_t == RS_F32)
+  if (a_t == RS_F32 && sa_t == RS_FP8E4M3) {
+    RS_TRY(S.sa_tmp.ensure((size_t)m * d * sizeof(float)));
+    RS_TRY(S.colmax.ensure((size_t)d * sizeof(uint32_t)));
+    RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, m,
+                                 S.sa_tmp.p, RS_F32, d, Qmax, s));
+    RS_TRY(quantize_fp8(S.sa_tmp.as<float>(), m, d, d, S.colmax.as<uint32_t>(), scale_out,
+                        reinterpret_cast<uint8_t*>(SA), ldsa, s));
+  } else if (a_t == RS_F32)
     RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, m, SA, sa_t,
                                  ldsa, Qmax, s));
   else
@@ -227,9 +236,21 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
 
 static rs_status check_sa_type(rs_dtype a_t, rs_dtype sa_t) {
   if (a_t == RS_F64 && sa_t != RS_F64) return set_error(RS_ERR_UNSUPPORTED, "F64 A needs F64 SA");
-  if (a_t == RS_F32 && !(sa_t == RS_F32 || sa_t == RS_BF16))
-    return set_error(RS_ERR_UNSUPPORTED, "F32 A supports F32 or BF16 SA");
+  if (a_t == RS_F32 && !(sa_t == RS_F32 || sa_t == RS_BF16 || sa_t == RS_FP8E4M3))
+    return set_error(RS_ERR_UNSUPPORTED, "F32 A supports F32, BF16 or FP8E4M3 SA");
   return RS_OK;
+}
+
+// Gaussian sketch into SA (no argument checks); FP8 goes through an FP32 stage.
+static rs_status gauss_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
+                           int64_t lda, int64_t m, uint64_t seed, uint32_t sid, void* SA,
+                           rs_dtype sa_t, int64_t ldsa, float* scale_out, hipStream_t s) {
+  if (sa_t != RS_FP8E4M3) return gauss_launch(A, a_t, n, d, lda, m, seed, sid, SA, sa_t, ldsa, s);
+  RS_TRY(S.sa_tmp.ensure((size_t)m * d * sizeof(float)));
+  RS_TRY(S.colmax.ensure((size_t)d * sizeof(uint32_t)));
+  RS_TRY(gauss_launch(A, a_t, n, d, lda, m, seed, sid, S.sa_tmp.p, RS_F32, d, s));
+  return quantize_fp8(S.sa_tmp.as<float>(), m, d, d, S.colmax.as<uint32_t>(), scale_out,
+                      reinterpret_cast<uint8_t*>(SA), ldsa, s);
 }
 
 }  // namespace rs
@@ -317,15 +338,16 @@ rs_status rs_sketch_srht(const void* A, rs_dtype a_t, int64_t n, int64_t d, int6
   RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_sketch_srht"));
   if (!SA) return set_error(RS_ERR_ARG, "rs_sketch_srht: SA is null");
   RS_TRY(check_sa_type(a_t, sa_t));
-  (void)sa_col_scale;
+  if (sa_t == RS_FP8E4M3 && !sa_col_scale)
+    return set_error(RS_ERR_ARG, "rs_sketch_srht: FP8 output needs sa_col_scale");
   const int64_t npad = next_pow2(n);
   if (npad > (int64_t)1 << 20) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: padded n above 2^20");
   if (m < 1 || m > npad) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: need 1 <= m <= padded n");
   if (ldsa < d) return set_error(RS_ERR_ARG, "rs_sketch_srht: ldsa < d");
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> g(S->mu);
-  return srht_run(*S, A, a_t, n, d, lda, m, seed, sketch_id, SA, sa_t, ldsa, rows_out, signs_out,
-                  stream);
+  return srht_run(*S, A, a_t, n, d, lda, m, seed, sketch_id, SA, sa_t, ldsa, sa_col_scale, rows_out,
+                  signs_out, stream);
 }
 
 rs_status rs_sketch_gaussian(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
@@ -334,10 +356,13 @@ rs_status rs_sketch_gaussian(const void* A, rs_dtype a_t, int64_t n, int64_t d, 
   RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_sketch_gaussian"));
   if (!SA) return set_error(RS_ERR_ARG, "rs_sketch_gaussian: SA is null");
   RS_TRY(check_sa_type(a_t, sa_t));
-  (void)sa_col_scale;
+  if (sa_t == RS_FP8E4M3 && !sa_col_scale)
+    return set_error(RS_ERR_ARG, "rs_sketch_gaussian: FP8 output needs sa_col_scale");
   if (m < 1 || m > n) return set_error(RS_ERR_SHAPE, "rs_sketch_gaussian: need 1 <= m <= n");
   if (ldsa < d) return set_error(RS_ERR_ARG, "rs_sketch_gaussian: ldsa < d");
-  return gauss_launch(A, a_t, n, d, lda, m, seed, sketch_id, SA, sa_t, ldsa, stream);
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  return gauss_run(*S, A, a_t, n, d, lda, m, seed, sketch_id, SA, sa_t, ldsa, sa_col_scale, stream);
 }
 
 static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
@@ -361,12 +386,13 @@ static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
 rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_scale, int64_t m,
                              int64_t d, int64_t ldsa, double nu2, rs_factor** out,
                              hipStream_t stream) {
-  (void)sa_col_scale;
   if (!SA || !out) return set_error(RS_ERR_ARG, "rs_factor_woodbury: null argument");
+  if (sa_t == RS_FP8E4M3 && !sa_col_scale)
+    return set_error(RS_ERR_ARG, "rs_factor_woodbury: FP8 SA needs sa_col_scale");
   if (m < 1 || d < 1 || ldsa < d) return set_error(RS_ERR_SHAPE, "rs_factor_woodbury: bad shape");
   if (!(nu2 > 0.0) || !std::isfinite(nu2))
     return set_error(RS_ERR_NOT_SPD, "rs_factor_woodbury: nu^2 must be positive");
-  if (sa_t != RS_F32 && sa_t != RS_F64 && sa_t != RS_BF16)
+  if (sa_t != RS_F32 && sa_t != RS_F64 && sa_t != RS_BF16 && sa_t != RS_FP8E4M3)
     return set_error(RS_ERR_UNSUPPORTED, "rs_factor_woodbury: SA dtype not supported");
   *out = nullptr;
   rs_factor* F = new rs_factor();
@@ -377,7 +403,7 @@ rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_
                     F->Cw.as<double>(), F->info.as<int>(), F->gram.p, F->gram.bytes};
     hipError_t e = hipMemsetAsync(B.info, 0, sizeof(int), stream);
     if (e != hipSuccess) st = set_error(RS_ERR_HIP, "hipMemsetAsync failed");
-    if (st == RS_OK) st = factor_build(B, SA, sa_t, m, d, ldsa, nu2, stream);
+    if (st == RS_OK) st = factor_build(B, SA, sa_t, sa_col_scale, m, d, ldsa, nu2, stream);
     int info = 0;
     if (st == RS_OK) {
       e = hipMemcpyAsync(&info, B.info, sizeof(int), hipMemcpyDeviceToHost, stream);
@@ -564,15 +590,20 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
 
   const CtlParams cp{prm.mu_p, prm.beta_p, prm.mu_gd, prm.cbar_p, prm.cbar_gd, opts->tol,
                      opts->max_iter};
-  const int64_t ldsa = d;
+  // SA rows padded to a multiple of 64 columns: the low-precision Gram reads
+  // whole 64-column segments
+  const int64_t ldsa = (d + 63) / 64 * 64;
 
   auto sketch_and_factor = [&](int64_t mm, uint32_t id) -> rs_status {
     RS_TRY(S->sa.ensure((size_t)mm * ldsa * sa_es));
+    RS_TRY(S->sa_scale.ensure((size_t)d * sizeof(float)));
+    float* scl = sa_t == RS_FP8E4M3 ? S->sa_scale.as<float>() : nullptr;
     if (srht) {
-      RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, nullptr,
-                      nullptr, stream));
+      RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, scl,
+                      nullptr, nullptr, stream));
     } else {
-      RS_TRY(gauss_launch(A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, stream));
+      RS_TRY(gauss_run(*S, A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, scl,
+                       stream));
     }
     RS_TRY(S->fM.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fLinv.ensure(factor_bytes_M(mm, d)));
@@ -581,7 +612,7 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
     RS_TRY(S->fGram.ensure(factor_bytes_gram(mm, d, sa_t)));
     FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
                      S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes};
-    return factor_build(FB, S->sa.p, sa_t, mm, d, ldsa, nu2, stream);
+    return factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream);
   };
   const int64_t dp = (d + 63) / 64 * 64;
   const double* Hinv_ptr = nullptr;

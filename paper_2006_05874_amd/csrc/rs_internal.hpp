@@ -59,8 +59,13 @@ struct FactorBuffers {
   void* gram;    // split-K partial Grams
   size_t gram_bytes;
 };
-rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t, int64_t m, int64_t d,
-                       int64_t ldsa, double nu2, hipStream_t s);
+rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                       const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------- FP8 storage
+rs_status quantize_fp8(const float* X, int64_t m, int64_t d, int64_t ldx, uint32_t* colmax,
+                       float* scale, uint8_t* Q, int64_t ldq, hipStream_t s);
 size_t factor_bytes_M(int64_t m, int64_t d);
 size_t factor_bytes_Hinv(int64_t d);
 size_t factor_bytes_gram(int64_t m, int64_t d, rs_dtype sa_t);

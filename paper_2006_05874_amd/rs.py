@@ -161,17 +161,21 @@ def rs_params(kind="srht", rho=0.1, eta=0.01):
 
 
 def rs_sketch_srht(A, m, seed=0, sketch_id=0, sa_dtype=None, rows=False, signs=False):
+    """SA (m x d); for sa_dtype "fp8" returns (SA uint8 codes, column scales) in
+    place of SA."""
     a_t = _mat(A, "rs_sketch_srht")
     n, d = A.shape
     sa_dtype = sa_dtype or ("f64" if a_t == 0 else "f32")
     SA = torch.empty(m, d, dtype=TORCH_DTYPES[sa_dtype], device=A.device)
+    scale = torch.empty(d, dtype=torch.float32, device=A.device) if sa_dtype == "fp8" else None
     npad = 1 << max(0, math.ceil(math.log2(n)))
     R = torch.empty(m, dtype=torch.int64, device=A.device) if rows else None
     E = torch.empty(npad, dtype=torch.int8, device=A.device) if signs else None
     st = load().rs_sketch_srht(_ptr(A), a_t, n, d, A.stride(0), m, seed, sketch_id, _ptr(SA),
-                               DTYPES[sa_dtype], SA.stride(0), None, _ptr(R), _ptr(E), _stream())
+                               DTYPES[sa_dtype], SA.stride(0), _ptr(scale), _ptr(R), _ptr(E),
+                               _stream())
     _check(st, "rs_sketch_srht")
-    out = [SA]
+    out = [(SA, scale) if scale is not None else SA]
     if rows:
         out.append(R)
     if signs:
@@ -184,29 +188,36 @@ def rs_sketch_gaussian(A, m, seed=0, sketch_id=0, sa_dtype=None):
     n, d = A.shape
     sa_dtype = sa_dtype or ("f64" if a_t == 0 else "f32")
     SA = torch.empty(m, d, dtype=TORCH_DTYPES[sa_dtype], device=A.device)
+    scale = torch.empty(d, dtype=torch.float32, device=A.device) if sa_dtype == "fp8" else None
     st = load().rs_sketch_gaussian(_ptr(A), a_t, n, d, A.stride(0), m, seed, sketch_id, _ptr(SA),
-                                   DTYPES[sa_dtype], SA.stride(0), None, _stream())
+                                   DTYPES[sa_dtype], SA.stride(0), _ptr(scale), _stream())
     _check(st, "rs_sketch_gaussian")
-    return SA
+    return (SA, scale) if scale is not None else SA
 
 
 class Factor:
-    """Handle from rs_factor_woodbury; keeps SA alive while in use."""
+    """Handle from rs_factor_woodbury; keeps SA alive while in use.  FP8 sketches
+    are passed as (codes uint8, column scales float32)."""
 
     def __init__(self, SA, nu2):
+        scale = None
+        if isinstance(SA, tuple):
+            SA, scale = SA
         if SA.dtype == torch.float32:
             sa_t = DTYPES["f32"]
         elif SA.dtype == torch.float64:
             sa_t = DTYPES["f64"]
         elif SA.dtype == torch.bfloat16:
             sa_t = DTYPES["bf16"]
+        elif SA.dtype == torch.uint8:
+            sa_t = DTYPES["fp8"]
         else:
             raise ValueError("SA dtype")
-        self.SA = SA
+        self.SA, self.scale = SA, scale
         self.m, self.d = SA.shape
         h = ctypes.c_void_p()
-        st = load().rs_factor_woodbury(_ptr(SA), sa_t, None, self.m, self.d, SA.stride(0), nu2,
-                                       ctypes.byref(h), _stream())
+        st = load().rs_factor_woodbury(_ptr(SA), sa_t, _ptr(scale), self.m, self.d, SA.stride(0),
+                                       nu2, ctypes.byref(h), _stream())
         _check(st, "rs_factor_woodbury")
         self.handle = h
 

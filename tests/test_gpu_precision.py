@@ -1,0 +1,130 @@
+"""GPU parity of the precision form: BF16 / FP8-E4M3 sketches, their Gram on the
+matrix cores with FP32 accumulation, FP64 factor, and the outer iteration
+reaching the FP64 oracle's solution."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ihs, lowprec, ridge, sketch  # noqa: E402
+from synth import make_problem, spectrum  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_05874_amd import rs as _rs
+    _rs.load()
+    return _rs
+
+
+def dev_padded(A, rs):
+    T = rs.padded(A.shape[0], A.shape[1], dtype=torch.float32)
+    T.copy_(torch.from_numpy(A))
+    return T
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,d,m", [(1024, 64, 48), (4096, 200, 300), (16384, 33, 1024)])
+def test_srht_fp8_codes_and_scales(rs, n, d, m):
+    A = np.random.default_rng(n + d).standard_normal((n, d)).astype(np.float32)
+    (codes, scale), S32 = (rs.rs_sketch_srht(dev_padded(A, rs), m, seed=4, sketch_id=1,
+                                             sa_dtype="fp8"),
+                           rs.rs_sketch_srht(dev_padded(A, rs), m, seed=4, sketch_id=1))
+    S32 = host(S32).astype(np.float64)
+    # the device quantizes its own FP32 sketch: same scales, codes within one step
+    want_codes, want_scale, _ = lowprec.fp8_quantize(S32)
+    np.testing.assert_array_equal(host(scale).astype(np.float64), want_scale)
+    got = lowprec.e4m3_decode(host(codes)) * want_scale[None, :]
+    ref = lowprec.e4m3_decode(want_codes) * want_scale[None, :]
+    assert np.mean(host(codes) == want_codes) > 0.999
+    # any differing code is a neighbour (ties met in FP32 vs FP64)
+    step = 2.0 ** -3 * np.maximum(np.abs(ref), 2.0 ** -6 * want_scale[None, :])
+    assert np.all(np.abs(got - ref) <= step + 1e-30)
+    # and the FP32 sketch itself matches the dense oracle
+    which = np.arange(min(m, 16))
+    np.testing.assert_allclose(S32[which], sketch.srht_sketch_rows(A.astype(np.float64), 4, 1, m,
+                                                                    which),
+                               rtol=0, atol=1e-4 * np.abs(S32).max())
+
+
+def test_gaussian_bf16_and_fp8(rs):
+    n, d, m = 2048, 72, 40
+    A = np.random.default_rng(9).standard_normal((n, d)).astype(np.float32)
+    Ad = dev_padded(A, rs)
+    S32 = host(rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2)).astype(np.float64)
+    S16 = host(rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2, sa_dtype="bf16").float())
+    np.testing.assert_array_equal(S16.astype(np.float64), lowprec.bf16_round(S32))
+    codes, scale = rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2, sa_dtype="fp8")
+    want_codes, want_scale, _ = lowprec.fp8_quantize(S32)
+    np.testing.assert_array_equal(host(scale).astype(np.float64), want_scale)
+    assert np.mean(host(codes) == want_codes) > 0.999
+
+
+@pytest.mark.parametrize("m,d", [(500, 256), (2048, 128)])
+def test_factor_lowprec_matrix_core_gram(rs, m, d):
+    # m >= d with 64-aligned rows: the Gram runs on the BF16 / FP8 K=32 MFMA path
+    rng = np.random.default_rng(m + 3 * d)
+    SA = rng.standard_normal((m, d)) / np.sqrt(m)
+    g = rng.standard_normal((1, d))
+    for dt in ("bf16", "fp8"):
+        if dt == "bf16":
+            dev = torch.from_numpy(SA.astype(np.float32)).cuda().to(torch.bfloat16)
+            used = dev.float().double().cpu().numpy()
+            arg = dev
+        else:
+            codes, s, used = lowprec.fp8_quantize(SA)
+            arg = (torch.from_numpy(codes).cuda(), torch.from_numpy(s.astype(np.float32)).cuda())
+        F = rs.rs_factor_woodbury(arg, 0.05)
+        GT, r = F.apply(torch.from_numpy(g).cuda())
+        want, rw = ihs.SketchedHessian(used, 0.05).decrement(g[0])
+        # BF16 products are summed exactly in FP32 (Gram error ~1e-8, times
+        # cond(H_S) ~ 1e2 here).  The FP8 K=32 instruction sums less exactly
+        # (Gram error ~1e-6 measured against the dequantized values), so its
+        # bound is 50x wider; H_S stays SPD and the outer iteration absorbs it.
+        tol = 2e-5 if dt == "bf16" else 1e-3
+        np.testing.assert_allclose(host(GT)[0], want, rtol=tol, atol=tol * np.abs(want).max())
+        assert abs(host(r)[0] - rw) <= tol * rw
+        F.close()
+
+
+@pytest.mark.parametrize("m,d", [(40, 100), (300, 200)])
+def test_factor_fp8_against_oracle(rs, m, d):
+    rng = np.random.default_rng(m + d)
+    SA = rng.standard_normal((m, d)) / np.sqrt(d)
+    codes, s, deq = lowprec.fp8_quantize(SA)
+    F = rs.rs_factor_woodbury((torch.from_numpy(codes).cuda(),
+                               torch.from_numpy(s.astype(np.float32)).cuda()), 0.1)
+    g = rng.standard_normal((1, d))
+    GT, r = F.apply(torch.from_numpy(g).cuda())
+    want, rw = ihs.SketchedHessian(deq, 0.1).decrement(g[0])
+    np.testing.assert_allclose(host(GT)[0], want, rtol=3e-5, atol=3e-5 * np.abs(want).max())
+    F.close()
+
+
+@pytest.fixture(scope="module")
+def problem():
+    # the precision workload's spectrum shape (exponential decay), shrunk so the
+    # oracle finishes in seconds
+    p = make_problem(8192, 256, spectrum("exp", 256, 25.0), 1e-3, 0.1, 0)
+    A64 = p.A.astype(np.float64)
+    xs = ridge.solve_direct(A64, p.b.astype(np.float64), p.nu2)
+    return p, xs, ridge.hessian(A64, p.nu2)
+
+
+@pytest.mark.parametrize("kind", ["srht", "gaussian"])
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_precision_form_reaches_oracle_solution(rs, problem, kind, dt):
+    p, xs, H = problem
+    x, info = rs.rs_adaptive_solve(dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2,
+                                   kind=kind, sketch_dtype=dt)
+    assert info["status"] == "ok", info
+    rel = ridge.relative_error(H, host(x), xs)
+    assert rel <= 1e-6, rel
