@@ -220,6 +220,55 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
                             const void* b, double nu2, const rs_solve_opts* opts,
                             double* x, rs_solve_info* info, hipStream_t stream);
 
+/* ------------------------------------------------------------------ learned start */
+
+/* Algorithm 1 holds for any initial sketch size (Theorems 5 and 6).  The learned
+ * form predicts log2 of the final sketch size of a plain run from 16 features and
+ * starts the doubling ladder at m_init = 2^floor(prediction); the adaptive rule
+ * stays as the fallback.  The predictor is a 16 -> 128 -> 128 -> 1 MLP with exact
+ * GELU, FP32, parameters in one flat array:
+ *   W1 [16][128] at 0, b1 [128] at 2048, W2 [128][128] at 2176, b2 [128] at 18560,
+ *   W3 [128] at 18688, b3 at 18816 (RS_MLP_PARAMS floats). */
+#define RS_MLP_FEATURES 16
+#define RS_MLP_PARAMS 18817
+#define RS_MLP_CACHE 273   /* floats per sample kept by the forward pass */
+#define RS_MLP_WORK 257    /* floats per sample used by the backward pass */
+
+/* Features of (A, nu^2), 16 floats on the device (feat):
+ *   log2 n, log2 d, log10 nu^2;
+ *   ln q_k, k = 0..7, q_k = (A^T w_k)^T H_S0^-1 (A^T w_k) with w_k Rademacher
+ *     (Philox stream 7, sketch_id k, counter = row) and H_S0 the sketched Hessian of
+ *     a min(256, padded n)-row SRHT (seed, sketch_id 0x7fff0000): a Hutchinson
+ *     estimate of the effective dimension tr(A H^-1 A^T);
+ *   order statistics at round(q (d-1)), q = 0, 1/4, 1/2, 3/4, 1, of ln ||A e_j||.
+ * d <= 8192.  Asynchronous. */
+rs_status rs_features(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                      double nu2, uint64_t seed, float* feat, hipStream_t stream);
+
+/* y[s] = MLP((X[s] - mu) / sd) for B samples (X: B x 16, mu, sd: 16; all device
+ * FP32).  cache: NULL or B * RS_MLP_CACHE floats kept for rs_mlp_backward. */
+rs_status rs_mlp_forward(const float* params, const float* X, int64_t B, const float* mu,
+                         const float* sd, float* y, float* cache, hipStream_t stream);
+
+/* Gradient of the loss mean_s (y_s - t_s)^2 with respect to every parameter
+ * (grad: RS_MLP_PARAMS floats), from the forward cache.  loss: NULL or one device
+ * float.  work: B * RS_MLP_WORK floats of scratch.  Sums over the batch run in a
+ * fixed order (deterministic).  Asynchronous. */
+rs_status rs_mlp_backward(const float* params, const float* cache, const float* t, int64_t B,
+                          float* grad, float* loss, float* work, hipStream_t stream);
+
+/* One Adam step (bias-corrected; step counts from 1) on count parameters. */
+rs_status rs_mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t count,
+                           int64_t step, float lr, float beta1, float beta2, float eps,
+                           hipStream_t stream);
+
+/* Features -> MLP -> m_init = clamp(2^floor(y), 1, m_max) -> rs_adaptive_solve with
+ * opts->m_init replaced.  m_init_used: host, may be NULL.  Synchronizes. */
+rs_status rs_learned_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                           const void* b, double nu2, const rs_solve_opts* opts,
+                           const float* params, const float* mu, const float* sd, double* x,
+                           rs_solve_info* info, int64_t* m_init_used, hipStream_t stream);
+
 /* ------------------------------------------------------------------ timing */
 
 /* Diagnostics for measuring the dominant kernel (not part of the method).

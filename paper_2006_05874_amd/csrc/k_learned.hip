@@ -1,0 +1,313 @@
+// Learned starting sketch size: features of a problem, and a small MLP trained
+// on the GPU by these kernels (forward, backward, Adam).
+//
+// Algorithm 1's guarantees hold for any initial sketch size (Theorems 5 and 6);
+// the predictor only decides where the doubling ladder starts.
+//
+// Features (16): log2 n, log2 d, log10 nu^2; ln of 8 Hutchinson probes
+// q_k = (A^T w_k)^T H_S0^-1 (A^T w_k) (w_k Rademacher from Philox stream 7, H_S0
+// from a 256-row SRHT); quantiles 0, 1/4, 1/2, 3/4, 1 of ln ||A e_j||.
+// MLP: 16 -> 128 -> 128 -> 1, exact GELU, inputs standardised (f - mu) / sd.
+#include "rs_internal.hpp"
+
+namespace rs {
+
+constexpr int kFeat = 16;
+constexpr int kHid = 128;
+constexpr int kProbes = 8;
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + kFeat * kHid;
+constexpr int OFF_W2 = OFF_B1 + kHid;
+constexpr int OFF_B2 = OFF_W2 + kHid * kHid;
+constexpr int OFF_W3 = OFF_B2 + kHid;
+constexpr int OFF_B3 = OFF_W3 + kHid;
+constexpr int kParams = OFF_B3 + 1;
+constexpr int kCache = kFeat + 2 * kHid + 1;   // xn, z1, z2, y per sample
+constexpr int kWork = 2 * kHid + 1;            // dz1, dz2, dy per sample
+
+// ------------------------------------------------------------------ features
+// Column sums over a chunk of 256 rows: acc[k][j] = sum_i w_k(i) A[i][j] for the
+// 8 probes and acc[8][j] = sum_i A[i][j]^2; thread = column, FP64 sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, int64_t n,
+                                                       int64_t d, int64_t lda, uint64_t seed,
+                                                       int64_t rows_per_chunk,
+                                                       double* __restrict__ part) {
+  __shared__ uint8_t sgn[256];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
+  double acc[kProbes + 1];
+#pragma unroll
+  for (int k = 0; k <= kProbes; ++k) acc[k] = 0.0;
+  for (int64_t base = r0; base < r1; base += 256) {
+    __syncthreads();
+    {
+      const int64_t i = base + threadIdx.x;
+      uint8_t bits = 0;
+      if (i < r1) {
+#pragma unroll
+        for (int k = 0; k < kProbes; ++k) {
+          const uint4 w = draw(seed, kStreamProbe, (uint32_t)k, (uint64_t)i);
+          bits |= (uint8_t)((w.x & 1u) << k);
+        }
+      }
+      sgn[threadIdx.x] = bits;
+    }
+    __syncthreads();
+    if (j < d) {
+      const int64_t cnt = (r1 - base) < 256 ? (r1 - base) : 256;
+      for (int64_t ii = 0; ii < cnt; ++ii) {
+        const double a = (double)A[(base + ii) * lda + j];
+        const uint8_t bits = sgn[ii];
+#pragma unroll
+        for (int k = 0; k < kProbes; ++k) acc[k] += ((bits >> k) & 1) ? -a : a;
+        acc[kProbes] = fma(a, a, acc[kProbes]);
+      }
+    }
+  }
+  if (j < d) {
+#pragma unroll
+    for (int k = 0; k <= kProbes; ++k) part[((int64_t)blockIdx.y * (kProbes + 1) + k) * d + j] = acc[k];
+  }
+}
+
+// U[k][j] = sum over chunks (fixed order), k = 0..8.
+__global__ __launch_bounds__(256) void k_probe_finish(const double* __restrict__ part, int nchunk,
+                                                      int64_t d, double* __restrict__ U) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t tot = (int64_t)(kProbes + 1) * d;
+  if (e >= tot) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * tot + e];
+  U[e] = s;
+}
+
+// One block: q_k = 2 r_k (r from the apply of the probes), log column norms,
+// sort, quantiles, and the 16 features.
+__global__ __launch_bounds__(1024) void k_feature_final(const double* __restrict__ U, int64_t d,
+                                                        const double* __restrict__ rprobe,
+                                                        int64_t n, double nu2,
+                                                        float* __restrict__ feat) {
+  __shared__ float v[8192];
+  int P = 1;
+  while (P < d) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += 1024) {
+    float x = 3.0e38f;
+    if (i < d) {
+      const double c2 = U[(int64_t)kProbes * d + i];
+      x = (float)(0.5 * log(c2 > 1e-300 ? c2 : 1e-300));
+    }
+    v[i] = x;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += 1024) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          if ((v[i] > v[l]) == up) {
+            const float t = v[i];
+            v[i] = v[l];
+            v[l] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    feat[0] = (float)log2((double)n);
+    feat[1] = (float)log2((double)d);
+    feat[2] = (float)log10(nu2);
+    for (int k = 0; k < kProbes; ++k) {
+      const double q = 2.0 * rprobe[k];
+      feat[3 + k] = (float)log(q > 1e-30 ? q : 1e-30);
+    }
+    const double qs[5] = {0.0, 0.25, 0.5, 0.75, 1.0};
+    for (int i = 0; i < 5; ++i) {
+      const int idx = (int)rint(qs[i] * (double)(d - 1));
+      feat[11 + i] = v[idx];
+    }
+  }
+}
+
+int feature_chunks(int64_t n) {
+  const int64_t c = (n + 4095) / 4096;
+  return (int)(c < 256 ? c : 256);
+}
+
+template <typename T>
+rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
+                        double* part, double* U, hipStream_t s) {
+  const int nchunk = feature_chunks(n);
+  const int64_t rpc = ((n + nchunk - 1) / nchunk + 255) / 256 * 256;
+  const int nch = (int)((n + rpc - 1) / rpc);
+  hipLaunchKernelGGL(k_probe_partial<T>, dim3((unsigned)((d + 255) / 256), (unsigned)nch), dim3(256),
+                     0, s, A, n, d, lda, seed, rpc, part);
+  const int64_t tot = (int64_t)(kProbes + 1) * d;
+  hipLaunchKernelGGL(k_probe_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
+                     nch, d, U);
+  return check_launch("features pass");
+}
+template rs_status features_pass<float>(const float*, int64_t, int64_t, int64_t, uint64_t, double*,
+                                        double*, hipStream_t);
+template rs_status features_pass<double>(const double*, int64_t, int64_t, int64_t, uint64_t,
+                                         double*, double*, hipStream_t);
+
+rs_status features_final(const double* U, int64_t d, const double* rprobe, int64_t n, double nu2,
+                         float* feat, hipStream_t s) {
+  if (d > 8192) return set_error(RS_ERR_UNSUPPORTED, "features: d above 8192");
+  hipLaunchKernelGGL(k_feature_final, dim3(1), dim3(1024), 0, s, U, d, rprobe, n, nu2, feat);
+  return check_launch("features final");
+}
+
+// ------------------------------------------------------------------ MLP
+__device__ __forceinline__ float gelu_f(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// One block (128 threads) per sample; cache row: xn (16), z1, z2 (128 each), y.
+__global__ __launch_bounds__(128) void k_mlp_forward(const float* __restrict__ P,
+                                                     const float* __restrict__ X, int64_t B,
+                                                     const float* __restrict__ mu,
+                                                     const float* __restrict__ sd,
+                                                     float* __restrict__ Y,
+                                                     float* __restrict__ cache) {
+  __shared__ float xn[kFeat];
+  __shared__ float h1[kHid];
+  __shared__ float part[kHid];
+  const int64_t s = blockIdx.x;
+  const int u = threadIdx.x;
+  if (u < kFeat) xn[u] = (X[s * kFeat + u] - mu[u]) / sd[u];
+  __syncthreads();
+  float z1 = P[OFF_B1 + u];
+#pragma unroll
+  for (int k = 0; k < kFeat; ++k) z1 = fmaf(xn[k], P[OFF_W1 + k * kHid + u], z1);
+  h1[u] = gelu_f(z1);
+  __syncthreads();
+  float z2 = P[OFF_B2 + u];
+  for (int v = 0; v < kHid; ++v) z2 = fmaf(h1[v], P[OFF_W2 + v * kHid + u], z2);
+  part[u] = gelu_f(z2) * P[OFF_W3 + u];
+  __syncthreads();
+  for (int off = kHid / 2; off > 0; off >>= 1) {
+    if (u < off) part[u] += part[u + off];
+    __syncthreads();
+  }
+  const float y = part[0] + P[OFF_B3];
+  if (u == 0) Y[s] = y;
+  if (cache) {
+    float* c = cache + s * kCache;
+    if (u < kFeat) c[u] = xn[u];
+    c[kFeat + u] = z1;
+    c[kFeat + kHid + u] = z2;
+    if (u == 0) c[kFeat + 2 * kHid] = y;
+  }
+}
+
+// Per-sample deltas of the loss mean((y - t)^2): dy, dz2, dz1 into work.
+__global__ __launch_bounds__(128) void k_mlp_delta(const float* __restrict__ P,
+                                                   const float* __restrict__ cache,
+                                                   const float* __restrict__ T, int64_t B,
+                                                   float* __restrict__ work) {
+  __shared__ float dz2[kHid];
+  const int64_t s = blockIdx.x;
+  const int u = threadIdx.x;
+  const float* c = cache + s * kCache;
+  const float dy = 2.0f * (c[kFeat + 2 * kHid] - T[s]) / (float)B;
+  const float g2 = dy * P[OFF_W3 + u] * gelu_grad_f(c[kFeat + kHid + u]);
+  dz2[u] = g2;
+  __syncthreads();
+  float dh1 = 0.0f;
+  for (int w = 0; w < kHid; ++w) dh1 = fmaf(dz2[w], P[OFF_W2 + u * kHid + w], dh1);
+  float* wk = work + s * kWork;
+  wk[u] = dh1 * gelu_grad_f(c[kFeat + u]);
+  wk[kHid + u] = g2;
+  if (u == 0) wk[2 * kHid] = dy;
+}
+
+// Gradient of every parameter: a fixed-order sum over the batch.  Also the
+// loss (by the thread of b3).
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ cache,
+                                                  const float* __restrict__ work, int64_t B,
+                                                  float* __restrict__ G, float* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= kParams) return;
+  float acc = 0.0f;
+  float lacc = 0.0f;
+  for (int64_t s = 0; s < B; ++s) {
+    const float* c = cache + s * kCache;
+    const float* w = work + s * kWork;
+    float v;
+    if (p < OFF_B1) {
+      const int k = p / kHid, u = p % kHid;
+      v = c[k] * w[u];
+    } else if (p < OFF_W2) {
+      v = w[p - OFF_B1];
+    } else if (p < OFF_B2) {
+      const int q = p - OFF_W2;
+      const int vv = q / kHid, u = q % kHid;
+      v = gelu_f(c[kFeat + vv]) * w[kHid + u];
+    } else if (p < OFF_W3) {
+      v = w[kHid + (p - OFF_B2)];
+    } else if (p < OFF_B3) {
+      const int u = p - OFF_W3;
+      v = gelu_f(c[kFeat + kHid + u]) * w[2 * kHid];
+    } else {
+      v = w[2 * kHid];
+      const float r = w[2 * kHid] * (float)B * 0.5f;
+      lacc = fmaf(r, r, lacc);
+    }
+    acc += v;
+  }
+  G[p] = acc;
+  if (p == OFF_B3 && loss) *loss = lacc / (float)B;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ Pm, const float* __restrict__ G,
+                                              float* __restrict__ M, float* __restrict__ V,
+                                              int64_t count, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float g = G[i];
+  const float m = b1 * M[i] + (1.0f - b1) * g;
+  const float v = b2 * V[i] + (1.0f - b2) * g * g;
+  M[i] = m;
+  V[i] = v;
+  Pm[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+rs_status mlp_forward(const float* P, const float* X, int64_t B, const float* mu, const float* sd,
+                      float* Y, float* cache, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)B), dim3(kHid), 0, s, P, X, B, mu, sd, Y, cache);
+  return check_launch("mlp forward");
+}
+
+rs_status mlp_backward(const float* P, const float* cache, const float* T, int64_t B, float* G,
+                       float* loss, float* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_delta, dim3((unsigned)B), dim3(kHid), 0, s, P, cache, T, B, work);
+  hipLaunchKernelGGL(k_mlp_grad, dim3((kParams + 255) / 256), dim3(256), 0, s, cache, work, B, G,
+                     loss);
+  return check_launch("mlp backward");
+}
+
+rs_status mlp_adam(float* P, const float* G, float* M, float* V, int64_t count, int64_t step,
+                   float lr, float b1, float b2, float eps, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step);
+  const float c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, P, G, M, V,
+                     count, lr, b1, b2, eps, c1, c2);
+  return check_launch("adam");
+}
+
+int mlp_params() { return kParams; }
+int mlp_cache_floats() { return kCache; }
+int mlp_work_floats() { return kWork; }
+
+}  // namespace rs

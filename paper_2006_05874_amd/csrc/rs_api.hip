@@ -130,6 +130,8 @@ struct DeviceScratch {
   DevBuf sa, fM, fLinv, fHinv, fCw, fGram;
   // FP8 staging: FP32 sketch, column maxima, per-column scales
   DevBuf sa_tmp, colmax, sa_scale;
+  // learned form: probe sketch and its factor, probe sums, features
+  DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
   void* host_pinned = nullptr;
 };
 
@@ -722,6 +724,119 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
   info->r_ref = h.r_ref;
   info->n_events = std::min<int64_t>(ne, RS_MAX_EVENTS);
   return result;
+}
+
+}  // extern "C"
+
+// ==================================================================== learned form
+extern "C" {
+
+rs_status rs_features(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, double nu2,
+                      uint64_t seed, float* feat, hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_features"));
+  if (!feat) return set_error(RS_ERR_ARG, "rs_features: feat is null");
+  if (d > 8192) return set_error(RS_ERR_UNSUPPORTED, "rs_features: d above 8192");
+  if (!(nu2 > 0.0)) return set_error(RS_ERR_NOT_SPD, "rs_features: nu^2 must be positive");
+  const int64_t npad = next_pow2(n);
+  if (npad > (int64_t)1 << 20) return set_error(RS_ERR_SHAPE, "rs_features: padded n above 2^20");
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  const int64_t m0 = std::min<int64_t>(256, npad);
+  const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
+  const int64_t es = a_t == RS_F64 ? 8 : 4;
+  // 1. the probe sketch and its factor
+  RS_TRY(S->psa.ensure((size_t)m0 * d * es));
+  RS_TRY(srht_run(*S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S->psa.p, sa_t, d, nullptr,
+                  nullptr, nullptr, stream));
+  RS_TRY(S->pM.ensure(factor_bytes_M(m0, d)));
+  RS_TRY(S->pLinv.ensure(factor_bytes_M(m0, d)));
+  RS_TRY(S->pHinv.ensure(factor_bytes_Hinv(d)));
+  if (m0 < d) RS_TRY(S->pCw.ensure(factor_bytes_Cw(m0, d)));
+  RS_TRY(S->pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
+  RS_TRY(S->pinfo.ensure(sizeof(int), true));
+  FactorBuffers FB{S->pM.as<double>(), S->pLinv.as<double>(), S->pHinv.as<double>(),
+                   S->pCw.as<double>(), S->pinfo.as<int>(), S->pGram.p, S->pGram.bytes};
+  RS_TRY(factor_build(FB, S->psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
+  // 2. one pass over A: the 8 probes A^T w_k and the squared column norms
+  const int nch = feature_chunks(n);
+  RS_TRY(S->ppart.ensure((size_t)nch * 9 * d * sizeof(double)));
+  RS_TRY(S->pU.ensure((size_t)9 * d * sizeof(double)));
+  if (a_t == RS_F32)
+    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda, seed,
+                                S->ppart.as<double>(), S->pU.as<double>(), stream));
+  else
+    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda, seed,
+                                 S->ppart.as<double>(), S->pU.as<double>(), stream));
+  // 3. q_k = u_k^T H_S0^-1 u_k = 2 r_k (two applies of 4 probes)
+  const int nrp = apply_blocks(d);
+  const int64_t dp = (d + 63) / 64 * 64;
+  RS_TRY(S->pY.ensure((size_t)8 * d * sizeof(double)));
+  RS_TRY(S->prp.ensure((size_t)nrp * 4 * sizeof(double)));
+  RS_TRY(S->pr.ensure(8 * sizeof(double)));
+  for (int h = 0; h < 2; ++h) {
+    RS_TRY(apply_launch(S->pHinv.as<double>(), dp, d, S->pU.as<double>() + (int64_t)4 * h * d, 4,
+                        S->pY.as<double>() + (int64_t)4 * h * d, S->prp.as<double>(), nullptr,
+                        stream));
+    RS_TRY(rsum_launch(S->prp.as<double>(), nrp, 4, S->pr.as<double>() + 4 * h, stream));
+  }
+  return features_final(S->pU.as<double>(), d, S->pr.as<double>(), n, nu2, feat, stream);
+}
+
+rs_status rs_mlp_forward(const float* params, const float* X, int64_t B, const float* mu,
+                         const float* sd, float* y, float* cache, hipStream_t stream) {
+  if (!params || !X || !mu || !sd || !y) return set_error(RS_ERR_ARG, "rs_mlp_forward: null argument");
+  if (B < 1) return set_error(RS_ERR_SHAPE, "rs_mlp_forward: empty batch");
+  return mlp_forward(params, X, B, mu, sd, y, cache, stream);
+}
+
+rs_status rs_mlp_backward(const float* params, const float* cache, const float* t, int64_t B,
+                          float* grad, float* loss, float* work, hipStream_t stream) {
+  if (!params || !cache || !t || !grad || !work)
+    return set_error(RS_ERR_ARG, "rs_mlp_backward: null argument");
+  if (B < 1) return set_error(RS_ERR_SHAPE, "rs_mlp_backward: empty batch");
+  return mlp_backward(params, cache, t, B, grad, loss, work, stream);
+}
+
+rs_status rs_mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t count,
+                           int64_t step, float lr, float beta1, float beta2, float eps,
+                           hipStream_t stream) {
+  if (!params || !grad || !m || !v) return set_error(RS_ERR_ARG, "rs_mlp_adam_step: null argument");
+  if (count < 1 || step < 1) return set_error(RS_ERR_ARG, "rs_mlp_adam_step: count, step >= 1");
+  return mlp_adam(params, grad, m, v, count, step, lr, beta1, beta2, eps, stream);
+}
+
+rs_status rs_learned_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                           const void* b, double nu2, const rs_solve_opts* opts,
+                           const float* params, const float* mu, const float* sd, double* x,
+                           rs_solve_info* info, int64_t* m_init_used, hipStream_t stream) {
+  if (!opts || !params || !mu || !sd) return set_error(RS_ERR_ARG, "rs_learned_solve: null argument");
+  float* feat;
+  float* yp;
+  {
+    DeviceScratch* S = scratch_for_current();
+    std::lock_guard<std::mutex> g(S->mu);
+    RS_TRY(S->pfeat.ensure(16 * sizeof(float)));
+    RS_TRY(S->py.ensure(sizeof(float)));
+    feat = S->pfeat.as<float>();
+    yp = S->py.as<float>();
+  }
+  RS_TRY(rs_features(A, a_t, n, d, lda, nu2, opts->seed, feat, stream));
+  RS_TRY(mlp_forward(params, feat, 1, mu, sd, yp, nullptr, stream));
+  float pred = 0.0f;
+  RS_HIP(hipMemcpyAsync(&pred, yp, sizeof(float), hipMemcpyDeviceToHost, stream));
+  RS_HIP(hipStreamSynchronize(stream));
+  const int64_t cap = opts->kind == RS_SKETCH_SRHT ? next_pow2(n) : n;
+  const int64_t mmax = opts->m_max > 0 ? std::min<int64_t>(opts->m_max, cap) : cap;
+  int64_t m0 = 1;
+  if (std::isfinite(pred) && pred > 0.0f) {
+    const int e = (int)std::floor(std::min(pred, 40.0f));
+    m0 = (int64_t)1 << e;
+  }
+  m0 = std::max<int64_t>(1, std::min<int64_t>(m0, mmax));
+  if (m_init_used) *m_init_used = m0;
+  rs_solve_opts o = *opts;
+  o.m_init = m0;
+  return rs_adaptive_solve(A, a_t, n, d, lda, b, nu2, &o, x, info, stream);
 }
 
 }  // extern "C"

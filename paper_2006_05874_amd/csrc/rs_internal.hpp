@@ -122,4 +122,21 @@ rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double
                                const double* GT, double* gt, int at_cap, hipStream_t s);
 rs_status pack2_launch(int64_t d, const double* a, const double* b, double* out, hipStream_t s);
 
+// ---------------------------------------------------------------- learned form
+int feature_chunks(int64_t n);
+template <typename T>
+rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
+                        double* part, double* U, hipStream_t s);
+rs_status features_final(const double* U, int64_t d, const double* rprobe, int64_t n, double nu2,
+                         float* feat, hipStream_t s);
+rs_status mlp_forward(const float* P, const float* X, int64_t B, const float* mu, const float* sd,
+                      float* Y, float* cache, hipStream_t s);
+rs_status mlp_backward(const float* P, const float* cache, const float* T, int64_t B, float* G,
+                       float* loss, float* work, hipStream_t s);
+rs_status mlp_adam(float* P, const float* G, float* M, float* V, int64_t count, int64_t step,
+                   float lr, float b1, float b2, float eps, hipStream_t s);
+int mlp_params();
+int mlp_cache_floats();
+int mlp_work_floats();
+
 }  // namespace rs

@@ -76,7 +76,11 @@ class SolveInfo(ctypes.Structure):
 EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
            "rs_factor_apply", "rs_factor_destroy", "rs_gradient", "rs_ihs_step",
            "rs_solve_opts_default", "rs_adaptive_solve", "rs_last_error", "rs_version",
-           "rs_profile_enable", "rs_profile_read"]
+           "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
+           "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve"]
+MLP_PARAMS = 18817
+MLP_CACHE = 273
+MLP_WORK = 257
 
 _lib = None
 
@@ -110,11 +114,20 @@ def load(path=LIB_PATH):
                                     vp, ctypes.POINTER(SolveInfo), vp]
     L.rs_profile_enable.argtypes = [c_int]
     L.rs_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    L.rs_features.argtypes = [vp, c_int, i64, i64, i64, dbl, u64, vp, vp]
+    L.rs_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    L.rs_mlp_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    L.rs_mlp_adam_step.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, vp]
+    L.rs_learned_solve.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, ctypes.POINTER(SolveOpts),
+                                   vp, vp, vp, vp, ctypes.POINTER(SolveInfo),
+                                   ctypes.POINTER(i64), vp]
     L.rs_last_error.restype = ctypes.c_char_p
     L.rs_version.restype = ctypes.c_char_p
     for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
                  "rs_factor_apply", "rs_gradient", "rs_ihs_step", "rs_adaptive_solve",
-                 "rs_profile_enable", "rs_profile_read"]:
+                 "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
+                 "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -281,23 +294,34 @@ def rs_ihs_step(A, b, nu2, F, params, variant, state):
     return {"accepted": out.accepted, "r_p": out.r_p, "r_gd": out.r_gd}
 
 
-def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh",
-                      sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
-                      max_iter=200, seed=0, check_every=4, x0=None, raise_on_error=True):
-    """Algorithm 1 end to end.  Returns (x float64 tensor, info dict)."""
-    a_t = _mat(A, "rs_adaptive_solve")
-    n, d = A.shape
+def _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
+          seed, check_every):
     o = SolveOpts()
     load().rs_solve_opts_default(ctypes.byref(o))
     o.kind, o.variant, o.resample = SKETCH[kind], VARIANT[variant], RESAMPLE[resample]
     o.sketch_dtype = DTYPES[sketch_dtype or ("f64" if a_t == 0 else "f32")]
     o.rho, o.eta, o.m_init, o.m_max, o.tol = rho, eta, m_init, m_max, tol
     o.max_iter, o.seed, o.check_every = max_iter, seed, check_every
+    return o
+
+
+def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh",
+                      sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
+                      max_iter=200, seed=0, check_every=4, x0=None, raise_on_error=True):
+    """Algorithm 1 end to end.  Returns (x float64 tensor, info dict)."""
+    a_t = _mat(A, "rs_adaptive_solve")
+    n, d = A.shape
+    o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
+              seed, check_every)
     x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
          else x0.to(torch.float64).contiguous().clone())
     info = SolveInfo()
     st = load().rs_adaptive_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
                                   ctypes.byref(o), _ptr(x), ctypes.byref(info), _stream())
+    return x, _info(info, st, raise_on_error, "rs_adaptive_solve")
+
+
+def _info(info, st, raise_on_error, where):
     res = {
         "status": STATUS_NAMES.get(info.status, str(info.status)),
         "m_final": info.m_final, "doublings": info.doublings, "steps": info.steps,
@@ -308,8 +332,63 @@ def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh"
                     int(info.event_m[i])) for i in range(info.n_events)],
     }
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
-        _check(st, "rs_adaptive_solve")
+        _check(st, where)
     res["status_code"] = st
+    return res
+
+
+def rs_features(A, nu2, seed=0):
+    """16 FP32 features of (A, nu2) on the device."""
+    a_t = _mat(A, "rs_features")
+    n, d = A.shape
+    f = torch.empty(16, dtype=torch.float32, device=A.device)
+    _check(load().rs_features(_ptr(A), a_t, n, d, A.stride(0), nu2, seed, _ptr(f), _stream()),
+           "rs_features")
+    return f
+
+
+def rs_mlp_forward(params, X, mu, sd, cache=False):
+    X = X.contiguous()
+    B = X.shape[0]
+    y = torch.empty(B, dtype=torch.float32, device=X.device)
+    C = torch.empty(B, MLP_CACHE, dtype=torch.float32, device=X.device) if cache else None
+    _check(load().rs_mlp_forward(_ptr(params), _ptr(X), B, _ptr(mu), _ptr(sd), _ptr(y), _ptr(C),
+                                 _stream()), "rs_mlp_forward")
+    return (y, C) if cache else y
+
+
+def rs_mlp_backward(params, cache, t):
+    B = t.shape[0]
+    G = torch.empty(MLP_PARAMS, dtype=torch.float32, device=t.device)
+    loss = torch.empty(1, dtype=torch.float32, device=t.device)
+    work = torch.empty(B, MLP_WORK, dtype=torch.float32, device=t.device)
+    _check(load().rs_mlp_backward(_ptr(params), _ptr(cache), _ptr(t.contiguous()), B, _ptr(G),
+                                  _ptr(loss), _ptr(work), _stream()), "rs_mlp_backward")
+    return G, loss
+
+
+def rs_mlp_adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load().rs_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(),
+                                   step, lr, b1, b2, eps, _stream()), "rs_mlp_adam_step")
+
+
+def rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant="polyak", resample="fresh",
+                     sketch_dtype=None, rho=0.1, eta=0.01, m_max=0, tol=1e-7, max_iter=200,
+                     seed=0, check_every=4, x0=None, raise_on_error=True):
+    """Learned starting m, then Algorithm 1.  Returns (x, info) with info["m_init"]."""
+    a_t = _mat(A, "rs_learned_solve")
+    n, d = A.shape
+    o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, 1, m_max, tol, max_iter,
+              seed, check_every)
+    x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
+         else x0.to(torch.float64).contiguous().clone())
+    info = SolveInfo()
+    used = ctypes.c_int64(0)
+    st = load().rs_learned_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+                                 ctypes.byref(o), _ptr(params), _ptr(mu), _ptr(sd), _ptr(x),
+                                 ctypes.byref(info), ctypes.byref(used), _stream())
+    res = _info(info, st, raise_on_error, "rs_learned_solve")
+    res["m_init"] = used.value
     return x, res
 
 

@@ -1,0 +1,129 @@
+"""GPU parity of the learned-start form: features, MLP forward/backward and Adam
+against the FP64 oracle, training on the GPU, and the learned solve's fallback."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import learned, ridge  # noqa: E402
+from synth import config_c1, make_problem, spectrum  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_05874_amd import rs as _rs
+    _rs.load()
+    return _rs
+
+
+def dev_padded(A, rs):
+    dt = torch.float64 if A.dtype == np.float64 else torch.float32
+    T = rs.padded(A.shape[0], A.shape[1], dtype=dt)
+    T.copy_(torch.from_numpy(A))
+    return T
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,d,dt", [(1024, 64, np.float64), (3000, 200, np.float64),
+                                    (5000, 300, np.float32), (100, 37, np.float64)])
+def test_features_against_oracle(rs, n, d, dt):
+    p = make_problem(n, d, spectrum("poly", d, 1.0), 1e-3, 0.1, n + d, dtype=dt)
+    f = host(rs.rs_features(dev_padded(p.A, rs), p.nu2, seed=7)).astype(np.float64)
+    want = learned.features(p.A.astype(np.float64), p.nu2, 7)
+    np.testing.assert_allclose(f[:3], want[:3], rtol=1e-6)
+    # probes: FP32 storage of the feature; FP32 sketch for FP32 data
+    tol = 1e-5 if dt == np.float64 else 2e-3
+    np.testing.assert_allclose(f[3:11], want[3:11], rtol=0, atol=tol)
+    np.testing.assert_allclose(f[11:], want[11:], rtol=0, atol=1e-5)
+
+
+@pytest.fixture(scope="module")
+def mlp_case():
+    rng = np.random.default_rng(0)
+    X = (rng.standard_normal((64, 16)) * 3 + 1).astype(np.float32)
+    t = (rng.standard_normal(64) * 2 + 5).astype(np.float32)
+    mu = X.mean(0).astype(np.float32)
+    sd = (X.std(0) + 0.1).astype(np.float32)
+    th = learned.init_params(1).astype(np.float32)
+    return X, t, mu, sd, th
+
+
+def test_mlp_forward_backward_against_oracle(rs, mlp_case):
+    X, t, mu, sd, th = mlp_case
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    y, C = rs.rs_mlp_forward(d(th), d(X), d(mu), d(sd), cache=True)
+    G, loss = rs.rs_mlp_backward(d(th), C, d(t))
+    y_o, _ = learned.forward(th.astype(np.float64), X, mu.astype(np.float64), sd.astype(np.float64))
+    l_o, g_o = learned.loss_and_grad(th.astype(np.float64), X, t, mu.astype(np.float64),
+                                     sd.astype(np.float64))
+    np.testing.assert_allclose(host(y), y_o, rtol=2e-5, atol=2e-5 * np.abs(y_o).max())
+    assert abs(host(loss)[0] - l_o) <= 2e-5 * l_o
+    np.testing.assert_allclose(host(G), g_o, rtol=0, atol=1e-5 * np.abs(g_o).max())
+
+
+def test_mlp_gradient_central_differences_on_gpu(rs, mlp_case):
+    X, t, mu, sd, th = mlp_case
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    _, C = rs.rs_mlp_forward(d(th), d(X), d(mu), d(sd), cache=True)
+    G = host(rs.rs_mlp_backward(d(th), C, d(t))[0])
+    th64 = th.astype(np.float64)
+    for idx in np.random.default_rng(2).choice(th.size, 12, replace=False):
+        e = np.zeros_like(th64)
+        e[idx] = 1e-4
+        lp, _ = learned.loss_and_grad(th64 + e, X, t, mu.astype(np.float64), sd.astype(np.float64))
+        lm, _ = learned.loss_and_grad(th64 - e, X, t, mu.astype(np.float64), sd.astype(np.float64))
+        assert abs((lp - lm) / 2e-4 - G[idx]) <= 1e-3 * max(1.0, abs(G[idx]))
+
+
+def test_adam_against_oracle(rs, mlp_case):
+    _, _, _, _, th = mlp_case
+    rng = np.random.default_rng(3)
+    P = torch.from_numpy(th.copy()).cuda()
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    cur, m, v = th.astype(np.float64), np.zeros(th.size), np.zeros(th.size)
+    for step in range(1, 4):
+        g = rng.standard_normal(th.size).astype(np.float32)
+        rs.rs_mlp_adam_step(P, torch.from_numpy(g).cuda(), M, V, step)
+        cur, m, v = learned.adam_step(cur, g.astype(np.float64), m, v, step)
+    np.testing.assert_allclose(host(P), cur, rtol=0, atol=1e-6)
+
+
+def test_training_on_gpu_lowers_the_loss(rs, mlp_case):
+    X, t, mu, sd, th = mlp_case
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    P, Xd, td, mud, sdd = d(th.copy()), d(X), d(t), d(mu), d(sd)
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    losses = []
+    for step in range(1, 301):
+        _, C = rs.rs_mlp_forward(P, Xd, mud, sdd, cache=True)
+        G, loss = rs.rs_mlp_backward(P, C, td)
+        rs.rs_mlp_adam_step(P, G, M, V, step, lr=3e-3)
+        losses.append(float(host(loss)[0]))
+    assert losses[-1] < 0.05 * losses[0]
+
+
+@pytest.mark.parametrize("bias", [-5.0, 3.0, 30.0])
+def test_learned_solve_falls_back_to_the_adaptive_rule(rs, bias):
+    # any starting m converges (Theorems 5 and 6 hold for every m_initial): a
+    # predictor forced to 2^-5, 2^3 or 2^30 (clamped) must still reach x*
+    p = config_c1()
+    th = np.zeros(18817, dtype=np.float32)
+    th[-1] = bias
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x, info = rs.rs_learned_solve(dev_padded(p.A, rs), d(p.b), p.nu2, d(th),
+                                  d(np.zeros(16, np.float32)), d(np.ones(16, np.float32)))
+    expect = 1 if bias < 0 else min(2 ** int(math.floor(bias)), 1024)
+    assert info["m_init"] == expect and info["status"] == "ok"
+    xs = ridge.solve_direct(p.A, p.b, p.nu2)
+    assert ridge.relative_error(ridge.hessian(p.A, p.nu2), host(x), xs) <= 1e-6
