@@ -220,6 +220,33 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
                             const void* b, double nu2, const rs_solve_opts* opts,
                             double* x, rs_solve_info* info, hipStream_t stream);
 
+/* One problem of a batch: A (n x d, row-major, leading dimension lda, F32 or F64,
+ * 16-byte aligned), b (n, same type), nu2 > 0, x (d FP64: in = x_1, out =
+ * solution).  All device pointers, owned by the caller. */
+typedef struct rs_problem {
+  const void* A;
+  rs_dtype a_t;
+  int32_t reserved;
+  int64_t n, d, lda;
+  const void* b;
+  double nu2;
+  double* x;
+} rs_problem;
+
+/* Many independent ridge problems of any sizes, each solved by Algorithm 1 with
+ * the same opts (result i identical to rs_adaptive_solve on problem i, whose
+ * arithmetic does not depend on how jobs are scheduled).  The library multiplexes
+ * the jobs over `workers` streams of its own (default priority; 0 = 8), each with
+ * private scratch; the host advances a job whenever its last queued work has
+ * finished, so small solves run concurrently and fill the device.  The worker
+ * streams wait for work already queued on `stream`, and `stream` waits for all of
+ * them on return.  infos: count host records.  Synchronizes.  Returns RS_OK when
+ * every job ended RS_OK or RS_ERR_NO_CONVERGENCE (see infos[i].status), else the
+ * first other error; an argument error in any problem is reported before any
+ * work is queued. */
+rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
+                         rs_solve_info* infos, int32_t workers, hipStream_t stream);
+
 /* ------------------------------------------------------------------ learned start */
 
 /* Algorithm 1 holds for any initial sketch size (Theorems 5 and 6).  The learned

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rs_internal.hpp"
@@ -118,6 +119,12 @@ struct DevBuf {
   T* as() const {
     return reinterpret_cast<T*>(p);
   }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
 };
 
 struct DeviceScratch {
@@ -133,6 +140,12 @@ struct DeviceScratch {
   // learned form: probe sketch and its factor, probe sums, features
   DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
   void* host_pinned = nullptr;
+  hipEvent_t done_ev = nullptr;
+  DeviceScratch() = default;
+  ~DeviceScratch() {
+    if (host_pinned) (void)hipHostFree(host_pinned);
+    if (done_ev) (void)hipEventDestroy(done_ev);
+  }
 };
 
 static DeviceScratch* scratch_for_current() {
@@ -432,10 +445,7 @@ rs_status rs_factor_apply(const rs_factor* F, const double* g, double* gtilde, d
 }
 
 void rs_factor_destroy(rs_factor* F) {
-  if (!F) return;
-  for (DevBuf* b : {&F->M, &F->Linv, &F->Hinv, &F->Cw, &F->info, &F->rpart, &F->gram})
-    if (b->p) (void)hipFree(b->p);
-  delete F;
+  delete F;  // the buffers free themselves
 }
 
 rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, const void* b,
@@ -539,74 +549,90 @@ void rs_solve_opts_default(rs_solve_opts* o) {
   o->check_every = 4;
 }
 
-rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
-                            const void* b, double nu2, const rs_solve_opts* opts, double* x,
-                            rs_solve_info* info, hipStream_t stream) {
-  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
-  if (!b || !opts || !x || !info) return set_error(RS_ERR_ARG, "rs_adaptive_solve: null argument");
-  if (n < d) return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: needs n >= d");
-  if (!(nu2 > 0.0) || !std::isfinite(nu2))
-    return set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: nu^2 must be positive");
-  if (!(opts->tol >= 0.0)) return set_error(RS_ERR_ARG, "rs_adaptive_solve: tol must be >= 0");
-  if (opts->max_iter < 1) return set_error(RS_ERR_ARG, "rs_adaptive_solve: max_iter must be >= 1");
-  RS_TRY(check_sa_type(a_t, opts->sketch_dtype));
-  rs_ihs_params prm;
-  RS_TRY(rs_params(opts->kind, opts->rho, opts->eta, &prm));
-  const bool srht = opts->kind == RS_SKETCH_SRHT;
-  const int64_t npad = next_pow2(n);
-  if (srht && npad > (int64_t)1 << 20)
-    return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: SRHT padded n above 2^20");
-  int64_t m_cap = srht ? npad : n;
-  if (opts->m_max > 0) m_cap = std::min<int64_t>(m_cap, opts->m_max);
-  int64_t m = std::min<int64_t>(std::max<int64_t>(opts->m_init, 1), m_cap);
-  const int K = opts->variant == RS_VARIANT_POLYAK ? 2 : 1;
-  const int check_every = std::max(1, (int)opts->check_every);
-  const rs_dtype sa_t = opts->sketch_dtype;
-  const size_t sa_es = dtype_size(sa_t);
+}  // extern "C"
+
+namespace rs {
+
+// One run of Algorithm 1 as a resumable job: start() enqueues the first sketch,
+// factor and g_1; every later advance() is called once the previous batch of
+// device work has finished (its event completed), reads the control record and
+// enqueues the next batch (queued steps, or a resampling).  A single solve
+// drives one job synchronously; rs_solve_batch multiplexes many jobs over
+// several streams.
+struct SolveJob {
+  const void* A = nullptr;
+  rs_dtype a_t = RS_F32;
+  int64_t n = 0, d = 0, lda = 0;
+  const void* b = nullptr;
+  double nu2 = 0.0;
+  double* x = nullptr;
+  rs_solve_opts o{};
+  rs_solve_info* info = nullptr;
+  hipStream_t stream = nullptr;
+  DeviceScratch* S = nullptr;
+
+  rs_ihs_params prm{};
+  bool srht = true;
+  int64_t m_cap = 0, m = 0, ldsa = 0, dp = 0;
+  int K = 2, check_every = 4, nrp = 0, ev_cap = 0;
+  rs_dtype sa_t = RS_F32;
+  size_t sa_es = 4;
   uint32_t sid = 0;
+  CtlParams cp{};
+  double *x_prev = nullptr, *g = nullptr, *gt = nullptr, *gref = nullptr;
+  double *X = nullptr, *G = nullptr, *GT = nullptr;
+  DevCtl* dctl = nullptr;
+  int* finfo = nullptr;
+  const int* status = nullptr;
+  const double* Hinv = nullptr;
+  std::vector<int32_t> dbl_t;  // step index of each doubling
+  std::vector<int64_t> dbl_m;  // m after it
+  DevCtl h{};
+  int64_t applies = 1;
+  rs_status result = RS_OK;
+  int queue = 1;
+  bool done = false;
 
-  std::memset(info, 0, sizeof(*info));
-  DeviceScratch* S = scratch_for_current();
-  std::lock_guard<std::mutex> lock(S->mu);
+  rs_status validate() {
+    RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
+    if (!b || !x || !info) return set_error(RS_ERR_ARG, "rs_adaptive_solve: null argument");
+    if (n < d) return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: needs n >= d");
+    if (!(nu2 > 0.0) || !std::isfinite(nu2))
+      return set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: nu^2 must be positive");
+    if (!(o.tol >= 0.0)) return set_error(RS_ERR_ARG, "rs_adaptive_solve: tol must be >= 0");
+    if (o.max_iter < 1) return set_error(RS_ERR_ARG, "rs_adaptive_solve: max_iter must be >= 1");
+    RS_TRY(check_sa_type(a_t, o.sketch_dtype));
+    RS_TRY(rs_params(o.kind, o.rho, o.eta, &prm));
+    srht = o.kind == RS_SKETCH_SRHT;
+    const int64_t npad = next_pow2(n);
+    if (srht && npad > (int64_t)1 << 20)
+      return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: SRHT padded n above 2^20");
+    m_cap = srht ? npad : n;
+    if (o.m_max > 0) m_cap = std::min<int64_t>(m_cap, o.m_max);
+    m = std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap);
+    K = o.variant == RS_VARIANT_POLYAK ? 2 : 1;
+    check_every = std::max(1, (int)o.check_every);
+    sa_t = o.sketch_dtype;
+    sa_es = dtype_size(sa_t);
+    // SA rows padded to a multiple of 64 columns: the low-precision Gram reads
+    // whole 64-column segments
+    ldsa = (d + 63) / 64 * 64;
+    dp = (d + 63) / 64 * 64;
+    nrp = apply_blocks(d);
+    ev_cap = (int)std::min<int64_t>(o.max_iter + 1, 1 << 20);
+    cp = CtlParams{prm.mu_p, prm.beta_p, prm.mu_gd, prm.cbar_p, prm.cbar_gd, o.tol, o.max_iter};
+    return RS_OK;
+  }
 
-  // scratch sized for this problem
-  const int nrp = apply_blocks(d);
-  RS_TRY(S->vecs.ensure((size_t)(4 + 3 * 2) * d * sizeof(double)));
-  RS_TRY(S->rpart.ensure((size_t)nrp * 4 * sizeof(double)));
-  RS_TRY(S->ctl.ensure(sizeof(DevCtl)));
-  const int ev_cap = (int)std::min<int64_t>(opts->max_iter + 1, 1 << 20);
-  RS_TRY(S->ev.ensure((size_t)ev_cap * sizeof(int32_t)));
-  RS_TRY(S->info.ensure(sizeof(int), true));
-  if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
-  double* x_prev = S->vecs.as<double>();
-  double* g = x_prev + d;
-  double* gt = g + d;
-  double* gref = gt + d;
-  double* X = gref + d;
-  double* G = X + 2 * d;
-  double* GT = G + 2 * d;
-  DevCtl* dctl = S->ctl.as<DevCtl>();
-  int* finfo = S->info.as<int>();
-  const int* status = &dctl->status;
-  RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
-
-  const CtlParams cp{prm.mu_p, prm.beta_p, prm.mu_gd, prm.cbar_p, prm.cbar_gd, opts->tol,
-                     opts->max_iter};
-  // SA rows padded to a multiple of 64 columns: the low-precision Gram reads
-  // whole 64-column segments
-  const int64_t ldsa = (d + 63) / 64 * 64;
-
-  auto sketch_and_factor = [&](int64_t mm, uint32_t id) -> rs_status {
+  rs_status sketch_and_factor(int64_t mm, uint32_t id) {
     RS_TRY(S->sa.ensure((size_t)mm * ldsa * sa_es));
     RS_TRY(S->sa_scale.ensure((size_t)d * sizeof(float)));
     float* scl = sa_t == RS_FP8E4M3 ? S->sa_scale.as<float>() : nullptr;
-    if (srht) {
-      RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, scl,
-                      nullptr, nullptr, stream));
-    } else {
-      RS_TRY(gauss_run(*S, A, a_t, n, d, lda, mm, opts->seed, id, S->sa.p, sa_t, ldsa, scl,
-                       stream));
-    }
+    if (srht)
+      RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, nullptr,
+                      nullptr, stream));
+    else
+      RS_TRY(gauss_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, stream));
     RS_TRY(S->fM.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fLinv.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fHinv.ensure(factor_bytes_Hinv(d)));
@@ -614,66 +640,87 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
     RS_TRY(S->fGram.ensure(factor_bytes_gram(mm, d, sa_t)));
     FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
                      S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes};
-    return factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream);
-  };
-  const int64_t dp = (d + 63) / 64 * 64;
-  const double* Hinv_ptr = nullptr;
+    RS_TRY(factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream));
+    Hinv = S->fHinv.as<double>();
+    return RS_OK;
+  }
 
-  std::vector<int32_t> dbl_t;   // step index of each doubling
-  std::vector<int64_t> dbl_m;   // m after it
-
-  RS_TRY(sketch_and_factor(m, sid));
-  Hinv_ptr = S->fHinv.as<double>();
-  // g_1, gtilde_1, r_1
-  RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
-  RS_TRY(apply_launch(Hinv_ptr, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
-  RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, opts->tol, opts->max_iter, d, G, GT, x,
-                           x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream));
-
-  DevCtl h{};
-  int64_t applies = 1;
-  rs_status result = RS_OK;
-  // steps queued per host read: one right after a resample (the next step is
-  // often rejected again while m is small), check_every after accepted steps
-  int queue = 1;
-  for (;;) {
-    // read the control record and the factor flag
+  // copy the control record and the factor flag to pinned memory, mark the point
+  rs_status enqueue_read() {
     RS_HIP(hipMemcpyAsync(S->host_pinned, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
-    RS_HIP(hipMemcpyAsync((char*)S->host_pinned + 512, finfo, sizeof(int), hipMemcpyDeviceToHost,
-                          stream));
-    RS_HIP(hipStreamSynchronize(stream));
+    RS_HIP(hipMemcpyAsync((char*)S->host_pinned + 512, finfo, sizeof(int),
+                          hipMemcpyDeviceToHost, stream));
+    RS_HIP(hipEventRecord(S->done_ev, stream));
+    return RS_OK;
+  }
+
+  rs_status start() {
+    std::memset(info, 0, sizeof(*info));
+    RS_TRY(S->vecs.ensure((size_t)(4 + 3 * 2) * d * sizeof(double)));
+    RS_TRY(S->rpart.ensure((size_t)nrp * 4 * sizeof(double)));
+    RS_TRY(S->ctl.ensure(sizeof(DevCtl)));
+    RS_TRY(S->ev.ensure((size_t)ev_cap * sizeof(int32_t)));
+    RS_TRY(S->info.ensure(sizeof(int), true));
+    if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
+    if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
+    x_prev = S->vecs.as<double>();
+    g = x_prev + d;
+    gt = g + d;
+    gref = gt + d;
+    X = gref + d;
+    G = X + 2 * d;
+    GT = G + 2 * d;
+    dctl = S->ctl.as<DevCtl>();
+    finfo = S->info.as<int>();
+    status = &dctl->status;
+    RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
+    RS_TRY(sketch_and_factor(m, sid));
+    // g_1, gtilde_1, r_1
+    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
+    RS_TRY(apply_launch(Hinv, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
+    RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, o.tol, o.max_iter, d, G, GT, x,
+                             x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream));
+    return enqueue_read();
+  }
+
+  bool ready() const { return hipEventQuery(S->done_ev) == hipSuccess; }
+
+  // the previous batch has finished: decide what to enqueue next
+  rs_status advance() {
     std::memcpy(&h, S->host_pinned, sizeof(DevCtl));
     int fbad = 0;
     std::memcpy(&fbad, (char*)S->host_pinned + 512, sizeof(int));
     if (fbad) {
       result = set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: sketched Hessian factor failed");
-      break;
+      return conclude();
     }
     if (h.status == RS_CTL_RUNNING) {
+      // one step right after a resample (the next step is often rejected again
+      // while m is small), check_every steps after accepted ones
       for (int it = 0; it < queue; ++it) {
         RS_TRY(candidates_launch(K, d, x, x_prev, gt, X, prm.mu_p, prm.beta_p, prm.mu_gd, status,
                                  stream));
         RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
-        RS_TRY(apply_launch(Hinv_ptr, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
+        RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
         RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
                              gt, S->ev.as<int32_t>(), ev_cap, stream));
       }
       queue = check_every;
-      continue;
+      return enqueue_read();
     }
     if (h.status == RS_CTL_DOUBLE) {
       m = std::min<int64_t>(2 * m, m_cap);
-      if (opts->resample == RS_RESAMPLE_FRESH) ++sid;
+      if (o.resample == RS_RESAMPLE_FRESH) ++sid;
       dbl_t.push_back((int32_t)h.t);
       dbl_m.push_back(m);
       RS_TRY(sketch_and_factor(m, sid));
       RS_TRY(pack2_launch(d, g, gref, X, stream));
-      RS_TRY(apply_launch(Hinv_ptr, dp, d, X, 2, GT, S->rpart.as<double>(), nullptr, stream));
-      RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, opts->tol, d, GT, gt,
+      RS_TRY(apply_launch(Hinv, dp, d, X, 2, GT, S->rpart.as<double>(), nullptr, stream));
+      RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, o.tol, d, GT, gt,
                                   m == m_cap ? 1 : 0, stream));
       applies += 1;
       queue = 1;
-      continue;
+      return enqueue_read();
     }
     if (h.status == RS_CTL_CONVERGED) result = RS_OK;
     else if (h.status == RS_CTL_NONFINITE)
@@ -682,48 +729,156 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
       result = set_error(RS_ERR_NO_CONVERGENCE,
                          h.status == RS_CTL_STUCK ? "rs_adaptive_solve: no progress at m_max"
                                                   : "rs_adaptive_solve: max_iter reached");
-    break;
+    return conclude();
   }
 
   // event log: doublings at step t come before the step accepted at t
-  const int64_t tfin = h.t;
-  std::vector<int32_t> kinds((size_t)std::max<int64_t>(tfin, 1), -1);
-  if (tfin > 1) {
-    const int64_t cnt = std::min<int64_t>(tfin, ev_cap);
-    RS_HIP(hipMemcpy(kinds.data(), S->ev.p, (size_t)cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
-  }
-  int64_t ne = 0;
-  size_t di = 0;
-  int64_t m_now = std::min<int64_t>(std::max<int64_t>(opts->m_init, 1), m_cap);
-  auto push = [&](int kind, int64_t t, int64_t mm) {
-    if (ne < RS_MAX_EVENTS) {
-      info->event_kind[ne] = kind;
-      info->event_t[ne] = (int32_t)t;
-      info->event_m[ne] = mm;
+  rs_status conclude() {
+    done = true;
+    const int64_t tfin = h.t;
+    std::vector<int32_t> kinds((size_t)std::max<int64_t>(tfin, 1), -1);
+    if (tfin > 1) {
+      const int64_t cnt = std::min<int64_t>(tfin, ev_cap);
+      RS_HIP(hipMemcpyAsync(kinds.data(), S->ev.p, (size_t)cnt * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, stream));
+      RS_HIP(hipStreamSynchronize(stream));
     }
-    ++ne;
+    int64_t ne = 0;
+    size_t di = 0;
+    int64_t m_now = std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap);
+    auto push = [&](int kind, int64_t t, int64_t mm) {
+      if (ne < RS_MAX_EVENTS) {
+        info->event_kind[ne] = kind;
+        info->event_t[ne] = (int32_t)t;
+        info->event_m[ne] = mm;
+      }
+      ++ne;
+    };
+    for (int64_t t = 1; t <= tfin; ++t) {
+      while (di < dbl_t.size() && dbl_t[di] == t) {
+        m_now = dbl_m[di];
+        push(RS_EVENT_DOUBLE, t, m_now);
+        ++di;
+      }
+      if (t < tfin && t < (int64_t)kinds.size() && kinds[t] >= 0)
+        push(kinds[t] == 0 ? RS_EVENT_POLYAK : RS_EVENT_GD, t, m_now);
+    }
+    info->status = result;
+    info->m_final = m;
+    info->doublings = (int64_t)dbl_t.size();
+    info->steps = h.steps;
+    info->grad_passes = h.passes;
+    info->applies = applies + h.passes;
+    info->accepted_polyak = h.polyak;
+    info->accepted_gd = h.gd;
+    info->r_final = h.r_t;
+    info->r_ref = h.r_ref;
+    info->n_events = std::min<int64_t>(ne, RS_MAX_EVENTS);
+    return result;
+  }
+};
+
+}  // namespace rs
+
+extern "C" {
+
+rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                            const void* b, double nu2, const rs_solve_opts* opts, double* x,
+                            rs_solve_info* info, hipStream_t stream) {
+  if (!opts) return set_error(RS_ERR_ARG, "rs_adaptive_solve: null argument");
+  SolveJob J;
+  J.A = A; J.a_t = a_t; J.n = n; J.d = d; J.lda = lda; J.b = b; J.nu2 = nu2; J.x = x;
+  J.o = *opts; J.info = info; J.stream = stream;
+  RS_TRY(J.validate());
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  J.S = S;
+  RS_TRY(J.start());
+  while (!J.done) {
+    RS_HIP(hipEventSynchronize(S->done_ev));
+    const rs_status st = J.advance();
+    if (st != RS_OK && !J.done) return st;
+  }
+  return J.result;
+}
+
+rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
+                         rs_solve_info* infos, int32_t workers, hipStream_t stream) {
+  if (!probs || !opts || !infos) return set_error(RS_ERR_ARG, "rs_solve_batch: null argument");
+  if (count < 0) return set_error(RS_ERR_ARG, "rs_solve_batch: count < 0");
+  if (count == 0) return RS_OK;
+  std::vector<SolveJob> jobs((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    SolveJob& J = jobs[i];
+    const rs_problem& P = probs[i];
+    J.A = P.A; J.a_t = P.a_t; J.n = P.n; J.d = P.d; J.lda = P.lda; J.b = P.b; J.nu2 = P.nu2;
+    J.x = P.x; J.o = *opts; J.info = &infos[i];
+    RS_TRY(J.validate());
+  }
+  const int W = (int)std::max<int64_t>(1, std::min<int64_t>(workers > 0 ? workers : 8, count));
+  // worker streams and scratch: private to this call
+  struct Worker {
+    DeviceScratch S;
+    hipStream_t s = nullptr;
+    int64_t job = -1;
   };
-  for (int64_t t = 1; t <= tfin; ++t) {
-    while (di < dbl_t.size() && dbl_t[di] == t) {
-      m_now = dbl_m[di];
-      push(RS_EVENT_DOUBLE, t, m_now);
-      ++di;
-    }
-    if (t < tfin && t < (int64_t)kinds.size() && kinds[t] >= 0)
-      push(kinds[t] == 0 ? RS_EVENT_POLYAK : RS_EVENT_GD, t, m_now);
+  std::vector<Worker> wk((size_t)W);
+  hipEvent_t entry;
+  RS_HIP(hipEventCreateWithFlags(&entry, hipEventDisableTiming));
+  RS_HIP(hipEventRecord(entry, stream));
+  rs_status first_err = RS_OK;
+  for (auto& w : wk) {
+    RS_HIP(hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking));
+    RS_HIP(hipStreamWaitEvent(w.s, entry, 0));
   }
-  info->status = result;
-  info->m_final = m;
-  info->doublings = (int64_t)dbl_t.size();
-  info->steps = h.steps;
-  info->grad_passes = h.passes;
-  info->applies = applies + h.passes;
-  info->accepted_polyak = h.polyak;
-  info->accepted_gd = h.gd;
-  info->r_final = h.r_t;
-  info->r_ref = h.r_ref;
-  info->n_events = std::min<int64_t>(ne, RS_MAX_EVENTS);
-  return result;
+  int64_t next = 0, finished = 0;
+  auto launch = [&](Worker& w) {
+    while (next < count) {
+      SolveJob& J = jobs[next];
+      J.S = &w.S;
+      J.stream = w.s;
+      const int64_t id = next++;
+      const rs_status st = J.start();
+      if (st == RS_OK) { w.job = id; return; }
+      J.result = st;
+      J.info->status = st;
+      J.done = true;
+      ++finished;
+      if (first_err == RS_OK) first_err = st;
+    }
+    w.job = -1;
+  };
+  for (auto& w : wk) launch(w);
+  while (finished < count) {
+    bool progressed = false;
+    for (auto& w : wk) {
+      if (w.job < 0) continue;
+      SolveJob& J = jobs[w.job];
+      if (!J.ready()) continue;
+      progressed = true;
+      const rs_status st = J.advance();
+      if (J.done || st != RS_OK) {
+        if (!J.done) { J.done = true; J.result = st; J.info->status = st; }
+        ++finished;
+        if (J.result != RS_OK && J.result != RS_ERR_NO_CONVERGENCE && first_err == RS_OK)
+          first_err = J.result;
+        launch(w);
+      }
+    }
+    if (!progressed) std::this_thread::yield();
+  }
+  // the caller's stream waits for every worker; then the workers go away
+  for (auto& w : wk) {
+    hipEvent_t e;
+    RS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    RS_HIP(hipEventRecord(e, w.s));
+    RS_HIP(hipStreamWaitEvent(stream, e, 0));
+    RS_HIP(hipStreamSynchronize(w.s));
+    (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(w.s);
+  }
+  (void)hipEventDestroy(entry);
+  return first_err;
 }
 
 }  // extern "C"

@@ -77,12 +77,18 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_factor_apply", "rs_factor_destroy", "rs_gradient", "rs_ihs_step",
            "rs_solve_opts_default", "rs_adaptive_solve", "rs_last_error", "rs_version",
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
-           "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve"]
+           "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
 
 _lib = None
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("a_t", ctypes.c_int), ("reserved", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("nu2", ctypes.c_double), ("x", ctypes.c_void_p)]
 
 
 def load(path=LIB_PATH):
@@ -122,12 +128,14 @@ def load(path=LIB_PATH):
     L.rs_learned_solve.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, ctypes.POINTER(SolveOpts),
                                    vp, vp, vp, vp, ctypes.POINTER(SolveInfo),
                                    ctypes.POINTER(i64), vp]
+    L.rs_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(SolveInfo), ctypes.c_int32, vp]
     L.rs_last_error.restype = ctypes.c_char_p
     L.rs_version.restype = ctypes.c_char_p
     for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
                  "rs_factor_apply", "rs_gradient", "rs_ihs_step", "rs_adaptive_solve",
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
-                 "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve"]:
+                 "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -319,6 +327,33 @@ def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh"
     st = load().rs_adaptive_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
                                   ctypes.byref(o), _ptr(x), ctypes.byref(info), _stream())
     return x, _info(info, st, raise_on_error, "rs_adaptive_solve")
+
+
+def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
+                   sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
+                   max_iter=200, seed=0, check_every=4, workers=8, raise_on_error=True):
+    """Solve a list of (A, b, nu2) problems with one option set.  Returns a list of
+    (x, info) pairs in the input order."""
+    if not problems:
+        return []
+    a_ts = [_mat(A, "rs_solve_batch") for A, _, _ in problems]
+    o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol,
+              max_iter, seed, check_every)
+    P = (Problem * len(problems))()
+    xs, bs = [], []
+    for i, (A, b, nu2) in enumerate(problems):
+        n, d = A.shape
+        x = torch.zeros(d, dtype=torch.float64, device=A.device)
+        bc = b.contiguous()
+        xs.append(x)
+        bs.append(bc)
+        P[i] = Problem(_ptr(A), a_ts[i], 0, n, d, A.stride(0), _ptr(bc), float(nu2), _ptr(x))
+    infos = (SolveInfo * len(problems))()
+    st = load().rs_solve_batch(P, len(problems), ctypes.byref(o), infos, workers, _stream())
+    if st != RS_OK and raise_on_error:
+        _check(st, "rs_solve_batch")
+    return [(xs[i], _info(infos[i], infos[i].status, False, "rs_solve_batch"))
+            for i in range(len(problems))]
 
 
 def _info(info, st, raise_on_error, where):

@@ -95,3 +95,22 @@ def make_problem_torch(n, d, sigma, noise, seed, device, dtype=None, row_block=1
         xi = torch.randn(r1 - r0, generator=gen, device=device, dtype=torch.float64)
         b[r0:r1] = (blk.to(torch.float64) @ x_pl + noise * xi).to(dtype)
     return A, b, x_pl
+
+
+def config_c4b_specs(count=256, seed=4):
+    """Uneven problem set: n = 2^U{12..16} (4096 to 65536), d = U{128..1024},
+    sigma_i = 0.95^i, nu^2 = 1e-3 (sigma_1 = 1), noise 0.1; problem i is drawn
+    with seed 4000 * seed + i.  Returns a list of dicts (n, d, seed, nu2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = 2 ** int(rng.integers(12, 17))
+        d = int(rng.integers(128, 1025))
+        out.append({"n": n, "d": d, "seed": 4000 * seed + i, "nu2": 1e-3})
+    return out
+
+
+def make_c4b_problem(spec, device, dtype=None):
+    """Device tensors (A, b) for one config_c4b_specs entry."""
+    return make_problem_torch(spec["n"], spec["d"], spectrum("geom", spec["d"], 0.95), 0.1,
+                              spec["seed"], device, dtype=dtype)[:2]

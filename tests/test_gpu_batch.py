@@ -1,0 +1,107 @@
+"""GPU parity of the batched form (rs_solve_batch): every job of a batch gives
+exactly what rs_adaptive_solve gives for the same problem alone, and reaches the
+oracle's solution; uneven shapes, more jobs than worker streams, low-precision
+sketches, empty batches and argument errors."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ihs, ridge  # noqa: E402
+from synth import config_c4b_specs, make_c4b_problem, make_problem, spectrum  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_05874_amd import rs as _rs
+    _rs.load()
+    return _rs
+
+
+def dev_padded(A, rs):
+    dt = torch.float64 if A.dtype == np.float64 else torch.float32
+    T = rs.padded(A.shape[0], A.shape[1], dtype=dt)
+    T.copy_(torch.from_numpy(A))
+    return T
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def small_uneven(count, dtype, seed=0):
+    """Ragged n (not powers of two) and d; sigma_i = 0.95^i as the uneven set."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(300, 5000))
+        d = int(rng.integers(5, 160))
+        out.append(make_problem(n, d, spectrum("geom", d, 0.95), 1e-3, 0.1, 100 + i, dtype=dtype))
+    return out
+
+
+@pytest.mark.parametrize("workers", [1, 3, 8])
+def test_batch_equals_single_solves_fp64(rs, workers):
+    probs = small_uneven(10, np.float64)
+    dev_probs = [(dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2) for p in probs]
+    res = rs.rs_solve_batch(dev_probs, seed=5, workers=workers)
+    for (A, b, nu2), p, (x, info) in zip(dev_probs, probs, res):
+        xs1, i1 = rs.rs_adaptive_solve(A, b, nu2, seed=5)
+        assert info["events"] == i1["events"] and info["m_final"] == i1["m_final"]
+        assert info["status"] == i1["status"] == "ok"
+        assert torch.equal(x, xs1)
+        # and the oracle's trajectory and solution
+        _, io = ihs.adaptive_solve(p.A, p.b, p.nu2, ihs.Options(seed=5))
+        assert info["events"] == [e for e in io.events if e[1] != "stop"]
+        xs = ridge.solve_direct(p.A, p.b, p.nu2)
+        assert ridge.relative_error(ridge.hessian(p.A, p.nu2), host(x), xs) <= 1e-6
+
+
+@pytest.mark.parametrize("sketch_dtype", ["f32", "bf16", "fp8"])
+def test_batch_low_precision_sketches_reach_tolerance(rs, sketch_dtype):
+    probs = small_uneven(12, np.float32, seed=1)
+    dev_probs = [(dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2) for p in probs]
+    res = rs.rs_solve_batch(dev_probs, sketch_dtype=sketch_dtype, workers=4)
+    for p, (x, info), (A, b, nu2) in zip(probs, res, dev_probs):
+        assert info["status"] == "ok"
+        A64 = p.A.astype(np.float64)
+        xs = ridge.solve_direct(A64, p.b.astype(np.float64), p.nu2)
+        assert ridge.relative_error(ridge.hessian(A64, p.nu2), host(x), xs) <= 1e-6
+        x1, i1 = rs.rs_adaptive_solve(A, b, nu2, sketch_dtype=sketch_dtype)
+        assert torch.equal(x, x1) and info["events"] == i1["events"]
+
+
+def test_batch_uneven_full_size_sampled(rs):
+    # the 256-problem uneven set (n 4096..65536, d 128..1024, BF16 sketches) in the
+    # launch shape the benchmark uses; four sampled problems checked against the
+    # oracle's direct solve in FP64
+    specs = config_c4b_specs()
+    dev_probs = []
+    for s in specs:
+        A0, b = make_c4b_problem(s, "cuda")
+        A = rs.padded(s["n"], s["d"], dtype=torch.float32)
+        A.copy_(A0)
+        dev_probs.append((A, b, s["nu2"]))
+    res = rs.rs_solve_batch(dev_probs, sketch_dtype="bf16", workers=8)
+    assert all(info["status"] == "ok" for _, info in res)
+    for i in np.random.default_rng(0).choice(len(specs), 4, replace=False):
+        A, b, nu2 = dev_probs[i]
+        A64 = host(A).astype(np.float64)
+        b64 = host(b).astype(np.float64)
+        xs = ridge.solve_direct(A64, b64, nu2)
+        assert ridge.relative_error(ridge.hessian(A64, nu2), host(res[i][0]), xs) <= 1e-6
+
+
+def test_batch_empty_and_errors(rs):
+    assert rs.rs_solve_batch([]) == []
+    p = small_uneven(2, np.float64)
+    good = (dev_padded(p[0].A, rs), torch.from_numpy(p[0].b).cuda(), p[0].nu2)
+    bad = (dev_padded(p[1].A, rs), torch.from_numpy(p[1].b).cuda(), -1.0)
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_solve_batch([good, bad])
+    assert e.value.name == "not_spd"
