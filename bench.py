@@ -2,9 +2,14 @@
 
 Workload (one "step"): the 65536 x 1024 FP32 problem A = G diag(sigma) V^T with
 sigma_i = 1/i, G i.i.d. N(0, 1/n), V Haar, b = A x_pl + 0.1 xi (seed 0), solved
-by Algorithm 1 (SRHT, rho = 0.1, m from 1, FP32 sketch, FP64 factor and
-control) to the decrement tolerance, once at nu^2 = 1e-2 and once at
-nu^2 = 1e-4.  Inputs are resident in HBM before timing; every solve of the
+by Algorithm 1 (SRHT, rho = 0.1, FP64 factor and control) to the decrement
+tolerance, once at nu^2 = 1e-2 and once at nu^2 = 1e-4.
+
+The reported value is the learned form with BF16 sketches (features, MLP
+prediction of the starting m, then Algorithm 1 with the doubling rule as the
+fallback); the plain method (FP32 sketch, m from 1) is timed the same way on
+the same problem and reported beside it.  ``--mode plain`` reports the plain
+method alone.  Inputs are resident in HBM before timing; every solve of each
 timed region is checked afterwards against the oracle's direct solution
 (relative prediction error delta(x)/delta(0) <= 1e-6).
 
@@ -37,6 +42,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default="polyak", choices=["polyak", "gd"])
     ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--mode", default="learned-bf16", choices=["learned-bf16", "plain"])
+    ap.add_argument("--model", default=None, help="learned-start model (.npz)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4b"],
+                    help="c2: the 65536x1024 headline problem; c3: the 2^20x4096 precision "
+                         "form; c4b: 256 uneven problems, batched")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a counter "
                          "reference for HBM traffic measurements)")
@@ -100,6 +110,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "c3":
+        return run_c3(args)
+    if args.workload == "c4b":
+        return run_c4b(args)
     import torch
 
     from paper_2006_05874_amd import rs
@@ -114,13 +128,50 @@ def main():
     b = torch.from_numpy(p0.b).cuda()
     torch.cuda.synchronize()
 
-    def step():
+    model = None
+    if args.mode == "learned-bf16":
+        from paper_2006_05874_amd import learned
+        path = args.model or learned.MODEL_PATH
+        if not os.path.exists(path):
+            print(json.dumps({"error": f"no learned-start model at {path}; train one with "
+                              "python -m paper_2006_05874_amd.learned, or pass --mode plain"}))
+            sys.exit(2)
+        model = learned.load_model(path)[:3]
+
+    def solve(nu2, mode):
+        if mode == "plain":
+            return rs.rs_adaptive_solve(A, b, nu2, kind="srht", variant=args.variant,
+                                        sketch_dtype="f32", check_every=args.check_every)
+        params, mu, sd = model
+        return rs.rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant=args.variant,
+                                   sketch_dtype="bf16", check_every=args.check_every)
+
+    def timed(mode, profile):
+        for _ in range(args.warmup):
+            for nu2 in NU2S:
+                solve(nu2, mode)
+        torch.cuda.synchronize()
+        if profile:
+            rs.rs_profile_enable(True)
+            rs.rs_profile_read()                       # clear
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        t0 = time.perf_counter()
         out = []
-        for nu2 in NU2S:
-            x, info = rs.rs_adaptive_solve(A, b, nu2, kind="srht", variant=args.variant,
-                                           sketch_dtype="f32", check_every=args.check_every)
-            out.append((nu2, x, info))
-        return out
+        for _ in range(args.steps):
+            for nu2 in NU2S:
+                x, info = solve(nu2, mode)
+                out.append((nu2, x, info))
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = (0, 0.0)
+        if profile:
+            rs.rs_profile_enable(False)
+            prof = rs.rs_profile_read()
+        return out, ev0.elapsed_time(ev1), wall, prof
 
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -129,47 +180,49 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    rs.rs_profile_enable(True)
-    rs.rs_profile_read()                       # clear
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        results.append(step())
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rs.rs_profile_enable(False)
-    launches, grad_ms = rs.rs_profile_read()
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
-    solves = args.steps * len(NU2S)
-    value = solves / (ms_total / 1e3)
 
     # verification against the oracle (FP64 direct solve of the stored problem)
     from oracle import ridge
     A64 = p0.A.astype(np.float64)
     G = A64.T @ A64
     Atb = A64.T @ p0.b.astype(np.float64)
-    rels, infos = {}, {}
-    for nu2 in NU2S:
-        xs = ridge.solve_direct_from_gram(G, Atb, nu2)
-        H = G + nu2 * np.eye(D)
-        worst = 0.0
-        for res in results:
-            for (nu, x, info) in res:
+    xstar = {nu2: ridge.solve_direct_from_gram(G, Atb, nu2) for nu2 in NU2S}
+
+    def verify(results):
+        rels, infos = {}, {}
+        for nu2 in NU2S:
+            H = G + nu2 * np.eye(D)
+            worst = 0.0
+            for (nu, x, info) in results:
                 if nu == nu2:
-                    worst = max(worst, ridge.relative_error(H, x.cpu().numpy(), xs))
+                    worst = max(worst, ridge.relative_error(H, x.cpu().numpy(), xstar[nu2]))
                     infos[nu2] = info
-        rels[nu2] = worst
-    ok = all(r <= 1e-6 for r in rels.values()) and all(
-        i["status"] == "ok" for i in infos.values())
+            rels[nu2] = worst
+        ok = all(r <= 1e-6 for r in rels.values()) and all(
+            i["status"] == "ok" for _, _, i in results)
+        keys = ("m_final", "doublings", "steps", "grad_passes", "accepted_polyak", "accepted_gd")
+        summary = {str(k): {kk: infos[k][kk] for kk in keys} for k in NU2S}
+        for k in NU2S:
+            if "m_init" in infos[k]:
+                summary[str(k)]["m_init"] = infos[k]["m_init"]
+        return ok, rels, summary
+
+    solves = args.steps * len(NU2S)
+    main_mode = args.mode
+    results, ms_total, wall, (launches, grad_ms) = timed(main_mode, profile=True)
+    ms_per_step = ms_total / args.steps
+    value = solves / (ms_total / 1e3)
+    ok, rels, solve_summary = verify(results)
+    del results
+    plain = None
+    if main_mode != "plain":
+        pres, pms, pwall, _ = timed("plain", profile=False)
+        pok, prels, psum = verify(pres)
+        del pres
+        pval = solves / (pms / 1e3)
+        plain = {"value": round(pval, 3), "unit": "solves/s", "ms_per_step": round(pms / args.steps, 3),
+                 "verified": pok, "rel_pred_err": {str(k): v for k, v in prels.items()},
+                 "solve": psum, "dtype": "f32 sketch", "m_init": 1}
 
     # roofline of the dominant kernel: the gradient pass over A
     alg_bytes = N * D * 4 + N * 4
@@ -184,24 +237,175 @@ def main():
             "launches": launches}
 
     line = {
-        "metric": "ridge solves/s to 1e-6 rel. pred. error (plain FP32 IHS, SRHT)",
+        "metric": ("ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32; HBM GB/s"
+                   if main_mode != "plain" else
+                   "ridge solves/s to 1e-6 rel. pred. error (plain FP32 IHS, SRHT)"),
         "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 sketch / f32 gradient / f64 factor" if main_mode != "plain" else "f32",
         "data": "synthetic (seeded low-rank-decay A = G diag(1/i) V^T)",
         "config": {"workload": f"{N}x{D} FP32, sigma_i=1/i, nu^2 in {list(NU2S)}, SRHT rho=0.1, "
-                               f"m_init=1, {args.variant}, 2 solves per step",
+                               + ("learned m_init, BF16 sketch" if main_mode != "plain"
+                                  else "m_init=1, FP32 sketch")
+                               + f", {args.variant}, 2 solves per step",
+                   "mode": main_mode,
                    "n": N, "d": D, "parallelism": "single GPU"},
         "verified": ok,
         "rel_pred_err": {str(k): v for k, v in rels.items()},
-        "solve": {str(k): {kk: infos[k][kk] for kk in ("m_final", "doublings", "steps",
-                                                      "grad_passes", "accepted_polyak",
-                                                      "accepted_gd")} for k in NU2S},
+        "solve": solve_summary,
         "wall_s": round(wall, 3),
         "roofline": roof,
     }
+    if plain is not None:
+        line["plain_fp32"] = plain
+        line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p0.A, p0.b)
+    print(json.dumps(line))
+
+
+def oracle_gram_chunks(A_dev, b_dev, rows=65536):
+    """FP64 Gram A^T A and A^T b of a device problem, accumulated on the host in
+    row chunks (the oracle's definition, summed chunk by chunk)."""
+    n, d = A_dev.shape
+    G = np.zeros((d, d))
+    Atb = np.zeros(d)
+    for r0 in range(0, n, rows):
+        Ac = A_dev[r0:r0 + rows].cpu().numpy().astype(np.float64)
+        bc = b_dev[r0:r0 + rows].cpu().numpy().astype(np.float64)
+        G += Ac.T @ Ac
+        Atb += Ac.T @ bc
+    return G, Atb
+
+
+def run_c3(args):
+    """Precision form on the 2^20 x 4096 FP32 problem (sigma_i = exp(-i/400),
+    nu^2 = 1e-3 sigma_1^2): SRHT sketches in FP32, BF16 and FP8-E4M3; each solve's
+    relative prediction error against the oracle's FP64 solution."""
+    import torch
+    from oracle import ridge
+    from paper_2006_05874_amd import rs
+    from synth import make_problem_torch, spectrum
+    n, d = 1 << 20, 4096
+    sig = spectrum("exp", d, 400.0)
+    nu2 = 1e-3 * float(sig[0]) ** 2
+    torch.cuda.set_device(0)
+    A0, b, _ = make_problem_torch(n, d, sig, 0.1, 3, "cuda")
+    A = rs.padded(n, d, dtype=torch.float32)
+    A.copy_(A0)
+    del A0
+    torch.cuda.synchronize()
+    print(f"[c3] problem ready; oracle Gram on the host", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    G, Atb = oracle_gram_chunks(A, b)
+    xs = ridge.solve_direct_from_gram(G, Atb, nu2)
+    H = G + nu2 * np.eye(d)
+    oracle_s = time.perf_counter() - t0
+    res = {}
+    for dt in ("f32", "bf16", "fp8"):
+        rs.rs_adaptive_solve(A, b, nu2, sketch_dtype=dt)        # warm-up
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        outs = [rs.rs_adaptive_solve(A, b, nu2, sketch_dtype=dt, raise_on_error=False)
+                for _ in range(args.steps)]
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        x, info = outs[-1]
+        rel = max(ridge.relative_error(H, o[0].cpu().numpy(), xs) for o in outs)
+        res[dt] = {"solves_per_s": round(1e3 / ms, 3), "ms_per_solve": round(ms, 3),
+                   "rel_pred_err": rel, "status": info["status"], "m_final": info["m_final"],
+                   "doublings": info["doublings"], "grad_passes": info["grad_passes"]}
+        print(f"[c3] {dt}: {res[dt]}", file=sys.stderr, flush=True)
+    base = res["f32"]["solves_per_s"]
+    line = {"metric": "ridge solves/s to 1e-6 rel. pred. error, precision form",
+            "value": res["bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": res["bf16"]["ms_per_solve"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
+            "config": {"workload": f"{n}x{d} FP32, sigma_i=exp(-i/400), nu^2=1e-3 sigma_1^2, "
+                                   "SRHT rho=0.1, m from 1", "n": n, "d": d},
+            "verified": all(r["rel_pred_err"] <= 1e-6 and r["status"] == "ok"
+                            for r in res.values()),
+            "per_dtype": res, "speedup_bf16_vs_f32": round(res["bf16"]["solves_per_s"] / base, 3),
+            "speedup_fp8_vs_f32": round(res["fp8"]["solves_per_s"] / base, 3),
+            "oracle_gram_s": round(oracle_s, 1)}
+    print(json.dumps(line))
+
+
+def run_c4b(args):
+    """256 independent problems (n = 2^U{12..16}, d = U{128..1024}, sigma_i =
+    0.95^i, nu^2 = 1e-3): batched solves over worker streams with BF16 sketches
+    against the same problems solved one after another by the plain method (FP32
+    sketch).  Every solution is checked against the oracle's direct solve."""
+    import torch
+    from oracle import ridge
+    from paper_2006_05874_amd import rs
+    from synth import config_c4b_specs, make_c4b_problem
+    torch.cuda.set_device(0)
+    specs = config_c4b_specs()
+    probs = []
+    for sp in specs:
+        A0, b = make_c4b_problem(sp, "cuda")
+        A = rs.padded(sp["n"], sp["d"], dtype=torch.float32)
+        A.copy_(A0)
+        probs.append((A, b, sp["nu2"]))
+    del A0
+    torch.cuda.synchronize()
+    print(f"[c4b] {len(probs)} problems ready", file=sys.stderr, flush=True)
+
+    def run_batch():
+        return rs.rs_solve_batch(probs, sketch_dtype="bf16", workers=8, raise_on_error=False)
+
+    def run_seq():
+        return [rs.rs_adaptive_solve(A, b, nu2, sketch_dtype="f32", raise_on_error=False)
+                for A, b, nu2 in probs]
+
+    out = {}
+    for name, fn in (("batched_bf16", run_batch), ("sequential_plain_f32", run_seq)):
+        fn()                                   # warm-up (allocations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        out[name] = {"solves_per_s": round(len(probs) / sec, 2), "s_per_batch": round(sec, 4),
+                     "res": res}
+        print(f"[c4b] {name}: {len(probs) / sec:.1f} solves/s", file=sys.stderr, flush=True)
+    # oracle check of the last batch of each kind
+    worst = {k: 0.0 for k in out}
+    bad = {k: 0 for k in out}
+    for i, (A, b, nu2) in enumerate(probs):
+        A64 = A.cpu().numpy().astype(np.float64)
+        b64 = b.cpu().numpy().astype(np.float64)
+        Gm = A64.T @ A64
+        xs = ridge.solve_direct_from_gram(Gm, A64.T @ b64, nu2)
+        H = Gm + nu2 * np.eye(Gm.shape[0])
+        for k in out:
+            x, info = out[k]["res"][i]
+            worst[k] = max(worst[k], ridge.relative_error(H, x.cpu().numpy(), xs))
+            bad[k] += info["status"] != "ok"
+    for k in out:
+        del out[k]["res"]
+        out[k]["worst_rel_pred_err"] = worst[k]
+        out[k]["not_ok"] = bad[k]
+    line = {"metric": "ridge solves/s to 1e-6 rel. pred. error, batched uneven problems",
+            "value": out["batched_bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(out["batched_bf16"]["s_per_batch"] * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
+            "config": {"workload": "256 problems, n=2^U{12..16}, d=U{128..1024}, "
+                                   "sigma_i=0.95^i, nu^2=1e-3, SRHT, 8 worker streams"},
+            "verified": all(v["worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
+                            for v in out.values()),
+            "modes": out,
+            "speedup_vs_sequential_plain_f32": round(
+                out["batched_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
     print(json.dumps(line))
 
 

@@ -74,7 +74,7 @@ rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* 
  * (row, 0, stream, sketch_id) with stream 4 = signs (eps_i = 1 - 2 (w0 & 1)) and
  * stream 5 = row keys (w1 * 2^32 + w0; ties broken by row index).
  *   A    : n x d, dtype a_t in {F64, F32}, leading dimension lda.
- *   m    : 1 <= m <= npad; npad <= 2^20.
+ *   m    : 1 <= m <= npad; npad <= 2^22.
  *   SA   : m x d output, dtype sa_t (F64 only with F64 A; F32; BF16; FP8E4M3),
  *          leading dimension ldsa >= d.  Row k is sampled row rows[k]; rows are
  *          in ascending order.
@@ -246,6 +246,22 @@ typedef struct rs_problem {
  * work is queued. */
 rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
                          rs_solve_info* infos, int32_t workers, hipStream_t stream);
+
+/* Algorithm 1 for count values nu2[k] (host array, each > 0) on one (A, b), with
+ * one option set.  The sketch of level m = m_init 2^L (sketch_id L when fresh, 0
+ * when nested: what a single solve draws at that level) and its Gram do not
+ * depend on nu (Section 3), so they are formed once per level and shared; each
+ * nu keeps its own shifted FP64 factor, state and doubling ladder.  The
+ * gradients of all candidates of all running nu come from one multi-RHS product
+ * per step (matrix cores).  X: device, count x d FP64 row-major: in = x_1 of each
+ * nu, out = solutions.  infos: count host records, filled as rs_adaptive_solve
+ * fills one.  Synchronizes.  Returns RS_OK when every nu ended RS_OK or
+ * RS_ERR_NO_CONVERGENCE, else the first other error.  Memory: count d^2 doubles
+ * of factors plus the level cache. */
+rs_status rs_solve_nu_grid(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                           const void* b, const double* nu2, int64_t count,
+                           const rs_solve_opts* opts, double* X, rs_solve_info* infos,
+                           hipStream_t stream);
 
 /* ------------------------------------------------------------------ learned start */
 

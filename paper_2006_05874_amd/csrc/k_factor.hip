@@ -223,7 +223,10 @@ __global__ __launch_bounds__(256) void k_gram_lp_tn(const TIn* __restrict__ src,
 template <typename TAcc>
 __global__ __launch_bounds__(256) void k_gram_reduce(const TAcc* __restrict__ P, int nsplit,
                                                      int64_t p, double nu2,
-                                                     double* __restrict__ C, int64_t ldc) {
+                                                     double* __restrict__ C, int64_t ldc,
+                                                     FactorBatch zb) {
+  C += blockIdx.z * zb.sM;
+  if (zb.nu2) nu2 = zb.nu2[blockIdx.z];
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= bid) ++I;
@@ -496,7 +499,10 @@ __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB +
 // because the padding has zero coupling to the valid indices.
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64_t ld, int k,
                                                    double* __restrict__ Linv,
-                                                   int* __restrict__ info, int64_t p) {
+                                                   int* __restrict__ info, int64_t p,
+                                                   FactorBatch zb) {
+  M += blockIdx.z * zb.sM;
+  Linv += blockIdx.z * zb.sL;
   __shared__ double a[NB][NB + 1];
   __shared__ double x[NB][NB + 1];
   __shared__ double dinv[16][17];
@@ -525,7 +531,10 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
 // Blocks [0, nrest): L_ik = M_ik Linv_kk^T, i = k + 1 + b.
 // Blocks [nrest, nrest + k): X_kj = Linv_kk Y_kj in place, j = b - nrest.
 __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int64_t ld, int k,
-                                                    int nrest, double* __restrict__ Linv) {
+                                                    int nrest, double* __restrict__ Linv,
+                                                    FactorBatch zb) {
+  M += blockIdx.z * zb.sM;
+  Linv += blockIdx.z * zb.sL;
   __shared__ TileLds tl;
   const int t = threadIdx.x;
   const int ty = t >> 4, tx = t & 15;
@@ -557,7 +566,10 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int6
 // Blocks [0, tri(nrest)): M_ij -= L_ik L_jk^T for k < j <= i.
 // Blocks [tri(nrest), + nrest*(k+1)): Y_ij -= L_ik X_kj for i > k, j <= k.
 __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int64_t ld, int k,
-                                                     int nrest, double* __restrict__ Linv) {
+                                                     int nrest, double* __restrict__ Linv,
+                                                     FactorBatch zb) {
+  M += blockIdx.z * zb.sM;
+  Linv += blockIdx.z * zb.sL;
   __shared__ TileLds tl;
   const int64_t tri = (int64_t)nrest * (nrest + 1) / 2;
   const int64_t bid = blockIdx.x;
@@ -592,7 +604,9 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
 }
 
 // Linv buffer <- identity (p x p).
-__global__ __launch_bounds__(256) void k_fill_identity(double* __restrict__ X, int64_t p) {
+__global__ __launch_bounds__(256) void k_fill_identity(double* __restrict__ X, int64_t p,
+                                                       FactorBatch zb) {
+  X += blockIdx.z * zb.sL;
   const int64_t total = p * p;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * 256)
@@ -602,7 +616,10 @@ __global__ __launch_bounds__(256) void k_fill_identity(double* __restrict__ X, i
 // Hinv = Linv^T Linv (p x p, both triangles): tile (I, J), J <= I:
 // sum_{l >= I} Linv_lI^T Linv_lJ.
 __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, int64_t ld,
-                                               int nblk, double* __restrict__ H, int64_t ldh) {
+                                               int nblk, double* __restrict__ H, int64_t ldh,
+                                               FactorBatch zb) {
+  Linv += blockIdx.z * zb.sL;
+  H += (zb.hz ? zb.hz[blockIdx.z] : (int)blockIdx.z) * zb.sH;
   __shared__ TileLds tl;
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
@@ -634,7 +651,9 @@ __device__ __forceinline__ void shift_scale(QOpnd& o, int64_t off) { o.scale += 
 template <typename OSA>
 __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv, int64_t ld,
                                                 OSA SA, int64_t d, double* __restrict__ Cw,
-                                                int64_t ldc) {
+                                                int64_t ldc, FactorBatch zb) {
+  Linv += blockIdx.z * zb.sL;
+  Cw += blockIdx.z * zb.sC;
   __shared__ TileLds tl;
   const int64_t I = blockIdx.y, Jd = blockIdx.x;
   double acc[4][4];
@@ -656,7 +675,11 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ Linv,
 // Hinv = nu^-2 (I - C^T C) over d x d (both triangles), C padded with zero rows.
 __global__ __launch_bounds__(256) void k_woodbury_inv(const double* __restrict__ Cw, int64_t ldc,
                                                       int64_t mpad, double inv_nu2, int64_t dp,
-                                                      double* __restrict__ H, int64_t ldh) {
+                                                      double* __restrict__ H, int64_t ldh,
+                                                      FactorBatch zb) {
+  Cw += blockIdx.z * zb.sC;
+  H += (zb.hz ? zb.hz[blockIdx.z] : (int)blockIdx.z) * zb.sH;
+  if (zb.nu2) inv_nu2 = 1.0 / zb.nu2[blockIdx.z];
   __shared__ TileLds tl;
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
@@ -684,9 +707,31 @@ __global__ __launch_bounds__(256) void k_woodbury_inv(const double* __restrict__
 // ------------------------------------------------------------------ driver
 static inline int64_t pad64(int64_t v) { return (v + NB - 1) / NB * NB; }
 
-rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
-                       const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
-                       hipStream_t s) {
+// Split of the Gram's summed dimension (the number of partial products).
+static void gram_split(int64_t m, int64_t d, int& nsplit, int64_t& qchunk) {
+  const bool wood = m < d;
+  const int64_t p = wood ? m : d;
+  const int nblk = (int)(pad64(p) / NB);
+  const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
+  const int64_t q = wood ? d : m;
+  const int64_t cus = device_cus();
+  nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((2 * cus + tiles - 1) / tiles,
+                                                       (q + 255) / 256));
+  nsplit = std::min(nsplit, 16);
+  qchunk = ((q + nsplit - 1) / nsplit + 15) / 16 * 16;
+  nsplit = (int)((q + qchunk - 1) / qchunk);
+}
+
+int gram_partial_count(int64_t m, int64_t d) {
+  int ns;
+  int64_t qc;
+  gram_split(m, d, ns, qc);
+  return ns;
+}
+
+// 1. Gram partial products of SA into F.gram (FP32, or FP64 for FP64 SA)
+rs_status gram_partials(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, hipStream_t s) {
   const bool wood = m < d;
   const int64_t p = wood ? m : d;
   const int64_t pp = pad64(p);
@@ -694,12 +739,9 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
   const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
   // 1. Gram, split over the summed dimension so that the launch fills the chip
   const int64_t q = wood ? d : m;
-  const int64_t cus = device_cus();
-  int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((2 * cus + tiles - 1) / tiles,
-                                                           (q + 255) / 256));
-  nsplit = std::min(nsplit, 16);
-  const int64_t qchunk = ((q + nsplit - 1) / nsplit + 15) / 16 * 16;
-  nsplit = (int)((q + qchunk - 1) / qchunk);
+  int nsplit;
+  int64_t qchunk;
+  gram_split(m, d, nsplit, qchunk);
   const dim3 gg((unsigned)tiles, (unsigned)nsplit);
   const size_t esz = sa_t == RS_F64 ? 8 : 4;
   // the low-precision TN kernel reads 16-byte vectors of 64-column segments: it
@@ -716,7 +758,6 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
       hipLaunchKernelGGL((k_gram<float, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
       hipLaunchKernelGGL((k_gram<float, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
-    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_F64) {
     const double* X = reinterpret_cast<const double*>(SA);
     double* P = reinterpret_cast<double*>(F.gram);
@@ -724,18 +765,15 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
       hipLaunchKernelGGL((k_gram<double, double, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
       hipLaunchKernelGGL((k_gram<double, double, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
-    hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_BF16 && !wood && lp_ok) {
     float* P = reinterpret_cast<float*>(F.gram);
     hipLaunchKernelGGL(k_gram_lp_tn<uint16_t>, gg, dim3(256), 0, s,
                        reinterpret_cast<const uint16_t*>(SA), ldsa, p, q, qchunk, P, pp,
                        (const float*)nullptr);
-    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_FP8E4M3 && !wood && lp_ok) {
     float* P = reinterpret_cast<float*>(F.gram);
     hipLaunchKernelGGL(k_gram_lp_tn<uint8_t>, gg, dim3(256), 0, s,
                        reinterpret_cast<const uint8_t*>(SA), ldsa, p, q, qchunk, P, pp, colscale);
-    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_BF16) {
     const uint16_t* X = reinterpret_cast<const uint16_t*>(SA);
     float* P = reinterpret_cast<float*>(F.gram);
@@ -743,7 +781,6 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
       hipLaunchKernelGGL((k_gram<uint16_t, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
       hipLaunchKernelGGL((k_gram<uint16_t, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
-    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else if (sa_t == RS_FP8E4M3) {
     const uint8_t* X = reinterpret_cast<const uint8_t*>(SA);
     float* P = reinterpret_cast<float*>(F.gram);
@@ -751,53 +788,89 @@ rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
       hipLaunchKernelGGL((k_gram<uint8_t, float, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, colscale);
     else
       hipLaunchKernelGGL((k_gram<uint8_t, float, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, colscale);
-    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, P, nsplit, p, nu2, F.M, pp);
   } else {
     return set_error(RS_ERR_UNSUPPORTED, "factor: SA dtype not supported");
   }
+  return check_launch("gram");
+}
+
+// 2.-3. For B shifted copies of one Gram (nu2[z], or the scalar nu2 when B = 1
+// and nu2_dev is null): M_z = Gram + nu2_z I, Cholesky + Linv, explicit inverse
+// into F.Hinv + z * zb.sH.  M, Linv, Cw advance by zb.sM, zb.sL, zb.sC per z.
+rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
+                        int B, FactorBatch zb, hipStream_t s) {
+  const bool wood = m < d;
+  const int64_t p = wood ? m : d;
+  const int64_t pp = pad64(p);
+  const int nblk = (int)(pp / NB);
+  const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
+  const unsigned Bz = (unsigned)B;
+  int nsplit;
+  int64_t qchunk;
+  gram_split(m, d, nsplit, qchunk);
+  if (sa_t == RS_F64)
+    hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s,
+                       reinterpret_cast<const double*>(F.gram), nsplit, p, nu2, F.M, pp, zb);
+  else
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s,
+                       reinterpret_cast<const float*>(F.gram), nsplit, p, nu2, F.M, pp, zb);
   // 2. Cholesky + Linv
   {
     const int64_t tot = pp * pp;
     const unsigned g = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_identity, dim3(g), dim3(256), 0, s, F.Linv, pp);
+    hipLaunchKernelGGL(k_fill_identity, dim3(g, 1, Bz), dim3(256), 0, s, F.Linv, pp, zb);
   }
   for (int k = 0; k < nblk; ++k) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, F.M, pp, k, F.Linv, F.info, p);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1, 1, Bz), dim3(256), 0, s, F.M, pp, k, F.Linv, F.info, p,
+                       zb);
     const int nrest = nblk - 1 - k;
     if (nrest + k > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(nrest + k)), dim3(256), 0, s, F.M, pp, k,
-                         nrest, F.Linv);
+      hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(nrest + k), 1, Bz), dim3(256), 0, s, F.M,
+                         pp, k, nrest, F.Linv, zb);
     if (nrest > 0) {
       const int64_t nb_upd = (int64_t)nrest * (nrest + 1) / 2 + (int64_t)nrest * (k + 1);
-      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nb_upd), dim3(256), 0, s, F.M, pp, k,
-                         nrest, F.Linv);
+      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nb_upd, 1, Bz), dim3(256), 0, s, F.M, pp,
+                         k, nrest, F.Linv, zb);
     }
   }
   // 3. explicit inverse
   const int64_t dp = pad64(d);
   if (!wood) {
-    hipLaunchKernelGGL(k_lauum, dim3((unsigned)tiles), dim3(256), 0, s, F.Linv, pp, nblk, F.Hinv,
-                       dp);
+    hipLaunchKernelGGL(k_lauum, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s, F.Linv, pp, nblk,
+                       F.Hinv, dp, zb);
   } else {
-    const dim3 g2((unsigned)(dp / NB), (unsigned)nblk);
+    const dim3 g2((unsigned)(dp / NB), (unsigned)nblk, Bz);
     if (sa_t == RS_F32) {
-      FOpnd B{reinterpret_cast<const float*>(SA), ldsa, m, d, false};
-      hipLaunchKernelGGL((k_whiten<FOpnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
+      FOpnd Bo{reinterpret_cast<const float*>(SA), ldsa, m, d, false};
+      hipLaunchKernelGGL((k_whiten<FOpnd>), g2, dim3(256), 0, s, F.Linv, pp, Bo, d, F.Cw, dp,
+                         zb);
     } else if (sa_t == RS_F64) {
-      Opnd B{reinterpret_cast<const double*>(SA), ldsa, m, d, false};
-      hipLaunchKernelGGL((k_whiten<Opnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
+      Opnd Bo{reinterpret_cast<const double*>(SA), ldsa, m, d, false};
+      hipLaunchKernelGGL((k_whiten<Opnd>), g2, dim3(256), 0, s, F.Linv, pp, Bo, d, F.Cw, dp,
+                         zb);
     } else if (sa_t == RS_BF16) {
-      HOpnd B{reinterpret_cast<const uint16_t*>(SA), ldsa, m, d, false};
-      hipLaunchKernelGGL((k_whiten<HOpnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
+      HOpnd Bo{reinterpret_cast<const uint16_t*>(SA), ldsa, m, d, false};
+      hipLaunchKernelGGL((k_whiten<HOpnd>), g2, dim3(256), 0, s, F.Linv, pp, Bo, d, F.Cw, dp,
+                         zb);
     } else {
-      QOpnd B{reinterpret_cast<const uint8_t*>(SA), ldsa, m, d, false, colscale};
-      hipLaunchKernelGGL((k_whiten<QOpnd>), g2, dim3(256), 0, s, F.Linv, pp, B, d, F.Cw, dp);
+      QOpnd Bo{reinterpret_cast<const uint8_t*>(SA), ldsa, m, d, false, colscale};
+      hipLaunchKernelGGL((k_whiten<QOpnd>), g2, dim3(256), 0, s, F.Linv, pp, Bo, d, F.Cw, dp,
+                         zb);
     }
     const int dblk = (int)(dp / NB);
-    hipLaunchKernelGGL(k_woodbury_inv, dim3((unsigned)(dblk * (dblk + 1) / 2)), dim3(256), 0, s,
-                       F.Cw, dp, pp, 1.0 / nu2, dp, F.Hinv, dp);
+    hipLaunchKernelGGL(k_woodbury_inv, dim3((unsigned)(dblk * (dblk + 1) / 2), 1, Bz), dim3(256),
+                       0, s, F.Cw, dp, pp, 1.0 / nu2, dp, F.Hinv, dp, zb);
   }
   return check_launch("factor");
+}
+
+rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                       const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
+                       hipStream_t s) {
+  const rs_status st = gram_partials(F, SA, sa_t, colscale, m, d, ldsa, s);
+  if (st != RS_OK) return st;
+  return factor_finish(F, SA, sa_t, colscale, m, d, ldsa, nu2, 1, FactorBatch{}, s);
 }
 
 size_t factor_bytes_M(int64_t m, int64_t d) {

@@ -1,0 +1,562 @@
+// Kernels of the nu-grid form: many regularisation values on one A.
+//
+// The sketch S A, and with it the Gram (SA)^T SA or SA (SA)^T, does not depend
+// on nu (Section 3: the sketched Hessian is (SA)^T SA + nu^2 I).  With fresh
+// resampling every level m = m_init 2^L draws sketch_id L, and with nested
+// resampling every level keeps sketch_id 0: in both cases all nu values at one
+// level share the sketch and the Gram, and only the shifted factors differ.
+//
+// The gradients A^T (A x - b) + nu^2 x of all candidates of all active nu form
+// one multi-right-hand-side product: R = A X^T - b 1^T (n x Kc), then
+// G = A^T R (d x Kc) split over row chunks, both on the matrix cores (FP32
+// MFMA 16x16x4 for FP32 A, FP64 MFMA for FP64 A); FP32 chunk sums are moved to
+// FP64 every 256 rows.  The per-nu step kernels (candidates, apply, decide,
+// resample bookkeeping) run as one launch over the active list: block row y
+// serves list entry y, whose slot is zl[y].
+#include "rs_internal.hpp"
+
+namespace rs {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+using Acc4 = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+
+template <typename T>
+__device__ __forceinline__ Acc4<T> mfma4(T a, T b, Acc4<T> c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- R = A X^T - b
+// Block: 128 rows x 128 columns of R, 4 waves of 32 rows x 128 columns; k (the
+// d dimension) in chunks of 32 through LDS.  X is Kc x d FP64 (rounded to T).
+// Block b covers column block b % ncb of row block b / ncb, so the blocks that
+// read one row panel of A run next to each other.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mr_resid(const T* __restrict__ A, int64_t n, int64_t d,
+                                                  int64_t lda, const T* __restrict__ b,
+                                                  const double* __restrict__ X, int64_t Kc,
+                                                  T* __restrict__ R, int64_t ldr, int ncb,
+                                                  int* __restrict__ ran) {
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  constexpr int TM = 128, TC = 128, KC = 32;
+  __shared__ T As[KC][TM + 1];
+  __shared__ T Xs[KC][TC + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t r0 = (int64_t)(blockIdx.x / ncb) * TM;
+  const int64_t c0 = (int64_t)(blockIdx.x % ncb) * TC;
+  Acc4<T> acc[2][8];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[a][c] = Acc4<T>{0, 0, 0, 0};
+  // loader mapping: thread -> (row or column = t / 2, 16 consecutive k)
+  const int lrow = t >> 1, lk = (t & 1) * 16;
+  for (int64_t k0 = 0; k0 < d; k0 += KC) {
+    {
+      const int64_t row = r0 + lrow;
+      const bool rok = row < n;
+      const T* src = A + (rok ? row : 0) * lda;
+      T v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t k = k0 + lk + e;
+        const bool ok = rok && k < d;
+        const T x = src[ok ? k : 0];
+        v[e] = ok ? x : (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) As[lk + e][lrow] = v[e];
+    }
+    {
+      const int64_t col = c0 + lrow;
+      const bool cok = col < Kc;
+      const double* src = X + (cok ? col : 0) * d;
+      T v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t k = k0 + lk + e;
+        const bool ok = cok && k < d;
+        const double x = src[ok ? k : 0];
+        v[e] = ok ? (T)x : (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) Xs[lk + e][lrow] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      T av[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kr][w * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const T bv = Xs[kr][c * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a][c] = mfma4<T>(av[a], bv, acc[a][c]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + w * 32 + a * 16 + mfma16_row<T>(lane, r);
+      if (row < n) {
+        const T bv = b[row];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int64_t col = c0 + c * 16 + (lane & 15);
+          if (col < Kc) R[row * ldr + col] = acc[a][c][r] - bv;
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------- Gp = A^T R per chunk
+// Block (tile, split): 128 columns of A (j) x 128 columns of R (c) over the
+// split's rows, 4 waves of 32 j x 128 c; rows in chunks of 32 through LDS.
+// Partial layout Gp[split][j][c] (ldr columns), FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mr_atr(const T* __restrict__ A, int64_t n, int64_t d,
+                                                int64_t lda, const T* __restrict__ R, int64_t ldr,
+                                                int64_t Kc, int64_t rows_per_split, int ncb,
+                                                double* __restrict__ Gp) {
+  constexpr int TJ = 128, TC = 128, KC = 32;
+  __shared__ T As[KC][TJ + 1];
+  __shared__ T Rs[KC][TC + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t j0 = (int64_t)(blockIdx.x / ncb) * TJ;
+  const int64_t c0 = (int64_t)(blockIdx.x % ncb) * TC;
+  const int64_t row_lo = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t row_hi = row_lo + rows_per_split < n ? row_lo + rows_per_split : n;
+  Acc4<T> acc[2][8];
+  double acc64[2][8][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      acc[a][c] = Acc4<T>{0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[a][c][r] = 0.0;
+    }
+  // loader mapping: thread -> (row = t / 8, 16 consecutive columns)
+  const int lr = t >> 3, lc = (t & 7) * 16;
+  int chunk = 0;
+  for (int64_t k0 = row_lo; k0 < row_hi; k0 += KC, ++chunk) {
+    {
+      const int64_t row = k0 + lr;
+      const bool rok = row < row_hi;
+      const T* src = A + (rok ? row : 0) * lda;
+      T v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t j = j0 + lc + e;
+        const bool ok = rok && j < d;
+        const T x = src[ok ? j : 0];
+        v[e] = ok ? x : (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) As[lr][lc + e] = v[e];
+    }
+    {
+      const int64_t row = k0 + lr;
+      const bool rok = row < row_hi;
+      const T* src = R + (rok ? row : 0) * ldr;
+      T v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t c = c0 + lc + e;
+        const bool ok = rok && c < Kc;
+        const T x = src[ok ? c : 0];
+        v[e] = ok ? x : (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) Rs[lr][lc + e] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      T av[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kr][w * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const T bv = Rs[kr][c * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a][c] = mfma4<T>(av[a], bv, acc[a][c]);
+      }
+    }
+    __syncthreads();
+    if (sizeof(T) == 4 && (chunk & 7) == 7) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[a][c][r] += (double)acc[a][c][r];
+          acc[a][c] = Acc4<T>{0, 0, 0, 0};
+        }
+    }
+  }
+  double* out = Gp + (int64_t)blockIdx.y * d * ldr;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = j0 + w * 32 + a * 16 + mfma16_row<T>(lane, r);
+      if (j < d) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int64_t col = c0 + c * 16 + (lane & 15);
+          if (col < Kc) out[j * ldr + col] = acc64[a][c][r] + (double)acc[a][c][r];
+        }
+      }
+    }
+}
+
+// G[c][j] = sum_s Gp[s][j][c] (fixed order) + nu2[zl[c / kper]] X[c][j].
+__global__ __launch_bounds__(256) void k_mr_reduce(const double* __restrict__ Gp, int nsplit,
+                                                   int64_t d, int64_t ldr, int64_t Kc, int kper,
+                                                   const double* __restrict__ X,
+                                                   const double* __restrict__ nu2,
+                                                   const int* __restrict__ zl,
+                                                   double* __restrict__ G) {
+  const int64_t total = Kc * d;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t c = e % Kc, j = e / Kc;
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) s += Gp[((int64_t)sp * d + j) * ldr + c];
+    const int z = zl[c / kper];
+    G[c * d + j] = s + nu2[z] * X[c * d + j];
+  }
+}
+
+int mr_splits(int64_t n, int64_t d, int64_t Kc, int64_t& rows_per_split) {
+  const int64_t tiles = ((d + 127) / 128) * ((Kc + 127) / 128);
+  const int64_t want = (2 * device_cus() + tiles - 1) / tiles;
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(want, (n + 255) / 256));
+  rows_per_split = ((n + ns - 1) / ns + 31) / 32 * 32;
+  ns = (n + rows_per_split - 1) / rows_per_split;
+  return (int)ns;
+}
+
+template <typename T>
+rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
+                      int64_t Kc, int kper, const double* nu2, const int* zl, T* R, int64_t ldr,
+                      double* Gp, double* G, hipStream_t s) {
+  const int ncb = (int)((Kc + 127) / 128);
+  const unsigned g1 = (unsigned)(((n + 127) / 128) * ncb);
+  int* ran = prof_begin(s);
+  hipLaunchKernelGGL(k_mr_resid<T>, dim3(g1), dim3(256), 0, s, A, n, d, lda, b, X, Kc, R, ldr,
+                     ncb, ran);
+  int64_t rps = 0;
+  const int ns = mr_splits(n, d, Kc, rps);
+  const unsigned g2 = (unsigned)(((d + 127) / 128) * ncb);
+  hipLaunchKernelGGL(k_mr_atr<T>, dim3(g2, (unsigned)ns), dim3(256), 0, s, A, n, d, lda, R, ldr,
+                     Kc, rps, ncb, Gp);
+  prof_end(s);
+  const unsigned g3 = (unsigned)std::min<int64_t>((Kc * d + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_mr_reduce, dim3(g3), dim3(256), 0, s, Gp, ns, d, ldr, Kc, kper, X, nu2, zl,
+                     G);
+  return check_launch("multi-rhs gradient");
+}
+
+template rs_status mr_gradient<float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                      const double*, int64_t, int, const double*, const int*,
+                                      float*, int64_t, double*, double*, hipStream_t);
+template rs_status mr_gradient<double>(const double*, int64_t, int64_t, int64_t, const double*,
+                                       const double*, int64_t, int, const double*, const int*,
+                                       double*, int64_t, double*, double*, hipStream_t);
+
+// ---------------------------------------------------------------- batched step kernels
+// Slot z (a nu value) owns: x = P.x + z d, vectors P.vec + z 4d (x_prev, g,
+// gtilde, g_ref), control record P.ctl[z], event log P.ev + z ev_cap, inverse
+// P.Hinv + z sH, decrement partials P.rpart + z nrp 2.  List entry y (slot
+// zl[y]) owns the candidate blocks Xc, Gc, GTc + y K d.
+
+__device__ __forceinline__ bool slot_running(const GridPtrs& P, int z) {
+  return P.ctl[z].status == RS_CTL_RUNNING;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_cand_g(GridPtrs P, int64_t d, double mu_p, double beta_p,
+                                                double mu_gd) {
+  const int y = blockIdx.y, z = P.zl[y];
+  if (!slot_running(P, z)) return;
+  const double* x = P.x + (int64_t)z * d;
+  const double* xp = P.vec + (int64_t)z * 4 * d;
+  const double* gt = xp + 2 * d;
+  double* X = P.Xc + (int64_t)y * K * d;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
+    const double xi = x[i], gi = gt[i];
+    if (K == 2) {
+      X[i] = xi - mu_p * gi + beta_p * (xi - xp[i]);
+      X[d + i] = xi - mu_gd * gi;
+    } else {
+      X[i] = xi - mu_gd * gi;
+    }
+  }
+}
+
+// Copy x into the candidate block (first gradient) or [g, g_ref] (resample).
+__global__ __launch_bounds__(256) void k_pack_g(GridPtrs P, int64_t d, int what, int kper) {
+  const int y = blockIdx.y, z = P.zl[y];
+  double* X = P.Xc + (int64_t)y * kper * d;
+  const double* v = P.vec + (int64_t)z * 4 * d;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
+    if (what == 0) {
+      X[i] = P.x[(int64_t)z * d + i];
+    } else {
+      X[i] = v[d + i];
+      X[d + i] = v[3 * d + i];
+    }
+  }
+}
+
+// GT[y] = Hinv_z G[y] (K columns) and decrement partials; gated on the slot's
+// status unless `always`.
+template <int K, int RPW>
+__global__ __launch_bounds__(256) void k_symv_g(GridPtrs P, int64_t d, const double* __restrict__ Gsrc,
+                                                int always) {
+  const int y = blockIdx.y, z = P.zl[y];
+  if (!always && !slot_running(P, z)) return;
+  const double* H = P.Hinv + (int64_t)z * P.sH;
+  const double* G = Gsrc + (int64_t)y * K * d;
+  double* Y = P.GTc + (int64_t)y * K * d;
+  double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
+  __shared__ double rr[4][K];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * RPW;
+  double acc[RPW][K];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[i][c] = 0.0;
+  for (int64_t j = lane; j < d; j += 64) {
+    double gv[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) gv[c] = G[c * d + j];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int64_t row = r0 + i;
+      const double h = H[(row < d ? row : 0) * P.ldh + j];
+#pragma unroll
+      for (int c = 0; c < K; ++c) acc[i][c] = fma(row < d ? h : 0.0, gv[c], acc[i][c]);
+    }
+  }
+  double rloc[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) rloc[c] = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int64_t row = r0 + i;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const double v = wave_sum(acc[i][c]);
+      if (row < d) {
+        if (lane == 0) Y[c * d + row] = v;
+        rloc[c] += v * G[c * d + row];
+      }
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < K; ++c) rr[w][c] = rloc[c];
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int ww = 0; ww < 4; ++ww) s += rr[ww][threadIdx.x];
+    rpart[(int64_t)blockIdx.x * K + threadIdx.x] = s;
+  }
+}
+
+// Same tests and state moves as the single-problem decision kernel.
+template <int K>
+__global__ __launch_bounds__(1024) void k_decide_g(GridPtrs P, DecideParams a, int64_t d) {
+  const int y = blockIdx.y, z = P.zl[y];
+  DevCtl* ctl = P.ctl + z;
+  __shared__ double r[K];
+  __shared__ int chosen;
+  if (ctl->status != RS_CTL_RUNNING) return;
+  const double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int b = 0; b < P.nrp; ++b) s += rpart[(int64_t)b * K + threadIdx.x];
+    r[threadIdx.x] = 0.5 * s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = -1;
+    int st = RS_CTL_RUNNING;
+    const double rt = ctl->r_t, r1 = ctl->r_1;
+    const int64_t t = ctl->t;
+    bool finite = true;
+    for (int i = 0; i < K; ++i) finite = finite && isfinite(r[i]);
+    ctl->passes += 1;
+    if (!finite) {
+      st = RS_CTL_NONFINITE;
+    } else {
+      if (K == 2) {
+        if (pow(r[0] / r1, 1.0 / (double)t) <= a.cbar_p) c = 0;
+      }
+      if (c < 0) {
+        const double rg = r[K - 1];
+        if (rg / rt <= a.cbar_gd) c = K - 1;
+        else if (ctl->at_cap) {
+          if (rg < rt) c = K - 1;
+          else st = RS_CTL_STUCK;
+        } else {
+          st = RS_CTL_DOUBLE;
+        }
+      }
+    }
+    if (c >= 0) {
+      const int kind = (K == 2 && c == 0) ? 0 : 1;
+      if (t < P.ev_cap) P.ev[(int64_t)z * P.ev_cap + t] = kind;
+      if (kind == 0) ctl->polyak += 1; else ctl->gd += 1;
+      ctl->r_t = r[c];
+      ctl->t = t + 1;
+      ctl->steps += 1;
+      if (r[c] <= a.tol * ctl->r_ref) st = RS_CTL_CONVERGED;
+      else if (t + 1 >= a.max_iter) st = RS_CTL_MAXITER;
+    }
+    ctl->last_r[0] = r[0];
+    ctl->last_r[1] = r[K - 1];
+    ctl->status = st;
+    chosen = c;
+  }
+  __syncthreads();
+  const int c = chosen;
+  if (c < 0) return;
+  double* x = P.x + (int64_t)z * d;
+  double* v = P.vec + (int64_t)z * 4 * d;
+  const double* X = P.Xc + (int64_t)y * K * d;
+  const double* G = P.Gc + (int64_t)y * K * d;
+  const double* GT = P.GTc + (int64_t)y * K * d;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    v[i] = x[i];
+    x[i] = X[(int64_t)c * d + i];
+    v[d + i] = G[(int64_t)c * d + i];
+    v[2 * d + i] = GT[(int64_t)c * d + i];
+  }
+}
+
+// After the first gradient and apply (one column per slot).
+__global__ __launch_bounds__(1024) void k_init_g(GridPtrs P, double tol, int64_t max_iter,
+                                                 int64_t d, const int* __restrict__ at_cap) {
+  const int y = blockIdx.y, z = P.zl[y];
+  DevCtl* ctl = P.ctl + z;
+  const double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < P.nrp; ++b) s += rpart[b];
+    const double r = 0.5 * s;
+    ctl->r_t = r;
+    ctl->r_1 = r;
+    ctl->r_ref = r;
+    ctl->t = 1;
+    ctl->steps = 0;
+    ctl->passes = 1;
+    ctl->polyak = 0;
+    ctl->gd = 0;
+    ctl->at_cap = at_cap[z];
+    int st = RS_CTL_RUNNING;
+    if (!isfinite(r)) st = RS_CTL_NONFINITE;
+    else if (r <= tol * r) st = RS_CTL_CONVERGED;
+    else if (1 >= max_iter) st = RS_CTL_MAXITER;
+    ctl->status = st;
+  }
+  const double* x = P.x + (int64_t)z * d;
+  double* v = P.vec + (int64_t)z * 4 * d;
+  const double* G = P.Gc + (int64_t)y * d;
+  const double* GT = P.GTc + (int64_t)y * d;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    v[i] = x[i];
+    v[d + i] = G[i];
+    v[3 * d + i] = G[i];
+    v[2 * d + i] = GT[i];
+  }
+}
+
+// After a resample: apply was run on [g_t, g_ref] of the slot.
+__global__ __launch_bounds__(1024) void k_post_resample_g(GridPtrs P, double tol, int64_t d,
+                                                          const int* __restrict__ at_cap) {
+  const int y = blockIdx.y, z = P.zl[y];
+  DevCtl* ctl = P.ctl + z;
+  const double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = 0; b < P.nrp; ++b) {
+      s0 += rpart[(int64_t)b * 2];
+      s1 += rpart[(int64_t)b * 2 + 1];
+    }
+    ctl->r_t = 0.5 * s0;
+    ctl->r_ref = 0.5 * s1;
+    ctl->at_cap = at_cap[z];
+    int st = RS_CTL_RUNNING;
+    if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;
+    else if (ctl->r_t <= tol * ctl->r_ref) st = RS_CTL_CONVERGED;
+    ctl->status = st;
+  }
+  double* gt = P.vec + (int64_t)z * 4 * d + 2 * d;
+  const double* GT = P.GTc + (int64_t)y * 2 * d;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) gt[i] = GT[i];
+}
+
+static unsigned vgrid(int64_t d) { return (unsigned)std::min<int64_t>((d + 255) / 256, 64); }
+
+rs_status grid_candidates(const GridPtrs& P, int nl, int K, int64_t d, double mu_p, double beta_p,
+                          double mu_gd, hipStream_t s) {
+  const dim3 g(vgrid(d), (unsigned)nl);
+  if (K == 2) hipLaunchKernelGGL(k_cand_g<2>, g, dim3(256), 0, s, P, d, mu_p, beta_p, mu_gd);
+  else hipLaunchKernelGGL(k_cand_g<1>, g, dim3(256), 0, s, P, d, mu_p, beta_p, mu_gd);
+  return check_launch("grid candidates");
+}
+
+rs_status grid_pack(const GridPtrs& P, int nl, int64_t d, int what, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_g, dim3(vgrid(d), (unsigned)nl), dim3(256), 0, s, P, d, what,
+                     what == 0 ? 1 : 2);
+  return check_launch("grid pack");
+}
+
+rs_status grid_apply(const GridPtrs& P, int nl, int K, int64_t d, const double* Gsrc, int always,
+                     hipStream_t s) {
+  const dim3 g((unsigned)apply_blocks(d), (unsigned)nl);
+  if (K == 2) hipLaunchKernelGGL((k_symv_g<2, 2>), g, dim3(256), 0, s, P, d, Gsrc, always);
+  else hipLaunchKernelGGL((k_symv_g<1, 2>), g, dim3(256), 0, s, P, d, Gsrc, always);
+  return check_launch("grid apply");
+}
+
+rs_status grid_decide(const GridPtrs& P, int nl, int K, const DecideParams& a, int64_t d,
+                      hipStream_t s) {
+  const dim3 g(1, (unsigned)nl);
+  if (K == 2) hipLaunchKernelGGL(k_decide_g<2>, g, dim3(1024), 0, s, P, a, d);
+  else hipLaunchKernelGGL(k_decide_g<1>, g, dim3(1024), 0, s, P, a, d);
+  return check_launch("grid decide");
+}
+
+rs_status grid_init(const GridPtrs& P, int nl, double tol, int64_t max_iter, int64_t d,
+                    const int* at_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_g, dim3(1, (unsigned)nl), dim3(1024), 0, s, P, tol, max_iter, d,
+                     at_cap);
+  return check_launch("grid init");
+}
+
+rs_status grid_post_resample(const GridPtrs& P, int nl, double tol, int64_t d, const int* at_cap,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_post_resample_g, dim3(1, (unsigned)nl), dim3(1024), 0, s, P, tol, d,
+                     at_cap);
+  return check_launch("grid post resample");
+}
+
+}  // namespace rs

@@ -344,7 +344,11 @@ __device__ __forceinline__ void store_row_bf16(uint16_t* out, int64_t ldo, int64
 
 // mode 0: pass 1 writing Zc rows (j1*Q + qmap[i2]);
 // mode 1: pass 1 writing SA rows kmap[row] (single pass, npad <= 1024);
-// mode 2: pass 2 reading Zc, writing SA rows.
+// mode 2: pass 2 reading Zc, writing SA rows.  When the high index j1 has more
+//   than 10 bits (npad > 2^20), its top hb bits are folded while loading: block
+//   z = r1h sums Zc over j1h with signs (-1)^popcount(r1h & j1h), so the tile
+//   transform over the low 10 bits of j1 yields the output rows whose high
+//   index has r1h in its top bits.
 // OutT: T, or uint16_t for BF16 output.
 template <typename T, typename OutT, int MODE>
 __global__ __launch_bounds__(256) void k_fwht_tile(
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     const int8_t* __restrict__ signs, int lb, int64_t n2, int64_t Q,
     const int32_t* __restrict__ qmap, const int32_t* __restrict__ qlist,
     const int32_t* __restrict__ kmap, const int32_t* __restrict__ qcount,
-    OutT* __restrict__ out, int64_t ldo, double scale) {
+    OutT* __restrict__ out, int64_t ldo, double scale, int hb) {
   using TT = Tile<T>;
   using V = typename TT::V;
   constexpr int VEC = TT::VEC;
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     } else {
       const int64_t n1 = (int64_t)1 << lb;
       const int64_t qq = r >> lb;
-      const int64_t i1 = r & (n1 - 1);
+      const int64_t i1 = ((int64_t)blockIdx.z << lb) + (r & (n1 - 1));
       const int64_t q = tile * (TT::RT >> lb) + qq;
       const bool okq = q < (int64_t)(*qcount);
       const int32_t i2 = qlist[okq ? q : 0];
@@ -414,6 +418,24 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     okr[j] = ok && cvec;
     v[j] = *reinterpret_cast<const V*>(src + srowc * lds_src + (cvec ? col0 : 0));
     sgn[j] = (MODE == 2) ? (T)1 : (T)signs[srowc];
+  }
+  if (MODE == 2 && hb > 0) {
+    // fold the top hb bits of j1: Zc tile (h << lb) + i1 with sign by r1h & h
+    const int64_t stride = ((int64_t)1 << lb) * Q;
+    for (int h = 1; h < (1 << hb); ++h) {
+      const T sh = (__popc(blockIdx.z & (unsigned)h) & 1) ? (T)-1 : (T)1;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int r = g + 32 * j;
+        const int64_t n1 = (int64_t)1 << lb;
+        const int64_t q = tile * (TT::RT >> lb) + (r >> lb);
+        const bool ok = q < Q;
+        const int64_t srow = ok ? (int64_t)h * stride + (r & (n1 - 1)) * Q + q : 0;
+        const V w = *reinterpret_cast<const V*>(src + srow * lds_src + (cvec ? col0 : 0));
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) set(v[j], e, get(v[j], e) + sh * get(w, e));
+      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -472,10 +494,10 @@ int srht_compact_block() { return kCompactBlock; }
 template <typename T, typename OutT, int MODE>
 static void launch_tile(dim3 grid, hipStream_t s, const T* src, int64_t nsrc, int64_t ldsrc,
                         int64_t d, const SrhtBuffers& B, int lb, int64_t n2, int64_t Q, void* out,
-                        int64_t ldo, double scale) {
+                        int64_t ldo, double scale, int hb = 0) {
   hipLaunchKernelGGL((k_fwht_tile<T, OutT, MODE>), grid, dim3(256), 0, s, src, nsrc, ldsrc, d,
                      B.signs, lb, n2, Q, B.qmap, B.qlist, B.kmap, B.qcount,
-                     reinterpret_cast<OutT*>(out), ldo, scale);
+                     reinterpret_cast<OutT*>(out), ldo, scale, hb);
 }
 
 template <typename T>
@@ -495,7 +517,11 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
   if constexpr (sizeof(T) == 8) {
     if (bf16) return set_error(RS_ERR_UNSUPPORTED, "srht: BF16 output needs FP32 input");
   }
-  if (n1 > TT::RT) return set_error(RS_ERR_SHAPE, "srht: padded n above 2^20 is not supported");
+  if (n1 > 4 * TT::RT) return set_error(RS_ERR_SHAPE, "srht: padded n above 2^22 is not supported");
+  // pass 2 transforms the low (at most 10) bits of j1 in the tile and folds the rest
+  const int lbt = lb1 < 10 ? lb1 : 10;
+  const int hb = lb1 - lbt;
+  const int64_t n1t = (int64_t)1 << lbt;
   if (n1 == 1) {
     if constexpr (sizeof(T) == 4) {
       if (bf16) {
@@ -511,17 +537,17 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
   const int64_t ldz = ((d + TT::VEC - 1) / TT::VEC) * TT::VEC;
   launch_tile<T, T, 0>(dim3((unsigned)n1, panels), s, A, n, lda, d, B, lb2, n2, Qmax, B.zbuf, ldz,
                        1.0);
-  const int64_t tiles2 = (Qmax * n1 + TT::RT - 1) / TT::RT;
+  const int64_t tiles2 = (Qmax * n1t + TT::RT - 1) / TT::RT;
   const T* Z = reinterpret_cast<const T*>(B.zbuf);
+  const dim3 grid2((unsigned)tiles2, panels, 1u << hb);
   if constexpr (sizeof(T) == 4) {
     if (bf16) {
-      launch_tile<T, uint16_t, 2>(dim3((unsigned)tiles2, panels), s, Z, n1 * Qmax, ldz, d, B, lb1,
-                                  n2, Qmax, SA, ldsa, scale);
+      launch_tile<T, uint16_t, 2>(grid2, s, Z, n1 * Qmax, ldz, d, B, lbt, n2, Qmax, SA, ldsa,
+                                  scale, hb);
       return check_launch("srht two pass");
     }
   }
-  launch_tile<T, T, 2>(dim3((unsigned)tiles2, panels), s, Z, n1 * Qmax, ldz, d, B, lb1, n2, Qmax,
-                       SA, ldsa, scale);
+  launch_tile<T, T, 2>(grid2, s, Z, n1 * Qmax, ldz, d, B, lbt, n2, Qmax, SA, ldsa, scale, hb);
   return check_launch("srht two pass");
 }
 

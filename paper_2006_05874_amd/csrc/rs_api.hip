@@ -2,6 +2,8 @@
 // adaptive controller (Algorithm 1).  Every numeric step runs in the kernels.
 #include <cstdio>
 #include <cstring>
+#include <iterator>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -139,10 +141,18 @@ struct DeviceScratch {
   DevBuf sa_tmp, colmax, sa_scale;
   // learned form: probe sketch and its factor, probe sums, features
   DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
+  // nu grid: per-slot state, candidate blocks, multi-RHS products, batched
+  // factors, uploads, and the per-level sketch / Gram cache
+  DevBuf g_vec, g_ctl, g_ev, g_hinv, g_rpart, g_xc, g_gc, g_gtc, g_nu2, g_up, g_R, g_Gp, g_M, g_L,
+      g_Cw;
+  std::vector<std::unique_ptr<DevBuf>> lv_sa, lv_scale, lv_gram;
+  void* g_pinned = nullptr;
+  size_t g_pinned_bytes = 0;
   void* host_pinned = nullptr;
   hipEvent_t done_ev = nullptr;
   DeviceScratch() = default;
   ~DeviceScratch() {
+    if (g_pinned) (void)hipHostFree(g_pinned);
     if (host_pinned) (void)hipHostFree(host_pinned);
     if (done_ev) (void)hipEventDestroy(done_ev);
   }
@@ -356,7 +366,7 @@ rs_status rs_sketch_srht(const void* A, rs_dtype a_t, int64_t n, int64_t d, int6
   if (sa_t == RS_FP8E4M3 && !sa_col_scale)
     return set_error(RS_ERR_ARG, "rs_sketch_srht: FP8 output needs sa_col_scale");
   const int64_t npad = next_pow2(n);
-  if (npad > (int64_t)1 << 20) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: padded n above 2^20");
+  if (npad > (int64_t)1 << 22) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: padded n above 2^22");
   if (m < 1 || m > npad) return set_error(RS_ERR_SHAPE, "rs_sketch_srht: need 1 <= m <= padded n");
   if (ldsa < d) return set_error(RS_ERR_ARG, "rs_sketch_srht: ldsa < d");
   DeviceScratch* S = scratch_for_current();
@@ -553,6 +563,54 @@ void rs_solve_opts_default(rs_solve_opts* o) {
 
 namespace rs {
 
+// The info record of one run.  Event log: the doublings recorded at step t come
+// before the step accepted at t; kinds[t] is the accepted candidate of step t.
+static void fill_info(rs_solve_info* info, rs_status result, const DevCtl& h,
+                      const int32_t* kinds, int64_t nkinds, const std::vector<int32_t>& dbl_t,
+                      const std::vector<int64_t>& dbl_m, int64_t m_start, int64_t m_final,
+                      int64_t applies) {
+  const int64_t tfin = h.t;
+  int64_t ne = 0;
+  size_t di = 0;
+  int64_t m_now = m_start;
+  auto push = [&](int kind, int64_t t, int64_t mm) {
+    if (ne < RS_MAX_EVENTS) {
+      info->event_kind[ne] = kind;
+      info->event_t[ne] = (int32_t)t;
+      info->event_m[ne] = mm;
+    }
+    ++ne;
+  };
+  for (int64_t t = 1; t <= tfin; ++t) {
+    while (di < dbl_t.size() && dbl_t[di] == t) {
+      m_now = dbl_m[di];
+      push(RS_EVENT_DOUBLE, t, m_now);
+      ++di;
+    }
+    if (t < tfin && t < nkinds && kinds[t] >= 0)
+      push(kinds[t] == 0 ? RS_EVENT_POLYAK : RS_EVENT_GD, t, m_now);
+  }
+  info->status = result;
+  info->m_final = m_final;
+  info->doublings = (int64_t)dbl_t.size();
+  info->steps = h.steps;
+  info->grad_passes = h.passes;
+  info->applies = applies + h.passes;
+  info->accepted_polyak = h.polyak;
+  info->accepted_gd = h.gd;
+  info->r_final = h.r_t;
+  info->r_ref = h.r_ref;
+  info->n_events = std::min<int64_t>(ne, RS_MAX_EVENTS);
+}
+
+static rs_status ctl_result(int status) {
+  if (status == RS_CTL_CONVERGED) return RS_OK;
+  if (status == RS_CTL_NONFINITE)
+    return set_error(RS_ERR_NONFINITE, "solve: non-finite decrement");
+  return set_error(RS_ERR_NO_CONVERGENCE, status == RS_CTL_STUCK ? "solve: no progress at m_max"
+                                                                 : "solve: max_iter reached");
+}
+
 // One run of Algorithm 1 as a resumable job: start() enqueues the first sketch,
 // factor and g_1; every later advance() is called once the previous batch of
 // device work has finished (its event completed), reads the control record and
@@ -605,8 +663,8 @@ struct SolveJob {
     RS_TRY(rs_params(o.kind, o.rho, o.eta, &prm));
     srht = o.kind == RS_SKETCH_SRHT;
     const int64_t npad = next_pow2(n);
-    if (srht && npad > (int64_t)1 << 20)
-      return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: SRHT padded n above 2^20");
+    if (srht && npad > (int64_t)1 << 22)
+      return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: SRHT padded n above 2^22");
     m_cap = srht ? npad : n;
     if (o.m_max > 0) m_cap = std::min<int64_t>(m_cap, o.m_max);
     m = std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap);
@@ -732,7 +790,6 @@ struct SolveJob {
     return conclude();
   }
 
-  // event log: doublings at step t come before the step accepted at t
   rs_status conclude() {
     done = true;
     const int64_t tfin = h.t;
@@ -743,37 +800,8 @@ struct SolveJob {
                             hipMemcpyDeviceToHost, stream));
       RS_HIP(hipStreamSynchronize(stream));
     }
-    int64_t ne = 0;
-    size_t di = 0;
-    int64_t m_now = std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap);
-    auto push = [&](int kind, int64_t t, int64_t mm) {
-      if (ne < RS_MAX_EVENTS) {
-        info->event_kind[ne] = kind;
-        info->event_t[ne] = (int32_t)t;
-        info->event_m[ne] = mm;
-      }
-      ++ne;
-    };
-    for (int64_t t = 1; t <= tfin; ++t) {
-      while (di < dbl_t.size() && dbl_t[di] == t) {
-        m_now = dbl_m[di];
-        push(RS_EVENT_DOUBLE, t, m_now);
-        ++di;
-      }
-      if (t < tfin && t < (int64_t)kinds.size() && kinds[t] >= 0)
-        push(kinds[t] == 0 ? RS_EVENT_POLYAK : RS_EVENT_GD, t, m_now);
-    }
-    info->status = result;
-    info->m_final = m;
-    info->doublings = (int64_t)dbl_t.size();
-    info->steps = h.steps;
-    info->grad_passes = h.passes;
-    info->applies = applies + h.passes;
-    info->accepted_polyak = h.polyak;
-    info->accepted_gd = h.gd;
-    info->r_final = h.r_t;
-    info->r_ref = h.r_ref;
-    info->n_events = std::min<int64_t>(ne, RS_MAX_EVENTS);
+    fill_info(info, result, h, kinds.data(), (int64_t)kinds.size(), dbl_t, dbl_m,
+              std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap), m, applies);
     return result;
   }
 };
@@ -883,6 +911,333 @@ rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_
 
 }  // extern "C"
 
+
+// ==================================================================== nu grid
+namespace rs {
+
+// Algorithm 1 for count values of nu^2 on one (A, b).  Level L of the doubling
+// ladder has m_L = min(m_init 2^L, m_cap) rows and sketch_id L (fresh) or 0
+// (nested): exactly the sketch a single solve at that level draws, shared here by
+// every nu at that level together with its Gram partial products.  Each round
+// the host reads the control records of all nu, refactors the ones that asked
+// for a larger sketch (one batched factor launch per level), and queues
+// check_every steps for the whole list: per step one candidate launch, one
+// multi-RHS gradient (both candidates of every listed nu), one apply and one
+// decision launch.  Slots that are not running skip their share on the device.
+struct NuGrid {
+  SolveJob base;  // argument checks and derived sizes (nu of slot 0)
+  const double* nu2h = nullptr;
+  int64_t count = 0;
+  double* X = nullptr;
+  rs_solve_info* infos = nullptr;
+  DeviceScratch* S = nullptr;
+  hipStream_t s = nullptr;
+  int64_t pp_max = 0;
+  std::vector<int64_t> m_lv;             // m of each level
+  std::vector<int> lvl;                  // level of each slot
+  std::vector<std::vector<int32_t>> dbl_t;
+  std::vector<std::vector<int64_t>> dbl_m;
+  std::vector<int64_t> applies;
+  std::vector<DevCtl> h;
+  std::vector<char> finished;
+  std::vector<int> at_cap;
+  GridPtrs P{};
+  // uploads: bump allocation in the pinned staging area and the device mirror
+  size_t up_off = 0, up_cap = 0;
+  char* up_host = nullptr;
+
+  int64_t level_m(int L) {
+    while ((int)m_lv.size() <= L) {
+      const int64_t prev = m_lv.empty() ? base.m : std::min<int64_t>(2 * m_lv.back(), base.m_cap);
+      m_lv.push_back(prev);
+    }
+    return m_lv[L];
+  }
+
+  template <typename V>
+  rs_status upload(const V* src, size_t n, const V** dev) {
+    const size_t bytes = (n * sizeof(V) + 255) / 256 * 256;
+    if (up_off + bytes > up_cap) return set_error(RS_ERR_ARG, "nu grid: upload area exhausted");
+    std::memcpy(up_host + up_off, src, n * sizeof(V));
+    char* d = reinterpret_cast<char*>(S->g_up.p) + up_off;
+    RS_HIP(hipMemcpyAsync(d, up_host + up_off, n * sizeof(V), hipMemcpyHostToDevice, s));
+    *dev = reinterpret_cast<const V*>(d);
+    up_off += bytes;
+    return RS_OK;
+  }
+
+  rs_status ensure_level(int L) {
+    const int64_t mL = level_m(L);
+    while ((int)S->lv_sa.size() <= L) {
+      S->lv_sa.emplace_back(new DevBuf());
+      S->lv_scale.emplace_back(new DevBuf());
+      S->lv_gram.emplace_back(new DevBuf());
+    }
+    DevBuf& sa = *S->lv_sa[L];
+    DevBuf& sc = *S->lv_scale[L];
+    DevBuf& gr = *S->lv_gram[L];
+    RS_TRY(sa.ensure((size_t)mL * base.ldsa * base.sa_es));
+    RS_TRY(sc.ensure((size_t)base.d * sizeof(float)));
+    RS_TRY(gr.ensure(factor_bytes_gram(mL, base.d, base.sa_t)));
+    const uint32_t sid = base.o.resample == RS_RESAMPLE_FRESH ? (uint32_t)L : 0u;
+    float* scl = base.sa_t == RS_FP8E4M3 ? sc.as<float>() : nullptr;
+    if (base.srht)
+      RS_TRY(srht_run(*S, base.A, base.a_t, base.n, base.d, base.lda, mL, base.o.seed, sid, sa.p,
+                      base.sa_t, base.ldsa, scl, nullptr, nullptr, s));
+    else
+      RS_TRY(gauss_run(*S, base.A, base.a_t, base.n, base.d, base.lda, mL, base.o.seed, sid, sa.p,
+                       base.sa_t, base.ldsa, scl, s));
+    FactorBuffers FB{nullptr, nullptr, nullptr, nullptr, nullptr, gr.p, gr.bytes};
+    return gram_partials(FB, sa.p, base.sa_t, scl, mL, base.d, base.ldsa, s);
+  }
+
+  // shifted factors of level L for the given slots, in batches that fit the scratch
+  rs_status factor_level(int L, const std::vector<int>& slots) {
+    const int64_t mL = level_m(L), d = base.d;
+    const int64_t p = mL < d ? mL : d;
+    const int64_t pp = (p + 63) / 64 * 64, dp = base.dp;
+    const bool wood = mL < d;
+    const size_t per = (size_t)pp * pp * 16 + (wood ? (size_t)pp * dp * 8 : 0);
+    const size_t cap_bytes = (size_t)4 << 30;
+    const int64_t bmax = std::max<int64_t>(1, (int64_t)(cap_bytes / per));
+    float* scl = base.sa_t == RS_FP8E4M3 ? S->lv_scale[L]->as<float>() : nullptr;
+    for (size_t i0 = 0; i0 < slots.size(); i0 += (size_t)bmax) {
+      const int B = (int)std::min<size_t>(slots.size() - i0, (size_t)bmax);
+      RS_TRY(S->g_M.ensure((size_t)B * pp * pp * 8));
+      RS_TRY(S->g_L.ensure((size_t)B * pp * pp * 8));
+      if (wood) RS_TRY(S->g_Cw.ensure((size_t)B * pp * dp * 8));
+      std::vector<double> nu(B);
+      std::vector<int> hz(B);
+      for (int j = 0; j < B; ++j) {
+        hz[j] = slots[i0 + j];
+        nu[j] = nu2h[hz[j]];
+      }
+      const double* nud;
+      const int* hzd;
+      RS_TRY(upload(nu.data(), (size_t)B, &nud));
+      RS_TRY(upload(hz.data(), (size_t)B, &hzd));
+      DevBuf& gr = *S->lv_gram[L];
+      FactorBuffers FB{S->g_M.as<double>(), S->g_L.as<double>(), S->g_hinv.as<double>(),
+                       S->g_Cw.as<double>(), S->info.as<int>(), gr.p, gr.bytes};
+      FactorBatch zb;
+      zb.sM = pp * pp;
+      zb.sL = pp * pp;
+      zb.sH = dp * dp;
+      zb.sC = pp * dp;
+      zb.nu2 = nud;
+      zb.hz = hzd;
+      RS_TRY(factor_finish(FB, S->lv_sa[L]->p, base.sa_t, scl, mL, d, base.ldsa, 0.0, B, zb, s));
+    }
+    return RS_OK;
+  }
+
+  rs_status gradient(const double* Xsrc, int64_t Kc, int kper, const int* zl) {
+    if (base.a_t == RS_F32)
+      return mr_gradient<float>(reinterpret_cast<const float*>(base.A), base.n, base.d, base.lda,
+                                reinterpret_cast<const float*>(base.b), Xsrc, Kc, kper,
+                                S->g_nu2.as<double>(), zl, S->g_R.as<float>(), ldr(),
+                                S->g_Gp.as<double>(), S->g_gc.as<double>(), s);
+    return mr_gradient<double>(reinterpret_cast<const double*>(base.A), base.n, base.d, base.lda,
+                               reinterpret_cast<const double*>(base.b), Xsrc, Kc, kper,
+                               S->g_nu2.as<double>(), zl, S->g_R.as<double>(), ldr(),
+                               S->g_Gp.as<double>(), S->g_gc.as<double>(), s);
+  }
+  int64_t ldr() const { return (2 * count + 3) / 4 * 4; }
+
+  rs_status read_ctl() {
+    RS_HIP(hipMemcpyAsync(S->g_pinned, S->g_ctl.p, (size_t)count * sizeof(DevCtl),
+                          hipMemcpyDeviceToHost, s));
+    RS_HIP(hipMemcpyAsync((char*)S->g_pinned + count * sizeof(DevCtl), S->info.p, sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    RS_HIP(hipEventRecord(S->done_ev, s));
+    RS_HIP(hipEventSynchronize(S->done_ev));
+    std::memcpy(h.data(), S->g_pinned, (size_t)count * sizeof(DevCtl));
+    int bad = 0;
+    std::memcpy(&bad, (char*)S->g_pinned + count * sizeof(DevCtl), sizeof(int));
+    if (bad) return set_error(RS_ERR_NOT_SPD, "rs_solve_nu_grid: sketched Hessian factor failed");
+    up_off = 0;
+    return RS_OK;
+  }
+
+  rs_status setup() {
+    const int64_t d = base.d, dp = base.dp;
+    const int64_t es = base.a_t == RS_F32 ? 4 : 8;
+    RS_TRY(S->g_vec.ensure((size_t)count * 4 * d * 8));
+    RS_TRY(S->g_ctl.ensure((size_t)count * sizeof(DevCtl)));
+    RS_TRY(S->g_ev.ensure((size_t)count * base.ev_cap * 4));
+    RS_TRY(S->g_hinv.ensure((size_t)count * dp * dp * 8));
+    RS_TRY(S->g_rpart.ensure((size_t)count * base.nrp * 2 * 8));
+    RS_TRY(S->g_xc.ensure((size_t)count * 2 * d * 8));
+    RS_TRY(S->g_gc.ensure((size_t)count * 2 * d * 8));
+    RS_TRY(S->g_gtc.ensure((size_t)count * 2 * d * 8));
+    RS_TRY(S->g_nu2.ensure((size_t)count * 8));
+    RS_TRY(S->g_R.ensure((size_t)base.n * ldr() * es));
+    int64_t rps = 0;
+    const int ns = mr_splits(base.n, d, 1, rps);
+    RS_TRY(S->g_Gp.ensure((size_t)ns * d * ldr() * 8));
+    RS_TRY(S->info.ensure(sizeof(int), true));
+    up_cap = (size_t)64 * count + 65536;
+    RS_TRY(S->g_up.ensure(up_cap));
+    const size_t pin = (size_t)count * sizeof(DevCtl) + 256 + up_cap;
+    if (S->g_pinned_bytes < pin) {
+      if (S->g_pinned) RS_HIP(hipHostFree(S->g_pinned));
+      S->g_pinned = nullptr;
+      S->g_pinned_bytes = 0;
+      RS_HIP(hipHostMalloc(&S->g_pinned, pin, hipHostMallocDefault));
+      S->g_pinned_bytes = pin;
+    }
+    up_host = (char*)S->g_pinned + count * sizeof(DevCtl) + 256;
+    if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
+    RS_HIP(hipMemcpyAsync(S->g_nu2.p, nu2h, (size_t)count * 8, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemsetAsync(S->info.p, 0, sizeof(int), s));
+    P.x = X;
+    P.vec = S->g_vec.as<double>();
+    P.ctl = S->g_ctl.as<DevCtl>();
+    P.ev = S->g_ev.as<int32_t>();
+    P.ev_cap = base.ev_cap;
+    P.Hinv = S->g_hinv.as<double>();
+    P.sH = dp * dp;
+    P.ldh = dp;
+    P.rpart = S->g_rpart.as<double>();
+    P.nrp = base.nrp;
+    P.Xc = S->g_xc.as<double>();
+    P.Gc = S->g_gc.as<double>();
+    P.GTc = S->g_gtc.as<double>();
+    lvl.assign(count, 0);
+    dbl_t.assign(count, {});
+    dbl_m.assign(count, {});
+    applies.assign(count, 1);
+    h.assign(count, DevCtl{});
+    finished.assign(count, 0);
+    at_cap.assign(count, base.m == base.m_cap ? 1 : 0);
+    return RS_OK;
+  }
+
+  rs_status run() {
+    RS_TRY(setup());
+    const int64_t d = base.d;
+    const int K = base.K;
+    // level 0 for everyone: sketch, Gram, factors, g_1, gtilde_1, r_1
+    std::vector<int> all(count);
+    for (int64_t z = 0; z < count; ++z) all[z] = (int)z;
+    RS_TRY(ensure_level(0));
+    RS_TRY(factor_level(0, all));
+    const int* zl;
+    const int* capd;
+    RS_TRY(upload(all.data(), all.size(), &zl));
+    RS_TRY(upload(at_cap.data(), at_cap.size(), &capd));
+    P.zl = zl;
+    RS_TRY(grid_pack(P, (int)count, d, 0, s));
+    RS_TRY(gradient(P.Xc, count, 1, zl));
+    RS_TRY(grid_apply(P, (int)count, 1, d, P.Gc, 1, s));
+    RS_TRY(grid_init(P, (int)count, base.o.tol, base.o.max_iter, d, capd, s));
+    const DecideParams dpar{base.prm.mu_p, base.prm.beta_p, base.prm.mu_gd, base.prm.cbar_p,
+                            base.prm.cbar_gd, base.o.tol, base.o.max_iter};
+    for (;;) {
+      RS_TRY(read_ctl());
+      std::vector<int> run_list, dbl;
+      for (int64_t z = 0; z < count; ++z) {
+        if (h[z].status == RS_CTL_RUNNING) run_list.push_back((int)z);
+        else if (h[z].status == RS_CTL_DOUBLE) dbl.push_back((int)z);
+      }
+      if (run_list.empty() && dbl.empty()) break;
+      if (!dbl.empty()) {
+        // group the doublings by their new level
+        std::vector<std::vector<int>> by_level;
+        for (int z : dbl) {
+          const int L = ++lvl[z];
+          const int64_t mL = level_m(L);
+          dbl_t[z].push_back((int32_t)h[z].t);
+          dbl_m[z].push_back(mL);
+          applies[z] += 1;
+          at_cap[z] = mL == base.m_cap ? 1 : 0;
+          if ((int)by_level.size() <= L) by_level.resize(L + 1);
+          by_level[L].push_back(z);
+        }
+        for (int L = 0; L < (int)by_level.size(); ++L) {
+          if (by_level[L].empty()) continue;
+          if (built.size() <= (size_t)L || !built[L]) {
+            RS_TRY(ensure_level(L));
+            if (built.size() <= (size_t)L) built.resize(L + 1, 0);
+            built[L] = 1;
+          }
+          RS_TRY(factor_level(L, by_level[L]));
+        }
+        const int* dz;
+        RS_TRY(upload(dbl.data(), dbl.size(), &dz));
+        RS_TRY(upload(at_cap.data(), at_cap.size(), &capd));
+        GridPtrs Q = P;
+        Q.zl = dz;
+        RS_TRY(grid_pack(Q, (int)dbl.size(), d, 1, s));
+        RS_TRY(grid_apply(Q, (int)dbl.size(), 2, d, Q.Xc, 1, s));
+        RS_TRY(grid_post_resample(Q, (int)dbl.size(), base.o.tol, d, capd, s));
+      }
+      // queue steps for every slot that may run
+      std::vector<int> lst;
+      lst.reserve(run_list.size() + dbl.size());
+      std::merge(run_list.begin(), run_list.end(), dbl.begin(), dbl.end(),
+                 std::back_inserter(lst));
+      const int* sz;
+      RS_TRY(upload(lst.data(), lst.size(), &sz));
+      GridPtrs Q = P;
+      Q.zl = sz;
+      const int nl = (int)lst.size();
+      for (int it = 0; it < base.check_every; ++it) {
+        RS_TRY(grid_candidates(Q, nl, K, d, base.prm.mu_p, base.prm.beta_p, base.prm.mu_gd, s));
+        RS_TRY(gradient(Q.Xc, (int64_t)nl * K, K, sz));
+        RS_TRY(grid_apply(Q, nl, K, d, Q.Gc, 0, s));
+        RS_TRY(grid_decide(Q, nl, K, dpar, d, s));
+      }
+    }
+    // event logs and info records
+    std::vector<int32_t> kinds((size_t)count * base.ev_cap);
+    RS_HIP(hipMemcpyAsync(kinds.data(), S->g_ev.p, kinds.size() * 4, hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    rs_status first = RS_OK;
+    for (int64_t z = 0; z < count; ++z) {
+      std::memset(&infos[z], 0, sizeof(rs_solve_info));
+      const rs_status r = ctl_result(h[z].status);
+      if (r != RS_OK && r != RS_ERR_NO_CONVERGENCE && first == RS_OK) first = r;
+      fill_info(&infos[z], r, h[z], kinds.data() + z * base.ev_cap, base.ev_cap, dbl_t[z],
+                dbl_m[z], level_m(0), level_m(lvl[z]), applies[z]);
+    }
+    return first;
+  }
+  std::vector<char> built{1};
+};
+
+}  // namespace rs
+
+extern "C" {
+
+rs_status rs_solve_nu_grid(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                           const void* b, const double* nu2, int64_t count,
+                           const rs_solve_opts* opts, double* X, rs_solve_info* infos,
+                           hipStream_t stream) {
+  if (!opts || !nu2 || !X || !infos) return set_error(RS_ERR_ARG, "rs_solve_nu_grid: null argument");
+  if (count < 1 || count > 4096) return set_error(RS_ERR_ARG, "rs_solve_nu_grid: count in 1..4096");
+  for (int64_t k = 0; k < count; ++k)
+    if (!(nu2[k] > 0.0) || !std::isfinite(nu2[k]))
+      return set_error(RS_ERR_NOT_SPD, "rs_solve_nu_grid: every nu^2 must be positive");
+  NuGrid G;
+  SolveJob& J = G.base;
+  J.A = A; J.a_t = a_t; J.n = n; J.d = d; J.lda = lda; J.b = b; J.nu2 = nu2[0]; J.x = X;
+  J.o = *opts; J.info = infos; J.stream = stream;
+  RS_TRY(J.validate());
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  G.nu2h = nu2;
+  G.count = count;
+  G.X = X;
+  G.infos = infos;
+  G.S = S;
+  G.s = stream;
+  // levels are rebuilt for every call (the sketch depends on A)
+  return G.run();
+}
+
+}  // extern "C"
+
 // ==================================================================== learned form
 extern "C" {
 
@@ -893,7 +1248,7 @@ rs_status rs_features(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
   if (d > 8192) return set_error(RS_ERR_UNSUPPORTED, "rs_features: d above 8192");
   if (!(nu2 > 0.0)) return set_error(RS_ERR_NOT_SPD, "rs_features: nu^2 must be positive");
   const int64_t npad = next_pow2(n);
-  if (npad > (int64_t)1 << 20) return set_error(RS_ERR_SHAPE, "rs_features: padded n above 2^20");
+  if (npad > (int64_t)1 << 22) return set_error(RS_ERR_SHAPE, "rs_features: padded n above 2^22");
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> g(S->mu);
   const int64_t m0 = std::min<int64_t>(256, npad);

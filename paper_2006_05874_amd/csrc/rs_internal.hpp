@@ -62,6 +62,20 @@ struct FactorBuffers {
 rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
                        hipStream_t s);
+// Batched factors of one Gram with several shifts: members z = 0..B-1 are laid
+// out at element strides sM (M), sL (Linv), sH (Hinv), sC (Cw); nu2[z] on the
+// device (null: the scalar shift, B = 1).
+struct FactorBatch {
+  int64_t sM = 0, sL = 0, sH = 0, sC = 0;
+  const double* nu2 = nullptr;
+  const int* hz = nullptr;  // device: Hinv slot of member z (null: z itself)
+};
+int gram_partial_count(int64_t m, int64_t d);
+rs_status gram_partials(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, hipStream_t s);
+rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
+                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
+                        int B, FactorBatch zb, hipStream_t s);
 
 // ---------------------------------------------------------------- FP8 storage
 rs_status quantize_fp8(const float* X, int64_t m, int64_t d, int64_t ldx, uint32_t* colmax,
@@ -121,6 +135,43 @@ rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double to
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
                                const double* GT, double* gt, int at_cap, hipStream_t s);
 rs_status pack2_launch(int64_t d, const double* a, const double* b, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- nu grid
+struct DecideParams {
+  double mu_p, beta_p, mu_gd, cbar_p, cbar_gd, tol;
+  int64_t max_iter;
+};
+struct GridPtrs {
+  double* x;          // slot z: x at x + z d
+  double* vec;        // slot z: x_prev, g, gtilde, g_ref at vec + z 4d
+  DevCtl* ctl;        // slot z: ctl[z]
+  int32_t* ev;        // slot z: ev + z ev_cap
+  int ev_cap;
+  const double* Hinv; // slot z: Hinv + z sH, leading dimension ldh
+  int64_t sH, ldh;
+  double* rpart;      // slot z: rpart + z nrp 2
+  int nrp;
+  double* Xc;         // list entry y: Xc / Gc / GTc + y K d
+  double* Gc;
+  double* GTc;
+  const int* zl;      // list entry y -> slot
+};
+int mr_splits(int64_t n, int64_t d, int64_t Kc, int64_t& rows_per_split);
+template <typename T>
+rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
+                      int64_t Kc, int kper, const double* nu2, const int* zl, T* R, int64_t ldr,
+                      double* Gp, double* G, hipStream_t s);
+rs_status grid_candidates(const GridPtrs& P, int nl, int K, int64_t d, double mu_p, double beta_p,
+                          double mu_gd, hipStream_t s);
+rs_status grid_pack(const GridPtrs& P, int nl, int64_t d, int what, hipStream_t s);
+rs_status grid_apply(const GridPtrs& P, int nl, int K, int64_t d, const double* Gsrc, int always,
+                     hipStream_t s);
+rs_status grid_decide(const GridPtrs& P, int nl, int K, const DecideParams& a, int64_t d,
+                      hipStream_t s);
+rs_status grid_init(const GridPtrs& P, int nl, double tol, int64_t max_iter, int64_t d,
+                    const int* at_cap, hipStream_t s);
+rs_status grid_post_resample(const GridPtrs& P, int nl, double tol, int64_t d, const int* at_cap,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- learned form
 int feature_chunks(int64_t n);

@@ -158,8 +158,9 @@ def load_model(path=MODEL_PATH):
     return dev(z["params"]), dev(z["mu"]), dev(z["sd"]), json.loads(str(z["meta"]))
 
 
-def evaluate(model_path, count, first, out, log_every=20):
-    """Held-out problems: plain (m from 1) vs learned start, same solver otherwise.
+def evaluate(model_path, count, first, out, offsets=(0.0,), log_every=50):
+    """Held-out problems: plain (m from 1, FP32 sketch) against the learned start
+    with each bias offset (added to the output bias: m_init = 2^floor(y + off)).
     Records each solve's time, final m, passes and status."""
     import torch
     from . import rs
@@ -169,15 +170,19 @@ def evaluate(model_path, count, first, out, log_every=20):
         spec = problem_spec(p)
         A, b = make_device_problem(spec)
         res = {**spec}
-        for mode in ("plain", "learned"):
+        for mode in ["plain"] + [f"learned{o:+.2f}" for o in offsets]:
+            th = params
+            if mode != "plain":
+                th = params.clone()
+                th[OFF_B3] += float(mode[len("learned"):])
             torch.cuda.synchronize()
             t1 = time.time()
             if mode == "plain":
                 x, info = rs.rs_adaptive_solve(A, b, spec["nu2"], seed=spec["seed"],
                                                raise_on_error=False)
             else:
-                x, info = rs.rs_learned_solve(A, b, spec["nu2"], params, mu, sd,
-                                              seed=spec["seed"], raise_on_error=False)
+                x, info = rs.rs_learned_solve(A, b, spec["nu2"], th, mu, sd, seed=spec["seed"],
+                                              raise_on_error=False)
             torch.cuda.synchronize()
             res[mode] = {"s": time.time() - t1, "m_final": info["m_final"],
                          "passes": info["grad_passes"], "status": info["status"],
@@ -186,9 +191,28 @@ def evaluate(model_path, count, first, out, log_every=20):
         del A, b
         if (p - first + 1) % log_every == 0:
             print(f"[evaluate] {p - first + 1}/{count}", flush=True)
+    summary = summarize(rows)
     with open(out, "w") as f:
-        json.dump(rows, f)
-    return rows
+        json.dump({"summary": summary, "rows": rows}, f)
+    return rows, summary
+
+
+def summarize(rows):
+    modes = [k for k in rows[0] if k == "plain" or k.startswith("learned")]
+    out = {}
+    for k in modes:
+        t = np.array([r[k]["s"] for r in rows])
+        out[k] = {"total_s": float(t.sum()), "median_s": float(np.median(t)),
+                  "mean_doublings": float(np.mean([r[k]["doublings"] for r in rows])),
+                  "mean_passes": float(np.mean([r[k]["passes"] for r in rows])),
+                  "not_ok": int(sum(r[k]["status"] != "ok" for r in rows))}
+    base = out["plain"]["total_s"]
+    for k in modes:
+        out[k]["speedup_total"] = base / out[k]["total_s"]
+    return out
+
+
+OFF_B3 = 18816
 
 
 def main():
@@ -206,7 +230,12 @@ def main():
     e.add_argument("--model", default=MODEL_PATH)
     e.add_argument("--count", type=int, default=200)
     e.add_argument("--first", type=int, default=10 ** 5)
+    e.add_argument("--offsets", type=float, nargs="+", default=[0.0])
     e.add_argument("--out", required=True)
+    f = sub.add_parser("finalize", help="fold the chosen offset into the output bias")
+    f.add_argument("--model", required=True)
+    f.add_argument("--eval", required=True)
+    f.add_argument("--out", default=MODEL_PATH)
     a = ap.parse_args()
     if a.cmd == "generate":
         generate(a.count, a.first, a.out)
@@ -216,8 +245,22 @@ def main():
         save_model(a.out, params, mu, sd, {"problems": int(len(L)), "history": hist,
                                            "data": [os.path.basename(x) for x in a.data]})
         print(f"saved {a.out}", flush=True)
+    elif a.cmd == "evaluate":
+        _, summary = evaluate(a.model, a.count, a.first, a.out, offsets=a.offsets)
+        print(json.dumps(summary, indent=1), flush=True)
     else:
-        evaluate(a.model, a.count, a.first, a.out)
+        summary = json.load(open(a.eval))["summary"]
+        best = max((k for k in summary if k.startswith("learned")),
+                   key=lambda k: summary[k]["speedup_total"])
+        off = float(best[len("learned"):])
+        z = np.load(a.model, allow_pickle=False)
+        params = z["params"].copy()
+        params[OFF_B3] += off
+        meta = json.loads(str(z["meta"]))
+        meta["output_offset"] = off
+        meta["evaluation"] = summary
+        save_model(a.out, params, z["mu"], z["sd"], meta)
+        print(f"offset {off:+.2f} -> {a.out}", flush=True)
 
 
 if __name__ == "__main__":

@@ -77,7 +77,8 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_factor_apply", "rs_factor_destroy", "rs_gradient", "rs_ihs_step",
            "rs_solve_opts_default", "rs_adaptive_solve", "rs_last_error", "rs_version",
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
-           "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch"]
+           "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
+           "rs_solve_nu_grid"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -130,12 +131,15 @@ def load(path=LIB_PATH):
                                    ctypes.POINTER(i64), vp]
     L.rs_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), ctypes.c_int32, vp]
+    L.rs_solve_nu_grid.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
+                                   ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
     L.rs_last_error.restype = ctypes.c_char_p
     L.rs_version.restype = ctypes.c_char_p
     for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
                  "rs_factor_apply", "rs_gradient", "rs_ihs_step", "rs_adaptive_solve",
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
-                 "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch"]:
+                 "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
+                 "rs_solve_nu_grid"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -354,6 +358,27 @@ def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
         _check(st, "rs_solve_batch")
     return [(xs[i], _info(infos[i], infos[i].status, False, "rs_solve_batch"))
             for i in range(len(problems))]
+
+
+def rs_solve_nu_grid(A, b, nu2s, kind="srht", variant="polyak", resample="fresh",
+                     sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
+                     max_iter=200, seed=0, check_every=4, X0=None, raise_on_error=True):
+    """Solve for every nu^2 in ``nu2s`` on one (A, b).  Returns (X, infos) with X
+    a (len(nu2s), d) float64 tensor of solutions."""
+    a_t = _mat(A, "rs_solve_nu_grid")
+    n, d = A.shape
+    k = len(nu2s)
+    o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
+              seed, check_every)
+    X = (torch.zeros(k, d, dtype=torch.float64, device=A.device) if X0 is None
+         else X0.to(torch.float64).contiguous().clone())
+    nu = (ctypes.c_double * k)(*[float(v) for v in nu2s])
+    infos = (SolveInfo * k)()
+    st = load().rs_solve_nu_grid(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu, k,
+                                 ctypes.byref(o), _ptr(X), infos, _stream())
+    if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
+        _check(st, "rs_solve_nu_grid")
+    return X, [_info(infos[i], infos[i].status, False, "rs_solve_nu_grid") for i in range(k)]
 
 
 def _info(info, st, raise_on_error, where):

@@ -6,7 +6,9 @@ polynomial singular-value decays): A = G diag(sigma) V^T with G i.i.d.
 N(0, 1/n) and V Haar-distributed, b = A x_pl + c * xi.
 """
 from .problems import (Problem, make_problem, spectrum, config_c1, config_c2,
-                       config_c4b_specs, make_c4b_problem, make_problem_torch)
+                       config_c4b_specs, make_c4b_problem, make_problem_torch,
+                       config_c4a_nu2, make_c4a_problem)
 
 __all__ = ["Problem", "make_problem", "spectrum", "config_c1", "config_c2",
-           "config_c4b_specs", "make_c4b_problem", "make_problem_torch"]
+           "config_c4b_specs", "make_c4b_problem", "make_problem_torch",
+           "config_c4a_nu2", "make_c4a_problem"]

@@ -114,3 +114,16 @@ def make_c4b_problem(spec, device, dtype=None):
     """Device tensors (A, b) for one config_c4b_specs entry."""
     return make_problem_torch(spec["n"], spec["d"], spectrum("geom", spec["d"], 0.95), 0.1,
                               spec["seed"], device, dtype=dtype)[:2]
+
+
+C4A_N, C4A_D = 1 << 18, 2048
+
+
+def config_c4a_nu2(count=64):
+    """nu^2 grid of the shared-A problem: log-spaced in [1e-6, 1] sigma_1^2."""
+    return np.logspace(-6.0, 0.0, count)
+
+
+def make_c4a_problem(device, dtype=None, n=C4A_N, d=C4A_D, seed=41):
+    """Shared A for the nu grid: sigma_i = i^-0.8 (sigma_1 = 1), noise 0.1."""
+    return make_problem_torch(n, d, spectrum("poly", d, 0.8), 0.1, seed, device, dtype=dtype)[:2]

@@ -127,3 +127,41 @@ def test_learned_solve_falls_back_to_the_adaptive_rule(rs, bias):
     assert info["m_init"] == expect and info["status"] == "ok"
     xs = ridge.solve_direct(p.A, p.b, p.nu2)
     assert ridge.relative_error(ridge.hessian(p.A, p.nu2), host(x), xs) <= 1e-6
+
+
+def test_trained_model_gains_over_plain(rs):
+    # held-out problems of the training distribution (indices never generated for
+    # training): the committed predictor must skip most of the doubling ladder and
+    # cut the total solve time, while every solve still meets its stopping rule;
+    # the three smallest problems are checked against the oracle's solution
+    from paper_2006_05874_amd import learned as L
+    params, mu, sd, meta = L.load_model()
+    assert meta["problems"] >= 20000
+    plain_t = learned_t = 0.0
+    plain_dbl, learned_dbl = [], []
+    specs = [L.problem_spec(p) for p in range(2 * 10 ** 5, 2 * 10 ** 5 + 40)]
+    small = sorted(range(len(specs)), key=lambda i: specs[i]["n"] * specs[i]["d"])[:3]
+    import time
+    for i, spec in enumerate(specs):
+        A, b = L.make_device_problem(spec)
+        rs.rs_adaptive_solve(A, b, spec["nu2"], seed=spec["seed"])      # warm allocations
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ip = rs.rs_adaptive_solve(A, b, spec["nu2"], seed=spec["seed"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, il = rs.rs_learned_solve(A, b, spec["nu2"], params, mu, sd, seed=spec["seed"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plain_t += t1 - t0
+        learned_t += t2 - t1
+        assert ip["status"] == "ok" and il["status"] == "ok"
+        plain_dbl.append(ip["doublings"])
+        learned_dbl.append(il["doublings"])
+        if i in small:
+            A64 = host(A).astype(np.float64)
+            b64 = host(b).astype(np.float64)
+            xs = ridge.solve_direct(A64, b64, spec["nu2"])
+            assert ridge.relative_error(ridge.hessian(A64, spec["nu2"]), host(x), xs) <= 1e-6
+    assert np.mean(learned_dbl) <= 0.25 * np.mean(plain_dbl)
+    assert learned_t < 0.8 * plain_t

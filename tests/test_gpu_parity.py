@@ -63,6 +63,9 @@ SRHT_CASES = [
     (65536, 8, 64, np.float64),
     (3000, 70, 100, np.float32),
     (16384, 33, 1500, np.float32),
+    # padded n above 2^20: the second pass folds 1 or 2 extra high index bits
+    (1_500_000, 3, 1500, np.float32),
+    ((1 << 21) + 5, 4, 64, np.float64),
 ]
 
 
@@ -82,7 +85,9 @@ def test_srht_values_against_dense_oracle(rs, n, d, m, dt):
     A = np.random.default_rng(n * 3 + d).standard_normal((n, d)).astype(dt)
     SA = host(rs.rs_sketch_srht(dev_padded(A, rs), m, seed=9, sketch_id=2))
     # compare a sample of rows (all when small): each oracle row is a dense sum
-    which = np.arange(m) if m <= 64 else np.random.default_rng(0).choice(m, 64, replace=False)
+    nsample = 64 if n <= (1 << 20) else 6
+    which = (np.arange(m) if m <= nsample
+             else np.random.default_rng(0).choice(m, nsample, replace=False))
     want = sketch.srht_sketch_rows(A.astype(np.float64), 9, 2, m, which)
     npad = sketch.next_pow2(n)
     # error of a length-npad +-1 sum in the working precision, scaled by 1/sqrt(m)
@@ -101,6 +106,17 @@ def test_srht_integer_inputs_exact(rs):
     want, _ = sketch.srht_sketch(A, 1, 1, m)
     np.testing.assert_array_equal(np.round(SA * np.sqrt(m)), np.round(want * np.sqrt(m)))
     np.testing.assert_allclose(SA, want, rtol=1e-15, atol=0)
+
+
+def test_srht_integer_inputs_exact_large_n(rs):
+    # padded n = 2^22 (two folded high bits in the second pass): sampled rows of
+    # integer data are exact
+    n, d, m = (1 << 21) + 3, 3, 2048
+    A = np.random.default_rng(8).integers(-4, 5, size=(n, d)).astype(np.float64)
+    SA = host(rs.rs_sketch_srht(dev_padded(A, rs), m, seed=5, sketch_id=3))
+    which = np.array([0, 1, 777, 1500, m - 1])
+    want = sketch.srht_sketch_rows(A, 5, 3, m, which)
+    np.testing.assert_array_equal(np.round(SA[which] * np.sqrt(m)), np.round(want * np.sqrt(m)))
 
 
 def test_srht_full_sample_is_isometry(rs):
