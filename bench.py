@@ -44,9 +44,12 @@ def parse():
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--mode", default="learned-bf16", choices=["learned-bf16", "plain"])
     ap.add_argument("--model", default=None, help="learned-start model (.npz)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4b"],
+    ap.add_argument("--skip-plain", action="store_true",
+                    help="do not time the plain method beside the learned form")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b"],
                     help="c2: the 65536x1024 headline problem; c3: the 2^20x4096 precision "
-                         "form; c4b: 256 uneven problems, batched")
+                         "form; c4a: 64 nu^2 on one 2^18x2048 problem; c4b: 256 uneven "
+                         "problems, batched")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a counter "
                          "reference for HBM traffic measurements)")
@@ -114,6 +117,8 @@ def main():
         return run_c3(args)
     if args.workload == "c4b":
         return run_c4b(args)
+    if args.workload == "c4a":
+        return run_c4a(args)
     import torch
 
     from paper_2006_05874_amd import rs
@@ -215,7 +220,7 @@ def main():
     ok, rels, solve_summary = verify(results)
     del results
     plain = None
-    if main_mode != "plain":
+    if main_mode != "plain" and not args.skip_plain:
         pres, pms, pwall, _ = timed("plain", profile=False)
         pok, prels, psum = verify(pres)
         del pres
@@ -276,6 +281,7 @@ def oracle_gram_chunks(A_dev, b_dev, rows=65536):
         bc = b_dev[r0:r0 + rows].cpu().numpy().astype(np.float64)
         G += Ac.T @ Ac
         Atb += Ac.T @ bc
+        print(f"[oracle] Gram rows {min(n, r0 + rows)}/{n}", file=sys.stderr, flush=True)
     return G, Atb
 
 
@@ -333,6 +339,81 @@ def run_c3(args):
             "per_dtype": res, "speedup_bf16_vs_f32": round(res["bf16"]["solves_per_s"] / base, 3),
             "speedup_fp8_vs_f32": round(res["fp8"]["solves_per_s"] / base, 3),
             "oracle_gram_s": round(oracle_s, 1)}
+    print(json.dumps(line))
+
+
+def run_c4a(args):
+    """64 values of nu^2 (log-spaced in [1e-6, 1]) on one 2^18 x 2048 FP32 problem
+    (sigma_i = i^-0.8): the nu-grid solver (shared level sketches, batched
+    factors, multi-RHS gradients; BF16 sketches) against 64 plain single solves
+    (FP32 sketch, m from 1).  Sampled nu checked against the oracle."""
+    import torch
+    from oracle import ridge
+    from paper_2006_05874_amd import rs
+    from synth import config_c4a_nu2, make_c4a_problem
+    torch.cuda.set_device(0)
+    A0, b = make_c4a_problem("cuda")
+    n, d = A0.shape
+    A = rs.padded(n, d, dtype=torch.float32)
+    A.copy_(A0)
+    del A0
+    nus = list(config_c4a_nu2())
+    torch.cuda.synchronize()
+    print("[c4a] problem ready", file=sys.stderr, flush=True)
+
+    def grid():
+        X, infos = rs.rs_solve_nu_grid(A, b, nus, sketch_dtype="bf16", raise_on_error=False)
+        return [(X[k], infos[k]) for k in range(len(nus))]
+
+    def seq():
+        return [rs.rs_adaptive_solve(A, b, nu, sketch_dtype="f32", raise_on_error=False)
+                for nu in nus]
+
+    out = {}
+    for name, fn in (("grid_bf16", grid), ("sequential_plain_f32", seq)):
+        fn()
+        torch.cuda.synchronize()
+        rs.rs_profile_enable(name == "grid_bf16")
+        rs.rs_profile_read()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        launches, gms = rs.rs_profile_read()
+        rs.rs_profile_enable(False)
+        out[name] = {"solves_per_s": round(len(nus) / sec, 2), "s_per_grid": round(sec, 4),
+                     "res": res}
+        if name == "grid_bf16":
+            out[name]["mr_gradient_launches"] = launches
+            out[name]["mr_gradient_ms_total"] = round(gms, 3)
+        print(f"[c4a] {name}: {len(nus) / sec:.1f} solves/s", file=sys.stderr, flush=True)
+    G, Atb = oracle_gram_chunks(A, b)
+    worst = {k: 0.0 for k in out}
+    for k in (0, 16, 32, 48, 63):
+        xs = ridge.solve_direct_from_gram(G, Atb, nus[k])
+        H = G + nus[k] * np.eye(d)
+        for name in out:
+            worst[name] = max(worst[name], ridge.relative_error(
+                H, out[name]["res"][k][0].cpu().numpy(), xs))
+    for name in out:
+        res = out[name].pop("res")
+        out[name]["not_ok"] = sum(i["status"] != "ok" for _, i in res)
+        out[name]["sampled_worst_rel_pred_err"] = worst[name]
+        out[name]["m_final"] = [i["m_final"] for _, i in res]
+    line = {"metric": "ridge solves/s to 1e-6 rel. pred. error, nu grid on one A",
+            "value": out["grid_bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(out["grid_bf16"]["s_per_grid"] * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
+            "config": {"workload": f"{n}x{d} FP32, sigma_i=i^-0.8, 64 nu^2 log-spaced in "
+                                   "[1e-6, 1], SRHT fresh, m from 1", "n": n, "d": d},
+            "verified": all(v["sampled_worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
+                            for v in out.values()),
+            "modes": out,
+            "speedup_vs_sequential_plain_f32": round(
+                out["grid_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
     print(json.dumps(line))
 
 

@@ -26,49 +26,87 @@ constexpr int kCache = kFeat + 2 * kHid + 1;   // xn, z1, z2, y per sample
 constexpr int kWork = 2 * kHid + 1;            // dz1, dz2, dy per sample
 
 // ------------------------------------------------------------------ features
-// Column sums over a chunk of 256 rows: acc[k][j] = sum_i w_k(i) A[i][j] for the
-// 8 probes and acc[8][j] = sum_i A[i][j]^2; thread = column, FP64 sums.
+// Column sums over a chunk of rows: part[chunk][k][j] = sum_i w_k(i) A[i][j] for
+// the 8 probes and part[chunk][8][j] = sum_i A[i][j]^2, FP64.  Block: 64 lanes x
+// VEC columns (one 16-byte vector per lane and row), 4 waves taking every 4th
+// row of the chunk, 4 rows per wave in flight; the probe signs of the chunk's
+// rows are drawn once into LDS.  The waves' sums meet in LDS in a fixed order.
+constexpr int kProbeChunkMax = 4096;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, int64_t n,
                                                        int64_t d, int64_t lda, uint64_t seed,
                                                        int64_t rows_per_chunk,
                                                        double* __restrict__ part) {
-  __shared__ uint8_t sgn[256];
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  using V = typename VecOf<T>::type;
+  constexpr int VEC = VecOf<T>::n;
+  constexpr int COLS = 64 * VEC;
+  constexpr int U = 4;
+  __shared__ uint8_t sgn[kProbeChunkMax];
+  __shared__ double red[kProbes + 1][COLS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * COLS + lane * VEC;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
-  double acc[kProbes + 1];
+  const int cnt = (int)(r1 - r0);
+  for (int i = t; i < cnt; i += 256) {
+    uint8_t bits = 0;
 #pragma unroll
-  for (int k = 0; k <= kProbes; ++k) acc[k] = 0.0;
-  for (int64_t base = r0; base < r1; base += 256) {
-    __syncthreads();
-    {
-      const int64_t i = base + threadIdx.x;
-      uint8_t bits = 0;
-      if (i < r1) {
-#pragma unroll
-        for (int k = 0; k < kProbes; ++k) {
-          const uint4 w = draw(seed, kStreamProbe, (uint32_t)k, (uint64_t)i);
-          bits |= (uint8_t)((w.x & 1u) << k);
-        }
-      }
-      sgn[threadIdx.x] = bits;
+    for (int k = 0; k < kProbes; ++k) {
+      const uint4 wd = draw(seed, kStreamProbe, (uint32_t)k, (uint64_t)(r0 + i));
+      bits |= (uint8_t)((wd.x & 1u) << k);
     }
-    __syncthreads();
-    if (j < d) {
-      const int64_t cnt = (r1 - base) < 256 ? (r1 - base) : 256;
-      for (int64_t ii = 0; ii < cnt; ++ii) {
-        const double a = (double)A[(base + ii) * lda + j];
-        const uint8_t bits = sgn[ii];
+    sgn[i] = bits;
+  }
+  __syncthreads();
+  bool cok[VEC];
 #pragma unroll
-        for (int k = 0; k < kProbes; ++k) acc[k] += ((bits >> k) & 1) ? -a : a;
-        acc[kProbes] = fma(a, a, acc[kProbes]);
+  for (int e = 0; e < VEC; ++e) cok[e] = c0 + e < d;
+  const int64_t cc = c0 < d ? c0 : 0;
+  double acc[kProbes + 1][VEC];
+#pragma unroll
+  for (int k = 0; k <= kProbes; ++k)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[k][e] = 0.0;
+  for (int i0 = w; i0 < cnt; i0 += 4 * U) {
+    V a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 4 * u;
+      const int ic = i < cnt ? i : 0;
+      a[u] = *reinterpret_cast<const V*>(A + (r0 + ic) * lda + cc);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 4 * u;
+      const bool rok = i < cnt;
+      const uint8_t bits = sgn[rok ? i : 0];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const double x = (rok && cok[e]) ? (double)get(a[u], e) : 0.0;
+#pragma unroll
+        for (int k = 0; k < kProbes; ++k) acc[k][e] += ((bits >> k) & 1) ? -x : x;
+        acc[kProbes][e] = fma(x, x, acc[kProbes][e]);
       }
     }
   }
-  if (j < d) {
+  // waves 0..3 in order
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
 #pragma unroll
-    for (int k = 0; k <= kProbes; ++k) part[((int64_t)blockIdx.y * (kProbes + 1) + k) * d + j] = acc[k];
+      for (int k = 0; k <= kProbes; ++k)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const int col = lane * VEC + e;
+          red[k][col] = (ww == 0 ? 0.0 : red[k][col]) + acc[k][e];
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < (kProbes + 1) * COLS; e += 256) {
+    const int k = e / COLS, col = e % COLS;
+    const int64_t j = (int64_t)blockIdx.x * COLS + col;
+    if (j < d) part[((int64_t)blockIdx.y * (kProbes + 1) + k) * d + j] = red[k][col];
   }
 }
 
@@ -133,19 +171,31 @@ __global__ __launch_bounds__(1024) void k_feature_final(const double* __restrict
   }
 }
 
-int feature_chunks(int64_t n) {
-  const int64_t c = (n + 4095) / 4096;
-  return (int)(c < 256 ? c : 256);
+// Row chunks of the probe pass: enough blocks to fill the chip, at most
+// kProbeChunkMax rows each.
+static int64_t probe_rows_per_chunk(int64_t n, int64_t d, int vec) {
+  const int64_t colblocks = (d + 64 * vec - 1) / (64 * vec);
+  int64_t want = (4 * device_cus() + colblocks - 1) / colblocks;
+  want = std::max<int64_t>(1, std::min<int64_t>(want, (n + 255) / 256));
+  int64_t rpc = ((n + want - 1) / want + 63) / 64 * 64;
+  if (rpc > kProbeChunkMax) rpc = kProbeChunkMax;
+  return rpc;
+}
+
+int feature_chunks(int64_t n, int64_t d, int vec) {
+  const int64_t rpc = probe_rows_per_chunk(n, d, vec);
+  return (int)((n + rpc - 1) / rpc);
 }
 
 template <typename T>
 rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
                         double* part, double* U, hipStream_t s) {
-  const int nchunk = feature_chunks(n);
-  const int64_t rpc = ((n + nchunk - 1) / nchunk + 255) / 256 * 256;
+  constexpr int VEC = VecOf<T>::n;
+  const int64_t rpc = probe_rows_per_chunk(n, d, VEC);
   const int nch = (int)((n + rpc - 1) / rpc);
-  hipLaunchKernelGGL(k_probe_partial<T>, dim3((unsigned)((d + 255) / 256), (unsigned)nch), dim3(256),
-                     0, s, A, n, d, lda, seed, rpc, part);
+  const unsigned colblocks = (unsigned)((d + 64 * VEC - 1) / (64 * VEC));
+  hipLaunchKernelGGL(k_probe_partial<T>, dim3(colblocks, (unsigned)nch), dim3(256), 0, s, A, n, d,
+                     lda, seed, rpc, part);
   const int64_t tot = (int64_t)(kProbes + 1) * d;
   hipLaunchKernelGGL(k_probe_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
                      nch, d, U);

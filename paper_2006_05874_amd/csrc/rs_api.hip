@@ -1268,7 +1268,7 @@ rs_status rs_features(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
                    S->pCw.as<double>(), S->pinfo.as<int>(), S->pGram.p, S->pGram.bytes};
   RS_TRY(factor_build(FB, S->psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
   // 2. one pass over A: the 8 probes A^T w_k and the squared column norms
-  const int nch = feature_chunks(n);
+  const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
   RS_TRY(S->ppart.ensure((size_t)nch * 9 * d * sizeof(double)));
   RS_TRY(S->pU.ensure((size_t)9 * d * sizeof(double)));
   if (a_t == RS_F32)

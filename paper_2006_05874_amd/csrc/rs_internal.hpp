@@ -174,7 +174,7 @@ rs_status grid_post_resample(const GridPtrs& P, int nl, double tol, int64_t d, c
                              hipStream_t s);
 
 // ---------------------------------------------------------------- learned form
-int feature_chunks(int64_t n);
+int feature_chunks(int64_t n, int64_t d, int vec);
 template <typename T>
 rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
                         double* part, double* U, hipStream_t s);
