@@ -7,9 +7,10 @@ tolerance, once at nu^2 = 1e-2 and once at nu^2 = 1e-4.
 
 The reported value is the learned form with BF16 sketches (features, MLP
 prediction of the starting m, then Algorithm 1 with the doubling rule as the
-fallback); the plain method (FP32 sketch, m from 1) is timed the same way on
-the same problem and reported beside it.  ``--mode plain`` reports the plain
-method alone.  Inputs are resident in HBM before timing; every solve of each
+fallback), each step's two solves run as one batch over two worker streams
+(rs_learned_solve_batch).  Beside it: the same learned solves one at a time,
+and the plain method (FP32 sketch, m from 1, one at a time), timed the same way
+on the same problem.  ``--mode plain`` reports the plain method alone.  Inputs are resident in HBM before timing; every solve of each
 timed region is checked afterwards against the oracle's direct solution
 (relative prediction error delta(x)/delta(0) <= 1e-6).
 
@@ -151,10 +152,22 @@ def main():
         return rs.rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant=args.variant,
                                    sketch_dtype="bf16", check_every=args.check_every)
 
+    def step_batched():
+        params, mu, sd = model
+        res = rs.rs_learned_solve_batch([(A, b, nu2) for nu2 in NU2S], params, mu, sd,
+                                        kind="srht", variant=args.variant, sketch_dtype="bf16",
+                                        check_every=args.check_every, workers=len(NU2S))
+        return [(nu2, x, info) for nu2, (x, info) in zip(NU2S, res)]
+
     def timed(mode, profile):
+        """mode: "plain" or "learned" (single solves, one after another) or
+        "learned-batched" (each step's solves as one batch over worker streams)."""
+        def one_step():
+            if mode == "learned-batched":
+                return step_batched()
+            return [(nu2,) + tuple(solve(nu2, mode)) for nu2 in NU2S]
         for _ in range(args.warmup):
-            for nu2 in NU2S:
-                solve(nu2, mode)
+            one_step()
         torch.cuda.synchronize()
         if profile:
             rs.rs_profile_enable(True)
@@ -166,9 +179,7 @@ def main():
         t0 = time.perf_counter()
         out = []
         for _ in range(args.steps):
-            for nu2 in NU2S:
-                x, info = solve(nu2, mode)
-                out.append((nu2, x, info))
+            out.extend(one_step())
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -214,13 +225,21 @@ def main():
 
     solves = args.steps * len(NU2S)
     main_mode = args.mode
-    results, ms_total, wall, (launches, grad_ms) = timed(main_mode, profile=True)
+    results, ms_total, wall, (launches, grad_ms) = timed(
+        "plain" if main_mode == "plain" else "learned-batched", profile=True)
     ms_per_step = ms_total / args.steps
     value = solves / (ms_total / 1e3)
     ok, rels, solve_summary = verify(results)
     del results
     plain = None
+    seq = None
     if main_mode != "plain" and not args.skip_plain:
+        sres, sms, _, _ = timed("learned", profile=False)
+        sok, srels, _ = verify(sres)
+        del sres
+        seq = {"value": round(solves / (sms / 1e3), 3), "unit": "solves/s",
+               "ms_per_step": round(sms / args.steps, 3), "verified": sok,
+               "rel_pred_err": {str(k): v for k, v in srels.items()}}
         pres, pms, pwall, _ = timed("plain", profile=False)
         pok, prels, psum = verify(pres)
         del pres
@@ -251,7 +270,8 @@ def main():
         "dtype": "bf16 sketch / f32 gradient / f64 factor" if main_mode != "plain" else "f32",
         "data": "synthetic (seeded low-rank-decay A = G diag(1/i) V^T)",
         "config": {"workload": f"{N}x{D} FP32, sigma_i=1/i, nu^2 in {list(NU2S)}, SRHT rho=0.1, "
-                               + ("learned m_init, BF16 sketch" if main_mode != "plain"
+                               + ("learned m_init, BF16 sketch, the step's solves batched "
+                                  "over 2 streams" if main_mode != "plain"
                                   else "m_init=1, FP32 sketch")
                                + f", {args.variant}, 2 solves per step",
                    "mode": main_mode,
@@ -262,6 +282,8 @@ def main():
         "wall_s": round(wall, 3),
         "roofline": roof,
     }
+    if seq is not None:
+        line["learned_bf16_one_at_a_time"] = seq
     if plain is not None:
         line["plain_fp32"] = plain
         line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)

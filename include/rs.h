@@ -307,6 +307,15 @@ rs_status rs_mlp_adam_step(float* params, const float* grad, float* m, float* v,
 
 /* Features -> MLP -> m_init = clamp(2^floor(y), 1, m_max) -> rs_adaptive_solve with
  * opts->m_init replaced.  m_init_used: host, may be NULL.  Synchronizes. */
+/* The batched form of rs_learned_solve: each problem's features and prediction
+ * run on its worker stream, then its Algorithm 1 run starts at the predicted m
+ * (fallback: the doubling rule).  m_init_used: NULL or count host int64.  Same
+ * scheduling, synchronization and return rules as rs_solve_batch. */
+rs_status rs_learned_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
+                                 const float* params, const float* mu, const float* sd,
+                                 rs_solve_info* infos, int64_t* m_init_used, int32_t workers,
+                                 hipStream_t stream);
+
 rs_status rs_learned_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
                            const void* b, double nu2, const rs_solve_opts* opts,
                            const float* params, const float* mu, const float* sd, double* x,

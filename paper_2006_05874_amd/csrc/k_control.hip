@@ -50,13 +50,11 @@ __global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
                                                  double* __restrict__ g, double* __restrict__ gt,
                                                  int32_t* __restrict__ ev_kind, int ev_cap) {
   __shared__ double r[K];
+  __shared__ double sh[1024 * K];
   __shared__ int chosen;
   if (ctl->status != RS_CTL_RUNNING) return;
-  if (threadIdx.x < K) {
-    double s = 0.0;
-    for (int b = 0; b < nrp; ++b) s += rpart[(int64_t)b * K + threadIdx.x];
-    r[threadIdx.x] = 0.5 * s;
-  }
+  block_sum_cols<K, 1024>(rpart, nrp, sh, r);
+  if (threadIdx.x < K) r[threadIdx.x] *= 0.5;
   __syncthreads();
   if (threadIdx.x == 0) {
     int c = -1;
@@ -123,10 +121,11 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
                                                      double* __restrict__ g,
                                                      double* __restrict__ gt,
                                                      double* __restrict__ gref, int at_cap) {
+  __shared__ double sh[1024];
+  __shared__ double rs1[1];
+  block_sum_cols<1, 1024>(rpart, nrp, sh, rs1);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nrp; ++b) s += rpart[b];
-    const double r = 0.5 * s;
+    const double r = 0.5 * rs1[0];
     ctl->r_t = r;
     ctl->r_1 = r;
     ctl->r_ref = r;
@@ -156,14 +155,12 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
                                                         double tol, int64_t d,
                                                         const double* __restrict__ GT,
                                                         double* __restrict__ gt, int at_cap) {
+  __shared__ double sh[2048];
+  __shared__ double s2[2];
+  block_sum_cols<2, 1024>(rpart, nrp, sh, s2);
   if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = 0; b < nrp; ++b) {
-      s0 += rpart[(int64_t)b * 2];
-      s1 += rpart[(int64_t)b * 2 + 1];
-    }
-    ctl->r_t = 0.5 * s0;
-    ctl->r_ref = 0.5 * s1;
+    ctl->r_t = 0.5 * s2[0];
+    ctl->r_ref = 0.5 * s2[1];
     ctl->at_cap = at_cap;
     int st = RS_CTL_RUNNING;
     if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;

@@ -386,9 +386,10 @@ __device__ __forceinline__ double rsqrt64(double x) {
 
 // Diagonal tile k: factor and invert the 64 x 64 block in LDS, 16 columns at a
 // time.  For each 16-wide panel: one wave factors the 16 x 16 diagonal piece in
-// registers (lane i holds row i; column values move between lanes by shuffles)
-// and 16 of its lanes invert it column by column; then the whole block applies
-// the panel below it, the matching block row of the inverse, and the trailing
+// registers (lane i holds row i; pivots and column entries are broadcast through
+// the scalar unit) and inverts it in the same registers (lane c builds column c
+// of the inverse by forward substitution); then the whole block applies the
+// panel below it, the matching block row of the inverse, and the trailing
 // update.  X = L^-1 is carried along as the right-hand side of L X = I.
 template <int Q>
 __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB + 1],
@@ -396,44 +397,42 @@ __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB +
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  // A: factor the 16 x 16 block at (Q, Q)
+  // A: factor the 16 x 16 block at (Q, Q) and invert it
   if (w == 0) {
     const int li = lane & 15;
     double r[16];
+    double rinv[16];  // 1 / L_jj (the same in every lane)
 #pragma unroll
     for (int c = 0; c < 16; ++c) r[c] = a[Q + li][Q + c];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const double piv = __shfl(r[j], j, 64);
+      const double piv = lane_value(r[j], j);
       bad |= !(piv > 0.0);
       const double inv = rsqrt64(piv);
+      rinv[j] = inv;
       const double l = r[j] * inv;
       r[j] = li > j ? l : (li == j ? piv * inv : r[j]);
 #pragma unroll
       for (int c = j + 1; c < 16; ++c) {
-        const double lc = __shfl(l, c, 64);
+        const double lc = lane_value(l, c);
         if (li >= c) r[c] -= l * lc;
       }
+    }
+    // column li of L^-1: X_ic = (delta_ic - sum_{l<i} L_il X_lc) / L_ii, i >= c
+    double col[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double acc = (i == li) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = 0; l < i; ++l) acc -= lane_value(r[l], i) * col[l];
+      col[i] = i >= li ? acc * rinv[i] : 0.0;
     }
     if (lane < 16) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[Q + lane][Q + c] = c <= lane ? r[c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dinv[i][lane] = col[i];
     }
-  }
-  __syncthreads();
-  // B: lane c < 16 of wave 0 computes column c of the 16 x 16 inverse
-  if (w == 0 && lane < 16) {
-    const int c = lane;
-    double col[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int l = 0; l < i; ++l) acc -= a[Q + i][Q + l] * col[l];
-      col[i] = i >= c ? acc / a[Q + i][Q + i] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) dinv[i][c] = col[i];
   }
   __syncthreads();
   // C: panel below (rows Q+16.., 16 columns) and block row Q.. of the inverse

@@ -324,60 +324,13 @@ __global__ __launch_bounds__(256) void k_pack_g(GridPtrs P, int64_t d, int what,
 
 // GT[y] = Hinv_z G[y] (K columns) and decrement partials; gated on the slot's
 // status unless `always`.
-template <int K, int RPW>
+template <int K>
 __global__ __launch_bounds__(256) void k_symv_g(GridPtrs P, int64_t d, const double* __restrict__ Gsrc,
                                                 int always) {
   const int y = blockIdx.y, z = P.zl[y];
   if (!always && !slot_running(P, z)) return;
-  const double* H = P.Hinv + (int64_t)z * P.sH;
-  const double* G = Gsrc + (int64_t)y * K * d;
-  double* Y = P.GTc + (int64_t)y * K * d;
-  double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
-  __shared__ double rr[4][K];
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * RPW;
-  double acc[RPW][K];
-#pragma unroll
-  for (int i = 0; i < RPW; ++i)
-#pragma unroll
-    for (int c = 0; c < K; ++c) acc[i][c] = 0.0;
-  for (int64_t j = lane; j < d; j += 64) {
-    double gv[K];
-#pragma unroll
-    for (int c = 0; c < K; ++c) gv[c] = G[c * d + j];
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int64_t row = r0 + i;
-      const double h = H[(row < d ? row : 0) * P.ldh + j];
-#pragma unroll
-      for (int c = 0; c < K; ++c) acc[i][c] = fma(row < d ? h : 0.0, gv[c], acc[i][c]);
-    }
-  }
-  double rloc[K];
-#pragma unroll
-  for (int c = 0; c < K; ++c) rloc[c] = 0.0;
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int64_t row = r0 + i;
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-      const double v = wave_sum(acc[i][c]);
-      if (row < d) {
-        if (lane == 0) Y[c * d + row] = v;
-        rloc[c] += v * G[c * d + row];
-      }
-    }
-  }
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < K; ++c) rr[w][c] = rloc[c];
-  __syncthreads();
-  if (threadIdx.x < K) {
-    double s = 0.0;
-    for (int ww = 0; ww < 4; ++ww) s += rr[ww][threadIdx.x];
-    rpart[(int64_t)blockIdx.x * K + threadIdx.x] = s;
-  }
+  symv_rows<K, 1>(P.Hinv + (int64_t)z * P.sH, P.ldh, d, Gsrc + (int64_t)y * K * d,
+                  P.GTc + (int64_t)y * K * d, P.rpart + (int64_t)z * P.nrp * 2 + (int64_t)blockIdx.x * K);
 }
 
 // Same tests and state moves as the single-problem decision kernel.
@@ -386,14 +339,12 @@ __global__ __launch_bounds__(1024) void k_decide_g(GridPtrs P, DecideParams a, i
   const int y = blockIdx.y, z = P.zl[y];
   DevCtl* ctl = P.ctl + z;
   __shared__ double r[K];
+  __shared__ double sh[1024 * K];
   __shared__ int chosen;
   if (ctl->status != RS_CTL_RUNNING) return;
   const double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
-  if (threadIdx.x < K) {
-    double s = 0.0;
-    for (int b = 0; b < P.nrp; ++b) s += rpart[(int64_t)b * K + threadIdx.x];
-    r[threadIdx.x] = 0.5 * s;
-  }
+  block_sum_cols<K, 1024>(rpart, P.nrp, sh, r);
+  if (threadIdx.x < K) r[threadIdx.x] *= 0.5;
   __syncthreads();
   if (threadIdx.x == 0) {
     int c = -1;
@@ -457,10 +408,11 @@ __global__ __launch_bounds__(1024) void k_init_g(GridPtrs P, double tol, int64_t
   const int y = blockIdx.y, z = P.zl[y];
   DevCtl* ctl = P.ctl + z;
   const double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
+  __shared__ double sh[1024];
+  __shared__ double rs1[1];
+  block_sum_cols<1, 1024>(rpart, P.nrp, sh, rs1);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < P.nrp; ++b) s += rpart[b];
-    const double r = 0.5 * s;
+    const double r = 0.5 * rs1[0];
     ctl->r_t = r;
     ctl->r_1 = r;
     ctl->r_ref = r;
@@ -494,14 +446,12 @@ __global__ __launch_bounds__(1024) void k_post_resample_g(GridPtrs P, double tol
   const int y = blockIdx.y, z = P.zl[y];
   DevCtl* ctl = P.ctl + z;
   const double* rpart = P.rpart + (int64_t)z * P.nrp * 2;
+  __shared__ double sh[2048];
+  __shared__ double s2[2];
+  block_sum_cols<2, 1024>(rpart, P.nrp, sh, s2);
   if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = 0; b < P.nrp; ++b) {
-      s0 += rpart[(int64_t)b * 2];
-      s1 += rpart[(int64_t)b * 2 + 1];
-    }
-    ctl->r_t = 0.5 * s0;
-    ctl->r_ref = 0.5 * s1;
+    ctl->r_t = 0.5 * s2[0];
+    ctl->r_ref = 0.5 * s2[1];
     ctl->at_cap = at_cap[z];
     int st = RS_CTL_RUNNING;
     if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;
@@ -532,8 +482,8 @@ rs_status grid_pack(const GridPtrs& P, int nl, int64_t d, int what, hipStream_t 
 rs_status grid_apply(const GridPtrs& P, int nl, int K, int64_t d, const double* Gsrc, int always,
                      hipStream_t s) {
   const dim3 g((unsigned)apply_blocks(d), (unsigned)nl);
-  if (K == 2) hipLaunchKernelGGL((k_symv_g<2, 2>), g, dim3(256), 0, s, P, d, Gsrc, always);
-  else hipLaunchKernelGGL((k_symv_g<1, 2>), g, dim3(256), 0, s, P, d, Gsrc, always);
+  if (K == 2) hipLaunchKernelGGL(k_symv_g<2>, g, dim3(256), 0, s, P, d, Gsrc, always);
+  else hipLaunchKernelGGL(k_symv_g<1>, g, dim3(256), 0, s, P, d, Gsrc, always);
   return check_launch("grid apply");
 }
 

@@ -110,15 +110,24 @@ __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, 
   }
 }
 
-// U[k][j] = sum over chunks (fixed order), k = 0..8.
+// U[k][j] = sum over chunks (fixed order), k = 0..8.  Block: 8 consecutive
+// elements x 32 chunk strides, then a tree over the strides in LDS.
 __global__ __launch_bounds__(256) void k_probe_finish(const double* __restrict__ part, int nchunk,
                                                       int64_t d, double* __restrict__ U) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double sh[32][8];
+  const int cl = threadIdx.x & 7, st = threadIdx.x >> 3;
   const int64_t tot = (int64_t)(kProbes + 1) * d;
-  if (e >= tot) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * tot + e];
-  U[e] = s;
+  const int64_t e = (int64_t)blockIdx.x * 8 + cl;
+  double v = 0.0;
+  if (e < tot)
+    for (int c = st; c < nchunk; c += 32) v += part[(int64_t)c * tot + e];
+  sh[st][cl] = v;
+  __syncthreads();
+  for (int off = 16; off > 0; off >>= 1) {
+    if (st < off) sh[st][cl] += sh[st + off][cl];
+    __syncthreads();
+  }
+  if (st == 0 && e < tot) U[e] = sh[0][cl];
 }
 
 // One block: q_k = 2 r_k (r from the apply of the probes), log column norms,
@@ -197,8 +206,8 @@ rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t 
   hipLaunchKernelGGL(k_probe_partial<T>, dim3(colblocks, (unsigned)nch), dim3(256), 0, s, A, n, d,
                      lda, seed, rpc, part);
   const int64_t tot = (int64_t)(kProbes + 1) * d;
-  hipLaunchKernelGGL(k_probe_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
-                     nch, d, U);
+  hipLaunchKernelGGL(k_probe_finish, dim3((unsigned)((tot + 7) / 8)), dim3(256), 0, s, part, nch,
+                     d, U);
   return check_launch("features pass");
 }
 template rs_status features_pass<float>(const float*, int64_t, int64_t, int64_t, uint64_t, double*,

@@ -169,6 +169,30 @@ static DeviceScratch* scratch_for_current() {
   return all[dev];
 }
 
+// Worker streams (default priority) with private scratch for batched solves.
+struct BatchWorker {
+  DeviceScratch S;
+  hipStream_t s = nullptr;
+  hipEvent_t join = nullptr;
+  int64_t job = -1;
+};
+struct WorkerPool {
+  std::mutex mu;
+  std::vector<std::unique_ptr<BatchWorker>> w;
+  hipEvent_t entry = nullptr;
+};
+
+static WorkerPool* pool_for_current() {
+  static std::mutex mu;
+  static std::vector<WorkerPool*> all;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)all.size() <= dev) all.resize(dev + 1, nullptr);
+  if (!all[dev]) all[dev] = new WorkerPool();
+  return all[dev];
+}
+
 static int64_t next_pow2(int64_t n) {
   int64_t p = 1;
   while (p < n) p <<= 1;
@@ -563,6 +587,75 @@ void rs_solve_opts_default(rs_solve_opts* o) {
 
 namespace rs {
 
+// The 16 features of (A, nu^2) into feat (device), on stream; no argument checks.
+static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
+                              int64_t d, int64_t lda, double nu2, uint64_t seed, float* feat,
+                              hipStream_t stream) {
+  const int64_t npad = next_pow2(n);
+  const int64_t m0 = std::min<int64_t>(256, npad);
+  const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
+  const int64_t es = a_t == RS_F64 ? 8 : 4;
+  // 1. the probe sketch and its factor
+  RS_TRY(S.psa.ensure((size_t)m0 * d * es));
+  RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
+                  nullptr, nullptr, stream));
+  RS_TRY(S.pM.ensure(factor_bytes_M(m0, d)));
+  RS_TRY(S.pLinv.ensure(factor_bytes_M(m0, d)));
+  RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
+  if (m0 < d) RS_TRY(S.pCw.ensure(factor_bytes_Cw(m0, d)));
+  RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
+  RS_TRY(S.pinfo.ensure(sizeof(int), true));
+  FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), S.pHinv.as<double>(),
+                   S.pCw.as<double>(), S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
+  RS_TRY(factor_build(FB, S.psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
+  // 2. one pass over A: the 8 probes A^T w_k and the squared column norms
+  const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
+  RS_TRY(S.ppart.ensure((size_t)nch * 9 * d * sizeof(double)));
+  RS_TRY(S.pU.ensure((size_t)9 * d * sizeof(double)));
+  if (a_t == RS_F32)
+    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda, seed,
+                                S.ppart.as<double>(), S.pU.as<double>(), stream));
+  else
+    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda, seed,
+                                 S.ppart.as<double>(), S.pU.as<double>(), stream));
+  // 3. q_k = u_k^T H_S0^-1 u_k = 2 r_k (two applies of 4 probes)
+  const int nrp = apply_blocks(d);
+  const int64_t dp = (d + 63) / 64 * 64;
+  RS_TRY(S.pY.ensure((size_t)8 * d * sizeof(double)));
+  RS_TRY(S.prp.ensure((size_t)nrp * 4 * sizeof(double)));
+  RS_TRY(S.pr.ensure(8 * sizeof(double)));
+  for (int h = 0; h < 2; ++h) {
+    RS_TRY(apply_launch(S.pHinv.as<double>(), dp, d, S.pU.as<double>() + (int64_t)4 * h * d, 4,
+                        S.pY.as<double>() + (int64_t)4 * h * d, S.prp.as<double>(), nullptr,
+                        stream));
+    RS_TRY(rsum_launch(S.prp.as<double>(), nrp, 4, S.pr.as<double>() + 4 * h, stream));
+  }
+  return features_final(S.pU.as<double>(), d, S.pr.as<double>(), n, nu2, feat, stream);
+}
+
+// m_init from the predicted log2 m: 2^floor(pred), clamped to [1, m_max].
+static int64_t learned_m_init(float pred, const rs_solve_opts& o, int64_t n) {
+  const int64_t cap = o.kind == RS_SKETCH_SRHT ? next_pow2(n) : n;
+  const int64_t mmax = o.m_max > 0 ? std::min<int64_t>(o.m_max, cap) : cap;
+  int64_t m0 = 1;
+  if (std::isfinite(pred) && pred > 0.0f) {
+    const int e = (int)std::floor(std::min(pred, 40.0f));
+    m0 = (int64_t)1 << e;
+  }
+  return std::max<int64_t>(1, std::min<int64_t>(m0, mmax));
+}
+
+static rs_status check_features_args(rs_dtype a_t, int64_t n, int64_t d, double nu2,
+                                     const char* who) {
+  if (d > 8192) return set_error(RS_ERR_UNSUPPORTED, (std::string(who) + ": d above 8192").c_str());
+  if (!(nu2 > 0.0))
+    return set_error(RS_ERR_NOT_SPD, (std::string(who) + ": nu^2 must be positive").c_str());
+  if (next_pow2(n) > (int64_t)1 << 22)
+    return set_error(RS_ERR_SHAPE, (std::string(who) + ": padded n above 2^22").c_str());
+  (void)a_t;
+  return RS_OK;
+}
+
 // The info record of one run.  Event log: the doublings recorded at step t come
 // before the step accepted at t; kinds[t] is the accepted candidate of step t.
 static void fill_info(rs_solve_info* info, rs_status result, const DevCtl& h,
@@ -650,6 +743,12 @@ struct SolveJob {
   rs_status result = RS_OK;
   int queue = 1;
   bool done = false;
+  // learned start: features and the prediction come first (phase 0)
+  const float* lp_params = nullptr;
+  const float* lp_mu = nullptr;
+  const float* lp_sd = nullptr;
+  int phase = 1;
+  int64_t m_init_used = 0;
 
   rs_status validate() {
     RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
@@ -743,8 +842,37 @@ struct SolveJob {
 
   bool ready() const { return hipEventQuery(S->done_ev) == hipSuccess; }
 
+  // first work of the job: the learned prediction if a model is given, else start()
+  rs_status begin() {
+    if (!lp_params) {
+      m_init_used = m;
+      return start();
+    }
+    phase = 0;
+    if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
+    if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
+    RS_TRY(S->pfeat.ensure(16 * sizeof(float)));
+    RS_TRY(S->py.ensure(sizeof(float)));
+    RS_TRY(features_run(*S, A, a_t, n, d, lda, nu2, o.seed, S->pfeat.as<float>(), stream));
+    RS_TRY(mlp_forward(lp_params, S->pfeat.as<float>(), 1, lp_mu, lp_sd, S->py.as<float>(),
+                       nullptr, stream));
+    RS_HIP(hipMemcpyAsync((char*)S->host_pinned + 1024, S->py.p, sizeof(float),
+                          hipMemcpyDeviceToHost, stream));
+    RS_HIP(hipEventRecord(S->done_ev, stream));
+    return RS_OK;
+  }
+
   // the previous batch has finished: decide what to enqueue next
   rs_status advance() {
+    if (phase == 0) {
+      float pred = 0.0f;
+      std::memcpy(&pred, (char*)S->host_pinned + 1024, sizeof(float));
+      o.m_init = learned_m_init(pred, o, n);
+      m = std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap);
+      m_init_used = m;
+      phase = 1;
+      return start();
+    }
     std::memcpy(&h, S->host_pinned, sizeof(DevCtl));
     int fbad = 0;
     std::memcpy(&fbad, (char*)S->host_pinned + 512, sizeof(int));
@@ -821,7 +949,7 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> lock(S->mu);
   J.S = S;
-  RS_TRY(J.start());
+  RS_TRY(J.begin());
   while (!J.done) {
     RS_HIP(hipEventSynchronize(S->done_ev));
     const rs_status st = J.advance();
@@ -830,8 +958,14 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
   return J.result;
 }
 
-rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
-                         rs_solve_info* infos, int32_t workers, hipStream_t stream) {
+}  // extern "C"
+
+namespace rs {
+
+static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
+                                  rs_solve_info* infos, int32_t workers, hipStream_t stream,
+                                  const float* params, const float* mu, const float* sd,
+                                  int64_t* m_init_used) {
   if (!probs || !opts || !infos) return set_error(RS_ERR_ARG, "rs_solve_batch: null argument");
   if (count < 0) return set_error(RS_ERR_ARG, "rs_solve_batch: count < 0");
   if (count == 0) return RS_OK;
@@ -841,32 +975,39 @@ rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_
     const rs_problem& P = probs[i];
     J.A = P.A; J.a_t = P.a_t; J.n = P.n; J.d = P.d; J.lda = P.lda; J.b = P.b; J.nu2 = P.nu2;
     J.x = P.x; J.o = *opts; J.info = &infos[i];
+    J.lp_params = params; J.lp_mu = mu; J.lp_sd = sd;
     RS_TRY(J.validate());
+    if (params) RS_TRY(check_features_args(P.a_t, P.n, P.d, P.nu2, "rs_learned_solve_batch"));
   }
   const int W = (int)std::max<int64_t>(1, std::min<int64_t>(workers > 0 ? workers : 8, count));
-  // worker streams and scratch: private to this call
-  struct Worker {
-    DeviceScratch S;
-    hipStream_t s = nullptr;
-    int64_t job = -1;
-  };
-  std::vector<Worker> wk((size_t)W);
-  hipEvent_t entry;
-  RS_HIP(hipEventCreateWithFlags(&entry, hipEventDisableTiming));
-  RS_HIP(hipEventRecord(entry, stream));
-  rs_status first_err = RS_OK;
-  for (auto& w : wk) {
-    RS_HIP(hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking));
-    RS_HIP(hipStreamWaitEvent(w.s, entry, 0));
+  // worker streams and scratch: a per-device pool kept across calls (its lock is
+  // held for the whole call)
+  WorkerPool* pool = pool_for_current();
+  std::lock_guard<std::mutex> plock(pool->mu);
+  while ((int)pool->w.size() < W) {
+    std::unique_ptr<BatchWorker> nw(new BatchWorker());
+    RS_HIP(hipStreamCreateWithFlags(&nw->s, hipStreamNonBlocking));
+    RS_HIP(hipEventCreateWithFlags(&nw->join, hipEventDisableTiming));
+    pool->w.push_back(std::move(nw));
   }
+  if (!pool->entry) RS_HIP(hipEventCreateWithFlags(&pool->entry, hipEventDisableTiming));
+  RS_HIP(hipEventRecord(pool->entry, stream));
+  std::vector<BatchWorker*> wk;
+  for (int i = 0; i < W; ++i) {
+    BatchWorker* w = pool->w[i].get();
+    w->job = -1;
+    RS_HIP(hipStreamWaitEvent(w->s, pool->entry, 0));
+    wk.push_back(w);
+  }
+  rs_status first_err = RS_OK;
   int64_t next = 0, finished = 0;
-  auto launch = [&](Worker& w) {
+  auto launch = [&](BatchWorker& w) {
     while (next < count) {
       SolveJob& J = jobs[next];
       J.S = &w.S;
       J.stream = w.s;
       const int64_t id = next++;
-      const rs_status st = J.start();
+      const rs_status st = J.begin();
       if (st == RS_OK) { w.job = id; return; }
       J.result = st;
       J.info->status = st;
@@ -876,10 +1017,11 @@ rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_
     }
     w.job = -1;
   };
-  for (auto& w : wk) launch(w);
+  for (BatchWorker* wp : wk) launch(*wp);
   while (finished < count) {
     bool progressed = false;
-    for (auto& w : wk) {
+    for (BatchWorker* wp : wk) {
+      BatchWorker& w = *wp;
       if (w.job < 0) continue;
       SolveJob& J = jobs[w.job];
       if (!J.ready()) continue;
@@ -895,18 +1037,35 @@ rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_
     }
     if (!progressed) std::this_thread::yield();
   }
-  // the caller's stream waits for every worker; then the workers go away
-  for (auto& w : wk) {
-    hipEvent_t e;
-    RS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    RS_HIP(hipEventRecord(e, w.s));
-    RS_HIP(hipStreamWaitEvent(stream, e, 0));
-    RS_HIP(hipStreamSynchronize(w.s));
-    (void)hipEventDestroy(e);
-    (void)hipStreamDestroy(w.s);
+  // the caller's stream waits for every worker
+  for (BatchWorker* wp : wk) {
+    RS_HIP(hipEventRecord(wp->join, wp->s));
+    RS_HIP(hipStreamWaitEvent(stream, wp->join, 0));
+    RS_HIP(hipStreamSynchronize(wp->s));
   }
-  (void)hipEventDestroy(entry);
+  if (m_init_used)
+    for (int64_t i = 0; i < count; ++i) m_init_used[i] = jobs[i].m_init_used;
   return first_err;
+}
+
+}  // namespace rs
+
+extern "C" {
+
+rs_status rs_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
+                         rs_solve_info* infos, int32_t workers, hipStream_t stream) {
+  return solve_batch_impl(probs, count, opts, infos, workers, stream, nullptr, nullptr, nullptr,
+                          nullptr);
+}
+
+rs_status rs_learned_solve_batch(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
+                                 const float* params, const float* mu, const float* sd,
+                                 rs_solve_info* infos, int64_t* m_init_used, int32_t workers,
+                                 hipStream_t stream) {
+  if (!params || !mu || !sd)
+    return set_error(RS_ERR_ARG, "rs_learned_solve_batch: null model argument");
+  return solve_batch_impl(probs, count, opts, infos, workers, stream, params, mu, sd,
+                          m_init_used);
 }
 
 }  // extern "C"
@@ -1251,45 +1410,7 @@ rs_status rs_features(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
   if (npad > (int64_t)1 << 22) return set_error(RS_ERR_SHAPE, "rs_features: padded n above 2^22");
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> g(S->mu);
-  const int64_t m0 = std::min<int64_t>(256, npad);
-  const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
-  const int64_t es = a_t == RS_F64 ? 8 : 4;
-  // 1. the probe sketch and its factor
-  RS_TRY(S->psa.ensure((size_t)m0 * d * es));
-  RS_TRY(srht_run(*S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S->psa.p, sa_t, d, nullptr,
-                  nullptr, nullptr, stream));
-  RS_TRY(S->pM.ensure(factor_bytes_M(m0, d)));
-  RS_TRY(S->pLinv.ensure(factor_bytes_M(m0, d)));
-  RS_TRY(S->pHinv.ensure(factor_bytes_Hinv(d)));
-  if (m0 < d) RS_TRY(S->pCw.ensure(factor_bytes_Cw(m0, d)));
-  RS_TRY(S->pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
-  RS_TRY(S->pinfo.ensure(sizeof(int), true));
-  FactorBuffers FB{S->pM.as<double>(), S->pLinv.as<double>(), S->pHinv.as<double>(),
-                   S->pCw.as<double>(), S->pinfo.as<int>(), S->pGram.p, S->pGram.bytes};
-  RS_TRY(factor_build(FB, S->psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
-  // 2. one pass over A: the 8 probes A^T w_k and the squared column norms
-  const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
-  RS_TRY(S->ppart.ensure((size_t)nch * 9 * d * sizeof(double)));
-  RS_TRY(S->pU.ensure((size_t)9 * d * sizeof(double)));
-  if (a_t == RS_F32)
-    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda, seed,
-                                S->ppart.as<double>(), S->pU.as<double>(), stream));
-  else
-    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda, seed,
-                                 S->ppart.as<double>(), S->pU.as<double>(), stream));
-  // 3. q_k = u_k^T H_S0^-1 u_k = 2 r_k (two applies of 4 probes)
-  const int nrp = apply_blocks(d);
-  const int64_t dp = (d + 63) / 64 * 64;
-  RS_TRY(S->pY.ensure((size_t)8 * d * sizeof(double)));
-  RS_TRY(S->prp.ensure((size_t)nrp * 4 * sizeof(double)));
-  RS_TRY(S->pr.ensure(8 * sizeof(double)));
-  for (int h = 0; h < 2; ++h) {
-    RS_TRY(apply_launch(S->pHinv.as<double>(), dp, d, S->pU.as<double>() + (int64_t)4 * h * d, 4,
-                        S->pY.as<double>() + (int64_t)4 * h * d, S->prp.as<double>(), nullptr,
-                        stream));
-    RS_TRY(rsum_launch(S->prp.as<double>(), nrp, 4, S->pr.as<double>() + 4 * h, stream));
-  }
-  return features_final(S->pU.as<double>(), d, S->pr.as<double>(), n, nu2, feat, stream);
+  return features_run(*S, A, a_t, n, d, lda, nu2, seed, feat, stream);
 }
 
 rs_status rs_mlp_forward(const float* params, const float* X, int64_t B, const float* mu,
@@ -1320,33 +1441,23 @@ rs_status rs_learned_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
                            const float* params, const float* mu, const float* sd, double* x,
                            rs_solve_info* info, int64_t* m_init_used, hipStream_t stream) {
   if (!opts || !params || !mu || !sd) return set_error(RS_ERR_ARG, "rs_learned_solve: null argument");
-  float* feat;
-  float* yp;
-  {
-    DeviceScratch* S = scratch_for_current();
-    std::lock_guard<std::mutex> g(S->mu);
-    RS_TRY(S->pfeat.ensure(16 * sizeof(float)));
-    RS_TRY(S->py.ensure(sizeof(float)));
-    feat = S->pfeat.as<float>();
-    yp = S->py.as<float>();
+  SolveJob J;
+  J.A = A; J.a_t = a_t; J.n = n; J.d = d; J.lda = lda; J.b = b; J.nu2 = nu2; J.x = x;
+  J.o = *opts; J.info = info; J.stream = stream;
+  J.lp_params = params; J.lp_mu = mu; J.lp_sd = sd;
+  RS_TRY(J.validate());
+  RS_TRY(check_features_args(a_t, n, d, nu2, "rs_learned_solve"));
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  J.S = S;
+  RS_TRY(J.begin());
+  while (!J.done) {
+    RS_HIP(hipEventSynchronize(S->done_ev));
+    const rs_status st = J.advance();
+    if (st != RS_OK && !J.done) return st;
   }
-  RS_TRY(rs_features(A, a_t, n, d, lda, nu2, opts->seed, feat, stream));
-  RS_TRY(mlp_forward(params, feat, 1, mu, sd, yp, nullptr, stream));
-  float pred = 0.0f;
-  RS_HIP(hipMemcpyAsync(&pred, yp, sizeof(float), hipMemcpyDeviceToHost, stream));
-  RS_HIP(hipStreamSynchronize(stream));
-  const int64_t cap = opts->kind == RS_SKETCH_SRHT ? next_pow2(n) : n;
-  const int64_t mmax = opts->m_max > 0 ? std::min<int64_t>(opts->m_max, cap) : cap;
-  int64_t m0 = 1;
-  if (std::isfinite(pred) && pred > 0.0f) {
-    const int e = (int)std::floor(std::min(pred, 40.0f));
-    m0 = (int64_t)1 << e;
-  }
-  m0 = std::max<int64_t>(1, std::min<int64_t>(m0, mmax));
-  if (m_init_used) *m_init_used = m0;
-  rs_solve_opts o = *opts;
-  o.m_init = m0;
-  return rs_adaptive_solve(A, a_t, n, d, lda, b, nu2, &o, x, info, stream);
+  if (m_init_used) *m_init_used = J.m_init_used;
+  return J.result;
 }
 
 }  // extern "C"

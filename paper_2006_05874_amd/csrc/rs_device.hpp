@@ -86,6 +86,103 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Value of v in lane src (src uniform across the wave), through the scalar
+// unit: two v_readlane_b32 instead of a cross-lane permute.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Fixed-order sum over a block of nthreads threads of per-thread values for K
+// columns: each thread first adds its strided share of src[b * K + c] (b <
+// count), then a tree in LDS.  Result in out[c] (shared) for every c < K.
+template <int K, int NT>
+__device__ __forceinline__ void block_sum_cols(const double* __restrict__ src, int count,
+                                               double* sh /* NT * K */, double* out) {
+  const int t = threadIdx.x;
+  double v[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) v[c] = 0.0;
+  for (int b = t; b < count; b += NT)
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] += src[(int64_t)b * K + c];
+#pragma unroll
+  for (int c = 0; c < K; ++c) sh[c * NT + t] = v[c];
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (t < off)
+#pragma unroll
+      for (int c = 0; c < K; ++c) sh[c * NT + t] += sh[c * NT + t + off];
+    __syncthreads();
+  }
+  if (t < K) out[t] = sh[t * NT];
+  __syncthreads();
+}
+
+// Rows r0.. of Y = H G (K columns) for one block: each wave takes RPW rows, lanes
+// read 16-byte pairs of H (128 columns per wave per step, ldh even and H 16-byte
+// aligned); the block's share of g^T Y goes to rpart[c].
+template <int K, int RPW>
+__device__ __forceinline__ void symv_rows(const double* __restrict__ H, int64_t ldh, int64_t d,
+                                          const double* __restrict__ G, double* __restrict__ Y,
+                                          double* __restrict__ rpart) {
+  __shared__ double rr[4][K];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * RPW;
+  double acc[RPW][K];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[i][c] = 0.0;
+  for (int64_t j0 = 0; j0 < d; j0 += 128) {
+    const int64_t j = j0 + 2 * lane;
+    const bool ok0 = j < d, ok1 = j + 1 < d;
+    const int64_t jc = ok0 ? j : 0;
+    double g0[K], g1[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const double a0 = G[c * d + jc];
+      const double a1 = G[c * d + (ok1 ? j + 1 : 0)];
+      g0[c] = ok0 ? a0 : 0.0;
+      g1[c] = ok1 ? a1 : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int64_t row = r0 + i < d ? r0 + i : 0;
+      const double2 h = *reinterpret_cast<const double2*>(H + row * ldh + jc);
+#pragma unroll
+      for (int c = 0; c < K; ++c) acc[i][c] = fma(h.x, g0[c], fma(h.y, g1[c], acc[i][c]));
+    }
+  }
+  double rloc[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) rloc[c] = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int64_t row = r0 + i;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const double y = wave_sum(acc[i][c]);
+      if (row < d) {
+        if (lane == 0) Y[c * d + row] = y;
+        rloc[c] += y * G[c * d + row];
+      }
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < K; ++c) rr[w][c] = rloc[c];
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int ww = 0; ww < 4; ++ww) s += rr[ww][threadIdx.x];
+    rpart[threadIdx.x] = s;
+  }
+}
+
 // ------------------------------------------------------------ conversions
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);

@@ -78,7 +78,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_solve_opts_default", "rs_adaptive_solve", "rs_last_error", "rs_version",
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
-           "rs_solve_nu_grid"]
+           "rs_solve_nu_grid", "rs_learned_solve_batch"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -133,13 +133,16 @@ def load(path=LIB_PATH):
                                  ctypes.POINTER(SolveInfo), ctypes.c_int32, vp]
     L.rs_solve_nu_grid.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
                                    ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
+    L.rs_learned_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
+                                         vp, vp, vp, ctypes.POINTER(SolveInfo),
+                                         ctypes.POINTER(i64), ctypes.c_int32, vp]
     L.rs_last_error.restype = ctypes.c_char_p
     L.rs_version.restype = ctypes.c_char_p
     for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
                  "rs_factor_apply", "rs_gradient", "rs_ihs_step", "rs_adaptive_solve",
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
-                 "rs_solve_nu_grid"]:
+                 "rs_solve_nu_grid", "rs_learned_solve_batch"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -333,16 +336,8 @@ def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh"
     return x, _info(info, st, raise_on_error, "rs_adaptive_solve")
 
 
-def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
-                   sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
-                   max_iter=200, seed=0, check_every=4, workers=8, raise_on_error=True):
-    """Solve a list of (A, b, nu2) problems with one option set.  Returns a list of
-    (x, info) pairs in the input order."""
-    if not problems:
-        return []
-    a_ts = [_mat(A, "rs_solve_batch") for A, _, _ in problems]
-    o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol,
-              max_iter, seed, check_every)
+def _batch_problems(problems, where):
+    a_ts = [_mat(A, where) for A, _, _ in problems]
     P = (Problem * len(problems))()
     xs, bs = [], []
     for i, (A, b, nu2) in enumerate(problems):
@@ -352,12 +347,50 @@ def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
         xs.append(x)
         bs.append(bc)
         P[i] = Problem(_ptr(A), a_ts[i], 0, n, d, A.stride(0), _ptr(bc), float(nu2), _ptr(x))
+    return a_ts, P, xs, bs
+
+
+def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
+                   sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
+                   max_iter=200, seed=0, check_every=4, workers=8, raise_on_error=True):
+    """Solve a list of (A, b, nu2) problems with one option set.  Returns a list of
+    (x, info) pairs in the input order."""
+    if not problems:
+        return []
+    a_ts, P, xs, bs = _batch_problems(problems, "rs_solve_batch")
+    o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol,
+              max_iter, seed, check_every)
     infos = (SolveInfo * len(problems))()
     st = load().rs_solve_batch(P, len(problems), ctypes.byref(o), infos, workers, _stream())
-    if st != RS_OK and raise_on_error:
+    if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
         _check(st, "rs_solve_batch")
     return [(xs[i], _info(infos[i], infos[i].status, False, "rs_solve_batch"))
             for i in range(len(problems))]
+
+
+def rs_learned_solve_batch(problems, params, mu, sd, kind="srht", variant="polyak",
+                           resample="fresh", sketch_dtype=None, rho=0.1, eta=0.01, m_max=0,
+                           tol=1e-7, max_iter=200, seed=0, check_every=4, workers=8,
+                           raise_on_error=True):
+    """Learned starting m for every problem, then the batched solve.  Returns a list
+    of (x, info) pairs; info["m_init"] is the starting m used."""
+    if not problems:
+        return []
+    a_ts, P, xs, bs = _batch_problems(problems, "rs_learned_solve_batch")
+    o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, 1, m_max, tol,
+              max_iter, seed, check_every)
+    infos = (SolveInfo * len(problems))()
+    used = (ctypes.c_int64 * len(problems))()
+    st = load().rs_learned_solve_batch(P, len(problems), ctypes.byref(o), _ptr(params), _ptr(mu),
+                                       _ptr(sd), infos, used, workers, _stream())
+    if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
+        _check(st, "rs_learned_solve_batch")
+    out = []
+    for i in range(len(problems)):
+        inf = _info(infos[i], infos[i].status, False, "rs_learned_solve_batch")
+        inf["m_init"] = int(used[i])
+        out.append((xs[i], inf))
+    return out
 
 
 def rs_solve_nu_grid(A, b, nu2s, kind="srht", variant="polyak", resample="fresh",

@@ -165,3 +165,24 @@ def test_trained_model_gains_over_plain(rs):
             assert ridge.relative_error(ridge.hessian(A64, spec["nu2"]), host(x), xs) <= 1e-6
     assert np.mean(learned_dbl) <= 0.25 * np.mean(plain_dbl)
     assert learned_t < 0.8 * plain_t
+
+
+def test_learned_batch_equals_single_learned_solves(rs):
+    # uneven problems through the batched learned form: every job gives exactly
+    # what rs_learned_solve gives alone (same prediction, same trajectory, same x)
+    from paper_2006_05874_amd import learned as L
+    params, mu, sd, _ = L.load_model()
+    probs = []
+    for i in range(6):
+        n, d = [(4096, 100), (3000, 37), (8192, 300), (5000, 64), (2048, 250), (6000, 129)][i]
+        p = make_problem(n, d, spectrum("poly", d, 1.0), 10.0 ** (-1 - i % 4), 0.1, 300 + i)
+        probs.append((dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2, p))
+    res = rs.rs_learned_solve_batch([(A, b, nu2) for A, b, nu2, _ in probs], params, mu, sd,
+                                    sketch_dtype="bf16", workers=3)
+    for (A, b, nu2, p), (x, info) in zip(probs, res):
+        x1, i1 = rs.rs_learned_solve(A, b, nu2, params, mu, sd, sketch_dtype="bf16")
+        assert info["m_init"] == i1["m_init"] and info["events"] == i1["events"]
+        assert info["status"] == "ok" and torch.equal(x, x1)
+        A64 = p.A.astype(np.float64)
+        xs = ridge.solve_direct(A64, p.b.astype(np.float64), nu2)
+        assert ridge.relative_error(ridge.hessian(A64, nu2), host(x), xs) <= 1e-6
