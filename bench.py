@@ -135,6 +135,8 @@ def main():
     A.copy_(torch.from_numpy(p0.A))
     b = torch.from_numpy(p0.b).cuda()
     torch.cuda.synchronize()
+    # the gradient pass's shape and grid, tuned on this problem (both k used)
+    plans = {k: rs.rs_gradient_autotune(A, b, k=k) for k in (1, 2)}
 
     model = None
     if args.mode == "learned-bf16":
@@ -277,6 +279,7 @@ def main():
                                   else "m_init=1, FP32 sketch")
                                + f", {args.variant}, 2 solves per step",
                    "mode": main_mode,
+                   "gradient_plan_k2": list(plans[2]),
                    "n": N, "d": D, "parallelism": "single GPU"},
         "verified": ok,
         "rel_pred_err": {str(k): v for k, v in rels.items()},
@@ -326,6 +329,8 @@ def run_c3(args):
     A.copy_(A0)
     del A0
     torch.cuda.synchronize()
+    for k in (1, 2):
+        rs.rs_gradient_autotune(A, b, k=k)
     print(f"[c3] problem ready; oracle Gram on the host", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     G, Atb = oracle_gram_chunks(A, b)
@@ -417,6 +422,8 @@ def run_c5(args):
     del A0
     torch.cuda.empty_cache()
     torch.cuda.synchronize()
+    for k in (1, 2):
+        rs.rs_gradient_autotune(A, b, k=k)
     print("[c5] problem ready", file=sys.stderr, flush=True)
     params, mu, sd, _ = learned.load_model(args.model or learned.MODEL_PATH)
     out = {}

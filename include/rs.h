@@ -153,6 +153,19 @@ typedef struct {
   double r_gd;      /* decrement at the gradient candidate */
 } rs_step_result;
 
+/* Autotuner of the gradient pass (the step's dominant kernel): times every built
+ * partial-sum shape that covers d (threads per row x 16-byte vectors per thread)
+ * at 1, 2 and 4 blocks per CU on this problem (k right-hand sides) and keeps the
+ * fastest for (dtype, n rounded up to a power of two, d, k); later gradients of
+ * that key, including those inside the solvers, use it.  plan: NULL or 3 host
+ * int32 (threads per row, vectors per thread, blocks).  Synchronizes.  Without
+ * tuning the shape follows d and the grid is 2 blocks per CU. */
+rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                               const void* b, int64_t k, int32_t* plan, hipStream_t stream);
+
+/* The plan the gradient pass uses for this key (tuned or default). */
+rs_status rs_gradient_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k, int32_t* plan);
+
 /* One step of Algorithm 1 under a fixed factor: candidates
  * x_p = x_t - mu_p g~_t + beta_p (x_t - x_{t-1}) and x_gd = x_t - mu_gd g~_t, their
  * gradients in one pass over A, their decrements, then the tests

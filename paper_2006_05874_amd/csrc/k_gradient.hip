@@ -11,6 +11,11 @@
 // A^T r products of the R rows are summed in T and then added to FP64
 // accumulators.  Each block writes one FP64 partial of length k*d; a second
 // kernel adds the partials in a fixed order (deterministic) and nu^2 X.
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "rs_internal.hpp"
 
 namespace rs {
@@ -285,28 +290,143 @@ int grad_partial_blocks(int64_t n) {
   return (int)(g < target ? g : target);
 }
 
+int grad_partial_blocks_max(int64_t n) {
+  const int64_t target = (int64_t)device_cus() * 4;
+  int64_t g = n / 64;
+  if (g < 1) g = 1;
+  return (int)(g < target ? g : target);
+}
+
+// ---------------------------------------------------------------- plans and autotuning
+// A plan is the (threads per row, vectors per thread) shape and the grid of the
+// partial-sum kernel.  Without tuning the shape follows d and the grid is two
+// blocks per CU; rs_gradient_autotune times every instantiated shape that covers d
+// (up to 4x the row) at 1, 2 and 4 blocks per CU on the caller's problem and keeps
+// the fastest for (type, n rounded up to a power of two, d, k).
+namespace {
+
+using PlanKey = std::tuple<int, int64_t, int64_t, int>;
+std::mutex g_plan_mu;
+std::map<PlanKey, GradPlan> g_plans;
+
+int64_t pow2_ceil(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+const GradShape kShapes[] = {{16, 1}, {64, 1}, {64, 2}, {64, 4}, {128, 4}, {256, 4}, {256, 8}};
+
+}  // namespace
+
+template <typename T>
+GradPlan grad_plan(int64_t n, int64_t d, int k) {
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    auto it = g_plans.find(PlanKey{(int)sizeof(T), pow2_ceil(n), d, k});
+    if (it != g_plans.end()) return it->second;
+  }
+  const GradShape sh = pick_shape<T>(d);
+  return GradPlan{sh.tpr, sh.nv, grad_partial_blocks(n)};
+}
+
+template <typename T>
+static bool launch_plan(const GradPlan& pl, const T* A, int64_t n, int64_t d, int64_t lda,
+                        const T* b, const double* X, int k, double* partial, const int* status,
+                        hipStream_t s) {
+  const GradShape sh{pl.tpr, pl.nv};
+  const int64_t rpb = (n + pl.grid - 1) / pl.grid;
+  switch (k) {
+    case 1: return dispatch_k<T, 1>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
+    case 2: return dispatch_k<T, 2>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
+    case 3: return dispatch_k<T, 3>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
+    case 4: return dispatch_k<T, 4>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
+  }
+  return false;
+}
+
 template <typename T>
 rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
-                          const double* X, int k, double* G, double* partial, int grid,
+                          const double* X, int k, double* G, double* partial, int grid_cap,
                           const int* status, hipStream_t s) {
-  const GradShape sh = pick_shape<T>(d);
-  if (sh.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
-  int64_t rpb = (n + grid - 1) / grid;
-  bool ok = false;
-  switch (k) {
-    case 1: ok = dispatch_k<T, 1>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
-    case 2: ok = dispatch_k<T, 2>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
-    case 3: ok = dispatch_k<T, 3>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
-    case 4: ok = dispatch_k<T, 4>(sh, A, n, d, lda, b, X, partial, grid, rpb, status, s); break;
-    default: return set_error(RS_ERR_ARG, "gradient: k must be in 1..4");
-  }
-  if (!ok) return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
+  if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "gradient: k must be in 1..4");
+  GradPlan pl = grad_plan<T>(n, d, k);
+  if (pl.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
+  if (pl.grid > grid_cap) pl.grid = grid_cap;
+  if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s))
+    return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
   const int64_t kd = (int64_t)k * d;
-  hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial, grid,
-                     kd, nu2, X, G, status);
+  hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
+                     pl.grid, kd, nu2, X, G, status);
   return check_launch("gradient");
 }
 
+template <typename T>
+rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
+                            const double* X, int k, double* G, double* partial, int grid_cap,
+                            hipStream_t s, GradPlan* chosen) {
+  if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "autotune: k must be in 1..4");
+  constexpr int VEC = VecOf<T>::n;
+  const int64_t row = (d + VEC - 1) / VEC;
+  std::vector<GradPlan> cand;
+  for (const GradShape& sh : kShapes) {
+    const int64_t cover = (int64_t)sh.tpr * sh.nv;
+    if (cover < row || cover > 4 * std::max<int64_t>(row, 16)) continue;
+    for (int f : {1, 2, 4}) {
+      int g = (int)std::min<int64_t>((int64_t)device_cus() * f, std::max<int64_t>(n / 64, 1));
+      g = std::min(g, grid_cap);
+      bool dup = false;
+      for (const GradPlan& c : cand) dup |= (c.tpr == sh.tpr && c.nv == sh.nv && c.grid == g);
+      if (!dup) cand.push_back(GradPlan{sh.tpr, sh.nv, g});
+    }
+  }
+  if (cand.empty()) return set_error(RS_ERR_UNSUPPORTED, "autotune: d too large for this build");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return set_error(RS_ERR_HIP, "autotune: event creation failed");
+  GradPlan best = cand[0];
+  float best_ms = 1e30f;
+  rs_status st = RS_OK;
+  for (const GradPlan& c : cand) {
+    const int64_t kd = (int64_t)k * d;
+    auto once = [&]() {
+      launch_plan<T>(c, A, n, d, lda, b, X, k, partial, nullptr, s);
+      hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
+                         c.grid, kd, 0.0, X, G, (const int*)nullptr);
+    };
+    once();
+    float ms = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      (void)hipEventRecord(e0, s);
+      once();
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) { st = set_error(RS_ERR_HIP, "autotune: sync"); break; }
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      ms = std::min(ms, t);
+    }
+    if (st != RS_OK) break;
+    if (ms < best_ms) { best_ms = ms; best = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != RS_OK) return st;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_plans[PlanKey{(int)sizeof(T), pow2_ceil(n), d, k}] = best;
+  }
+  if (chosen) *chosen = best;
+  return check_launch("autotune");
+}
+
+template GradPlan grad_plan<float>(int64_t, int64_t, int);
+template GradPlan grad_plan<double>(int64_t, int64_t, int);
+template rs_status gradient_autotune<float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                            const double*, int, double*, double*, int,
+                                            hipStream_t, GradPlan*);
+template rs_status gradient_autotune<double>(const double*, int64_t, int64_t, int64_t,
+                                             const double*, const double*, int, double*, double*,
+                                             int, hipStream_t, GradPlan*);
 template rs_status gradient_launch<float>(const float*, int64_t, int64_t, int64_t, const float*,
                                           double, const double*, int, double*, double*, int,
                                           const int*, hipStream_t);

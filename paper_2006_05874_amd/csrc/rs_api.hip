@@ -489,7 +489,7 @@ rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
   if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "rs_gradient: k must be in 1..4");
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> g(S->mu);
-  const int grid = grad_partial_blocks(n);
+  const int grid = grad_partial_blocks_max(n);
   RS_TRY(S->partial.ensure((size_t)grid * k * d * sizeof(double)));
   if (a_t == RS_F32)
     return gradient_launch<float>(reinterpret_cast<const float*>(A), n, d, lda,
@@ -503,8 +503,8 @@ rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
 static rs_status grad_any(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                           int64_t lda, const void* b, double nu2, const double* X, int k, double* G,
                           const int* status, hipStream_t s) {
-  const int grid = grad_partial_blocks(n);
-  RS_TRY(S.partial.ensure((size_t)grid * k * d * sizeof(double)));
+  const int grid = grad_partial_blocks_max(n);
+  RS_TRY(S.partial.ensure((size_t)grid * 4 * d * sizeof(double)));
   if (a_t == RS_F32)
     return gradient_launch<float>(reinterpret_cast<const float*>(A), n, d, lda,
                                   reinterpret_cast<const float*>(b), nu2, X, k, G,
@@ -512,6 +512,47 @@ static rs_status grad_any(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
   return gradient_launch<double>(reinterpret_cast<const double*>(A), n, d, lda,
                                  reinterpret_cast<const double*>(b), nu2, X, k, G,
                                  S.partial.as<double>(), grid, status, s);
+}
+
+rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                               const void* b, int64_t k, int32_t* plan, hipStream_t stream) {
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_gradient_autotune"));
+  if (!b) return set_error(RS_ERR_ARG, "rs_gradient_autotune: b is null");
+  if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "rs_gradient_autotune: k must be in 1..4");
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  const int grid = grad_partial_blocks_max(n);
+  RS_TRY(S->partial.ensure((size_t)grid * 4 * d * sizeof(double)));
+  RS_TRY(S->rvec.ensure((size_t)2 * 4 * d * sizeof(double)));
+  double* X = S->rvec.as<double>();
+  double* G = X + 4 * d;
+  RS_HIP(hipMemsetAsync(X, 0, (size_t)4 * d * sizeof(double), stream));
+  GradPlan pl;
+  if (a_t == RS_F32)
+    RS_TRY(gradient_autotune<float>(reinterpret_cast<const float*>(A), n, d, lda,
+                                    reinterpret_cast<const float*>(b), X, (int)k, G,
+                                    S->partial.as<double>(), grid, stream, &pl));
+  else
+    RS_TRY(gradient_autotune<double>(reinterpret_cast<const double*>(A), n, d, lda,
+                                     reinterpret_cast<const double*>(b), X, (int)k, G,
+                                     S->partial.as<double>(), grid, stream, &pl));
+  if (plan) {
+    plan[0] = pl.tpr;
+    plan[1] = pl.nv;
+    plan[2] = pl.grid;
+  }
+  return RS_OK;
+}
+
+rs_status rs_gradient_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k, int32_t* plan) {
+  if (!plan) return set_error(RS_ERR_ARG, "rs_gradient_plan: plan is null");
+  if (a_t != RS_F32 && a_t != RS_F64) return set_error(RS_ERR_ARG, "rs_gradient_plan: F32 or F64");
+  if (n < 1 || d < 1 || k < 1 || k > 4) return set_error(RS_ERR_SHAPE, "rs_gradient_plan: bad shape");
+  const GradPlan pl = a_t == RS_F32 ? grad_plan<float>(n, d, (int)k) : grad_plan<double>(n, d, (int)k);
+  plan[0] = pl.tpr;
+  plan[1] = pl.nv;
+  plan[2] = pl.grid;
+  return RS_OK;
 }
 
 rs_status rs_ihs_step(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, const void* b,
@@ -749,6 +790,55 @@ struct SolveJob {
   const float* lp_sd = nullptr;
   int phase = 1;
   int64_t m_init_used = 0;
+  // queued steps replayed from HIP graphs (one for a single step, one for
+  // check_every steps), captured on first use: every pointer they touch is fixed
+  // for the job's lifetime
+  bool use_graph = false;
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+
+  SolveJob() = default;
+  SolveJob(const SolveJob&) = delete;
+  SolveJob& operator=(const SolveJob&) = delete;
+  ~SolveJob() {
+    for (hipGraphExec_t& g : gx)
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+
+  rs_status enqueue_steps(int q) {
+    for (int it = 0; it < q; ++it) {
+      RS_TRY(candidates_launch(K, d, x, x_prev, gt, X, prm.mu_p, prm.beta_p, prm.mu_gd, status,
+                               stream));
+      RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
+      RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
+      RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
+                           gt, S->ev.as<int32_t>(), ev_cap, stream));
+    }
+    return RS_OK;
+  }
+
+  rs_status steps(int q) {
+    if (!use_graph || g_prof_on) return enqueue_steps(q);
+    hipGraphExec_t& ex = gx[q == 1 ? 0 : 1];
+    if (!ex) {
+      RS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      const rs_status st = enqueue_steps(q);
+      hipGraph_t gr = nullptr;
+      const hipError_t e = hipStreamEndCapture(stream, &gr);
+      if (st != RS_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+      }
+      if (e != hipSuccess) return set_error(RS_ERR_HIP, hipGetErrorString(e));
+      const hipError_t e2 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e2 != hipSuccess) {
+        ex = nullptr;
+        return set_error(RS_ERR_HIP, hipGetErrorString(e2));
+      }
+    }
+    RS_HIP(hipGraphLaunch(ex, stream));
+    return RS_OK;
+  }
 
   rs_status validate() {
     RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
@@ -883,14 +973,7 @@ struct SolveJob {
     if (h.status == RS_CTL_RUNNING) {
       // one step right after a resample (the next step is often rejected again
       // while m is small), check_every steps after accepted ones
-      for (int it = 0; it < queue; ++it) {
-        RS_TRY(candidates_launch(K, d, x, x_prev, gt, X, prm.mu_p, prm.beta_p, prm.mu_gd, status,
-                                 stream));
-        RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
-        RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
-        RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
-                             gt, S->ev.as<int32_t>(), ev_cap, stream));
-      }
+      RS_TRY(steps(queue));
       queue = check_every;
       return enqueue_read();
     }
@@ -976,6 +1059,7 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
     J.A = P.A; J.a_t = P.a_t; J.n = P.n; J.d = P.d; J.lda = P.lda; J.b = P.b; J.nu2 = P.nu2;
     J.x = P.x; J.o = *opts; J.info = &infos[i];
     J.lp_params = params; J.lp_mu = mu; J.lp_sd = sd;
+    J.use_graph = true;
     RS_TRY(J.validate());
     if (params) RS_TRY(check_features_args(P.a_t, P.n, P.d, P.nu2, "rs_learned_solve_batch"));
   }

@@ -87,6 +87,16 @@ size_t factor_bytes_Cw(int64_t m, int64_t d);
 
 // ---------------------------------------------------------------- gradient
 int grad_partial_blocks(int64_t n);
+int grad_partial_blocks_max(int64_t n);  // partial-sum blocks of any plan (buffer size)
+struct GradPlan {
+  int tpr = 0, nv = 0, grid = 0;
+};
+template <typename T>
+GradPlan grad_plan(int64_t n, int64_t d, int k);
+template <typename T>
+rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
+                            const double* X, int k, double* G, double* partial, int grid_cap,
+                            hipStream_t s, GradPlan* chosen);
 template <typename T>
 rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
                           const double* X, int k, double* G, double* partial, int grid,

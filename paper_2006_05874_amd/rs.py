@@ -78,7 +78,8 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_solve_opts_default", "rs_adaptive_solve", "rs_last_error", "rs_version",
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
-           "rs_solve_nu_grid", "rs_learned_solve_batch"]
+           "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
+           "rs_gradient_plan"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -136,13 +137,16 @@ def load(path=LIB_PATH):
     L.rs_learned_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
                                          vp, vp, vp, ctypes.POINTER(SolveInfo),
                                          ctypes.POINTER(i64), ctypes.c_int32, vp]
+    L.rs_gradient_autotune.argtypes = [vp, c_int, i64, i64, i64, vp, i64, vp, vp]
+    L.rs_gradient_plan.argtypes = [c_int, i64, i64, i64, vp]
     L.rs_last_error.restype = ctypes.c_char_p
     L.rs_version.restype = ctypes.c_char_p
     for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
                  "rs_factor_apply", "rs_gradient", "rs_ihs_step", "rs_adaptive_solve",
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
-                 "rs_solve_nu_grid", "rs_learned_solve_batch"]:
+                 "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
+                 "rs_gradient_plan"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -483,6 +487,25 @@ def rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant="polyak", r
     res = _info(info, st, raise_on_error, "rs_learned_solve")
     res["m_init"] = used.value
     return x, res
+
+
+def rs_gradient_autotune(A, b, k=2):
+    """Tune the gradient pass for this problem and k; returns the chosen plan
+    (threads per row, vectors per thread, blocks)."""
+    a_t = _mat(A, "rs_gradient_autotune")
+    n, d = A.shape
+    plan = (ctypes.c_int32 * 3)()
+    _check(load().rs_gradient_autotune(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), k,
+                                       ctypes.cast(plan, ctypes.c_void_p), _stream()),
+           "rs_gradient_autotune")
+    return tuple(plan)
+
+
+def rs_gradient_plan(dtype, n, d, k):
+    plan = (ctypes.c_int32 * 3)()
+    _check(load().rs_gradient_plan(DTYPES[dtype], n, d, k, ctypes.cast(plan, ctypes.c_void_p)),
+           "rs_gradient_plan")
+    return tuple(plan)
 
 
 def rs_profile_enable(on=True):

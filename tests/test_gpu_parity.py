@@ -187,6 +187,37 @@ def test_gradient_against_oracle(rs, n, d, k, dt):
             assert np.all(np.abs(G[c] - want) <= tol + 1e-12)
 
 
+@pytest.mark.parametrize("n,d,k", [(20000, 300, 2), (9000, 1000, 1), (3001, 37, 2)])
+def test_gradient_autotune_then_parity(rs, n, d, k):
+    # the tuned plan covers the row, is reported back, and the gradient it runs
+    # still meets the FP32 bound against the exact gradient at the rounded iterate
+    rng = np.random.default_rng(n + d)
+    A = (rng.standard_normal((n, d)) / np.sqrt(n)).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    Ad, bd = dev_padded(A, rs), dev(b)
+    tpr, nv, grid = rs.rs_gradient_autotune(Ad, bd, k=k)
+    assert tpr * nv * 4 >= d and grid >= 1
+    assert rs.rs_gradient_plan("f32", n, d, k) == (tpr, nv, grid)
+    X = rng.standard_normal((k, d))
+    G = host(rs.rs_gradient(Ad, bd, 0.37, dev(X)))
+    A64, b64 = A.astype(np.float64), b.astype(np.float64)
+    for c in range(k):
+        x32 = X[c].astype(np.float32).astype(np.float64)
+        want = A64.T @ (A64 @ x32 - b64) + 0.37 * X[c]
+        row = np.abs(A64) @ np.abs(x32) + np.abs(b64)
+        tol = 8 * np.finfo(np.float32).eps * (np.abs(A64).T @ row) * math.log2(max(d, 2))
+        assert np.all(np.abs(G[c] - want) <= tol + 1e-12)
+    # and a solve with the tuned pass reaches the oracle's solution
+    p = make_problem(n, d, spectrum("poly", d, 1.0), 1e-3, 0.1, 3)
+    A2 = dev_padded(p.A, rs)
+    rs.rs_gradient_autotune(A2, dev(p.b), k=2)
+    x, info = rs.rs_adaptive_solve(A2, dev(p.b), p.nu2)
+    A64 = p.A.astype(np.float64)
+    xs = ridge.solve_direct(A64, p.b.astype(np.float64), p.nu2)
+    assert info["status"] == "ok"
+    assert ridge.relative_error(ridge.hessian(A64, p.nu2), host(x), xs) <= 1e-6
+
+
 # ------------------------------------------------------------------ factor
 FACTOR_CASES = [(1, 64), (5, 64), (63, 64), (64, 64), (65, 64), (200, 64), (100, 300),
                 (512, 1024), (1024, 1024), (2048, 1024), (300, 100)]
