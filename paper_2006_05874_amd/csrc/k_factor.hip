@@ -412,11 +412,9 @@ __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB +
       rinv[j] = inv;
       const double l = r[j] * inv;
       r[j] = li > j ? l : (li == j ? piv * inv : r[j]);
+      // lanes above the diagonal update entries that are never read (no masks)
 #pragma unroll
-      for (int c = j + 1; c < 16; ++c) {
-        const double lc = lane_value(l, c);
-        if (li >= c) r[c] -= l * lc;
-      }
+      for (int c = j + 1; c < 16; ++c) r[c] -= l * lane_value(l, c);
     }
     // column li of L^-1: X_ic = (delta_ic - sum_{l<i} L_il X_lc) / L_ii, i >= c
     double col[16];
@@ -833,7 +831,8 @@ rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
                          k, nrest, F.Linv, zb);
     }
   }
-  // 3. explicit inverse
+  // 3. explicit inverse (skipped when the caller only needs L and L^-1)
+  if (!F.Hinv) return check_launch("factor");
   const int64_t dp = pad64(d);
   if (!wood) {
     hipLaunchKernelGGL(k_lauum, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s, F.Linv, pp, nblk,

@@ -130,6 +130,72 @@ __global__ __launch_bounds__(256) void k_probe_finish(const double* __restrict__
   if (st == 0 && e < tot) U[e] = sh[0][cl];
 }
 
+// Probe quadratic forms through the m0 x m0 factor when m0 < d (Woodbury): with
+// W = nu^2 I + SA SA^T = L L^T, u^T H^-1 u = (|u|^2 - |L^-1 SA u|^2) / nu^2.
+// k_probe_sav: v[k][i] = SA_i . u_k, one wave per row i, lanes along d.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_probe_sav(const TS* __restrict__ SA, int64_t m,
+                                                   int64_t d, int64_t ldsa,
+                                                   const double* __restrict__ U,
+                                                   double* __restrict__ V) {
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= m) return;
+  const double* u = U + (int64_t)k * d;
+  const TS* row = SA + i * ldsa;
+  double acc = 0.0;
+  for (int64_t j = lane; j < d; j += 64) acc = fma((double)row[j], u[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) V[(int64_t)k * m + i] = acc;
+}
+
+// One block per probe: y = L^-1 v (thread i takes row i of the triangle), then
+// r_k = (|u_k|^2 - |y|^2) / (2 nu^2) (the decrement convention r = q / 2).
+__global__ __launch_bounds__(256) void k_probe_quad(const double* __restrict__ V, int64_t m,
+                                                    const double* __restrict__ Linv, int64_t ldl,
+                                                    const double* __restrict__ U, int64_t d,
+                                                    double nu2, double* __restrict__ r) {
+  __shared__ double sh[2 * 256];
+  __shared__ double out[2];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const double* v = V + (int64_t)k * m;
+  double yy = 0.0;
+  for (int64_t i = t; i < m; i += 256) {
+    double y = 0.0;
+    for (int64_t l = 0; l <= i; ++l) y = fma(Linv[i * ldl + l], v[l], y);
+    yy = fma(y, y, yy);
+  }
+  double uu = 0.0;
+  const double* u = U + (int64_t)k * d;
+  for (int64_t j = t; j < d; j += 256) uu = fma(u[j], u[j], uu);
+  sh[t] = yy;
+  sh[256 + t] = uu;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+      sh[t] += sh[t + off];
+      sh[256 + t] += sh[256 + t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) r[k] = 0.5 * (sh[256] - sh[0]) / nu2;
+}
+
+rs_status probe_quads(const void* SA, rs_dtype sa_t, int64_t m, int64_t d, int64_t ldsa,
+                      const double* Linv, int64_t ldl, const double* U, double nu2, double* V,
+                      double* r, hipStream_t s) {
+  const dim3 g1(kProbes, (unsigned)((m + 3) / 4));
+  if (sa_t == RS_F64)
+    hipLaunchKernelGGL(k_probe_sav<double>, g1, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(SA), m, d, ldsa, U, V);
+  else
+    hipLaunchKernelGGL(k_probe_sav<float>, g1, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(SA), m, d, ldsa, U, V);
+  hipLaunchKernelGGL(k_probe_quad, dim3(kProbes), dim3(256), 0, s, V, m, Linv, ldl, U, d, nu2, r);
+  return check_launch("probe quadratic forms");
+}
+
 // One block: q_k = 2 r_k (r from the apply of the probes), log column norms,
 // sort, quantiles, and the 16 features.
 __global__ __launch_bounds__(1024) void k_feature_final(const double* __restrict__ U, int64_t d,

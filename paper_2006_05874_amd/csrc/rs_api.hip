@@ -636,18 +636,19 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
   const int64_t m0 = std::min<int64_t>(256, npad);
   const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
   const int64_t es = a_t == RS_F64 ? 8 : 4;
-  // 1. the probe sketch and its factor
+  // 1. the probe sketch and its factor (when m0 < d only L and L^-1 of the m0 x m0
+  //    Woodbury matrix are needed)
+  const bool wood = m0 < d;
   RS_TRY(S.psa.ensure((size_t)m0 * d * es));
   RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
                   nullptr, nullptr, stream));
   RS_TRY(S.pM.ensure(factor_bytes_M(m0, d)));
   RS_TRY(S.pLinv.ensure(factor_bytes_M(m0, d)));
-  RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
-  if (m0 < d) RS_TRY(S.pCw.ensure(factor_bytes_Cw(m0, d)));
+  if (!wood) RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
   RS_TRY(S.pinfo.ensure(sizeof(int), true));
-  FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), S.pHinv.as<double>(),
-                   S.pCw.as<double>(), S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
+  FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), wood ? nullptr : S.pHinv.as<double>(),
+                   nullptr, S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
   RS_TRY(factor_build(FB, S.psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
   // 2. one pass over A: the 8 probes A^T w_k and the squared column norms
   const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
@@ -659,17 +660,23 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
   else
     RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda, seed,
                                  S.ppart.as<double>(), S.pU.as<double>(), stream));
-  // 3. q_k = u_k^T H_S0^-1 u_k = 2 r_k (two applies of 4 probes)
-  const int nrp = apply_blocks(d);
-  const int64_t dp = (d + 63) / 64 * 64;
-  RS_TRY(S.pY.ensure((size_t)8 * d * sizeof(double)));
-  RS_TRY(S.prp.ensure((size_t)nrp * 4 * sizeof(double)));
+  // 3. r_k = q_k / 2 with q_k = u_k^T H_S0^-1 u_k
   RS_TRY(S.pr.ensure(8 * sizeof(double)));
-  for (int h = 0; h < 2; ++h) {
-    RS_TRY(apply_launch(S.pHinv.as<double>(), dp, d, S.pU.as<double>() + (int64_t)4 * h * d, 4,
-                        S.pY.as<double>() + (int64_t)4 * h * d, S.prp.as<double>(), nullptr,
-                        stream));
-    RS_TRY(rsum_launch(S.prp.as<double>(), nrp, 4, S.pr.as<double>() + 4 * h, stream));
+  if (wood) {
+    RS_TRY(S.pY.ensure((size_t)8 * m0 * sizeof(double)));
+    RS_TRY(probe_quads(S.psa.p, sa_t, m0, d, d, S.pLinv.as<double>(), (m0 + 63) / 64 * 64,
+                       S.pU.as<double>(), nu2, S.pY.as<double>(), S.pr.as<double>(), stream));
+  } else {
+    const int nrp = apply_blocks(d);
+    const int64_t dp = (d + 63) / 64 * 64;
+    RS_TRY(S.pY.ensure((size_t)8 * d * sizeof(double)));
+    RS_TRY(S.prp.ensure((size_t)nrp * 4 * sizeof(double)));
+    for (int h = 0; h < 2; ++h) {
+      RS_TRY(apply_launch(S.pHinv.as<double>(), dp, d, S.pU.as<double>() + (int64_t)4 * h * d, 4,
+                          S.pY.as<double>() + (int64_t)4 * h * d, S.prp.as<double>(), nullptr,
+                          stream));
+      RS_TRY(rsum_launch(S.prp.as<double>(), nrp, 4, S.pr.as<double>() + 4 * h, stream));
+    }
   }
   return features_final(S.pU.as<double>(), d, S.pr.as<double>(), n, nu2, feat, stream);
 }

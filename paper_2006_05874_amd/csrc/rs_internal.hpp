@@ -188,6 +188,9 @@ int feature_chunks(int64_t n, int64_t d, int vec);
 template <typename T>
 rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
                         double* part, double* U, hipStream_t s);
+rs_status probe_quads(const void* SA, rs_dtype sa_t, int64_t m, int64_t d, int64_t ldsa,
+                      const double* Linv, int64_t ldl, const double* U, double nu2, double* V,
+                      double* r, hipStream_t s);
 rs_status features_final(const double* U, int64_t d, const double* rprobe, int64_t n, double nu2,
                          float* feat, hipStream_t s);
 rs_status mlp_forward(const float* P, const float* X, int64_t B, const float* mu, const float* sd,
