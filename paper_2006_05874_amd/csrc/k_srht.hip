@@ -323,12 +323,26 @@ __device__ __forceinline__ void reg_fwht(V (&v)[J], int bit_lo, int lb) {
   }
 }
 
-__device__ __forceinline__ int lds_slot(int r, int c) { return r * 8 + (c ^ ((r >> 5) & 7)); }
+// Transpose buffer slot of (row r, vector c < 4): the row-bit-5..8 XOR spreads the
+// 16 lanes served together over 16 different bank groups in both directions.
+__device__ __forceinline__ int lds_slot(int r, int c) { return (r * 4 + c) ^ (((r >> 5) & 15) << 2); }
 
+// Row segment store: one 16-byte (8-byte for BF16) vector store when the segment
+// lies inside the row and the destination is aligned (vec_ok, uniform), else
+// element by element.
 template <typename T>
 __device__ __forceinline__ void store_row(T* out, int64_t ldo, int64_t orow, int64_t col0,
-                                          int64_t d, const typename VecOf<T>::type& v, T scale) {
+                                          int64_t d, const typename VecOf<T>::type& v, T scale,
+                                          bool vec_ok) {
+  using V = typename VecOf<T>::type;
   constexpr int VEC = VecOf<T>::n;
+  if (vec_ok && col0 + VEC <= d) {
+    V w;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) set(w, e, get(v, e) * scale);
+    *reinterpret_cast<V*>(out + orow * ldo + col0) = w;
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < VEC; ++e)
     if (col0 + e < d) out[orow * ldo + col0 + e] = get(v, e) * scale;
@@ -336,7 +350,15 @@ __device__ __forceinline__ void store_row(T* out, int64_t ldo, int64_t orow, int
 
 __device__ __forceinline__ void store_row_bf16(uint16_t* out, int64_t ldo, int64_t orow,
                                                int64_t col0, int64_t d, const float4& v,
-                                               float scale) {
+                                               float scale, bool vec_ok) {
+  if (vec_ok && col0 + 4 <= d) {
+    const uint32_t lo = (uint32_t)f32_to_bf16_rne(v.x * scale) |
+                        ((uint32_t)f32_to_bf16_rne(v.y * scale) << 16);
+    const uint32_t hi = (uint32_t)f32_to_bf16_rne(v.z * scale) |
+                        ((uint32_t)f32_to_bf16_rne(v.w * scale) << 16);
+    *reinterpret_cast<uint2*>(out + orow * ldo + col0) = make_uint2(lo, hi);
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < 4; ++e)
     if (col0 + e < d) out[orow * ldo + col0 + e] = f32_to_bf16_rne(get(v, e) * scale);
@@ -350,7 +372,7 @@ __device__ __forceinline__ void store_row_bf16(uint16_t* out, int64_t ldo, int64
 //   transform over the low 10 bits of j1 yields the output rows whose high
 //   index has r1h in its top bits.
 // OutT: T, or uint16_t for BF16 output.
-template <typename T, typename OutT, int MODE>
+template <typename T, typename OutT, int MODE, bool FOLD = false>
 __global__ __launch_bounds__(256) void k_fwht_tile(
     const T* __restrict__ src, int64_t n_src_rows, int64_t lds_src, int64_t d,
     const int8_t* __restrict__ signs, int lb, int64_t n2, int64_t Q,
@@ -361,12 +383,16 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
   using V = typename TT::V;
   constexpr int VEC = TT::VEC;
   constexpr int J = TT::J;
-  __shared__ V lds[TT::RT * TT::CW];
+  __shared__ V lds[TT::RT * TT::CW / 2];
   __shared__ int32_t dest[TT::RT];
 
   const int t = threadIdx.x;
+  // lanes (g, c): 8 lanes cover a 128-byte row segment.  The LDS transpose runs in
+  // two halves (vectors 0-3, then 4-7), so a block needs half the LDS and two
+  // blocks fit a CU: one loads while the other computes
   const int c = t & 7;
   const int g = t >> 3;
+  const int half = c >> 2;
   const int64_t col0 = ((int64_t)blockIdx.y * TT::CW + c) * VEC;
   const bool cvec = col0 < d;
 
@@ -419,7 +445,7 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     v[j] = *reinterpret_cast<const V*>(src + srowc * lds_src + (cvec ? col0 : 0));
     sgn[j] = (MODE == 2) ? (T)1 : (T)signs[srowc];
   }
-  if (MODE == 2 && hb > 0) {
+  if (FOLD && MODE == 2 && hb > 0) {
     // fold the top hb bits of j1: Zc tile (h << lb) + i1 with sign by r1h & h
     const int64_t stride = ((int64_t)1 << lb) * Q;
     for (int h = 1; h < (1 << hb); ++h) {
@@ -446,22 +472,34 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     }
   }
   reg_fwht<V, J>(v, 5, lb);
+for (int h = 0; h < 2; ++h) {
+    if (half == h) {
 #pragma unroll
-  for (int j = 0; j < J; ++j) lds[lds_slot(g + 32 * j, c)] = v[j];
-  __syncthreads();
+      for (int j = 0; j < J; ++j) lds[lds_slot(g + 32 * j, c & 3)] = v[j];
+    }
+    __syncthreads();
+    if (half == h) {
 #pragma unroll
-  for (int j = 0; j < J; ++j) v[j] = lds[lds_slot(32 * g + j, c)];
+      for (int j = 0; j < J; ++j) v[j] = lds[lds_slot(32 * g + j, c & 3)];
+    }
+    __syncthreads();
+  }
   reg_fwht<V, J>(v, 0, lb);
 
+  // vector stores need the row pitch and base aligned to the store width
+  constexpr uintptr_t kAlign = sizeof(OutT) == 2 ? 8 : 16;
+  const bool vec_ok = ((reinterpret_cast<uintptr_t>(out) |
+                        (uintptr_t)(ldo * (int64_t)sizeof(OutT))) & (kAlign - 1)) == 0;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int r = 32 * g + j;
     const int32_t dst = dest[r];
     if (dst >= 0 && cvec) {
       if constexpr (sizeof(OutT) == 2) {
-        store_row_bf16(reinterpret_cast<uint16_t*>(out), ldo, dst, col0, d, v[j], (float)scale);
+        store_row_bf16(reinterpret_cast<uint16_t*>(out), ldo, dst, col0, d, v[j], (float)scale,
+                       vec_ok);
       } else {
-        store_row<T>(reinterpret_cast<T*>(out), ldo, dst, col0, d, v[j], (T)scale);
+        store_row<T>(reinterpret_cast<T*>(out), ldo, dst, col0, d, v[j], (T)scale, vec_ok);
       }
     }
   }
@@ -495,9 +533,14 @@ template <typename T, typename OutT, int MODE>
 static void launch_tile(dim3 grid, hipStream_t s, const T* src, int64_t nsrc, int64_t ldsrc,
                         int64_t d, const SrhtBuffers& B, int lb, int64_t n2, int64_t Q, void* out,
                         int64_t ldo, double scale, int hb = 0) {
-  hipLaunchKernelGGL((k_fwht_tile<T, OutT, MODE>), grid, dim3(256), 0, s, src, nsrc, ldsrc, d,
-                     B.signs, lb, n2, Q, B.qmap, B.qlist, B.kmap, B.qcount,
-                     reinterpret_cast<OutT*>(out), ldo, scale, hb);
+  if (hb > 0)
+    hipLaunchKernelGGL((k_fwht_tile<T, OutT, MODE, true>), grid, dim3(256), 0, s, src, nsrc,
+                       ldsrc, d, B.signs, lb, n2, Q, B.qmap, B.qlist, B.kmap, B.qcount,
+                       reinterpret_cast<OutT*>(out), ldo, scale, hb);
+  else
+    hipLaunchKernelGGL((k_fwht_tile<T, OutT, MODE, false>), grid, dim3(256), 0, s, src, nsrc,
+                       ldsrc, d, B.signs, lb, n2, Q, B.qmap, B.qlist, B.kmap, B.qcount,
+                       reinterpret_cast<OutT*>(out), ldo, scale, hb);
 }
 
 template <typename T>
