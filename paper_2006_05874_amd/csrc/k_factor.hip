@@ -640,6 +640,63 @@ __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, 
     }
 }
 
+// The same product split over row chunks of Linv (chunk s covers block rows
+// [s CH, (s+1) CH) from I on), for factors whose few long tile chains would
+// otherwise run on a few CUs: partial P[s][tile] then a fixed-order sum.
+__global__ __launch_bounds__(256) void k_lauum_part(const double* __restrict__ Linv, int64_t ld,
+                                                    int nblk, int ch, double* __restrict__ P) {
+  __shared__ TileLds tl;
+  const int64_t bid = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= bid) ++I;
+  while (I * (I + 1) / 2 > bid) --I;
+  const int64_t J = bid - I * (I + 1) / 2;
+  const int64_t l0 = std::max<int64_t>(I, (int64_t)blockIdx.y * ch);
+  const int64_t l1 = std::min<int64_t>(nblk, ((int64_t)blockIdx.y + 1) * ch);
+  if (l0 >= l1) return;  // the sum skips this chunk
+  double acc[4][4];
+  zero_acc(acc);
+  const int64_t oI = I * NB, oJ = J * NB, o0 = l0 * NB;
+  const int64_t rows = (l1 - l0) * NB;
+  Opnd A{Linv + o0 * ld + oI, ld, NB, rows, true};
+  Opnd B{Linv + o0 * ld + oJ, ld, rows, NB, false};
+  tile_mm(acc, A, B, rows, tl);
+  const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
+  double* out = P + ((int64_t)blockIdx.y * tiles + bid) * NB * NB;
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[(ty * 4 + i) * NB + tx * 4 + j] = acc[i][j];
+}
+
+__global__ __launch_bounds__(256) void k_lauum_sum(const double* __restrict__ P, int nblk, int ch,
+                                                   int nsplit, double* __restrict__ H,
+                                                   int64_t ldh) {
+  const int64_t bid = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= bid) ++I;
+  while (I * (I + 1) / 2 > bid) --I;
+  const int64_t J = bid - I * (I + 1) / 2;
+  const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
+  const int s0 = (int)(I / ch);
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    double v = 0.0;
+    for (int sp = s0; sp < nsplit; ++sp) v += P[((int64_t)sp * tiles + bid) * NB * NB + e];
+    const int64_t r = I * NB + e / NB, c = J * NB + e % NB;
+    H[r * ldh + c] = v;
+    H[c * ldh + r] = v;
+  }
+}
+
+// Chunks of the split product: about two blocks per CU over all tiles.
+static int lauum_chunk(int nblk) {
+  const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
+  const int64_t want = std::max<int64_t>(1, (2 * device_cus() + tiles - 1) / tiles);
+  const int64_t ch = std::max<int64_t>(1, (nblk + want - 1) / want);
+  return (int)ch;
+}
+
 template <typename O>
 __device__ __forceinline__ void shift_scale(O&, int64_t) {}
 __device__ __forceinline__ void shift_scale(QOpnd& o, int64_t off) { o.scale += off; }
@@ -835,8 +892,18 @@ rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
   if (!F.Hinv) return check_launch("factor");
   const int64_t dp = pad64(d);
   if (!wood) {
-    hipLaunchKernelGGL(k_lauum, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s, F.Linv, pp, nblk,
-                       F.Hinv, dp, zb);
+    const int ch = lauum_chunk(nblk);
+    const int nsplit = (nblk + ch - 1) / ch;
+    const size_t need = (size_t)nsplit * tiles * NB * NB * sizeof(double);
+    if (B == 1 && nsplit > 1 && F.Cw && F.cw_bytes >= need) {
+      hipLaunchKernelGGL(k_lauum_part, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s,
+                         F.Linv, pp, nblk, ch, F.Cw);
+      hipLaunchKernelGGL(k_lauum_sum, dim3((unsigned)tiles), dim3(256), 0, s, F.Cw, nblk, ch,
+                         nsplit, F.Hinv, dp);
+    } else {
+      hipLaunchKernelGGL(k_lauum, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s, F.Linv, pp, nblk,
+                         F.Hinv, dp, zb);
+    }
   } else {
     const dim3 g2((unsigned)(dp / NB), (unsigned)nblk, Bz);
     if (sa_t == RS_F32) {
@@ -882,7 +949,12 @@ size_t factor_bytes_gram(int64_t m, int64_t d, rs_dtype sa_t) {
 }
 size_t factor_bytes_Hinv(int64_t d) { return (size_t)pad64(d) * pad64(d) * sizeof(double); }
 size_t factor_bytes_Cw(int64_t m, int64_t d) {
-  return m < d ? (size_t)pad64(m) * pad64(d) * sizeof(double) : 0;
+  if (m < d) return (size_t)pad64(m) * pad64(d) * sizeof(double);
+  // m >= d: partial products of the split LinvT Linv
+  const int nblk = (int)(pad64(d) / NB);
+  const int ch = lauum_chunk(nblk);
+  const int64_t tiles = (int64_t)nblk * (nblk + 1) / 2;
+  return (size_t)((nblk + ch - 1) / ch) * tiles * NB * NB * sizeof(double);
 }
 
 }  // namespace rs

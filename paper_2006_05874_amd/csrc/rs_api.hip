@@ -425,7 +425,7 @@ static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
   RS_TRY(F->M.ensure(factor_bytes_M(m, d)));
   RS_TRY(F->Linv.ensure(factor_bytes_M(m, d)));
   RS_TRY(F->Hinv.ensure(factor_bytes_Hinv(d)));
-  if (F->wood) RS_TRY(F->Cw.ensure(factor_bytes_Cw(m, d)));
+  RS_TRY(F->Cw.ensure(factor_bytes_Cw(m, d)));
   RS_TRY(F->info.ensure(sizeof(int), true));
   RS_TRY(F->rpart.ensure((size_t)apply_blocks(d) * 4 * sizeof(double)));
   RS_TRY(F->gram.ensure(factor_bytes_gram(m, d, F->sa_t)));
@@ -449,7 +449,8 @@ rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_
   rs_status st = factor_alloc(F, m, d, nu2);
   if (st == RS_OK) {
     FactorBuffers B{F->M.as<double>(), F->Linv.as<double>(), F->Hinv.as<double>(),
-                    F->Cw.as<double>(), F->info.as<int>(), F->gram.p, F->gram.bytes};
+                    F->Cw.as<double>(), F->info.as<int>(), F->gram.p, F->gram.bytes,
+                    F->Cw.bytes};
     hipError_t e = hipMemsetAsync(B.info, 0, sizeof(int), stream);
     if (e != hipSuccess) st = set_error(RS_ERR_HIP, "hipMemsetAsync failed");
     if (st == RS_OK) st = factor_build(B, SA, sa_t, sa_col_scale, m, d, ldsa, nu2, stream);
@@ -890,10 +891,10 @@ struct SolveJob {
     RS_TRY(S->fM.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fLinv.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fHinv.ensure(factor_bytes_Hinv(d)));
-    if (mm < d) RS_TRY(S->fCw.ensure(factor_bytes_Cw(mm, d)));
+    RS_TRY(S->fCw.ensure(factor_bytes_Cw(mm, d)));
     RS_TRY(S->fGram.ensure(factor_bytes_gram(mm, d, sa_t)));
     FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
-                     S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes};
+                     S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes, S->fCw.bytes};
     RS_TRY(factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream));
     Hinv = S->fHinv.as<double>();
     return RS_OK;

@@ -58,6 +58,7 @@ struct FactorBuffers {
   int* info;     // 1: a pivot failed
   void* gram;    // split-K partial Grams
   size_t gram_bytes;
+  size_t cw_bytes = 0;  // bytes at Cw (m >= d: scratch of the split inverse product)
 };
 rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,

@@ -9,6 +9,9 @@ work: launches queued behind a raised status flag return at once (a few
 microseconds) and are excluded by dropping dispatches shorter than 10% of that
 kernel's longest one.
 
+``--last N`` keeps only the kernel's last N dispatches (those of the timed region
+when the program tunes or warms up before it).
+
 ``traffic``: FETCH_SIZE and WRITE_SIZE per dispatch (KiB), scaled by what the
 same counters read for a plain device-to-device copy of 256 MiB recorded in the
 same process (the rocclr copyBuffer dispatch with the largest WRITE_SIZE), for
@@ -32,9 +35,9 @@ def short_name(name):
     return s
 
 
-def trace_summary(db, kernel=None):
+def trace_summary(db, kernel=None, last=None):
     c = sqlite3.connect(db)
-    rows = c.execute("select name, start, end from kernels").fetchall()
+    rows = c.execute("select name, start, end from kernels order by start").fetchall()
     agg = collections.defaultdict(list)
     for name, st, en in rows:
         agg[short_name(name)].append((en - st) / 1e3)  # us
@@ -45,7 +48,9 @@ def trace_summary(db, kernel=None):
                      f"{sum(v) / len(v):9.2f}  {k}")
     out = {"lines": lines, "busy_ms": total / 1e3}
     if kernel:
-        ds = [d for k, v in agg.items() if k.startswith(kernel) for d in v]
+        ds = [(en - st) / 1e3 for name, st, en in rows if short_name(name).startswith(kernel)]
+        if last:
+            ds = ds[-last:]
         if ds:
             cut = 0.1 * max(ds)
             work = [d for d in ds if d >= cut]
@@ -57,11 +62,11 @@ def trace_summary(db, kernel=None):
 def _pmc(db, counter):
     c = sqlite3.connect(db)
     rows = c.execute("select name, counter_name, counter_value from pmc_events "
-                     "where counter_name = ?", (counter,)).fetchall()
+                     "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
     return [(short_name(n), v) for n, _, v in rows]
 
 
-def traffic_summary(fetch_db, write_db, kernel):
+def traffic_summary(fetch_db, write_db, kernel, last=None):
     f = _pmc(fetch_db, "FETCH_SIZE")
     w = _pmc(write_db, "WRITE_SIZE")
     copy_w = max(v for n, v in w if n.startswith("__amd_rocclr_copyBuffer"))
@@ -71,6 +76,8 @@ def traffic_summary(fetch_db, write_db, kernel):
     w_scale = COPY_BYTES / (copy_w * 1024.0)
     kf = [v for n, v in f if n.startswith(kernel)]
     kw = [v for n, v in w if n.startswith(kernel)]
+    if last:
+        kf, kw = kf[-last:], kw[-last:]
     kf_work = [v for v in kf if v >= 0.1 * max(kf)]
     kw_work = sorted(kw)[-len(kf_work):] if kf_work else []
     fetch_b = sum(kf_work) / len(kf_work) * 1024.0 * f_scale
@@ -87,13 +94,15 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--kernel")
+    t.add_argument("--last", type=int, default=None)
     tr = sub.add_parser("traffic")
     tr.add_argument("fetch_db")
     tr.add_argument("write_db")
     tr.add_argument("--kernel", required=True)
+    tr.add_argument("--last", type=int, default=None)
     a = ap.parse_args()
     if a.cmd == "trace":
-        out = trace_summary(a.db, a.kernel)
+        out = trace_summary(a.db, a.kernel, a.last)
         print(f"busy_ms {out['busy_ms']:.3f}")
         if "kernel" in out:
             k = out["kernel"]
@@ -101,7 +110,7 @@ def main():
                   f"mean_us_working {k['mean_us_working']:.2f}")
         print("\n".join(out["lines"]))
     else:
-        out = traffic_summary(a.fetch_db, a.write_db, a.kernel)
+        out = traffic_summary(a.fetch_db, a.write_db, a.kernel, a.last)
         for k, v in out.items():
             print(f"{k}: {v}")
 
