@@ -32,14 +32,14 @@ __device__ __forceinline__ Acc4<T> mfma4(T a, T b, Acc4<T> c) {
 }
 
 // ---------------------------------------------------------------- R = A X^T - b
-// Block: 128 rows x 128 columns of R, 4 waves of 32 rows x 128 columns; k (the
-// d dimension) in chunks of 32 through LDS.  X is Kc x d FP64 (rounded to T).
-// Block b covers column block b % ncb of row block b / ncb, so the blocks that
-// read one row panel of A run next to each other.
+// Block: 128 rows x 128 columns of R, 8 waves of 32 rows x 64 columns (two waves
+// per SIMD); k (the d dimension) in chunks of 32 through LDS.  XT is X (Kc x d)
+// already in T.  Block b covers column block b % ncb of row block b / ncb, so
+// the blocks that read one row panel of A run next to each other.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mr_resid(const T* __restrict__ A, int64_t n, int64_t d,
+__global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64_t n, int64_t d,
                                                   int64_t lda, const T* __restrict__ b,
-                                                  const double* __restrict__ X, int64_t Kc,
+                                                  const T* __restrict__ XT, int64_t Kc,
                                                   T* __restrict__ R, int64_t ldr, int ncb,
                                                   int* __restrict__ ran) {
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
@@ -47,56 +47,51 @@ __global__ __launch_bounds__(256) void k_mr_resid(const T* __restrict__ A, int64
   __shared__ T As[KC][TM + 1];
   __shared__ T Xs[KC][TC + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w & 3, wc = w >> 2;  // wave tile: rows wr*32.., columns wc*64..
   const int64_t r0 = (int64_t)(blockIdx.x / ncb) * TM;
   const int64_t c0 = (int64_t)(blockIdx.x % ncb) * TC;
-  Acc4<T> acc[2][8];
+  Acc4<T> acc[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[a][c] = Acc4<T>{0, 0, 0, 0};
-  // loader mapping: thread -> (row or column = t / 2, 16 consecutive k)
-  const int lrow = t >> 1, lk = (t & 1) * 16;
-  for (int64_t k0 = 0; k0 < d; k0 += KC) {
-    {
-      const int64_t row = r0 + lrow;
-      const bool rok = row < n;
-      const T* src = A + (rok ? row : 0) * lda;
-      T v[16];
+    for (int c = 0; c < 4; ++c) acc[a][c] = Acc4<T>{0, 0, 0, 0};
+  // loader mapping: thread -> (row or column = t / 4, 8 consecutive k); the next
+  // chunk is fetched into registers while the current one is multiplied
+  const int lrow = t >> 2, lk = (t & 3) * 8;
+  const int64_t arow = r0 + lrow, xcol = c0 + lrow;
+  const bool rok = arow < n, cok = xcol < Kc;
+  const T* asrc = A + (rok ? arow : 0) * lda;
+  const T* xsrc = XT + (cok ? xcol : 0) * d;
+  T va[8], vx[8];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t k = k0 + lk + e;
-        const bool ok = rok && k < d;
-        const T x = src[ok ? k : 0];
-        v[e] = ok ? x : (T)0;
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) As[lk + e][lrow] = v[e];
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + lk + e;
+      const bool okk = k < d;
+      const T x = asrc[(rok && okk) ? k : 0];
+      const T y = xsrc[(cok && okk) ? k : 0];
+      va[e] = (rok && okk) ? x : (T)0;
+      vx[e] = (cok && okk) ? y : (T)0;
     }
-    {
-      const int64_t col = c0 + lrow;
-      const bool cok = col < Kc;
-      const double* src = X + (cok ? col : 0) * d;
-      T v[16];
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < d; k0 += KC) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t k = k0 + lk + e;
-        const bool ok = cok && k < d;
-        const double x = src[ok ? k : 0];
-        v[e] = ok ? (T)x : (T)0;
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) Xs[lk + e][lrow] = v[e];
+    for (int e = 0; e < 8; ++e) {
+      As[lk + e][lrow] = va[e];
+      Xs[lk + e][lrow] = vx[e];
     }
     __syncthreads();
+    if (k0 + KC < d) fetch(k0 + KC);
 #pragma unroll
     for (int k4 = 0; k4 < KC / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
       T av[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kr][w * 32 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 2; ++a) av[a] = As[kr][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const T bv = Xs[kr][c * 16 + (lane & 15)];
+      for (int c = 0; c < 4; ++c) {
+        const T bv = Xs[kr][wc * 64 + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a][c] = mfma4<T>(av[a], bv, acc[a][c]);
       }
@@ -107,12 +102,12 @@ __global__ __launch_bounds__(256) void k_mr_resid(const T* __restrict__ A, int64
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + w * 32 + a * 16 + mfma16_row<T>(lane, r);
+      const int64_t row = r0 + wr * 32 + a * 16 + mfma16_row<T>(lane, r);
       if (row < n) {
         const T bv = b[row];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int64_t col = c0 + c * 16 + (lane & 15);
+        for (int c = 0; c < 4; ++c) {
+          const int64_t col = c0 + wc * 64 + c * 16 + (lane & 15);
           if (col < Kc) R[row * ldr + col] = acc[a][c][r] - bv;
         }
       }
@@ -121,10 +116,10 @@ __global__ __launch_bounds__(256) void k_mr_resid(const T* __restrict__ A, int64
 
 // ---------------------------------------------------------------- Gp = A^T R per chunk
 // Block (tile, split): 128 columns of A (j) x 128 columns of R (c) over the
-// split's rows, 4 waves of 32 j x 128 c; rows in chunks of 32 through LDS.
+// split's rows, 8 waves of 32 j x 64 c; rows in chunks of 32 through LDS.
 // Partial layout Gp[split][j][c] (ldr columns), FP64.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mr_atr(const T* __restrict__ A, int64_t n, int64_t d,
+__global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t n, int64_t d,
                                                 int64_t lda, const T* __restrict__ R, int64_t ldr,
                                                 int64_t Kc, int64_t rows_per_split, int ncb,
                                                 double* __restrict__ Gp) {
@@ -132,64 +127,59 @@ __global__ __launch_bounds__(256) void k_mr_atr(const T* __restrict__ A, int64_t
   __shared__ T As[KC][TJ + 1];
   __shared__ T Rs[KC][TC + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wj = w & 3, wc = w >> 2;
   const int64_t j0 = (int64_t)(blockIdx.x / ncb) * TJ;
   const int64_t c0 = (int64_t)(blockIdx.x % ncb) * TC;
   const int64_t row_lo = (int64_t)blockIdx.y * rows_per_split;
   const int64_t row_hi = row_lo + rows_per_split < n ? row_lo + rows_per_split : n;
-  Acc4<T> acc[2][8];
-  double acc64[2][8][4];
+  Acc4<T> acc[2][4];
+  double acc64[2][4][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < 4; ++c) {
       acc[a][c] = Acc4<T>{0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc64[a][c][r] = 0.0;
     }
-  // loader mapping: thread -> (row = t / 8, 16 consecutive columns)
-  const int lr = t >> 3, lc = (t & 7) * 16;
+  // loader mapping: thread -> (row = t / 16, 8 consecutive columns); the next
+  // chunk is fetched into registers while the current one is multiplied
+  const int lr = t >> 4, lc = (t & 15) * 8;
+  T va[8], vr[8];
+  auto fetch = [&](int64_t k0) {
+    const int64_t row = k0 + lr;
+    const bool rok = row < row_hi;
+    const T* as = A + (rok ? row : 0) * lda;
+    const T* rsrc = R + (rok ? row : 0) * ldr;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t j = j0 + lc + e, c = c0 + lc + e;
+      const bool oj = rok && j < d, oc = rok && c < Kc;
+      const T x = as[oj ? j : 0];
+      const T y = rsrc[oc ? c : 0];
+      va[e] = oj ? x : (T)0;
+      vr[e] = oc ? y : (T)0;
+    }
+  };
+  fetch(row_lo);
   int chunk = 0;
   for (int64_t k0 = row_lo; k0 < row_hi; k0 += KC, ++chunk) {
-    {
-      const int64_t row = k0 + lr;
-      const bool rok = row < row_hi;
-      const T* src = A + (rok ? row : 0) * lda;
-      T v[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t j = j0 + lc + e;
-        const bool ok = rok && j < d;
-        const T x = src[ok ? j : 0];
-        v[e] = ok ? x : (T)0;
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) As[lr][lc + e] = v[e];
-    }
-    {
-      const int64_t row = k0 + lr;
-      const bool rok = row < row_hi;
-      const T* src = R + (rok ? row : 0) * ldr;
-      T v[16];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t c = c0 + lc + e;
-        const bool ok = rok && c < Kc;
-        const T x = src[ok ? c : 0];
-        v[e] = ok ? x : (T)0;
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) Rs[lr][lc + e] = v[e];
+    for (int e = 0; e < 8; ++e) {
+      As[lr][lc + e] = va[e];
+      Rs[lr][lc + e] = vr[e];
     }
     __syncthreads();
+    if (k0 + KC < row_hi) fetch(k0 + KC);
 #pragma unroll
     for (int k4 = 0; k4 < KC / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
       T av[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kr][w * 32 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 2; ++a) av[a] = As[kr][wj * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const T bv = Rs[kr][c * 16 + (lane & 15)];
+      for (int c = 0; c < 4; ++c) {
+        const T bv = Rs[kr][wc * 64 + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a][c] = mfma4<T>(av[a], bv, acc[a][c]);
       }
@@ -199,7 +189,7 @@ __global__ __launch_bounds__(256) void k_mr_atr(const T* __restrict__ A, int64_t
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < 4; ++c) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc64[a][c][r] += (double)acc[a][c][r];
           acc[a][c] = Acc4<T>{0, 0, 0, 0};
@@ -211,15 +201,24 @@ __global__ __launch_bounds__(256) void k_mr_atr(const T* __restrict__ A, int64_t
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t j = j0 + w * 32 + a * 16 + mfma16_row<T>(lane, r);
+      const int64_t j = j0 + wj * 32 + a * 16 + mfma16_row<T>(lane, r);
       if (j < d) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int64_t col = c0 + c * 16 + (lane & 15);
+        for (int c = 0; c < 4; ++c) {
+          const int64_t col = c0 + wc * 64 + c * 16 + (lane & 15);
           if (col < Kc) out[j * ldr + col] = acc64[a][c][r] + (double)acc[a][c][r];
         }
       }
     }
+}
+
+// X (FP64) rounded to T once per sweep.
+template <typename T>
+__global__ __launch_bounds__(256) void k_round_x(const double* __restrict__ X, int64_t count,
+                                                 T* __restrict__ XT) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256)
+    XT[i] = (T)X[i];
 }
 
 // G[c][j] = sum_s Gp[s][j][c] (fixed order) + nu2[zl[c / kper]] X[c][j].
@@ -252,16 +251,19 @@ int mr_splits(int64_t n, int64_t d, int64_t Kc, int64_t& rows_per_split) {
 template <typename T>
 rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
                       int64_t Kc, int kper, const double* nu2, const int* zl, T* R, int64_t ldr,
-                      double* Gp, double* G, hipStream_t s) {
+                      double* Gp, double* G, T* XT, hipStream_t s) {
   const int ncb = (int)((Kc + 127) / 128);
+  const int64_t nx = Kc * d;
+  const unsigned g0 = (unsigned)std::min<int64_t>((nx + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_round_x<T>, dim3(g0), dim3(256), 0, s, X, nx, XT);
   const unsigned g1 = (unsigned)(((n + 127) / 128) * ncb);
   int* ran = prof_begin(s);
-  hipLaunchKernelGGL(k_mr_resid<T>, dim3(g1), dim3(256), 0, s, A, n, d, lda, b, X, Kc, R, ldr,
+  hipLaunchKernelGGL(k_mr_resid<T>, dim3(g1), dim3(512), 0, s, A, n, d, lda, b, XT, Kc, R, ldr,
                      ncb, ran);
   int64_t rps = 0;
   const int ns = mr_splits(n, d, Kc, rps);
   const unsigned g2 = (unsigned)(((d + 127) / 128) * ncb);
-  hipLaunchKernelGGL(k_mr_atr<T>, dim3(g2, (unsigned)ns), dim3(256), 0, s, A, n, d, lda, R, ldr,
+  hipLaunchKernelGGL(k_mr_atr<T>, dim3(g2, (unsigned)ns), dim3(512), 0, s, A, n, d, lda, R, ldr,
                      Kc, rps, ncb, Gp);
   prof_end(s);
   const unsigned g3 = (unsigned)std::min<int64_t>((Kc * d + 255) / 256, 4096);
@@ -272,10 +274,10 @@ rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
 
 template rs_status mr_gradient<float>(const float*, int64_t, int64_t, int64_t, const float*,
                                       const double*, int64_t, int, const double*, const int*,
-                                      float*, int64_t, double*, double*, hipStream_t);
+                                      float*, int64_t, double*, double*, float*, hipStream_t);
 template rs_status mr_gradient<double>(const double*, int64_t, int64_t, int64_t, const double*,
                                        const double*, int64_t, int, const double*, const int*,
-                                       double*, int64_t, double*, double*, hipStream_t);
+                                       double*, int64_t, double*, double*, double*, hipStream_t);
 
 // ---------------------------------------------------------------- batched step kernels
 // Slot z (a nu value) owns: x = P.x + z d, vectors P.vec + z 4d (x_prev, g,

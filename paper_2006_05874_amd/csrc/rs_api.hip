@@ -144,7 +144,7 @@ struct DeviceScratch {
   // nu grid: per-slot state, candidate blocks, multi-RHS products, batched
   // factors, uploads, and the per-level sketch / Gram cache
   DevBuf g_vec, g_ctl, g_ev, g_hinv, g_rpart, g_xc, g_gc, g_gtc, g_nu2, g_up, g_R, g_Gp, g_M, g_L,
-      g_Cw;
+      g_Cw, g_xt;
   std::vector<std::unique_ptr<DevBuf>> lv_sa, lv_scale, lv_gram;
   void* g_pinned = nullptr;
   size_t g_pinned_bytes = 0;
@@ -1287,11 +1287,13 @@ struct NuGrid {
       return mr_gradient<float>(reinterpret_cast<const float*>(base.A), base.n, base.d, base.lda,
                                 reinterpret_cast<const float*>(base.b), Xsrc, Kc, kper,
                                 S->g_nu2.as<double>(), zl, S->g_R.as<float>(), ldr(),
-                                S->g_Gp.as<double>(), S->g_gc.as<double>(), s);
+                                S->g_Gp.as<double>(), S->g_gc.as<double>(),
+                                S->g_xt.as<float>(), s);
     return mr_gradient<double>(reinterpret_cast<const double*>(base.A), base.n, base.d, base.lda,
                                reinterpret_cast<const double*>(base.b), Xsrc, Kc, kper,
                                S->g_nu2.as<double>(), zl, S->g_R.as<double>(), ldr(),
-                               S->g_Gp.as<double>(), S->g_gc.as<double>(), s);
+                               S->g_Gp.as<double>(), S->g_gc.as<double>(),
+                               S->g_xt.as<double>(), s);
   }
   int64_t ldr() const { return (2 * count + 3) / 4 * 4; }
 
@@ -1321,6 +1323,7 @@ struct NuGrid {
     RS_TRY(S->g_xc.ensure((size_t)count * 2 * d * 8));
     RS_TRY(S->g_gc.ensure((size_t)count * 2 * d * 8));
     RS_TRY(S->g_gtc.ensure((size_t)count * 2 * d * 8));
+    RS_TRY(S->g_xt.ensure((size_t)count * 2 * d * 8));
     RS_TRY(S->g_nu2.ensure((size_t)count * 8));
     RS_TRY(S->g_R.ensure((size_t)base.n * ldr() * es));
     int64_t rps = 0;

@@ -171,7 +171,7 @@ int mr_splits(int64_t n, int64_t d, int64_t Kc, int64_t& rows_per_split);
 template <typename T>
 rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
                       int64_t Kc, int kper, const double* nu2, const int* zl, T* R, int64_t ldr,
-                      double* Gp, double* G, hipStream_t s);
+                      double* Gp, double* G, T* XT, hipStream_t s);
 rs_status grid_candidates(const GridPtrs& P, int nl, int K, int64_t d, double mu_p, double beta_p,
                           double mu_gd, hipStream_t s);
 rs_status grid_pack(const GridPtrs& P, int nl, int64_t d, int what, hipStream_t s);
