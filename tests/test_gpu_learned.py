@@ -186,3 +186,28 @@ def test_learned_batch_equals_single_learned_solves(rs):
         A64 = p.A.astype(np.float64)
         xs = ridge.solve_direct(A64, p.b.astype(np.float64), nu2)
         assert ridge.relative_error(ridge.hessian(A64, nu2), host(x), xs) <= 1e-6
+
+
+def test_full_size_65536x1024_learned_bf16_batched_and_plain(rs):
+    # the benchmark's problem and launch configuration: both nu^2 solved as one
+    # learned + BF16 batch over two streams, and by the plain FP32 method; every
+    # solution against the oracle's FP64 solution of the stored problem
+    from paper_2006_05874_amd import learned as L
+    from synth import config_c2
+    p = config_c2(nu2=1e-2, seed=0)
+    A = dev_padded(p.A, rs)
+    b = torch.from_numpy(p.b).cuda()
+    params, mu, sd, _ = L.load_model()
+    nus = (1e-2, 1e-4)
+    res = rs.rs_learned_solve_batch([(A, b, nu) for nu in nus], params, mu, sd,
+                                    sketch_dtype="bf16", workers=2)
+    A64 = p.A.astype(np.float64)
+    G = A64.T @ A64
+    Atb = A64.T @ p.b.astype(np.float64)
+    for nu, (x, info) in zip(nus, res):
+        assert info["status"] == "ok"
+        xs = ridge.solve_direct_from_gram(G, Atb, nu)
+        assert ridge.relative_error(G + nu * np.eye(1024), host(x), xs) <= 1e-6
+        xp, ip = rs.rs_adaptive_solve(A, b, nu, sketch_dtype="f32")
+        assert ip["status"] == "ok"
+        assert ridge.relative_error(G + nu * np.eye(1024), host(xp), xs) <= 1e-6

@@ -128,3 +128,32 @@ def test_precision_form_reaches_oracle_solution(rs, problem, kind, dt):
     assert info["status"] == "ok", info
     rel = ridge.relative_error(H, host(x), xs)
     assert rel <= 1e-6, rel
+
+
+def test_precision_form_full_size_2p20x4096(rs):
+    # the 2^20 x 4096 FP32 problem (16 GiB, sigma_i = exp(-i/400), nu^2 = 1e-3):
+    # BF16 and FP8 sketches, and the learned start with BF16 sketches, each against
+    # the oracle's FP64 solution from a Gram accumulated from the stored A
+    from paper_2006_05874_amd import learned as L
+    from synth import make_problem_torch, spectrum
+    n, d = 1 << 20, 4096
+    sig = spectrum("exp", d, 400.0)
+    nu2 = 1e-3 * float(sig[0]) ** 2
+    A0, b, _ = make_problem_torch(n, d, sig, 0.1, 3, "cuda")
+    A = rs.padded(n, d, dtype=torch.float32)
+    A.copy_(A0)
+    del A0
+    params, mu, sd, _ = L.load_model()
+    sols = {dt: rs.rs_adaptive_solve(A, b, nu2, sketch_dtype=dt) for dt in ("bf16", "fp8")}
+    sols["learned_bf16"] = rs.rs_learned_solve(A, b, nu2, params, mu, sd, sketch_dtype="bf16")
+    G = np.zeros((d, d))
+    Atb = np.zeros(d)
+    for r0 in range(0, n, 65536):
+        Ac = A[r0:r0 + 65536].cpu().numpy().astype(np.float64)
+        G += Ac.T @ Ac
+        Atb += Ac.T @ b[r0:r0 + 65536].cpu().numpy().astype(np.float64)
+    xs = ridge.solve_direct_from_gram(G, Atb, nu2)
+    H = G + nu2 * np.eye(d)
+    for name, (x, info) in sols.items():
+        assert info["status"] == "ok", name
+        assert ridge.relative_error(H, x.cpu().numpy(), xs) <= 1e-6, name
