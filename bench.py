@@ -542,9 +542,10 @@ def run_c4a(args):
 
 def run_c4b(args):
     """256 independent problems (n = 2^U{12..16}, d = U{128..1024}, sigma_i =
-    0.95^i, nu^2 = 1e-3): batched solves over worker streams with BF16 sketches
-    against the same problems solved one after another by the plain method (FP32
-    sketch).  Every solution is checked against the oracle's direct solve."""
+    0.95^i, nu^2 = 1e-3): learned-start batched solves over worker streams with
+    BF16 sketches (the value), the same batch starting at m = 1, and the problems
+    solved one after another by the plain method (FP32 sketch).  Every solution is
+    checked against the oracle's direct solve."""
     import torch
     from oracle import ridge
     from paper_2006_05874_amd import rs
@@ -561,6 +562,13 @@ def run_c4b(args):
     torch.cuda.synchronize()
     print(f"[c4b] {len(probs)} problems ready", file=sys.stderr, flush=True)
 
+    from paper_2006_05874_amd import learned
+    params, mu, sd, _ = learned.load_model(args.model or learned.MODEL_PATH)
+
+    def run_learned():
+        return rs.rs_learned_solve_batch(probs, params, mu, sd, sketch_dtype="bf16", workers=8,
+                                         raise_on_error=False)
+
     def run_batch():
         return rs.rs_solve_batch(probs, sketch_dtype="bf16", workers=8, raise_on_error=False)
 
@@ -569,8 +577,9 @@ def run_c4b(args):
                 for A, b, nu2 in probs]
 
     out = {}
-    for name, fn in (("batched_bf16", run_batch), ("sequential_plain_f32", run_seq)):
-        fn()                                   # warm-up (allocations)
+    for name, fn in (("learned_bf16_batched", run_learned), ("batched_bf16", run_batch),
+                     ("sequential_plain_f32", run_seq)):
+        fn()                                   # warm-up (allocations, graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -598,18 +607,20 @@ def run_c4b(args):
         out[k]["worst_rel_pred_err"] = worst[k]
         out[k]["not_ok"] = bad[k]
     line = {"metric": "ridge solves/s to 1e-6 rel. pred. error, batched uneven problems",
-            "value": out["batched_bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "value": out["learned_bf16_batched"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1,
-            "ms_per_step": round(out["batched_bf16"]["s_per_batch"] * 1e3, 3),
+            "ms_per_step": round(out["learned_bf16_batched"]["s_per_batch"] * 1e3, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
             "config": {"workload": "256 problems, n=2^U{12..16}, d=U{128..1024}, "
-                                   "sigma_i=0.95^i, nu^2=1e-3, SRHT, 8 worker streams"},
+                                   "sigma_i=0.95^i, nu^2=1e-3, SRHT, 8 worker streams, "
+                                   "learned start + BF16 sketches, steps replayed from HIP graphs"},
             "verified": all(v["worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
                             for v in out.values()),
             "modes": out,
             "speedup_vs_sequential_plain_f32": round(
-                out["batched_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
+                out["learned_bf16_batched"]["solves_per_s"] /
+                out["sequential_plain_f32"]["solves_per_s"], 3)}
     print(json.dumps(line))
 
 
