@@ -113,3 +113,35 @@ def test_solver_argument_errors(lib):
     st = lib.rs_adaptive_solve(vp(256), 1, 64, 16, 16, vp(256), 0.1, ctypes.byref(o), vp(256),
                                ctypes.byref(info), vp(0))
     assert st == 1
+
+
+def test_batch_and_grid_argument_errors_before_device_work(lib):
+    from paper_2006_05874_amd import rs
+    vp = ctypes.c_void_p
+    opts = rs.SolveOpts()
+    lib.rs_solve_opts_default(ctypes.byref(opts))
+    infos = (rs.SolveInfo * 2)()
+    # empty batch: nothing to do
+    assert lib.rs_solve_batch((rs.Problem * 1)(), 0, ctypes.byref(opts), infos, 2, vp(0)) == 0
+    # a problem with nu^2 <= 0 is rejected before any job starts
+    P = (rs.Problem * 1)()
+    P[0] = rs.Problem(vp(256), 1, 0, 100, 10, 12, vp(256), -1.0, vp(256))
+    assert lib.rs_solve_batch(P, 1, ctypes.byref(opts), infos, 2, vp(0)) == 4
+    # the learned batch needs a model
+    assert lib.rs_learned_solve_batch(P, 1, ctypes.byref(opts), vp(0), vp(0), vp(0), infos,
+                                      None, 2, vp(0)) == 1
+    # nu grid: count, nu^2 and null checks
+    nu = (ctypes.c_double * 2)(1e-2, 0.0)
+    assert lib.rs_solve_nu_grid(vp(256), 1, 100, 10, 12, vp(256), nu, 0, ctypes.byref(opts),
+                                vp(256), infos, vp(0)) == 1
+    assert lib.rs_solve_nu_grid(vp(256), 1, 100, 10, 12, vp(256), nu, 2, ctypes.byref(opts),
+                                vp(256), infos, vp(0)) == 4
+    assert lib.rs_solve_nu_grid(vp(256), 1, 100, 10, 12, vp(256), None, 2, ctypes.byref(opts),
+                                vp(256), infos, vp(0)) == 1
+    # autotuner: k out of range, misaligned lda
+    assert lib.rs_gradient_autotune(vp(256), 1, 100, 10, 12, vp(256), 5, None, vp(0)) == 1
+    assert lib.rs_gradient_autotune(vp(256), 1, 100, 10, 10, vp(256), 2, None, vp(0)) == 1
+    # plan query: bad shapes
+    plan = (ctypes.c_int32 * 3)()
+    assert lib.rs_gradient_plan(1, 100, 10, 0, ctypes.cast(plan, vp)) == 2
+    assert lib.rs_gradient_plan(2, 100, 10, 1, ctypes.cast(plan, vp)) == 1
