@@ -22,11 +22,16 @@ __device__ __forceinline__ double gauss_at<double>(uint64_t seed, uint32_t sid, 
   return gauss_f64(seed, sid, idx);
 }
 
+// Rows k_off .. m-1 of SA (earlier rows untouched).  With split > 0 the block
+// sums only A's rows [z * split, (z+1) * split) (z = blockIdx.z) and writes its
+// unscaled partial to P[z] (rows k - k_off, leading dimension d) instead.
 template <typename T, typename OutT>
 __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, int64_t n, int64_t d,
                                                       int64_t lda, int64_t m, uint64_t seed,
                                                       uint32_t sid, double scale,
-                                                      OutT* __restrict__ SA, int64_t ldsa) {
+                                                      OutT* __restrict__ SA, int64_t ldsa,
+                                                      int64_t k_off, int64_t split,
+                                                      T* __restrict__ P) {
   constexpr int TM = 64, TD = 128, KC = 16;
   __shared__ T Ss[KC][TM + 1];  // Ss[j][k] = S[k0 + k][j0 + j]
   __shared__ T As[KC][TD + 1];  // As[j][c] = A[j0 + j][c0 + c]
@@ -34,7 +39,7 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
   const int lane = t & 63;
   const int w = t >> 6;
   const int wr = w >> 1, wc = w & 1;  // wave quadrant: 32 rows x 64 cols
-  const int64_t k0 = (int64_t)blockIdx.y * TM;
+  const int64_t k0 = k_off + (int64_t)blockIdx.y * TM;
   const int64_t c0 = (int64_t)blockIdx.x * TD;
   using Acc4 = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
   Acc4 acc[2][4];
@@ -43,14 +48,16 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = Acc4{0, 0, 0, 0};
 
-  for (int64_t j0 = 0; j0 < n; j0 += KC) {
+  const int64_t jlo = split > 0 ? (int64_t)blockIdx.z * split : 0;
+  const int64_t jhi = split > 0 ? (jlo + split < n ? jlo + split : n) : n;
+  for (int64_t j0 = jlo; j0 < jhi; j0 += KC) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {  // S slice: 64 x 16 = 1024 draws
       const int idx = t * 4 + e;
       const int kk = idx / KC, jj = idx % KC;
       const int64_t k = k0 + kk, j = j0 + jj;
       T v = 0;
-      if (k < m && j < n) v = gauss_at<T>(seed, sid, (uint64_t)k * (uint64_t)n + (uint64_t)j);
+      if (k < m && j < jhi) v = gauss_at<T>(seed, sid, (uint64_t)k * (uint64_t)n + (uint64_t)j);
       Ss[jj][kk] = v;
     }
 #pragma unroll
@@ -58,7 +65,7 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
       const int idx = t * 8 + e;
       const int jj = idx / TD, cc = idx % TD;
       const int64_t j = j0 + jj, c = c0 + cc;
-      As[jj][cc] = (j < n && c < d) ? A[j * lda + c] : (T)0;
+      As[jj][cc] = (j < jhi && c < d) ? A[j * lda + c] : (T)0;
     }
     __syncthreads();
 #pragma unroll
@@ -88,37 +95,132 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
         const int64_t k = k0 + wr * 32 + a * 16 + mfma16_row<T>(lane, r);
         const int64_t c = c0 + wc * 64 + b * 16 + (lane & 15);
         if (k < m && c < d) {
-          const double v = (double)acc[a][b][r] * scale;
-          if constexpr (sizeof(OutT) == 2)
-            SA[k * ldsa + c] = f32_to_bf16_rne((float)v);
-          else
-            SA[k * ldsa + c] = (OutT)v;
+          if (split > 0) {
+            P[((int64_t)blockIdx.z * (m - k_off) + (k - k_off)) * d + c] = acc[a][b][r];
+          } else {
+            const double v = (double)acc[a][b][r] * scale;
+            if constexpr (sizeof(OutT) == 2)
+              SA[k * ldsa + c] = f32_to_bf16_rne((float)v);
+            else
+              SA[k * ldsa + c] = (OutT)v;
+          }
         }
       }
 }
 
+// SA[k] = scale * sum_z P[z][k - k_off] (fixed order, FP64) for rows k_off .. m-1.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(256) void k_gauss_reduce(const T* __restrict__ P, int nz,
+                                                      int64_t rows, int64_t d, int64_t k_off,
+                                                      double scale, OutT* __restrict__ SA,
+                                                      int64_t ldsa) {
+  const int64_t r = blockIdx.x;
+  for (int64_t c = threadIdx.x; c < d; c += 256) {
+    double v = 0.0;
+    for (int z = 0; z < nz; ++z) v += (double)P[((int64_t)z * rows + r) * d + c];
+    v *= scale;
+    if constexpr (sizeof(OutT) == 2)
+      SA[(k_off + r) * ldsa + c] = f32_to_bf16_rne((float)v);
+    else
+      SA[(k_off + r) * ldsa + c] = (OutT)v;
+  }
+}
+
+// Splits of the summed dimension (A's rows) so that the launch fills the chip
+// when m is small; the partials go through P (gauss_split_bytes of scratch).
+static int gauss_splits(int64_t n, int64_t d, int64_t rows) {
+  const int64_t tiles = ((d + 127) / 128) * ((rows + 63) / 64);
+  int64_t z = (2 * device_cus() + tiles - 1) / tiles;
+  z = std::max<int64_t>(1, std::min<int64_t>(z, (n + 1023) / 1024));
+  return (int)std::min<int64_t>(z, 64);
+}
+
+size_t gauss_split_bytes(int64_t n, int64_t d, int64_t rows, rs_dtype a_t) {
+  const int z = gauss_splits(n, d, rows);
+  return z > 1 ? (size_t)z * rows * d * (a_t == RS_F64 ? 8 : 4) : 0;
+}
+
+template <typename T, typename OutT>
+static void gauss_go(const T* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed,
+                     uint32_t sid, double scale, OutT* SA, int64_t ldsa, int64_t k_off,
+                     void* part, size_t part_bytes, hipStream_t s) {
+  const int64_t rows = m - k_off;
+  const int z = gauss_splits(n, d, rows);
+  const size_t need = (size_t)z * rows * d * sizeof(T);
+  if (z > 1 && part && part_bytes >= need) {
+    const int64_t split = ((n + z - 1) / z + 15) / 16 * 16;
+    const unsigned nz = (unsigned)((n + split - 1) / split);
+    const dim3 grid((unsigned)((d + 127) / 128), (unsigned)((rows + 63) / 64), nz);
+    hipLaunchKernelGGL((k_gauss_sketch<T, OutT>), grid, dim3(256), 0, s, A, n, d, lda, m, seed,
+                       sid, scale, SA, ldsa, k_off, split, reinterpret_cast<T*>(part));
+    hipLaunchKernelGGL((k_gauss_reduce<T, OutT>), dim3((unsigned)rows), dim3(256), 0, s,
+                       reinterpret_cast<const T*>(part), (int)nz, rows, d, k_off, scale, SA, ldsa);
+  } else {
+    const dim3 grid((unsigned)((d + 127) / 128), (unsigned)((rows + 63) / 64));
+    hipLaunchKernelGGL((k_gauss_sketch<T, OutT>), grid, dim3(256), 0, s, A, n, d, lda, m, seed,
+                       sid, scale, SA, ldsa, k_off, (int64_t)0, (T*)nullptr);
+  }
+}
+
 rs_status gauss_launch(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
                        uint64_t seed, uint32_t sid, void* SA, rs_dtype sa_t, int64_t ldsa,
-                       hipStream_t s) {
-  const dim3 grid((unsigned)((d + 127) / 128), (unsigned)((m + 63) / 64));
-  const double scale = 1.0 / std::sqrt((double)m);
+                       hipStream_t s, int64_t k_off, double scale_override, void* part,
+                       size_t part_bytes) {
+  if (k_off >= m) return RS_OK;
+  const double scale = scale_override > 0.0 ? scale_override : 1.0 / std::sqrt((double)m);
   if (a_t == RS_F64) {
     if (sa_t != RS_F64) return set_error(RS_ERR_UNSUPPORTED, "gaussian: F64 A needs F64 SA");
-    hipLaunchKernelGGL((k_gauss_sketch<double, double>), grid, dim3(256), 0, s,
-                       reinterpret_cast<const double*>(A), n, d, lda, m, seed, sid, scale,
-                       reinterpret_cast<double*>(SA), ldsa);
+    gauss_go<double, double>(reinterpret_cast<const double*>(A), n, d, lda, m, seed, sid, scale,
+                             reinterpret_cast<double*>(SA), ldsa, k_off, part, part_bytes, s);
   } else if (sa_t == RS_F32) {
-    hipLaunchKernelGGL((k_gauss_sketch<float, float>), grid, dim3(256), 0, s,
-                       reinterpret_cast<const float*>(A), n, d, lda, m, seed, sid, scale,
-                       reinterpret_cast<float*>(SA), ldsa);
+    gauss_go<float, float>(reinterpret_cast<const float*>(A), n, d, lda, m, seed, sid, scale,
+                           reinterpret_cast<float*>(SA), ldsa, k_off, part, part_bytes, s);
   } else if (sa_t == RS_BF16) {
-    hipLaunchKernelGGL((k_gauss_sketch<float, uint16_t>), grid, dim3(256), 0, s,
-                       reinterpret_cast<const float*>(A), n, d, lda, m, seed, sid, scale,
-                       reinterpret_cast<uint16_t*>(SA), ldsa);
+    gauss_go<float, uint16_t>(reinterpret_cast<const float*>(A), n, d, lda, m, seed, sid, scale,
+                              reinterpret_cast<uint16_t*>(SA), ldsa, k_off, part, part_bytes, s);
   } else {
     return set_error(RS_ERR_UNSUPPORTED, "gaussian: SA dtype not supported");
   }
   return check_launch("gaussian sketch");
+}
+
+// SA = scale * G for the cached unscaled rows G (m x d, leading dimension d) of
+// the nested Gaussian sketch: the same product and rounding as the sketch
+// kernel's output stage.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(256) void k_gauss_scale(const T* __restrict__ G, int64_t d,
+                                                     double scale, OutT* __restrict__ SA,
+                                                     int64_t ldsa) {
+  const int64_t k = blockIdx.x;
+  for (int64_t c = threadIdx.x; c < d; c += 256) {
+    const double v = (double)G[k * d + c] * scale;
+    if constexpr (sizeof(OutT) == 2)
+      SA[k * ldsa + c] = f32_to_bf16_rne((float)v);
+    else
+      SA[k * ldsa + c] = (OutT)v;
+  }
+}
+
+rs_status gauss_scale_rows(const void* G, rs_dtype g_t, int64_t m, int64_t d, double scale,
+                           void* SA, rs_dtype sa_t, int64_t ldsa, hipStream_t s) {
+  const dim3 g((unsigned)m);
+  if (g_t == RS_F64) {
+    if (sa_t != RS_F64) return set_error(RS_ERR_UNSUPPORTED, "gaussian: F64 A needs F64 SA");
+    hipLaunchKernelGGL((k_gauss_scale<double, double>), g, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(G), d, scale,
+                       reinterpret_cast<double*>(SA), ldsa);
+  } else if (sa_t == RS_F32) {
+    hipLaunchKernelGGL((k_gauss_scale<float, float>), g, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(G), d, scale, reinterpret_cast<float*>(SA),
+                       ldsa);
+  } else if (sa_t == RS_BF16) {
+    hipLaunchKernelGGL((k_gauss_scale<float, uint16_t>), g, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(G), d, scale,
+                       reinterpret_cast<uint16_t*>(SA), ldsa);
+  } else {
+    return set_error(RS_ERR_UNSUPPORTED, "gaussian: SA dtype not supported");
+  }
+  return check_launch("gaussian scale");
 }
 
 }  // namespace rs

@@ -546,7 +546,7 @@ static void launch_tile(dim3 grid, hipStream_t s, const T* src, int64_t nsrc, in
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
-                         int64_t Qmax, hipStream_t s) {
+                         int64_t Qmax, hipStream_t s, double scale_override) {
   using TT = Tile<T>;
   const int64_t n2 = npad < TT::RT ? npad : TT::RT;
   const int64_t n1 = npad / n2;
@@ -555,7 +555,7 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
   int lb1 = 0;
   while (((int64_t)1 << lb1) < n1) ++lb1;
   const unsigned panels = (unsigned)((d + TT::W - 1) / TT::W);
-  const double scale = 1.0 / std::sqrt((double)m);
+  const double scale = scale_override > 0.0 ? scale_override : 1.0 / std::sqrt((double)m);
   const bool bf16 = sa_t == RS_BF16;
   if constexpr (sizeof(T) == 8) {
     if (bf16) return set_error(RS_ERR_UNSUPPORTED, "srht: BF16 output needs FP32 input");
@@ -596,9 +596,53 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
 
 template rs_status srht_transform<float>(const SrhtBuffers&, const float*, int64_t, int64_t,
                                          int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
-                                         int64_t, hipStream_t);
+                                         int64_t, hipStream_t, double);
 template rs_status srht_transform<double>(const SrhtBuffers&, const double*, int64_t, int64_t,
                                           int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
-                                          int64_t, hipStream_t);
+                                          int64_t, hipStream_t, double);
+
+// ---------------------------------------------------------------- nested gather
+// SA[k] = scale * HDA[rows[k]] for the cached transform of the whole padded A
+// (nested resampling keeps signs and keys, so every level's rows index the same
+// H D A).  One block per row; the product and rounding are those of the direct
+// transform's output stage.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ H, int64_t ldh,
+                                                     const int64_t* __restrict__ rows,
+                                                     int64_t d, double scale,
+                                                     OutT* __restrict__ SA, int64_t ldsa) {
+  const int64_t k = blockIdx.x;
+  const T* src = H + rows[k] * ldh;
+  OutT* dst = SA + k * ldsa;
+  for (int64_t c = threadIdx.x; c < d; c += 256) {
+    if constexpr (sizeof(OutT) == 2)
+      dst[c] = f32_to_bf16_rne((float)src[c] * (float)scale);
+    else
+      dst[c] = (OutT)(src[c] * (T)scale);
+  }
+}
+
+rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* rows, int64_t m,
+                      int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
+                      hipStream_t s) {
+  const dim3 g((unsigned)m);
+  if (h_t == RS_F64) {
+    if (sa_t != RS_F64) return set_error(RS_ERR_UNSUPPORTED, "gather: F64 data needs F64 SA");
+    hipLaunchKernelGGL((k_gather_rows<double, double>), g, dim3(256), 0, s,
+                       reinterpret_cast<const double*>(H), ldh, rows, d, scale,
+                       reinterpret_cast<double*>(SA), ldsa);
+  } else if (sa_t == RS_BF16) {
+    hipLaunchKernelGGL((k_gather_rows<float, uint16_t>), g, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(H), ldh, rows, d, scale,
+                       reinterpret_cast<uint16_t*>(SA), ldsa);
+  } else if (sa_t == RS_F32) {
+    hipLaunchKernelGGL((k_gather_rows<float, float>), g, dim3(256), 0, s,
+                       reinterpret_cast<const float*>(H), ldh, rows, d, scale,
+                       reinterpret_cast<float*>(SA), ldsa);
+  } else {
+    return set_error(RS_ERR_UNSUPPORTED, "gather: SA dtype not supported");
+  }
+  return check_launch("srht gather");
+}
 
 }  // namespace rs

@@ -117,6 +117,29 @@ struct DevBuf {
     bytes = sz;
     return RS_OK;
   }
+  // grow-only, keeping the first `keep` bytes (copied on the stream, which is
+  // synchronized before the old block is released)
+  rs_status grow_keep(size_t want, size_t keep, hipStream_t s) {
+    if (want <= bytes && p) return RS_OK;
+    void* np = nullptr;
+    hipError_t e = hipMalloc(&np, want);
+    if (e != hipSuccess) {
+      g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? RS_ERR_OOM : RS_ERR_HIP;
+    }
+    if (p && keep) {
+      e = hipMemcpyAsync(np, p, keep, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        (void)hipFree(np);
+        return set_error(RS_ERR_HIP, "grow_keep: copy failed");
+      }
+    }
+    if (p) (void)hipFree(p);
+    p = np;
+    bytes = want;
+    return RS_OK;
+  }
   template <typename T>
   T* as() const {
     return reinterpret_cast<T*>(p);
@@ -139,6 +162,10 @@ struct DeviceScratch {
   DevBuf sa, fM, fLinv, fHinv, fCw, fGram;
   // FP8 staging: FP32 sketch, column maxima, per-column scales
   DevBuf sa_tmp, colmax, sa_scale;
+  // nested resampling: H D A of the whole padded A, and the unscaled Gaussian rows
+  DevBuf hda, graw;
+  // split partial products of the Gaussian sketch
+  DevBuf gpart;
   // learned form: probe sketch and its factor, probe sums, features
   DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
   // nu grid: per-slot state, candidate blocks, multi-RHS products, batched
@@ -294,12 +321,82 @@ static rs_status check_sa_type(rs_dtype a_t, rs_dtype sa_t) {
 static rs_status gauss_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                            int64_t lda, int64_t m, uint64_t seed, uint32_t sid, void* SA,
                            rs_dtype sa_t, int64_t ldsa, float* scale_out, hipStream_t s) {
-  if (sa_t != RS_FP8E4M3) return gauss_launch(A, a_t, n, d, lda, m, seed, sid, SA, sa_t, ldsa, s);
+  RS_TRY(S.gpart.ensure(std::max<size_t>(gauss_split_bytes(n, d, m, a_t), 256)));
+  if (sa_t != RS_FP8E4M3)
+    return gauss_launch(A, a_t, n, d, lda, m, seed, sid, SA, sa_t, ldsa, s, 0, 0.0, S.gpart.p,
+                        S.gpart.bytes);
   RS_TRY(S.sa_tmp.ensure((size_t)m * d * sizeof(float)));
   RS_TRY(S.colmax.ensure((size_t)d * sizeof(uint32_t)));
-  RS_TRY(gauss_launch(A, a_t, n, d, lda, m, seed, sid, S.sa_tmp.p, RS_F32, d, s));
+  RS_TRY(gauss_launch(A, a_t, n, d, lda, m, seed, sid, S.sa_tmp.p, RS_F32, d, s, 0, 0.0,
+                      S.gpart.p, S.gpart.bytes));
   return quantize_fp8(S.sa_tmp.as<float>(), m, d, d, S.colmax.as<uint32_t>(), scale_out,
                       reinterpret_cast<uint8_t*>(SA), ldsa, s);
+}
+
+// Nested resampling keeps the sketch's randomness from level to level: the
+// SRHT's signs and keys (so H D A is computed once, at the first level, and every
+// level gathers its sampled rows from it) and the Gaussian's rows (each level
+// computes only its new rows, unscaled, and scales all of them by 1/sqrt(m)).
+// The values are those of the direct sketch: the same products and roundings.
+struct NestedCache {
+  bool hda_ready = false;
+  int64_t graw_rows = 0;
+};
+
+static rs_status nested_sketch(DeviceScratch& S, NestedCache& C, bool srht, const void* A,
+                               rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
+                               uint64_t seed, uint32_t sid, void* SA, rs_dtype sa_t,
+                               int64_t ldsa, float* scale_out, hipStream_t s) {
+  const int64_t es = (int64_t)dtype_size(a_t);
+  void* dst = SA;
+  rs_dtype dst_t = sa_t;
+  int64_t ldd = ldsa;
+  if (sa_t == RS_FP8E4M3) {  // through an FP32 stage and the per-column quantizer
+    RS_TRY(S.sa_tmp.ensure((size_t)m * d * sizeof(float)));
+    RS_TRY(S.colmax.ensure((size_t)d * sizeof(uint32_t)));
+    dst = S.sa_tmp.p;
+    dst_t = RS_F32;
+    ldd = d;
+  }
+  const double scale = 1.0 / std::sqrt((double)m);
+  if (srht) {
+    const int64_t npad = next_pow2(n);
+    const int64_t n2 = std::min<int64_t>(npad, 1024);
+    const int64_t vec = 16 / es;
+    const int64_t ldh = (d + vec - 1) / vec * vec;
+    SrhtBuffers B;
+    RS_TRY(S.rows.ensure((size_t)npad * sizeof(int64_t)));
+    if (!C.hda_ready) {
+      const int64_t n1 = npad / n2;
+      RS_TRY(ensure_srht(S, npad, n1 > 1 ? n1 * n2 * ldh * es : 0, B));
+      RS_TRY(S.hda.ensure((size_t)npad * ldh * es));
+      RS_TRY(srht_select(B, seed, sid, npad, npad, n2, S.rows.as<int64_t>(), s));
+      if (a_t == RS_F32)
+        RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, npad,
+                                     S.hda.p, RS_F32, ldh, n2, s, 1.0));
+      else
+        RS_TRY(srht_transform<double>(B, reinterpret_cast<const double*>(A), n, d, lda, npad,
+                                      npad, S.hda.p, RS_F64, ldh, n2, s, 1.0));
+      C.hda_ready = true;
+    } else {
+      RS_TRY(ensure_srht(S, npad, 0, B));
+    }
+    RS_TRY(srht_select(B, seed, sid, npad, m, n2, S.rows.as<int64_t>(), s));
+    RS_TRY(srht_gather(S.hda.p, a_t, ldh, S.rows.as<int64_t>(), m, d, scale, dst, dst_t, ldd, s));
+  } else {
+    if (m > C.graw_rows) {
+      RS_TRY(S.graw.grow_keep((size_t)m * d * es, (size_t)C.graw_rows * d * es, s));
+      RS_TRY(S.gpart.ensure(std::max<size_t>(gauss_split_bytes(n, d, m - C.graw_rows, a_t), 256)));
+      RS_TRY(gauss_launch(A, a_t, n, d, lda, m, seed, sid, S.graw.p, a_t, d, s, C.graw_rows,
+                          1.0, S.gpart.p, S.gpart.bytes));
+      C.graw_rows = m;
+    }
+    RS_TRY(gauss_scale_rows(S.graw.p, a_t, m, d, scale, dst, dst_t, ldd, s));
+  }
+  if (sa_t == RS_FP8E4M3)
+    return quantize_fp8(S.sa_tmp.as<float>(), m, d, d, S.colmax.as<uint32_t>(), scale_out,
+                        reinterpret_cast<uint8_t*>(SA), ldsa, s);
+  return RS_OK;
 }
 
 }  // namespace rs
@@ -803,6 +900,7 @@ struct SolveJob {
   // for the job's lifetime
   bool use_graph = false;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
+  NestedCache ncache;
 
   SolveJob() = default;
   SolveJob(const SolveJob&) = delete;
@@ -883,7 +981,10 @@ struct SolveJob {
     RS_TRY(S->sa.ensure((size_t)mm * ldsa * sa_es));
     RS_TRY(S->sa_scale.ensure((size_t)d * sizeof(float)));
     float* scl = sa_t == RS_FP8E4M3 ? S->sa_scale.as<float>() : nullptr;
-    if (srht)
+    if (o.resample == RS_RESAMPLE_NESTED)
+      RS_TRY(nested_sketch(*S, ncache, srht, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t,
+                           ldsa, scl, stream));
+    else if (srht)
       RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, nullptr,
                       nullptr, stream));
     else
@@ -1177,6 +1278,7 @@ namespace rs {
 // decision launch.  Slots that are not running skip their share on the device.
 struct NuGrid {
   SolveJob base;  // argument checks and derived sizes (nu of slot 0)
+  NestedCache ncache;
   const double* nu2h = nullptr;
   int64_t count = 0;
   double* X = nullptr;
@@ -1232,7 +1334,10 @@ struct NuGrid {
     RS_TRY(gr.ensure(factor_bytes_gram(mL, base.d, base.sa_t)));
     const uint32_t sid = base.o.resample == RS_RESAMPLE_FRESH ? (uint32_t)L : 0u;
     float* scl = base.sa_t == RS_FP8E4M3 ? sc.as<float>() : nullptr;
-    if (base.srht)
+    if (base.o.resample == RS_RESAMPLE_NESTED)
+      RS_TRY(nested_sketch(*S, ncache, base.srht, base.A, base.a_t, base.n, base.d, base.lda, mL,
+                           base.o.seed, sid, sa.p, base.sa_t, base.ldsa, scl, s));
+    else if (base.srht)
       RS_TRY(srht_run(*S, base.A, base.a_t, base.n, base.d, base.lda, mL, base.o.seed, sid, sa.p,
                       base.sa_t, base.ldsa, scl, nullptr, nullptr, s));
     else

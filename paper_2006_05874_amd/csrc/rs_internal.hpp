@@ -39,15 +39,24 @@ rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
-                         int64_t Qmax, hipStream_t s);
+                         int64_t Qmax, hipStream_t s, double scale_override = 0.0);
+rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* rows, int64_t m,
+                      int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
+                      hipStream_t s);
 size_t srht_state_bytes();
 int srht_cand_cap();
 int srht_compact_block();
 
 // ---------------------------------------------------------------- Gaussian
+rs_status gauss_scale_rows(const void* G, rs_dtype g_t, int64_t m, int64_t d, double scale,
+                           void* SA, rs_dtype sa_t, int64_t ldsa, hipStream_t s);
+// part: scratch of at least gauss_split_bytes(n, d, m - k_off, a_t) bytes for the
+// split over A's rows (without it the launch runs unsplit).
+size_t gauss_split_bytes(int64_t n, int64_t d, int64_t rows, rs_dtype a_t);
 rs_status gauss_launch(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
                        uint64_t seed, uint32_t sid, void* SA, rs_dtype sa_t, int64_t ldsa,
-                       hipStream_t s);
+                       hipStream_t s, int64_t k_off = 0, double scale_override = 0.0,
+                       void* part = nullptr, size_t part_bytes = 0);
 
 // ---------------------------------------------------------------- factor
 struct FactorBuffers {
