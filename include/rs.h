@@ -157,9 +157,11 @@ typedef struct {
  * partial-sum shape that covers d (threads per row x 16-byte vectors per thread)
  * at 1, 2 and 4 blocks per CU on this problem (k right-hand sides) and keeps the
  * fastest for (dtype, n rounded up to a power of two, d, k); later gradients of
- * that key, including those inside the solvers, use it.  plan: NULL or 3 host
- * int32 (threads per row, vectors per thread, blocks).  Synchronizes.  Without
- * tuning the shape follows d and the grid is 2 blocks per CU. */
+ * that key, including those inside the solvers, use it.  The shapes include
+ * deeper row batches per step (more loads in flight).  plan: NULL or 4 host
+ * int32 (threads per row, vectors per thread, blocks, rows per group and step).
+ * Synchronizes.  Without tuning the shape follows d and the grid is 2 blocks
+ * per CU. */
 rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
                                const void* b, int64_t k, int32_t* plan, hipStream_t stream);
 

@@ -237,27 +237,28 @@ __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ 
 namespace {
 
 struct GradShape {
-  int tpr, nv;
+  int tpr, nv, r;  // threads per row, vectors per thread, rows per group and step (0: default)
 };
 
 template <typename T>
 GradShape pick_shape(int64_t d) {
   constexpr int VEC = VecOf<T>::n;
   const int64_t chunks = (d + VEC - 1) / VEC;  // 16-byte vectors per row
-  if (chunks <= 16) return {16, 1};
-  if (chunks <= 64) return {64, 1};
-  if (chunks <= 128) return {64, 2};
-  if (chunks <= 256) return {64, 4};
-  if (chunks <= 512) return {128, 4};
-  if (chunks <= 1024) return {256, 4};
-  if (chunks <= 2048) return {256, 8};
-  return {0, 0};
+  if (chunks <= 16) return {16, 1, 0};
+  if (chunks <= 64) return {64, 1, 0};
+  if (chunks <= 128) return {64, 2, 0};
+  if (chunks <= 256) return {64, 4, 0};
+  if (chunks <= 512) return {128, 4, 0};
+  if (chunks <= 1024) return {256, 4, 0};
+  if (chunks <= 2048) return {256, 8, 0};
+  return {0, 0, 0};
 }
 
-template <typename T, int TPR, int NV, int K>
+constexpr int default_rows(int nv) { return nv >= 8 ? 2 : (nv >= 4 ? 4 : 8); }
+
+template <typename T, int TPR, int NV, int K, int R>
 void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
                     double* partial, int grid, int64_t rpb, const int* status, hipStream_t s) {
-  constexpr int R = (NV >= 8) ? 2 : (NV >= 4 ? 4 : 8);
   constexpr int GPB = 256 / TPR;
   const int iters = (int)((rpb + GPB * R - 1) / (GPB * R));
   int* ran = prof_begin(s);
@@ -270,13 +271,15 @@ template <typename T, int K>
 bool dispatch_k(GradShape sh, const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
                 const double* X, double* partial, int grid, int64_t rpb, const int* status,
                 hipStream_t s) {
-#define RS_GCASE(TP, NVV)                                                                    \
-  if (sh.tpr == TP && sh.nv == NVV) {                                                        \
-    launch_partial<T, TP, NVV, K>(A, n, d, lda, b, X, partial, grid, rpb, status, s);        \
+#define RS_GCASE(TP, NVV, RR)                                                                \
+  if (sh.tpr == TP && sh.nv == NVV && (sh.r == RR || (sh.r == 0 && RR == default_rows(NVV)))) { \
+    launch_partial<T, TP, NVV, K, RR>(A, n, d, lda, b, X, partial, grid, rpb, status, s);    \
     return true;                                                                             \
   }
-  RS_GCASE(16, 1) RS_GCASE(64, 1) RS_GCASE(64, 2) RS_GCASE(64, 4) RS_GCASE(128, 4)
-  RS_GCASE(256, 4) RS_GCASE(256, 8)
+  RS_GCASE(16, 1, 8) RS_GCASE(64, 1, 8) RS_GCASE(64, 2, 8) RS_GCASE(64, 4, 4) RS_GCASE(128, 4, 4)
+  RS_GCASE(256, 4, 4) RS_GCASE(256, 8, 2)
+  // deeper row batches (more loads in flight per step), offered to the autotuner
+  RS_GCASE(64, 4, 8) RS_GCASE(128, 4, 8) RS_GCASE(256, 4, 8) RS_GCASE(256, 8, 4)
 #undef RS_GCASE
   return false;
 }
@@ -315,7 +318,9 @@ int64_t pow2_ceil(int64_t v) {
   return p;
 }
 
-const GradShape kShapes[] = {{16, 1}, {64, 1}, {64, 2}, {64, 4}, {128, 4}, {256, 4}, {256, 8}};
+const GradShape kShapes[] = {{16, 1, 8},  {64, 1, 8},  {64, 2, 8},  {64, 4, 4},
+                             {128, 4, 4}, {256, 4, 4}, {256, 8, 2}, {64, 4, 8},
+                             {128, 4, 8}, {256, 4, 8}, {256, 8, 4}};
 
 }  // namespace
 
@@ -327,14 +332,14 @@ GradPlan grad_plan(int64_t n, int64_t d, int k) {
     if (it != g_plans.end()) return it->second;
   }
   const GradShape sh = pick_shape<T>(d);
-  return GradPlan{sh.tpr, sh.nv, grad_partial_blocks(n)};
+  return GradPlan{sh.tpr, sh.nv, grad_partial_blocks(n), default_rows(sh.nv)};
 }
 
 template <typename T>
 static bool launch_plan(const GradPlan& pl, const T* A, int64_t n, int64_t d, int64_t lda,
                         const T* b, const double* X, int k, double* partial, const int* status,
                         hipStream_t s) {
-  const GradShape sh{pl.tpr, pl.nv};
+  const GradShape sh{pl.tpr, pl.nv, pl.r};
   const int64_t rpb = (n + pl.grid - 1) / pl.grid;
   switch (k) {
     case 1: return dispatch_k<T, 1>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
@@ -376,8 +381,9 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
       int g = (int)std::min<int64_t>((int64_t)device_cus() * f, std::max<int64_t>(n / 64, 1));
       g = std::min(g, grid_cap);
       bool dup = false;
-      for (const GradPlan& c : cand) dup |= (c.tpr == sh.tpr && c.nv == sh.nv && c.grid == g);
-      if (!dup) cand.push_back(GradPlan{sh.tpr, sh.nv, g});
+      for (const GradPlan& c : cand)
+        dup |= (c.tpr == sh.tpr && c.nv == sh.nv && c.grid == g && c.r == sh.r);
+      if (!dup) cand.push_back(GradPlan{sh.tpr, sh.nv, g, sh.r});
     }
   }
   if (cand.empty()) return set_error(RS_ERR_UNSUPPORTED, "autotune: d too large for this build");

@@ -638,6 +638,7 @@ rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d
     plan[0] = pl.tpr;
     plan[1] = pl.nv;
     plan[2] = pl.grid;
+    plan[3] = pl.r;
   }
   return RS_OK;
 }
@@ -650,6 +651,7 @@ rs_status rs_gradient_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k, int32_
   plan[0] = pl.tpr;
   plan[1] = pl.nv;
   plan[2] = pl.grid;
+  plan[3] = pl.r;
   return RS_OK;
 }
 

@@ -99,7 +99,7 @@ size_t factor_bytes_Cw(int64_t m, int64_t d);
 int grad_partial_blocks(int64_t n);
 int grad_partial_blocks_max(int64_t n);  // partial-sum blocks of any plan (buffer size)
 struct GradPlan {
-  int tpr = 0, nv = 0, grid = 0;
+  int tpr = 0, nv = 0, grid = 0, r = 0;  // r: rows per group and step
 };
 template <typename T>
 GradPlan grad_plan(int64_t n, int64_t d, int k);

@@ -491,10 +491,10 @@ def rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant="polyak", r
 
 def rs_gradient_autotune(A, b, k=2):
     """Tune the gradient pass for this problem and k; returns the chosen plan
-    (threads per row, vectors per thread, blocks)."""
+    (threads per row, vectors per thread, blocks, rows per group and step)."""
     a_t = _mat(A, "rs_gradient_autotune")
     n, d = A.shape
-    plan = (ctypes.c_int32 * 3)()
+    plan = (ctypes.c_int32 * 4)()
     _check(load().rs_gradient_autotune(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), k,
                                        ctypes.cast(plan, ctypes.c_void_p), _stream()),
            "rs_gradient_autotune")
@@ -502,7 +502,7 @@ def rs_gradient_autotune(A, b, k=2):
 
 
 def rs_gradient_plan(dtype, n, d, k):
-    plan = (ctypes.c_int32 * 3)()
+    plan = (ctypes.c_int32 * 4)()
     _check(load().rs_gradient_plan(DTYPES[dtype], n, d, k, ctypes.cast(plan, ctypes.c_void_p)),
            "rs_gradient_plan")
     return tuple(plan)

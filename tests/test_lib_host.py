@@ -142,6 +142,6 @@ def test_batch_and_grid_argument_errors_before_device_work(lib):
     assert lib.rs_gradient_autotune(vp(256), 1, 100, 10, 12, vp(256), 5, None, vp(0)) == 1
     assert lib.rs_gradient_autotune(vp(256), 1, 100, 10, 10, vp(256), 2, None, vp(0)) == 1
     # plan query: bad shapes
-    plan = (ctypes.c_int32 * 3)()
+    plan = (ctypes.c_int32 * 4)()
     assert lib.rs_gradient_plan(1, 100, 10, 0, ctypes.cast(plan, vp)) == 2
     assert lib.rs_gradient_plan(2, 100, 10, 1, ctypes.cast(plan, vp)) == 1
