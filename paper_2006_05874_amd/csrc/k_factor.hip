@@ -433,59 +433,69 @@ __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB +
     }
   }
   __syncthreads();
-  // C: panel below (rows Q+16.., 16 columns) and block row Q.. of the inverse
-  constexpr int NPAN = (NB - Q - 16) * 16;
-  constexpr int NINV = 16 * (Q + 16);
-  constexpr int PER = (NPAN + NINV + 255) / 256;
-  double res[PER];
+  // C: panel below (rows Q+16.., 16 columns) and block row Q.. of the inverse, as
+  // 16 x 16 tiles on the FP64 matrix cores: the panel has (48 - Q) / 16 tiles and
+  // the inverse block row (Q + 16) / 16, four in all, one per wave.  Lane layout
+  // of v_mfma_f64_16x16x4: A[lane % 16][k0 + lane / 16], B[k0 + lane / 16][lane % 16],
+  // result slot r at row lane / 16 + 4 r, column lane % 16.
+  {
+    constexpr int NPT = (NB - Q - 16) / 16;
+    const int li = lane & 15, lk = lane >> 4;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (w < NPT) {
+      const int r0 = Q + 16 + 16 * w;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = t + 256 * u;
-    double v = 0.0;
-    if (e < NPAN) {
-      const int r = Q + 16 + e / 16, c = e % 16;
-#pragma unroll
-      for (int l = 0; l < 16; ++l) v += a[r][Q + l] * dinv[c][l];
-    } else if (e < NPAN + NINV) {
-      const int e2 = e - NPAN;
-      const int i = e2 / (Q + 16), c = e2 % (Q + 16);
-#pragma unroll
-      for (int l = 0; l < 16; ++l) v += dinv[i][l] * x[Q + l][c];
-    }
-    res[u] = v;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = t + 256 * u;
-    if (e < NPAN) {
-      a[Q + 16 + e / 16][Q + e % 16] = res[u];
-    } else if (e < NPAN + NINV) {
-      const int e2 = e - NPAN;
-      x[Q + e2 / (Q + 16)][e2 % (Q + 16)] = res[u];
-    }
-  }
-  __syncthreads();
-  // D: trailing update of the lower part and of the rows of Y below the panel
-  constexpr int NR = NB - Q - 16;
-  constexpr int NUPD = NR * NR;
-  constexpr int NY = NR * (Q + 16);
-  if constexpr (NR > 0) for (int e = t; e < NUPD + NY; e += 256) {
-    if (e < NUPD) {
-      const int r = Q + 16 + e / NR, c = Q + 16 + e % NR;
-      if (c <= r) {
-        double v = a[r][c];
-#pragma unroll
-        for (int l = 0; l < 16; ++l) v -= a[r][Q + l] * a[c][Q + l];
-        a[r][c] = v;
-      }
+      for (int k4 = 0; k4 < 4; ++k4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r0 + li][Q + 4 * k4 + lk],
+                                                   dinv[li][4 * k4 + lk], acc, 0, 0, 0);
     } else {
-      const int e2 = e - NUPD;
-      const int r = Q + 16 + e2 / (Q + 16), c = e2 % (Q + 16);
-      double v = x[r][c];
+      const int c0 = 16 * (w - NPT);
 #pragma unroll
-      for (int l = 0; l < 16; ++l) v -= a[r][Q + l] * x[Q + l][c];
-      x[r][c] = v;
+      for (int k4 = 0; k4 < 4; ++k4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(dinv[li][4 * k4 + lk],
+                                                   x[Q + 4 * k4 + lk][c0 + li], acc, 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = lk + 4 * r;
+      if (w < NPT) a[Q + 16 + 16 * w + row][Q + li] = acc[r];
+      else x[Q + row][16 * (w - NPT) + li] = acc[r];
+    }
+  }
+  __syncthreads();
+  // D: trailing update of the lower part (tiles I >= J of the rows and columns
+  // past the panel) and of the rows of Y below the panel, tiles spread over the
+  // waves; each output tile belongs to one wave
+  constexpr int NT = (NB - Q - 16) / 16;
+  constexpr int NTRI = NT * (NT + 1) / 2;
+  constexpr int NYT = NT * ((Q + 16) / 16);
+  if constexpr (NT > 0) {
+    const int li = lane & 15, lk = lane >> 4;
+    for (int tile = w; tile < NTRI + NYT; tile += 4) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (tile < NTRI) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+        const int J = tile - I * (I + 1) / 2;
+        const int r0 = Q + 16 + 16 * I, c0 = Q + 16 + 16 * J;
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r0 + li][Q + 4 * k4 + lk],
+                                                     a[c0 + li][Q + 4 * k4 + lk], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r0 + lk + 4 * r][c0 + li] -= acc[r];
+      } else {
+        const int y = tile - NTRI;
+        const int I = y / ((Q + 16) / 16), J = y % ((Q + 16) / 16);
+        const int r0 = Q + 16 + 16 * I, c0 = 16 * J;
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r0 + li][Q + 4 * k4 + lk],
+                                                     x[Q + 4 * k4 + lk][c0 + li], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r0 + lk + 4 * r][c0 + li] -= acc[r];
+      }
     }
   }
   __syncthreads();
