@@ -326,10 +326,22 @@ __device__ __forceinline__ void tile_fetch(const OA& A, const OB& B, int64_t k0,
   }
 }
 
+// acc (thread (ty, tx) holds rows 4ty.., columns 4tx..) += op(A) op(B) over kd.
+// The products run on the FP64 matrix cores: wave w owns the 32 x 32 quadrant
+// (w / 2, w % 2) as 2 x 2 tiles of v_mfma_f64_16x16x4 (operands A[row][k] and
+// B[k][col] read from the staged chunks); at the end the quadrants pass through
+// LDS into the per-thread 4 x 4 layout the callers use.
 template <typename OA, typename OB>
 __device__ void tile_mm(double (&acc)[4][4], const OA& A, const OB& B, int64_t kd, TileLds& L) {
   const int t = threadIdx.x;
   const int ty = t >> 4, tx = t & 15;
+  const int lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  f64x4 q[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) q[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   double ra[8], rb[8];
   tile_fetch(A, B, 0, ra, rb);
   int buf = 0;
@@ -342,20 +354,38 @@ __device__ void tile_mm(double (&acc)[4][4], const OA& A, const OB& B, int64_t k
     }
     __syncthreads();
     if (k0 + TKC < kd) tile_fetch(A, B, k0 + TKC, ra, rb);
-#pragma unroll 8
-    for (int kk = 0; kk < TKC; ++kk) {
-      double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = L.A[buf][kk][ty * 4 + i];
+    for (int k4 = 0; k4 < TKC / 4; ++k4) {
+      const int kk = 4 * k4 + (lane >> 4);
+      double av[2], bv[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = L.B[buf][kk][tx * 4 + j];
+      for (int a = 0; a < 2; ++a) av[a] = L.A[buf][kk][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int b = 0; b < 2; ++b) bv[b] = L.B[buf][kk][wc * 32 + b * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          q[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], q[a][b], 0, 0, 0);
     }
     buf ^= 1;
   }
+  __syncthreads();
+  // quadrants -> LDS (64 x 65) -> per-thread 4 x 4
+  double* F = &L.A[0][0][0];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        F[(wr * 32 + a * 16 + (lane >> 4) + 4 * r) * (NB + 1) + wc * 32 + b * 16 + (lane & 15)] =
+            q[a][b][r];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] += F[(ty * 4 + i) * (NB + 1) + tx * 4 + j];
   __syncthreads();
 }
 
