@@ -39,6 +39,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--graph-steps", action="store_true",
+                    help="batched solves replay each job's queued steps from HIP graphs")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default="polyak", choices=["polyak", "gd"])
@@ -160,7 +162,8 @@ def main():
         params, mu, sd = model
         res = rs.rs_learned_solve_batch([(A, b, nu2) for nu2 in NU2S], params, mu, sd,
                                         kind="srht", variant=args.variant, sketch_dtype="bf16",
-                                        check_every=args.check_every, workers=len(NU2S))
+                                        check_every=args.check_every, workers=len(NU2S),
+                                        graph_steps=args.graph_steps)
         return [(nu2, x, info) for nu2, (x, info) in zip(NU2S, res)]
 
     def timed(mode, profile):
@@ -567,10 +570,11 @@ def run_c4b(args):
 
     def run_learned():
         return rs.rs_learned_solve_batch(probs, params, mu, sd, sketch_dtype="bf16", workers=8,
-                                         raise_on_error=False)
+                                         graph_steps=args.graph_steps, raise_on_error=False)
 
     def run_batch():
-        return rs.rs_solve_batch(probs, sketch_dtype="bf16", workers=8, raise_on_error=False)
+        return rs.rs_solve_batch(probs, sketch_dtype="bf16", workers=8,
+                                 graph_steps=args.graph_steps, raise_on_error=False)
 
     def run_seq():
         return [rs.rs_adaptive_solve(A, b, nu2, sketch_dtype="f32", raise_on_error=False)
@@ -579,7 +583,7 @@ def run_c4b(args):
     out = {}
     for name, fn in (("learned_bf16_batched", run_learned), ("batched_bf16", run_batch),
                      ("sequential_plain_f32", run_seq)):
-        fn()                                   # warm-up (allocations, graphs)
+        fn()                                   # warm-up (allocations)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -614,7 +618,10 @@ def run_c4b(args):
             "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
             "config": {"workload": "256 problems, n=2^U{12..16}, d=U{128..1024}, "
                                    "sigma_i=0.95^i, nu^2=1e-3, SRHT, 8 worker streams, "
-                                   "learned start + BF16 sketches, steps replayed from HIP graphs"},
+                                   "learned start + BF16 sketches, one host thread per worker"
+                                   + (", steps replayed from HIP graphs" if args.graph_steps
+                                      else ""),
+                       "graph_steps": bool(args.graph_steps)},
             "verified": all(v["worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
                             for v in out.values()),
             "modes": out,

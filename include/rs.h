@@ -197,8 +197,13 @@ typedef struct {
   int64_t max_iter;          /* cap on accepted steps; default 200 */
   uint64_t seed;
   int32_t check_every;       /* steps queued between host reads of the device state; default 4 */
-  int32_t reserved;
+  int32_t flags;             /* RS_SOLVE_* bits; default 0 */
 } rs_solve_opts;
+
+/* rs_solve_opts.flags: replay each job's queued steps from HIP graphs captured on
+ * the job's first use (batched solves only; the capture and instantiation are
+ * paid once per solve, so this pays off when a solve takes many step rounds). */
+#define RS_SOLVE_GRAPH_STEPS 1
 
 /* Event kinds recorded in rs_solve_info. */
 #define RS_EVENT_POLYAK 0

@@ -1,5 +1,6 @@
 // C ABI of librs: argument checks, per-device scratch, and the host side of the
 // adaptive controller (Algorithm 1).  Every numeric step runs in the kernels.
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <iterator>
@@ -45,7 +46,7 @@ rs_status check_launch(const char* what) {
   } while (0)
 
 int device_cus() {
-  static int cus[64] = {0};
+  static std::atomic<int> cus[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
   if (cus[dev] == 0) {
@@ -61,33 +62,38 @@ int device_cus() {
 // Launches bracketed while profiling: event pairs plus a device flag per launch
 // that the kernel sets when it does its work (launches queued behind a raised
 // status flag return at once and are not counted).
-static bool g_prof_on = false;
+// Worker threads of a batch launch concurrently: the slot counter and the event
+// list are guarded by g_prof_mu, and each launch keeps its own slot.
+static std::mutex g_prof_mu;
+static std::atomic<bool> g_prof_on{false};
 static std::vector<hipEvent_t> g_prof_ev;  // begin/end pairs
-static size_t g_prof_n = 0;                // events recorded
+static size_t g_prof_pairs = 0;            // launches bracketed
 static int* g_prof_ran = nullptr;          // device flags, one per launch
 static constexpr size_t kProfCap = 1 << 16;
 
-static hipEvent_t prof_event() {
-  if (g_prof_n >= g_prof_ev.size()) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    g_prof_ev.push_back(e);
+ProfSlot prof_begin(hipStream_t s) {
+  ProfSlot ps;
+  if (!g_prof_on.load(std::memory_order_relaxed)) return ps;
+  hipEvent_t e = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on || g_prof_pairs >= kProfCap) return ps;
+    while (g_prof_ev.size() < 2 * (g_prof_pairs + 1)) {
+      hipEvent_t ne;
+      if (hipEventCreate(&ne) != hipSuccess) return ps;
+      g_prof_ev.push_back(ne);
+    }
+    ps.slot = (int64_t)g_prof_pairs++;
+    e = g_prof_ev[2 * ps.slot];
+    ps.end = g_prof_ev[2 * ps.slot + 1];
   }
-  return g_prof_ev[g_prof_n++];
+  (void)hipEventRecord(e, s);
+  ps.ran = g_prof_ran ? g_prof_ran + ps.slot : nullptr;
+  return ps;
 }
 
-int* prof_begin(hipStream_t s) {
-  if (!g_prof_on || g_prof_n / 2 >= kProfCap) return nullptr;
-  const size_t slot = g_prof_n / 2;
-  hipEvent_t e = prof_event();
-  if (e) (void)hipEventRecord(e, s);
-  return g_prof_ran ? g_prof_ran + slot : nullptr;
-}
-
-void prof_end(hipStream_t s) {
-  if (!g_prof_on || g_prof_n % 2 == 0) return;
-  hipEvent_t e = prof_event();
-  if (e) (void)hipEventRecord(e, s);
+void prof_end(const ProfSlot& ps, hipStream_t s) {
+  if (ps.slot >= 0 && ps.end) (void)hipEventRecord(ps.end, s);
 }
 
 // ------------------------------------------------------------------ scratch
@@ -201,7 +207,6 @@ struct BatchWorker {
   DeviceScratch S;
   hipStream_t s = nullptr;
   hipEvent_t join = nullptr;
-  int64_t job = -1;
 };
 struct WorkerPool {
   std::mutex mu;
@@ -418,6 +423,7 @@ const char* rs_last_error(void) { return g_err.c_str(); }
 const char* rs_version(void) { return "librs 0.1 (gfx950)"; }
 
 rs_status rs_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
   if (on && !g_prof_ran) {
     RS_HIP(hipMalloc(&g_prof_ran, kProfCap * sizeof(int)));
     RS_HIP(hipMemset(g_prof_ran, 0, kProfCap * sizeof(int)));
@@ -428,9 +434,10 @@ rs_status rs_profile_enable(int on) {
 
 rs_status rs_profile_read(int64_t* launches, double* total_ms) {
   if (!launches || !total_ms) return set_error(RS_ERR_ARG, "rs_profile_read: null argument");
+  std::lock_guard<std::mutex> g(g_prof_mu);
   double tot = 0.0;
   int64_t cnt = 0;
-  const size_t pairs = g_prof_n / 2;
+  const size_t pairs = g_prof_pairs;
   std::vector<int> ran(pairs, 1);
   if (g_prof_ran && pairs) {
     RS_HIP(hipDeviceSynchronize());
@@ -445,7 +452,7 @@ rs_status rs_profile_read(int64_t* launches, double* total_ms) {
     tot += ms;
     ++cnt;
   }
-  g_prof_n = 0;
+  g_prof_pairs = 0;
   *launches = cnt;
   *total_ms = tot;
   return RS_OK;
@@ -1170,11 +1177,13 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
     J.A = P.A; J.a_t = P.a_t; J.n = P.n; J.d = P.d; J.lda = P.lda; J.b = P.b; J.nu2 = P.nu2;
     J.x = P.x; J.o = *opts; J.info = &infos[i];
     J.lp_params = params; J.lp_mu = mu; J.lp_sd = sd;
-    J.use_graph = true;
+    J.use_graph = (opts->flags & RS_SOLVE_GRAPH_STEPS) != 0;
     RS_TRY(J.validate());
     if (params) RS_TRY(check_features_args(P.a_t, P.n, P.d, P.nu2, "rs_learned_solve_batch"));
   }
   const int W = (int)std::max<int64_t>(1, std::min<int64_t>(workers > 0 ? workers : 8, count));
+  int dev = 0;
+  RS_HIP(hipGetDevice(&dev));
   // worker streams and scratch: a per-device pool kept across calls (its lock is
   // held for the whole call)
   WorkerPool* pool = pool_for_current();
@@ -1187,57 +1196,70 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
   }
   if (!pool->entry) RS_HIP(hipEventCreateWithFlags(&pool->entry, hipEventDisableTiming));
   RS_HIP(hipEventRecord(pool->entry, stream));
-  std::vector<BatchWorker*> wk;
-  for (int i = 0; i < W; ++i) {
-    BatchWorker* w = pool->w[i].get();
-    w->job = -1;
-    RS_HIP(hipStreamWaitEvent(w->s, pool->entry, 0));
-    wk.push_back(w);
-  }
+  for (int i = 0; i < W; ++i) RS_HIP(hipStreamWaitEvent(pool->w[i]->s, pool->entry, 0));
+  // Each worker runs on a host thread of its own (worker 0 on the caller's): it
+  // takes the next unstarted job, drives it to the end on its stream (queue work,
+  // wait for the job's completion event, read the control record, queue more),
+  // then takes the next.  One host thread per stream keeps every stream fed while
+  // another thread waits or launches.
+  std::atomic<int64_t> next{0};
+  std::mutex emu;
   rs_status first_err = RS_OK;
-  int64_t next = 0, finished = 0;
-  auto launch = [&](BatchWorker& w) {
-    while (next < count) {
-      SolveJob& J = jobs[next];
+  std::string first_msg;
+  auto note = [&](rs_status st) {
+    std::lock_guard<std::mutex> g(emu);
+    if (first_err == RS_OK) {
+      first_err = st;
+      first_msg = rs_last_error();
+    }
+  };
+  auto run = [&](int wi, bool own_thread) {
+    BatchWorker& w = *pool->w[wi];
+    if (own_thread && hipSetDevice(dev) != hipSuccess) {
+      note(set_error(RS_ERR_HIP, "rs_solve_batch: hipSetDevice failed in a worker"));
+      return;
+    }
+    for (;;) {
+      const int64_t id = next.fetch_add(1);
+      if (id >= count) return;
+      SolveJob& J = jobs[id];
       J.S = &w.S;
       J.stream = w.s;
-      const int64_t id = next++;
-      const rs_status st = J.begin();
-      if (st == RS_OK) { w.job = id; return; }
-      J.result = st;
-      J.info->status = st;
-      J.done = true;
-      ++finished;
-      if (first_err == RS_OK) first_err = st;
-    }
-    w.job = -1;
-  };
-  for (BatchWorker* wp : wk) launch(*wp);
-  while (finished < count) {
-    bool progressed = false;
-    for (BatchWorker* wp : wk) {
-      BatchWorker& w = *wp;
-      if (w.job < 0) continue;
-      SolveJob& J = jobs[w.job];
-      if (!J.ready()) continue;
-      progressed = true;
-      const rs_status st = J.advance();
-      if (J.done || st != RS_OK) {
-        if (!J.done) { J.done = true; J.result = st; J.info->status = st; }
-        ++finished;
-        if (J.result != RS_OK && J.result != RS_ERR_NO_CONVERGENCE && first_err == RS_OK)
-          first_err = J.result;
-        launch(w);
+      rs_status st = J.begin();
+      while (st == RS_OK && !J.done) {
+        const hipError_t e = hipEventSynchronize(w.S.done_ev);
+        if (e != hipSuccess) {
+          st = set_error(RS_ERR_HIP, hipGetErrorString(e));
+          break;
+        }
+        st = J.advance();
       }
+      if (!J.done) {
+        J.done = true;
+        J.result = st;
+        J.info->status = st;
+      }
+      if (J.result != RS_OK && J.result != RS_ERR_NO_CONVERGENCE) note(J.result);
     }
-    if (!progressed) std::this_thread::yield();
+  };
+  std::vector<std::thread> th;
+  for (int i = 1; i < W; ++i) {
+    try {
+      th.emplace_back(run, i, true);
+    } catch (...) {
+      break;  // the remaining jobs go to the workers that did start
+    }
   }
+  run(0, false);
+  for (std::thread& t : th) t.join();
   // the caller's stream waits for every worker
-  for (BatchWorker* wp : wk) {
+  for (int i = 0; i < W; ++i) {
+    BatchWorker* wp = pool->w[i].get();
     RS_HIP(hipEventRecord(wp->join, wp->s));
     RS_HIP(hipStreamWaitEvent(stream, wp->join, 0));
     RS_HIP(hipStreamSynchronize(wp->s));
   }
+  if (first_err != RS_OK) set_error(first_err, first_msg.c_str());
   if (m_init_used)
     for (int64_t i = 0; i < count; ++i) m_init_used[i] = jobs[i].m_init_used;
   return first_err;

@@ -16,8 +16,13 @@ rs_status set_error(rs_status st, const char* msg);
 rs_status check_launch(const char* what);
 int device_cus();
 // kernel timing hooks (no-ops unless rs_profile_enable(1))
-int* prof_begin(hipStream_t s);  // returns the launch's "did work" flag slot or null
-void prof_end(hipStream_t s);
+struct ProfSlot {
+  int64_t slot = -1;        // -1: not profiled
+  int* ran = nullptr;       // the launch's "did work" flag, or null
+  hipEvent_t end = nullptr;
+};
+ProfSlot prof_begin(hipStream_t s);
+void prof_end(const ProfSlot& ps, hipStream_t s);
 
 // ---------------------------------------------------------------- SRHT
 struct SrhtBuffers {

@@ -56,7 +56,10 @@ class SolveOpts(ctypes.Structure):
                 ("sketch_dtype", ctypes.c_int), ("rho", ctypes.c_double), ("eta", ctypes.c_double),
                 ("m_init", ctypes.c_int64), ("m_max", ctypes.c_int64), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+RS_SOLVE_GRAPH_STEPS = 1
 
 
 class SolveInfo(ctypes.Structure):
@@ -356,14 +359,17 @@ def _batch_problems(problems, where):
 
 def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
                    sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
-                   max_iter=200, seed=0, check_every=4, workers=8, raise_on_error=True):
+                   max_iter=200, seed=0, check_every=4, workers=8, graph_steps=False,
+                   raise_on_error=True):
     """Solve a list of (A, b, nu2) problems with one option set.  Returns a list of
-    (x, info) pairs in the input order."""
+    (x, info) pairs in the input order.  ``graph_steps`` replays each job's queued
+    steps from HIP graphs."""
     if not problems:
         return []
     a_ts, P, xs, bs = _batch_problems(problems, "rs_solve_batch")
     o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol,
               max_iter, seed, check_every)
+    o.flags = RS_SOLVE_GRAPH_STEPS if graph_steps else 0
     infos = (SolveInfo * len(problems))()
     st = load().rs_solve_batch(P, len(problems), ctypes.byref(o), infos, workers, _stream())
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
@@ -375,7 +381,7 @@ def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
 def rs_learned_solve_batch(problems, params, mu, sd, kind="srht", variant="polyak",
                            resample="fresh", sketch_dtype=None, rho=0.1, eta=0.01, m_max=0,
                            tol=1e-7, max_iter=200, seed=0, check_every=4, workers=8,
-                           raise_on_error=True):
+                           graph_steps=False, raise_on_error=True):
     """Learned starting m for every problem, then the batched solve.  Returns a list
     of (x, info) pairs; info["m_init"] is the starting m used."""
     if not problems:
@@ -383,6 +389,7 @@ def rs_learned_solve_batch(problems, params, mu, sd, kind="srht", variant="polya
     a_ts, P, xs, bs = _batch_problems(problems, "rs_learned_solve_batch")
     o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, 1, m_max, tol,
               max_iter, seed, check_every)
+    o.flags = RS_SOLVE_GRAPH_STEPS if graph_steps else 0
     infos = (SolveInfo * len(problems))()
     used = (ctypes.c_int64 * len(problems))()
     st = load().rs_learned_solve_batch(P, len(problems), ctypes.byref(o), _ptr(params), _ptr(mu),

@@ -45,11 +45,14 @@ def small_uneven(count, dtype, seed=0):
     return out
 
 
-@pytest.mark.parametrize("workers", [1, 3, 8])
-def test_batch_equals_single_solves_fp64(rs, workers):
+@pytest.mark.parametrize("workers,graph_steps", [(1, False), (3, False), (8, False), (3, True),
+                                                 (8, True)])
+def test_batch_equals_single_solves_fp64(rs, workers, graph_steps):
+    # workers run on host threads of their own; with graph_steps the queued steps
+    # are replayed from HIP graphs
     probs = small_uneven(10, np.float64)
     dev_probs = [(dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2) for p in probs]
-    res = rs.rs_solve_batch(dev_probs, seed=5, workers=workers)
+    res = rs.rs_solve_batch(dev_probs, seed=5, workers=workers, graph_steps=graph_steps)
     for (A, b, nu2), p, (x, info) in zip(dev_probs, probs, res):
         xs1, i1 = rs.rs_adaptive_solve(A, b, nu2, seed=5)
         assert info["events"] == i1["events"] and info["m_final"] == i1["m_final"]
@@ -105,3 +108,18 @@ def test_batch_empty_and_errors(rs):
     with pytest.raises(rs.RsError) as e:
         rs.rs_solve_batch([good, bad])
     assert e.value.name == "not_spd"
+
+
+def test_batch_worker_error_reaches_caller(rs):
+    # a non-finite right-hand side stops its own job in a worker thread; the other
+    # jobs finish, and the error and its message reach the calling thread
+    p = small_uneven(4, np.float64, seed=3)
+    dev_probs = [(dev_padded(q.A, rs), torch.from_numpy(q.b).cuda(), q.nu2) for q in p]
+    bad_b = dev_probs[2][1].clone()
+    bad_b[0] = float("nan")
+    dev_probs[2] = (dev_probs[2][0], bad_b, dev_probs[2][2])
+    res = rs.rs_solve_batch(dev_probs, workers=3, raise_on_error=False)
+    assert [info["status"] for _, info in res] == ["ok", "ok", "nonfinite", "ok"]
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_solve_batch(dev_probs, workers=3)
+    assert e.value.name == "nonfinite" and "non-finite" in str(e.value)
