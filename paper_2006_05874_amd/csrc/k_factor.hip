@@ -415,15 +415,28 @@ __device__ __forceinline__ double rsqrt64(double x) {
 }
 
 // Diagonal tile k: factor and invert the 64 x 64 block in LDS, 16 columns at a
-// time.  For each 16-wide panel: one wave factors the 16 x 16 diagonal piece in
-// registers (lane i holds row i; pivots and column entries are broadcast through
-// the scalar unit) and inverts it in the same registers (lane c builds column c
-// of the inverse by forward substitution); then the whole block applies the
-// panel below it, the matching block row of the inverse, and the trailing
-// update.  X = L^-1 is carried along as the right-hand side of L X = I.
+// time.  For each 16-wide panel: one wave factors the 16 x 16 diagonal piece
+// (lane i holds row i in registers) four columns at a time: the 4 x 4 pivot block
+// is factored (L_D) and inverted (M = L_D^-1) by every lane alike, each row's four
+// entries v_i become P_i = v_i L_D^-T by forward substitution, and the columns
+// past them take the rank-4 update -P_i P_j^T, the P_j read back from LDS; then
+// lane c builds column c of the 16 x 16 inverse by block forward substitution
+// over the 4 x 4 blocks.
+// After that the whole block applies the panel below, the matching block row of
+// the inverse, and the trailing update on the FP64 matrix cores.  X = L^-1 is
+// carried along as the right-hand side of L X = I.
+//
+// LDS traffic inside the one wave needs no barrier: a wave's LDS operations
+// execute in order, and the wavefront fence keeps the compiler from moving the
+// reads of other lanes' rows above the writes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int Q>
 __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB + 1],
-                                           double (*dinv)[17], bool& bad) {
+                                           double (*dinv)[17], double (*pbuf)[4], bool& bad) {
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
@@ -431,33 +444,111 @@ __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB +
   if (w == 0) {
     const int li = lane & 15;
     double r[16];
-    double rinv[16];  // 1 / L_jj (the same in every lane)
 #pragma unroll
     for (int c = 0; c < 16; ++c) r[c] = a[Q + li][Q + c];
+    double M[4][4][4];  // inverse of each 4 x 4 diagonal factor (lower part used)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double piv = lane_value(r[j], j);
-      bad |= !(piv > 0.0);
-      const double inv = rsqrt64(piv);
-      rinv[j] = inv;
-      const double l = r[j] * inv;
-      r[j] = li > j ? l : (li == j ? piv * inv : r[j]);
-      // lanes above the diagonal update entries that are never read (no masks)
+    for (int sb = 0; sb < 4; ++sb) {
+      const int c0 = 4 * sb;
+      // the rows' current entries in columns c0..c0+3; the pivot block (rows
+      // c0..c0+3) read back by every lane
+      if (lane < 16) {
 #pragma unroll
-      for (int c = j + 1; c < 16; ++c) r[c] -= l * lane_value(l, c);
-    }
-    // column li of L^-1: X_ic = (delta_ic - sum_{l<i} L_il X_lc) / L_ii, i >= c
-    double col[16];
+        for (int e = 0; e < 4; ++e) pbuf[li][e] = r[c0 + e];
+      }
+      wave_lds_sync();
+      double D[4][4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      double acc = (i == li) ? 1.0 : 0.0;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int l = 0; l < i; ++l) acc -= lane_value(r[l], i) * col[l];
-      col[i] = i >= li ? acc * rinv[i] : 0.0;
+        for (int j = 0; j <= i; ++j) D[i][j] = pbuf[c0 + i][j];
+      // 4 x 4 Cholesky L_D and its inverse, the same in every lane
+      double L[4][4], inv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double dd = D[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dd = fma(-L[j][k], L[j][k], dd);
+        bad |= !(dd > 0.0);
+        inv[j] = rsqrt64(dd);
+        L[j][j] = dd * inv[j];
+#pragma unroll
+        for (int i = j + 1; i < 4; ++i) {
+          double v = D[i][j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v = fma(-L[i][k], L[j][k], v);
+          L[i][j] = v * inv[j];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        M[sb][i][i] = inv[i];
+#pragma unroll
+        for (int j = i - 1; j >= 0; --j) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = j; k < i; ++k) v = fma(L[i][k], M[sb][k][j], v);
+          M[sb][i][j] = -inv[i] * v;
+        }
+      }
+      // P_i = v_i L_D^-T by forward substitution: on the pivot rows this repeats
+      // the operations above and gives L_D exactly
+      double P[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double v = r[c0 + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v = fma(-P[k], L[j][k], v);
+        P[j] = v * inv[j];
+        r[c0 + j] = P[j];
+      }
+      // rank-4 update of the columns past the block (rows above them update
+      // entries that are never read)
+      if (c0 + 4 < 16) {
+        wave_lds_sync();
+        if (lane < 16) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pbuf[li][e] = P[e];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int j = c0 + 4; j < 16; ++j) {
+          double v = r[j];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v = fma(-P[e], pbuf[j][e], v);
+          r[j] = v;
+        }
+        wave_lds_sync();
+      }
     }
     if (lane < 16) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[Q + lane][Q + c] = c <= lane ? r[c] : 0.0;
+    }
+    wave_lds_sync();
+    // column li of L^-1: block row s is M_s (e_li - sum_{u<s} L_su x_u)
+    double col[16];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      double y[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[i] = (4 * sb + i == li) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < sb; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            y[i] = fma(-a[Q + 4 * sb + i][Q + 4 * u + k], col[4 * u + k], y[i]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) v = fma(M[sb][i][k], y[k], v);
+        col[4 * sb + i] = v;
+      }
+    }
+    if (lane < 16) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) dinv[i][lane] = col[i];
     }
@@ -543,6 +634,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
   __shared__ double a[NB][NB + 1];
   __shared__ double x[NB][NB + 1];
   __shared__ double dinv[16][17];
+  __shared__ double pbuf[16][4];
   const int t = threadIdx.x;
   const int64_t o = (int64_t)k * NB;
   for (int idx = t; idx < NB * NB; idx += 256) {
@@ -553,10 +645,10 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
   __syncthreads();
   bool bad = false;
   const int64_t valid = p - o;  // valid indices in this tile (>= 1)
-  diag_panel<0>(a, x, dinv, bad);
-  if (valid > 16) diag_panel<16>(a, x, dinv, bad);
-  if (valid > 32) diag_panel<32>(a, x, dinv, bad);
-  if (valid > 48) diag_panel<48>(a, x, dinv, bad);
+  diag_panel<0>(a, x, dinv, pbuf, bad);
+  if (valid > 16) diag_panel<16>(a, x, dinv, pbuf, bad);
+  if (valid > 32) diag_panel<32>(a, x, dinv, pbuf, bad);
+  if (valid > 48) diag_panel<48>(a, x, dinv, pbuf, bad);
   if (bad) atomicExch(info, 1);
   for (int idx = t; idx < NB * NB; idx += 256) {
     const int i = idx >> 6, j = idx & 63;

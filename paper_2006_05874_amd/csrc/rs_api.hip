@@ -183,11 +183,23 @@ struct DeviceScratch {
   size_t g_pinned_bytes = 0;
   void* host_pinned = nullptr;
   hipEvent_t done_ev = nullptr;
+  // side stream (default priority) for work that runs beside the caller's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   DeviceScratch() = default;
   ~DeviceScratch() {
     if (g_pinned) (void)hipHostFree(g_pinned);
     if (host_pinned) (void)hipHostFree(host_pinned);
     if (done_ev) (void)hipEventDestroy(done_ev);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (aux) (void)hipStreamDestroy(aux);
+  }
+  rs_status ensure_aux() {
+    if (!aux) RS_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    if (!fork_ev) RS_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+    if (!join_ev) RS_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    return RS_OK;
   }
 };
 
@@ -747,26 +759,32 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
   //    Woodbury matrix are needed)
   const bool wood = m0 < d;
   RS_TRY(S.psa.ensure((size_t)m0 * d * es));
-  RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
-                  nullptr, nullptr, stream));
   RS_TRY(S.pM.ensure(factor_bytes_M(m0, d)));
   RS_TRY(S.pLinv.ensure(factor_bytes_M(m0, d)));
   if (!wood) RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
   RS_TRY(S.pinfo.ensure(sizeof(int), true));
-  FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), wood ? nullptr : S.pHinv.as<double>(),
-                   nullptr, S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
-  RS_TRY(factor_build(FB, S.psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
-  // 2. one pass over A: the 8 probes A^T w_k and the squared column norms
   const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
   RS_TRY(S.ppart.ensure((size_t)nch * 9 * d * sizeof(double)));
   RS_TRY(S.pU.ensure((size_t)9 * d * sizeof(double)));
+  // 2. (on the side stream, beside 1) one pass over A: the 8 probes A^T w_k and
+  //    the squared column norms; it does not depend on the probe sketch
+  RS_TRY(S.ensure_aux());
+  RS_HIP(hipEventRecord(S.fork_ev, stream));
+  RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
   if (a_t == RS_F32)
     RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda, seed,
-                                S.ppart.as<double>(), S.pU.as<double>(), stream));
+                                S.ppart.as<double>(), S.pU.as<double>(), S.aux));
   else
     RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda, seed,
-                                 S.ppart.as<double>(), S.pU.as<double>(), stream));
+                                 S.ppart.as<double>(), S.pU.as<double>(), S.aux));
+  RS_HIP(hipEventRecord(S.join_ev, S.aux));
+  RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
+                  nullptr, nullptr, stream));
+  FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), wood ? nullptr : S.pHinv.as<double>(),
+                   nullptr, S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
+  RS_TRY(factor_build(FB, S.psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
+  RS_HIP(hipStreamWaitEvent(stream, S.join_ev, 0));
   // 3. r_k = q_k / 2 with q_k = u_k^T H_S0^-1 u_k
   RS_TRY(S.pr.ensure(8 * sizeof(double)));
   if (wood) {
