@@ -219,6 +219,161 @@ __global__ __launch_bounds__(256) void k_gram_lp_tn(const TIn* __restrict__ src,
       }
 }
 
+// BF16 Gram on the K=32 matrix instructions with a software pipeline:
+//   TN: C[i][j] = sum_l X[l][i] X[l][j]   (SA^T SA; X row l is a sketch row)
+//   NT: C[i][j] = sum_l X[i][l] X[j][l]   (SA SA^T; K runs along the rows)
+// over l in this block's K range, for the lower 64 x 64 tile (I, J).  Each stage
+// holds KC = 128 values of l for the 64 columns of each operand in LDS as
+// S[col][l] (l contiguous, the operand layout of v_mfma_f32_16x16x32_bf16: lane
+// reads 8 consecutive l of one column with one 16-byte read).  For TN every
+// thread loads an 8 x 8 block (8 rows of X, 8 columns) and writes it transposed;
+// for NT the rows of X already run along l.  The next stage's global loads are
+// in flight while the current stage multiplies; two LDS buffers, one barrier per
+// stage.  A diagonal tile stages one operand.
+namespace {
+constexpr int GKC = 128;          // l per stage
+constexpr int GKP = GKC + 8;      // LDS row pitch (elements): 16-byte aligned rows
+
+__device__ __forceinline__ uint4 bf16_transpose_col(const uint4 (&in)[8], int c) {
+  // column c of the 8 x 8 block: rows 0..7 packed two per 32-bit word
+  const int wsel = c >> 1;
+  uint32_t o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t a = reinterpret_cast<const uint32_t*>(&in[2 * q])[wsel];
+    const uint32_t b = reinterpret_cast<const uint32_t*>(&in[2 * q + 1])[wsel];
+    o[q] = (c & 1) ? ((a >> 16) | (b & 0xFFFF0000u)) : ((a & 0xFFFFu) | (b << 16));
+  }
+  return make_uint4(o[0], o[1], o[2], o[3]);
+}
+}  // namespace
+
+template <bool TN>
+__global__ __launch_bounds__(256) void k_gram_bf16(const uint16_t* __restrict__ src, int64_t ld,
+                                                   int64_t p, int64_t q, int64_t qchunk,
+                                                   float* __restrict__ P, int64_t ldc) {
+  const int64_t bid = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= bid) ++I;
+  while (I * (I + 1) / 2 > bid) --I;
+  const int64_t J = bid - I * (I + 1) / 2;
+  const int64_t i0 = I * NB, j0 = J * NB;
+  const bool diag = I == J;
+  __shared__ __attribute__((aligned(16))) uint16_t S[2][2][NB][GKP];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int64_t lbeg = (int64_t)blockIdx.y * qchunk;
+  const int64_t lend = lbeg + qchunk < q ? lbeg + qchunk : q;
+  const int nst = (int)((lend - lbeg + GKC - 1) / GKC);
+  // this thread's staging piece: operand op, 8 x 8 block (TN) or 4 row segments (NT)
+  const int op = t >> 7;
+  const bool stager = !(diag && op == 1);
+  const int64_t c0 = op ? j0 : i0;
+  uint4 rg[8];
+  auto load = [&](int st) {
+    const int64_t l0 = lbeg + (int64_t)st * GKC;
+    if (TN) {
+      // rows l0 + 8 g .. + 7, columns c0 + 8 cb .. + 7
+      const int g = (t >> 3) & 15, cb = t & 7;
+      const int64_t col = c0 + 8 * cb;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t l = l0 + 8 * g + e;
+        const bool ok = l < lend && col < p;
+        const int64_t lc = l < lend ? l : lbeg;
+        const uint4 v = *reinterpret_cast<const uint4*>(src + lc * ld + (col < p ? col : 0));
+        uint4 z = ok ? v : make_uint4(0, 0, 0, 0);
+        if (ok && col + 8 > p) {  // columns past p inside the last group
+          uint16_t* h = reinterpret_cast<uint16_t*>(&z);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (col + u >= p) h[u] = 0;
+        }
+        rg[e] = z;
+      }
+    } else {
+      // row c0 + r of X, l0 + 8 seg .. + 7 for 8 (r, seg) pairs
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int idx = (t & 127) + 128 * e;  // 0..1023 = 64 rows x 16 segments
+        const int r = idx >> 4, seg = idx & 15;
+        const int64_t row = c0 + r;
+        const int64_t l = l0 + 8 * seg;
+        const bool ok = row < p && l < lend;
+        const uint4 v = *reinterpret_cast<const uint4*>(src + (row < p ? row : 0) * ld +
+                                                       (l < lend ? l : lbeg));
+        uint4 z = ok ? v : make_uint4(0, 0, 0, 0);
+        if (ok && l + 8 > lend) {  // ragged end of K inside the segment
+          uint16_t* h = reinterpret_cast<uint16_t*>(&z);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (l + u >= lend) h[u] = 0;
+        }
+        rg[e] = z;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    if (!stager) return;
+    if (TN) {
+      const int g = (t >> 3) & 15, cb = t & 7;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        *reinterpret_cast<uint4*>(&S[buf][op][8 * cb + c][8 * g]) = bf16_transpose_col(rg, c);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int idx = (t & 127) + 128 * e;
+        *reinterpret_cast<uint4*>(&S[buf][op][idx >> 4][8 * (idx & 15)]) = rg[e];
+      }
+    }
+  };
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+  if (stager) load(0);
+  store(0);
+  __syncthreads();
+  const int opb = diag ? 0 : 1;
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst && stager) load(st + 1);
+#pragma unroll
+    for (int k32 = 0; k32 < GKC / 32; ++k32) {
+      const int kof = k32 * 32 + 8 * (lane >> 4);
+      bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        av[a] = *reinterpret_cast<const bf16x8*>(&S[buf][0][wr * 32 + a * 16 + (lane & 15)][kof]);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        bv[b] = *reinterpret_cast<const bf16x8*>(&S[buf][opb][wc * 32 + b * 16 + (lane & 15)][kof]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (st + 1 < nst) store(buf ^ 1);
+    __syncthreads();
+  }
+  float* Ps = P + (int64_t)blockIdx.y * ldc * ldc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wr * 32 + a * 16 + mfma16_row<float>(lane, r);
+        const int64_t j = j0 + wc * 32 + b * 16 + (lane & 15);
+        Ps[i * ldc + j] = acc[a][b][r];
+      }
+}
+
 // M = sum_s P[s] (fixed order, FP64) + nu2 I on the lower tiles; identity past p.
 template <typename TAcc>
 __global__ __launch_bounds__(256) void k_gram_reduce(const TAcc* __restrict__ P, int nsplit,
@@ -935,6 +1090,10 @@ rs_status gram_partials(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
   const size_t lpes = sa_t == RS_BF16 ? 2 : 1;
   const bool lp_ok = (sa_t == RS_BF16 || sa_t == RS_FP8E4M3) &&
                      ((uintptr_t)SA % 16 == 0) && ((ldsa * lpes) % 16 == 0) && ldsa >= pp;
+  // the pipelined BF16 kernel reads 8-element groups: rows 16-byte aligned and
+  // the summed (NT) or column (TN) extent readable up to a multiple of 8
+  const bool bf16_ok = sa_t == RS_BF16 && ((uintptr_t)SA % 16 == 0) && (ldsa % 8 == 0) &&
+                       ldsa >= (wood ? (d + 7) / 8 * 8 : (p + 7) / 8 * 8);
   if ((size_t)nsplit * pp * pp * esz > F.gram_bytes)
     return set_error(RS_ERR_ARG, "factor: Gram scratch too small");
   if (sa_t == RS_F32) {
@@ -951,11 +1110,13 @@ rs_status gram_partials(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
       hipLaunchKernelGGL((k_gram<double, double, false>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
     else
       hipLaunchKernelGGL((k_gram<double, double, true>), gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp, (const float*)nullptr);
-  } else if (sa_t == RS_BF16 && !wood && lp_ok) {
+  } else if (sa_t == RS_BF16 && bf16_ok) {
     float* P = reinterpret_cast<float*>(F.gram);
-    hipLaunchKernelGGL(k_gram_lp_tn<uint16_t>, gg, dim3(256), 0, s,
-                       reinterpret_cast<const uint16_t*>(SA), ldsa, p, q, qchunk, P, pp,
-                       (const float*)nullptr);
+    const uint16_t* X = reinterpret_cast<const uint16_t*>(SA);
+    if (wood)
+      hipLaunchKernelGGL(k_gram_bf16<false>, gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
+    else
+      hipLaunchKernelGGL(k_gram_bf16<true>, gg, dim3(256), 0, s, X, ldsa, p, q, qchunk, P, pp);
   } else if (sa_t == RS_FP8E4M3 && !wood && lp_ok) {
     float* P = reinterpret_cast<float*>(F.gram);
     hipLaunchKernelGGL(k_gram_lp_tn<uint8_t>, gg, dim3(256), 0, s,
