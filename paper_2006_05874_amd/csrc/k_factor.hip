@@ -555,10 +555,13 @@ __device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
 // Right-looking blocked Cholesky M = L L^T, and Linv = L^-1 by block forward
 // substitution of L X = I carried along the same sweep: the Linv buffer starts
 // as the identity and holds the partially reduced right-hand side Y.  At step k
-//   diag  : L_kk (in place in M) and Linv_kk = L_kk^-1 (into the Linv buffer);
-//   panel : L_ik = M_ik Linv_kk^T (i > k), and X_kj = Linv_kk Y_kj (j < k);
+//   diag  : L_kk and Linv_kk = L_kk^-1 (into the Linv buffer);
+//   panel : L_ik = M_ik Linv_kk^T (i > k, into M), and X_kj = Linv_kk Y_kj (j < k);
 //   update: M_ij -= L_ik L_jk^T (k < j <= i), Y_ij -= L_ik X_kj (i > k, j <= k).
-// Every step adds one 64^3 tile product to the critical path.
+// The three run as one launch per step (k_chol_step): the update of step k - 1 is
+// applied by the blocks of step k that read the tiles it changes, and every block
+// that needs Linv_kk factors the diagonal tile itself.  The critical path of a step
+// is one tile product, the diagonal factor and one more tile product.
 
 // 1/sqrt(x) in FP64: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rsqrt64(double x) {
@@ -777,11 +780,68 @@ __device__ __forceinline__ void diag_panel(double (*a)[NB + 1], double (*x)[NB +
   __syncthreads();
 }
 
-// Panels that lie entirely in the identity padding (index >= p) are skipped:
-// there L = I and X = I already, and the earlier panels leave them unchanged
-// because the padding has zero coupling to the valid indices.
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64_t ld, int k,
-                                                   double* __restrict__ Linv,
+// LDS-operand 64 x 64 x 64 product on the FP64 matrix cores: q = op(A) op(B) with
+// op(A)[r][l] = A[r][l] and op(B)[l][c] = TB ? B[c][l] : B[l][c].  Wave w owns the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 tiles; slot r of tile (a, b) is row
+// 32 (w / 2) + 16 a + lane / 16 + 4 r, column 32 (w % 2) + 16 b + lane % 16.
+template <bool TB>
+__device__ __forceinline__ void lds_mm(f64x4 (&q)[2][2], const double (*A)[NB + 1],
+                                       const double (*B)[NB + 1]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) q[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k4 = 0; k4 < NB / 4; ++k4) {
+    const int kk = 4 * k4 + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) av[i] = A[wr * 32 + i * 16 + (lane & 15)][kk];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wc * 32 + j * 16 + (lane & 15);
+      bv[j] = TB ? B[c][kk] : B[kk][c];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        q[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], q[i][j], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void store_quadrants(const f64x4 (&q)[2][2], double* dst, int64_t ld) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dst[(int64_t)(wr * 32 + i * 16 + (lane >> 4) + 4 * r) * ld + wc * 32 + j * 16 +
+            (lane & 15)] = q[i][j][r];
+}
+
+// One step k of the blocked factor in a single launch.  The trailing update of step
+// k - 1 is applied lazily here, by the blocks that need it:
+//   block 0         : diagonal tile M_kk - L_k,k-1 L_k,k-1^T, factored and inverted
+//                     in LDS; writes Linv_kk (and the pivot flag);
+//   blocks 1..nrest : the same diagonal factor (recomputed, bitwise equal), then
+//                     L_ik = (M_ik - L_i,k-1 L_k,k-1^T) Linv_kk^T, i = k + b;
+//   next k blocks   : the same diagonal factor, then
+//                     X_kj = Linv_kk (Y_kj - L_k,k-1 X_k-1,j), j < k;
+//   the rest        : M_ij -= L_i,k-1 L_j,k-1^T (k < j <= i) and
+//                     Y_ij -= L_i,k-1 X_k-1,j (i > k, j < k).
+// No block writes what another block of the same launch reads: the diagonal tile of
+// M is only read (its factor is not needed after the step), column k of M and row k
+// of Linv are written by their own blocks, and the lazy updates touch only tiles past
+// column k or below row k.  Panels of the diagonal tile that lie entirely in the
+// identity padding (index >= p) are skipped: there L = I and X = I already.
+__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64_t ld, int k,
+                                                   int nblk, double* __restrict__ Linv,
                                                    int* __restrict__ info, int64_t p,
                                                    FactorBatch zb) {
   M += blockIdx.z * zb.sM;
@@ -790,101 +850,109 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
   __shared__ double x[NB][NB + 1];
   __shared__ double dinv[16][17];
   __shared__ double pbuf[16][4];
+  __shared__ TileLds tl;
   const int t = threadIdx.x;
-  const int64_t o = (int64_t)k * NB;
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    a[i][j] = M[(o + i) * ld + o + j];
-    x[i][j] = (i == j) ? 1.0 : 0.0;
+  const int ty = t >> 4, tx = t & 15;
+  const int nrest = nblk - 1 - k;
+  const int64_t ok = (int64_t)k * NB, okm = ok - NB;
+  const int64_t bid = blockIdx.x;
+  const int64_t nfac = 1 + nrest + k;
+  double acc[4][4];
+  zero_acc(acc);
+  if (bid >= nfac) {
+    // lazy trailing update by column block k - 1 (present only when k > 0)
+    const int64_t u = bid - nfac;
+    const int64_t tri = (int64_t)nrest * (nrest + 1) / 2;
+    double* dst;
+    if (u < tri) {
+      int64_t I = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+      while ((I + 1) * (I + 2) / 2 <= u) ++I;
+      while (I * (I + 1) / 2 > u) --I;
+      const int64_t J = u - I * (I + 1) / 2;
+      const int64_t oi = ok + (1 + I) * NB, oj = ok + (1 + J) * NB;
+      Opnd A{M + oi * ld + okm, ld, NB, NB, false};
+      Opnd B{M + oj * ld + okm, ld, NB, NB, true};
+      tile_mm(acc, A, B, NB, tl);
+      dst = M + oi * ld + oj;
+    } else {
+      const int64_t r = u - tri;
+      const int64_t I = r / k, J = r % k;
+      const int64_t oi = ok + (1 + I) * NB, oj = J * NB;
+      Opnd A{M + oi * ld + okm, ld, NB, NB, false};
+      Opnd B{Linv + okm * ld + oj, ld, NB, NB, false};
+      tile_mm(acc, A, B, NB, tl);
+      dst = Linv + oi * ld + oj;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[(int64_t)(ty * 4 + i) * ld + tx * 4 + j] -= acc[i][j];
+    return;
   }
+  // the diagonal tile with the update of step k - 1, then its factor and inverse
+  if (k > 0) {
+    Opnd A{M + ok * ld + okm, ld, NB, NB, false};
+    Opnd B{M + ok * ld + okm, ld, NB, NB, true};
+    tile_mm(acc, A, B, NB, tl);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = ty * 4 + i, c = tx * 4 + j;
+      a[r][c] = M[(ok + r) * ld + ok + c] - acc[i][j];
+      x[r][c] = (r == c) ? 1.0 : 0.0;
+    }
   __syncthreads();
   bool bad = false;
-  const int64_t valid = p - o;  // valid indices in this tile (>= 1)
+  const int64_t valid = p - ok;  // valid indices in this tile (>= 1)
   diag_panel<0>(a, x, dinv, pbuf, bad);
   if (valid > 16) diag_panel<16>(a, x, dinv, pbuf, bad);
   if (valid > 32) diag_panel<32>(a, x, dinv, pbuf, bad);
   if (valid > 48) diag_panel<48>(a, x, dinv, pbuf, bad);
-  if (bad) atomicExch(info, 1);
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    M[(o + i) * ld + o + j] = j <= i ? a[i][j] : 0.0;
-    Linv[(o + i) * ld + o + j] = j <= i ? x[i][j] : 0.0;
+  if (bid == 0) {
+    if (bad) atomicExch(info, 1);
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      const int i = idx >> 6, j = idx & 63;
+      Linv[(ok + i) * ld + ok + j] = j <= i ? x[i][j] : 0.0;
+    }
+    return;
   }
-}
-
-// Blocks [0, nrest): L_ik = M_ik Linv_kk^T, i = k + 1 + b.
-// Blocks [nrest, nrest + k): X_kj = Linv_kk Y_kj in place, j = b - nrest.
-__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int64_t ld, int k,
-                                                    int nrest, double* __restrict__ Linv,
-                                                    FactorBatch zb) {
-  M += blockIdx.z * zb.sM;
-  Linv += blockIdx.z * zb.sL;
-  __shared__ TileLds tl;
-  const int t = threadIdx.x;
-  const int ty = t >> 4, tx = t & 15;
-  const int64_t ok = (int64_t)k * NB;
-  double acc[4][4];
   zero_acc(acc);
-  double* dst;
-  int64_t ldd = ld;
-  if ((int)blockIdx.x < nrest) {
-    const int64_t oi = ok + (int64_t)(blockIdx.x + 1) * NB;
-    Opnd A{M + oi * ld + ok, ld, NB, NB, false};
-    Opnd B{Linv + ok * ld + ok, ld, NB, NB, true};
-    tile_mm(acc, A, B, NB, tl);
-    dst = M + oi * ld + ok;
+  f64x4 q[2][2];
+  if (bid <= nrest) {
+    // L_ik = (M_ik - L_i,k-1 L_k,k-1^T) Linv_kk^T
+    const int64_t oi = ok + bid * NB;
+    if (k > 0) {
+      Opnd A{M + oi * ld + okm, ld, NB, NB, false};
+      Opnd B{M + ok * ld + okm, ld, NB, NB, true};
+      tile_mm(acc, A, B, NB, tl);
+    }
+    // a is free: the diagonal factor is no longer needed (diag_panel and tile_mm end
+    // with a barrier)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        a[ty * 4 + i][tx * 4 + j] = M[(oi + ty * 4 + i) * ld + ok + tx * 4 + j] - acc[i][j];
+    __syncthreads();
+    lds_mm<true>(q, a, x);
+    store_quadrants(q, M + oi * ld + ok, ld);
   } else {
-    const int64_t oj = (int64_t)(blockIdx.x - nrest) * NB;
-    Opnd A{Linv + ok * ld + ok, ld, NB, NB, false};
-    Opnd B{Linv + ok * ld + oj, ld, NB, NB, false};
+    // X_kj = Linv_kk (Y_kj - L_k,k-1 X_k-1,j)
+    const int64_t oj = (bid - nrest - 1) * NB;
+    Opnd A{M + ok * ld + okm, ld, NB, NB, false};
+    Opnd B{Linv + okm * ld + oj, ld, NB, NB, false};
     tile_mm(acc, A, B, NB, tl);
-    dst = Linv + ok * ld + oj;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        a[ty * 4 + i][tx * 4 + j] = Linv[(ok + ty * 4 + i) * ld + oj + tx * 4 + j] - acc[i][j];
+    __syncthreads();
+    lds_mm<false>(q, x, a);
+    store_quadrants(q, Linv + ok * ld + oj, ld);
   }
-  // tile_mm ends with a barrier: every read of the destination tile is done
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dst[(int64_t)(ty * 4 + i) * ldd + tx * 4 + j] = acc[i][j];
-}
-
-// Blocks [0, tri(nrest)): M_ij -= L_ik L_jk^T for k < j <= i.
-// Blocks [tri(nrest), + nrest*(k+1)): Y_ij -= L_ik X_kj for i > k, j <= k.
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int64_t ld, int k,
-                                                     int nrest, double* __restrict__ Linv,
-                                                     FactorBatch zb) {
-  M += blockIdx.z * zb.sM;
-  Linv += blockIdx.z * zb.sL;
-  __shared__ TileLds tl;
-  const int64_t tri = (int64_t)nrest * (nrest + 1) / 2;
-  const int64_t bid = blockIdx.x;
-  const int64_t ok = (int64_t)k * NB;
-  double acc[4][4];
-  zero_acc(acc);
-  double* dst;
-  if (bid < tri) {
-    int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= bid) ++I;
-    while (I * (I + 1) / 2 > bid) --I;
-    const int64_t J = bid - I * (I + 1) / 2;
-    const int64_t oi = (k + 1 + I) * NB, oj = (k + 1 + J) * NB;
-    Opnd A{M + oi * ld + ok, ld, NB, NB, false};
-    Opnd B{M + oj * ld + ok, ld, NB, NB, true};
-    tile_mm(acc, A, B, NB, tl);
-    dst = M + oi * ld + oj;
-  } else {
-    const int64_t r = bid - tri;
-    const int64_t I = r / (k + 1), J = r % (k + 1);
-    const int64_t oi = (k + 1 + I) * NB, oj = J * NB;
-    Opnd A{M + oi * ld + ok, ld, NB, NB, false};
-    Opnd B{Linv + ok * ld + oj, ld, NB, NB, false};
-    tile_mm(acc, A, B, NB, tl);
-    dst = Linv + oi * ld + oj;
-  }
-  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dst[(int64_t)(ty * 4 + i) * ld + tx * 4 + j] -= acc[i][j];
 }
 
 // Linv buffer <- identity (p x p).
@@ -1169,17 +1237,11 @@ rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
     hipLaunchKernelGGL(k_fill_identity, dim3(g, 1, Bz), dim3(256), 0, s, F.Linv, pp, zb);
   }
   for (int k = 0; k < nblk; ++k) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1, 1, Bz), dim3(256), 0, s, F.M, pp, k, F.Linv, F.info, p,
-                       zb);
     const int nrest = nblk - 1 - k;
-    if (nrest + k > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)(nrest + k), 1, Bz), dim3(256), 0, s, F.M,
-                         pp, k, nrest, F.Linv, zb);
-    if (nrest > 0) {
-      const int64_t nb_upd = (int64_t)nrest * (nrest + 1) / 2 + (int64_t)nrest * (k + 1);
-      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nb_upd, 1, Bz), dim3(256), 0, s, F.M, pp,
-                         k, nrest, F.Linv, zb);
-    }
+    const int64_t nfac = 1 + nrest + k;
+    const int64_t nupd = k > 0 ? (int64_t)nrest * (nrest + 1) / 2 + (int64_t)nrest * k : 0;
+    hipLaunchKernelGGL(k_chol_step, dim3((unsigned)(nfac + nupd), 1, Bz), dim3(256), 0, s, F.M,
+                       pp, k, nblk, F.Linv, F.info, p, zb);
   }
   // 3. explicit inverse (skipped when the caller only needs L and L^-1)
   if (!F.Hinv) return check_launch("factor");

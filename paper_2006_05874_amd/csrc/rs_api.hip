@@ -1028,11 +1028,14 @@ struct SolveJob {
     return RS_OK;
   }
 
+  // the control record and the factor flag share one allocation (the flag right
+  // after the record), so one copy brings both to pinned memory
+  static constexpr size_t kFlagOff = (sizeof(DevCtl) + 15) / 16 * 16;
+
   // copy the control record and the factor flag to pinned memory, mark the point
   rs_status enqueue_read() {
-    RS_HIP(hipMemcpyAsync(S->host_pinned, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
-    RS_HIP(hipMemcpyAsync((char*)S->host_pinned + 512, finfo, sizeof(int),
-                          hipMemcpyDeviceToHost, stream));
+    RS_HIP(hipMemcpyAsync(S->host_pinned, dctl, kFlagOff + sizeof(int), hipMemcpyDeviceToHost,
+                          stream));
     RS_HIP(hipEventRecord(S->done_ev, stream));
     return RS_OK;
   }
@@ -1041,9 +1044,8 @@ struct SolveJob {
     std::memset(info, 0, sizeof(*info));
     RS_TRY(S->vecs.ensure((size_t)(4 + 3 * 2) * d * sizeof(double)));
     RS_TRY(S->rpart.ensure((size_t)nrp * 4 * sizeof(double)));
-    RS_TRY(S->ctl.ensure(sizeof(DevCtl)));
+    RS_TRY(S->ctl.ensure(kFlagOff + 16));
     RS_TRY(S->ev.ensure((size_t)ev_cap * sizeof(int32_t)));
-    RS_TRY(S->info.ensure(sizeof(int), true));
     if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
     if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
     x_prev = S->vecs.as<double>();
@@ -1054,7 +1056,7 @@ struct SolveJob {
     G = X + 2 * d;
     GT = G + 2 * d;
     dctl = S->ctl.as<DevCtl>();
-    finfo = S->info.as<int>();
+    finfo = reinterpret_cast<int*>(S->ctl.as<char>() + kFlagOff);
     status = &dctl->status;
     RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
     RS_TRY(sketch_and_factor(m, sid));
@@ -1101,7 +1103,7 @@ struct SolveJob {
     }
     std::memcpy(&h, S->host_pinned, sizeof(DevCtl));
     int fbad = 0;
-    std::memcpy(&fbad, (char*)S->host_pinned + 512, sizeof(int));
+    std::memcpy(&fbad, (char*)S->host_pinned + kFlagOff, sizeof(int));
     if (fbad) {
       result = set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: sketched Hessian factor failed");
       return conclude();
