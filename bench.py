@@ -211,8 +211,9 @@ def main():
     ms_per_step = ms_total / args.steps
     value = solves / (ms_total / 1e3)
     sres = pres = None
+    iso_launches, iso_ms = 0, 0.0
     if main_mode != "plain" and not args.skip_plain:
-        sres, sms, _, _ = timed("learned", profile=False)
+        sres, sms, _, (iso_launches, iso_ms) = timed("learned", profile=True)
         pres, pms, pwall, _ = timed("plain", profile=False)
 
     # verification against the oracle (FP64 direct solve of the stored problem),
@@ -271,6 +272,15 @@ def main():
             "kernel": "k_grad_partial (A^T(AX-b) pass, 2 RHS)", "avg_launch_us": round(avg_ms * 1e3, 2),
             "launches": launches}
 
+    roof_iso = None
+    if seq is not None and iso_launches:
+        iso_us = iso_ms / iso_launches * 1e3
+        iso_ach = alg_bytes / (iso_us / 1e6) / 1e9
+        roof_iso = {"bound": "hbm", "achieved": round(iso_ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(iso_ach / HBM_PEAK_GBS, 4),
+                    "avg_launch_us": round(iso_us, 2), "launches": iso_launches,
+                    "region": "learned + BF16 solves one at a time (no other stream's work "
+                              "beside the gradient pass)"}
     line = {
         "metric": ("ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32; HBM GB/s"
                    if main_mode != "plain" else
@@ -296,6 +306,8 @@ def main():
     }
     if seq is not None:
         line["learned_bf16_one_at_a_time"] = seq
+    if roof_iso is not None:
+        line["roofline_isolated"] = roof_iso
     if plain is not None:
         line["plain_fp32"] = plain
         line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)

@@ -25,8 +25,6 @@ __global__ __launch_bounds__(256) void k_rsum(const double* __restrict__ rpart, 
   if (threadIdx.x < K) r[threadIdx.x] = 0.5 * out[threadIdx.x];
 }
 
-constexpr int kApplyRPW = 1;
-
 int apply_blocks(int64_t d) { return (int)((d + 4 * kApplyRPW - 1) / (4 * kApplyRPW)); }
 
 rs_status apply_launch(const double* Hinv, int64_t ldh, int64_t d, const double* G, int k,

@@ -12,7 +12,19 @@
 namespace rs {
 
 // X[0] = x - mu_p gt + beta_p (x - x_prev), X[K-1] = x - mu_gd gt (K = 2);
-// K = 1 (gradient-only): X[0] = x - mu_gd gt.
+// K = 1 (gradient-only): X[0] = x - mu_gd gt.  One element; every kernel that
+// writes candidates goes through here, so they agree bit for bit.
+__device__ __forceinline__ void candidate_at(int K, int64_t d, int64_t i, double xi, double xpi,
+                                             double gi, double* __restrict__ X, double mu_p,
+                                             double beta_p, double mu_gd) {
+  if (K == 2) {
+    X[i] = xi - mu_p * gi + beta_p * (xi - xpi);
+    X[d + i] = xi - mu_gd * gi;
+  } else {
+    X[i] = xi - mu_gd * gi;
+  }
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_candidates(int64_t d, const double* __restrict__ x,
                                                     const double* __restrict__ x_prev,
@@ -21,15 +33,8 @@ __global__ __launch_bounds__(256) void k_candidates(int64_t d, const double* __r
                                                     double beta_p, double mu_gd,
                                                     const int* __restrict__ status) {
   if (status && *status != 0) return;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
-    const double xi = x[i], gi = gt[i];
-    if (K == 2) {
-      X[i] = xi - mu_p * gi + beta_p * (xi - x_prev[i]);
-      X[d + i] = xi - mu_gd * gi;
-    } else {
-      X[i] = xi - mu_gd * gi;
-    }
-  }
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256)
+    candidate_at(K, d, i, x[i], x_prev[i], gt[i], X, mu_p, beta_p, mu_gd);
 }
 
 struct DecideArgs {
@@ -38,22 +43,23 @@ struct DecideArgs {
   int32_t polyak;  // variant has a Polyak candidate (K = 2)
 };
 
-// Single block.  rpart: nrp x K partial sums of g^T gtilde.
-template <int K>
-__global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
-                                                 const double* __restrict__ rpart, int nrp,
-                                                 DecideArgs a, int64_t d,
-                                                 const double* __restrict__ X,
-                                                 const double* __restrict__ G,
-                                                 const double* __restrict__ GT,
-                                                 double* __restrict__ x, double* __restrict__ x_prev,
-                                                 double* __restrict__ g, double* __restrict__ gt,
-                                                 int32_t* __restrict__ ev_kind, int ev_cap) {
+// The decision on one block of NT threads.  rpart: nrp x K partial sums of
+// g^T gtilde.  With next set, an accepted step that leaves the state running also
+// writes the next step's candidates into X (from the new x, the old x and the new
+// gtilde).
+template <int K, int NT>
+__device__ __forceinline__ void decide_body(DevCtl* __restrict__ ctl,
+                                            const double* __restrict__ rpart, int nrp,
+                                            const DecideArgs& a, int64_t d,
+                                            double* __restrict__ X, const double* __restrict__ G,
+                                            const double* __restrict__ GT,
+                                            double* __restrict__ x, double* __restrict__ x_prev,
+                                            double* __restrict__ g, double* __restrict__ gt,
+                                            int32_t* __restrict__ ev_kind, int ev_cap, bool next) {
   __shared__ double r[K];
-  __shared__ double sh[1024 * K];
-  __shared__ int chosen;
-  if (ctl->status != RS_CTL_RUNNING) return;
-  block_sum_cols<K, 1024>(rpart, nrp, sh, r);
+  __shared__ double sh[NT * K];
+  __shared__ int chosen, run_next;
+  block_sum_cols<K, NT>(rpart, nrp, sh, r);
   if (threadIdx.x < K) r[threadIdx.x] *= 0.5;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -96,17 +102,39 @@ __global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
     ctl->last_r[1] = r[K - 1];
     ctl->status = st;
     chosen = c;
+    run_next = next && c >= 0 && st == RS_CTL_RUNNING;
   }
   __syncthreads();
   const int c = chosen;
   if (c < 0) return;
-  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+  const bool nx = run_next != 0;
+  for (int64_t i = threadIdx.x; i < d; i += NT) {
     const double xi = x[i];
+    const double xn = X[(int64_t)c * d + i];
+    const double gtn = GT[(int64_t)c * d + i];
     x_prev[i] = xi;
-    x[i] = X[(int64_t)c * d + i];
+    x[i] = xn;
     g[i] = G[(int64_t)c * d + i];
-    gt[i] = GT[(int64_t)c * d + i];
+    gt[i] = gtn;
+    if (nx) candidate_at(K, d, i, xn, xi, gtn, X, a.mu_p, a.beta_p, a.mu_gd);
   }
+}
+
+// Single block.  With next set the decision also writes the next step's
+// candidates (the step then needs no separate candidate launch).
+template <int K>
+__global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
+                                                 const double* __restrict__ rpart, int nrp,
+                                                 DecideArgs a, int64_t d, double* __restrict__ X,
+                                                 const double* __restrict__ G,
+                                                 const double* __restrict__ GT,
+                                                 double* __restrict__ x, double* __restrict__ x_prev,
+                                                 double* __restrict__ g, double* __restrict__ gt,
+                                                 int32_t* __restrict__ ev_kind, int ev_cap,
+                                                 int next) {
+  if (ctl->status != RS_CTL_RUNNING) return;
+  decide_body<K, 1024>(ctl, rpart, nrp, a, d, X, G, GT, x, x_prev, g, gt, ev_kind, ev_cap,
+                       next != 0);
 }
 
 // After the first gradient and apply: g <- G[0], gtilde <- GT[0], g_ref <- G[0],
@@ -120,9 +148,11 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
                                                      double* __restrict__ x_prev,
                                                      double* __restrict__ g,
                                                      double* __restrict__ gt,
-                                                     double* __restrict__ gref, int at_cap) {
+                                                     double* __restrict__ gref, int at_cap,
+                                                     NextCand nc) {
   __shared__ double sh[1024];
   __shared__ double rs1[1];
+  __shared__ int run;
   block_sum_cols<1, 1024>(rpart, nrp, sh, rs1);
   if (threadIdx.x == 0) {
     const double r = 0.5 * rs1[0];
@@ -140,12 +170,17 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
     else if (r <= tol * r) st = RS_CTL_CONVERGED;
     else if (1 >= max_iter) st = RS_CTL_MAXITER;
     ctl->status = st;
+    run = nc.X != nullptr && st == RS_CTL_RUNNING;
   }
+  __syncthreads();
+  const bool nx = run != 0;
   for (int64_t i = threadIdx.x; i < d; i += 1024) {
-    x_prev[i] = x[i];
+    const double xi = x[i], gti = GT[i];
+    x_prev[i] = xi;
     g[i] = G[i];
     gref[i] = G[i];
-    gt[i] = GT[i];
+    gt[i] = gti;
+    if (nx) candidate_at(nc.K, d, i, xi, xi, gti, nc.X, nc.mu_p, nc.beta_p, nc.mu_gd);
   }
 }
 
@@ -154,9 +189,13 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
                                                         const double* __restrict__ rpart, int nrp,
                                                         double tol, int64_t d,
                                                         const double* __restrict__ GT,
-                                                        double* __restrict__ gt, int at_cap) {
+                                                        double* __restrict__ gt, int at_cap,
+                                                        NextCand nc,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ x_prev) {
   __shared__ double sh[2048];
   __shared__ double s2[2];
+  __shared__ int run;
   block_sum_cols<2, 1024>(rpart, nrp, sh, s2);
   if (threadIdx.x == 0) {
     ctl->r_t = 0.5 * s2[0];
@@ -166,8 +205,15 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
     if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;
     else if (ctl->r_t <= tol * ctl->r_ref) st = RS_CTL_CONVERGED;
     ctl->status = st;
+    run = nc.X != nullptr && st == RS_CTL_RUNNING;
   }
-  for (int64_t i = threadIdx.x; i < d; i += 1024) gt[i] = GT[i];
+  __syncthreads();
+  const bool nx = run != 0;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    const double gti = GT[i];
+    gt[i] = gti;
+    if (nx) candidate_at(nc.K, d, i, x[i], x_prev[i], gti, nc.X, nc.mu_p, nc.beta_p, nc.mu_gd);
+  }
 }
 
 // Copy two vectors into a 2-column block (for the post-resample apply).
@@ -195,32 +241,35 @@ rs_status candidates_launch(int K, int64_t d, const double* x, const double* x_p
 }
 
 rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const CtlParams& p,
-                        int64_t d, const double* X, const double* G, const double* GT, double* x,
+                        int64_t d, double* X, const double* G, const double* GT, double* x,
                         double* x_prev, double* g, double* gt, int32_t* ev_kind, int ev_cap,
-                        hipStream_t s) {
+                        hipStream_t s, bool next) {
   DecideArgs a{p.mu_p, p.beta_p, p.mu_gd, p.cbar_p, p.cbar_gd, p.tol, p.max_iter, K == 2 ? 1 : 0};
+  const int nx = next ? 1 : 0;
   if (K == 2)
     hipLaunchKernelGGL(k_decide<2>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, a, d, X, G, GT, x,
-                       x_prev, g, gt, ev_kind, ev_cap);
+                       x_prev, g, gt, ev_kind, ev_cap, nx);
   else
     hipLaunchKernelGGL(k_decide<1>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, a, d, X, G, GT, x,
-                       x_prev, g, gt, ev_kind, ev_cap);
+                       x_prev, g, gt, ev_kind, ev_cap, nx);
   return check_launch("decide");
 }
 
 rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
                             int64_t max_iter, int64_t d, const double* G, const double* GT,
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
-                            int at_cap, hipStream_t s) {
+                            int at_cap, hipStream_t s, NextCand nc) {
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, max_iter, d, G,
-                     GT, x, x_prev, g, gt, gref, at_cap);
+                     GT, x, x_prev, g, gt, gref, at_cap, nc);
   return check_launch("init state");
 }
 
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
-                               const double* GT, double* gt, int at_cap, hipStream_t s) {
+                               const double* GT, double* gt, int at_cap, hipStream_t s,
+                               NextCand nc, const double* x, const double* x_prev) {
+  if (nc.X && (!x || !x_prev)) return set_error(RS_ERR_ARG, "post resample: candidates need x");
   hipLaunchKernelGGL(k_post_resample, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, d, GT, gt,
-                     at_cap);
+                     at_cap, nc, x, x_prev);
   return check_launch("post resample");
 }
 

@@ -937,17 +937,20 @@ struct SolveJob {
       if (g) (void)hipGraphExecDestroy(g);
   }
 
+  // one step = the gradient pass over the candidates (left in X by the previous
+  // decision, or by the start / resample kernels), the apply, and the decision,
+  // which also writes the next step's candidates
   rs_status enqueue_steps(int q) {
     for (int it = 0; it < q; ++it) {
-      RS_TRY(candidates_launch(K, d, x, x_prev, gt, X, prm.mu_p, prm.beta_p, prm.mu_gd, status,
-                               stream));
       RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
       RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
       RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
-                           gt, S->ev.as<int32_t>(), ev_cap, stream));
+                           gt, S->ev.as<int32_t>(), ev_cap, stream, true));
     }
     return RS_OK;
   }
+
+  NextCand next_cand() { return NextCand{X, prm.mu_p, prm.beta_p, prm.mu_gd, K}; }
 
   rs_status steps(int q) {
     if (!use_graph || g_prof_on) return enqueue_steps(q);
@@ -1064,7 +1067,7 @@ struct SolveJob {
     RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
     RS_TRY(apply_launch(Hinv, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
     RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, o.tol, o.max_iter, d, G, GT, x,
-                             x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream));
+                             x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream, next_cand()));
     return enqueue_read();
   }
 
@@ -1124,7 +1127,7 @@ struct SolveJob {
       RS_TRY(pack2_launch(d, g, gref, X, stream));
       RS_TRY(apply_launch(Hinv, dp, d, X, 2, GT, S->rpart.as<double>(), nullptr, stream));
       RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, o.tol, d, GT, gt,
-                                  m == m_cap ? 1 : 0, stream));
+                                  m == m_cap ? 1 : 0, stream, next_cand(), x, x_prev));
       applies += 1;
       queue = 1;
       return enqueue_read();

@@ -118,6 +118,7 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
                           const int* status, hipStream_t s);
 
 // ---------------------------------------------------------------- apply
+constexpr int kApplyRPW = 1;  // rows of H_S^-1 per wave in the apply
 int apply_blocks(int64_t d);
 rs_status apply_launch(const double* Hinv, int64_t ldh, int64_t d, const double* G, int k,
                        double* Y, double* rpart, const int* status, hipStream_t s);
@@ -150,15 +151,24 @@ rs_status candidates_launch(int K, int64_t d, const double* x, const double* x_p
                             const double* gt, double* X, double mu_p, double beta_p, double mu_gd,
                             const int* status, hipStream_t s);
 rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const CtlParams& p,
-                        int64_t d, const double* X, const double* G, const double* GT, double* x,
+                        int64_t d, double* X, const double* G, const double* GT, double* x,
                         double* x_prev, double* g, double* gt, int32_t* ev_kind, int ev_cap,
-                        hipStream_t s);
+                        hipStream_t s, bool next = false);
+// The next step's candidates, written by the kernel that leaves the state running
+// (X null: not written).
+struct NextCand {
+  double* X = nullptr;
+  double mu_p = 0.0, beta_p = 0.0, mu_gd = 0.0;
+  int K = 2;
+};
 rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
                             int64_t max_iter, int64_t d, const double* G, const double* GT,
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
-                            int at_cap, hipStream_t s);
+                            int at_cap, hipStream_t s, NextCand nc = NextCand());
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
-                               const double* GT, double* gt, int at_cap, hipStream_t s);
+                               const double* GT, double* gt, int at_cap, hipStream_t s,
+                               NextCand nc = NextCand(), const double* x = nullptr,
+                               const double* x_prev = nullptr);
 rs_status pack2_launch(int64_t d, const double* a, const double* b, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- nu grid
