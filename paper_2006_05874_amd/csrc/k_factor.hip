@@ -481,6 +481,31 @@ __device__ __forceinline__ void tile_fetch(const OA& A, const OB& B, int64_t k0,
   }
 }
 
+// quadrants (MFMA layout, wave w owns (w / 2, w % 2)) -> LDS (64 x 65) -> the
+// per-thread 4 x 4 layout, added into acc; ends with a barrier.
+__device__ __forceinline__ void quadrants_to_acc(const f64x4 (&q)[2][2], double (&acc)[4][4],
+                                                 TileLds& L) {
+  const int t = threadIdx.x;
+  const int ty = t >> 4, tx = t & 15;
+  const int lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  double* F = &L.A[0][0][0];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        F[(wr * 32 + a * 16 + (lane >> 4) + 4 * r) * (NB + 1) + wc * 32 + b * 16 + (lane & 15)] =
+            q[a][b][r];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] += F[(ty * 4 + i) * (NB + 1) + tx * 4 + j];
+  __syncthreads();
+}
+
 // acc (thread (ty, tx) holds rows 4ty.., columns 4tx..) += op(A) op(B) over kd.
 // The products run on the FP64 matrix cores: wave w owns the 32 x 32 quadrant
 // (w / 2, w % 2) as 2 x 2 tiles of v_mfma_f64_16x16x4 (operands A[row][k] and
@@ -489,7 +514,6 @@ __device__ __forceinline__ void tile_fetch(const OA& A, const OB& B, int64_t k0,
 template <typename OA, typename OB>
 __device__ void tile_mm(double (&acc)[4][4], const OA& A, const OB& B, int64_t kd, TileLds& L) {
   const int t = threadIdx.x;
-  const int ty = t >> 4, tx = t & 15;
   const int lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   f64x4 q[2][2];
@@ -526,22 +550,52 @@ __device__ void tile_mm(double (&acc)[4][4], const OA& A, const OB& B, int64_t k
     buf ^= 1;
   }
   __syncthreads();
-  // quadrants -> LDS (64 x 65) -> per-thread 4 x 4
-  double* F = &L.A[0][0][0];
+  quadrants_to_acc(q, acc, L);
+}
+
+// The same product for kd = 64 (one tile of the blocked factor): both K chunks are
+// fetched at once, so the product waits for one round trip to memory instead of
+// two.  The summation order is that of tile_mm.
+template <typename OA, typename OB>
+__device__ void tile_mm_k64(double (&acc)[4][4], const OA& A, const OB& B, TileLds& L) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  f64x4 q[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) q[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double ra[2][8], rb[2][8];
+  tile_fetch(A, B, 0, ra[0], rb[0]);
+  tile_fetch(A, B, TKC, ra[1], rb[1]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        F[(wr * 32 + a * 16 + (lane >> 4) + 4 * r) * (NB + 1) + wc * 32 + b * 16 + (lane & 15)] =
-            q[a][b][r];
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = t + 256 * e;
+      L.A[c][idx & 31][idx >> 5] = ra[c][e];
+      L.B[c][idx >> 6][idx & 63] = rb[c][e];
+    }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] += F[(ty * 4 + i) * (NB + 1) + tx * 4 + j];
+    for (int k4 = 0; k4 < TKC / 4; ++k4) {
+      const int kk = 4 * k4 + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = L.A[c][kk][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = L.B[c][kk][wc * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          q[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], q[a][b], 0, 0, 0);
+    }
   __syncthreads();
+  quadrants_to_acc(q, acc, L);
 }
 
 __device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
@@ -846,11 +900,17 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
                                                    FactorBatch zb) {
   M += blockIdx.z * zb.sM;
   Linv += blockIdx.z * zb.sL;
-  __shared__ double a[NB][NB + 1];
-  __shared__ double x[NB][NB + 1];
-  __shared__ double dinv[16][17];
-  __shared__ double pbuf[16][4];
-  __shared__ TileLds tl;
+  // one LDS region: the tile products' staging first, then the diagonal tile, its
+  // inverse and the small factor buffers (every product precedes the factor)
+  constexpr size_t kTile = sizeof(double) * NB * (NB + 1);
+  constexpr size_t kFac = 2 * kTile + sizeof(double) * (16 * 17 + 16 * 4);
+  constexpr size_t kLds = kFac > sizeof(TileLds) ? kFac : sizeof(TileLds);
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kLds];
+  TileLds& tl = *reinterpret_cast<TileLds*>(lds);
+  double (*a)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(lds);
+  double (*x)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(lds + kTile);
+  double (*dinv)[17] = reinterpret_cast<double (*)[17]>(lds + 2 * kTile);
+  double (*pbuf)[4] = reinterpret_cast<double (*)[4]>(lds + 2 * kTile + sizeof(double) * 16 * 17);
   const int t = threadIdx.x;
   const int ty = t >> 4, tx = t & 15;
   const int nrest = nblk - 1 - k;
@@ -872,7 +932,7 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
       const int64_t oi = ok + (1 + I) * NB, oj = ok + (1 + J) * NB;
       Opnd A{M + oi * ld + okm, ld, NB, NB, false};
       Opnd B{M + oj * ld + okm, ld, NB, NB, true};
-      tile_mm(acc, A, B, NB, tl);
+      tile_mm_k64(acc, A, B, tl);
       dst = M + oi * ld + oj;
     } else {
       const int64_t r = u - tri;
@@ -880,7 +940,7 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
       const int64_t oi = ok + (1 + I) * NB, oj = J * NB;
       Opnd A{M + oi * ld + okm, ld, NB, NB, false};
       Opnd B{Linv + okm * ld + oj, ld, NB, NB, false};
-      tile_mm(acc, A, B, NB, tl);
+      tile_mm_k64(acc, A, B, tl);
       dst = Linv + oi * ld + oj;
     }
 #pragma unroll
@@ -889,11 +949,40 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
       for (int j = 0; j < 4; ++j) dst[(int64_t)(ty * 4 + i) * ld + tx * 4 + j] -= acc[i][j];
     return;
   }
+  const bool pan = bid >= 1 && bid <= nrest;  // panel block (row tile k + bid)
+  const bool xrow = bid > nrest;              // inverse block row (column tile bid - nrest - 1)
+  // the panel or inverse tile with the update of step k - 1, kept in registers
+  // across the diagonal factor
+  double tile2[4][4];
+  zero_acc(tile2);
+  if (pan) {
+    const int64_t oi = ok + bid * NB;
+    if (k > 0) {
+      Opnd A{M + oi * ld + okm, ld, NB, NB, false};
+      Opnd B{M + ok * ld + okm, ld, NB, NB, true};
+      tile_mm_k64(tile2, A, B, tl);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        tile2[i][j] = M[(oi + ty * 4 + i) * ld + ok + tx * 4 + j] - tile2[i][j];
+  } else if (xrow) {
+    const int64_t oj = (bid - nrest - 1) * NB;
+    Opnd A{M + ok * ld + okm, ld, NB, NB, false};
+    Opnd B{Linv + okm * ld + oj, ld, NB, NB, false};
+    tile_mm_k64(tile2, A, B, tl);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        tile2[i][j] = Linv[(ok + ty * 4 + i) * ld + oj + tx * 4 + j] - tile2[i][j];
+  }
   // the diagonal tile with the update of step k - 1, then its factor and inverse
   if (k > 0) {
     Opnd A{M + ok * ld + okm, ld, NB, NB, false};
     Opnd B{M + ok * ld + okm, ld, NB, NB, true};
-    tile_mm(acc, A, B, NB, tl);
+    tile_mm_k64(acc, A, B, tl);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -918,40 +1007,21 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
     }
     return;
   }
-  zero_acc(acc);
+  // a is free (diag_panel ends with a barrier): the saved tile goes there
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[ty * 4 + i][tx * 4 + j] = tile2[i][j];
+  __syncthreads();
   f64x4 q[2][2];
-  if (bid <= nrest) {
+  if (pan) {
     // L_ik = (M_ik - L_i,k-1 L_k,k-1^T) Linv_kk^T
-    const int64_t oi = ok + bid * NB;
-    if (k > 0) {
-      Opnd A{M + oi * ld + okm, ld, NB, NB, false};
-      Opnd B{M + ok * ld + okm, ld, NB, NB, true};
-      tile_mm(acc, A, B, NB, tl);
-    }
-    // a is free: the diagonal factor is no longer needed (diag_panel and tile_mm end
-    // with a barrier)
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        a[ty * 4 + i][tx * 4 + j] = M[(oi + ty * 4 + i) * ld + ok + tx * 4 + j] - acc[i][j];
-    __syncthreads();
     lds_mm<true>(q, a, x);
-    store_quadrants(q, M + oi * ld + ok, ld);
+    store_quadrants(q, M + (ok + bid * NB) * ld + ok, ld);
   } else {
     // X_kj = Linv_kk (Y_kj - L_k,k-1 X_k-1,j)
-    const int64_t oj = (bid - nrest - 1) * NB;
-    Opnd A{M + ok * ld + okm, ld, NB, NB, false};
-    Opnd B{Linv + okm * ld + oj, ld, NB, NB, false};
-    tile_mm(acc, A, B, NB, tl);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        a[ty * 4 + i][tx * 4 + j] = Linv[(ok + ty * 4 + i) * ld + oj + tx * 4 + j] - acc[i][j];
-    __syncthreads();
     lds_mm<false>(q, x, a);
-    store_quadrants(q, Linv + ok * ld + oj, ld);
+    store_quadrants(q, Linv + ok * ld + (bid - nrest - 1) * NB, ld);
   }
 }
 

@@ -125,28 +125,13 @@ __global__ __launch_bounds__(256) void k_collect(uint64_t seed, uint32_t sid, in
   if (threadIdx.x == 0) blk_less[blockIdx.x] = cnt;
 }
 
-// One block: sort the candidates by (key, index) (bitonic, in LDS), keep the
-// first `need`, record the threshold, and turn blk_less into exclusive offsets.
-__global__ __launch_bounds__(1024) void k_cand_sort(SelectState* __restrict__ st,
-                                                    uint64_t* __restrict__ cand_key,
-                                                    int64_t* __restrict__ cand_idx,
-                                                    uint32_t* __restrict__ blk_less, int nblk) {
-  __shared__ uint64_t sk[kCandCap];
-  __shared__ int32_t si[kCandCap];
-  __shared__ uint32_t part[1024];
-  const uint32_t nc = st->ncand < (uint32_t)kCandCap ? st->ncand : (uint32_t)kCandCap;
-  uint32_t P = 1;
-  while (P < nc) P <<= 1;
-  for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-    if (i < nc) {
-      sk[i] = cand_key[i];
-      si[i] = (int32_t)cand_idx[i];
-    } else {
-      sk[i] = ~0ull;
-      si[i] = 0x7fffffff;
-    }
-  }
-  __syncthreads();
+// One block: sort the candidates by (key, index) (bitonic), keep the first `need`,
+// record the threshold, and turn blk_less into exclusive offsets.  The sort runs
+// in LDS sized at launch for the expected bin population (`cap` entries, dynamic
+// shared memory, so the block does not reserve the worst case and can start next
+// to other kernels); a bin larger than that is sorted in place in global memory.
+template <typename KeyT, typename IdxT>
+__device__ __forceinline__ void bitonic_by_key_index(KeyT* sk, IdxT* si, uint32_t P) {
   for (uint32_t k = 2; k <= P; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
@@ -155,18 +140,52 @@ __global__ __launch_bounds__(1024) void k_cand_sort(SelectState* __restrict__ st
           const bool up = (i & k) == 0;
           const bool gt = (sk[i] > sk[l]) || (sk[i] == sk[l] && si[i] > si[l]);
           if (gt == up) {
-            uint64_t tk = sk[i]; sk[i] = sk[l]; sk[l] = tk;
-            int32_t ti = si[i]; si[i] = si[l]; si[l] = ti;
+            KeyT tk = sk[i]; sk[i] = sk[l]; sk[l] = tk;
+            IdxT ti = si[i]; si[i] = si[l]; si[l] = ti;
           }
         }
       }
       __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void k_cand_sort(SelectState* __restrict__ st,
+                                                    uint64_t* __restrict__ cand_key,
+                                                    int64_t* __restrict__ cand_idx,
+                                                    uint32_t* __restrict__ blk_less, int nblk,
+                                                    uint32_t cap) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  __shared__ uint32_t part[1024];
+  const uint32_t nc = st->ncand < (uint32_t)kCandCap ? st->ncand : (uint32_t)kCandCap;
+  uint32_t P = 1;
+  while (P < nc) P <<= 1;
+  uint64_t* sk;
+  int64_t* si;
+  if (P <= cap) {
+    sk = reinterpret_cast<uint64_t*>(dyn);
+    si = reinterpret_cast<int64_t*>(dyn + (size_t)cap * sizeof(uint64_t));
+    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+      sk[i] = i < nc ? cand_key[i] : ~0ull;
+      si[i] = i < nc ? cand_idx[i] : (int64_t)0x7fffffffffffffffll;
+    }
+  } else {
+    // rare: the lists in global memory (capacity kCandCap) padded in place
+    sk = cand_key;
+    si = cand_idx;
+    for (uint32_t i = nc + threadIdx.x; i < P; i += blockDim.x) {
+      sk[i] = ~0ull;
+      si[i] = (int64_t)0x7fffffffffffffffll;
+    }
+  }
+  __syncthreads();
+  bitonic_by_key_index(sk, si, P);
   const uint32_t need = st->need;
   // write back the selected members sorted by index order is not needed: keep
   // them sorted by (key, idx); the scatter pass only counts them.
-  for (uint32_t i = threadIdx.x; i < need && i < nc; i += blockDim.x) cand_idx[i] = si[i];
+  // (in the global fallback the sorted indices are already in cand_idx)
+  if (P <= cap)
+    for (uint32_t i = threadIdx.x; i < need && i < nc; i += blockDim.x) cand_idx[i] = si[i];
   if (threadIdx.x == 0 && need >= 1 && need <= nc) {
     st->tkey = sk[need - 1];
     st->tidx = si[need - 1];
@@ -516,8 +535,12 @@ rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t
   const int nblk = (int)((npad + kCompactBlock - 1) / kCompactBlock);
   hipLaunchKernelGGL(k_collect, dim3(nblk), dim3(256), 0, s, seed, sid, npad, st, B.cand_key,
                      B.cand_idx, B.blk_less);
-  hipLaunchKernelGGL(k_cand_sort, dim3(1), dim3(1024), 0, s, st, B.cand_key, B.cand_idx,
-                     B.blk_less, nblk);
+  // expected boundary-bin population npad / 4096; LDS for 16x that (at least 256,
+  // at most 4096 entries = 64 KiB)
+  uint32_t cap = 256;
+  while ((int64_t)cap < 16 * ((npad + kHistBins - 1) / kHistBins) && cap < 4096u) cap <<= 1;
+  hipLaunchKernelGGL(k_cand_sort, dim3(1), dim3(1024), (size_t)cap * 16, s, st, B.cand_key,
+                     B.cand_idx, B.blk_less, nblk, cap);
   hipLaunchKernelGGL(k_scatter_rows, dim3(nblk), dim3(256), 0, s, seed, sid, npad, st,
                      B.cand_idx, B.blk_less, rows, B.kmap, B.used, n2 - 1, m);
   hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, s, B.used, (int)n2, B.qmap, B.qlist,
