@@ -879,6 +879,77 @@ __device__ __forceinline__ void store_quadrants(const f64x4 (&q)[2][2], double* 
             (lane & 15)] = q[i][j][r];
 }
 
+// The lazy products of one factor step in one pass over two staged operands:
+// U (A-layout, L.A[k][row] = U[row][k]) and V (B-layout, L.B[k][col] = V[k][col]),
+// both 64 x 64 with K = 64, fetched in one round trip.  d += S S^T where S is the
+// step's previous column tile L_k,k-1, read from L.A (sfromA: S = U) or from L.B
+// (S^T = V); with pair set also p += U V.  The k order is that of tile_mm, so every
+// block that forms S S^T gets the same bits.
+template <typename OU, typename OV>
+__device__ void step_products(double (&dacc)[4][4], double (&pacc)[4][4], const OU& U,
+                              const OV& V, bool stage_v, bool sfromA, bool pair, TileLds& L) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  f64x4 qd[2][2], qp[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      qd[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+      qp[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+  double ra[2][8], rb[2][8];
+  tile_fetch(U, V, 0, ra[0], rb[0]);
+  tile_fetch(U, V, TKC, ra[1], rb[1]);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = t + 256 * e;
+      L.A[c][idx & 31][idx >> 5] = ra[c][e];
+      if (stage_v) L.B[c][idx >> 6][idx & 63] = rb[c][e];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int k4 = 0; k4 < TKC / 4; ++k4) {
+      const int kk = 4 * k4 + (lane >> 4);
+      double sr[2], sc[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = wr * 32 + a * 16 + (lane & 15);
+        sr[a] = sfromA ? L.A[c][kk][r] : L.B[c][kk][r];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int col = wc * 32 + b * 16 + (lane & 15);
+        sc[b] = sfromA ? L.A[c][kk][col] : L.B[c][kk][col];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          qd[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sr[a], sc[b], qd[a][b], 0, 0, 0);
+      if (pair) {
+        double ur[2], vc[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) ur[a] = L.A[c][kk][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) vc[b] = L.B[c][kk][wc * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            qp[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ur[a], vc[b], qp[a][b], 0, 0, 0);
+      }
+    }
+  __syncthreads();
+  quadrants_to_acc(qd, dacc, L);
+  if (pair) quadrants_to_acc(qp, pacc, L);
+}
+
 // One step k of the blocked factor in a single launch.  The trailing update of step
 // k - 1 is applied lazily here, by the blocks that need it:
 //   block 0         : diagonal tile M_kk - L_k,k-1 L_k,k-1^T, factored and inverted
@@ -951,17 +1022,26 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
   }
   const bool pan = bid >= 1 && bid <= nrest;  // panel block (row tile k + bid)
   const bool xrow = bid > nrest;              // inverse block row (column tile bid - nrest - 1)
-  // the panel or inverse tile with the update of step k - 1, kept in registers
-  // across the diagonal factor
+  // the update of step k - 1 on the diagonal tile (acc) and on the block's panel or
+  // inverse tile (tile2, kept in registers across the diagonal factor), from one
+  // staging of L_k,k-1 and the tile's own operand
   double tile2[4][4];
   zero_acc(tile2);
+  if (k > 0) {
+    const Opnd S{M + ok * ld + okm, ld, NB, NB, false};     // L_k,k-1
+    const Opnd ST{M + ok * ld + okm, ld, NB, NB, true};     // L_k,k-1^T
+    if (pan) {
+      const Opnd U{M + (ok + bid * NB) * ld + okm, ld, NB, NB, false};  // L_i,k-1
+      step_products(acc, tile2, U, ST, true, false, true, tl);
+    } else if (xrow) {
+      const Opnd V{Linv + okm * ld + (bid - nrest - 1) * NB, ld, NB, NB, false};  // X_k-1,j
+      step_products(acc, tile2, S, V, true, true, true, tl);
+    } else {
+      step_products(acc, tile2, S, S, false, true, false, tl);
+    }
+  }
   if (pan) {
     const int64_t oi = ok + bid * NB;
-    if (k > 0) {
-      Opnd A{M + oi * ld + okm, ld, NB, NB, false};
-      Opnd B{M + ok * ld + okm, ld, NB, NB, true};
-      tile_mm_k64(tile2, A, B, tl);
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -969,20 +1049,11 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
         tile2[i][j] = M[(oi + ty * 4 + i) * ld + ok + tx * 4 + j] - tile2[i][j];
   } else if (xrow) {
     const int64_t oj = (bid - nrest - 1) * NB;
-    Opnd A{M + ok * ld + okm, ld, NB, NB, false};
-    Opnd B{Linv + okm * ld + oj, ld, NB, NB, false};
-    tile_mm_k64(tile2, A, B, tl);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         tile2[i][j] = Linv[(ok + ty * 4 + i) * ld + oj + tx * 4 + j] - tile2[i][j];
-  }
-  // the diagonal tile with the update of step k - 1, then its factor and inverse
-  if (k > 0) {
-    Opnd A{M + ok * ld + okm, ld, NB, NB, false};
-    Opnd B{M + ok * ld + okm, ld, NB, NB, true};
-    tile_mm_k64(acc, A, B, tl);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
