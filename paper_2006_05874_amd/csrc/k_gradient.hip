@@ -261,11 +261,9 @@ void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, c
                     double* partial, int grid, int64_t rpb, const int* status, hipStream_t s) {
   constexpr int GPB = 256 / TPR;
   const int iters = (int)((rpb + GPB * R - 1) / (GPB * R));
-  const ProfSlot ps = prof_begin(s);
-  int* ran = ps.ran;
-  hipLaunchKernelGGL((k_grad_partial<T, TPR, NV, K, R>), dim3(grid), dim3(256), 0, s, A, n, d, lda,
-                     b, X, rpb, iters, partial, status, ran);
-  prof_end(ps, s);
+  const ProfSlot ps = prof_begin();
+  launch_timed(k_grad_partial<T, TPR, NV, K, R>, dim3(grid), dim3(256), s, ps.begin, ps.end, A, n,
+               d, lda, b, X, rpb, iters, partial, status, ps.ran);
 }
 
 template <typename T, int K>

@@ -257,16 +257,15 @@ rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
   const unsigned g0 = (unsigned)std::min<int64_t>((nx + 255) / 256, 4096);
   hipLaunchKernelGGL(k_round_x<T>, dim3(g0), dim3(256), 0, s, X, nx, XT);
   const unsigned g1 = (unsigned)(((n + 127) / 128) * ncb);
-  const ProfSlot ps = prof_begin(s);
-  int* ran = ps.ran;
-  hipLaunchKernelGGL(k_mr_resid<T>, dim3(g1), dim3(512), 0, s, A, n, d, lda, b, XT, Kc, R, ldr,
-                     ncb, ran);
+  // profiled as one span: the first kernel's start to the second one's stop
+  const ProfSlot ps = prof_begin();
+  launch_timed(k_mr_resid<T>, dim3(g1), dim3(512), s, ps.begin, nullptr, A, n, d, lda, b,
+               (const T*)XT, Kc, R, ldr, ncb, ps.ran);
   int64_t rps = 0;
   const int ns = mr_splits(n, d, Kc, rps);
   const unsigned g2 = (unsigned)(((d + 127) / 128) * ncb);
-  hipLaunchKernelGGL(k_mr_atr<T>, dim3(g2, (unsigned)ns), dim3(512), 0, s, A, n, d, lda, R, ldr,
-                     Kc, rps, ncb, Gp);
-  prof_end(ps, s);
+  launch_timed(k_mr_atr<T>, dim3(g2, (unsigned)ns), dim3(512), s, nullptr, ps.end, A, n, d, lda,
+               (const T*)R, ldr, Kc, rps, ncb, Gp);
   const unsigned g3 = (unsigned)std::min<int64_t>((Kc * d + 255) / 256, 4096);
   hipLaunchKernelGGL(k_mr_reduce, dim3(g3), dim3(256), 0, s, Gp, ns, d, ldr, Kc, kper, X, nu2, zl,
                      G);

@@ -63,7 +63,8 @@ int device_cus() {
 // that the kernel sets when it does its work (launches queued behind a raised
 // status flag return at once and are not counted).
 // Worker threads of a batch launch concurrently: the slot counter and the event
-// list are guarded by g_prof_mu, and each launch keeps its own slot.
+// list are guarded by g_prof_mu, and each launch keeps its own slot.  The events
+// are updated by the profiled launch itself with the kernel's start and stop.
 static std::mutex g_prof_mu;
 static std::atomic<bool> g_prof_on{false};
 static std::vector<hipEvent_t> g_prof_ev;  // begin/end pairs
@@ -71,29 +72,21 @@ static size_t g_prof_pairs = 0;            // launches bracketed
 static int* g_prof_ran = nullptr;          // device flags, one per launch
 static constexpr size_t kProfCap = 1 << 16;
 
-ProfSlot prof_begin(hipStream_t s) {
+ProfSlot prof_begin() {
   ProfSlot ps;
   if (!g_prof_on.load(std::memory_order_relaxed)) return ps;
-  hipEvent_t e = nullptr;
-  {
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on || g_prof_pairs >= kProfCap) return ps;
-    while (g_prof_ev.size() < 2 * (g_prof_pairs + 1)) {
-      hipEvent_t ne;
-      if (hipEventCreate(&ne) != hipSuccess) return ps;
-      g_prof_ev.push_back(ne);
-    }
-    ps.slot = (int64_t)g_prof_pairs++;
-    e = g_prof_ev[2 * ps.slot];
-    ps.end = g_prof_ev[2 * ps.slot + 1];
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (!g_prof_on || g_prof_pairs >= kProfCap) return ps;
+  while (g_prof_ev.size() < 2 * (g_prof_pairs + 1)) {
+    hipEvent_t ne;
+    if (hipEventCreate(&ne) != hipSuccess) return ps;
+    g_prof_ev.push_back(ne);
   }
-  (void)hipEventRecord(e, s);
+  ps.slot = (int64_t)g_prof_pairs++;
+  ps.begin = g_prof_ev[2 * ps.slot];
+  ps.end = g_prof_ev[2 * ps.slot + 1];
   ps.ran = g_prof_ran ? g_prof_ran + ps.slot : nullptr;
   return ps;
-}
-
-void prof_end(const ProfSlot& ps, hipStream_t s) {
-  if (ps.slot >= 0 && ps.end) (void)hipEventRecord(ps.end, s);
 }
 
 // ------------------------------------------------------------------ scratch
@@ -1062,12 +1055,26 @@ struct SolveJob {
     finfo = reinterpret_cast<int*>(S->ctl.as<char>() + kFlagOff);
     status = &dctl->status;
     RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
+    // g_1 at x_0 needs no sketch: it runs on the side stream beside the sketch and
+    // the factor (its scratch is not theirs)
+    RS_TRY(S->ensure_aux());
+    RS_HIP(hipEventRecord(S->fork_ev, stream));
+    RS_HIP(hipStreamWaitEvent(S->aux, S->fork_ev, 0));
+    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, S->aux));
+    RS_HIP(hipEventRecord(S->join_ev, S->aux));
     RS_TRY(sketch_and_factor(m, sid));
-    // g_1, gtilde_1, r_1
-    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
+    RS_HIP(hipStreamWaitEvent(stream, S->join_ev, 0));
+    // gtilde_1, r_1
     RS_TRY(apply_launch(Hinv, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
     RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, o.tol, o.max_iter, d, G, GT, x,
                              x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream, next_cand()));
+    if (lp_params) {
+      // a predicted starting m is usually large enough for the first steps to be
+      // accepted: queue check_every of them now instead of reading the state first
+      // (a rejection turns the rest into no-ops, as in any queued batch)
+      RS_TRY(steps(check_every));
+      queue = check_every;
+    }
     return enqueue_read();
   }
 

@@ -1,6 +1,7 @@
 // Internal declarations shared by the librs translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -16,13 +17,25 @@ rs_status set_error(rs_status st, const char* msg);
 rs_status check_launch(const char* what);
 int device_cus();
 // kernel timing hooks (no-ops unless rs_profile_enable(1))
+// A profiled launch gets a slot: its "did work" flag and the two events that the
+// launch itself updates with the kernel's start and stop times
+// (hipExtLaunchKernelGGL), so timing adds no packets to the stream.
 struct ProfSlot {
   int64_t slot = -1;        // -1: not profiled
   int* ran = nullptr;       // the launch's "did work" flag, or null
-  hipEvent_t end = nullptr;
+  hipEvent_t begin = nullptr, end = nullptr;
 };
-ProfSlot prof_begin(hipStream_t s);
-void prof_end(const ProfSlot& ps, hipStream_t s);
+ProfSlot prof_begin();
+
+// hipLaunchKernelGGL, or with start/stop events when either is given.
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 // ---------------------------------------------------------------- SRHT
 struct SrhtBuffers {

@@ -347,9 +347,15 @@ def _batch_problems(problems, where):
     a_ts = [_mat(A, where) for A, _, _ in problems]
     P = (Problem * len(problems))()
     xs, bs = [], []
+    # one zeroed allocation for every solution (views of it, 16-byte aligned)
+    offs, tot = [], 0
+    for A, _, _ in problems:
+        offs.append(tot)
+        tot += (A.shape[1] + 1) // 2 * 2
+    X = torch.zeros(max(tot, 1), dtype=torch.float64, device=problems[0][0].device)
     for i, (A, b, nu2) in enumerate(problems):
         n, d = A.shape
-        x = torch.zeros(d, dtype=torch.float64, device=A.device)
+        x = X[offs[i]:offs[i] + d]
         bc = b.contiguous()
         xs.append(x)
         bs.append(bc)
