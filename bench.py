@@ -47,7 +47,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default="polyak", choices=["polyak", "gd"])
     ap.add_argument("--check-every", type=int, default=4)
-    ap.add_argument("--mode", default="learned-bf16", choices=["learned-bf16", "plain"])
+    ap.add_argument("--mode", default="learned-bf16",
+                    choices=["learned-bf16", "learned-single", "plain"],
+                    help="learned-bf16: the step's solves batched (the value); learned-single: "
+                         "the same solves one at a time; plain: FP32 sketch, m from 1")
     ap.add_argument("--model", default=None, help="learned-start model (.npz)")
     ap.add_argument("--skip-plain", action="store_true",
                     help="do not time the plain method beside the learned form")
@@ -143,7 +146,7 @@ def main():
     plans = {k: rs.rs_gradient_autotune(A, b, k=k) for k in (1, 2)}
 
     model = None
-    if args.mode == "learned-bf16":
+    if args.mode in ("learned-bf16", "learned-single"):
         from paper_2006_05874_amd import learned
         path = args.model or learned.MODEL_PATH
         if not os.path.exists(path):
@@ -208,7 +211,7 @@ def main():
 
     solves = args.steps * len(NU2S)
     main_mode = args.mode
-    main = "plain" if main_mode == "plain" else "learned-batched"
+    main = {"plain": "plain", "learned-single": "learned"}.get(main_mode, "learned-batched")
     # value: the timed steps as the library runs them; roofline: the same steps
     # again with every gradient launch timed by HIP events (timing costs about 4%
     # of the step, so it gets a timed region of its own)
@@ -218,7 +221,7 @@ def main():
     rres, rms, _, (launches, grad_ms) = timed(main, profile=True)
     sres = pres = None
     iso_launches, iso_ms = 0, 0.0
-    if main_mode != "plain" and not args.skip_plain:
+    if main_mode == "learned-bf16" and not args.skip_plain:
         sres, sms, _, _ = timed("learned", profile=False)
         ires, _, _, (iso_launches, iso_ms) = timed("learned", profile=True)
         pres, pms, pwall, _ = timed("plain", profile=False)
@@ -274,28 +277,28 @@ def main():
 
     # roofline of the dominant kernel: the gradient pass over A
     alg_bytes = N * D * 4 + N * 4
-    avg_ms = grad_ms / max(launches, 1)
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
-    traffic = recorded_traffic()
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": round(traffic) if traffic else None,
-            "algorithmic_bytes": alg_bytes,
-            "kernel": "k_grad_partial (A^T(AX-b) pass, 2 RHS)", "avg_launch_us": round(avg_ms * 1e3, 2),
-            "launches": launches,
-            "region": "the timed steps repeated with each gradient launch timed by its own "
-                      "HIP start/stop events (hipExtLaunchKernelGGL), on its stream",
-            "profiled_ms_per_step": round(rms / args.steps, 3)}
+    def roofline(n_launch, ms, region):
+        us = ms / max(n_launch, 1) * 1e3
+        ach = alg_bytes / (us / 1e6) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic else None, "algorithmic_bytes": alg_bytes,
+                "kernel": "k_grad_partial (A^T(AX-b) pass, 2 RHS)",
+                "avg_launch_us": round(us, 2), "launches": n_launch, "region": region}
 
+    traffic = recorded_traffic()
+    timing = ("each gradient launch timed by its own HIP start/stop events "
+              "(hipExtLaunchKernelGGL) on its stream")
+    roof_main = roofline(launches, grad_ms, "the timed steps repeated, " + timing)
+    roof_main["profiled_ms_per_step"] = round(rms / args.steps, 3)
     roof_iso = None
     if seq is not None and iso_launches:
-        iso_us = iso_ms / iso_launches * 1e3
-        iso_ach = alg_bytes / (iso_us / 1e6) / 1e9
-        roof_iso = {"bound": "hbm", "achieved": round(iso_ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(iso_ach / HBM_PEAK_GBS, 4),
-                    "avg_launch_us": round(iso_us, 2), "launches": iso_launches,
-                    "region": "learned + BF16 solves one at a time (no other stream's work "
-                              "beside the gradient pass)"}
+        roof_iso = roofline(iso_launches, iso_ms,
+                            "the learned + BF16 solves one at a time, repeated, " + timing +
+                            "; no other stream's kernels beside the pass")
+    # the roofline reported is the kernel's own (solves one at a time); in the
+    # batched steps two streams share HBM, which lengthens each launch
+    roof = roof_iso if roof_iso is not None else roof_main
     line = {
         "metric": ("ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32; HBM GB/s"
                    if main_mode != "plain" else
@@ -306,9 +309,11 @@ def main():
         "dtype": "bf16 sketch / f32 gradient / f64 factor" if main_mode != "plain" else "f32",
         "data": "synthetic (seeded low-rank-decay A = G diag(1/i) V^T)",
         "config": {"workload": f"{N}x{D} FP32, sigma_i=1/i, nu^2 in {list(NU2S)}, SRHT rho=0.1, "
-                               + ("learned m_init, BF16 sketch, the step's solves batched "
-                                  "over 2 streams" if main_mode != "plain"
-                                  else "m_init=1, FP32 sketch")
+                               + {"learned-bf16": "learned m_init, BF16 sketch, the step's "
+                                                  "solves batched over 2 streams",
+                                  "learned-single": "learned m_init, BF16 sketch, one solve "
+                                                    "at a time",
+                                  "plain": "m_init=1, FP32 sketch"}[main_mode]
                                + f", {args.variant}, 2 solves per step",
                    "mode": main_mode,
                    "gradient_plan_k2": list(plans[2]),
@@ -322,7 +327,7 @@ def main():
     if seq is not None:
         line["learned_bf16_one_at_a_time"] = seq
     if roof_iso is not None:
-        line["roofline_isolated"] = roof_iso
+        line["roofline_overlapped"] = roof_main
     if plain is not None:
         line["plain_fp32"] = plain
         line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)
