@@ -375,12 +375,15 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const uint16_t* __restrict__ 
 }
 
 // M = sum_s P[s] (fixed order, FP64) + nu2 I on the lower tiles; identity past p.
+// Also sets the same tile of the L^-1 buffer (when given) to the identity: the
+// lower tiles are all the factor sweep reads of it.
 template <typename TAcc>
 __global__ __launch_bounds__(256) void k_gram_reduce(const TAcc* __restrict__ P, int nsplit,
                                                      int64_t p, double nu2,
                                                      double* __restrict__ C, int64_t ldc,
-                                                     FactorBatch zb) {
+                                                     FactorBatch zb, double* __restrict__ X) {
   C += blockIdx.z * zb.sM;
+  if (X) X += blockIdx.z * zb.sL;
   if (zb.nu2) nu2 = zb.nu2[blockIdx.z];
   const int64_t bid = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
@@ -395,6 +398,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const TAcc* __restrict__ P,
     if (i == j) v += nu2;
     if (i >= p || j >= p) v = (i == j) ? 1.0 : 0.0;
     C[i * ldc + j] = v;
+    if (X) X[i * ldc + j] = (i == j) ? 1.0 : 0.0;
   }
 }
 
@@ -1096,16 +1100,6 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
   }
 }
 
-// Linv buffer <- identity (p x p).
-__global__ __launch_bounds__(256) void k_fill_identity(double* __restrict__ X, int64_t p,
-                                                       FactorBatch zb) {
-  X += blockIdx.z * zb.sL;
-  const int64_t total = p * p;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * 256)
-    X[i] = (i / p == i % p) ? 1.0 : 0.0;
-}
-
 // Hinv = Linv^T Linv (p x p, both triangles): tile (I, J), J <= I:
 // sum_{l >= I} Linv_lI^T Linv_lJ.
 __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, int64_t ld,
@@ -1365,18 +1359,16 @@ rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
   int nsplit;
   int64_t qchunk;
   gram_split(m, d, nsplit, qchunk);
+  // (the reduction also starts the L^-1 buffer as the identity)
   if (sa_t == RS_F64)
     hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s,
-                       reinterpret_cast<const double*>(F.gram), nsplit, p, nu2, F.M, pp, zb);
+                       reinterpret_cast<const double*>(F.gram), nsplit, p, nu2, F.M, pp, zb,
+                       F.Linv);
   else
     hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles, 1, Bz), dim3(256), 0, s,
-                       reinterpret_cast<const float*>(F.gram), nsplit, p, nu2, F.M, pp, zb);
+                       reinterpret_cast<const float*>(F.gram), nsplit, p, nu2, F.M, pp, zb,
+                       F.Linv);
   // 2. Cholesky + Linv
-  {
-    const int64_t tot = pp * pp;
-    const unsigned g = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_identity, dim3(g, 1, Bz), dim3(256), 0, s, F.Linv, pp, zb);
-  }
   for (int k = 0; k < nblk; ++k) {
     const int nrest = nblk - 1 - k;
     const int64_t nfac = 1 + nrest + k;

@@ -946,7 +946,7 @@ struct SolveJob {
   NextCand next_cand() { return NextCand{X, prm.mu_p, prm.beta_p, prm.mu_gd, K}; }
 
   rs_status steps(int q) {
-    if (!use_graph || g_prof_on) return enqueue_steps(q);
+    if (!use_graph || g_prof_on || (q != 1 && q != check_every)) return enqueue_steps(q);
     hipGraphExec_t& ex = gx[q == 1 ? 0 : 1];
     if (!ex) {
       RS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -1120,8 +1120,18 @@ struct SolveJob {
     }
     if (h.status == RS_CTL_RUNNING) {
       // one step right after a resample (the next step is often rejected again
-      // while m is small), check_every steps after accepted ones
-      RS_TRY(steps(queue));
+      // while m is small), check_every steps after accepted ones; with accepted
+      // steps behind it and no resample yet, as many as the observed contraction
+      // (r_t / r_1)^(1 / (t - 1)) needs to reach tol * r_ref (queued steps past
+      // convergence are no-ops, a shortfall only costs one more read)
+      int q = queue;
+      if (queue == check_every && dbl_t.empty() && h.t > 1 && h.r_t > 0.0 && h.r_t < h.r_1) {
+        const double rho = std::pow(h.r_t / h.r_1, 1.0 / (double)(h.t - 1));
+        const double need = std::log(o.tol * h.r_ref / h.r_t) / std::log(rho);
+        if (std::isfinite(need) && need > 0.0)
+          q = (int)std::min<double>(std::ceil(need), 2.0 * check_every);
+      }
+      RS_TRY(steps(q));
       queue = check_every;
       return enqueue_read();
     }
