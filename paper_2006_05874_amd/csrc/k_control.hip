@@ -43,6 +43,16 @@ struct DecideArgs {
   int32_t polyak;  // variant has a Polyak candidate (K = 2)
 };
 
+// Thread 0, after it changed the record: the copy for the host (system-scope
+// release, so it is visible once the kernel has completed).
+__device__ __forceinline__ void publish(const DevCtl* ctl, const CtlSnap& sn) {
+  if (!sn.host) return;
+  *reinterpret_cast<DevCtl*>(sn.host) = *ctl;
+  *reinterpret_cast<int*>(reinterpret_cast<char*>(sn.host) + kSnapFlagOff) =
+      sn.flag ? *sn.flag : 0;
+  __threadfence_system();
+}
+
 // The decision on one block of NT threads.  rpart: nrp x K partial sums of
 // g^T gtilde.  With next set, an accepted step that leaves the state running also
 // writes the next step's candidates into X (from the new x, the old x and the new
@@ -55,7 +65,8 @@ __device__ __forceinline__ void decide_body(DevCtl* __restrict__ ctl,
                                             const double* __restrict__ GT,
                                             double* __restrict__ x, double* __restrict__ x_prev,
                                             double* __restrict__ g, double* __restrict__ gt,
-                                            int32_t* __restrict__ ev_kind, int ev_cap, bool next) {
+                                            int32_t* __restrict__ ev_kind, int ev_cap, bool next,
+                                            const CtlSnap& sn) {
   __shared__ double r[K];
   __shared__ double sh[NT * K];
   __shared__ int chosen, run_next;
@@ -103,6 +114,7 @@ __device__ __forceinline__ void decide_body(DevCtl* __restrict__ ctl,
     ctl->status = st;
     chosen = c;
     run_next = next && c >= 0 && st == RS_CTL_RUNNING;
+    publish(ctl, sn);
   }
   __syncthreads();
   const int c = chosen;
@@ -131,10 +143,10 @@ __global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
                                                  double* __restrict__ x, double* __restrict__ x_prev,
                                                  double* __restrict__ g, double* __restrict__ gt,
                                                  int32_t* __restrict__ ev_kind, int ev_cap,
-                                                 int next) {
+                                                 int next, CtlSnap sn) {
   if (ctl->status != RS_CTL_RUNNING) return;
   decide_body<K, 1024>(ctl, rpart, nrp, a, d, X, G, GT, x, x_prev, g, gt, ev_kind, ev_cap,
-                       next != 0);
+                       next != 0, sn);
 }
 
 // After the first gradient and apply: g <- G[0], gtilde <- GT[0], g_ref <- G[0],
@@ -149,7 +161,7 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
                                                      double* __restrict__ g,
                                                      double* __restrict__ gt,
                                                      double* __restrict__ gref, int at_cap,
-                                                     NextCand nc) {
+                                                     NextCand nc, CtlSnap sn) {
   __shared__ double sh[1024];
   __shared__ double rs1[1];
   __shared__ int run;
@@ -171,6 +183,7 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
     else if (1 >= max_iter) st = RS_CTL_MAXITER;
     ctl->status = st;
     run = nc.X != nullptr && st == RS_CTL_RUNNING;
+    publish(ctl, sn);
   }
   __syncthreads();
   const bool nx = run != 0;
@@ -192,7 +205,8 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
                                                         double* __restrict__ gt, int at_cap,
                                                         NextCand nc,
                                                         const double* __restrict__ x,
-                                                        const double* __restrict__ x_prev) {
+                                                        const double* __restrict__ x_prev,
+                                                        CtlSnap sn) {
   __shared__ double sh[2048];
   __shared__ double s2[2];
   __shared__ int run;
@@ -206,6 +220,7 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
     else if (ctl->r_t <= tol * ctl->r_ref) st = RS_CTL_CONVERGED;
     ctl->status = st;
     run = nc.X != nullptr && st == RS_CTL_RUNNING;
+    publish(ctl, sn);
   }
   __syncthreads();
   const bool nx = run != 0;
@@ -243,33 +258,34 @@ rs_status candidates_launch(int K, int64_t d, const double* x, const double* x_p
 rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const CtlParams& p,
                         int64_t d, double* X, const double* G, const double* GT, double* x,
                         double* x_prev, double* g, double* gt, int32_t* ev_kind, int ev_cap,
-                        hipStream_t s, bool next) {
+                        hipStream_t s, bool next, CtlSnap snap) {
   DecideArgs a{p.mu_p, p.beta_p, p.mu_gd, p.cbar_p, p.cbar_gd, p.tol, p.max_iter, K == 2 ? 1 : 0};
   const int nx = next ? 1 : 0;
   if (K == 2)
     hipLaunchKernelGGL(k_decide<2>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, a, d, X, G, GT, x,
-                       x_prev, g, gt, ev_kind, ev_cap, nx);
+                       x_prev, g, gt, ev_kind, ev_cap, nx, snap);
   else
     hipLaunchKernelGGL(k_decide<1>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, a, d, X, G, GT, x,
-                       x_prev, g, gt, ev_kind, ev_cap, nx);
+                       x_prev, g, gt, ev_kind, ev_cap, nx, snap);
   return check_launch("decide");
 }
 
 rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
                             int64_t max_iter, int64_t d, const double* G, const double* GT,
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
-                            int at_cap, hipStream_t s, NextCand nc) {
+                            int at_cap, hipStream_t s, NextCand nc, CtlSnap snap) {
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, max_iter, d, G,
-                     GT, x, x_prev, g, gt, gref, at_cap, nc);
+                     GT, x, x_prev, g, gt, gref, at_cap, nc, snap);
   return check_launch("init state");
 }
 
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
                                const double* GT, double* gt, int at_cap, hipStream_t s,
-                               NextCand nc, const double* x, const double* x_prev) {
+                               NextCand nc, const double* x, const double* x_prev,
+                               CtlSnap snap) {
   if (nc.X && (!x || !x_prev)) return set_error(RS_ERR_ARG, "post resample: candidates need x");
   hipLaunchKernelGGL(k_post_resample, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, d, GT, gt,
-                     at_cap, nc, x, x_prev);
+                     at_cap, nc, x, x_prev, snap);
   return check_launch("post resample");
 }
 

@@ -938,7 +938,7 @@ struct SolveJob {
       RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
       RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
       RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
-                           gt, S->ev.as<int32_t>(), ev_cap, stream, true));
+                           gt, S->ev.as<int32_t>(), ev_cap, stream, true, snap()));
     }
     return RS_OK;
   }
@@ -1024,25 +1024,21 @@ struct SolveJob {
     return RS_OK;
   }
 
-  // the control record and the factor flag share one allocation (the flag right
-  // after the record), so one copy brings both to pinned memory
-  static constexpr size_t kFlagOff = (sizeof(DevCtl) + 15) / 16 * 16;
-
-  // copy the control record and the factor flag to pinned memory, mark the point
+  // the control record and the factor's pivot flag reach pinned host memory from
+  // the kernels that change them (CtlSnap); the host waits for this event
   rs_status enqueue_read() {
-    RS_HIP(hipMemcpyAsync(S->host_pinned, dctl, kFlagOff + sizeof(int), hipMemcpyDeviceToHost,
-                          stream));
     RS_HIP(hipEventRecord(S->done_ev, stream));
     return RS_OK;
   }
+  CtlSnap snap() const { return CtlSnap{S->host_pinned, finfo}; }
 
   rs_status start() {
     std::memset(info, 0, sizeof(*info));
     RS_TRY(S->vecs.ensure((size_t)(4 + 3 * 2) * d * sizeof(double)));
     RS_TRY(S->rpart.ensure((size_t)nrp * 4 * sizeof(double)));
-    RS_TRY(S->ctl.ensure(kFlagOff + 16));
+    RS_TRY(S->ctl.ensure(kSnapFlagOff + 16));
     RS_TRY(S->ev.ensure((size_t)ev_cap * sizeof(int32_t)));
-    if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
+    if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocCoherent));
     if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
     x_prev = S->vecs.as<double>();
     g = x_prev + d;
@@ -1052,7 +1048,7 @@ struct SolveJob {
     G = X + 2 * d;
     GT = G + 2 * d;
     dctl = S->ctl.as<DevCtl>();
-    finfo = reinterpret_cast<int*>(S->ctl.as<char>() + kFlagOff);
+    finfo = reinterpret_cast<int*>(S->ctl.as<char>() + kSnapFlagOff);
     status = &dctl->status;
     RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
     // g_1 at x_0 needs no sketch: it runs on the side stream beside the sketch and
@@ -1067,7 +1063,8 @@ struct SolveJob {
     // gtilde_1, r_1
     RS_TRY(apply_launch(Hinv, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
     RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, o.tol, o.max_iter, d, G, GT, x,
-                             x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream, next_cand()));
+                             x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream, next_cand(),
+                             snap()));
     if (lp_params) {
       // a predicted starting m is usually large enough for the first steps to be
       // accepted: queue check_every of them now instead of reading the state first
@@ -1087,15 +1084,13 @@ struct SolveJob {
       return start();
     }
     phase = 0;
-    if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocDefault));
+    if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocCoherent));
     if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
     RS_TRY(S->pfeat.ensure(16 * sizeof(float)));
-    RS_TRY(S->py.ensure(sizeof(float)));
     RS_TRY(features_run(*S, A, a_t, n, d, lda, nu2, o.seed, S->pfeat.as<float>(), stream));
-    RS_TRY(mlp_forward(lp_params, S->pfeat.as<float>(), 1, lp_mu, lp_sd, S->py.as<float>(),
-                       nullptr, stream));
-    RS_HIP(hipMemcpyAsync((char*)S->host_pinned + 1024, S->py.p, sizeof(float),
-                          hipMemcpyDeviceToHost, stream));
+    // the prediction goes straight to pinned host memory
+    RS_TRY(mlp_forward(lp_params, S->pfeat.as<float>(), 1, lp_mu, lp_sd,
+                       reinterpret_cast<float*>((char*)S->host_pinned + 1024), nullptr, stream));
     RS_HIP(hipEventRecord(S->done_ev, stream));
     return RS_OK;
   }
@@ -1113,7 +1108,7 @@ struct SolveJob {
     }
     std::memcpy(&h, S->host_pinned, sizeof(DevCtl));
     int fbad = 0;
-    std::memcpy(&fbad, (char*)S->host_pinned + kFlagOff, sizeof(int));
+    std::memcpy(&fbad, (char*)S->host_pinned + kSnapFlagOff, sizeof(int));
     if (fbad) {
       result = set_error(RS_ERR_NOT_SPD, "rs_adaptive_solve: sketched Hessian factor failed");
       return conclude();
@@ -1144,7 +1139,7 @@ struct SolveJob {
       RS_TRY(pack2_launch(d, g, gref, X, stream));
       RS_TRY(apply_launch(Hinv, dp, d, X, 2, GT, S->rpart.as<double>(), nullptr, stream));
       RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, o.tol, d, GT, gt,
-                                  m == m_cap ? 1 : 0, stream, next_cand(), x, x_prev));
+                                  m == m_cap ? 1 : 0, stream, next_cand(), x, x_prev, snap()));
       applies += 1;
       queue = 1;
       return enqueue_read();

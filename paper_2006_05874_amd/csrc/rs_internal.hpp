@@ -155,6 +155,16 @@ struct DevCtl {
   int32_t at_cap;
 };
 
+// A copy of the control record (and the factor's pivot flag right after it, at
+// kSnapFlagOff) that the kernels changing the record write into host memory the
+// device can store to (pinned), so the host reads the state after the completion
+// event with no copy on the stream.  ctl null: not written.
+constexpr size_t kSnapFlagOff = (sizeof(DevCtl) + 15) / 16 * 16;
+struct CtlSnap {
+  void* host = nullptr;         // DevCtl at offset 0, int flag at kSnapFlagOff
+  const int* flag = nullptr;    // the factor's pivot flag on the device
+};
+
 struct CtlParams {
   double mu_p, beta_p, mu_gd, cbar_p, cbar_gd, tol;
   int64_t max_iter;
@@ -166,7 +176,7 @@ rs_status candidates_launch(int K, int64_t d, const double* x, const double* x_p
 rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const CtlParams& p,
                         int64_t d, double* X, const double* G, const double* GT, double* x,
                         double* x_prev, double* g, double* gt, int32_t* ev_kind, int ev_cap,
-                        hipStream_t s, bool next = false);
+                        hipStream_t s, bool next = false, CtlSnap snap = CtlSnap());
 // The next step's candidates, written by the kernel that leaves the state running
 // (X null: not written).
 struct NextCand {
@@ -177,11 +187,12 @@ struct NextCand {
 rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
                             int64_t max_iter, int64_t d, const double* G, const double* GT,
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
-                            int at_cap, hipStream_t s, NextCand nc = NextCand());
+                            int at_cap, hipStream_t s, NextCand nc = NextCand(),
+                            CtlSnap snap = CtlSnap());
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
                                const double* GT, double* gt, int at_cap, hipStream_t s,
                                NextCand nc = NextCand(), const double* x = nullptr,
-                               const double* x_prev = nullptr);
+                               const double* x_prev = nullptr, CtlSnap snap = CtlSnap());
 rs_status pack2_launch(int64_t d, const double* a, const double* b, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- nu grid
