@@ -7,6 +7,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <condition_variable>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -207,11 +209,53 @@ static DeviceScratch* scratch_for_current() {
   return all[dev];
 }
 
-// Worker streams (default priority) with private scratch for batched solves.
+// Worker streams (default priority) with private scratch for batched solves.  A
+// worker past the first also keeps a host thread of its own (started on first use,
+// current device set once), which runs the tasks a batch hands it; the pool is never
+// destroyed, so its threads wait for work until the process ends.
 struct BatchWorker {
   DeviceScratch S;
   hipStream_t s = nullptr;
   hipEvent_t join = nullptr;
+  std::thread th;
+  std::mutex m;
+  std::condition_variable cv;
+  std::function<void()> task;  // set by the batch, cleared by the thread when done
+  bool started = false;
+
+  // start the thread if needed; false if it cannot be started
+  bool ensure_thread(int dev) {
+    if (started) return true;
+    try {
+      th = std::thread([this, dev] {
+        (void)hipSetDevice(dev);
+        std::unique_lock<std::mutex> lk(m);
+        for (;;) {
+          cv.wait(lk, [this] { return (bool)task; });
+          std::function<void()> f = task;  // task stays set until f has run
+          lk.unlock();
+          f();
+          lk.lock();
+          task = nullptr;
+          cv.notify_all();
+        }
+      });
+    } catch (...) {
+      return false;
+    }
+    th.detach();
+    started = true;
+    return true;
+  }
+  void post(std::function<void()> f) {
+    std::lock_guard<std::mutex> g(m);
+    task = std::move(f);
+    cv.notify_all();
+  }
+  void wait_idle() {
+    std::unique_lock<std::mutex> lk(m);
+    cv.wait(lk, [this] { return !task; });
+  }
 };
 struct WorkerPool {
   std::mutex mu;
@@ -1232,7 +1276,8 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
   if (!pool->entry) RS_HIP(hipEventCreateWithFlags(&pool->entry, hipEventDisableTiming));
   RS_HIP(hipEventRecord(pool->entry, stream));
   for (int i = 0; i < W; ++i) RS_HIP(hipStreamWaitEvent(pool->w[i]->s, pool->entry, 0));
-  // Each worker runs on a host thread of its own (worker 0 on the caller's): it
+  // Each worker runs on a host thread of its own (worker 0 on the caller's, the
+  // others on their persistent threads): it
   // takes the next unstarted job, drives it to the end on its stream (queue work,
   // wait for the job's completion event, read the control record, queue more),
   // then takes the next.  One host thread per stream keeps every stream fed while
@@ -1248,12 +1293,8 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
       first_msg = rs_last_error();
     }
   };
-  auto run = [&](int wi, bool own_thread) {
+  auto run = [&](int wi) {
     BatchWorker& w = *pool->w[wi];
-    if (own_thread && hipSetDevice(dev) != hipSuccess) {
-      note(set_error(RS_ERR_HIP, "rs_solve_batch: hipSetDevice failed in a worker"));
-      return;
-    }
     for (;;) {
       const int64_t id = next.fetch_add(1);
       if (id >= count) return;
@@ -1277,16 +1318,15 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
       if (J.result != RS_OK && J.result != RS_ERR_NO_CONVERGENCE) note(J.result);
     }
   };
-  std::vector<std::thread> th;
+  std::vector<BatchWorker*> posted;
   for (int i = 1; i < W; ++i) {
-    try {
-      th.emplace_back(run, i, true);
-    } catch (...) {
-      break;  // the remaining jobs go to the workers that did start
-    }
+    BatchWorker* wp = pool->w[i].get();
+    if (!wp->ensure_thread(dev)) break;  // the remaining jobs go to the workers that run
+    wp->post([&run, i] { run(i); });
+    posted.push_back(wp);
   }
-  run(0, false);
-  for (std::thread& t : th) t.join();
+  run(0);
+  for (BatchWorker* wp : posted) wp->wait_idle();
   // the caller's stream waits for every worker
   for (int i = 0; i < W; ++i) {
     BatchWorker* wp = pool->w[i].get();
