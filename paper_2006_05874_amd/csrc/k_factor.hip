@@ -1031,6 +1031,18 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
   // staging of L_k,k-1 and the tile's own operand
   double tile2[4][4];
   zero_acc(tile2);
+  // this block's tiles of M (and of the inverse buffer), loaded now so that the
+  // loads overlap the products below
+  double mkk[4][4], m2[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t r = ty * 4 + i, c = tx * 4 + j;
+      mkk[i][j] = M[(ok + r) * ld + ok + c];
+      m2[i][j] = pan ? M[(ok + bid * NB + r) * ld + ok + c]
+                     : (xrow ? Linv[(ok + r) * ld + (bid - nrest - 1) * NB + c] : 0.0);
+    }
   if (k > 0) {
     const Opnd S{M + ok * ld + okm, ld, NB, NB, false};     // L_k,k-1
     const Opnd ST{M + ok * ld + okm, ld, NB, NB, true};     // L_k,k-1^T
@@ -1044,27 +1056,16 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ M, int64
       step_products(acc, tile2, S, S, false, true, false, tl);
     }
   }
-  if (pan) {
-    const int64_t oi = ok + bid * NB;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        tile2[i][j] = M[(oi + ty * 4 + i) * ld + ok + tx * 4 + j] - tile2[i][j];
-  } else if (xrow) {
-    const int64_t oj = (bid - nrest - 1) * NB;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        tile2[i][j] = Linv[(ok + ty * 4 + i) * ld + oj + tx * 4 + j] - tile2[i][j];
-  }
+    for (int j = 0; j < 4; ++j) tile2[i][j] = m2[i][j] - tile2[i][j];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = ty * 4 + i, c = tx * 4 + j;
-      a[r][c] = M[(ok + r) * ld + ok + c] - acc[i][j];
+      a[r][c] = mkk[i][j] - acc[i][j];
       x[r][c] = (r == c) ? 1.0 : 0.0;
     }
   __syncthreads();
