@@ -41,6 +41,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--workers", type=int, default=8,
+                    help="worker streams for the uneven batch (c4b)")
     ap.add_argument("--graph-steps", action="store_true",
                     help="batched solves replay each job's queued steps from HIP graphs")
     ap.add_argument("--warmup", type=int, default=2)
@@ -613,11 +615,12 @@ def run_c4b(args):
     params, mu, sd, _ = learned.load_model(args.model or learned.MODEL_PATH)
 
     def run_learned():
-        return rs.rs_learned_solve_batch(probs, params, mu, sd, sketch_dtype="bf16", workers=8,
-                                         graph_steps=args.graph_steps, raise_on_error=False)
+        return rs.rs_learned_solve_batch(probs, params, mu, sd, sketch_dtype="bf16",
+                                         workers=args.workers, graph_steps=args.graph_steps,
+                                         raise_on_error=False)
 
     def run_batch():
-        return rs.rs_solve_batch(probs, sketch_dtype="bf16", workers=8,
+        return rs.rs_solve_batch(probs, sketch_dtype="bf16", workers=args.workers,
                                  graph_steps=args.graph_steps, raise_on_error=False)
 
     def run_seq():
@@ -661,7 +664,7 @@ def run_c4b(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
             "config": {"workload": "256 problems, n=2^U{12..16}, d=U{128..1024}, "
-                                   "sigma_i=0.95^i, nu^2=1e-3, SRHT, 8 worker streams, "
+                                   f"sigma_i=0.95^i, nu^2=1e-3, SRHT, {args.workers} worker streams, "
                                    "learned start + BF16 sketches, one host thread per worker"
                                    + (", steps replayed from HIP graphs" if args.graph_steps
                                       else ""),
