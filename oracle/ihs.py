@@ -23,7 +23,13 @@ Readings where the paper is silent (each is listed in the design notes):
   - Stopping: the paper runs a fixed number of steps and measures precision
     against x*.  Here the run stops when r_t <= tol * r_ref, with
     r_ref = 1/2 g_1^T H_S^-1 g_1 re-evaluated under the current sketch, or after
-    max_iter accepted steps.
+    max_iter accepted steps.  With ref_at_zero the reference gradient is the one
+    at the origin, g(0) = -A^T b, whatever the starting point: a warm-started
+    solve then stops at the accuracy delta(x) / delta(0) a cold one would (a start
+    at the origin is its own reference, so nothing extra is evaluated).
+* Regularization path (Section 4, warm starts): nu^2 decreasing, each solve
+  starting from the previous solution and at the previous final sketch size,
+  with nested sketches so that one sketch family serves the whole path.
 """
 import math
 from dataclasses import dataclass, field
@@ -158,6 +164,7 @@ class Options:
     max_iter: int = 200
     seed: int = 0
     gauss_precision: str = "f64"
+    ref_at_zero: bool = False    # stop-test reference gradient at x = 0 (warm starts)
 
 
 @dataclass
@@ -203,11 +210,16 @@ def adaptive_solve(A, b, nu2, opts=None, x_init=None):
     x_prev = x.copy()
     P = SketchedHessian(make_sketch(A, opts.kind, opts.seed, sketch_id, m, opts.gauss_precision), nu2)
     g = grad(x)
-    g_ref = g.copy()
     gt, r = P.decrement(g)
     info.applies += 1
     r1 = r
-    r_ref = r
+    if opts.ref_at_zero and np.any(x != 0):
+        g_ref = grad(np.zeros(d))
+        _, r_ref = P.decrement(g_ref)
+        info.applies += 1
+    else:
+        g_ref = g.copy()
+        r_ref = r
     t = 1
     while True:
         info.r_history.append(r)
@@ -262,3 +274,26 @@ def adaptive_solve(A, b, nu2, opts=None, x_init=None):
     info.m_final = m
     info.t_final = t
     return x, info
+
+
+def solve_path(A, b, nu2s, opts=None):
+    """Regularization path: nu^2 in the given (non-increasing) order, each solve
+    warm-started at the previous solution, starting at the previous final m, with
+    nested sketches and the stop test referred to x = 0.  Returns (X, infos) with
+    X[j] the solution at nu2s[j]."""
+    opts = opts or Options()
+    A = np.asarray(A, dtype=np.float64)
+    d = A.shape[1]
+    X = np.zeros((len(nu2s), d))
+    infos = []
+    x = np.zeros(d)
+    m = opts.m_init
+    for j, nu2 in enumerate(nu2s):
+        if j and nu2 > nu2s[j - 1]:
+            raise ValueError("solve_path: nu^2 must not increase along the path")
+        o = Options(**{**opts.__dict__, "m_init": m, "resample": "nested", "ref_at_zero": True})
+        x, info = adaptive_solve(A, b, nu2, o, x_init=x)
+        X[j] = x
+        infos.append(info)
+        m = info.m_final
+    return X, infos

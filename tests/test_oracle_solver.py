@@ -271,3 +271,71 @@ def test_iteration_count_bound_after_last_doubling(c1):
     last_double = max([i for i, e in enumerate(info.events) if e[1] == "double"], default=-1)
     accepted_after = sum(1 for e in info.events[last_double + 1:] if e[1] in ("gd", "polyak"))
     assert accepted_after <= T
+
+
+# --- regularization path with warm starts (Section 4) ---------------------------
+
+PATH_NU2 = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]
+
+
+def test_path_reaches_direct_solution_at_every_nu(c1):
+    p, _, _ = c1
+    X, infos = ihs.solve_path(p.A, p.b, PATH_NU2, ihs.Options(tol=1e-8))
+    for j, nu2 in enumerate(PATH_NU2):
+        xs = ridge.solve_direct(p.A, p.b, nu2)
+        assert infos[j].status == "ok"
+        assert ridge.relative_error(ridge.hessian(p.A, nu2), X[j], xs) <= 1e-6
+
+
+def test_path_first_point_is_the_cold_nested_solve(c1):
+    # at x = 0 the origin reference is the start's own gradient: same arithmetic
+    p, _, _ = c1
+    X, infos = ihs.solve_path(p.A, p.b, PATH_NU2[:1], ihs.Options())
+    x, info = ihs.adaptive_solve(p.A, p.b, PATH_NU2[0], ihs.Options(resample="nested"))
+    assert np.array_equal(X[0], x)
+    assert infos[0].events == info.events
+    assert infos[0].grad_evals == info.grad_evals
+
+
+def test_path_sketch_size_never_shrinks_and_warm_starts_pay(c1):
+    p, _, _ = c1
+    X, infos = ihs.solve_path(p.A, p.b, PATH_NU2, ihs.Options())
+    ms = [inf.m_final for inf in infos]
+    assert ms == sorted(ms)
+    cold = sum(ihs.adaptive_solve(p.A, p.b, nu2, ihs.Options(resample="nested"))[1].grad_evals
+               for nu2 in PATH_NU2)
+    assert sum(inf.grad_evals for inf in infos) < cold
+
+
+def test_path_rejects_increasing_nu(c1):
+    p, _, _ = c1
+    with pytest.raises(ValueError):
+        ihs.solve_path(p.A, p.b, [1e-3, 1e-2], ihs.Options())
+
+
+def test_warm_start_at_solution_stops_with_origin_reference(c1):
+    # delta(x*) = 0 < tol * delta(0): the origin-referenced test stops at once; the
+    # start-referenced test compares the (rounding-level) decrement with itself
+    p, xs, _ = c1
+    x, info = ihs.adaptive_solve(p.A, p.b, p.nu2, ihs.Options(ref_at_zero=True), x_init=xs)
+    # g(x*) and the reference g(0), then the stop
+    assert info.grad_evals == 2 and info.events == [(1, "stop", 1)]
+    assert np.array_equal(x, xs)
+    _, info0 = ihs.adaptive_solve(p.A, p.b, p.nu2, ihs.Options(), x_init=xs)
+    assert info0.grad_evals > 1
+
+
+def test_origin_reference_is_the_cold_first_decrement(c1):
+    # r_ref from g(0) = -A^T b under the same sketch equals the cold run's r_1
+    p, xs, _ = c1
+    x0 = 0.5 * xs
+    _, warm = ihs.adaptive_solve(p.A, p.b, p.nu2, ihs.Options(ref_at_zero=True, tol=1e-3), x_init=x0)
+    _, cold = ihs.adaptive_solve(p.A, p.b, p.nu2, ihs.Options(tol=1e-3))
+    r_cold_1 = cold.r_history[0]
+    # the warm run stops once r_t <= tol * r_ref(0); r_ref(0) is the cold r_1 when
+    # both runs still hold the first sketch
+    if warm.doublings == 0:
+        assert warm.r_history[-1] <= 1e-3 * r_cold_1 * (1 + 1e-12)
+    # half-way start: delta(x0) = delta(0) / 4 exactly, so the warm r_1 is a
+    # quarter of the cold one under the same sketch
+    assert warm.r_history[0] == pytest.approx(r_cold_1 / 4, rel=1e-10)
