@@ -16,8 +16,8 @@ the timed steps in which every gradient launch carries HIP start/stop events
 timed region is checked afterwards against the oracle's direct solution
 (relative prediction error delta(x)/delta(0) <= 1e-6).
 
-Prints one JSON line (see the repository's design notes for the roofline and
-baseline definitions).
+Prints one JSON line: the throughput, the dominant kernel's roofline (live HIP
+events; traffic from the counter passes when given) and the oracle's CPU rate.
 """
 import argparse
 import hashlib
@@ -56,10 +56,14 @@ def parse():
     ap.add_argument("--model", default=None, help="learned-start model (.npz)")
     ap.add_argument("--skip-plain", action="store_true",
                     help="do not time the plain method beside the learned form")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4a", "c4b", "c5"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "c4a", "c4b", "c5", "path"],
                     help="c2: the 65536x1024 headline problem; c3: the 2^20x4096 precision "
                          "form; c4a: 64 nu^2 on one 2^18x2048 problem; c4b: 256 uneven "
-                         "problems, batched")
+                         "problems, batched; path: the warm-started regularization path "
+                         "nu = 10^0..10^-4 on one 65536x1024 problem")
+    ap.add_argument("--path-modes", default="path_warm_f32,path_warm_bf16,cold_f32",
+                    help="path workload: the modes to time (the first listed is the value)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a counter "
                          "reference for HBM traffic measurements)")
@@ -131,6 +135,8 @@ def main():
         return run_c4a(args)
     if args.workload == "c5":
         return run_c5(args)
+    if args.workload == "path":
+        return run_path(args)
     import torch
 
     from paper_2006_05874_amd import rs
@@ -586,6 +592,85 @@ def run_c4a(args):
             "modes": out,
             "speedup_vs_sequential_plain_f32": round(
                 out["grid_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
+    print(json.dumps(line))
+
+
+def run_path(args):
+    """The regularization path nu = 10^0 .. 10^-4 (decreasing) on one 65536 x 1024
+    FP32 problem (sigma_i = 1/i), each solve stopped at eps = 1e-10 measured from
+    the origin: the path solver (warm starts, sketch size carried over, nested
+    sketches with one transformed A) against the same five solves run cold (x = 0,
+    m from 1, fresh sketches).  Every solution is checked against the oracle."""
+    import torch
+    from oracle import ridge
+    from paper_2006_05874_amd import rs
+    from synth import config_path_nu2, make_path_problem
+    torch.cuda.set_device(0)
+    A0, b = make_path_problem("cuda")
+    n, d = A0.shape
+    A = rs.padded(n, d, dtype=torch.float32)
+    A.copy_(A0)
+    del A0
+    nus = list(config_path_nu2())
+    tol = 1e-10
+    torch.cuda.synchronize()
+    print("[path] problem ready", file=sys.stderr, flush=True)
+
+    def path(sd):
+        def fn():
+            X, infos = rs.rs_solve_path(A, b, nus, sketch_dtype=sd, tol=tol,
+                                        raise_on_error=False)
+            return [(X[k], infos[k]) for k in range(len(nus))]
+        return fn
+
+    def cold():
+        return [rs.rs_adaptive_solve(A, b, nu, sketch_dtype="f32", tol=tol,
+                                     raise_on_error=False) for nu in nus]
+
+    modes = {"path_warm_f32": path("f32"), "path_warm_bf16": path("bf16"), "cold_f32": cold}
+    names = args.path_modes.split(",")
+    out = {}
+    for name in names:
+        fn = modes[name]
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        out[name] = {"solves_per_s": round(len(nus) / sec, 2), "ms_per_path": round(sec * 1e3, 3),
+                     "res": res}
+        print(f"[path] {name}: {sec * 1e3:.2f} ms per path", file=sys.stderr, flush=True)
+    G, Atb = oracle_gram_chunks(A, b)
+    for name in out:
+        res = out[name].pop("res")
+        worst = 0.0
+        for k, nu2 in enumerate(nus):
+            xs = ridge.solve_direct_from_gram(G, Atb, nu2)
+            worst = max(worst, ridge.relative_error(G + nu2 * np.eye(d), res[k][0].cpu().numpy(),
+                                                    xs))
+        out[name]["worst_rel_pred_err"] = worst
+        out[name]["not_ok"] = sum(i["status"] != "ok" for _, i in res)
+        out[name]["m_final"] = [i["m_final"] for _, i in res]
+        out[name]["grad_passes"] = [i["grad_passes"] for _, i in res]
+        out[name]["doublings"] = [i["doublings"] for _, i in res]
+    best = names[0]
+    line = {"metric": "ridge solves/s along a regularization path (eps = 1e-10 rel. pred. error)",
+            "value": out[best]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": out[best]["ms_per_path"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 gradient / f32 sketch / f64 factor", "data": "synthetic",
+            "config": {"workload": f"{n}x{d} FP32, sigma_i=1/i, path nu^2 in "
+                                   f"{[float(v) for v in nus]} "
+                                   "(decreasing), warm starts, SRHT nested, eps=1e-10",
+                       "n": n, "d": d},
+            "verified": all(v["worst_rel_pred_err"] <= 1e-9 and v["not_ok"] == 0
+                            for v in out.values()),
+            "modes": out}
+    if "cold_f32" in out:
+        line["speedup_vs_cold_f32"] = round(out[best]["solves_per_s"]
+                                            / out["cold_f32"]["solves_per_s"], 3)
     print(json.dumps(line))
 
 

@@ -204,6 +204,13 @@ typedef struct {
  * the job's first use (batched solves only; the capture and instantiation are
  * paid once per solve, so this pays off when a solve takes many step rounds). */
 #define RS_SOLVE_GRAPH_STEPS 1
+/* rs_solve_opts.flags: take the stop test's reference from the origin,
+ * r_ref = 1/2 g(0)^T H_S^-1 g(0) with g(0) = -A^T b (re-evaluated under each new
+ * sketch), instead of from the starting point.  A warm-started solve then stops at
+ * the relative accuracy delta(x) / delta(0) <= tol a cold one reaches (Section 4,
+ * warm starts along a regularization path).  g(0) is one more column of the
+ * first gradient pass.  A start at the origin is unchanged by the flag. */
+#define RS_SOLVE_REF_AT_ZERO 2
 
 /* Event kinds recorded in rs_solve_info. */
 #define RS_EVENT_POLYAK 0
@@ -226,10 +233,10 @@ typedef struct {
 /* Fill opts with the defaults listed above. */
 void rs_solve_opts_default(rs_solve_opts* opts);
 
-/* Algorithm 1 end to end (Section 3 and the readings in the design notes):
- * start at m = m_init, double m and resample whenever both candidates fail their
- * tests, stop at r_t <= tol * r_ref with r_ref = 1/2 g_1^T H_S^-1 g_1 under the
- * current sketch.  The step control runs on the device; the host reads a small
+/* Algorithm 1 end to end (Section 3): start at m = m_init, double m and resample
+ * whenever both candidates fail their tests, stop at r_t <= tol * r_ref with
+ * r_ref = 1/2 g_1^T H_S^-1 g_1 under the current sketch (g(0) in place of g_1
+ * under RS_SOLVE_REF_AT_ZERO).  The step control runs on the device; the host reads a small
  * state record every check_every steps and performs the resamplings.
  *   A, b   : problem (F64 or F32); nu2 > 0.
  *   x      : device, d FP64: in = initial point x_1 (= x_0), out = solution.
@@ -282,6 +289,32 @@ rs_status rs_solve_nu_grid(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
                            const void* b, const double* nu2, int64_t count,
                            const rs_solve_opts* opts, double* X, rs_solve_info* infos,
                            hipStream_t stream);
+
+/* Regularization path (Section 4, warm starts): Algorithm 1 for count values
+ * nu2[k] (host array, each > 0, non-increasing) on one (A, b), one after another.
+ * Solve k starts at solution k - 1 and at its final sketch size (m_init of solve 0
+ * is opts->m_init), with nested resampling (a sketch of size m is the first m rows
+ * of one sketch family, so the transformed A of the SRHT, or the Gaussian rows
+ * already drawn, serve the whole path) and RS_SOLVE_REF_AT_ZERO set: every solve
+ * stops at the relative accuracy tol measured from the origin.  Solve k starts at
+ * the sketch solve k - 1 ended with; that sketch and its Gram do not depend on nu
+ * (Section 3), so only the shifted FP64 factor is formed again.  opts->resample is
+ * ignored (nested) and RS_SOLVE_GRAPH_STEPS has no effect.
+ *   X     : device, count x d FP64 row-major: in = row 0 holds the first start
+ *           (zeros for a cold path; rows 1.. are overwritten), out = row k the
+ *           solution at nu2[k].
+ *   infos : count host records, each filled as rs_adaptive_solve fills one.
+ * Result k equals rs_adaptive_solve at nu2[k] started at row k - 1 with
+ * m_init = infos[k - 1].m_final, nested resampling and RS_SOLVE_REF_AT_ZERO.
+ * Synchronizes.
+ * Returns RS_OK when every solve ended RS_OK or RS_ERR_NO_CONVERGENCE (then its
+ * row holds the last iterate and the path goes on from it), RS_ERR_ARG for an
+ * increasing nu2, else the first other error (rows past the failing solve are
+ * left as they were). */
+rs_status rs_solve_path(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                        const void* b, const double* nu2, int64_t count,
+                        const rs_solve_opts* opts, double* X, rs_solve_info* infos,
+                        hipStream_t stream);
 
 /* ------------------------------------------------------------------ learned start */
 

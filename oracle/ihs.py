@@ -12,7 +12,7 @@ Test infrastructure: see the package docstring.
 * Algorithm 1 ("Adaptive Polyak-IHS") and its gradient-only variant (Section
   4, numerical experiments).
 
-Readings where the paper is silent (each is listed in the design notes):
+Readings where the paper is silent:
   - x_0 = x_1 = the initial point.
   - After doubling m, g~_t is recomputed (as written) and so is r_t, which is
     defined as 1/2 g_t^T H_S^-1 g_t under the current sketch; r_1 and t keep

@@ -149,8 +149,11 @@ __global__ __launch_bounds__(1024) void k_decide(DevCtl* __restrict__ ctl,
                        next != 0, sn);
 }
 
-// After the first gradient and apply: g <- G[0], gtilde <- GT[0], g_ref <- G[0],
-// x_prev <- x, r_t = r_1 = r_ref = r.
+// After the first gradient and apply: g <- G[0], gtilde <- GT[0], x_prev <- x,
+// r_t = r_1 = r.  With C = 1 the start is its own reference (g_ref <- G[0],
+// r_ref = r_1); with C = 2 column 1 holds the gradient at the origin and its
+// decrement (g_ref <- G[1], r_ref from the second sum).
+template <int C>
 __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
                                                      const double* __restrict__ rpart, int nrp,
                                                      double tol, int64_t max_iter, int64_t d,
@@ -162,15 +165,16 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
                                                      double* __restrict__ gt,
                                                      double* __restrict__ gref, int at_cap,
                                                      NextCand nc, CtlSnap sn) {
-  __shared__ double sh[1024];
-  __shared__ double rs1[1];
+  __shared__ double sh[C * 1024];
+  __shared__ double rs1[C];
   __shared__ int run;
-  block_sum_cols<1, 1024>(rpart, nrp, sh, rs1);
+  block_sum_cols<C, 1024>(rpart, nrp, sh, rs1);
   if (threadIdx.x == 0) {
     const double r = 0.5 * rs1[0];
+    const double rr = 0.5 * rs1[C - 1];
     ctl->r_t = r;
     ctl->r_1 = r;
-    ctl->r_ref = r;
+    ctl->r_ref = rr;
     ctl->t = 1;
     ctl->steps = 0;
     ctl->passes = 1;
@@ -178,8 +182,8 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
     ctl->gd = 0;
     ctl->at_cap = at_cap;
     int st = RS_CTL_RUNNING;
-    if (!isfinite(r)) st = RS_CTL_NONFINITE;
-    else if (r <= tol * r) st = RS_CTL_CONVERGED;
+    if (!isfinite(r) || !isfinite(rr)) st = RS_CTL_NONFINITE;
+    else if (r <= tol * rr) st = RS_CTL_CONVERGED;
     else if (1 >= max_iter) st = RS_CTL_MAXITER;
     ctl->status = st;
     run = nc.X != nullptr && st == RS_CTL_RUNNING;
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
     const double xi = x[i], gti = GT[i];
     x_prev[i] = xi;
     g[i] = G[i];
-    gref[i] = G[i];
+    gref[i] = G[(C - 1) * d + i];
     gt[i] = gti;
     if (nx) candidate_at(nc.K, d, i, xi, xi, gti, nc.X, nc.mu_p, nc.beta_p, nc.mu_gd);
   }
@@ -273,9 +277,13 @@ rs_status decide_launch(int K, DevCtl* ctl, const double* rpart, int nrp, const 
 rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double tol,
                             int64_t max_iter, int64_t d, const double* G, const double* GT,
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
-                            int at_cap, hipStream_t s, NextCand nc, CtlSnap snap) {
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, max_iter, d, G,
-                     GT, x, x_prev, g, gt, gref, at_cap, nc, snap);
+                            int at_cap, hipStream_t s, NextCand nc, CtlSnap snap, int cols) {
+  if (cols == 2)
+    hipLaunchKernelGGL(k_init_state<2>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, max_iter,
+                       d, G, GT, x, x_prev, g, gt, gref, at_cap, nc, snap);
+  else
+    hipLaunchKernelGGL(k_init_state<1>, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, tol, max_iter,
+                       d, G, GT, x, x_prev, g, gt, gref, at_cap, nc, snap);
   return check_launch("init state");
 }
 

@@ -157,7 +157,6 @@ __global__ __launch_bounds__(256) void k_probe_quad(const double* __restrict__ V
                                                     const double* __restrict__ U, int64_t d,
                                                     double nu2, double* __restrict__ r) {
   __shared__ double sh[2 * 256];
-  __shared__ double out[2];
   const int k = blockIdx.x, t = threadIdx.x;
   const double* v = V + (int64_t)k * m;
   double yy = 0.0;

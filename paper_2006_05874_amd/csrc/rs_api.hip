@@ -395,6 +395,9 @@ static rs_status gauss_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_
 struct NestedCache {
   bool hda_ready = false;
   int64_t graw_rows = 0;
+  // a path's solves share the scratch: the sketch of size gram_m and its split
+  // Gram partials are still in it (0: none)
+  int64_t gram_m = 0;
 };
 
 static rs_status nested_sketch(DeviceScratch& S, NestedCache& C, bool srht, const void* A,
@@ -965,6 +968,7 @@ struct SolveJob {
   bool use_graph = false;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   NestedCache ncache;
+  NestedCache* nc_shared = nullptr;  // a path's cache, kept across its solves
 
   SolveJob() = default;
   SolveJob(const SolveJob&) = delete;
@@ -1045,12 +1049,18 @@ struct SolveJob {
   }
 
   rs_status sketch_and_factor(int64_t mm, uint32_t id) {
+    // along a path a solve starts at the sketch its predecessor ended with: that
+    // sketch and its Gram do not depend on nu, only the shifted factor is new
+    const bool reuse = nc_shared && nc_shared->gram_m == mm;
+    if (nc_shared) nc_shared->gram_m = 0;
     RS_TRY(S->sa.ensure((size_t)mm * ldsa * sa_es));
     RS_TRY(S->sa_scale.ensure((size_t)d * sizeof(float)));
     float* scl = sa_t == RS_FP8E4M3 ? S->sa_scale.as<float>() : nullptr;
-    if (o.resample == RS_RESAMPLE_NESTED)
-      RS_TRY(nested_sketch(*S, ncache, srht, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t,
-                           ldsa, scl, stream));
+    if (reuse)
+      ;  // SA (and its FP8 column scales) already hold this sketch
+    else if (o.resample == RS_RESAMPLE_NESTED)
+      RS_TRY(nested_sketch(*S, nc_shared ? *nc_shared : ncache, srht, A, a_t, n, d, lda, mm,
+                           o.seed, id, S->sa.p, sa_t, ldsa, scl, stream));
     else if (srht)
       RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, nullptr,
                       nullptr, stream));
@@ -1063,7 +1073,11 @@ struct SolveJob {
     RS_TRY(S->fGram.ensure(factor_bytes_gram(mm, d, sa_t)));
     FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
                      S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes, S->fCw.bytes};
-    RS_TRY(factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream));
+    if (reuse)
+      RS_TRY(factor_finish(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, 1, FactorBatch{}, stream));
+    else
+      RS_TRY(factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream));
+    if (nc_shared) nc_shared->gram_m = mm;
     Hinv = S->fHinv.as<double>();
     return RS_OK;
   }
@@ -1097,18 +1111,27 @@ struct SolveJob {
     RS_HIP(hipMemsetAsync(finfo, 0, sizeof(int), stream));
     // g_1 at x_0 needs no sketch: it runs on the side stream beside the sketch and
     // the factor (its scratch is not theirs)
+    // (with the origin as the stop test's reference, the gradient at 0 rides in
+    // the same pass as a second column: [x_1, 0] -> [g_1, g(0)])
+    const int cols = (o.flags & RS_SOLVE_REF_AT_ZERO) ? 2 : 1;
     RS_TRY(S->ensure_aux());
     RS_HIP(hipEventRecord(S->fork_ev, stream));
     RS_HIP(hipStreamWaitEvent(S->aux, S->fork_ev, 0));
-    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, S->aux));
+    const double* gin = x;
+    if (cols == 2) {
+      RS_HIP(hipMemcpyAsync(X, x, (size_t)d * sizeof(double), hipMemcpyDeviceToDevice, S->aux));
+      RS_HIP(hipMemsetAsync(X + d, 0, (size_t)d * sizeof(double), S->aux));
+      gin = X;
+    }
+    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, gin, cols, G, nullptr, S->aux));
     RS_HIP(hipEventRecord(S->join_ev, S->aux));
     RS_TRY(sketch_and_factor(m, sid));
     RS_HIP(hipStreamWaitEvent(stream, S->join_ev, 0));
-    // gtilde_1, r_1
-    RS_TRY(apply_launch(Hinv, dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
+    // gtilde_1, r_1 (and r_ref from g(0))
+    RS_TRY(apply_launch(Hinv, dp, d, G, cols, GT, S->rpart.as<double>(), nullptr, stream));
     RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, o.tol, o.max_iter, d, G, GT, x,
                              x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream, next_cand(),
-                             snap()));
+                             snap(), cols));
     if (lp_params) {
       // a predicted starting m is usually large enough for the first steps to be
       // accepted: queue check_every of them now instead of reading the state first
@@ -1236,6 +1259,53 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
     if (st != RS_OK && !J.done) return st;
   }
   return J.result;
+}
+
+rs_status rs_solve_path(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                        const void* b, const double* nu2, int64_t count,
+                        const rs_solve_opts* opts, double* X, rs_solve_info* infos,
+                        hipStream_t stream) {
+  if (!opts || !nu2 || !X || !infos) return set_error(RS_ERR_ARG, "rs_solve_path: null argument");
+  if (count < 0) return set_error(RS_ERR_ARG, "rs_solve_path: count < 0");
+  if (count == 0) return RS_OK;
+  for (int64_t j = 0; j < count; ++j) {
+    if (!(nu2[j] > 0.0) || !std::isfinite(nu2[j]))
+      return set_error(RS_ERR_NOT_SPD, "rs_solve_path: nu^2 must be positive");
+    if (j && nu2[j] > nu2[j - 1])
+      return set_error(RS_ERR_ARG, "rs_solve_path: nu^2 must not increase along the path");
+  }
+  rs_solve_opts o = *opts;
+  o.resample = RS_RESAMPLE_NESTED;
+  o.flags = (o.flags | RS_SOLVE_REF_AT_ZERO) & ~RS_SOLVE_GRAPH_STEPS;
+  {  // argument errors before any work
+    SolveJob J0;
+    J0.A = A; J0.a_t = a_t; J0.n = n; J0.d = d; J0.lda = lda; J0.b = b; J0.nu2 = nu2[0];
+    J0.x = X; J0.o = o; J0.info = infos;
+    RS_TRY(J0.validate());
+  }
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  NestedCache cache;  // one nested sketch family (and its transformed A) for the path
+  for (int64_t j = 0; j < count; ++j) {
+    double* xj = X + j * d;
+    if (j)
+      RS_HIP(hipMemcpyAsync(xj, xj - d, (size_t)d * sizeof(double), hipMemcpyDeviceToDevice,
+                            stream));
+    SolveJob J;
+    J.A = A; J.a_t = a_t; J.n = n; J.d = d; J.lda = lda; J.b = b; J.nu2 = nu2[j]; J.x = xj;
+    J.o = o; J.info = &infos[j]; J.stream = stream; J.nc_shared = &cache;
+    RS_TRY(J.validate());
+    J.S = S;
+    RS_TRY(J.begin());
+    while (!J.done) {
+      RS_HIP(hipEventSynchronize(S->done_ev));
+      const rs_status st = J.advance();
+      if (st != RS_OK && !J.done) return st;
+    }
+    if (J.result != RS_OK && J.result != RS_ERR_NO_CONVERGENCE) return J.result;
+    o.m_init = infos[j].m_final;
+  }
+  return RS_OK;
 }
 
 }  // extern "C"

@@ -188,7 +188,7 @@ rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double to
                             int64_t max_iter, int64_t d, const double* G, const double* GT,
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
                             int at_cap, hipStream_t s, NextCand nc = NextCand(),
-                            CtlSnap snap = CtlSnap());
+                            CtlSnap snap = CtlSnap(), int cols = 1);
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
                                const double* GT, double* gt, int at_cap, hipStream_t s,
                                NextCand nc = NextCand(), const double* x = nullptr,

@@ -60,6 +60,7 @@ class SolveOpts(ctypes.Structure):
 
 
 RS_SOLVE_GRAPH_STEPS = 1
+RS_SOLVE_REF_AT_ZERO = 2
 
 
 class SolveInfo(ctypes.Structure):
@@ -82,7 +83,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-           "rs_gradient_plan"]
+           "rs_gradient_plan", "rs_solve_path"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -137,6 +138,8 @@ def load(path=LIB_PATH):
                                  ctypes.POINTER(SolveInfo), ctypes.c_int32, vp]
     L.rs_solve_nu_grid.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
                                    ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
+    L.rs_solve_path.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
+                                ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
     L.rs_learned_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
                                          vp, vp, vp, ctypes.POINTER(SolveInfo),
                                          ctypes.POINTER(i64), ctypes.c_int32, vp]
@@ -149,7 +152,7 @@ def load(path=LIB_PATH):
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-                 "rs_gradient_plan"]:
+                 "rs_gradient_plan", "rs_solve_path"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -329,12 +332,15 @@ def _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, t
 
 def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh",
                       sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
-                      max_iter=200, seed=0, check_every=4, x0=None, raise_on_error=True):
-    """Algorithm 1 end to end.  Returns (x float64 tensor, info dict)."""
+                      max_iter=200, seed=0, check_every=4, x0=None, raise_on_error=True,
+                      ref_at_zero=False):
+    """Algorithm 1 end to end.  Returns (x float64 tensor, info dict).  ref_at_zero
+    takes the stop test's reference decrement at the origin."""
     a_t = _mat(A, "rs_adaptive_solve")
     n, d = A.shape
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
+    o.flags = RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
     x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
          else x0.to(torch.float64).contiguous().clone())
     info = SolveInfo()
@@ -429,6 +435,29 @@ def rs_solve_nu_grid(A, b, nu2s, kind="srht", variant="polyak", resample="fresh"
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
         _check(st, "rs_solve_nu_grid")
     return X, [_info(infos[i], infos[i].status, False, "rs_solve_nu_grid") for i in range(k)]
+
+
+def rs_solve_path(A, b, nu2s, kind="srht", variant="polyak", sketch_dtype=None, rho=0.1,
+                  eta=0.01, m_init=1, m_max=0, tol=1e-7, max_iter=200, seed=0, check_every=4,
+                  x0=None, raise_on_error=True):
+    """Regularization path over the non-increasing ``nu2s`` with warm starts and
+    nested sketches.  Returns (X, infos) with X a (len(nu2s), d) float64 tensor of
+    solutions; x0 is the first start (zeros when None)."""
+    a_t = _mat(A, "rs_solve_path")
+    n, d = A.shape
+    k = len(nu2s)
+    o = _opts(a_t, kind, variant, "nested", sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
+              seed, check_every)
+    X = torch.zeros(max(k, 1), d, dtype=torch.float64, device=A.device)
+    if x0 is not None:
+        X[0] = x0.to(torch.float64)
+    nu = (ctypes.c_double * max(k, 1))(*[float(v) for v in nu2s])
+    infos = (SolveInfo * max(k, 1))()
+    st = load().rs_solve_path(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu, k,
+                              ctypes.byref(o), _ptr(X), infos, _stream())
+    if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
+        _check(st, "rs_solve_path")
+    return X[:k], [_info(infos[i], infos[i].status, False, "rs_solve_path") for i in range(k)]
 
 
 def _info(info, st, raise_on_error, where):

@@ -127,3 +127,17 @@ def config_c4a_nu2(count=64):
 def make_c4a_problem(device, dtype=None, n=C4A_N, d=C4A_D, seed=41):
     """Shared A for the nu grid: sigma_i = i^-0.8 (sigma_1 = 1), noise 0.1."""
     return make_problem_torch(n, d, spectrum("poly", d, 0.8), 0.1, seed, device, dtype=dtype)[:2]
+
+
+PATH_N, PATH_D = 1 << 16, 1024
+
+
+def config_path_nu2():
+    """Regularization path of the synthetic experiments: nu = 10^0 .. 10^-4 in
+    decreasing order, as nu^2 = 1, 1e-2, 1e-4, 1e-6, 1e-8."""
+    return np.array([10.0 ** (-2 * j) for j in range(5)])
+
+
+def make_path_problem(device, dtype=None, n=PATH_N, d=PATH_D, seed=17):
+    """A for the path: 65536 x 1024, sigma_i = 1/i (sigma_1 = 1), noise 0.1."""
+    return make_problem_torch(n, d, spectrum("poly", d, 1.0), 0.1, seed, device, dtype=dtype)[:2]
