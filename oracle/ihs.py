@@ -27,6 +27,8 @@ Readings where the paper is silent:
     at the origin, g(0) = -A^T b, whatever the starting point: a warm-started
     solve then stops at the accuracy delta(x) / delta(0) a cold one would (a start
     at the origin is its own reference, so nothing extra is evaluated).
+* Underdetermined case (appendix, the dual problem): Algorithm 1 unchanged on the
+  data matrix A^T with gradient A A^T z - b + nu^2 z; the primal solution is A^T z.
 * Regularization path (Section 4, warm starts): nu^2 decreasing, each solve
   starting from the previous solution and at the previous final sketch size,
   with nested sketches so that one sketch family serves the whole path.
@@ -190,9 +192,26 @@ def adaptive_solve(A, b, nu2, opts=None, x_init=None):
     (r_p / r_1)^(1/t) <= cbar_p, else a gradient candidate with the test
     r_gd / r_t <= cbar_gd, else double m, resample, recompute g~_t and retry.
     """
-    opts = opts or Options()
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
+    return _algorithm1(A, lambda x: ridge.gradient(A, b, nu2, x), nu2, opts, x_init)
+
+
+def adaptive_solve_dual(A, b, nu2, opts=None, z_init=None):
+    """The underdetermined case (appendix, dual problem): Algorithm 1 on
+    min_z 1/2 |A^T z - b^|^2 + nu^2/2 |z|^2, whose data matrix is A^T (d x n, the
+    sketch acts on its d rows) and whose gradient A A^T z - b + nu^2 z needs no
+    b^ = A^+ b.  Returns (x, z, info) with x = A^T z the primal solution."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    z, info = _algorithm1(A.T, lambda z: ridge.dual_gradient(A, b, nu2, z), nu2, opts, z_init)
+    return A.T @ z, z, info
+
+
+def _algorithm1(A, gradient, nu2, opts, x_init):
+    """Algorithm 1 for the ridge problem with data matrix A (n x d, sketched along
+    its n rows) and gradient function `gradient`."""
+    opts = opts or Options()
     n, d = A.shape
     prm = params_for(opts.kind, opts.rho, opts.eta)
     m_cap = sketch.next_pow2(n) if opts.kind == "srht" else n
@@ -203,7 +222,7 @@ def adaptive_solve(A, b, nu2, opts=None, x_init=None):
 
     def grad(x):
         info.grad_evals += 1
-        return ridge.gradient(A, b, nu2, x)
+        return gradient(x)
 
     info = Info()
     x = np.zeros(d) if x_init is None else np.asarray(x_init, dtype=np.float64).copy()

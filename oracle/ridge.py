@@ -21,6 +21,21 @@ def gradient(A, b, nu2, x):
     return A.T @ (A @ x - np.asarray(b, dtype=np.float64)) + nu2 * x
 
 
+def dual_gradient(A, b, nu2, z):
+    """grad g(z) = A A^T z - b + nu^2 z: the gradient of the dual problem of the
+    underdetermined case (appendix), min_z 1/2 |A^T z|^2 + nu^2/2 |z|^2 - b^T z."""
+    A = np.asarray(A, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    return A @ (A.T @ z) - np.asarray(b, dtype=np.float64) + nu2 * z
+
+
+def solve_dual_direct(A, b, nu2):
+    """z* = (A A^T + nu^2 I)^-1 b by Cholesky: the dual optimum (appendix)."""
+    A = np.asarray(A, dtype=np.float64)
+    L = np.linalg.cholesky(A @ A.T + nu2 * np.eye(A.shape[0]))
+    return np.linalg.solve(L.T, np.linalg.solve(L, np.asarray(b, dtype=np.float64)))
+
+
 def hessian(A, nu2):
     """H = Abar^T Abar = A^T A + nu^2 I."""
     A = np.asarray(A, dtype=np.float64)
