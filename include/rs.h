@@ -290,6 +290,24 @@ rs_status rs_solve_nu_grid(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
                            const rs_solve_opts* opts, double* X, rs_solve_info* infos,
                            hipStream_t stream);
 
+/* The underdetermined case n <= d (appendix, the dual problem): Algorithm 1 on
+ * min_z 1/2 |A^T z - b^|^2 + nu^2/2 |z|^2 with b^ = A^+ b, whose data matrix is A^T
+ * (the sketch acts on its d rows, m <= padded d) and whose gradient is
+ * A A^T z - b + nu^2 z (b^ is never formed); the primal solution is x = A^T z.
+ * The library forms A^T once (d x n, row-major, in its own scratch: d * n elements
+ * of A's type), then runs the solver of rs_adaptive_solve on it; every option of
+ * rs_adaptive_solve applies (RS_SOLVE_GRAPH_STEPS has no effect), and info
+ * describes the dual run (its r values are dual decrements).
+ *   A, b   : problem (F64 or F32), A n x d with n <= d; nu2 > 0.
+ *   z      : device, n FP64: in = initial dual point (zeros for a cold start),
+ *            out = dual solution.
+ *   x      : device, d FP64, out = A^T z (also after RS_ERR_NO_CONVERGENCE).
+ * Synchronizes.  Returns RS_OK, RS_ERR_NO_CONVERGENCE, RS_ERR_SHAPE when n > d, or
+ * another error. */
+rs_status rs_adaptive_solve_dual(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                                 const void* b, double nu2, const rs_solve_opts* opts, double* z,
+                                 double* x, rs_solve_info* info, hipStream_t stream);
+
 /* Regularization path (Section 4, warm starts): Algorithm 1 for count values
  * nu2[k] (host array, each > 0, non-increasing) on one (A, b), one after another.
  * Solve k starts at solution k - 1 and at its final sketch size (m_init of solve 0

@@ -209,13 +209,15 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
   }
 }
 
-// G[k][j] = sum over blocks of partial[b][k][j] (fixed order) + nu2 X[k][j].
+// G[k][j] = sum over blocks of partial[b][k][j] (fixed order) + nu2 X[k][j] - sub[j]
+// (sub null: 0; the dual problem's gradient carries -b there).
 // Block: 8 columns x 32 block-strides; LDS tree over the 32 strides.
 __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ partial, int nblk,
                                                      int64_t kd, double nu2,
                                                      const double* __restrict__ X,
                                                      double* __restrict__ G,
-                                                     const int* __restrict__ status) {
+                                                     const int* __restrict__ status,
+                                                     const double* __restrict__ sub, int64_t d) {
   if (status && *status != 0) return;
   __shared__ double s[32][8];
   const int cl = threadIdx.x & 7;
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ 
     double u = 0.0;
     for (int r = 0; r < 32; ++r) u += s[r][threadIdx.x];
     const int64_t cc = (int64_t)blockIdx.x * 8 + threadIdx.x;
-    if (cc < kd) G[cc] = u + nu2 * X[cc];
+    if (cc < kd) G[cc] = sub ? u + nu2 * X[cc] - sub[cc % d] : u + nu2 * X[cc];
   }
 }
 
@@ -352,7 +354,7 @@ static bool launch_plan(const GradPlan& pl, const T* A, int64_t n, int64_t d, in
 template <typename T>
 rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
                           const double* X, int k, double* G, double* partial, int grid_cap,
-                          const int* status, hipStream_t s) {
+                          const int* status, hipStream_t s, const double* c) {
   if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "gradient: k must be in 1..4");
   GradPlan pl = grad_plan<T>(n, d, k);
   if (pl.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
@@ -361,7 +363,7 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
     return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
   const int64_t kd = (int64_t)k * d;
   hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
-                     pl.grid, kd, nu2, X, G, status);
+                     pl.grid, kd, nu2, X, G, status, c, d);
   return check_launch("gradient");
 }
 
@@ -397,7 +399,7 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
     auto once = [&]() {
       launch_plan<T>(c, A, n, d, lda, b, X, k, partial, nullptr, s);
       hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
-                         c.grid, kd, 0.0, X, G, (const int*)nullptr);
+                         c.grid, kd, 0.0, X, G, (const int*)nullptr, (const double*)nullptr, d);
     };
     once();
     float ms = 1e30f;
@@ -434,9 +436,9 @@ template rs_status gradient_autotune<double>(const double*, int64_t, int64_t, in
                                              int, hipStream_t, GradPlan*);
 template rs_status gradient_launch<float>(const float*, int64_t, int64_t, int64_t, const float*,
                                           double, const double*, int, double*, double*, int,
-                                          const int*, hipStream_t);
+                                          const int*, hipStream_t, const double*);
 template rs_status gradient_launch<double>(const double*, int64_t, int64_t, int64_t, const double*,
                                            double, const double*, int, double*, double*, int,
-                                           const int*, hipStream_t);
+                                           const int*, hipStream_t, const double*);
 
 }  // namespace rs

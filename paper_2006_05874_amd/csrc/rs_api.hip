@@ -167,6 +167,8 @@ struct DeviceScratch {
   DevBuf hda, graw;
   // split partial products of the Gaussian sketch
   DevBuf gpart;
+  // dual problem: the data matrix A^T, a zero right-hand side, b in FP64
+  DevBuf dM, dzero, dc;
   // learned form: probe sketch and its factor, probe sums, features
   DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
   // nu grid: per-slot state, candidate blocks, multi-RHS products, batched
@@ -659,16 +661,16 @@ rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
 
 static rs_status grad_any(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                           int64_t lda, const void* b, double nu2, const double* X, int k, double* G,
-                          const int* status, hipStream_t s) {
+                          const int* status, hipStream_t s, const double* c = nullptr) {
   const int grid = grad_partial_blocks_max(n);
   RS_TRY(S.partial.ensure((size_t)grid * 4 * d * sizeof(double)));
   if (a_t == RS_F32)
     return gradient_launch<float>(reinterpret_cast<const float*>(A), n, d, lda,
                                   reinterpret_cast<const float*>(b), nu2, X, k, G,
-                                  S.partial.as<double>(), grid, status, s);
+                                  S.partial.as<double>(), grid, status, s, c);
   return gradient_launch<double>(reinterpret_cast<const double*>(A), n, d, lda,
                                  reinterpret_cast<const double*>(b), nu2, X, k, G,
-                                 S.partial.as<double>(), grid, status, s);
+                                 S.partial.as<double>(), grid, status, s, c);
 }
 
 rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
@@ -969,6 +971,9 @@ struct SolveJob {
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   NestedCache ncache;
   NestedCache* nc_shared = nullptr;  // a path's cache, kept across its solves
+  // the dual problem: A holds the data matrix A^T of the dual, b a zero vector,
+  // and the gradient subtracts cvec (the primal b, FP64)
+  const double* cvec = nullptr;
 
   SolveJob() = default;
   SolveJob(const SolveJob&) = delete;
@@ -983,7 +988,7 @@ struct SolveJob {
   // which also writes the next step's candidates
   rs_status enqueue_steps(int q) {
     for (int it = 0; it < q; ++it) {
-      RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
+      RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream, cvec));
       RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
       RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
                            gt, S->ev.as<int32_t>(), ev_cap, stream, true, snap()));
@@ -1123,7 +1128,7 @@ struct SolveJob {
       RS_HIP(hipMemsetAsync(X + d, 0, (size_t)d * sizeof(double), S->aux));
       gin = X;
     }
-    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, gin, cols, G, nullptr, S->aux));
+    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, gin, cols, G, nullptr, S->aux, cvec));
     RS_HIP(hipEventRecord(S->join_ev, S->aux));
     RS_TRY(sketch_and_factor(m, sid));
     RS_HIP(hipStreamWaitEvent(stream, S->join_ev, 0));
@@ -1257,6 +1262,47 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
     RS_HIP(hipEventSynchronize(S->done_ev));
     const rs_status st = J.advance();
     if (st != RS_OK && !J.done) return st;
+  }
+  return J.result;
+}
+
+rs_status rs_adaptive_solve_dual(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                                 const void* b, double nu2, const rs_solve_opts* opts, double* z,
+                                 double* x, rs_solve_info* info, hipStream_t stream) {
+  if (!opts || !z || !x || !info || !b)
+    return set_error(RS_ERR_ARG, "rs_adaptive_solve_dual: null argument");
+  RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve_dual"));
+  if (n > d) return set_error(RS_ERR_SHAPE, "rs_adaptive_solve_dual: needs n <= d");
+  const int64_t es = (int64_t)dtype_size(a_t);
+  const int64_t ldm = (n * es + 15) / 16 * 16 / es;  // rows of A^T: 16-byte multiples
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  SolveJob J;
+  J.a_t = a_t; J.n = d; J.d = n; J.lda = ldm; J.nu2 = nu2; J.x = z;
+  J.o = *opts; J.o.flags &= ~RS_SOLVE_GRAPH_STEPS; J.info = info; J.stream = stream;
+  // argument checks of the dual job (shape, nu, options) before any allocation
+  J.A = A; J.b = b;
+  RS_TRY(J.validate());
+  RS_TRY(S->dM.ensure((size_t)d * ldm * es));
+  RS_TRY(S->dzero.ensure((size_t)d * es));
+  RS_TRY(S->dc.ensure((size_t)n * sizeof(double)));
+  RS_TRY(dual_transpose(A, a_t, n, d, lda, S->dM.p, ldm, stream));
+  RS_HIP(hipMemsetAsync(S->dzero.p, 0, (size_t)d * es, stream));
+  RS_TRY(dual_widen(b, a_t, n, S->dc.as<double>(), stream));
+  J.A = S->dM.p;
+  J.b = S->dzero.p;
+  J.cvec = S->dc.as<double>();
+  J.S = S;
+  RS_TRY(J.begin());
+  while (!J.done) {
+    RS_HIP(hipEventSynchronize(S->done_ev));
+    const rs_status st = J.advance();
+    if (st != RS_OK && !J.done) return st;
+  }
+  // x = A^T z, also for a solve that ended without convergence (last iterate)
+  if (J.result == RS_OK || J.result == RS_ERR_NO_CONVERGENCE) {
+    RS_TRY(dual_rowdot(S->dM.p, a_t, d, n, ldm, z, x, stream));
+    RS_HIP(hipStreamSynchronize(stream));
   }
   return J.result;
 }

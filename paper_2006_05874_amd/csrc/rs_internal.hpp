@@ -128,7 +128,15 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
 template <typename T>
 rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
                           const double* X, int k, double* G, double* partial, int grid,
-                          const int* status, hipStream_t s);
+                          const int* status, hipStream_t s, const double* c = nullptr);
+
+// ---------------------------------------------------------------- dual (n < d)
+// M = A^T (d x ldm, padding columns zeroed); c = b in FP64; x = M z.
+rs_status dual_transpose(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, void* M,
+                         int64_t ldm, hipStream_t s);
+rs_status dual_widen(const void* b, rs_dtype a_t, int64_t n, double* c, hipStream_t s);
+rs_status dual_rowdot(const void* M, rs_dtype a_t, int64_t rows, int64_t cols, int64_t ldm,
+                      const double* z, double* x, hipStream_t s);
 
 // ---------------------------------------------------------------- apply
 constexpr int kApplyRPW = 1;  // rows of H_S^-1 per wave in the apply

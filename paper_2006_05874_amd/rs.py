@@ -83,7 +83,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-           "rs_gradient_plan", "rs_solve_path"]
+           "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -138,6 +138,9 @@ def load(path=LIB_PATH):
                                  ctypes.POINTER(SolveInfo), ctypes.c_int32, vp]
     L.rs_solve_nu_grid.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
                                    ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
+    L.rs_adaptive_solve_dual.argtypes = [vp, c_int, i64, i64, i64, vp, dbl,
+                                         ctypes.POINTER(SolveOpts), vp, vp,
+                                         ctypes.POINTER(SolveInfo), vp]
     L.rs_solve_path.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
                                 ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
     L.rs_learned_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
@@ -152,7 +155,7 @@ def load(path=LIB_PATH):
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-                 "rs_gradient_plan", "rs_solve_path"]:
+                 "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -435,6 +438,28 @@ def rs_solve_nu_grid(A, b, nu2s, kind="srht", variant="polyak", resample="fresh"
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
         _check(st, "rs_solve_nu_grid")
     return X, [_info(infos[i], infos[i].status, False, "rs_solve_nu_grid") for i in range(k)]
+
+
+def rs_adaptive_solve_dual(A, b, nu2, kind="srht", variant="polyak", resample="fresh",
+                           sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
+                           max_iter=200, seed=0, check_every=4, z0=None, raise_on_error=True,
+                           ref_at_zero=False):
+    """The underdetermined case (n <= d) through the dual problem.  Returns
+    (x, z, info): x = A^T z the primal solution (d), z the dual one (n), both
+    float64 tensors."""
+    a_t = _mat(A, "rs_adaptive_solve_dual")
+    n, d = A.shape
+    o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
+              seed, check_every)
+    o.flags = RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
+    z = (torch.zeros(n, dtype=torch.float64, device=A.device) if z0 is None
+         else z0.to(torch.float64).contiguous().clone())
+    x = torch.zeros(d, dtype=torch.float64, device=A.device)
+    info = SolveInfo()
+    st = load().rs_adaptive_solve_dual(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+                                       ctypes.byref(o), _ptr(z), _ptr(x), ctypes.byref(info),
+                                       _stream())
+    return x, z, _info(info, st, raise_on_error, "rs_adaptive_solve_dual")
 
 
 def rs_solve_path(A, b, nu2s, kind="srht", variant="polyak", sketch_dtype=None, rho=0.1,

@@ -141,3 +141,29 @@ def config_path_nu2():
 def make_path_problem(device, dtype=None, n=PATH_N, d=PATH_D, seed=17):
     """A for the path: 65536 x 1024, sigma_i = 1/i (sigma_1 = 1), noise 0.1."""
     return make_problem_torch(n, d, spectrum("poly", d, 1.0), 0.1, seed, device, dtype=dtype)[:2]
+
+
+def make_wide_problem_torch(n, d, sigma, noise, seed, device, dtype=None):
+    """An underdetermined problem (n < d) on the device: A is the transpose of a
+    d x n draw of make_problem_torch (so its singular values are sigma), and
+    b = A x_pl + noise * xi with x_pl ~ N(0, I_d) from the same seed."""
+    import torch
+    dtype = dtype or torch.float32
+    T = make_problem_torch(d, n, sigma, noise, seed, device, dtype=dtype)[0]
+    A = T.t().contiguous()
+    del T
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed + 1)
+    x_pl = torch.randn(d, generator=gen, device=device, dtype=torch.float64)
+    xi = torch.randn(n, generator=gen, device=device, dtype=torch.float64)
+    b = (A.to(torch.float64) @ x_pl + noise * xi).to(dtype)
+    return A, b
+
+
+DUAL_N, DUAL_D = 1024, 1 << 16
+
+
+def make_dual_problem(device, dtype=None, n=DUAL_N, d=DUAL_D, seed=23):
+    """The wide problem of the dual form: 1024 x 65536 (the transpose of the
+    headline shape), sigma_i = 1/i, noise 0.1."""
+    return make_wide_problem_torch(n, d, spectrum("poly", n, 1.0), 0.1, seed, device, dtype=dtype)

@@ -1,0 +1,137 @@
+"""GPU parity of the underdetermined case (rs_adaptive_solve_dual, appendix: the
+dual problem): the FP64 dual trajectory equals the oracle's, x = A^T z matches
+the primal solution for ragged FP32 shapes and at the full 1024 x 65536 size,
+and a tall matrix is rejected."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ihs, ridge  # noqa: E402
+from synth import make_dual_problem, make_problem, spectrum  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_05874_amd import rs as _rs
+    _rs.load()
+    return _rs
+
+
+def dev_padded(A, rs):
+    dt = torch.float64 if A.dtype == np.float64 else torch.float32
+    T = rs.padded(A.shape[0], A.shape[1], dtype=dt)
+    T.copy_(torch.from_numpy(A))
+    return T
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def primal_bound(tol, s1, nu2):
+    # appendix: delta(A^T z) <= sigma_1^2 eps(z), so a dual stop at relative tol
+    # leaves a primal relative error of order tol sigma_1^2 / nu^2 (the extra
+    # log(sigma_1^2 / nu^2) iterations of its count); 10x covers the decrement proxy
+    return 10.0 * tol * (1.0 + s1 * s1 / nu2)
+
+
+def wide(n, d, rate, seed, dtype):
+    # the transpose of a tall draw; b of length n
+    p = make_problem(d, n, spectrum("geom", n, rate), 1e-2, 0.01, seed, dtype=np.float64)
+    A = np.ascontiguousarray(p.A.T).astype(dtype)
+    b = np.random.default_rng(seed + 100).standard_normal(n).astype(dtype)
+    return A, b
+
+
+@pytest.mark.parametrize("kind,variant,resample", [("srht", "polyak", "fresh"),
+                                                   ("srht", "gd", "nested"),
+                                                   ("gaussian", "polyak", "nested"),
+                                                   ("gaussian", "gd", "fresh")])
+def test_dual_fp64_trajectories(rs, kind, variant, resample):
+    A, b = wide(64, 1024, 0.9, 5, np.float64)
+    nu2 = 1e-2
+    x, z, info = rs.rs_adaptive_solve_dual(dev_padded(A, rs), torch.from_numpy(b).cuda(), nu2,
+                                           kind=kind, variant=variant, resample=resample,
+                                           tol=1e-10, seed=3)
+    xo, zo, io = ihs.adaptive_solve_dual(A, b, nu2, ihs.Options(kind=kind, variant=variant,
+                                                                resample=resample, tol=1e-10,
+                                                                seed=3))
+    assert info["status"] == "ok"
+    assert info["events"] == [e for e in io.events if e[1] != "stop"]
+    assert info["m_final"] == io.m_final
+    np.testing.assert_allclose(host(z), zo, rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(host(x), xo, rtol=1e-8, atol=1e-12)
+    xs = ridge.solve_svd(A, b, nu2)
+    s1 = np.linalg.svd(A, compute_uv=False)[0]
+    assert ridge.relative_error(ridge.hessian(A, nu2), host(x), xs) <= primal_bound(1e-10, s1,
+                                                                                  nu2)
+
+
+@pytest.mark.parametrize("n,d,sketch_dtype", [(70, 3000, "f32"), (300, 5001, "bf16"),
+                                              (129, 129, "f32")])
+def test_dual_fp32_ragged_reaches_primal_solution(rs, n, d, sketch_dtype):
+    A, b = wide(n, d, 0.97, 11, np.float32)
+    nu2 = 1e-3
+    x, z, info = rs.rs_adaptive_solve_dual(dev_padded(A, rs), torch.from_numpy(b).cuda(), nu2,
+                                           sketch_dtype=sketch_dtype, tol=1e-11, seed=7)
+    assert info["status"] == "ok"
+    A64, b64 = A.astype(np.float64), b.astype(np.float64)
+    zs = ridge.solve_dual_direct(A64, b64, nu2)
+    xs = A64.T @ zs
+    xh = host(x)
+    e = xh - xs
+    delta = np.sum((A64 @ e) ** 2) + nu2 * np.sum(e ** 2)
+    delta0 = np.sum((A64 @ xs) ** 2) + nu2 * np.sum(xs ** 2)
+    s1 = np.linalg.svd(A64, compute_uv=False)[0]
+    assert delta / delta0 <= primal_bound(1e-11, s1, nu2)
+    # the returned x is the map of the returned z
+    np.testing.assert_allclose(xh, A64.T @ host(z), rtol=1e-10, atol=1e-12)
+
+
+def test_dual_full_size_reaches_primal_solution(rs):
+    # 1024 x 65536 FP32, sigma_i = 1/i, nu^2 = 1e-2 and 1e-4
+    A0, b = make_dual_problem("cuda")
+    n, d = A0.shape
+    A = rs.padded(n, d, dtype=torch.float32)
+    A.copy_(A0)
+    del A0
+    A64 = host(A).astype(np.float64)
+    b64 = host(b).astype(np.float64)
+    K = A64 @ A64.T
+    s1 = np.sqrt(np.linalg.eigvalsh(K)[-1])
+    for nu2 in (1e-2, 1e-4):
+        x, z, info = rs.rs_adaptive_solve_dual(A, b, nu2, tol=1e-12)
+        assert info["status"] == "ok"
+        zs = np.linalg.solve(K + nu2 * np.eye(n), b64)
+        xs = A64.T @ zs
+        e = host(x) - xs
+        delta = np.sum((A64 @ e) ** 2) + nu2 * np.sum(e ** 2)
+        delta0 = np.sum((A64 @ xs) ** 2) + nu2 * np.sum(xs ** 2)
+        assert delta / delta0 <= min(1e-6, primal_bound(1e-12, s1, nu2)), nu2
+
+
+def test_dual_warm_start_at_solution_stops(rs):
+    A, b = wide(64, 1024, 0.9, 5, np.float64)
+    Ad, bd = dev_padded(A, rs), torch.from_numpy(b).cuda()
+    x, z, info = rs.rs_adaptive_solve_dual(Ad, bd, 1e-2, tol=1e-10)
+    x2, z2, i2 = rs.rs_adaptive_solve_dual(Ad, bd, 1e-2, tol=1e-6, z0=z, ref_at_zero=True)
+    assert i2["events"] == [] and i2["grad_passes"] == 1
+    np.testing.assert_array_equal(host(x2), host(x))
+
+
+def test_dual_argument_errors(rs):
+    p = make_problem(300, 20, spectrum("geom", 20, 0.9), 1e-2, 0.01, 1, dtype=np.float64)
+    A = dev_padded(p.A, rs)               # tall: n > d
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_adaptive_solve_dual(A, torch.from_numpy(p.b).cuda(), 1e-2)
+    assert e.value.name == "shape"
+    Aw = dev_padded(np.ascontiguousarray(p.A.T), rs)
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_adaptive_solve_dual(Aw, torch.zeros(20, dtype=torch.float64, device="cuda"), -1.0)
+    assert e.value.name == "not_spd"
