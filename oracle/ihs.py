@@ -316,3 +316,47 @@ def solve_path(A, b, nu2s, opts=None):
         infos.append(info)
         m = info.m_final
     return X, infos
+
+
+@dataclass
+class RefreshInfo:
+    status: str = "ok"
+    steps: int = 0            # updates taken
+    r_history: list = field(default_factory=list)
+
+
+def refreshed_ihs(A, b, nu2, m, opts=None, x_init=None):
+    """IHS with refreshed embeddings (Section 1, other versions of the IHS): the
+    update of eq. EqnPolyak (beta = 0 for the gradient variant) with a new sketch
+    S_t of fixed size m drawn at every step (sketch_id = t - 1) and H_{S_t}
+    re-formed; no acceptance tests and no doubling.  The parameters are the
+    fixed-embedding ones for (kind, rho, eta).  Stops once
+    r_t = 1/2 g_t^T H_{S_t}^-1 g_t <= tol * r_1 or after max_iter updates.
+    Returns (x, RefreshInfo)."""
+    opts = opts or Options()
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n, d = A.shape
+    prm = params_for(opts.kind, opts.rho, opts.eta)
+    mu, beta = (prm.mu_p, prm.beta_p) if opts.variant == "polyak" else (prm.mu_gd, 0.0)
+    x = np.zeros(d) if x_init is None else np.asarray(x_init, dtype=np.float64).copy()
+    x_prev = x.copy()
+    info = RefreshInfo()
+    r1 = None
+    t = 1
+    while True:
+        P = SketchedHessian(make_sketch(A, opts.kind, opts.seed, t - 1, m, opts.gauss_precision),
+                            nu2)
+        gt, r = P.decrement(ridge.gradient(A, b, nu2, x))
+        info.r_history.append(r)
+        if r1 is None:
+            r1 = r
+        if r <= opts.tol * r1:
+            break
+        if info.steps >= opts.max_iter:
+            info.status = "no_convergence"
+            break
+        x_prev, x = x, polyak_candidate(x, x_prev, gt, mu, beta)
+        info.steps += 1
+        t += 1
+    return x, info

@@ -339,3 +339,45 @@ def test_origin_reference_is_the_cold_first_decrement(c1):
     # half-way start: delta(x0) = delta(0) / 4 exactly, so the warm r_1 is a
     # quarter of the cold one under the same sketch
     assert warm.r_history[0] == pytest.approx(r_cold_1 / 4, rel=1e-10)
+
+
+# --- refreshed embeddings (Section 1, other versions of the IHS) -------------------
+
+def test_refreshed_full_srht_contracts_by_rho_squared(c1):
+    # m = padded n: every refreshed sketch is exact (H_S = H), so the gradient
+    # variant contracts delta by exactly (1 - mu_gd)^2 = rho^2 per step
+    p, xs, H = c1
+    x = np.zeros(64)
+    errs = []
+    for steps in range(1, 5):
+        x, info = ihs.refreshed_ihs(p.A, p.b, p.nu2, 1024, ihs.Options(variant="gd",
+                                                                        max_iter=steps, tol=0.0))
+        errs.append(ridge.relative_error(H, x, xs))
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 / e0 == pytest.approx(0.01, rel=1e-6)
+
+
+def test_refreshed_step_follows_the_error_recursion(c1):
+    # x_{t+1} - x* = (I - mu H_t^-1 H)(x_t - x*) + beta (x_t - x_{t-1}), H_t from S_t
+    p, xs, H = c1
+    opts = ihs.Options(kind="gaussian", variant="polyak", max_iter=2, tol=0.0, seed=6)
+    m = 200
+    x1, _ = ihs.refreshed_ihs(p.A, p.b, p.nu2, m, ihs.Options(**{**opts.__dict__, "max_iter": 1}))
+    x2, _ = ihs.refreshed_ihs(p.A, p.b, p.nu2, m, opts)
+    SA = ihs.make_sketch(p.A, "gaussian", 6, 1, m)
+    Ht = SA.T @ SA + p.nu2 * np.eye(64)
+    prm = ihs.params_for("gaussian", opts.rho, opts.eta)
+    pred = xs + (np.eye(64) - prm.mu_p * np.linalg.solve(Ht, H)) @ (x1 - xs) + prm.beta_p * x1
+    np.testing.assert_allclose(x2, pred, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["srht", "gaussian"])
+def test_refreshed_reaches_solution_and_stops_on_its_rule(c1, kind):
+    p, xs, H = c1
+    x, info = ihs.refreshed_ihs(p.A, p.b, p.nu2, 512, ihs.Options(kind=kind, variant="gd",
+                                                                  tol=1e-9))
+    assert info.status == "ok"
+    assert ridge.relative_error(H, x, xs) <= 1e-7
+    assert info.r_history[-1] <= 1e-9 * info.r_history[0]
+    assert all(r > 1e-9 * info.r_history[0] for r in info.r_history[:-1])
+    assert len(info.r_history) == info.steps + 1
