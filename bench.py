@@ -57,12 +57,13 @@ def parse():
     ap.add_argument("--skip-plain", action="store_true",
                     help="do not time the plain method beside the learned form")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c4a", "c4b", "c5", "path", "dual"],
+                    choices=["c2", "c3", "c4a", "c4b", "c5", "path", "dual", "refreshed"],
                     help="c2: the 65536x1024 headline problem; c3: the 2^20x4096 precision "
                          "form; c4a: 64 nu^2 on one 2^18x2048 problem; c4b: 256 uneven "
                          "problems, batched; path: the warm-started regularization path "
                          "nu = 10^0..10^-4 on one 65536x1024 problem; dual: the "
-                         "underdetermined 1024x65536 problem through the dual")
+                         "underdetermined 1024x65536 problem through the dual; refreshed: "
+                         "fixed vs refreshed sketches at a fixed m on the headline problem")
     ap.add_argument("--path-modes", default="path_warm_f32,path_warm_bf16,cold_f32",
                     help="path workload: the modes to time (the first listed is the value)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -140,6 +141,8 @@ def main():
         return run_path(args)
     if args.workload == "dual":
         return run_dual(args)
+    if args.workload == "refreshed":
+        return run_refreshed(args)
     import torch
 
     from paper_2006_05874_amd import rs
@@ -739,6 +742,68 @@ def run_dual(args):
                                    "problem, SRHT fresh, m from 1, eps=1e-10 (dual)",
                        "n": n, "d": d},
             "verified": all(v["worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
+                            for v in out.values()),
+            "modes": out}
+    print(json.dumps(line))
+
+
+def run_refreshed(args):
+    """Ablation of the fixed embedding: on the 65536 x 1024 headline problem at
+    nu^2 = 1e-2 and a fixed sketch size m (the final m of a plain run, 512), the
+    IHS with a new sketch and factor every step against Algorithm 1 started at
+    that m (one sketch, step tests), for the SRHT and the Gaussian embedding and
+    both update variants, to eps = 1e-10.  Every solution is checked against the
+    oracle's direct solve."""
+    import torch
+    from oracle import ridge
+    from paper_2006_05874_amd import rs
+    from synth import config_c2
+    torch.cuda.set_device(0)
+    p = config_c2(nu2=1e-2, seed=0)
+    n, d = p.A.shape
+    A = rs.padded(n, d, dtype=torch.float32)
+    A.copy_(torch.from_numpy(p.A))
+    b = torch.from_numpy(p.b).cuda()
+    m, tol = 512, 1e-10
+    xs = ridge.solve_direct(p.A.astype(np.float64), p.b.astype(np.float64), p.nu2)
+    H = ridge.hessian(p.A.astype(np.float64), p.nu2)
+    print("[refreshed] problem ready", file=sys.stderr, flush=True)
+    out = {}
+    for kind in ("srht", "gaussian"):
+        for variant in ("gd", "polyak"):
+            def refreshed():
+                x, rh, i = rs.rs_refreshed_ihs(A, b, p.nu2, m, kind=kind, variant=variant,
+                                               tol=tol, raise_on_error=False)
+                return x, i
+
+            def fixed():
+                return rs.rs_adaptive_solve(A, b, p.nu2, kind=kind, variant=variant, m_init=m,
+                                            tol=tol, raise_on_error=False)
+            for name, fn in (("refreshed", refreshed), ("fixed", fixed)):
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    x, info = fn()
+                torch.cuda.synchronize()
+                sec = (time.perf_counter() - t0) / args.steps
+                out[f"{kind}_{variant}_{name}"] = {
+                    "ms_per_solve": round(sec * 1e3, 3), "steps": info["steps"],
+                    "m_final": info["m_final"], "doublings": info.get("doublings", 0),
+                    "status": info["status"],
+                    "rel_pred_err": ridge.relative_error(H, x.cpu().numpy(), xs)}
+                print(f"[refreshed] {kind} {variant} {name}: {sec * 1e3:.2f} ms, "
+                      f"{info['steps']} steps", file=sys.stderr, flush=True)
+    best = "srht_gd_refreshed"
+    line = {"metric": "ridge solves/s to eps = 1e-10, refreshed-embedding IHS (ablation)",
+            "value": round(1e3 / out[best]["ms_per_solve"], 2), "unit": "solves/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": out[best]["ms_per_solve"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 gradient / f32 sketch / f64 factor", "data": "synthetic",
+            "config": {"workload": f"{n}x{d} FP32, sigma_i=1/i, nu^2=1e-2, fixed m={m}, "
+                                   "refreshed vs fixed sketch, eps=1e-10", "n": n, "d": d},
+            "verified": all(v["rel_pred_err"] <= 1e-8 and v["status"] == "ok"
                             for v in out.values()),
             "modes": out}
     print(json.dumps(line))

@@ -290,6 +290,24 @@ rs_status rs_solve_nu_grid(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
                            const rs_solve_opts* opts, double* X, rs_solve_info* infos,
                            hipStream_t stream);
 
+/* IHS with refreshed embeddings (Section 1, other versions of the IHS), an
+ * ablation of the fixed sketch: the update of eq. EqnPolyak (beta = 0 for
+ * RS_VARIANT_GD) with a new sketch of fixed size m = opts->m_init (clamped to the
+ * padded n, SRHT, or n, Gaussian) drawn at every step t (sketch_id t - 1) and
+ * H_S re-formed; the step sizes are the fixed-embedding ones for (kind, rho, eta);
+ * no acceptance tests, no doubling.  Stops at r_t <= tol * r_1, with r_t the
+ * decrement under step t's sketch, or after max_iter updates.  opts->resample,
+ * check_every and flags are ignored.
+ *   x      : device, d FP64: in = x_1 (= x_0), out = last iterate.
+ *   r_hist : host, max_iter + 1 doubles or null: r_1, r_2, ... (info->grad_passes
+ *            of them are written).
+ *   info   : host; steps = updates taken, grad_passes = decrements evaluated,
+ *            r_ref = r_1, m_final = m, no events.
+ * Synchronizes every step.  Returns RS_OK, RS_ERR_NO_CONVERGENCE, or an error. */
+rs_status rs_refreshed_ihs(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                           const void* b, double nu2, const rs_solve_opts* opts, double* x,
+                           double* r_hist, rs_solve_info* info, hipStream_t stream);
+
 /* The underdetermined case n <= d (appendix, the dual problem): Algorithm 1 on
  * min_z 1/2 |A^T z - b^|^2 + nu^2/2 |z|^2 with b^ = A^+ b, whose data matrix is A^T
  * (the sketch acts on its d rows, m <= padded d) and whose gradient is

@@ -235,6 +235,59 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
   }
 }
 
+// IHS with refreshed embeddings, after the gradient and the apply of evaluation t
+// under that step's own sketch: r_t = 1/2 g_t^T gtilde_t (r_1 kept from t = 1,
+// r_t stored at rhist[t - 1]); stop at r_t <= tol r_1 (or after max_iter updates),
+// else x <- x - mu gtilde + beta (x - x_prev), x_prev <- the old x, t += 1.
+__global__ __launch_bounds__(1024) void k_refresh_step(DevCtl* __restrict__ ctl,
+                                                       const double* __restrict__ rpart, int nrp,
+                                                       int64_t d, const double* __restrict__ GT,
+                                                       double* __restrict__ x,
+                                                       double* __restrict__ x_prev, double mu,
+                                                       double beta, double tol, int64_t max_iter,
+                                                       double* __restrict__ rhist, int64_t rcap) {
+  __shared__ double sh[1024];
+  __shared__ double rs1[1];
+  __shared__ int upd;
+  block_sum_cols<1, 1024>(rpart, nrp, sh, rs1);
+  if (threadIdx.x == 0) {
+    const double r = 0.5 * rs1[0];
+    const int64_t t = ctl->t;
+    if (t == 1) ctl->r_1 = r;
+    ctl->r_t = r;
+    ctl->r_ref = ctl->r_1;
+    if (t - 1 < rcap) rhist[t - 1] = r;
+    int st = RS_CTL_RUNNING;
+    if (!isfinite(r)) st = RS_CTL_NONFINITE;
+    else if (r <= tol * ctl->r_1) st = RS_CTL_CONVERGED;
+    else if (ctl->steps >= max_iter) st = RS_CTL_MAXITER;
+    ctl->status = st;
+    ctl->passes += 1;
+    upd = st == RS_CTL_RUNNING;
+    if (upd) {
+      ctl->steps += 1;
+      ctl->t = t + 1;
+    }
+  }
+  __syncthreads();
+  if (!upd) return;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    const double xi = x[i];
+    const double xn = xi - mu * GT[i] + beta * (xi - x_prev[i]);
+    x_prev[i] = xi;
+    x[i] = xn;
+  }
+}
+
+rs_status refresh_step_launch(DevCtl* ctl, const double* rpart, int nrp, int64_t d,
+                              const double* GT, double* x, double* x_prev, double mu, double beta,
+                              double tol, int64_t max_iter, double* rhist, int64_t rcap,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_step, dim3(1), dim3(1024), 0, s, ctl, rpart, nrp, d, GT, x, x_prev,
+                     mu, beta, tol, max_iter, rhist, rcap);
+  return check_launch("refresh step");
+}
+
 // Copy two vectors into a 2-column block (for the post-resample apply).
 __global__ __launch_bounds__(256) void k_pack2(int64_t d, const double* __restrict__ a,
                                                const double* __restrict__ b,

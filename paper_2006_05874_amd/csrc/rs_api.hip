@@ -1266,6 +1266,74 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
   return J.result;
 }
 
+rs_status rs_refreshed_ihs(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                           const void* b, double nu2, const rs_solve_opts* opts, double* x,
+                           double* r_hist, rs_solve_info* info, hipStream_t stream) {
+  if (!opts || !info) return set_error(RS_ERR_ARG, "rs_refreshed_ihs: null argument");
+  SolveJob J;
+  J.A = A; J.a_t = a_t; J.n = n; J.d = d; J.lda = lda; J.b = b; J.nu2 = nu2; J.x = x;
+  J.o = *opts; J.o.resample = RS_RESAMPLE_FRESH; J.info = info; J.stream = stream;
+  RS_TRY(J.validate());
+  const int64_t m = J.m;  // fixed: m_init clamped to [1, m_cap]
+  const bool polyak = J.o.variant == RS_VARIANT_POLYAK;
+  const double mu = polyak ? J.prm.mu_p : J.prm.mu_gd;
+  const double beta = polyak ? J.prm.beta_p : 0.0;
+  const int64_t rcap = J.o.max_iter + 1;
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  J.S = S;
+  std::memset(info, 0, sizeof(*info));
+  RS_TRY(S->vecs.ensure((size_t)3 * d * sizeof(double)));
+  RS_TRY(S->rpart.ensure((size_t)J.nrp * 4 * sizeof(double)));
+  RS_TRY(S->ctl.ensure(kSnapFlagOff + 16));
+  RS_TRY(S->rvec.ensure((size_t)rcap * sizeof(double)));
+  double* xp = S->vecs.as<double>();
+  double* G = xp + d;
+  double* GT = G + d;
+  double* rhist = S->rvec.as<double>();
+  DevCtl* dctl = S->ctl.as<DevCtl>();
+  J.finfo = reinterpret_cast<int*>(S->ctl.as<char>() + kSnapFlagOff);
+  DevCtl h{};
+  h.t = 1;
+  RS_HIP(hipMemcpyAsync(dctl, &h, sizeof(DevCtl), hipMemcpyHostToDevice, stream));
+  RS_HIP(hipMemsetAsync(J.finfo, 0, sizeof(int), stream));
+  RS_HIP(hipMemcpyAsync(xp, x, (size_t)d * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  rs_status result = RS_OK;
+  for (;;) {
+    // a new sketch (sketch_id t - 1) and factor every step, then one step
+    RS_TRY(J.sketch_and_factor(m, (uint32_t)(h.t - 1)));
+    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
+    RS_TRY(apply_launch(J.Hinv, J.dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
+    RS_TRY(refresh_step_launch(dctl, S->rpart.as<double>(), J.nrp, d, GT, x, xp, mu, beta,
+                               J.o.tol, J.o.max_iter, rhist, rcap, stream));
+    int fbad = 0;
+    RS_HIP(hipMemcpyAsync(&h, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
+    RS_HIP(hipMemcpyAsync(&fbad, J.finfo, sizeof(int), hipMemcpyDeviceToHost, stream));
+    RS_HIP(hipStreamSynchronize(stream));
+    if (fbad) {
+      result = set_error(RS_ERR_NOT_SPD, "rs_refreshed_ihs: sketched Hessian factor failed");
+      break;
+    }
+    if (h.status == RS_CTL_RUNNING) continue;
+    if (h.status == RS_CTL_NONFINITE)
+      result = set_error(RS_ERR_NONFINITE, "rs_refreshed_ihs: non-finite decrement");
+    else if (h.status == RS_CTL_MAXITER)
+      result = set_error(RS_ERR_NO_CONVERGENCE, "rs_refreshed_ihs: max_iter reached");
+    break;
+  }
+  const int64_t evals = std::min<int64_t>(h.passes, rcap);
+  if (r_hist && evals > 0)
+    RS_HIP(hipMemcpy(r_hist, rhist, (size_t)evals * sizeof(double), hipMemcpyDeviceToHost));
+  info->status = result;
+  info->m_final = m;
+  info->steps = h.steps;
+  info->grad_passes = h.passes;
+  info->applies = h.passes;
+  info->r_final = h.r_t;
+  info->r_ref = h.r_1;
+  return result;
+}
+
 rs_status rs_adaptive_solve_dual(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
                                  const void* b, double nu2, const rs_solve_opts* opts, double* z,
                                  double* x, rs_solve_info* info, hipStream_t stream) {

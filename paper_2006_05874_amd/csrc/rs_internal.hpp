@@ -197,6 +197,10 @@ rs_status init_state_launch(DevCtl* ctl, const double* rpart, int nrp, double to
                             const double* x, double* x_prev, double* g, double* gt, double* gref,
                             int at_cap, hipStream_t s, NextCand nc = NextCand(),
                             CtlSnap snap = CtlSnap(), int cols = 1);
+rs_status refresh_step_launch(DevCtl* ctl, const double* rpart, int nrp, int64_t d,
+                              const double* GT, double* x, double* x_prev, double mu, double beta,
+                              double tol, int64_t max_iter, double* rhist, int64_t rcap,
+                              hipStream_t s);
 rs_status post_resample_launch(DevCtl* ctl, const double* rpart, int nrp, double tol, int64_t d,
                                const double* GT, double* gt, int at_cap, hipStream_t s,
                                NextCand nc = NextCand(), const double* x = nullptr,

@@ -83,7 +83,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-           "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual"]
+           "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -141,6 +141,8 @@ def load(path=LIB_PATH):
     L.rs_adaptive_solve_dual.argtypes = [vp, c_int, i64, i64, i64, vp, dbl,
                                          ctypes.POINTER(SolveOpts), vp, vp,
                                          ctypes.POINTER(SolveInfo), vp]
+    L.rs_refreshed_ihs.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, ctypes.POINTER(SolveOpts),
+                                   vp, ctypes.POINTER(dbl), ctypes.POINTER(SolveInfo), vp]
     L.rs_solve_path.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
                                 ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
     L.rs_learned_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
@@ -155,7 +157,8 @@ def load(path=LIB_PATH):
                  "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-                 "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual"]:
+                 "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual",
+                 "rs_refreshed_ihs"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -460,6 +463,23 @@ def rs_adaptive_solve_dual(A, b, nu2, kind="srht", variant="polyak", resample="f
                                        ctypes.byref(o), _ptr(z), _ptr(x), ctypes.byref(info),
                                        _stream())
     return x, z, _info(info, st, raise_on_error, "rs_adaptive_solve_dual")
+
+
+def rs_refreshed_ihs(A, b, nu2, m, kind="srht", variant="gd", sketch_dtype=None, rho=0.1,
+                     eta=0.01, tol=1e-7, max_iter=200, seed=0, x0=None, raise_on_error=True):
+    """IHS with a new sketch of size m at every step (the refreshed-embedding
+    ablation).  Returns (x, r_history list, info dict)."""
+    a_t = _mat(A, "rs_refreshed_ihs")
+    n, d = A.shape
+    o = _opts(a_t, kind, variant, "fresh", sketch_dtype, rho, eta, m, 0, tol, max_iter, seed, 1)
+    x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
+         else x0.to(torch.float64).contiguous().clone())
+    rh = (ctypes.c_double * (max_iter + 1))()
+    info = SolveInfo()
+    st = load().rs_refreshed_ihs(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+                                 ctypes.byref(o), _ptr(x), rh, ctypes.byref(info), _stream())
+    res = _info(info, st, raise_on_error, "rs_refreshed_ihs")
+    return x, [rh[i] for i in range(min(info.grad_passes, max_iter + 1))], res
 
 
 def rs_solve_path(A, b, nu2s, kind="srht", variant="polyak", sketch_dtype=None, rho=0.1,

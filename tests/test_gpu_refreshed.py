@@ -1,0 +1,63 @@
+"""GPU parity of the refreshed-embedding IHS (rs_refreshed_ihs, the ablation of
+Section 1's other IHS versions): the FP64 decrement history and iterate equal the
+oracle's, and an FP32 run at the full 65536 x 1024 size reaches the solution."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ihs, ridge  # noqa: E402
+from synth import config_c1, make_problem, spectrum  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_05874_amd import rs as _rs
+    _rs.load()
+    return _rs
+
+
+def dev_padded(A, rs):
+    dt = torch.float64 if A.dtype == np.float64 else torch.float32
+    T = rs.padded(A.shape[0], A.shape[1], dtype=dt)
+    T.copy_(torch.from_numpy(A))
+    return T
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["srht", "gaussian"])
+@pytest.mark.parametrize("variant", ["gd", "polyak"])
+@pytest.mark.parametrize("m", [128, 512])
+def test_refreshed_fp64_history(rs, kind, variant, m):
+    p = config_c1()
+    x, rh, info = rs.rs_refreshed_ihs(dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2, m,
+                                      kind=kind, variant=variant, tol=1e-8, seed=2, max_iter=100)
+    xo, io = ihs.refreshed_ihs(p.A, p.b, p.nu2, m, ihs.Options(kind=kind, variant=variant,
+                                                               tol=1e-8, seed=2, max_iter=100))
+    assert info["status"] == io.status
+    assert info["steps"] == io.steps and len(rh) == len(io.r_history)
+    np.testing.assert_allclose(rh, io.r_history, rtol=1e-8, atol=0)
+    np.testing.assert_allclose(host(x), xo, rtol=1e-8, atol=1e-12)
+
+
+def test_refreshed_fp32_ragged_and_cap(rs):
+    p = make_problem(5000, 300, spectrum("geom", 300, 0.97), 1e-3, 0.1, 3)
+    A = dev_padded(p.A, rs)
+    b = torch.from_numpy(p.b).cuda()
+    x, rh, info = rs.rs_refreshed_ihs(A, b, p.nu2, 1024, sketch_dtype="bf16", tol=1e-9)
+    assert info["status"] == "ok" and rh[-1] <= 1e-9 * rh[0]
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    xs = ridge.solve_direct(A64, b64, p.nu2)
+    assert ridge.relative_error(ridge.hessian(A64, p.nu2), host(x), xs) <= 1e-7
+    # a step cap: no convergence reported, the history holds max_iter + 1 values
+    x2, rh2, i2 = rs.rs_refreshed_ihs(A, b, p.nu2, 1024, tol=1e-9, max_iter=3,
+                                      raise_on_error=False)
+    assert i2["status"] == "no_convergence" and i2["steps"] == 3 and len(rh2) == 4
