@@ -27,6 +27,10 @@ Readings where the paper is silent:
     at the origin, g(0) = -A^T b, whatever the starting point: a warm-started
     solve then stops at the accuracy delta(x) / delta(0) a cold one would (a start
     at the origin is its own reference, so nothing extra is evaluated).
+* Sparse A (the remark on sparse data matrices): the CountSketch, whose cost is
+  O(nnz); the paper leaves its analysis open, so the step sizes are the SRHT's for
+  the same rho, and a doubling refines each bucket into two (nested) or re-hashes
+  (fresh).
 * Underdetermined case (appendix, the dual problem): Algorithm 1 unchanged on the
   data matrix A^T with gradient A A^T z - b + nu^2 z; the primal solution is A^T z.
 * Regularization path (Section 4, warm starts): nu^2 decreasing, each solve
@@ -93,7 +97,8 @@ class Params:
 
 
 def params_for(kind, rho=0.1, eta=0.01):
-    lam, Lam = srht_bounds(rho) if kind == "srht" else gaussian_bounds(rho, eta)
+    # the CountSketch takes the SRHT's bounds (a reading: the paper gives none)
+    lam, Lam = srht_bounds(rho) if kind in ("srht", "count") else gaussian_bounds(rho, eta)
     return Params(mu_gd=mu_gd(lam, Lam), mu_p=mu_p(lam, Lam), beta_p=beta_p(lam, Lam),
                   cbar_gd=c_gd(lam, Lam), cbar_p=c_p(lam, Lam))
 
@@ -135,6 +140,8 @@ class SketchedHessian:
 
 
 def make_sketch(A, kind, seed, sketch_id, m, gauss_precision="f64"):
+    if kind == "count":
+        return sketch.count_sketch(A, seed, sketch_id, m)
     if kind == "srht":
         SA, _ = sketch.srht_sketch(A, seed, sketch_id, m)
         return SA
@@ -206,6 +213,13 @@ def adaptive_solve_dual(A, b, nu2, opts=None, z_init=None):
     b = np.asarray(b, dtype=np.float64)
     z, info = _algorithm1(A.T, lambda z: ridge.dual_gradient(A, b, nu2, z), nu2, opts, z_init)
     return A.T @ z, z, info
+
+
+def adaptive_solve_sparse(A, b, nu2, opts=None, x_init=None):
+    """Algorithm 1 for a sparse A (scipy.sparse, n x d) with the CountSketch
+    (opts.kind "count"): the sketch and the gradient cost O(nnz).  Returns (x, info)."""
+    b = np.asarray(b, dtype=np.float64)
+    return _algorithm1(A, lambda x: ridge.sparse_gradient(A, b, nu2, x), nu2, opts, x_init)
 
 
 def _algorithm1(A, gradient, nu2, opts, x_init):

@@ -29,6 +29,7 @@ STREAM_SIGNS = 4
 STREAM_ROWKEYS = 5
 STREAM_GAUSS = 6
 STREAM_PROBE = 7
+STREAM_COUNT = 8
 
 
 def philox4x32_10_scalar(counter, key):
@@ -124,3 +125,12 @@ def gaussian_entries(seed, sketch_id, idx, precision):
     else:
         raise ValueError(precision)
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def count_sketch_hash(seed, sketch_id, n, m):
+    """CountSketch column of each row i = 0..n-1: bucket h_i = (word0 * m) >> 32
+    (the high word of the product, uniform on [0, m) and refined by doubling m:
+    h_i at 2m is 2 h_i or 2 h_i + 1) and sign s_i = 1 - 2 * (word1 & 1)."""
+    w0, w1, _, _ = draw(seed, STREAM_COUNT, sketch_id, np.arange(n, dtype=np.uint64))
+    h = ((w0 * np.uint64(m)) >> np.uint64(32)).astype(np.int64)
+    return h, 1.0 - 2.0 * (w1 & np.uint64(1)).astype(np.float64)

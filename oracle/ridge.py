@@ -21,6 +21,12 @@ def gradient(A, b, nu2, x):
     return A.T @ (A @ x - np.asarray(b, dtype=np.float64)) + nu2 * x
 
 
+def sparse_gradient(A, b, nu2, x):
+    """grad f(x) = A^T (A x - b) + nu^2 x for a scipy.sparse A (two products)."""
+    x = np.asarray(x, dtype=np.float64)
+    return A.T @ (A @ x - np.asarray(b, dtype=np.float64)) + nu2 * x
+
+
 def dual_gradient(A, b, nu2, z):
     """grad g(z) = A A^T z - b + nu^2 z: the gradient of the dual problem of the
     underdetermined case (appendix), min_z 1/2 |A^T z|^2 + nu^2/2 |z|^2 - b^T z."""

@@ -17,6 +17,11 @@ the previous sketch (the nested resampling option).
 
 Gaussian (Section 1): S[k, j] = z_{k n + j} / sqrt(m) with z standard normal.
 
+CountSketch (the O(nnz) sparse embedding the paper names for sparse A in its
+complexity remark): S has one nonzero per column, S[h_i, i] = s_i, with the bucket
+h_i uniform on [0, m) and the sign s_i Rademacher; S^T S has a unit diagonal and
+E[S^T S] = I without scaling.
+
 Nothing here uses a fast transform: every Hadamard entry is evaluated from its
 definition.
 """
@@ -108,3 +113,14 @@ def gaussian_sketch(A, seed, sketch_id, m, precision="f64", row_block=64):
         z = philox.gaussian_entries(seed, sketch_id, idx.ravel(), precision).reshape(k1 - k0, n)
         SA[k0:k1] = z @ A
     return SA / np.sqrt(m)
+
+
+def count_sketch(A, seed, sketch_id, m):
+    """SA for the CountSketch S (m x n, S[h_i, i] = s_i), as a sparse-times-matrix
+    product; A may be dense or a scipy.sparse matrix.  Returns a dense FP64 array."""
+    import scipy.sparse as sp
+    n = A.shape[0]
+    h, s = philox.count_sketch_hash(seed, sketch_id, n, m)
+    S = sp.csr_matrix((s, (h, np.arange(n))), shape=(m, n))
+    SA = S @ A
+    return np.asarray(SA.todense() if sp.issparse(SA) else SA, dtype=np.float64)
