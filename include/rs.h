@@ -46,7 +46,9 @@ typedef enum {
 } rs_status;
 
 typedef enum { RS_F64 = 0, RS_F32 = 1, RS_BF16 = 2, RS_FP8E4M3 = 3 } rs_dtype;
-typedef enum { RS_SKETCH_SRHT = 0, RS_SKETCH_GAUSSIAN = 1 } rs_sketch_kind;
+/* COUNT: the CountSketch, one signed nonzero per column of S (for sparse A, see
+ * rs_adaptive_solve_csr). */
+typedef enum { RS_SKETCH_SRHT = 0, RS_SKETCH_GAUSSIAN = 1, RS_SKETCH_COUNT = 2 } rs_sketch_kind;
 /* FRESH: each doubling draws a new sketch (Algorithm 1 samples S afresh).
  * NESTED: keeps the signs and row keys; the 2m rows include the previous m. */
 typedef enum { RS_RESAMPLE_FRESH = 0, RS_RESAMPLE_NESTED = 1 } rs_resample;
@@ -289,6 +291,29 @@ rs_status rs_solve_nu_grid(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
                            const void* b, const double* nu2, int64_t count,
                            const rs_solve_opts* opts, double* X, rs_solve_info* infos,
                            hipStream_t stream);
+
+/* Sparse A (the remark on sparse data matrices, which names O(nnz) embeddings
+ * and leaves them open): Algorithm 1 with the CountSketch, S[h_i, i] = s_i, bucket
+ * h_i = high word of (Philox word0 * m) and sign s_i from word1 (stream 8, counter
+ * (i, sketch_id), key seed).  Forming SA and the gradient cost O(nnz); the step
+ * sizes are the SRHT's for the same rho (the paper gives none); under NESTED
+ * resampling a doubling splits every bucket in two, under FRESH it re-hashes.
+ * m is capped at n (or opts->m_max).  opts->kind must be RS_SKETCH_COUNT;
+ * sketch_dtype F64 (F64 values), F32 or BF16.  The library forms a column-major
+ * copy of A once per call (nnz indices and values) for the A^T r pass; every sum
+ * runs in a fixed order (no floating-point atomics).
+ *   rowptr : device, n + 1 int64, rowptr[0] = 0, rowptr[n] = nnz, non-decreasing.
+ *   col    : device, nnz int32 in [0, d), distinct within a row (a repeated
+ *            column within a row gives an unspecified sketch).
+ *   val    : device, nnz values of type a_t (F32 or F64).
+ *   b      : device, n values of type a_t.   x: device, d FP64 in = x_1, out.
+ * n >= d, n and nnz below 2^31, d <= 8192.  Synchronizes.  Returns RS_OK,
+ * RS_ERR_NO_CONVERGENCE, RS_ERR_ARG for a malformed CSR (checked on the device
+ * before any other work), or another error. */
+rs_status rs_adaptive_solve_csr(const int64_t* rowptr, const int32_t* col, const void* val,
+                                rs_dtype a_t, int64_t n, int64_t d, int64_t nnz, const void* b,
+                                double nu2, const rs_solve_opts* opts, double* x,
+                                rs_solve_info* info, hipStream_t stream);
 
 /* IHS with refreshed embeddings (Section 1, other versions of the IHS), an
  * ablation of the fixed sketch: the update of eq. EqnPolyak (beta = 0 for

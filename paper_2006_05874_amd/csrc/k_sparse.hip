@@ -1,0 +1,437 @@
+// Sparse A (CSR) with the CountSketch, the O(nnz) embedding named for sparse data
+// matrices: S has one signed nonzero per column, S[h_i, i] = s_i.  Every sum has a
+// fixed order (no floating-point atomics): rows are grouped by bucket with a
+// stable radix sort, the gradient's A^T r pass runs over a column-major (CSC) copy
+// formed once per solve by the same kind of sort.
+#include <hipcub/hipcub.hpp>
+
+#include "rs_internal.hpp"
+
+namespace rs {
+
+#define SP_HIP(call)                                                                \
+  do {                                                                              \
+    const hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                           \
+      return set_error(e_ == hipErrorOutOfMemory ? RS_ERR_OOM : RS_ERR_HIP,         \
+                       hipGetErrorString(e_));                                      \
+  } while (0)
+#define SP_TRY(expr)                   \
+  do {                                 \
+    const rs_status st_ = (expr);      \
+    if (st_ != RS_OK) return st_;      \
+  } while (0)
+
+static size_t value_size(rs_dtype t) { return t == RS_F64 ? 8 : 4; }
+
+rs_status GrowBuf::ensure(size_t want) {
+  if (want <= bytes && p) return RS_OK;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+  const size_t sz = want ? want : 256;
+  const hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return set_error(e == hipErrorOutOfMemory ? RS_ERR_OOM : RS_ERR_HIP, hipGetErrorString(e));
+  }
+  bytes = sz;
+  return RS_OK;
+}
+
+// bad = 1 unless rowptr[0] = 0, rowptr[n] = nnz, rowptr never decreases and every
+// column index is in [0, d)
+__global__ __launch_bounds__(256) void k_csr_check(const int64_t* __restrict__ rowptr, int64_t n,
+                                                   const int32_t* __restrict__ col, int64_t nnz,
+                                                   int64_t d, int* __restrict__ bad) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool ok = true;
+  if (t == 0) ok = rowptr[0] == 0 && rowptr[n] == nnz;
+  for (int64_t i = t; i < n; i += stride) ok = ok && rowptr[i] <= rowptr[i + 1];
+  for (int64_t q = t; q < nnz; q += stride) ok = ok && col[q] >= 0 && col[q] < d;
+  if (!ok) *bad = 1;
+}
+
+// bucket h_i = high word of (word0 * m), sign from word1 (Philox stream 8)
+__global__ __launch_bounds__(256) void k_cs_hash(int64_t n, uint64_t seed, uint32_t sid,
+                                                 uint32_t m, uint32_t* __restrict__ bucket,
+                                                 int32_t* __restrict__ row,
+                                                 float* __restrict__ sign) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const uint4 w = draw(seed, kStreamCount, sid, (uint64_t)i);
+    bucket[i] = (uint32_t)(((uint64_t)w.x * (uint64_t)m) >> 32);
+    row[i] = (int32_t)i;
+    sign[i] = (w.y & 1u) ? -1.0f : 1.0f;
+  }
+}
+
+// off[k] = first position p of the sorted keys with key[p] >= k, k = 0..nk
+__global__ __launch_bounds__(256) void k_segment_offsets(const uint32_t* __restrict__ key,
+                                                         int64_t n, uint32_t nk,
+                                                         int64_t* __restrict__ off) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p <= n;
+       p += (int64_t)gridDim.x * 256) {
+    const uint32_t lo = p == 0 ? 0u : key[p - 1] + 1u;
+    const uint32_t hi = p == n ? nk : key[p];
+    for (uint32_t k = lo; k <= hi && k <= nk; ++k) off[k] = p;
+  }
+}
+
+// Rows are grouped by bucket (ascending within a bucket, from the stable sort) and
+// each bucket's rows are cut into chunks of kCsChunk rows: chunk c of the chunk
+// list (cst[h] = first chunk of bucket h) is one block.  The block's W groups of
+// 16 lanes take the chunk's rows in turn, each group adding its rows in order into
+// its own FP64 LDS row (a row's columns are distinct, so the lanes never collide);
+// the W rows are then summed in group order into the chunk's partial row.
+constexpr int kCsChunk = 256;
+
+__device__ __forceinline__ int64_t upper_index(const int64_t* __restrict__ v, int64_t len,
+                                               int64_t x) {  // last k with v[k] <= x
+  int64_t lo = 0, hi = len - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (v[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_counts(const int64_t* __restrict__ off, int64_t nseg,
+                                                      int64_t per, int64_t* __restrict__ nch) {
+  for (int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x; h <= nseg;
+       h += (int64_t)gridDim.x * 256)
+    nch[h] = h == nseg ? 0 : (off[h + 1] - off[h] + per - 1) / per;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cs_partial(const int64_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const T* __restrict__ val,
+                                                    const int32_t* __restrict__ srow,
+                                                    const float* __restrict__ sign,
+                                                    const int64_t* __restrict__ off,
+                                                    const int64_t* __restrict__ cst, int64_t m,
+                                                    int64_t d, int W, double* __restrict__ part) {
+  extern __shared__ double acc[];
+  const int64_t c = blockIdx.x;
+  if (c >= cst[m]) return;
+  const int64_t h = upper_index(cst, m + 1, c);
+  const int64_t p0 = off[h] + (c - cst[h]) * kCsChunk;
+  const int64_t p1 = min(off[h + 1], p0 + (int64_t)kCsChunk);
+  const int w = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  for (int64_t j = threadIdx.x; j < (int64_t)W * d; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  double* a = acc + (int64_t)w * d;
+  for (int64_t p = p0 + w; p < p1; p += W) {
+    const int32_t i = srow[p];
+    const double sg = (double)sign[i];
+    for (int64_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += 16) a[col[q]] += sg * (double)val[q];
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+    double v = acc[j];
+    for (int u = 1; u < W; ++u) v += acc[(int64_t)u * d + j];
+    part[c * d + j] = v;
+  }
+}
+
+// SA row h = the bucket's chunk partials summed in chunk order (0 for an empty bucket)
+template <typename TO>
+__global__ __launch_bounds__(256) void k_cs_sum(const double* __restrict__ part,
+                                                const int64_t* __restrict__ cst, int64_t d,
+                                                TO* __restrict__ SA, int64_t ldsa) {
+  const int64_t h = blockIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (j >= ldsa) return;
+  double v = 0.0;
+  if (j < d)
+    for (int64_t c = cst[h]; c < cst[h + 1]; ++c) v += part[c * d + j];
+  if constexpr (std::is_same<TO, uint16_t>::value)
+    SA[h * ldsa + j] = f32_to_bf16_rne((float)v);
+  else
+    SA[h * ldsa + j] = (TO)v;
+}
+
+// row id of every stored entry, and the entries' positions
+__global__ __launch_bounds__(256) void k_expand_rows(const int64_t* __restrict__ rowptr, int64_t n,
+                                                     int32_t* __restrict__ rid) {
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n;
+       i += (int64_t)gridDim.x * 4)
+    for (int64_t q = rowptr[i] + (threadIdx.x & 63); q < rowptr[i + 1]; q += 64)
+      rid[q] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_iota(int64_t n, int64_t* __restrict__ v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    v[i] = i;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_csc(int64_t nnz, const int64_t* __restrict__ pos,
+                                                    const int32_t* __restrict__ rid,
+                                                    const T* __restrict__ val,
+                                                    int32_t* __restrict__ crow,
+                                                    T* __restrict__ cval) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nnz;
+       p += (int64_t)gridDim.x * 256) {
+    const int64_t q = pos[p];
+    crow[p] = rid[q];
+    cval[p] = val[q];
+  }
+}
+
+// R[i][k] = sum over row i of a_ij X[k][j] - b_i (FP64, interleaved so that the
+// column pass gathers a row's K residuals from one cache line), K <= 4: 16 lanes
+// per row stride its entries, then a fixed butterfly over the 16 lanes
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr_resid(const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val,
+                                                   const T* __restrict__ b, int64_t n, int64_t d,
+                                                   const double* __restrict__ X, int K,
+                                                   double* __restrict__ R,
+                                                   const int* __restrict__ status) {
+  if (status && *status != 0) return;
+  const int l = threadIdx.x & 15;
+  for (int64_t i0 = (int64_t)blockIdx.x * 16; i0 < n; i0 += (int64_t)gridDim.x * 16) {
+    const int64_t i = i0 + (threadIdx.x >> 4);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n)
+      for (int64_t q = rowptr[i] + l; q < rowptr[i + 1]; q += 16) {
+        const double a = (double)val[q];
+        const int32_t j = col[q];
+        for (int k = 0; k < K; ++k) s[k] += a * X[(int64_t)k * d + j];
+      }
+    for (int off = 8; off > 0; off >>= 1)
+      for (int k = 0; k < 4; ++k) s[k] += __shfl_xor(s[k], off, 16);
+    if (i < n && l == 0) {
+      const double bi = (double)b[i];
+      for (int k = 0; k < K; ++k) R[i * K + k] = s[k] - bi;
+    }
+  }
+}
+
+// A^T R over the column-major copy, each column cut into chunks of kAtrChunk
+// entries (ccst[j] = first chunk of column j): a block sums its chunk with a
+// fixed-shape tree into part[c][k]; the finish adds the chunks of a column in
+// order, G[k][j] = sum + nu2 X[k][j].
+constexpr int kAtrChunk = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_csc_partial(const int64_t* __restrict__ colptr,
+                                                     const int32_t* __restrict__ crow,
+                                                     const T* __restrict__ cval,
+                                                     const int64_t* __restrict__ ccst, int64_t n,
+                                                     int64_t d, const double* __restrict__ R,
+                                                     int K, double* __restrict__ part,
+                                                     const int* __restrict__ status) {
+  if (status && *status != 0) return;
+  __shared__ double sh[4][256];
+  const int64_t c = blockIdx.x;
+  if (c >= ccst[d]) return;
+  const int64_t j = upper_index(ccst, d + 1, c);
+  const int64_t q0 = colptr[j] + (c - ccst[j]) * kAtrChunk;
+  const int64_t q1 = min(colptr[j + 1], q0 + (int64_t)kAtrChunk);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+    const double a = (double)cval[q];
+    const int32_t i = crow[q];
+    for (int k = 0; k < K; ++k) s[k] += a * R[(int64_t)i * K + k];
+  }
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < K) part[c * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_csc_finish(const int64_t* __restrict__ ccst, int64_t d,
+                                                    const double* __restrict__ part, int K,
+                                                    double nu2, const double* __restrict__ X,
+                                                    double* __restrict__ G,
+                                                    const int* __restrict__ status) {
+  if (status && *status != 0) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)K * d) return;
+  const int64_t k = t / d, j = t - k * d;
+  double v = 0.0;
+  for (int64_t c = ccst[j]; c < ccst[j + 1]; ++c) v += part[c * 4 + k];
+  G[t] = v + nu2 * X[t];
+}
+
+static unsigned grid_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+}
+
+static int bits_for(uint64_t v) {  // bits to hold values 0..v
+  int b = 1;
+  while (b < 32 && (v >> b) != 0) ++b;
+  return b;
+}
+
+// stable sort of (key, value) pairs, scratch grown in place
+template <typename V>
+static rs_status radix_pairs(const uint32_t* kin, uint32_t* kout, const V* vin, V* vout, int64_t n,
+                             int end_bit, GrowBuf& tmp, hipStream_t s) {
+  size_t need = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, 0, end_bit,
+                                         s) != hipSuccess)
+    return set_error(RS_ERR_HIP, "sparse: radix sort sizing failed");
+  SP_TRY(tmp.ensure(need));
+  size_t have = tmp.bytes;
+  SP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, have, kin, kout, vin, vout, (int)n, 0, end_bit,
+                                            s));
+  return RS_OK;
+}
+
+// cst = exclusive prefix sum of the chunk counts of the nseg segments given by off
+// (cst[nseg] = total chunks)
+static rs_status chunk_starts(const int64_t* off, int64_t nseg, int64_t per, GrowBuf& nch,
+                              GrowBuf& cst, GrowBuf& tmp, hipStream_t s) {
+  SP_TRY(nch.ensure((size_t)(nseg + 1) * sizeof(int64_t)));
+  SP_TRY(cst.ensure((size_t)(nseg + 1) * sizeof(int64_t)));
+  hipLaunchKernelGGL(k_chunk_counts, dim3(grid_for(nseg + 1)), dim3(256), 0, s, off, nseg, per,
+                     nch.as<int64_t>());
+  size_t need = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, nch.as<int64_t>(), cst.as<int64_t>(),
+                                       (int)(nseg + 1), s) != hipSuccess)
+    return set_error(RS_ERR_HIP, "sparse: scan sizing failed");
+  SP_TRY(tmp.ensure(need));
+  size_t have = tmp.bytes;
+  SP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, have, nch.as<int64_t>(), cst.as<int64_t>(),
+                                          (int)(nseg + 1), s));
+  return check_launch("sparse chunks");
+}
+
+rs_status sparse_check(SparseWork& W, const SparseA& sp, hipStream_t s, int* bad_host) {
+  SP_TRY(W.flag.ensure(sizeof(int)));
+  SP_HIP(hipMemsetAsync(W.flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_csr_check, dim3(grid_for(std::max(sp.n, sp.nnz))), dim3(256), 0, s,
+                     sp.rowptr, sp.n, sp.col, sp.nnz, sp.d, W.flag.as<int>());
+  SP_TRY(check_launch("sparse check"));
+  SP_HIP(hipMemcpyAsync(bad_host, W.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  SP_HIP(hipStreamSynchronize(s));
+  return RS_OK;
+}
+
+rs_status sparse_to_csc(SparseWork& W, const SparseA& sp, hipStream_t s) {
+  const int64_t nnz = sp.nnz;
+  SP_TRY(W.ckey.ensure((size_t)nnz * sizeof(uint32_t) * 2));
+  SP_TRY(W.cpos.ensure((size_t)nnz * sizeof(int64_t) * 2));
+  SP_TRY(W.rid.ensure((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+  SP_TRY(W.crow.ensure((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+  SP_TRY(W.cval.ensure((size_t)std::max<int64_t>(nnz, 1) * value_size(sp.a_t)));
+  SP_TRY(W.colptr.ensure((size_t)(sp.d + 1) * sizeof(int64_t)));
+  uint32_t* k0 = W.ckey.as<uint32_t>();
+  uint32_t* k1 = k0 + nnz;
+  int64_t* p0 = W.cpos.as<int64_t>();
+  int64_t* p1 = p0 + nnz;
+  // column of every entry as the key, its position as the value
+  SP_HIP(hipMemcpyAsync(k0, sp.col, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, p0);
+  hipLaunchKernelGGL(k_expand_rows, dim3((unsigned)std::min<int64_t>((sp.n + 3) / 4, 65535)),
+                     dim3(256), 0, s, sp.rowptr, sp.n, W.rid.as<int32_t>());
+  SP_TRY(radix_pairs(k0, k1, p0, p1, nnz, bits_for((uint64_t)sp.d), W.tmp, s));
+  hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(nnz + 1)), dim3(256), 0, s, k1, nnz,
+                     (uint32_t)sp.d, W.colptr.as<int64_t>());
+  if (sp.a_t == RS_F32)
+    hipLaunchKernelGGL(k_gather_csc<float>, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, p1,
+                       W.rid.as<int32_t>(), reinterpret_cast<const float*>(sp.val),
+                       W.crow.as<int32_t>(), W.cval.as<float>());
+  else
+    hipLaunchKernelGGL(k_gather_csc<double>, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, p1,
+                       W.rid.as<int32_t>(), reinterpret_cast<const double*>(sp.val),
+                       W.crow.as<int32_t>(), W.cval.as<double>());
+  SP_TRY(check_launch("sparse csc"));
+  // chunks of the columns for the A^T r pass: at most nnz / kAtrChunk + d
+  W.atr_chunks = nnz / kAtrChunk + sp.d;
+  SP_TRY(W.cpart.ensure((size_t)W.atr_chunks * 4 * sizeof(double)));
+  return chunk_starts(W.colptr.as<int64_t>(), sp.d, kAtrChunk, W.cnch, W.ccst, W.tmp, s);
+}
+
+rs_status sparse_gradient(SparseWork& W, const SparseA& sp, const void* b, double nu2,
+                          const double* X, int K, double* G, const int* status, hipStream_t s,
+                          const double* sub) {
+  if (K < 1 || K > 4) return set_error(RS_ERR_ARG, "sparse gradient: k must be in 1..4");
+  if (sub) return set_error(RS_ERR_UNSUPPORTED, "sparse gradient: no subtracted vector");
+  SP_TRY(W.R.ensure((size_t)4 * sp.n * sizeof(double)));
+  double* R = W.R.as<double>();
+  const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sp.n + 15) / 16, 65536));
+  const unsigned cg = (unsigned)std::max<int64_t>(W.atr_chunks, 1);
+  const unsigned fg = (unsigned)(((int64_t)K * sp.d + 255) / 256);
+  if (sp.a_t == RS_F32) {
+    hipLaunchKernelGGL(k_csr_resid<float>, dim3(rg), dim3(256), 0, s, sp.rowptr, sp.col,
+                       reinterpret_cast<const float*>(sp.val), reinterpret_cast<const float*>(b),
+                       sp.n, sp.d, X, K, R, status);
+    hipLaunchKernelGGL(k_csc_partial<float>, dim3(cg), dim3(256), 0, s, W.colptr.as<int64_t>(),
+                       W.crow.as<int32_t>(), W.cval.as<float>(), W.ccst.as<int64_t>(), sp.n, sp.d,
+                       R, K, W.cpart.as<double>(), status);
+  } else {
+    hipLaunchKernelGGL(k_csr_resid<double>, dim3(rg), dim3(256), 0, s, sp.rowptr, sp.col,
+                       reinterpret_cast<const double*>(sp.val),
+                       reinterpret_cast<const double*>(b), sp.n, sp.d, X, K, R, status);
+    hipLaunchKernelGGL(k_csc_partial<double>, dim3(cg), dim3(256), 0, s, W.colptr.as<int64_t>(),
+                       W.crow.as<int32_t>(), W.cval.as<double>(), W.ccst.as<int64_t>(), sp.n, sp.d,
+                       R, K, W.cpart.as<double>(), status);
+  }
+  hipLaunchKernelGGL(k_csc_finish, dim3(fg), dim3(256), 0, s, W.ccst.as<int64_t>(), sp.d,
+                     W.cpart.as<double>(), K, nu2, X, G, status);
+  return check_launch("sparse gradient");
+}
+
+rs_status count_sketch_run(SparseWork& W, const SparseA& sp, int64_t m, uint64_t seed,
+                           uint32_t sid, void* SA, rs_dtype sa_t, int64_t ldsa, hipStream_t s) {
+  const int64_t n = sp.n;
+  if ((size_t)sp.d * sizeof(double) > 65536)
+    return set_error(RS_ERR_SHAPE, "count sketch: d above 8192");
+  SP_TRY(W.hkey.ensure((size_t)n * sizeof(uint32_t) * 2));
+  SP_TRY(W.hrow.ensure((size_t)n * sizeof(int32_t) * 2));
+  SP_TRY(W.hsign.ensure((size_t)n * sizeof(float)));
+  SP_TRY(W.hoff.ensure((size_t)(m + 1) * sizeof(int64_t)));
+  uint32_t* k0 = W.hkey.as<uint32_t>();
+  uint32_t* k1 = k0 + n;
+  int32_t* r0 = W.hrow.as<int32_t>();
+  int32_t* r1 = r0 + n;
+  hipLaunchKernelGGL(k_cs_hash, dim3(grid_for(n)), dim3(256), 0, s, n, seed, sid, (uint32_t)m, k0,
+                     r0, W.hsign.as<float>());
+  SP_TRY(radix_pairs(k0, k1, r0, r1, n, bits_for((uint64_t)(m - 1)), W.tmp, s));
+  hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(n + 1)), dim3(256), 0, s, k1, n,
+                     (uint32_t)m, W.hoff.as<int64_t>());
+  // chunks of the buckets: at most n / kCsChunk + m
+  SP_TRY(chunk_starts(W.hoff.as<int64_t>(), m, kCsChunk, W.hnch, W.hcst, W.tmp, s));
+  const int64_t chunks = n / kCsChunk + m;
+  SP_TRY(W.spart.ensure((size_t)chunks * sp.d * sizeof(double)));
+  // groups of 16 lanes, each with an FP64 LDS row: 64 KB of LDS at most
+  const int waves = (int)std::max<int64_t>(1, std::min<int64_t>(16, 8192 / sp.d));
+  const size_t lds = (size_t)waves * sp.d * sizeof(double);
+  if (sp.a_t == RS_F32)
+    hipLaunchKernelGGL(k_cs_partial<float>, dim3((unsigned)chunks), dim3(16 * waves), lds, s,
+                       sp.rowptr, sp.col, reinterpret_cast<const float*>(sp.val), r1,
+                       W.hsign.as<float>(), W.hoff.as<int64_t>(), W.hcst.as<int64_t>(), m, sp.d,
+                       waves, W.spart.as<double>());
+  else
+    hipLaunchKernelGGL(k_cs_partial<double>, dim3((unsigned)chunks), dim3(16 * waves), lds, s,
+                       sp.rowptr, sp.col, reinterpret_cast<const double*>(sp.val), r1,
+                       W.hsign.as<float>(), W.hoff.as<int64_t>(), W.hcst.as<int64_t>(), m, sp.d,
+                       waves, W.spart.as<double>());
+  const dim3 g2((unsigned)m, (unsigned)((ldsa + 255) / 256));
+#define RS_CS_SUM(TO)                                                                             \
+  hipLaunchKernelGGL((k_cs_sum<TO>), g2, dim3(256), 0, s, W.spart.as<double>(),                  \
+                     W.hcst.as<int64_t>(), sp.d, reinterpret_cast<TO*>(SA), ldsa)
+  if (sa_t == RS_F32) RS_CS_SUM(float);
+  else if (sa_t == RS_BF16 && sp.a_t == RS_F32) RS_CS_SUM(uint16_t);
+  else if (sa_t == RS_F64 && sp.a_t == RS_F64) RS_CS_SUM(double);
+  else return set_error(RS_ERR_UNSUPPORTED, "count sketch: sketch dtype not supported");
+#undef RS_CS_SUM
+  return check_launch("count sketch");
+}
+
+#undef SP_HIP
+#undef SP_TRY
+
+}  // namespace rs

@@ -169,6 +169,8 @@ struct DeviceScratch {
   DevBuf gpart;
   // dual problem: the data matrix A^T, a zero right-hand side, b in FP64
   DevBuf dM, dzero, dc;
+  // sparse A: its column-major copy, the gradient's residuals, the sketch's sort
+  SparseWork spw;
   // learned form: probe sketch and its factor, probe sums, features
   DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
   // nu grid: per-slot state, candidate blocks, multi-RHS products, batched
@@ -515,7 +517,8 @@ rs_status rs_profile_read(int64_t* launches, double* total_ms) {
 rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* out) {
   if (!out) return set_error(RS_ERR_ARG, "rs_params: out is null");
   double lam, Lam;
-  if (kind == RS_SKETCH_SRHT) {
+  if (kind == RS_SKETCH_SRHT || kind == RS_SKETCH_COUNT) {
+    // the CountSketch takes the SRHT's bounds (the paper gives none for it)
     if (!(rho > 0.0 && rho < 1.0)) return set_error(RS_ERR_ARG, "rs_params: SRHT needs rho in (0,1)");
     lam = 1.0 - std::sqrt(rho);
     Lam = 1.0 + std::sqrt(rho);
@@ -974,6 +977,8 @@ struct SolveJob {
   // the dual problem: A holds the data matrix A^T of the dual, b a zero vector,
   // and the gradient subtracts cvec (the primal b, FP64)
   const double* cvec = nullptr;
+  // sparse A (CSR, CountSketch): the gradient and the sketch take these instead
+  const SparseA* sp = nullptr;
 
   SolveJob() = default;
   SolveJob(const SolveJob&) = delete;
@@ -983,12 +988,17 @@ struct SolveJob {
       if (g) (void)hipGraphExecDestroy(g);
   }
 
+  rs_status grad(const double* Xin, int k, double* Gout, const int* st, hipStream_t s) {
+    if (sp) return sparse_gradient(S->spw, *sp, b, nu2, Xin, k, Gout, st, s, cvec);
+    return grad_any(*S, A, a_t, n, d, lda, b, nu2, Xin, k, Gout, st, s, cvec);
+  }
+
   // one step = the gradient pass over the candidates (left in X by the previous
   // decision, or by the start / resample kernels), the apply, and the decision,
   // which also writes the next step's candidates
   rs_status enqueue_steps(int q) {
     for (int it = 0; it < q; ++it) {
-      RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream, cvec));
+      RS_TRY(grad(X, K, G, status, stream));
       RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
       RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
                            gt, S->ev.as<int32_t>(), ev_cap, stream, true, snap()));
@@ -1023,7 +1033,10 @@ struct SolveJob {
   }
 
   rs_status validate() {
-    RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
+    if (!sp) RS_TRY(check_matrix(A, a_t, n, d, lda, "rs_adaptive_solve"));
+    if ((o.kind == RS_SKETCH_COUNT) != (sp != nullptr))
+      return set_error(RS_ERR_UNSUPPORTED,
+                       "rs_adaptive_solve: the CountSketch is for sparse A (and sparse A for it)");
     if (!b || !x || !info) return set_error(RS_ERR_ARG, "rs_adaptive_solve: null argument");
     if (n < d) return set_error(RS_ERR_SHAPE, "rs_adaptive_solve: needs n >= d");
     if (!(nu2 > 0.0) || !std::isfinite(nu2))
@@ -1063,6 +1076,8 @@ struct SolveJob {
     float* scl = sa_t == RS_FP8E4M3 ? S->sa_scale.as<float>() : nullptr;
     if (reuse)
       ;  // SA (and its FP8 column scales) already hold this sketch
+    else if (sp)  // nested: the same hash at 2m splits every bucket in two
+      RS_TRY(count_sketch_run(S->spw, *sp, mm, o.seed, id, S->sa.p, sa_t, ldsa, stream));
     else if (o.resample == RS_RESAMPLE_NESTED)
       RS_TRY(nested_sketch(*S, nc_shared ? *nc_shared : ncache, srht, A, a_t, n, d, lda, mm,
                            o.seed, id, S->sa.p, sa_t, ldsa, scl, stream));
@@ -1128,7 +1143,7 @@ struct SolveJob {
       RS_HIP(hipMemsetAsync(X + d, 0, (size_t)d * sizeof(double), S->aux));
       gin = X;
     }
-    RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, gin, cols, G, nullptr, S->aux, cvec));
+    RS_TRY(grad(gin, cols, G, nullptr, S->aux));
     RS_HIP(hipEventRecord(S->join_ev, S->aux));
     RS_TRY(sketch_and_factor(m, sid));
     RS_HIP(hipStreamWaitEvent(stream, S->join_ev, 0));
@@ -1256,6 +1271,49 @@ rs_status rs_adaptive_solve(const void* A, rs_dtype a_t, int64_t n, int64_t d, i
   RS_TRY(J.validate());
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> lock(S->mu);
+  J.S = S;
+  RS_TRY(J.begin());
+  while (!J.done) {
+    RS_HIP(hipEventSynchronize(S->done_ev));
+    const rs_status st = J.advance();
+    if (st != RS_OK && !J.done) return st;
+  }
+  return J.result;
+}
+
+rs_status rs_adaptive_solve_csr(const int64_t* rowptr, const int32_t* col, const void* val,
+                                rs_dtype a_t, int64_t n, int64_t d, int64_t nnz, const void* b,
+                                double nu2, const rs_solve_opts* opts, double* x,
+                                rs_solve_info* info, hipStream_t stream) {
+  if (!rowptr || !opts || !b || !x || !info || (nnz > 0 && (!col || !val)))
+    return set_error(RS_ERR_ARG, "rs_adaptive_solve_csr: null argument");
+  if (a_t != RS_F32 && a_t != RS_F64)
+    return set_error(RS_ERR_ARG, "rs_adaptive_solve_csr: values must be F32 or F64");
+  if (n < 1 || d < 1 || nnz < 0)
+    return set_error(RS_ERR_SHAPE, "rs_adaptive_solve_csr: empty matrix");
+  if (n >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31) || d > 8192)
+    return set_error(RS_ERR_SHAPE, "rs_adaptive_solve_csr: needs n, nnz < 2^31 and d <= 8192");
+  if (opts->kind != RS_SKETCH_COUNT)
+    return set_error(RS_ERR_UNSUPPORTED, "rs_adaptive_solve_csr: sparse A takes the CountSketch");
+  if (opts->sketch_dtype == RS_FP8E4M3)
+    return set_error(RS_ERR_UNSUPPORTED, "rs_adaptive_solve_csr: no FP8 CountSketch");
+  SparseA spa;
+  spa.rowptr = rowptr; spa.col = col; spa.val = val; spa.a_t = a_t;
+  spa.n = n; spa.d = d; spa.nnz = nnz;
+  SolveJob J;
+  J.a_t = a_t; J.n = n; J.d = d; J.lda = d; J.b = b; J.nu2 = nu2; J.x = x;
+  J.o = *opts; J.o.flags &= ~RS_SOLVE_GRAPH_STEPS; J.info = info; J.stream = stream;
+  J.sp = &spa;
+  RS_TRY(J.validate());
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> lock(S->mu);
+  int bad = 0;
+  RS_TRY(sparse_check(S->spw, spa, stream, &bad));
+  if (bad)
+    return set_error(RS_ERR_ARG,
+                     "rs_adaptive_solve_csr: rowptr must run from 0 to nnz without decreasing "
+                     "and columns must lie in [0, d)");
+  RS_TRY(sparse_to_csc(S->spw, spa, stream));
   J.S = S;
   RS_TRY(J.begin());
   while (!J.done) {

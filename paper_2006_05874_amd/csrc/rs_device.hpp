@@ -19,6 +19,7 @@ constexpr uint32_t kStreamSigns = 4;
 constexpr uint32_t kStreamRowKeys = 5;
 constexpr uint32_t kStreamGauss = 6;
 constexpr uint32_t kStreamProbe = 7;
+constexpr uint32_t kStreamCount = 8;
 
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll

@@ -130,6 +130,45 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
                           const double* X, int k, double* G, double* partial, int grid,
                           const int* status, hipStream_t s, const double* c = nullptr);
 
+// ---------------------------------------------------------------- sparse A (CSR)
+struct GrowBuf {  // grow-only device buffer released with its owner
+  void* p = nullptr;
+  size_t bytes = 0;
+  GrowBuf() = default;
+  GrowBuf(const GrowBuf&) = delete;
+  GrowBuf& operator=(const GrowBuf&) = delete;
+  ~GrowBuf() {
+    if (p) (void)hipFree(p);
+  }
+  rs_status ensure(size_t want);
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+struct SparseA {
+  const int64_t* rowptr = nullptr;  // n + 1 entries
+  const int32_t* col = nullptr;     // nnz column indices
+  const void* val = nullptr;        // nnz values (a_t)
+  rs_dtype a_t = RS_F32;
+  int64_t n = 0, d = 0, nnz = 0;
+};
+struct SparseWork {
+  GrowBuf ckey, cpos, rid, crow, cval, colptr, R, hkey, hrow, hsign, hoff, flag;
+  GrowBuf cnch, ccst, cpart;  // chunks of the columns (A^T r pass)
+  GrowBuf hnch, hcst, spart;  // chunks of the buckets (sketch)
+  GrowBuf tmp;
+  int64_t atr_chunks = 0;     // upper bound on the column chunks
+};
+// 0 when rowptr runs from 0 to nnz without decreasing and every column is in [0, d)
+rs_status sparse_check(SparseWork& W, const SparseA& sp, hipStream_t s, int* bad_host);
+rs_status sparse_to_csc(SparseWork& W, const SparseA& sp, hipStream_t s);
+rs_status sparse_gradient(SparseWork& W, const SparseA& sp, const void* b, double nu2,
+                          const double* X, int K, double* G, const int* status, hipStream_t s,
+                          const double* sub);
+rs_status count_sketch_run(SparseWork& W, const SparseA& sp, int64_t m, uint64_t seed,
+                           uint32_t sid, void* SA, rs_dtype sa_t, int64_t ldsa, hipStream_t s);
+
 // ---------------------------------------------------------------- dual (n < d)
 // M = A^T (d x ldm, padding columns zeroed); c = b in FP64; x = M z.
 rs_status dual_transpose(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, void* M,

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "ok", 1: "arg", 2: "shape", 3: "not_pow2", 4: "not_spd", 5: "
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
                 "fp8": torch.uint8}
-SKETCH = {"srht": 0, "gaussian": 1}
+SKETCH = {"srht": 0, "gaussian": 1, "count": 2}
 RESAMPLE = {"fresh": 0, "nested": 1}
 VARIANT = {"polyak": 0, "gd": 1}
 EVENT_NAMES = {0: "polyak", 1: "gd", 2: "double"}
@@ -83,7 +83,8 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_profile_enable", "rs_profile_read", "rs_features", "rs_mlp_forward",
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
-           "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs"]
+           "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs",
+           "rs_adaptive_solve_csr"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -143,6 +144,9 @@ def load(path=LIB_PATH):
                                          ctypes.POINTER(SolveInfo), vp]
     L.rs_refreshed_ihs.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, ctypes.POINTER(SolveOpts),
                                    vp, ctypes.POINTER(dbl), ctypes.POINTER(SolveInfo), vp]
+    L.rs_adaptive_solve_csr.argtypes = [vp, vp, vp, c_int, i64, i64, i64, vp, dbl,
+                                        ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo),
+                                        vp]
     L.rs_solve_path.argtypes = [vp, c_int, i64, i64, i64, vp, ctypes.POINTER(dbl), i64,
                                 ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp]
     L.rs_learned_solve_batch.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(SolveOpts),
@@ -158,7 +162,7 @@ def load(path=LIB_PATH):
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
                  "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual",
-                 "rs_refreshed_ihs"]:
+                 "rs_refreshed_ihs", "rs_adaptive_solve_csr"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -463,6 +467,29 @@ def rs_adaptive_solve_dual(A, b, nu2, kind="srht", variant="polyak", resample="f
                                        ctypes.byref(o), _ptr(z), _ptr(x), ctypes.byref(info),
                                        _stream())
     return x, z, _info(info, st, raise_on_error, "rs_adaptive_solve_dual")
+
+
+def rs_adaptive_solve_csr(rowptr, col, val, d, b, nu2, variant="polyak", resample="fresh",
+                          sketch_dtype=None, rho=0.1, m_init=1, m_max=0, tol=1e-7, max_iter=200,
+                          seed=0, check_every=4, x0=None, raise_on_error=True):
+    """Algorithm 1 with the CountSketch for a sparse A given as device CSR tensors
+    (rowptr int64 n + 1, col int32 nnz, val float32/float64 nnz).  Returns (x, info)."""
+    if rowptr.dtype != torch.int64 or col.dtype != torch.int32:
+        raise RsError(1, "rs_adaptive_solve_csr", "rowptr must be int64 and col int32")
+    if val.dtype not in (torch.float32, torch.float64) or b.dtype != val.dtype:
+        raise RsError(1, "rs_adaptive_solve_csr", "val and b must share float32 or float64")
+    a_t = 0 if val.dtype == torch.float64 else 1
+    n = rowptr.numel() - 1
+    o = _opts(a_t, "count", variant, resample, sketch_dtype, rho, 0.01, m_init, m_max, tol,
+              max_iter, seed, check_every)
+    x = (torch.zeros(d, dtype=torch.float64, device=val.device) if x0 is None
+         else x0.to(torch.float64).contiguous().clone())
+    info = SolveInfo()
+    st = load().rs_adaptive_solve_csr(_ptr(rowptr.contiguous()), _ptr(col.contiguous()),
+                                      _ptr(val.contiguous()), a_t, n, d, col.numel(),
+                                      _ptr(b.contiguous()), nu2, ctypes.byref(o), _ptr(x),
+                                      ctypes.byref(info), _stream())
+    return x, _info(info, st, raise_on_error, "rs_adaptive_solve_csr")
 
 
 def rs_refreshed_ihs(A, b, nu2, m, kind="srht", variant="gd", sketch_dtype=None, rho=0.1,

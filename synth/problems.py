@@ -167,3 +167,36 @@ def make_dual_problem(device, dtype=None, n=DUAL_N, d=DUAL_D, seed=23):
     """The wide problem of the dual form: 1024 x 65536 (the transpose of the
     headline shape), sigma_i = 1/i, noise 0.1."""
     return make_wide_problem_torch(n, d, spectrum("poly", n, 1.0), 0.1, seed, device, dtype=dtype)
+
+
+def make_sparse_problem(n, d, per_row, alpha, noise, seed, dtype=np.float32):
+    """A sparse CSR problem with power-law column popularity (text-like data):
+    each row draws per_row columns with P(j) proportional to (j + 1)^-alpha
+    (repeats within a row dropped), values N(0, 1) / sqrt(n); b = A x_pl + noise
+    * xi with x_pl ~ N(0, I_d).  Returns numpy (rowptr int64, col int32, val, b)."""
+    rng = np.random.default_rng(seed)
+    p = (np.arange(1, d + 1, dtype=np.float64)) ** (-alpha)
+    cdf = np.cumsum(p / p.sum())
+    cols = np.searchsorted(cdf, rng.random((n, per_row)), side="right").clip(0, d - 1)
+    cols.sort(axis=1)
+    keep = np.ones_like(cols, dtype=bool)
+    keep[:, 1:] = cols[:, 1:] != cols[:, :-1]
+    counts = keep.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    col = cols[keep].astype(np.int32)
+    val = (rng.standard_normal(col.size) / np.sqrt(n)).astype(dtype)
+    x_pl = rng.standard_normal(d)
+    Ax = np.zeros(n)
+    np.add.at(Ax, np.repeat(np.arange(n), counts), val.astype(np.float64) * x_pl[col])
+    b = (Ax + noise * rng.standard_normal(n)).astype(dtype)
+    return rowptr, col, val, b
+
+
+SPARSE_N, SPARSE_D, SPARSE_PER_ROW = 1 << 20, 1024, 16
+
+
+def config_sparse(seed=29):
+    """The sparse workload: 2^20 x 1024, 16 draws per row, alpha = 0.8, noise 0.1,
+    nu^2 = 0.1 (d_e about 105)."""
+    return make_sparse_problem(SPARSE_N, SPARSE_D, SPARSE_PER_ROW, 0.8, 0.1, seed), 0.1
