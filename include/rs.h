@@ -229,7 +229,7 @@ typedef struct {
   int32_t event_kind[RS_MAX_EVENTS];    /* RS_EVENT_* in order */
   int32_t event_t[RS_MAX_EVENTS];       /* step index t of each event */
   int64_t event_m[RS_MAX_EVENTS];       /* sketch size after the event */
-  double ms_sketch, ms_factor, ms_iterate; /* host-timed phases (0 unless timing enabled) */
+  double ms_sketch, ms_factor, ms_iterate; /* reserved (written as 0) */
 } rs_solve_info;
 
 /* Fill opts with the defaults listed above. */

@@ -26,7 +26,11 @@ static size_t value_size(rs_dtype t) { return t == RS_F64 ? 8 : 4; }
 
 rs_status GrowBuf::ensure(size_t want) {
   if (want <= bytes && p) return RS_OK;
-  if (p) (void)hipFree(p);
+  if (p) {
+    // work already queued may still read the old block
+    SP_HIP(hipDeviceSynchronize());
+    (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
   const size_t sz = want ? want : 256;
