@@ -335,15 +335,20 @@ rs_status sparse_to_csc(SparseWork& W, const SparseA& sp, hipStream_t s) {
   uint32_t* k1 = k0 + nnz;
   int64_t* p0 = W.cpos.as<int64_t>();
   int64_t* p1 = p0 + nnz;
-  // column of every entry as the key, its position as the value
-  SP_HIP(hipMemcpyAsync(k0, sp.col, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, p0);
-  hipLaunchKernelGGL(k_expand_rows, dim3((unsigned)std::min<int64_t>((sp.n + 3) / 4, 65535)),
-                     dim3(256), 0, s, sp.rowptr, sp.n, W.rid.as<int32_t>());
-  SP_TRY(radix_pairs(k0, k1, p0, p1, nnz, bits_for((uint64_t)sp.d), W.tmp, s));
+  // column of every entry as the key, its position as the value (no entries: every
+  // column is empty and only the offsets are written)
+  if (nnz > 0) {
+    SP_HIP(hipMemcpyAsync(k0, sp.col, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, p0);
+    hipLaunchKernelGGL(k_expand_rows, dim3((unsigned)std::min<int64_t>((sp.n + 3) / 4, 65535)),
+                       dim3(256), 0, s, sp.rowptr, sp.n, W.rid.as<int32_t>());
+    SP_TRY(radix_pairs(k0, k1, p0, p1, nnz, bits_for((uint64_t)sp.d), W.tmp, s));
+  }
   hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(nnz + 1)), dim3(256), 0, s, k1, nnz,
                      (uint32_t)sp.d, W.colptr.as<int64_t>());
-  if (sp.a_t == RS_F32)
+  if (nnz == 0)
+    ;
+  else if (sp.a_t == RS_F32)
     hipLaunchKernelGGL(k_gather_csc<float>, dim3(grid_for(nnz)), dim3(256), 0, s, nnz, p1,
                        W.rid.as<int32_t>(), reinterpret_cast<const float*>(sp.val),
                        W.crow.as<int32_t>(), W.cval.as<float>());

@@ -135,3 +135,15 @@ def test_dual_argument_errors(rs):
     with pytest.raises(rs.RsError) as e:
         rs.rs_adaptive_solve_dual(Aw, torch.zeros(20, dtype=torch.float64, device="cuda"), -1.0)
     assert e.value.name == "not_spd"
+
+
+def test_dual_single_row(rs):
+    # n = 1: the dual is a scalar problem, z* = b / (|a|^2 + nu^2)
+    A, b = wide(1, 333, 0.9, 2, np.float64)
+    # (r is quadratic in the error: a stop at 1e-24 leaves about 1e-12 relative in z)
+    x, z, info = rs.rs_adaptive_solve_dual(dev_padded(A, rs), torch.from_numpy(b).cuda(), 0.5,
+                                           tol=1e-24)
+    assert info["status"] == "ok"
+    zs = b[0] / (A[0] @ A[0] + 0.5)
+    np.testing.assert_allclose(host(z), [zs], rtol=1e-10)
+    np.testing.assert_allclose(host(x), A[0] * zs, rtol=1e-10, atol=1e-15)

@@ -120,3 +120,20 @@ def test_path_argument_errors(rs):
     assert e.value.name == "not_spd"
     X, infos = rs.rs_solve_path(A, b, [])
     assert X.shape == (0, 64) and infos == []
+
+
+def test_path_single_nu_and_warm_first_start(rs):
+    p = config_c1()
+    A = dev_padded(p.A, rs)
+    b = torch.from_numpy(p.b).cuda()
+    # one nu: the cold nested solve with the origin reference (same steps)
+    X, infos = rs.rs_solve_path(A, b, [p.nu2], seed=5)
+    x1, i1 = rs.rs_adaptive_solve(A, b, p.nu2, resample="nested", seed=5)
+    assert infos[0]["events"] == i1["events"]
+    # a nonzero first start: the oracle's warm solve from that point
+    xs = ridge.solve_direct(p.A, p.b, 0.1)
+    X2, inf2 = rs.rs_solve_path(A, b, [p.nu2, 1e-3], x0=torch.from_numpy(xs).cuda(), seed=5)
+    o = ihs.Options(resample="nested", ref_at_zero=True, seed=5)
+    xa, ia = ihs.adaptive_solve(p.A, p.b, p.nu2, o, x_init=xs)
+    assert inf2[0]["events"] == [e for e in ia.events if e[1] != "stop"]
+    np.testing.assert_allclose(host(X2[0]), xa, rtol=1e-8, atol=1e-12)

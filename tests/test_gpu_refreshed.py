@@ -61,3 +61,21 @@ def test_refreshed_fp32_ragged_and_cap(rs):
     x2, rh2, i2 = rs.rs_refreshed_ihs(A, b, p.nu2, 1024, tol=1e-9, max_iter=3,
                                       raise_on_error=False)
     assert i2["status"] == "no_convergence" and i2["steps"] == 3 and len(rh2) == 4
+
+
+def test_refreshed_edge_sizes(rs):
+    p = config_c1()
+    A = dev_padded(p.A, rs)
+    b = torch.from_numpy(p.b).cuda()
+    # m = 1: a rank-one sketch each step, still the oracle's history
+    x, rh, info = rs.rs_refreshed_ihs(A, b, p.nu2, 1, tol=1e-3, max_iter=30, seed=1,
+                                      raise_on_error=False)
+    xo, io = ihs.refreshed_ihs(p.A, p.b, p.nu2, 1, ihs.Options(tol=1e-3, max_iter=30, seed=1,
+                                                               variant="gd"))
+    assert info["status"] == io.status and len(rh) == len(io.r_history)
+    np.testing.assert_allclose(rh, io.r_history, rtol=1e-8)
+    # m above the padded n is clamped to it: every sketch is exact, delta falls by rho^2
+    x2, rh2, i2 = rs.rs_refreshed_ihs(A, b, p.nu2, 5000, tol=1e-8)
+    assert i2["m_final"] == 1024 and i2["status"] == "ok"
+    for r0, r1 in zip(rh2, rh2[1:]):
+        assert r1 / r0 == pytest.approx(0.01, rel=1e-6)

@@ -100,3 +100,25 @@ def test_sparse_malformed_csr_rejected(rs):
     with pytest.raises(rs.RsError) as e:
         rs.rs_adaptive_solve(A, *dev(b), 0.1, kind="count")
     assert e.value.name == "unsupported"
+
+
+def test_sparse_empty_rows_and_empty_matrix(rs):
+    # rows without entries (every third row emptied) still reach the solution
+    n, d = 3001, 40
+    rowptr, col, val, b = make_sparse_problem(n, d, 5, 0.5, 0.1, 8, dtype=np.float64)
+    keep = np.repeat(np.arange(n) % 3 != 0, np.diff(rowptr))
+    counts = np.where(np.arange(n) % 3 != 0, np.diff(rowptr), 0)
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp2[1:])
+    col2, val2 = col[keep], val[keep]
+    x, info = rs.rs_adaptive_solve_csr(*dev(rp2, col2, val2), d, *dev(b), 0.05, tol=1e-10, seed=2)
+    A = as_scipy(rp2, col2, val2, n, d)
+    xo, io = ihs.adaptive_solve_sparse(A, b, 0.05, ihs.Options(kind="count", tol=1e-10, seed=2))
+    assert info["events"] == [e for e in io.events if e[1] != "stop"]
+    np.testing.assert_allclose(host(x), xo, rtol=1e-8, atol=1e-12)
+    # no entries at all: A = 0, g(0) = 0, so x* = 0 and the solve stops at once
+    rp0 = np.zeros(n + 1, dtype=np.int64)
+    x0, i0 = rs.rs_adaptive_solve_csr(*dev(rp0), torch.zeros(0, dtype=torch.int32).cuda(),
+                                      torch.zeros(0, dtype=torch.float64).cuda(), d, *dev(b), 0.05)
+    assert i0["status"] == "ok" and i0["events"] == []
+    assert np.all(host(x0) == 0.0)
