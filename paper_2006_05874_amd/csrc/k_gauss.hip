@@ -22,6 +22,14 @@ __device__ __forceinline__ double gauss_at<double>(uint64_t seed, uint32_t sid, 
   return gauss_f64(seed, sid, idx);
 }
 
+// Output tile 64 x TD: every S slice drawn by a block serves TD columns of SA, so a
+// wider tile draws S fewer times (d / TD per slice).  FP32: 256 (512 halves the
+// occupancy and is slower); FP64: 128 (its accumulators are twice as large).
+template <typename T>
+struct GaussTile {
+  static constexpr int TD = sizeof(T) == 4 ? 256 : 128;
+};
+
 // Rows k_off .. m-1 of SA (earlier rows untouched).  With split > 0 the block
 // sums only A's rows [z * split, (z+1) * split) (z = blockIdx.z) and writes its
 // unscaled partial to P[z] (rows k - k_off, leading dimension d) instead.
@@ -32,21 +40,22 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
                                                       OutT* __restrict__ SA, int64_t ldsa,
                                                       int64_t k_off, int64_t split,
                                                       T* __restrict__ P) {
-  constexpr int TM = 64, TD = 128, KC = 16;
+  constexpr int TM = 64, TD = GaussTile<T>::TD, KC = 16;
+  constexpr int NB = TD / 32;  // 16-column tiles per wave (a wave owns 32 x TD / 2)
   __shared__ T Ss[KC][TM + 1];  // Ss[j][k] = S[k0 + k][j0 + j]
   __shared__ T As[KC][TD + 1];  // As[j][c] = A[j0 + j][c0 + c]
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;  // wave quadrant: 32 rows x 64 cols
+  const int wr = w >> 1, wc = w & 1;  // wave quadrant: 32 rows x TD / 2 cols
   const int64_t k0 = k_off + (int64_t)blockIdx.y * TM;
   const int64_t c0 = (int64_t)blockIdx.x * TD;
   using Acc4 = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
-  Acc4 acc[2][4];
+  Acc4 acc[2][NB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = Acc4{0, 0, 0, 0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = Acc4{0, 0, 0, 0};
 
   const int64_t jlo = split > 0 ? (int64_t)blockIdx.z * split : 0;
   const int64_t jhi = split > 0 ? (jlo + split < n ? jlo + split : n) : n;
@@ -61,8 +70,8 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
       Ss[jj][kk] = v;
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {  // A slice: 16 x 128
-      const int idx = t * 8 + e;
+    for (int e = 0; e < KC * TD / 256; ++e) {  // A slice: 16 x TD
+      const int idx = t * (KC * TD / 256) + e;
       const int jj = idx / TD, cc = idx % TD;
       const int64_t j = j0 + jj, c = c0 + cc;
       As[jj][cc] = (j < jhi && c < d) ? A[j * lda + c] : (T)0;
@@ -75,8 +84,8 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
       for (int a = 0; a < 2; ++a) {
         const T av = Ss[kr][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const T bv = As[kr][wc * 64 + b * 16 + (lane & 15)];
+        for (int b = 0; b < NB; ++b) {
+          const T bv = As[kr][wc * (TD / 2) + b * 16 + (lane & 15)];
           if constexpr (sizeof(T) == 4)
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
           else
@@ -89,11 +98,11 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(const T* __restrict__ A, i
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t k = k0 + wr * 32 + a * 16 + mfma16_row<T>(lane, r);
-        const int64_t c = c0 + wc * 64 + b * 16 + (lane & 15);
+        const int64_t c = c0 + wc * (TD / 2) + b * 16 + (lane & 15);
         if (k < m && c < d) {
           if (split > 0) {
             P[((int64_t)blockIdx.z * (m - k_off) + (k - k_off)) * d + c] = acc[a][b][r];
@@ -128,15 +137,16 @@ __global__ __launch_bounds__(256) void k_gauss_reduce(const T* __restrict__ P, i
 
 // Splits of the summed dimension (A's rows) so that the launch fills the chip
 // when m is small; the partials go through P (gauss_split_bytes of scratch).
-static int gauss_splits(int64_t n, int64_t d, int64_t rows) {
-  const int64_t tiles = ((d + 127) / 128) * ((rows + 63) / 64);
+static int gauss_splits(int64_t n, int64_t d, int64_t rows, int td) {
+  const int64_t tiles = ((d + td - 1) / td) * ((rows + 63) / 64);
   int64_t z = (2 * device_cus() + tiles - 1) / tiles;
   z = std::max<int64_t>(1, std::min<int64_t>(z, (n + 1023) / 1024));
   return (int)std::min<int64_t>(z, 64);
 }
 
 size_t gauss_split_bytes(int64_t n, int64_t d, int64_t rows, rs_dtype a_t) {
-  const int z = gauss_splits(n, d, rows);
+  const int z = gauss_splits(n, d, rows, a_t == RS_F64 ? GaussTile<double>::TD
+                                                      : GaussTile<float>::TD);
   return z > 1 ? (size_t)z * rows * d * (a_t == RS_F64 ? 8 : 4) : 0;
 }
 
@@ -145,18 +155,19 @@ static void gauss_go(const T* A, int64_t n, int64_t d, int64_t lda, int64_t m, u
                      uint32_t sid, double scale, OutT* SA, int64_t ldsa, int64_t k_off,
                      void* part, size_t part_bytes, hipStream_t s) {
   const int64_t rows = m - k_off;
-  const int z = gauss_splits(n, d, rows);
+  constexpr int TD = GaussTile<T>::TD;
+  const int z = gauss_splits(n, d, rows, TD);
   const size_t need = (size_t)z * rows * d * sizeof(T);
   if (z > 1 && part && part_bytes >= need) {
     const int64_t split = ((n + z - 1) / z + 15) / 16 * 16;
     const unsigned nz = (unsigned)((n + split - 1) / split);
-    const dim3 grid((unsigned)((d + 127) / 128), (unsigned)((rows + 63) / 64), nz);
+    const dim3 grid((unsigned)((d + TD - 1) / TD), (unsigned)((rows + 63) / 64), nz);
     hipLaunchKernelGGL((k_gauss_sketch<T, OutT>), grid, dim3(256), 0, s, A, n, d, lda, m, seed,
                        sid, scale, SA, ldsa, k_off, split, reinterpret_cast<T*>(part));
     hipLaunchKernelGGL((k_gauss_reduce<T, OutT>), dim3((unsigned)rows), dim3(256), 0, s,
                        reinterpret_cast<const T*>(part), (int)nz, rows, d, k_off, scale, SA, ldsa);
   } else {
-    const dim3 grid((unsigned)((d + 127) / 128), (unsigned)((rows + 63) / 64));
+    const dim3 grid((unsigned)((d + TD - 1) / TD), (unsigned)((rows + 63) / 64));
     hipLaunchKernelGGL((k_gauss_sketch<T, OutT>), grid, dim3(256), 0, s, A, n, d, lda, m, seed,
                        sid, scale, SA, ldsa, k_off, (int64_t)0, (T*)nullptr);
   }
