@@ -652,7 +652,15 @@ def run_path(args):
         out[name] = {"solves_per_s": round(len(nus) / sec, 2), "ms_per_path": round(sec * 1e3, 3),
                      "res": res}
         print(f"[path] {name}: {sec * 1e3:.2f} ms per path", file=sys.stderr, flush=True)
+    roof = gradient_roofline(rs, path("f32"), n * d * 4 + n * 4,
+                             "k_grad_partial (A^T(AX-b) pass)", "one more path_warm_f32 path")
     G, Atb = oracle_gram_chunks(A, b)
+    A64 = A.cpu().numpy().astype(np.float64)
+    b64 = b.cpu().numpy().astype(np.float64)
+    cpu = oracle_rate([lambda nu=nu: ridge.solve_direct(A64, b64, nu) for nu in nus],
+                      f"oracle direct FP64 Cholesky solves of the full {n}x{d} problem at the "
+                      "path's nu^2 (the oracle's path itself forms dense Hadamard sketches)")
+    del A64
     for name in out:
         res = out[name].pop("res")
         worst = 0.0
@@ -677,6 +685,7 @@ def run_path(args):
                        "n": n, "d": d},
             "verified": all(v["worst_rel_pred_err"] <= 1e-9 and v["not_ok"] == 0
                             for v in out.values()),
+            "roofline": roof, "cpu_baseline": cpu,
             "modes": out}
     if "cold_f32" in out:
         line["speedup_vs_cold_f32"] = round(out[best]["solves_per_s"]
@@ -718,9 +727,18 @@ def run_dual(args):
         out[f"dual_{sd}"] = {"solves_per_s": round(len(nus) / sec, 2),
                              "ms_per_solve": round(sec * 1e3 / len(nus), 3), "res": res}
         print(f"[dual] {sd}: {len(nus) / sec:.1f} solves/s", file=sys.stderr, flush=True)
+    roof = gradient_roofline(
+        rs, lambda: [rs.rs_adaptive_solve_dual(A, b, nu, sketch_dtype="f32", tol=tol,
+                                               raise_on_error=False) for nu in nus],
+        d * n * 4 + d * 4, "k_grad_partial over A^T (the dual's A A^T z pass)",
+        "the dual_f32 solves repeated")
     # oracle: z* = (A A^T + nu^2 I)^-1 b in FP64 on the host, x* = A^T z*
+    from oracle import ridge
     A64 = A.cpu().numpy().astype(np.float64)
     b64 = b.cpu().numpy().astype(np.float64)
+    cpu = oracle_rate([lambda nu=nu: A64.T @ ridge.solve_dual_direct(A64, b64, nu) for nu in nus],
+                      f"oracle direct FP64 dual solves z* = (A A^T + nu^2 I)^-1 b, x* = A^T z* "
+                      f"of the full {n}x{d} problem")
     K = A64 @ A64.T
     for name in out:
         res = out[name].pop("res")
@@ -747,8 +765,47 @@ def run_dual(args):
                        "n": n, "d": d},
             "verified": all(v["worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
                             for v in out.values()),
+            "roofline": roof, "cpu_baseline": cpu,
             "modes": out}
     print(json.dumps(line))
+
+
+def gradient_roofline(rs, fn, alg_bytes, kernel, region):
+    """Repeat fn with every gradient pass timed by HIP events on its own stream
+    (rs_profile_enable); the roofline of the pass from its average duration."""
+    import torch
+    torch.cuda.synchronize()
+    rs.rs_profile_enable(True)
+    rs.rs_profile_read()
+    fn()
+    torch.cuda.synchronize()
+    rs.rs_profile_enable(False)
+    n, ms = rs.rs_profile_read()
+    us = ms / max(n, 1) * 1e3
+    ach = alg_bytes / (us / 1e6) / 1e9 if us > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes": int(alg_bytes), "kernel": kernel, "avg_launch_us": round(us, 2),
+            "launches": n, "region": region + "; each pass timed by its own HIP start/stop "
+                                              "events; no counter passes taken for this workload"}
+
+
+def oracle_rate(calls, sample, budget_s=10.0):
+    """The oracle's direct solves timed on the host: the calls in turn, repeated while
+    under budget_s (at least one)."""
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        for c in calls:
+            c()
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(done / dt, 4), "unit": "solves/s", "cores": blas_threads(),
+            "kind": "oracle", "sample": f"{sample}; {done} solves in {dt:.1f} s"}
 
 
 def run_refreshed(args):
@@ -798,6 +855,13 @@ def run_refreshed(args):
                     "rel_pred_err": ridge.relative_error(H, x.cpu().numpy(), xs)}
                 print(f"[refreshed] {kind} {variant} {name}: {sec * 1e3:.2f} ms, "
                       f"{info['steps']} steps", file=sys.stderr, flush=True)
+    roof = gradient_roofline(
+        rs, lambda: rs.rs_refreshed_ihs(A, b, p.nu2, m, kind="srht", variant="gd", tol=tol,
+                                        raise_on_error=False),
+        n * d * 4 + n * 4, "k_grad_partial (A^T(AX-b) pass)", "one more SRHT gd refreshed solve")
+    A64, b64 = p.A.astype(np.float64), p.b.astype(np.float64)
+    cpu = oracle_rate([lambda: ridge.solve_direct(A64, b64, p.nu2)],
+                      f"oracle direct FP64 Cholesky solve of the full {n}x{d} problem")
     best = "srht_gd_refreshed"
     line = {"metric": "ridge solves/s to eps = 1e-10, refreshed-embedding IHS (ablation)",
             "value": round(1e3 / out[best]["ms_per_solve"], 2), "unit": "solves/s",
@@ -809,6 +873,7 @@ def run_refreshed(args):
                                    "refreshed vs fixed sketch, eps=1e-10", "n": n, "d": d},
             "verified": all(v["rel_pred_err"] <= 1e-8 and v["status"] == "ok"
                             for v in out.values()),
+            "roofline": roof, "cpu_baseline": cpu,
             "modes": out}
     print(json.dumps(line))
 
@@ -857,7 +922,20 @@ def run_sparse(args):
                      "status": info["status"], "x": x.cpu().numpy()}
         print(f"[sparse] {name}: {sec * 1e3:.2f} ms, m = {info['m_final']}", file=sys.stderr,
               flush=True)
+    nnz = int(rowptr[-1])
+    # per pass (2 right-hand sides): indices and values twice (rows, then columns),
+    # rowptr and b, the residuals written once and read once
+    roof = gradient_roofline(rs, csr("f32"), 2 * nnz * (4 + 4) + n * (8 + 4) + 2 * n * 2 * 8,
+                             "sparse gradient pass (k_csr_resid .. k_csc_finish)",
+                             "one more count_f32 solve")
     A = sp.csr_matrix((val.astype(np.float64), col, rowptr), shape=(n, d))
+    b64 = b.astype(np.float64)
+
+    def direct():
+        Gs = (A.T @ A).toarray()
+        return ridge.solve_direct_from_gram(Gs, A.T @ b64, nu2)
+    cpu = oracle_rate([direct], f"oracle direct FP64 solve from the sparse Gram of the full "
+                                f"{n}x{d} CSR problem (scipy sparse product, Cholesky)")
     G = (A.T @ A).toarray()
     xs = ridge.solve_direct_from_gram(G, A.T @ b.astype(np.float64), nu2)
     for v in out.values():
@@ -873,6 +951,7 @@ def run_sparse(args):
                                    "eps=1e-10", "n": n, "d": d, "nnz": int(rowptr[-1])},
             "verified": all(v["rel_pred_err"] <= 1e-8 and v["status"] == "ok"
                             for v in out.values()),
+            "roofline": roof, "cpu_baseline": cpu,
             "modes": out,
             "speedup_vs_dense_srht_f32": round(out[best]["solves_per_s"]
                                                / out["dense_srht_f32"]["solves_per_s"], 3)}

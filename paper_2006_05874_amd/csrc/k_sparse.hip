@@ -196,8 +196,10 @@ __global__ __launch_bounds__(256) void k_csr_resid(const int64_t* __restrict__ r
                                                    const T* __restrict__ b, int64_t n, int64_t d,
                                                    const double* __restrict__ X, int K,
                                                    double* __restrict__ R,
-                                                   const int* __restrict__ status) {
+                                                   const int* __restrict__ status,
+                                                   int* __restrict__ ran) {
   if (status && *status != 0) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
   const int l = threadIdx.x & 15;
   for (int64_t i0 = (int64_t)blockIdx.x * 16; i0 < n; i0 += (int64_t)gridDim.x * 16) {
     const int64_t i = i0 + (threadIdx.x >> 4);
@@ -373,23 +375,26 @@ rs_status sparse_gradient(SparseWork& W, const SparseA& sp, const void* b, doubl
   const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sp.n + 15) / 16, 65536));
   const unsigned cg = (unsigned)std::max<int64_t>(W.atr_chunks, 1);
   const unsigned fg = (unsigned)(((int64_t)K * sp.d + 255) / 256);
+  // the pass is timed from the row kernel's start to the finish kernel's stop when
+  // profiling is on
+  const ProfSlot ps = prof_begin();
   if (sp.a_t == RS_F32) {
-    hipLaunchKernelGGL(k_csr_resid<float>, dim3(rg), dim3(256), 0, s, sp.rowptr, sp.col,
-                       reinterpret_cast<const float*>(sp.val), reinterpret_cast<const float*>(b),
-                       sp.n, sp.d, X, K, R, status);
+    launch_timed(k_csr_resid<float>, dim3(rg), dim3(256), s, ps.begin, nullptr, sp.rowptr, sp.col,
+                 reinterpret_cast<const float*>(sp.val), reinterpret_cast<const float*>(b), sp.n,
+                 sp.d, X, K, R, status, ps.ran);
     hipLaunchKernelGGL(k_csc_partial<float>, dim3(cg), dim3(256), 0, s, W.colptr.as<int64_t>(),
                        W.crow.as<int32_t>(), W.cval.as<float>(), W.ccst.as<int64_t>(), sp.n, sp.d,
                        R, K, W.cpart.as<double>(), status);
   } else {
-    hipLaunchKernelGGL(k_csr_resid<double>, dim3(rg), dim3(256), 0, s, sp.rowptr, sp.col,
-                       reinterpret_cast<const double*>(sp.val),
-                       reinterpret_cast<const double*>(b), sp.n, sp.d, X, K, R, status);
+    launch_timed(k_csr_resid<double>, dim3(rg), dim3(256), s, ps.begin, nullptr, sp.rowptr,
+                 sp.col, reinterpret_cast<const double*>(sp.val),
+                 reinterpret_cast<const double*>(b), sp.n, sp.d, X, K, R, status, ps.ran);
     hipLaunchKernelGGL(k_csc_partial<double>, dim3(cg), dim3(256), 0, s, W.colptr.as<int64_t>(),
                        W.crow.as<int32_t>(), W.cval.as<double>(), W.ccst.as<int64_t>(), sp.n, sp.d,
                        R, K, W.cpart.as<double>(), status);
   }
-  hipLaunchKernelGGL(k_csc_finish, dim3(fg), dim3(256), 0, s, W.ccst.as<int64_t>(), sp.d,
-                     W.cpart.as<double>(), K, nu2, X, G, status);
+  launch_timed(k_csc_finish, dim3(fg), dim3(256), s, nullptr, ps.end, W.ccst.as<int64_t>(), sp.d,
+               (const double*)W.cpart.as<double>(), K, nu2, X, G, status);
   return check_launch("sparse gradient");
 }
 
