@@ -51,7 +51,8 @@ def test_version_string(lib):
 
 
 @pytest.mark.parametrize("kind,rho,eta", [("srht", 0.1, 0.01), ("srht", 0.37, 0.01),
-                                          ("gaussian", 0.1, 0.01), ("gaussian", 0.18, 0.004)])
+                                          ("gaussian", 0.1, 0.01), ("gaussian", 0.18, 0.004),
+                                          ("count", 0.1, 0.01)])
 def test_params_match_oracle(lib, kind, rho, eta):
     from paper_2006_05874_amd import rs
     got = rs.rs_params(kind, rho, eta)
@@ -145,3 +146,53 @@ def test_batch_and_grid_argument_errors_before_device_work(lib):
     plan = (ctypes.c_int32 * 4)()
     assert lib.rs_gradient_plan(1, 100, 10, 0, ctypes.cast(plan, vp)) == 2
     assert lib.rs_gradient_plan(2, 100, 10, 1, ctypes.cast(plan, vp)) == 1
+
+
+def test_next_forms_argument_errors_before_device_work(lib):
+    from paper_2006_05874_amd import rs
+    vp = ctypes.c_void_p
+    o = rs.SolveOpts()
+    lib.rs_solve_opts_default(ctypes.byref(o))
+    infos = (rs.SolveInfo * 3)()
+    info = rs.SolveInfo()
+    # path: nu^2 increasing (arg), not positive (not_spd), empty (nothing to do)
+    nu = (ctypes.c_double * 3)(1e-2, 1e-1, 1e-3)
+    assert lib.rs_solve_path(vp(256), 1, 100, 10, 12, vp(256), nu, 3, ctypes.byref(o), vp(256),
+                             infos, vp(0)) == 1
+    nu = (ctypes.c_double * 3)(1e-2, -1.0, 1e-3)
+    assert lib.rs_solve_path(vp(256), 1, 100, 10, 12, vp(256), nu, 3, ctypes.byref(o), vp(256),
+                             infos, vp(0)) == 4
+    assert lib.rs_solve_path(vp(256), 1, 100, 10, 12, vp(256), nu, 0, ctypes.byref(o), vp(256),
+                             infos, vp(0)) == 0
+    # dual: a tall matrix (shape), a null output (arg)
+    assert lib.rs_adaptive_solve_dual(vp(256), 1, 100, 10, 12, vp(256), 0.1, ctypes.byref(o),
+                                      vp(256), vp(256), ctypes.byref(info), vp(0)) == 2
+    assert lib.rs_adaptive_solve_dual(vp(256), 1, 10, 100, 100, vp(256), 0.1, ctypes.byref(o),
+                                      vp(256), None, ctypes.byref(info), vp(0)) == 1
+    # CSR: the CountSketch is required (unsupported otherwise), d above 8192 (shape),
+    # n < d (shape), null rowptr (arg), an FP8 CountSketch (unsupported)
+    assert lib.rs_adaptive_solve_csr(vp(256), vp(256), vp(256), 1, 100, 10, 50, vp(256), 0.1,
+                                     ctypes.byref(o), vp(256), ctypes.byref(info), vp(0)) == 9
+    o.kind = 2
+    assert lib.rs_adaptive_solve_csr(vp(256), vp(256), vp(256), 1, 100000, 9000, 50, vp(256), 0.1,
+                                     ctypes.byref(o), vp(256), ctypes.byref(info), vp(0)) == 2
+    assert lib.rs_adaptive_solve_csr(vp(256), vp(256), vp(256), 1, 10, 100, 50, vp(256), 0.1,
+                                     ctypes.byref(o), vp(256), ctypes.byref(info), vp(0)) == 2
+    assert lib.rs_adaptive_solve_csr(None, vp(256), vp(256), 1, 100, 10, 50, vp(256), 0.1,
+                                     ctypes.byref(o), vp(256), ctypes.byref(info), vp(0)) == 1
+    o.sketch_dtype = 3
+    assert lib.rs_adaptive_solve_csr(vp(256), vp(256), vp(256), 1, 100, 10, 50, vp(256), 0.1,
+                                     ctypes.byref(o), vp(256), ctypes.byref(info), vp(0)) == 9
+    # the dense solvers refuse the CountSketch
+    o.sketch_dtype = 1
+    assert lib.rs_adaptive_solve(vp(256), 1, 64, 16, 16, vp(256), 0.1, ctypes.byref(o), vp(256),
+                                 ctypes.byref(info), vp(0)) == 9
+    # refreshed: nu^2 not positive, n < d
+    lib.rs_solve_opts_default(ctypes.byref(o))
+    rh = (ctypes.c_double * 8)()
+    assert lib.rs_refreshed_ihs(vp(256), 1, 64, 16, 16, vp(256), 0.0, ctypes.byref(o), vp(256), rh,
+                                ctypes.byref(info), vp(0)) == 4
+    assert lib.rs_refreshed_ihs(vp(256), 1, 8, 16, 16, vp(256), 0.1, ctypes.byref(o), vp(256), rh,
+                                ctypes.byref(info), vp(0)) == 2
+    # rs_params: the CountSketch takes the SRHT's parameters
+    assert rs.rs_params("count", 0.25, 0.01) == rs.rs_params("srht", 0.25, 0.01)
