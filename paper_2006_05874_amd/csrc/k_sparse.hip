@@ -128,10 +128,42 @@ __global__ __launch_bounds__(256) void k_cs_partial(const int64_t* __restrict__ 
   for (int64_t j = threadIdx.x; j < (int64_t)W * d; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   double* a = acc + (int64_t)w * d;
-  for (int64_t p = p0 + w; p < p1; p += W) {
-    const int32_t i = srow[p];
-    const double sg = (double)sign[i];
-    for (int64_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += 16) a[col[q]] += sg * (double)val[q];
+  // the group's rows p0 + w, p0 + w + W, ...: each lane fetches one row's id, sign
+  // and bounds (16 rows at a time), then the rows' first 16 entries are loaded four
+  // rows at a time before they are added, row after row (a row's remaining entries
+  // right after its first 16), so the sums keep a fixed order
+  for (int64_t pb = p0 + w; pb < p1; pb += (int64_t)W * 16) {
+    const int64_t pl = pb + (int64_t)lane * W;
+    long long rb = 0, re = 0;
+    double sg = 0.0;
+    if (pl < p1) {
+      const int32_t i = srow[pl];
+      sg = (double)sign[i];
+      rb = rowptr[i];
+      re = rowptr[i + 1];
+    }
+    const int nrow = (int)min<int64_t>(16, (p1 - pb + W - 1) / W);
+    for (int r0 = 0; r0 < nrow; r0 += 4) {
+      int32_t cc[4];
+      double vv[4], su[4];
+      long long qb[4], qe[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        qb[u] = __shfl(rb, r0 + u, 16);
+        qe[u] = __shfl(re, r0 + u, 16);
+        su[u] = __shfl(sg, r0 + u, 16);
+        const long long q = qb[u] + lane;
+        const bool on = r0 + u < nrow && q < qe[u];
+        cc[u] = on ? col[q] : -1;
+        vv[u] = on ? su[u] * (double)val[q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (r0 + u >= nrow) break;
+        if (cc[u] >= 0) a[cc[u]] += vv[u];
+        for (long long q = qb[u] + 16 + lane; q < qe[u]; q += 16) a[col[q]] += su[u] * (double)val[q];
+      }
+    }
   }
   __syncthreads();
   for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
@@ -141,21 +173,31 @@ __global__ __launch_bounds__(256) void k_cs_partial(const int64_t* __restrict__ 
   }
 }
 
-// SA row h = the bucket's chunk partials summed in chunk order (0 for an empty bucket)
+// SA row h = the sum of the bucket's chunk partials (0 for an empty bucket).  A block
+// covers 16 columns with 16 chunk lanes: lane z adds chunks z, z + 16, ... in order
+// and the 16 sums are added in lane order, so a bucket with many chunks (small m)
+// still spreads over 256 threads.
 template <typename TO>
 __global__ __launch_bounds__(256) void k_cs_sum(const double* __restrict__ part,
                                                 const int64_t* __restrict__ cst, int64_t d,
                                                 TO* __restrict__ SA, int64_t ldsa) {
+  __shared__ double sh[16][17];
   const int64_t h = blockIdx.x;
-  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  if (j >= ldsa) return;
+  const int cl = threadIdx.x & 15, z = threadIdx.x >> 4;
+  const int64_t j = (int64_t)blockIdx.y * 16 + cl;
   double v = 0.0;
   if (j < d)
-    for (int64_t c = cst[h]; c < cst[h + 1]; ++c) v += part[c * d + j];
-  if constexpr (std::is_same<TO, uint16_t>::value)
-    SA[h * ldsa + j] = f32_to_bf16_rne((float)v);
-  else
-    SA[h * ldsa + j] = (TO)v;
+    for (int64_t c = cst[h] + z; c < cst[h + 1]; c += 16) v += part[c * d + j];
+  sh[z][cl] = v;
+  __syncthreads();
+  if (z == 0 && j < ldsa) {
+    double t = sh[0][cl];
+    for (int u = 1; u < 16; ++u) t += sh[u][cl];
+    if constexpr (std::is_same<TO, uint16_t>::value)
+      SA[h * ldsa + j] = f32_to_bf16_rne((float)t);
+    else
+      SA[h * ldsa + j] = (TO)t;
+  }
 }
 
 // row id of every stored entry, and the entries' positions
@@ -433,7 +475,7 @@ rs_status count_sketch_run(SparseWork& W, const SparseA& sp, int64_t m, uint64_t
                        sp.rowptr, sp.col, reinterpret_cast<const double*>(sp.val), r1,
                        W.hsign.as<float>(), W.hoff.as<int64_t>(), W.hcst.as<int64_t>(), m, sp.d,
                        waves, W.spart.as<double>());
-  const dim3 g2((unsigned)m, (unsigned)((ldsa + 255) / 256));
+  const dim3 g2((unsigned)m, (unsigned)((ldsa + 15) / 16));
 #define RS_CS_SUM(TO)                                                                             \
   hipLaunchKernelGGL((k_cs_sum<TO>), g2, dim3(256), 0, s, W.spart.as<double>(),                  \
                      W.hcst.as<int64_t>(), sp.d, reinterpret_cast<TO*>(SA), ldsa)
