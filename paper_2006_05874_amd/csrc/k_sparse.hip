@@ -283,10 +283,27 @@ __global__ __launch_bounds__(256) void k_csc_partial(const int64_t* __restrict__
   const int64_t q0 = colptr[j] + (c - ccst[j]) * kAtrChunk;
   const int64_t q1 = min(colptr[j + 1], q0 + (int64_t)kAtrChunk);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
-    const double a = (double)cval[q];
-    const int32_t i = crow[q];
-    for (int k = 0; k < K; ++k) s[k] += a * R[(int64_t)i * K + k];
+  // four entries per thread at a time: their rows and values, then the residual
+  // gathers, then the products in entry order
+  for (int64_t qb = q0 + threadIdx.x; qb < q1; qb += 4 * 256) {
+    int32_t ii[4];
+    double aa[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t q = qb + (int64_t)u * 256;
+      ii[u] = q < q1 ? crow[q] : -1;
+      aa[u] = q < q1 ? (double)cval[q] : 0.0;
+    }
+    double rr[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        rr[u][k] = (ii[u] >= 0 && k < K) ? R[(int64_t)ii[u] * K + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] += aa[u] * rr[u][k];
   }
   for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = s[k];
   __syncthreads();
