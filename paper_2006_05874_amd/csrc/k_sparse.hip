@@ -230,7 +230,8 @@ __global__ __launch_bounds__(256) void k_gather_csc(int64_t nnz, const int64_t* 
 
 // R[i][k] = sum over row i of a_ij X[k][j] - b_i (FP64, interleaved so that the
 // column pass gathers a row's K residuals from one cache line), K <= 4: 16 lanes
-// per row stride its entries, then a fixed butterfly over the 16 lanes
+// per row stride its entries, then a fixed butterfly over the 16 lanes.  A group
+// takes two rows at a time (i and i + 16) with their loads issued together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_csr_resid(const int64_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
@@ -243,20 +244,40 @@ __global__ __launch_bounds__(256) void k_csr_resid(const int64_t* __restrict__ r
   if (status && *status != 0) return;
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
   const int l = threadIdx.x & 15;
-  for (int64_t i0 = (int64_t)blockIdx.x * 16; i0 < n; i0 += (int64_t)gridDim.x * 16) {
-    const int64_t i = i0 + (threadIdx.x >> 4);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < n)
-      for (int64_t q = rowptr[i] + l; q < rowptr[i + 1]; q += 16) {
-        const double a = (double)val[q];
-        const int32_t j = col[q];
-        for (int k = 0; k < K; ++k) s[k] += a * X[(int64_t)k * d + j];
+  for (int64_t i0 = (int64_t)blockIdx.x * 32; i0 < n; i0 += (int64_t)gridDim.x * 32) {
+    int64_t ii[2], qb[2], qe[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ii[u] = i0 + 16 * u + (threadIdx.x >> 4);
+      qb[u] = ii[u] < n ? rowptr[ii[u]] : 0;
+      qe[u] = ii[u] < n ? rowptr[ii[u] + 1] : 0;
+    }
+    double s[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    const int64_t len = max(qe[0] - qb[0], qe[1] - qb[1]);
+    for (int64_t o = l; o < len; o += 16) {
+      int32_t jj[2];
+      double aa[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool on = qb[u] + o < qe[u];
+        jj[u] = on ? col[qb[u] + o] : 0;
+        aa[u] = on ? (double)val[qb[u] + o] : 0.0;
       }
-    for (int off = 8; off > 0; off >>= 1)
-      for (int k = 0; k < 4; ++k) s[k] += __shfl_xor(s[k], off, 16);
-    if (i < n && l == 0) {
-      const double bi = (double)b[i];
-      for (int k = 0; k < K; ++k) R[i * K + k] = s[k] - bi;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        for (int k = 0; k < K; ++k) s[u][k] += aa[u] * X[(int64_t)k * d + jj[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      for (int off = 8; off > 0; off >>= 1)
+        for (int k = 0; k < 4; ++k) s[u][k] += __shfl_xor(s[u][k], off, 16);
+    if (l == 0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (ii[u] < n) {
+          const double bi = (double)b[ii[u]];
+          for (int k = 0; k < K; ++k) R[ii[u] * K + k] = s[u][k] - bi;
+        }
     }
   }
 }
@@ -431,7 +452,7 @@ rs_status sparse_gradient(SparseWork& W, const SparseA& sp, const void* b, doubl
   if (sub) return set_error(RS_ERR_UNSUPPORTED, "sparse gradient: no subtracted vector");
   SP_TRY(W.R.ensure((size_t)4 * sp.n * sizeof(double)));
   double* R = W.R.as<double>();
-  const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sp.n + 15) / 16, 65536));
+  const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sp.n + 31) / 32, 65536));
   const unsigned cg = (unsigned)std::max<int64_t>(W.atr_chunks, 1);
   const unsigned fg = (unsigned)(((int64_t)K * sp.d + 255) / 256);
   // the pass is timed from the row kernel's start to the finish kernel's stop when
