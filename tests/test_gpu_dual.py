@@ -147,3 +147,13 @@ def test_dual_single_row(rs):
     zs = b[0] / (A[0] @ A[0] + 0.5)
     np.testing.assert_allclose(host(z), [zs], rtol=1e-10)
     np.testing.assert_allclose(host(x), A[0] * zs, rtol=1e-10, atol=1e-15)
+
+
+def test_dual_runs_are_bitwise_repeatable(rs):
+    A, b = wide(70, 3000, 0.97, 11, np.float32)
+    Ad, bd = dev_padded(A, rs), torch.from_numpy(b).cuda()
+    x1, z1, i1 = rs.rs_adaptive_solve_dual(Ad, bd, 1e-3, tol=1e-10, seed=4)
+    x2, z2, i2 = rs.rs_adaptive_solve_dual(Ad, bd, 1e-3, tol=1e-10, seed=4)
+    assert i1["events"] == i2["events"]
+    np.testing.assert_array_equal(host(z1), host(z2))
+    np.testing.assert_array_equal(host(x1), host(x2))

@@ -137,3 +137,14 @@ def test_path_single_nu_and_warm_first_start(rs):
     xa, ia = ihs.adaptive_solve(p.A, p.b, p.nu2, o, x_init=xs)
     assert inf2[0]["events"] == [e for e in ia.events if e[1] != "stop"]
     np.testing.assert_allclose(host(X2[0]), xa, rtol=1e-8, atol=1e-12)
+
+
+def test_path_runs_are_bitwise_repeatable(rs):
+    p = make_problem(3000, 70, spectrum("poly", 70, 1.0), 1e-3, 0.1, 7)
+    A = dev_padded(p.A, rs)
+    b = torch.from_numpy(p.b).cuda()
+    nus = [1.0, 1e-2, 1e-4]
+    X1, i1 = rs.rs_solve_path(A, b, nus, sketch_dtype="bf16", tol=1e-9, seed=2)
+    X2, i2 = rs.rs_solve_path(A, b, nus, sketch_dtype="bf16", tol=1e-9, seed=2)
+    assert [i["events"] for i in i1] == [i["events"] for i in i2]
+    np.testing.assert_array_equal(host(X1), host(X2))

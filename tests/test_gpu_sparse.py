@@ -122,3 +122,13 @@ def test_sparse_empty_rows_and_empty_matrix(rs):
                                       torch.zeros(0, dtype=torch.float64).cuda(), d, *dev(b), 0.05)
     assert i0["status"] == "ok" and i0["events"] == []
     assert np.all(host(x0) == 0.0)
+
+
+def test_sparse_runs_are_bitwise_repeatable(rs):
+    # sorts, chunked sums and the column pass all run in a fixed order
+    rowptr, col, val, b = make_sparse_problem(20000, 300, 9, 1.0, 0.1, 5)
+    args = (*dev(rowptr, col, val), 300, *dev(b), 0.05)
+    x1, i1 = rs.rs_adaptive_solve_csr(*args, tol=1e-10, seed=9)
+    x2, i2 = rs.rs_adaptive_solve_csr(*args, tol=1e-10, seed=9)
+    assert i1["events"] == i2["events"]
+    np.testing.assert_array_equal(host(x1), host(x2))
