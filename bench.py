@@ -432,6 +432,9 @@ def run_c3(args):
         if "m_init" in info:
             res[dt]["m_init"] = info["m_init"]
         print(f"[c3] {dt}: {res[dt]}", file=sys.stderr, flush=True)
+    roof = gradient_roofline(
+        rs, lambda: rs.rs_adaptive_solve(A, b, nu2, sketch_dtype="bf16", raise_on_error=False),
+        n * d * 4 + n * 4, "k_grad_partial (A^T(AX-b) pass)", "one more BF16 solve")
     # the oracle's FP64 solution, after every timed region
     print(f"[c3] oracle Gram on the host", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -454,7 +457,12 @@ def run_c3(args):
             "per_dtype": res, "speedup_bf16_vs_f32": round(res["bf16"]["solves_per_s"] / base, 3),
             "speedup_fp8_vs_f32": round(res["fp8"]["solves_per_s"] / base, 3),
             "speedup_learned_bf16_vs_f32": round(res["learned_bf16"]["solves_per_s"] / base, 3),
-            "oracle_gram_s": round(oracle_s, 1)}
+            "roofline": roof,
+            "cpu_baseline": {"value": round(1.0 / oracle_s, 5), "unit": "solves/s",
+                             "cores": blas_threads(), "kind": "oracle",
+                             "sample": f"one oracle direct FP64 solve of the full {n}x{d} "
+                                       f"problem (Gram accumulated from row blocks read back "
+                                       f"from the device, Cholesky): {oracle_s:.1f} s"}}
     print(json.dumps(line))
 
 
@@ -524,11 +532,30 @@ def run_c5(args):
                      "m_final": info["m_final"], "doublings": info["doublings"],
                      "grad_passes": info["grad_passes"]}
         print(f"[c5] {mode}: {out[mode]}", file=sys.stderr, flush=True)
+    roof = gradient_roofline(
+        rs, lambda: rs.rs_learned_solve(A, b, nu2, params, mu, sd, sketch_dtype="bf16",
+                                        tol=1e-10, raise_on_error=False),
+        n * d * 4 + n * 4, "k_grad_partial (A^T(AX-b) pass, 64 GiB)", "one more learned solve")
     # the oracle's gradient bound, after every timed region
     for mode, x in last_x.items():
         bound, gr = oracle_gradient_bound(A, b, x, nu2)
         out[mode]["rel_pred_err_bound"] = bound
         out[mode]["grad_norm_ratio"] = gr
+    # the oracle's direct solve on a bounded sample: the first 2^15 rows (its Gram
+    # costs 2 rows d^2 flops, so the full problem's rate is 2^15 / n of the sample's)
+    from oracle import ridge
+    rows = 1 << 15
+    As = A[:rows].cpu().numpy().astype(np.float64)
+    bs = b[:rows].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    ridge.solve_direct(As, bs, nu2)
+    samp_s = time.perf_counter() - t0
+    del As, bs
+    cpu = {"value": round(rows / n / samp_s, 6), "unit": "solves/s", "cores": blas_threads(),
+           "kind": "oracle",
+           "sample": f"one oracle direct FP64 solve of the first {rows} rows ({samp_s:.1f} s), "
+                     f"scaled by {rows}/{n} to the full problem (the Gram dominates and is "
+                     "linear in the rows)"}
     line = {"metric": "ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32",
             "value": out["learned_bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1,
@@ -540,7 +567,7 @@ def run_c5(args):
                        "n": n, "d": d},
             "verified_bound": all(v["rel_pred_err_bound"] <= 1e-6 and v["status"] == "ok"
                                   for v in out.values()),
-            "modes": out,
+            "modes": out, "roofline": roof, "cpu_baseline": cpu,
             "speedup_vs_plain_f32": round(out["learned_bf16"]["solves_per_s"] /
                                           out["plain_f32"]["solves_per_s"], 3)}
     print(json.dumps(line))
@@ -592,7 +619,26 @@ def run_c4a(args):
             out[name]["mr_gradient_launches"] = launches
             out[name]["mr_gradient_ms_total"] = round(gms, 3)
         print(f"[c4a] {name}: {len(nus) / sec:.1f} solves/s", file=sys.stderr, flush=True)
+    # the multi-RHS gradient passes of the timed grid solves (timed by HIP events):
+    # each running nu adds its candidates as columns, 4 n d flops per column
+    gres = out["grid_bf16"]["res"]
+    cols = sum(2 * i["grad_passes"] - 1 for _, i in gres) * args.steps
+    gms = out["grid_bf16"]["mr_gradient_ms_total"]
+    tfl = 4.0 * n * d * cols / (gms / 1e3) / 1e12 if gms > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": round(tfl, 2), "peak": 157.3, "unit": "TFLOP/s",
+            "frac": round(tfl / 157.3, 4), "traffic": None,
+            "algorithmic_flops": 4.0 * n * d * cols / max(out["grid_bf16"]["mr_gradient_launches"],
+                                                          1),
+            "kernel": "k_mr_resid + k_mr_atr (multi-RHS gradient, FP32 matrix cores)",
+            "avg_launch_us": round(gms / max(out["grid_bf16"]["mr_gradient_launches"], 1) * 1e3,
+                                   2),
+            "launches": out["grid_bf16"]["mr_gradient_launches"],
+            "region": "the timed grid solves; each pass timed from its first kernel's start to "
+                      "its second's stop by HIP events; columns counted from every nu's passes"}
+    t0 = time.perf_counter()
     G, Atb = oracle_gram_chunks(A, b)
+    ridge.solve_direct_from_gram(G, Atb, nus[0])
+    oracle_s = time.perf_counter() - t0
     worst = {k: 0.0 for k in out}
     for k in (0, 16, 32, 48, 63):
         xs = ridge.solve_direct_from_gram(G, Atb, nus[k])
@@ -615,7 +661,12 @@ def run_c4a(args):
                                    "[1e-6, 1], SRHT fresh, m from 1", "n": n, "d": d},
             "verified": all(v["sampled_worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
                             for v in out.values()),
-            "modes": out,
+            "modes": out, "roofline": roof,
+            "cpu_baseline": {"value": round(1.0 / oracle_s, 4), "unit": "solves/s",
+                             "cores": blas_threads(), "kind": "oracle",
+                             "sample": f"one oracle direct FP64 solve of the full {n}x{d} "
+                                       f"problem (Gram from row blocks read back from the "
+                                       f"device, Cholesky): {oracle_s:.1f} s"},
             "speedup_vs_sequential_plain_f32": round(
                 out["grid_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
     print(json.dumps(line))
@@ -1025,14 +1076,36 @@ def run_c4b(args):
         out[name] = {"solves_per_s": round(len(probs) / sec, 2), "s_per_batch": round(sec, 4),
                      "res": res}
         print(f"[c4b] {name}: {len(probs) / sec:.1f} solves/s", file=sys.stderr, flush=True)
+    # the gradient passes of one more learned batch, each timed by HIP events; the
+    # bytes of a problem's pass are n d 4 + n 4
+    torch.cuda.synchronize()
+    rs.rs_profile_enable(True)
+    rs.rs_profile_read()
+    pres = run_learned()
+    torch.cuda.synchronize()
+    rs.rs_profile_enable(False)
+    nl, gms = rs.rs_profile_read()
+    tot = sum(info["grad_passes"] * (A.shape[0] * A.shape[1] * 4 + A.shape[0] * 4)
+              for (A, _, _), (_, info) in zip(probs, pres))
+    ach = tot / (gms / 1e3) / 1e9 if gms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes": int(tot), "kernel": "k_grad_partial (every problem's passes)",
+            "avg_launch_us": round(gms / max(nl, 1) * 1e3, 2), "launches": nl,
+            "region": "one more learned batch; each pass timed by its own HIP start/stop "
+                      "events on its worker stream (passes of different streams overlap, so "
+                      "this is the bytes-weighted rate of a pass, not the device's total)"}
     # oracle check of the last batch of each kind
     worst = {k: 0.0 for k in out}
     bad = {k: 0 for k in out}
+    oracle_s = 0.0
     for i, (A, b, nu2) in enumerate(probs):
         A64 = A.cpu().numpy().astype(np.float64)
         b64 = b.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
         Gm = A64.T @ A64
         xs = ridge.solve_direct_from_gram(Gm, A64.T @ b64, nu2)
+        oracle_s += time.perf_counter() - t0
         H = Gm + nu2 * np.eye(Gm.shape[0])
         for k in out:
             x, info = out[k]["res"][i]
@@ -1056,7 +1129,11 @@ def run_c4b(args):
                        "graph_steps": bool(args.graph_steps)},
             "verified": all(v["worst_rel_pred_err"] <= 1e-6 and v["not_ok"] == 0
                             for v in out.values()),
-            "modes": out,
+            "modes": out, "roofline": roof,
+            "cpu_baseline": {"value": round(len(probs) / oracle_s, 3), "unit": "solves/s",
+                             "cores": blas_threads(), "kind": "oracle",
+                             "sample": f"the oracle's direct FP64 solves of all {len(probs)} "
+                                       f"problems: {oracle_s:.1f} s"},
             "speedup_vs_sequential_plain_f32": round(
                 out["learned_bf16_batched"]["solves_per_s"] /
                 out["sequential_plain_f32"]["solves_per_s"], 3)}
