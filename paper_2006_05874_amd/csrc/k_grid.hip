@@ -36,30 +36,30 @@ __device__ __forceinline__ Acc4<T> mfma4(T a, T b, Acc4<T> c) {
 // per SIMD); k (the d dimension) in chunks of 32 through LDS.  XT is X (Kc x d)
 // already in T.  Block b covers column block b % ncb of row block b / ncb, so
 // the blocks that read one row panel of A run next to each other.
-template <typename T>
+template <typename T, int TC>
 __global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64_t n, int64_t d,
                                                   int64_t lda, const T* __restrict__ b,
                                                   const T* __restrict__ XT, int64_t Kc,
                                                   T* __restrict__ R, int64_t ldr, int ncb,
                                                   int* __restrict__ ran) {
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
-  constexpr int TM = 128, TC = 128, KC = 32;
+  constexpr int TM = 128, KC = 32, NC = TC / 32;  // NC 16-column tiles per wave
   __shared__ T As[KC][TM + 1];
   __shared__ T Xs[KC][TC + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w & 3, wc = w >> 2;  // wave tile: rows wr*32.., columns wc*64..
+  const int wr = w & 3, wc = w >> 2;  // wave tile: rows wr*32.., columns wc*TC/2..
   const int64_t r0 = (int64_t)(blockIdx.x / ncb) * TM;
   const int64_t c0 = (int64_t)(blockIdx.x % ncb) * TC;
-  Acc4<T> acc[2][4];
+  Acc4<T> acc[2][NC];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = Acc4<T>{0, 0, 0, 0};
+    for (int c = 0; c < NC; ++c) acc[a][c] = Acc4<T>{0, 0, 0, 0};
   // loader mapping: thread -> (row or column = t / 4, 8 consecutive k); the next
   // chunk is fetched into registers while the current one is multiplied
   const int lrow = t >> 2, lk = (t & 3) * 8;
   const int64_t arow = r0 + lrow, xcol = c0 + lrow;
-  const bool rok = arow < n, cok = xcol < Kc;
+  const bool rok = arow < n, cok = lrow < TC && xcol < Kc;
   const T* asrc = A + (rok ? arow : 0) * lda;
   const T* xsrc = XT + (cok ? xcol : 0) * d;
   T va[8], vx[8];
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       As[lk + e][lrow] = va[e];
-      Xs[lk + e][lrow] = vx[e];
+      if (lrow < TC) Xs[lk + e][lrow] = vx[e];
     }
     __syncthreads();
     if (k0 + KC < d) fetch(k0 + KC);
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = As[kr][wr * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const T bv = Xs[kr][wc * 64 + c * 16 + (lane & 15)];
+      for (int c = 0; c < NC; ++c) {
+        const T bv = Xs[kr][wc * (TC / 2) + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a][c] = mfma4<T>(av[a], bv, acc[a][c]);
       }
@@ -106,8 +106,8 @@ __global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64
       if (row < n) {
         const T bv = b[row];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t col = c0 + wc * 64 + c * 16 + (lane & 15);
+        for (int c = 0; c < NC; ++c) {
+          const int64_t col = c0 + wc * (TC / 2) + c * 16 + (lane & 15);
           if (col < Kc) R[row * ldr + col] = acc[a][c][r] - bv;
         }
       }
@@ -118,12 +118,12 @@ __global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64
 // Block (tile, split): 128 columns of A (j) x 128 columns of R (c) over the
 // split's rows, 8 waves of 32 j x 64 c; rows in chunks of 32 through LDS.
 // Partial layout Gp[split][j][c] (ldr columns), FP64.
-template <typename T>
+template <typename T, int TC>
 __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t n, int64_t d,
                                                 int64_t lda, const T* __restrict__ R, int64_t ldr,
                                                 int64_t Kc, int64_t rows_per_split, int ncb,
                                                 double* __restrict__ Gp) {
-  constexpr int TJ = 128, TC = 128, KC = 32;
+  constexpr int TJ = 128, KC = 32, NC = TC / 32;
   __shared__ T As[KC][TJ + 1];
   __shared__ T Rs[KC][TC + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -132,12 +132,12 @@ __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t
   const int64_t c0 = (int64_t)(blockIdx.x % ncb) * TC;
   const int64_t row_lo = (int64_t)blockIdx.y * rows_per_split;
   const int64_t row_hi = row_lo + rows_per_split < n ? row_lo + rows_per_split : n;
-  Acc4<T> acc[2][4];
-  double acc64[2][4][4];
+  Acc4<T> acc[2][NC];
+  double acc64[2][NC][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NC; ++c) {
       acc[a][c] = Acc4<T>{0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc64[a][c][r] = 0.0;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int64_t j = j0 + lc + e, c = c0 + lc + e;
-      const bool oj = rok && j < d, oc = rok && c < Kc;
+      const bool oj = rok && j < d, oc = rok && lc < TC && c < Kc;
       const T x = as[oj ? j : 0];
       const T y = rsrc[oc ? c : 0];
       va[e] = oj ? x : (T)0;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       As[lr][lc + e] = va[e];
-      Rs[lr][lc + e] = vr[e];
+      if (lc < TC) Rs[lr][lc + e] = vr[e];
     }
     __syncthreads();
     if (k0 + KC < row_hi) fetch(k0 + KC);
@@ -178,8 +178,8 @@ __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = As[kr][wj * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const T bv = Rs[kr][wc * 64 + c * 16 + (lane & 15)];
+      for (int c = 0; c < NC; ++c) {
+        const T bv = Rs[kr][wc * (TC / 2) + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a][c] = mfma4<T>(av[a], bv, acc[a][c]);
       }
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NC; ++c) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc64[a][c][r] += (double)acc[a][c][r];
           acc[a][c] = Acc4<T>{0, 0, 0, 0};
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t
       const int64_t j = j0 + wj * 32 + a * 16 + mfma16_row<T>(lane, r);
       if (j < d) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t col = c0 + wc * 64 + c * 16 + (lane & 15);
+        for (int c = 0; c < NC; ++c) {
+          const int64_t col = c0 + wc * (TC / 2) + c * 16 + (lane & 15);
           if (col < Kc) out[j * ldr + col] = acc64[a][c][r] + (double)acc[a][c][r];
         }
       }
@@ -239,8 +239,13 @@ __global__ __launch_bounds__(256) void k_mr_reduce(const double* __restrict__ Gp
   }
 }
 
+// Column tile of the two products: the narrowest of 32, 64, 128 that holds Kc
+// (wider tiles only multiply padding).
+static int mr_tc(int64_t Kc) { return Kc <= 32 ? 32 : (Kc <= 64 ? 64 : 128); }
+
 int mr_splits(int64_t n, int64_t d, int64_t Kc, int64_t& rows_per_split) {
-  const int64_t tiles = ((d + 127) / 128) * ((Kc + 127) / 128);
+  const int tc = mr_tc(Kc);
+  const int64_t tiles = ((d + 127) / 128) * ((Kc + tc - 1) / tc);
   const int64_t want = (2 * device_cus() + tiles - 1) / tiles;
   int64_t ns = std::max<int64_t>(1, std::min<int64_t>(want, (n + 255) / 256));
   rows_per_split = ((n + ns - 1) / ns + 31) / 32 * 32;
@@ -252,20 +257,30 @@ template <typename T>
 rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
                       int64_t Kc, int kper, const double* nu2, const int* zl, T* R, int64_t ldr,
                       double* Gp, double* G, T* XT, hipStream_t s) {
-  const int ncb = (int)((Kc + 127) / 128);
+  const int tc = mr_tc(Kc);
+  const int ncb = (int)((Kc + tc - 1) / tc);
   const int64_t nx = Kc * d;
   const unsigned g0 = (unsigned)std::min<int64_t>((nx + 255) / 256, 4096);
   hipLaunchKernelGGL(k_round_x<T>, dim3(g0), dim3(256), 0, s, X, nx, XT);
   const unsigned g1 = (unsigned)(((n + 127) / 128) * ncb);
-  // profiled as one span: the first kernel's start to the second one's stop
-  const ProfSlot ps = prof_begin();
-  launch_timed(k_mr_resid<T>, dim3(g1), dim3(512), s, ps.begin, nullptr, A, n, d, lda, b,
-               (const T*)XT, Kc, R, ldr, ncb, ps.ran);
   int64_t rps = 0;
   const int ns = mr_splits(n, d, Kc, rps);
   const unsigned g2 = (unsigned)(((d + 127) / 128) * ncb);
-  launch_timed(k_mr_atr<T>, dim3(g2, (unsigned)ns), dim3(512), s, nullptr, ps.end, A, n, d, lda,
-               (const T*)R, ldr, Kc, rps, ncb, Gp);
+  // profiled as one span: the first kernel's start to the second one's stop
+  const ProfSlot ps = prof_begin();
+#define RS_MR_PASS(TCV)                                                                          \
+  launch_timed(k_mr_resid<T, TCV>, dim3(g1), dim3(512), s, ps.begin, nullptr, A, n, d, lda, b,    \
+               (const T*)XT, Kc, R, ldr, ncb, ps.ran);                                            \
+  launch_timed(k_mr_atr<T, TCV>, dim3(g2, (unsigned)ns), dim3(512), s, nullptr, ps.end, A, n, d,  \
+               lda, (const T*)R, ldr, Kc, rps, ncb, Gp)
+  if (tc == 32) {
+    RS_MR_PASS(32);
+  } else if (tc == 64) {
+    RS_MR_PASS(64);
+  } else {
+    RS_MR_PASS(128);
+  }
+#undef RS_MR_PASS
   const unsigned g3 = (unsigned)std::min<int64_t>((Kc * d + 255) / 256, 4096);
   hipLaunchKernelGGL(k_mr_reduce, dim3(g3), dim3(256), 0, s, Gp, ns, d, ldr, Kc, kper, X, nu2, zl,
                      G);
