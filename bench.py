@@ -108,9 +108,9 @@ def blas_threads():
 
 def plain_in_child(args):
     """The plain FP32 method (m from 1) on the same problem, timed by this script in
-    a process of its own started before this one initialises the GPU.  Timed in the
-    same process after the learned regions it measures 25-50% slower (more warm-up
-    does not change that), an effect of that process's history, not of the method."""
+    a child process of its own (this process waits, idle, for it).  Timed in the same
+    process after the learned regions it measures 25-50% slower (more warm-up does
+    not change that), an effect of that process's history, not of the method."""
     import subprocess
     cmd = [sys.executable, os.path.abspath(__file__), "--mode", "plain", "--steps",
            str(args.steps), "--warmup", str(args.warmup), "--no-cpu-baseline", "--variant",
@@ -166,11 +166,6 @@ def main():
         return run_refreshed(args)
     if args.workload == "sparse":
         return run_sparse(args)
-    # the plain method first, in a process of its own, before this one touches the GPU
-    plain = None
-    if args.mode == "learned-bf16" and not args.skip_plain:
-        plain = plain_in_child(args)
-
     import torch
 
     from paper_2006_05874_amd import rs
@@ -362,7 +357,11 @@ def main():
         line["learned_bf16_one_at_a_time"] = seq
     if roof_iso is not None:
         line["roofline_overlapped"] = roof_main
-    if plain is not None:
+    # the plain method in a process of its own, once this one's timed work is done
+    # (this one stays idle meanwhile)
+    if main_mode == "learned-bf16" and not args.skip_plain:
+        torch.cuda.synchronize()
+        plain = plain_in_child(args)
         line["plain_fp32"] = plain
         line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)
     if not args.no_cpu_baseline:
