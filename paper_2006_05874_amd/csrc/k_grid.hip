@@ -32,8 +32,9 @@ __device__ __forceinline__ Acc4<T> mfma4(T a, T b, Acc4<T> c) {
 }
 
 // ---------------------------------------------------------------- R = A X^T - b
-// Block: 128 rows x 128 columns of R, 8 waves of 32 rows x 64 columns (two waves
-// per SIMD); k (the d dimension) in chunks of 32 through LDS.  XT is X (Kc x d)
+// Block: 128 rows x TC columns of R (TC = 32, 64 or 128, the narrowest that holds
+// Kc), 8 waves of 32 rows x TC/2 columns (two waves per SIMD); k (the d dimension)
+// in chunks of 32 through LDS.  XT is X (Kc x d)
 // already in T.  Block b covers column block b % ncb of row block b / ncb, so
 // the blocks that read one row panel of A run next to each other.
 template <typename T, int TC>
@@ -115,8 +116,8 @@ __global__ __launch_bounds__(512) void k_mr_resid(const T* __restrict__ A, int64
 }
 
 // ---------------------------------------------------------------- Gp = A^T R per chunk
-// Block (tile, split): 128 columns of A (j) x 128 columns of R (c) over the
-// split's rows, 8 waves of 32 j x 64 c; rows in chunks of 32 through LDS.
+// Block (tile, split): 128 columns of A (j) x TC columns of R (c) over the
+// split's rows, 8 waves of 32 j x TC/2 c; rows in chunks of 32 through LDS.
 // Partial layout Gp[split][j][c] (ldr columns), FP64.
 template <typename T, int TC>
 __global__ __launch_bounds__(512) void k_mr_atr(const T* __restrict__ A, int64_t n, int64_t d,
