@@ -1,7 +1,7 @@
 /*
  * rs.h -- C ABI of librs, the MI355X (gfx950) adaptive Hessian-sketch ridge solver.
  *
- * Problem (Lacotte & Pilanci, NeurIPS 2020, eq. EqnMain):
+ * Problem (Lacotte & Pilanci, NeurIPS 2020, eq. (1)):
  *     x* = argmin_x  1/2 ||A x - b||^2 + nu^2/2 ||x||^2,   A is n x d, n >= d.
  *
  * Conventions shared by every entry point
@@ -105,7 +105,7 @@ rs_status rs_sketch_gaussian(const void* A, rs_dtype a_t, int64_t n, int64_t d, 
 
 typedef struct rs_factor rs_factor;
 
-/* Factor the sketched Hessian H_S = (SA)^T SA + nu^2 I (eq. EqnApproximateHessian)
+/* Factor the sketched Hessian H_S = (SA)^T SA + nu^2 I (eq. (3))
  * for repeated solves.  m < d: Woodbury identity through the m x m matrix
  * nu^2 I_m + SA SA^T (proof of Theorem 7); m >= d: the d x d matrix itself.  The
  * Gram is accumulated in FP32 (FP64 for F64 SA) on the matrix cores, the
@@ -129,7 +129,7 @@ void rs_factor_destroy(rs_factor* F);
 
 /* ------------------------------------------------------------------ gradient */
 
-/* G = A^T (A X - b) + nu^2 X for k right-hand sides (from eq. EqnMain), in one
+/* G = A^T (A X - b) + nu^2 X for k right-hand sides (from eq. (1)), in one
  * read of A.  X, G: d x k FP64; b: n entries of A's dtype.  Row residuals are
  * formed in A's precision; the A^T r sums are accumulated in FP64 (FP32 over
  * groups of at most 8 rows for FP32 A).  k in 1..4.  Asynchronous. */
@@ -316,7 +316,7 @@ rs_status rs_adaptive_solve_csr(const int64_t* rowptr, const int32_t* col, const
                                 rs_solve_info* info, hipStream_t stream);
 
 /* IHS with refreshed embeddings (Section 1, other versions of the IHS), an
- * ablation of the fixed sketch: the update of eq. EqnPolyak (beta = 0 for
+ * ablation of the fixed sketch: the update of eq. (2) (beta = 0 for
  * RS_VARIANT_GD) with a new sketch of fixed size m = opts->m_init (clamped to the
  * padded n, SRHT, or n, Gaussian) drawn at every step t (sketch_id t - 1) and
  * H_S re-formed; the step sizes are the fixed-embedding ones for (kind, rho, eta);

@@ -13,7 +13,7 @@ philox  : Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
           stream map used to draw the sketches' randomness.
 sketch  : SRHT (dense Walsh-Hadamard, no fast transform) and Gaussian embeddings
           (Section 1; Appendix C.2 "SRHT matrices").
-ridge   : the problem (eq. EqnMain), its direct solution, gradient, error metric
+ridge   : the problem (eq. (1)), its direct solution, gradient, error metric
           and effective dimension (Section 1.1 "Notations").
 ihs     : algorithmic parameters (Theorems 1-2, Definitions 3.1-3.2), the
           sketched Hessian and its Woodbury inverse (proof of Theorem 7), the

@@ -4,7 +4,7 @@ Test infrastructure: see the package docstring.
 
 * Step sizes and rates: Theorem 1 (gradient-IHS) and Theorem 2 (Polyak-IHS),
   evaluated at the bounds of Definition 3.1 (Gaussian) or 3.2 (SRHT).
-* Sketched Hessian H_S = A^T S^T S A + nu^2 I (eq. EqnApproximateHessian),
+* Sketched Hessian H_S = A^T S^T S A + nu^2 I (eq. (3)),
   inverted through the Woodbury identity with an m x m Cholesky factor as in the
   proof of Theorem 7; when m >= d the d x d matrix is factored instead (it is
   the same H_S).
@@ -150,12 +150,12 @@ def make_sketch(A, kind, seed, sketch_id, m, gauss_precision="f64"):
 
 # ---------------------------------------------------------------- updates
 def polyak_candidate(x, x_prev, gt, mu, beta):
-    """Polyak-IHS update (eq. EqnPolyak): x - mu H_S^-1 g + beta (x - x_prev)."""
+    """Polyak-IHS update (eq. (2)): x - mu H_S^-1 g + beta (x - x_prev)."""
     return x - mu * gt + beta * (x - x_prev)
 
 
 def gd_candidate(x, gt, mu):
-    """Gradient-IHS update: eq. EqnPolyak with beta = 0."""
+    """Gradient-IHS update: eq. (2) with beta = 0."""
     return x - mu * gt
 
 
@@ -341,7 +341,7 @@ class RefreshInfo:
 
 def refreshed_ihs(A, b, nu2, m, opts=None, x_init=None):
     """IHS with refreshed embeddings (Section 1, other versions of the IHS): the
-    update of eq. EqnPolyak (beta = 0 for the gradient variant) with a new sketch
+    update of eq. (2) (beta = 0 for the gradient variant) with a new sketch
     S_t of fixed size m drawn at every step (sketch_id = t - 1) and H_{S_t}
     re-formed; no acceptance tests and no doubling.  The parameters are the
     fixed-embedding ones for (kind, rho, eta).  Stops once

@@ -2,20 +2,20 @@
 
 Test infrastructure: see the package docstring.
 
-Problem (eq. EqnMain): x* = argmin_x f(x) = 1/2 ||Ax - b||^2 + nu^2/2 ||x||^2,
+Problem (eq. (1)): x* = argmin_x f(x) = 1/2 ||Ax - b||^2 + nu^2/2 ||x||^2,
 with A (n x d), n >= d.  Section 1.1 ("Notations") defines the stacked matrix
 Abar = [A; nu I], the error delta(x) = 1/2 ||Abar (x - x*)||^2, the diagonal
 D = diag(sigma_i / sqrt(sigma_i^2 + nu^2)) and the effective dimension.
 
 The method converges to x* for any sketch: the fixed point of the update
-(eq. EqnPolyak) is grad f = 0 (error recursion in the proof of Theorems 1-2),
+(eq. (2)) is grad f = 0 (error recursion in the proof of Theorems 1-2),
 so the final-answer oracle is the plain definition written out below.
 """
 import numpy as np
 
 
 def gradient(A, b, nu2, x):
-    """grad f(x) = A^T (A x - b) + nu^2 x (from eq. EqnMain)."""
+    """grad f(x) = A^T (A x - b) + nu^2 x (from eq. (1))."""
     A = np.asarray(A, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     return A.T @ (A @ x - np.asarray(b, dtype=np.float64)) + nu2 * x

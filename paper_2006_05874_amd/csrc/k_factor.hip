@@ -1,4 +1,4 @@
-// Factor of the sketched Hessian H_S = (SA)^T SA + nu^2 I (eq. EqnApproximateHessian).
+// Factor of the sketched Hessian H_S = (SA)^T SA + nu^2 I (eq. (3)).
 //
 // m >= d: M = (SA)^T SA + nu^2 I_d (d x d).  m < d: Woodbury through
 // M = nu^2 I_m + SA (SA)^T (m x m), as in the proof of Theorem 7.

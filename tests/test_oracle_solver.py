@@ -146,7 +146,7 @@ def test_newton_decrement_identity(small, kind):
 
 
 def test_error_recursion_predicts_polyak_step(small):
-    # e_{t+1} = ((1+beta) I - mu C_S^-1) e_t - beta e_{t-1}  (eq. EqnDynamics)
+    # e_{t+1} = ((1+beta) I - mu C_S^-1) e_t - beta e_{t-1}  (proofs of Theorems 1-2)
     A, b, nu2 = small.A, small.b, small.nu2
     n, d = A.shape
     S = sketch.srht_sketch(np.eye(n), 2, 0, 32)[0]
