@@ -1,7 +1,8 @@
 """ctypes binding of librs (include/rs.h): argument marshalling only.
 
 Every computation runs in the HIP library.  torch provides device memory and
-the current HIP stream.  Loading fails loudly when librs.so is missing: there
+the current HIP stream.  The binding checks what the C ABI cannot see: that each
+buffer passed is device memory holding as many values as the call reads.  Loading fails loudly when librs.so is missing: there
 is no CPU fallback.
 """
 import ctypes
@@ -189,6 +190,29 @@ def _mat(A, where):
     raise ValueError(f"{where}: A must be float32 or float64")
 
 
+def _dev(t, where, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{where}: {name} must be a device tensor")
+    return t
+
+
+def _rhs(b, A, where):
+    """b as a contiguous device vector of A's dtype with at least A's n values (the
+    library reads n of them: a shorter or host buffer would be read out of bounds)."""
+    if b.numel() < A.shape[0]:
+        raise ValueError(f"{where}: b holds {b.numel()} values, A has {A.shape[0]} rows")
+    return _dev(b, where, "b").to(A.dtype).contiguous()
+
+
+def _start(x0, length, device, where, name="x0"):
+    """A private FP64 copy of a start vector of ``length`` values (zeros when None)."""
+    if x0 is None:
+        return torch.zeros(length, dtype=torch.float64, device=device)
+    if x0.numel() != length:
+        raise ValueError(f"{where}: {name} holds {x0.numel()} values, expected {length}")
+    return _dev(x0, where, name).to(torch.float64).contiguous().clone()
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -304,9 +328,12 @@ def rs_gradient(A, b, nu2, X):
     """G = A^T (A X - b) + nu2 X for X of shape (k, d) float64."""
     a_t = _mat(A, "rs_gradient")
     n, d = A.shape
-    X = X.contiguous()
+    if X.dim() != 2 or X.shape[1] != d:
+        raise ValueError(f"rs_gradient: X must be (k, {d})")
+    X = _dev(X, "rs_gradient", "X").to(torch.float64).contiguous()
     G = torch.empty_like(X)
-    st = load().rs_gradient(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2, _ptr(X),
+    bc = _rhs(b, A, "rs_gradient")
+    st = load().rs_gradient(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2, _ptr(X),
                             X.shape[0], _ptr(G), _stream())
     _check(st, "rs_gradient")
     return G
@@ -351,10 +378,10 @@ def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh"
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
     o.flags = RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
-    x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
-         else x0.to(torch.float64).contiguous().clone())
+    x = _start(x0, d, A.device, "rs_adaptive_solve")
+    bc = _rhs(b, A, "rs_adaptive_solve")
     info = SolveInfo()
-    st = load().rs_adaptive_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+    st = load().rs_adaptive_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2,
                                   ctypes.byref(o), _ptr(x), ctypes.byref(info), _stream())
     return x, _info(info, st, raise_on_error, "rs_adaptive_solve")
 
@@ -372,7 +399,7 @@ def _batch_problems(problems, where):
     for i, (A, b, nu2) in enumerate(problems):
         n, d = A.shape
         x = X[offs[i]:offs[i] + d]
-        bc = b.contiguous()
+        bc = _rhs(b, A, where)
         xs.append(x)
         bs.append(bc)
         P[i] = Problem(_ptr(A), a_ts[i], 0, n, d, A.stride(0), _ptr(bc), float(nu2), _ptr(x))
@@ -436,11 +463,14 @@ def rs_solve_nu_grid(A, b, nu2s, kind="srht", variant="polyak", resample="fresh"
     k = len(nu2s)
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
+    if X0 is not None and tuple(X0.shape) != (k, d):
+        raise ValueError(f"rs_solve_nu_grid: X0 must be ({k}, {d})")
     X = (torch.zeros(k, d, dtype=torch.float64, device=A.device) if X0 is None
-         else X0.to(torch.float64).contiguous().clone())
+         else _dev(X0, "rs_solve_nu_grid", "X0").to(torch.float64).contiguous().clone())
+    bc = _rhs(b, A, "rs_solve_nu_grid")
     nu = (ctypes.c_double * k)(*[float(v) for v in nu2s])
     infos = (SolveInfo * k)()
-    st = load().rs_solve_nu_grid(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu, k,
+    st = load().rs_solve_nu_grid(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu, k,
                                  ctypes.byref(o), _ptr(X), infos, _stream())
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
         _check(st, "rs_solve_nu_grid")
@@ -459,11 +489,11 @@ def rs_adaptive_solve_dual(A, b, nu2, kind="srht", variant="polyak", resample="f
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
     o.flags = RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
-    z = (torch.zeros(n, dtype=torch.float64, device=A.device) if z0 is None
-         else z0.to(torch.float64).contiguous().clone())
+    z = _start(z0, n, A.device, "rs_adaptive_solve_dual", "z0")
+    bc = _rhs(b, A, "rs_adaptive_solve_dual")
     x = torch.zeros(d, dtype=torch.float64, device=A.device)
     info = SolveInfo()
-    st = load().rs_adaptive_solve_dual(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+    st = load().rs_adaptive_solve_dual(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2,
                                        ctypes.byref(o), _ptr(z), _ptr(x), ctypes.byref(info),
                                        _stream())
     return x, z, _info(info, st, raise_on_error, "rs_adaptive_solve_dual")
@@ -480,10 +510,14 @@ def rs_adaptive_solve_csr(rowptr, col, val, d, b, nu2, variant="polyak", resampl
         raise RsError(1, "rs_adaptive_solve_csr", "val and b must share float32 or float64")
     a_t = 0 if val.dtype == torch.float64 else 1
     n = rowptr.numel() - 1
+    if n < 1 or val.numel() != col.numel() or b.numel() < n:
+        raise ValueError("rs_adaptive_solve_csr: needs n >= 1 rows, one value per column "
+                         "index and n values of b")
+    for t, name in ((rowptr, "rowptr"), (col, "col"), (val, "val"), (b, "b")):
+        _dev(t, "rs_adaptive_solve_csr", name)
     o = _opts(a_t, "count", variant, resample, sketch_dtype, rho, 0.01, m_init, m_max, tol,
               max_iter, seed, check_every)
-    x = (torch.zeros(d, dtype=torch.float64, device=val.device) if x0 is None
-         else x0.to(torch.float64).contiguous().clone())
+    x = _start(x0, d, val.device, "rs_adaptive_solve_csr")
     info = SolveInfo()
     st = load().rs_adaptive_solve_csr(_ptr(rowptr.contiguous()), _ptr(col.contiguous()),
                                       _ptr(val.contiguous()), a_t, n, d, col.numel(),
@@ -499,11 +533,11 @@ def rs_refreshed_ihs(A, b, nu2, m, kind="srht", variant="gd", sketch_dtype=None,
     a_t = _mat(A, "rs_refreshed_ihs")
     n, d = A.shape
     o = _opts(a_t, kind, variant, "fresh", sketch_dtype, rho, eta, m, 0, tol, max_iter, seed, 1)
-    x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
-         else x0.to(torch.float64).contiguous().clone())
+    x = _start(x0, d, A.device, "rs_refreshed_ihs")
+    bc = _rhs(b, A, "rs_refreshed_ihs")
     rh = (ctypes.c_double * (max_iter + 1))()
     info = SolveInfo()
-    st = load().rs_refreshed_ihs(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+    st = load().rs_refreshed_ihs(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2,
                                  ctypes.byref(o), _ptr(x), rh, ctypes.byref(info), _stream())
     res = _info(info, st, raise_on_error, "rs_refreshed_ihs")
     return x, [rh[i] for i in range(min(info.grad_passes, max_iter + 1))], res
@@ -522,10 +556,11 @@ def rs_solve_path(A, b, nu2s, kind="srht", variant="polyak", sketch_dtype=None, 
               seed, check_every)
     X = torch.zeros(max(k, 1), d, dtype=torch.float64, device=A.device)
     if x0 is not None:
-        X[0] = x0.to(torch.float64)
+        X[0] = _start(x0, d, A.device, "rs_solve_path")
+    bc = _rhs(b, A, "rs_solve_path")
     nu = (ctypes.c_double * max(k, 1))(*[float(v) for v in nu2s])
     infos = (SolveInfo * max(k, 1))()
-    st = load().rs_solve_path(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu, k,
+    st = load().rs_solve_path(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu, k,
                               ctypes.byref(o), _ptr(X), infos, _stream())
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
         _check(st, "rs_solve_path")
@@ -591,11 +626,11 @@ def rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant="polyak", r
     n, d = A.shape
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, 1, m_max, tol, max_iter,
               seed, check_every)
-    x = (torch.zeros(d, dtype=torch.float64, device=A.device) if x0 is None
-         else x0.to(torch.float64).contiguous().clone())
+    x = _start(x0, d, A.device, "rs_learned_solve")
+    bc = _rhs(b, A, "rs_learned_solve")
     info = SolveInfo()
     used = ctypes.c_int64(0)
-    st = load().rs_learned_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), nu2,
+    st = load().rs_learned_solve(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2,
                                  ctypes.byref(o), _ptr(params), _ptr(mu), _ptr(sd), _ptr(x),
                                  ctypes.byref(info), ctypes.byref(used), _stream())
     res = _info(info, st, raise_on_error, "rs_learned_solve")
@@ -609,7 +644,8 @@ def rs_gradient_autotune(A, b, k=2):
     a_t = _mat(A, "rs_gradient_autotune")
     n, d = A.shape
     plan = (ctypes.c_int32 * 4)()
-    _check(load().rs_gradient_autotune(_ptr(A), a_t, n, d, A.stride(0), _ptr(b.contiguous()), k,
+    bc = _rhs(b, A, "rs_gradient_autotune")
+    _check(load().rs_gradient_autotune(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), k,
                                        ctypes.cast(plan, ctypes.c_void_p), _stream()),
            "rs_gradient_autotune")
     return tuple(plan)

@@ -196,3 +196,32 @@ def test_next_forms_argument_errors_before_device_work(lib):
                                 ctypes.byref(info), vp(0)) == 2
     # rs_params: the CountSketch takes the SRHT's parameters
     assert rs.rs_params("count", 0.25, 0.01) == rs.rs_params("srht", 0.25, 0.01)
+
+
+def test_binding_rejects_host_and_short_buffers():
+    # the library reads n values of b, d of a start vector and nnz of val through raw
+    # pointers: the binding refuses host tensors and buffers of the wrong size before
+    # any call (a host pointer or a short buffer would be read out of bounds)
+    import torch
+    from paper_2006_05874_amd import rs
+    A = torch.zeros(100, 12)
+    with pytest.raises(ValueError, match="device tensor"):
+        rs.rs_adaptive_solve(A, torch.zeros(100), 0.1)
+    with pytest.raises(ValueError, match="b holds 99 values"):
+        rs._rhs(torch.zeros(99), A, "w")
+    with pytest.raises(ValueError, match="b must be a device tensor"):
+        rs._rhs(torch.zeros(100), A, "w")
+    z = rs._start(None, 12, "cpu", "w")
+    assert z.dtype == torch.float64 and z.shape == (12,) and not z.any()
+    with pytest.raises(ValueError, match="x0 holds 11 values, expected 12"):
+        rs._start(torch.zeros(11), 12, "cpu", "w")
+    with pytest.raises(ValueError, match="z0 must be a device tensor"):
+        rs._start(torch.zeros(12), 12, "cpu", "w", "z0")
+    rowptr = torch.tensor([0, 2, 3], dtype=torch.int64)
+    col = torch.tensor([0, 4, 1], dtype=torch.int32)
+    with pytest.raises(ValueError, match="one value per column index"):
+        rs.rs_adaptive_solve_csr(rowptr, col, torch.zeros(2), 5, torch.zeros(2), 0.1)
+    with pytest.raises(ValueError, match="n values of b"):
+        rs.rs_adaptive_solve_csr(rowptr, col, torch.zeros(3), 5, torch.zeros(1), 0.1)
+    with pytest.raises(ValueError, match="rowptr must be a device tensor"):
+        rs.rs_adaptive_solve_csr(rowptr, col, torch.zeros(3), 5, torch.zeros(2), 0.1)
