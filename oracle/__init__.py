@@ -9,16 +9,24 @@ routes through it, and it shares no code with the GPU library.
 
 Modules
 -------
-philox  : Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
-          stream map used to draw the sketches' randomness.
-sketch  : SRHT (dense Walsh-Hadamard, no fast transform) and Gaussian embeddings
-          (Section 1; Appendix C.2 "SRHT matrices").
-ridge   : the problem (eq. (1)), its direct solution, gradient, error metric
-          and effective dimension (Section 1.1 "Notations").
+philox  : Philox4x32-10 counter-based generator (Salmon et al., SC'11), the
+          stream map used to draw the sketches' randomness, and the CountSketch
+          hash.
+sketch  : SRHT (dense Walsh-Hadamard, no fast transform), Gaussian embeddings
+          (Section 1; Appendix C.2 "SRHT matrices") and the CountSketch for
+          sparse A.
+ridge   : the problem (eq. (1)), its direct solution, gradient (dense, dual and
+          sparse), error metric and effective dimension (Section 1.1
+          "Notations").
 ihs     : algorithmic parameters (Theorems 1-2, Definitions 3.1-3.2), the
           sketched Hessian and its Woodbury inverse (proof of Theorem 7), the
-          sketched Newton decrement (Lemma 1) and Algorithm 1.
-mlp     : FP64 reference of the small MLP used by the learned starting-m form.
+          sketched Newton decrement (Lemma 1), Algorithm 1, the regularization
+          path with warm starts, the dual and sparse solves and the IHS with
+          refreshed embeddings.
+lowprec : BF16 rounding and the FP8-E4M3 encoder with per-column power-of-two
+          scales (the low-precision sketch form).
+learned : features and the FP64 reference of the small MLP of the learned
+          starting-m form, its gradient and Adam step.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test except those
 whose docstring says "parity unpinned".
