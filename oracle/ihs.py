@@ -36,6 +36,9 @@ Readings where the paper is silent:
 * Regularization path (Section 4, warm starts): nu^2 decreasing, each solve
   starting from the previous solution and at the previous final sketch size,
   with nested sketches so that one sketch family serves the whole path.
+* IHS with refreshed embeddings (Section 1, the other IHS versions it cites): a
+  new sketch of fixed size m at every step, the fixed-embedding step sizes, no
+  tests and no doubling; an ablation of the fixed sketch.
 """
 import math
 from dataclasses import dataclass, field

@@ -13,7 +13,7 @@ constants between rounds.
 
 Stream map (counter word 2):
     4 = SRHT Rademacher signs, 5 = SRHT row keys, 6 = Gaussian sketch entries,
-    7 = Hutchinson probe signs.
+    7 = Hutchinson probe signs, 8 = CountSketch bucket and sign.
 Counter = (idx mod 2^32, idx div 2^32, stream, sketch_id); key = (seed mod 2^32,
 seed div 2^32).
 """
