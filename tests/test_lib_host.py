@@ -225,3 +225,20 @@ def test_binding_rejects_host_and_short_buffers():
         rs.rs_adaptive_solve_csr(rowptr, col, torch.zeros(3), 5, torch.zeros(1), 0.1)
     with pytest.raises(ValueError, match="rowptr must be a device tensor"):
         rs.rs_adaptive_solve_csr(rowptr, col, torch.zeros(3), 5, torch.zeros(2), 0.1)
+
+
+def test_missing_library_fails_loudly():
+    # with no built library every entry point raises: there is no fallback path
+    import subprocess
+    import sys
+    code = ("from paper_2006_05874_amd import rs\n"
+            "rs.load.__defaults__ = ('/nonexistent/librs.so',)\n"
+            "try:\n"
+            "    rs.rs_params('srht', 0.1)\n"
+            "except ImportError as e:\n"
+            "    print('raised:', e)\n"
+            "    raise SystemExit(3)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 3, r.stdout + r.stderr
+    assert "librs.so not built" in r.stdout
