@@ -501,18 +501,18 @@ rs_status count_sketch_run(SparseWork& W, const SparseA& sp, int64_t m, uint64_t
   const int64_t chunks = n / kCsChunk + m;
   SP_TRY(W.spart.ensure((size_t)chunks * sp.d * sizeof(double)));
   // groups of 16 lanes, each with an FP64 LDS row: 64 KB of LDS at most
-  const int waves = (int)std::max<int64_t>(1, std::min<int64_t>(16, 8192 / sp.d));
-  const size_t lds = (size_t)waves * sp.d * sizeof(double);
+  const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(16, 8192 / sp.d));
+  const size_t lds = (size_t)groups * sp.d * sizeof(double);
   if (sp.a_t == RS_F32)
-    hipLaunchKernelGGL(k_cs_partial<float>, dim3((unsigned)chunks), dim3(16 * waves), lds, s,
+    hipLaunchKernelGGL(k_cs_partial<float>, dim3((unsigned)chunks), dim3(16 * groups), lds, s,
                        sp.rowptr, sp.col, reinterpret_cast<const float*>(sp.val), r1,
                        W.hsign.as<float>(), W.hoff.as<int64_t>(), W.hcst.as<int64_t>(), m, sp.d,
-                       waves, W.spart.as<double>());
+                       groups, W.spart.as<double>());
   else
-    hipLaunchKernelGGL(k_cs_partial<double>, dim3((unsigned)chunks), dim3(16 * waves), lds, s,
+    hipLaunchKernelGGL(k_cs_partial<double>, dim3((unsigned)chunks), dim3(16 * groups), lds, s,
                        sp.rowptr, sp.col, reinterpret_cast<const double*>(sp.val), r1,
                        W.hsign.as<float>(), W.hoff.as<int64_t>(), W.hcst.as<int64_t>(), m, sp.d,
-                       waves, W.spart.as<double>());
+                       groups, W.spart.as<double>());
   const dim3 g2((unsigned)m, (unsigned)((ldsa + 15) / 16));
 #define RS_CS_SUM(TO)                                                                             \
   hipLaunchKernelGGL((k_cs_sum<TO>), g2, dim3(256), 0, s, W.spart.as<double>(),                  \
