@@ -66,6 +66,35 @@ typedef struct {
  * Theorem 2 (mu_p, beta_p, cbar_p).  out: host.  RS_ERR_ARG outside the domains. */
 rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* out);
 
+/* Outcomes of the step and start rules below. */
+#define RS_RULE_ACCEPT_POLYAK 0  /* step: the Polyak candidate passes its test */
+#define RS_RULE_ACCEPT_GD 1      /* step: the gradient candidate is taken */
+#define RS_RULE_RUNNING 2        /* start: keep iterating */
+#define RS_RULE_CONVERGED 3      /* start: r <= tol * r_ref already */
+#define RS_RULE_DOUBLE 4         /* double m and resample */
+#define RS_RULE_STUCK 5          /* both rejected at m_max, no decrease */
+#define RS_RULE_NONFINITE 6      /* a decrement is NaN or infinite */
+#define RS_RULE_INDEFINITE 7     /* a decrement < 0 at m_max */
+
+/* The tests of one step of Algorithm 1 exactly as the decision kernels apply them
+ * (one FP64 copy of the rule, compiled for host and device; host side exported so
+ * the rule can be checked without a GPU).  Polyak candidate (decrement r_p, when
+ * polyak != 0): accepted if (r_p / r_1)^(1/t) <= cbar_p; else the gradient
+ * candidate (r_gd) if r_gd / r_t <= cbar_gd (ties accept); else at m_max
+ * (at_cap != 0) the gradient candidate if r_gd < r_t, or STUCK; else DOUBLE.  The
+ * decrement 1/2 g^T H_S^-1 g of Lemma 1 is >= 0 for the positive definite H_S of
+ * eq. (3); a negative one (a factor that lost definiteness, e.g. the Woodbury
+ * subtraction of a low-precision Gram at small nu^2) fails every test: DOUBLE, or
+ * INDEFINITE at m_max (solves then return RS_ERR_NOT_SPD).  Returns RS_RULE_*. */
+int32_t rs_step_rule(int32_t polyak, double r_p, double r_gd, double r_t, double r_1, int64_t t,
+                     int32_t at_cap, double cbar_p, double cbar_gd);
+
+/* The state right after a (re)factor, as the start and resample kernels judge it:
+ * r = decrement at the current point, r_ref = the stop test's reference, both
+ * under the new sketch.  NONFINITE, then DOUBLE / INDEFINITE (at_cap) for a
+ * negative value, then CONVERGED if r <= tol * r_ref, else RUNNING. */
+int32_t rs_start_rule(double r, double r_ref, double tol, int32_t at_cap);
+
 /* ------------------------------------------------------------------ sketches */
 
 /* SRHT embedding (Appendix C.2): SA = (1/sqrt(m)) R H diag(eps) A, with H the

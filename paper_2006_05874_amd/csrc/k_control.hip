@@ -74,31 +74,13 @@ __device__ __forceinline__ void decide_body(DevCtl* __restrict__ ctl,
   if (threadIdx.x < K) r[threadIdx.x] *= 0.5;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int c = -1;
     int st = RS_CTL_RUNNING;
-    const double rt = ctl->r_t, r1 = ctl->r_1;
     const int64_t t = ctl->t;
-    bool finite = true;
-    for (int i = 0; i < K; ++i) finite = finite && isfinite(r[i]);
     ctl->passes += 1;
-    if (!finite) {
-      st = RS_CTL_NONFINITE;
-    } else {
-      if (a.polyak) {
-        // (r_p / r_1)^(1/t) <= cbar_p
-        if (pow(r[0] / r1, 1.0 / (double)t) <= a.cbar_p) c = 0;
-      }
-      if (c < 0) {
-        const double rg = r[K - 1];
-        if (rg / rt <= a.cbar_gd) c = K - 1;
-        else if (ctl->at_cap) {
-          if (rg < rt) c = K - 1;
-          else st = RS_CTL_STUCK;
-        } else {
-          st = RS_CTL_DOUBLE;
-        }
-      }
-    }
+    const bool pk = a.polyak && K == 2;
+    const int rule = step_rule(pk, r[0], r[K - 1], ctl->r_t, ctl->r_1, t, ctl->at_cap, a.cbar_p,
+                               a.cbar_gd, &st);
+    const int c = rule == 0 ? 0 : (rule == 1 ? K - 1 : -1);
     if (c >= 0) {
       const int kind = (a.polyak && c == 0) ? 0 : 1;
       if (t < ev_cap) ev_kind[t] = kind;
@@ -181,10 +163,8 @@ __global__ __launch_bounds__(1024) void k_init_state(DevCtl* __restrict__ ctl,
     ctl->polyak = 0;
     ctl->gd = 0;
     ctl->at_cap = at_cap;
-    int st = RS_CTL_RUNNING;
-    if (!isfinite(r) || !isfinite(rr)) st = RS_CTL_NONFINITE;
-    else if (r <= tol * rr) st = RS_CTL_CONVERGED;
-    else if (1 >= max_iter) st = RS_CTL_MAXITER;
+    int st = start_rule(r, rr, tol, at_cap);
+    if (st == RS_CTL_RUNNING && 1 >= max_iter) st = RS_CTL_MAXITER;
     ctl->status = st;
     run = nc.X != nullptr && st == RS_CTL_RUNNING;
     publish(ctl, sn);
@@ -219,9 +199,10 @@ __global__ __launch_bounds__(1024) void k_post_resample(DevCtl* __restrict__ ctl
     ctl->r_t = 0.5 * s2[0];
     ctl->r_ref = 0.5 * s2[1];
     ctl->at_cap = at_cap;
-    int st = RS_CTL_RUNNING;
-    if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;
-    else if (ctl->r_t <= tol * ctl->r_ref) st = RS_CTL_CONVERGED;
+    const int st = start_rule(ctl->r_t, ctl->r_ref, tol, at_cap);
+    // r_1 stays from the start (Algorithm 1) unless the start's own factor was
+    // indefinite: then the first valid decrement takes its place
+    if (st == RS_CTL_RUNNING && !(ctl->r_1 >= 0.0)) ctl->r_1 = ctl->r_t;
     ctl->status = st;
     run = nc.X != nullptr && st == RS_CTL_RUNNING;
     publish(ctl, sn);
@@ -259,6 +240,7 @@ __global__ __launch_bounds__(1024) void k_refresh_step(DevCtl* __restrict__ ctl,
     if (t - 1 < rcap) rhist[t - 1] = r;
     int st = RS_CTL_RUNNING;
     if (!isfinite(r)) st = RS_CTL_NONFINITE;
+    else if (r < 0.0 || !(ctl->r_1 >= 0.0)) st = RS_CTL_INDEFINITE;  // H_S^-1 lost definiteness
     else if (r <= tol * ctl->r_1) st = RS_CTL_CONVERGED;
     else if (ctl->steps >= max_iter) st = RS_CTL_MAXITER;
     ctl->status = st;

@@ -365,30 +365,12 @@ __global__ __launch_bounds__(1024) void k_decide_g(GridPtrs P, DecideParams a, i
   if (threadIdx.x < K) r[threadIdx.x] *= 0.5;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int c = -1;
     int st = RS_CTL_RUNNING;
-    const double rt = ctl->r_t, r1 = ctl->r_1;
     const int64_t t = ctl->t;
-    bool finite = true;
-    for (int i = 0; i < K; ++i) finite = finite && isfinite(r[i]);
     ctl->passes += 1;
-    if (!finite) {
-      st = RS_CTL_NONFINITE;
-    } else {
-      if (K == 2) {
-        if (pow(r[0] / r1, 1.0 / (double)t) <= a.cbar_p) c = 0;
-      }
-      if (c < 0) {
-        const double rg = r[K - 1];
-        if (rg / rt <= a.cbar_gd) c = K - 1;
-        else if (ctl->at_cap) {
-          if (rg < rt) c = K - 1;
-          else st = RS_CTL_STUCK;
-        } else {
-          st = RS_CTL_DOUBLE;
-        }
-      }
-    }
+    const int rule = step_rule(K == 2, r[0], r[K - 1], ctl->r_t, ctl->r_1, t, ctl->at_cap,
+                               a.cbar_p, a.cbar_gd, &st);
+    const int c = rule == 0 ? 0 : (rule == 1 ? K - 1 : -1);
     if (c >= 0) {
       const int kind = (K == 2 && c == 0) ? 0 : 1;
       if (t < P.ev_cap) P.ev[(int64_t)z * P.ev_cap + t] = kind;
@@ -440,10 +422,8 @@ __global__ __launch_bounds__(1024) void k_init_g(GridPtrs P, double tol, int64_t
     ctl->polyak = 0;
     ctl->gd = 0;
     ctl->at_cap = at_cap[z];
-    int st = RS_CTL_RUNNING;
-    if (!isfinite(r)) st = RS_CTL_NONFINITE;
-    else if (r <= tol * r) st = RS_CTL_CONVERGED;
-    else if (1 >= max_iter) st = RS_CTL_MAXITER;
+    int st = start_rule(r, r, tol, at_cap[z]);
+    if (st == RS_CTL_RUNNING && 1 >= max_iter) st = RS_CTL_MAXITER;
     ctl->status = st;
   }
   const double* x = P.x + (int64_t)z * d;
@@ -471,9 +451,9 @@ __global__ __launch_bounds__(1024) void k_post_resample_g(GridPtrs P, double tol
     ctl->r_t = 0.5 * s2[0];
     ctl->r_ref = 0.5 * s2[1];
     ctl->at_cap = at_cap[z];
-    int st = RS_CTL_RUNNING;
-    if (!isfinite(ctl->r_t) || !isfinite(ctl->r_ref)) st = RS_CTL_NONFINITE;
-    else if (ctl->r_t <= tol * ctl->r_ref) st = RS_CTL_CONVERGED;
+    const int st = start_rule(ctl->r_t, ctl->r_ref, tol, at_cap[z]);
+    // r_1 stays from the start unless the start's own factor was indefinite
+    if (st == RS_CTL_RUNNING && !(ctl->r_1 >= 0.0)) ctl->r_1 = ctl->r_t;
     ctl->status = st;
   }
   double* gt = P.vec + (int64_t)z * 4 * d + 2 * d;

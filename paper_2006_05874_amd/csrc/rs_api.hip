@@ -541,6 +541,30 @@ rs_status rs_params(rs_sketch_kind kind, double rho, double eta, rs_ihs_params* 
   return RS_OK;
 }
 
+static int32_t rule_code(int st) {
+  switch (st) {
+    case RS_CTL_RUNNING: return RS_RULE_RUNNING;
+    case RS_CTL_CONVERGED: return RS_RULE_CONVERGED;
+    case RS_CTL_DOUBLE: return RS_RULE_DOUBLE;
+    case RS_CTL_STUCK: return RS_RULE_STUCK;
+    case RS_CTL_NONFINITE: return RS_RULE_NONFINITE;
+    default: return RS_RULE_INDEFINITE;
+  }
+}
+
+int32_t rs_step_rule(int32_t polyak, double r_p, double r_gd, double r_t, double r_1, int64_t t,
+                     int32_t at_cap, double cbar_p, double cbar_gd) {
+  int st = RS_CTL_RUNNING;
+  const int c = step_rule(polyak != 0, r_p, r_gd, r_t, r_1, t, at_cap, cbar_p, cbar_gd, &st);
+  if (c == 0) return RS_RULE_ACCEPT_POLYAK;
+  if (c == 1) return RS_RULE_ACCEPT_GD;
+  return rule_code(st);
+}
+
+int32_t rs_start_rule(double r, double r_ref, double tol, int32_t at_cap) {
+  return rule_code(start_rule(r, r_ref, tol, at_cap));
+}
+
 rs_status rs_sketch_srht(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda, int64_t m,
                          uint64_t seed, uint32_t sketch_id, void* SA, rs_dtype sa_t, int64_t ldsa,
                          float* sa_col_scale, int64_t* rows_out, int8_t* signs_out,
@@ -727,6 +751,8 @@ rs_status rs_ihs_step(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
     return set_error(RS_ERR_ARG, "rs_ihs_step: null argument");
   if (F->d != d) return set_error(RS_ERR_SHAPE, "rs_ihs_step: factor built for another d");
   if (st->t < 1) return set_error(RS_ERR_ARG, "rs_ihs_step: t must start at 1");
+  if (!(st->r_t >= 0.0) || !(st->r_1 >= 0.0))
+    return set_error(RS_ERR_ARG, "rs_ihs_step: r_t and r_1 must be >= 0 (Lemma 1)");
   const int K = variant == RS_VARIANT_POLYAK ? 2 : 1;
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> g(S->mu);
@@ -759,6 +785,8 @@ rs_status rs_ihs_step(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
   RS_HIP(hipMemcpyAsync(&h, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
   RS_HIP(hipStreamSynchronize(stream));
   if (h.status == RS_CTL_NONFINITE) return set_error(RS_ERR_NONFINITE, "rs_ihs_step: non-finite decrement");
+  if (h.last_r[1] < 0.0 || (K == 2 && h.last_r[0] < 0.0))
+    return set_error(RS_ERR_NOT_SPD, "rs_ihs_step: negative decrement (H_S^-1 of F indefinite)");
   out->r_p = K == 2 ? h.last_r[0] : std::nan("");
   out->r_gd = h.last_r[1];
   if (h.status == RS_CTL_DOUBLE) {
@@ -918,6 +946,8 @@ static rs_status ctl_result(int status) {
   if (status == RS_CTL_CONVERGED) return RS_OK;
   if (status == RS_CTL_NONFINITE)
     return set_error(RS_ERR_NONFINITE, "solve: non-finite decrement");
+  if (status == RS_CTL_INDEFINITE)
+    return set_error(RS_ERR_NOT_SPD, "solve: negative decrement at m_max (H_S^-1 indefinite)");
   return set_error(RS_ERR_NO_CONVERGENCE, status == RS_CTL_STUCK ? "solve: no progress at m_max"
                                                                  : "solve: max_iter reached");
 }
@@ -1234,6 +1264,9 @@ struct SolveJob {
     if (h.status == RS_CTL_CONVERGED) result = RS_OK;
     else if (h.status == RS_CTL_NONFINITE)
       result = set_error(RS_ERR_NONFINITE, "rs_adaptive_solve: non-finite decrement");
+    else if (h.status == RS_CTL_INDEFINITE)
+      result = set_error(RS_ERR_NOT_SPD,
+                         "rs_adaptive_solve: negative decrement at m_max (H_S^-1 indefinite)");
     else
       result = set_error(RS_ERR_NO_CONVERGENCE,
                          h.status == RS_CTL_STUCK ? "rs_adaptive_solve: no progress at m_max"
@@ -1375,6 +1408,8 @@ rs_status rs_refreshed_ihs(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
     if (h.status == RS_CTL_RUNNING) continue;
     if (h.status == RS_CTL_NONFINITE)
       result = set_error(RS_ERR_NONFINITE, "rs_refreshed_ihs: non-finite decrement");
+    else if (h.status == RS_CTL_INDEFINITE)
+      result = set_error(RS_ERR_NOT_SPD, "rs_refreshed_ihs: negative decrement (H_S^-1 indefinite)");
     else if (h.status == RS_CTL_MAXITER)
       result = set_error(RS_ERR_NO_CONVERGENCE, "rs_refreshed_ihs: max_iter reached");
     break;

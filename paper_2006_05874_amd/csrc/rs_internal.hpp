@@ -191,8 +191,55 @@ enum {
   RS_CTL_DOUBLE = 2,
   RS_CTL_STUCK = 3,
   RS_CTL_MAXITER = 4,
-  RS_CTL_NONFINITE = 5
+  RS_CTL_NONFINITE = 5,
+  RS_CTL_INDEFINITE = 6  // a decrement < 0 at m_max: the factor's H_S^-1 is not positive definite
 };
+
+// The two tests of one step of Algorithm 1, in FP64: the Polyak candidate
+// (decrement r0, only when `polyak`) passes if (r0 / r1)^(1/t) <= cbar_p, else the
+// gradient candidate (rg) if rg / rt <= cbar_gd; ties accept.  At m_max a double
+// rejection still takes the gradient candidate if it lowers r.  Returns the chosen
+// candidate (0 Polyak, 1 gradient, -1 none) and the status in *st.  H_S is positive
+// definite (eq. (3)), so each decrement 1/2 g^T H_S^-1 g is >= 0; a negative one
+// means the factor lost definiteness (the Woodbury subtraction of a low-precision
+// Gram when nu^2 is small): it fails every test and asks for a larger sketch, and
+// at m_max ends the run as INDEFINITE.  Every decision kernel and the exported
+// host check (rs_step_rule) run this one copy.
+// v - v is 0 exactly for finite v and NaN for NaN or an infinity (host and device alike)
+__host__ __device__ inline bool finite_value(double v) { return (v - v) == 0.0; }
+
+__host__ __device__ inline int step_rule(bool polyak, double r0, double rg, double rt, double r1,
+                                         int64_t t, int at_cap, double cbar_p, double cbar_gd,
+                                         int* st) {
+  *st = RS_CTL_RUNNING;
+  if (!finite_value(rg) || (polyak && !finite_value(r0))) {
+    *st = RS_CTL_NONFINITE;
+    return -1;
+  }
+  if (rg < 0.0 || (polyak && r0 < 0.0)) {
+    *st = at_cap ? RS_CTL_INDEFINITE : RS_CTL_DOUBLE;
+    return -1;
+  }
+  if (polyak && pow(r0 / r1, 1.0 / (double)t) <= cbar_p) return 0;
+  if (rg / rt <= cbar_gd) return 1;
+  if (at_cap) {
+    if (rg < rt) return 1;
+    *st = RS_CTL_STUCK;
+    return -1;
+  }
+  *st = RS_CTL_DOUBLE;
+  return -1;
+}
+
+// The state after a (re)factor: decrement r at the current point and the stop
+// test's reference r_ref, both under the new sketch.  Negative values mean an
+// indefinite H_S^-1 (see step_rule): a larger sketch, or INDEFINITE at m_max.
+__host__ __device__ inline int start_rule(double r, double r_ref, double tol, int at_cap) {
+  if (!finite_value(r) || !finite_value(r_ref)) return RS_CTL_NONFINITE;
+  if (r < 0.0 || r_ref < 0.0) return at_cap ? RS_CTL_INDEFINITE : RS_CTL_DOUBLE;
+  if (r <= tol * r_ref) return RS_CTL_CONVERGED;
+  return RS_CTL_RUNNING;
+}
 
 struct DevCtl {
   double r_t, r_1, r_ref;

@@ -85,7 +85,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
            "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs",
-           "rs_adaptive_solve_csr"]
+           "rs_adaptive_solve_csr", "rs_step_rule", "rs_start_rule"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -155,6 +155,10 @@ def load(path=LIB_PATH):
                                          ctypes.POINTER(i64), ctypes.c_int32, vp]
     L.rs_gradient_autotune.argtypes = [vp, c_int, i64, i64, i64, vp, i64, vp, vp]
     L.rs_gradient_plan.argtypes = [c_int, i64, i64, i64, vp]
+    L.rs_step_rule.argtypes = [ctypes.c_int32, dbl, dbl, dbl, dbl, i64, ctypes.c_int32, dbl, dbl]
+    L.rs_step_rule.restype = ctypes.c_int32
+    L.rs_start_rule.argtypes = [dbl, dbl, dbl, ctypes.c_int32]
+    L.rs_start_rule.restype = ctypes.c_int32
     L.rs_last_error.restype = ctypes.c_char_p
     L.rs_version.restype = ctypes.c_char_p
     for name in ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodbury",
@@ -167,6 +171,21 @@ def load(path=LIB_PATH):
         getattr(L, name).restype = c_int
     _lib = L
     return L
+
+
+RULES = {0: "accept_polyak", 1: "accept_gd", 2: "running", 3: "converged", 4: "double",
+         5: "stuck", 6: "nonfinite", 7: "indefinite"}
+
+
+def rs_step_rule(polyak, r_p, r_gd, r_t, r_1, t, at_cap, cbar_p, cbar_gd):
+    """Outcome name of Algorithm 1's tests for one step (the kernels' rule)."""
+    return RULES[load().rs_step_rule(int(bool(polyak)), r_p, r_gd, r_t, r_1, t, int(bool(at_cap)),
+                                     cbar_p, cbar_gd)]
+
+
+def rs_start_rule(r, r_ref, tol, at_cap):
+    """Outcome name of the state check after a (re)factor (the kernels' rule)."""
+    return RULES[load().rs_start_rule(r, r_ref, tol, int(bool(at_cap)))]
 
 
 def _check(st, where):

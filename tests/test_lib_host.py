@@ -242,3 +242,48 @@ def test_missing_library_fails_loudly():
                        timeout=300)
     assert r.returncode == 3, r.stdout + r.stderr
     assert "librs.so not built" in r.stdout
+
+
+# ------------------------------------------------ Algorithm 1's tests as the kernels run them
+def test_step_rule_accepts_as_algorithm1(lib):
+    """The decision kernels' rule (host copy of the same source) against the tests
+    of Algorithm 1 written out here: Polyak first, then the gradient candidate,
+    ties accept, doubling otherwise, and the m_max reading."""
+    from paper_2006_05874_amd import rs
+    prm = ihs.params_for("srht", 0.1)
+    cp, cg = prm.cbar_p, prm.cbar_gd
+    r1, rt = 1.0, 0.5
+    # (r_p / r_1)^(1/t) <= cbar_p at t = 2: r_p = cbar_p^2 r_1 ties, accepted
+    assert rs.rs_step_rule(1, cp ** 2 * r1, 0.4, rt, r1, 2, 0, cp, cg) == "accept_polyak"
+    # just above: the Polyak candidate fails, the gradient one passes
+    assert rs.rs_step_rule(1, 1.01 * cp ** 2, cg * rt, rt, r1, 2, 0, cp, cg) == "accept_gd"
+    # an off-by-one exponent would accept this one: (cp^1.5)^(1/2) > cp, but ^(1/3) < cp
+    assert rs.rs_step_rule(1, cp ** 1.5, 0.9 * rt, rt, r1, 2, 0, cp, cg) == "double"
+    assert rs.rs_step_rule(0, 0.0, 1.01 * cg * rt, rt, r1, 3, 0, cp, cg) == "double"
+    # at m_max: any decrease is taken, else stuck
+    assert rs.rs_step_rule(0, 0.0, 0.9 * rt, rt, r1, 3, 1, cp, cg) == "accept_gd"
+    assert rs.rs_step_rule(0, 0.0, 1.1 * rt, rt, r1, 3, 1, cp, cg) == "stuck"
+    assert rs.rs_step_rule(1, float("nan"), 0.1, rt, r1, 3, 0, cp, cg) == "nonfinite"
+
+
+@pytest.mark.parametrize("polyak,r_p,r_gd", [(1, -1e-12, 1e-3), (1, 1e-3, -1e-12),
+                                             (0, 0.0, -1e-12), (1, -5.0, -5.0)])
+def test_step_rule_refuses_negative_decrements(lib, polyak, r_p, r_gd):
+    """A negative decrement (an indefinite H_S^-1) passes no test: it asks for a
+    larger sketch, and at m_max ends the run, instead of passing r/r_t <= cbar."""
+    from paper_2006_05874_amd import rs
+    prm = ihs.params_for("srht", 0.1)
+    assert rs.rs_step_rule(polyak, r_p, r_gd, 0.5, 1.0, 2, 0, prm.cbar_p, prm.cbar_gd) == "double"
+    assert rs.rs_step_rule(polyak, r_p, r_gd, 0.5, 1.0, 2, 1, prm.cbar_p,
+                           prm.cbar_gd) == "indefinite"
+
+
+def test_start_rule(lib):
+    from paper_2006_05874_amd import rs
+    assert rs.rs_start_rule(1.0, 2.0, 1e-7, 0) == "running"
+    assert rs.rs_start_rule(1e-8, 1.0, 1e-7, 0) == "converged"
+    assert rs.rs_start_rule(0.0, 0.0, 1e-7, 0) == "converged"
+    assert rs.rs_start_rule(-1e-9, 1.0, 1e-7, 0) == "double"
+    assert rs.rs_start_rule(1.0, -1.0, 1e-7, 0) == "double"
+    assert rs.rs_start_rule(-1e-9, 1.0, 1e-7, 1) == "indefinite"
+    assert rs.rs_start_rule(float("inf"), 1.0, 1e-7, 0) == "nonfinite"
