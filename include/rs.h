@@ -199,6 +199,14 @@ rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d
 /* The plan the gradient pass uses for this key (tuned or default). */
 rs_status rs_gradient_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k, int32_t* plan);
 
+/* Fix the plan of a key (dtype, n rounded up to a power of two, d, k) without
+ * timing, e.g. one tuned earlier and stored by the caller.  plan: 4 host int32 as
+ * returned by rs_gradient_autotune.  RS_ERR_UNSUPPORTED for a shape that is not
+ * built, RS_ERR_SHAPE for one that does not cover d (or exceeds it more than 4x),
+ * RS_ERR_ARG for a grid outside [1, 4 blocks per CU].  Host only. */
+rs_status rs_gradient_set_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k,
+                               const int32_t* plan);
+
 /* One step of Algorithm 1 under a fixed factor: candidates
  * x_p = x_t - mu_p g~_t + beta_p (x_t - x_{t-1}) and x_gd = x_t - mu_gd g~_t, their
  * gradients in one pass over A, their decrements, then the tests

@@ -426,6 +426,28 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
   return check_launch("autotune");
 }
 
+// A caller-chosen plan for a key: the shape must be one of the built ones and cover
+// the row of d columns (at most 4x over), the grid at least 1 block.
+template <typename T>
+rs_status gradient_set_plan(int64_t n, int64_t d, int k, const GradPlan& pl) {
+  constexpr int VEC = VecOf<T>::n;
+  const int64_t row = (d + VEC - 1) / VEC;
+  bool built = false;
+  for (const GradShape& sh : kShapes)
+    built |= sh.tpr == pl.tpr && sh.nv == pl.nv && sh.r == pl.r;
+  if (!built) return set_error(RS_ERR_UNSUPPORTED, "gradient plan: shape not built");
+  const int64_t cover = (int64_t)pl.tpr * pl.nv;
+  if (cover < row || cover > 4 * std::max<int64_t>(row, 16))
+    return set_error(RS_ERR_SHAPE, "gradient plan: shape does not fit this d");
+  if (pl.grid < 1 || pl.grid > grad_partial_blocks_max(n))
+    return set_error(RS_ERR_ARG, "gradient plan: grid outside [1, 4 blocks per CU]");
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  g_plans[PlanKey{(int)sizeof(T), pow2_ceil(n), d, k}] = pl;
+  return RS_OK;
+}
+
+template rs_status gradient_set_plan<float>(int64_t, int64_t, int, const GradPlan&);
+template rs_status gradient_set_plan<double>(int64_t, int64_t, int, const GradPlan&);
 template GradPlan grad_plan<float>(int64_t, int64_t, int);
 template GradPlan grad_plan<double>(int64_t, int64_t, int);
 template rs_status gradient_autotune<float>(const float*, int64_t, int64_t, int64_t, const float*,

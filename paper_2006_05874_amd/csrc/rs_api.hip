@@ -731,6 +731,22 @@ rs_status rs_gradient_autotune(const void* A, rs_dtype a_t, int64_t n, int64_t d
   return RS_OK;
 }
 
+rs_status rs_gradient_set_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k,
+                               const int32_t* plan) {
+  if (!plan) return set_error(RS_ERR_ARG, "rs_gradient_set_plan: plan is null");
+  if (a_t != RS_F32 && a_t != RS_F64)
+    return set_error(RS_ERR_ARG, "rs_gradient_set_plan: F32 or F64");
+  if (n < 1 || d < 1 || k < 1 || k > 4)
+    return set_error(RS_ERR_SHAPE, "rs_gradient_set_plan: bad shape");
+  GradPlan pl;
+  pl.tpr = plan[0];
+  pl.nv = plan[1];
+  pl.grid = plan[2];
+  pl.r = plan[3];
+  return a_t == RS_F32 ? gradient_set_plan<float>(n, d, (int)k, pl)
+                       : gradient_set_plan<double>(n, d, (int)k, pl);
+}
+
 rs_status rs_gradient_plan(rs_dtype a_t, int64_t n, int64_t d, int64_t k, int32_t* plan) {
   if (!plan) return set_error(RS_ERR_ARG, "rs_gradient_plan: plan is null");
   if (a_t != RS_F32 && a_t != RS_F64) return set_error(RS_ERR_ARG, "rs_gradient_plan: F32 or F64");

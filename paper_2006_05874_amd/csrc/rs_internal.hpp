@@ -122,6 +122,8 @@ struct GradPlan {
 template <typename T>
 GradPlan grad_plan(int64_t n, int64_t d, int k);
 template <typename T>
+rs_status gradient_set_plan(int64_t n, int64_t d, int k, const GradPlan& pl);
+template <typename T>
 rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
                             const double* X, int k, double* G, double* partial, int grid_cap,
                             hipStream_t s, GradPlan* chosen);

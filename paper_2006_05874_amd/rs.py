@@ -85,7 +85,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
            "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs",
-           "rs_adaptive_solve_csr", "rs_step_rule", "rs_start_rule"]
+           "rs_adaptive_solve_csr", "rs_step_rule", "rs_start_rule", "rs_gradient_set_plan"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -155,6 +155,7 @@ def load(path=LIB_PATH):
                                          ctypes.POINTER(i64), ctypes.c_int32, vp]
     L.rs_gradient_autotune.argtypes = [vp, c_int, i64, i64, i64, vp, i64, vp, vp]
     L.rs_gradient_plan.argtypes = [c_int, i64, i64, i64, vp]
+    L.rs_gradient_set_plan.argtypes = [c_int, i64, i64, i64, vp]
     L.rs_step_rule.argtypes = [ctypes.c_int32, dbl, dbl, dbl, dbl, i64, ctypes.c_int32, dbl, dbl]
     L.rs_step_rule.restype = ctypes.c_int32
     L.rs_start_rule.argtypes = [dbl, dbl, dbl, ctypes.c_int32]
@@ -167,7 +168,7 @@ def load(path=LIB_PATH):
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
                  "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual",
-                 "rs_refreshed_ihs", "rs_adaptive_solve_csr"]:
+                 "rs_refreshed_ihs", "rs_adaptive_solve_csr", "rs_gradient_set_plan"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -675,6 +676,13 @@ def rs_gradient_plan(dtype, n, d, k):
     _check(load().rs_gradient_plan(DTYPES[dtype], n, d, k, ctypes.cast(plan, ctypes.c_void_p)),
            "rs_gradient_plan")
     return tuple(plan)
+
+
+def rs_gradient_set_plan(dtype, n, d, k, plan):
+    """Fix the gradient plan (threads per row, vectors, grid, rows per step) of a key."""
+    arr = (ctypes.c_int32 * 4)(*[int(v) for v in plan])
+    _check(load().rs_gradient_set_plan(DTYPES[dtype], n, d, k, ctypes.cast(arr, ctypes.c_void_p)),
+           "rs_gradient_set_plan")
 
 
 def rs_profile_enable(on=True):

@@ -35,11 +35,20 @@ def host(t):
 
 
 @pytest.mark.parametrize("n,d,dt", [(1024, 64, np.float64), (3000, 200, np.float64),
-                                    (5000, 300, np.float32), (100, 37, np.float64)])
+                                    (5000, 300, np.float32), (100, 37, np.float64),
+                                    (9000, 8192, np.float32)])
 def test_features_against_oracle(rs, n, d, dt):
-    p = make_problem(n, d, spectrum("poly", d, 1.0), 1e-3, 0.1, n + d, dtype=dt)
-    f = host(rs.rs_features(dev_padded(p.A, rs), p.nu2, seed=7)).astype(np.float64)
-    want = learned.features(p.A.astype(np.float64), p.nu2, 7)
+    if d > 4096:
+        # the evaluation width: Gaussian rows with decaying column scales (a Haar
+        # rotation at this d costs half a minute of host time and is not needed here)
+        rng = np.random.default_rng(n + d)
+        A = (rng.standard_normal((n, d)) / np.sqrt(n) * spectrum("poly", d, 1.0)).astype(dt)
+        nu2 = 1e-3
+    else:
+        p = make_problem(n, d, spectrum("poly", d, 1.0), 1e-3, 0.1, n + d, dtype=dt)
+        A, nu2 = p.A, p.nu2
+    f = host(rs.rs_features(dev_padded(A, rs), nu2, seed=7)).astype(np.float64)
+    want = learned.features(A.astype(np.float64), nu2, 7)
     np.testing.assert_allclose(f[:3], want[:3], rtol=1e-6)
     # probes: FP32 storage of the feature; FP32 sketch for FP32 data
     tol = 1e-5 if dt == np.float64 else 2e-3

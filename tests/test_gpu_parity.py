@@ -218,9 +218,93 @@ def test_gradient_autotune_then_parity(rs, n, d, k):
     assert ridge.relative_error(ridge.hessian(A64, p.nu2), host(x), xs) <= 1e-6
 
 
+def _fp32_grad_check(A, b, X, G, nu2):
+    A64, b64 = A.astype(np.float64), b.astype(np.float64)
+    d = A.shape[1]
+    for c in range(X.shape[0]):
+        x32 = X[c].astype(np.float32).astype(np.float64)
+        want = A64.T @ (A64 @ x32 - b64) + nu2 * X[c]
+        row = np.abs(A64) @ np.abs(x32) + np.abs(b64)
+        tol = 8 * np.finfo(np.float32).eps * (np.abs(A64).T @ row) * math.log2(max(d, 2))
+        assert np.all(np.abs(G[c] - want) <= tol + 1e-12)
+
+
+WIDE_SHAPES = [(tpr, nv, r) for tpr in (16, 64, 128, 256) for nv in (1, 2, 4, 8)
+               for r in (2, 4, 8)]
+
+
+@pytest.mark.parametrize("d", [8192, 4096])
+@pytest.mark.parametrize("k", [1, 2])
+def test_gradient_every_built_shape_at_wide_d(rs, d, k):
+    """Every partial-sum shape the library builds that covers d (the ones the tuner
+    can pick at the 2^21 x 8192 evaluation size among them), forced through
+    rs_gradient_set_plan, against the oracle's gradient; ragged n, several grids."""
+    n = 3001
+    rng = np.random.default_rng(d + k)
+    A = (rng.standard_normal((n, d)) / np.sqrt(n)).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    X = rng.standard_normal((k, d))
+    Ad, bd, Xd = dev_padded(A, rs), dev(b), dev(X)
+    tried = 0
+    for (tpr, nv, r) in WIDE_SHAPES:
+        for grid in (7, 47):
+            try:
+                rs.rs_gradient_set_plan("f32", n, d, k, (tpr, nv, grid, r))
+            except rs.RsError as e:
+                assert e.name in ("unsupported", "shape")
+                break
+            assert rs.rs_gradient_plan("f32", n, d, k) == (tpr, nv, grid, r)
+            G = host(rs.rs_gradient(Ad, bd, 0.37, Xd))
+            _fp32_grad_check(A, b, X, G, 0.37)
+            tried += 1
+    assert tried >= 4          # (256, 8, 2) and (256, 8, 4) at d = 8192, two grids each
+
+
+def test_gradient_set_plan_rejects_bad_plans(rs):
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_gradient_set_plan("f32", 4096, 8192, 2, (64, 1, 16, 8))     # does not cover d
+    assert e.value.name == "shape"
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_gradient_set_plan("f32", 4096, 8192, 2, (256, 8, 16, 3))    # not built
+    assert e.value.name == "unsupported"
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_gradient_set_plan("f32", 4096, 8192, 2, (256, 8, 0, 4))     # empty grid
+    assert e.value.name == "arg"
+
+
 # ------------------------------------------------------------------ factor
 FACTOR_CASES = [(1, 64), (5, 64), (63, 64), (64, 64), (65, 64), (200, 64), (100, 300),
                 (512, 1024), (1024, 1024), (2048, 1024), (300, 100)]
+
+
+@pytest.mark.parametrize("m,d", [(1024, 8192), (520, 8192), (8192, 8192)])
+def test_factor_apply_at_evaluation_width(rs, m, d):
+    """The factor and apply at d = 8192, the width of the 2^21 x 8192 evaluation
+    problem: the m x m Woodbury route with 128 column blocks (m < d) and the
+    8192 x 8192 Cholesky route (m = d), FP32 SA as the solver stores it."""
+    rng = np.random.default_rng(m + d)
+    SA = (rng.standard_normal((m, d)) / np.sqrt(d)).astype(np.float32)
+    nu2 = 0.05
+    F = rs.rs_factor_woodbury(dev(SA), nu2)
+    G = rng.standard_normal((2, d))
+    GT, r = F.apply(dev(G))
+    GT, r = host(GT), host(r)
+    F.close()
+    SA64 = SA.astype(np.float64)
+    P = ihs.SketchedHessian(SA64, nu2)
+    # |SA|_2^2 by power iteration on SA^T SA (converges from below; 1.25x margin)
+    v = rng.standard_normal(d)
+    for _ in range(30):
+        v = SA64.T @ (SA64 @ v)
+        v /= np.linalg.norm(v)
+    smax2 = 1.25 * float(np.linalg.norm(SA64 @ v) ** 2)
+    cond = (smax2 + nu2) / nu2          # H_S = SA^T SA + nu^2 I
+    for c in range(2):
+        want, rw = P.decrement(G[c])
+        err = np.linalg.norm(GT[c] - want) / np.linalg.norm(want)
+        # FP32 Gram on the matrix cores: relative error ~ 1e-7 sqrt(q) amplified by cond
+        assert err <= 2e-6 * cond, (err, cond)
+        assert abs(r[c] - rw) <= 2e-6 * cond * abs(rw)
 
 
 @pytest.mark.parametrize("m,d", FACTOR_CASES)
