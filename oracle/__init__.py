@@ -25,6 +25,9 @@ ihs     : algorithmic parameters (Theorems 1-2, Definitions 3.1-3.2), the
           refreshed embeddings.
 lowprec : BF16 rounding and the FP8-E4M3 encoder with per-column power-of-two
           scales (the low-precision sketch form).
+certify : an upper bound on delta(x)/delta(0) from one FP64 pass over the rows of
+          A (Nystrom approximation of A^T A below H, and the dual bound on
+          delta(0)), for problems too large for the FP64 Gram.
 learned : features and the FP64 reference of the small MLP of the learned
           starting-m form, its gradient and Adam step.
 
