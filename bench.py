@@ -1,20 +1,24 @@
 """Throughput of the adaptive Hessian-sketch ridge solver on one MI355X.
 
-Workload (one "step"): the 65536 x 1024 FP32 problem A = G diag(sigma) V^T with
-sigma_i = 1/i, G i.i.d. N(0, 1/n), V Haar, b = A x_pl + 0.1 xi (seed 0), solved
-by Algorithm 1 (SRHT, rho = 0.1, FP64 factor and control) to the decrement
-tolerance, once at nu^2 = 1e-2 and once at nu^2 = 1e-4.
+Default workload (one "step"): the 2^21 x 8192 FP32 problem (64 GiB) A = G
+diag(sigma) V^T with sigma_i = 1/i, G i.i.d. N(0, 1/n), V Haar, b = A x_pl +
+0.1 xi (seed 5), solved by Algorithm 1 (SRHT, rho = 0.1, FP64 factor and
+control) to the decrement tolerance, once at nu^2 = 1e-2 and once at nu^2 =
+1e-4, one solve after the other on one stream.
 
 The reported value is the learned form with BF16 sketches (features, MLP
 prediction of the starting m, then Algorithm 1 with the doubling rule as the
-fallback), each step's two solves run as one batch over two worker streams
-(rs_learned_solve_batch).  Beside it: the same learned solves one at a time,
-and the plain method (FP32 sketch, m from 1, one at a time), timed the same way
-on the same problem.  The roofline of the gradient pass comes from a repeat of
-the timed steps in which every gradient launch carries HIP start/stop events
-(the events cost about 4% of a step, so the value is timed without them).  ``--mode plain`` reports the plain method alone.  Inputs are resident in HBM before timing; every solve of each
-timed region is checked afterwards against the oracle's direct solution
-(relative prediction error delta(x)/delta(0) <= 1e-6).
+fallback).  Beside it: the plain method (FP32 sketch, m from 1) on the same
+problem in the same process (--plain-steps steps), the roofline of the gradient
+pass (one more step with every gradient launch bracketed by HIP events on its
+stream) and of the SRHT at the learned starting sizes.  Inputs are resident in
+HBM before timing.  Every timed solve is judged afterwards by the oracle's
+streamed certificate, an upper bound on delta(x)/delta(0) from one FP64 pass over
+the stored A (verified when <= 1e-6), and the oracle's direct solve is timed on
+a row sample of the same problem.
+
+Other workloads (--workload): c2 (65536 x 1024), c3 (precision form), c4a (nu
+grid), c4b (uneven batch), path, dual, refreshed, sparse.
 
 Prints one JSON line: the throughput, the dominant kernel's roofline (live HIP
 events; traffic from the counter passes when given) and the oracle's CPU rate.
@@ -22,6 +26,7 @@ events; traffic from the counter passes when given) and the oracle's CPU rate.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -56,10 +61,13 @@ def parse():
     ap.add_argument("--model", default=None, help="learned-start model (.npz)")
     ap.add_argument("--skip-plain", action="store_true",
                     help="do not time the plain method beside the learned form")
-    ap.add_argument("--workload", default="c2",
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="c5: timed steps of the plain FP32 comparison (at most --steps)")
+    ap.add_argument("--workload", default="c5",
                     choices=["c2", "c3", "c4a", "c4b", "c5", "path", "dual", "refreshed",
                              "sparse"],
-                    help="c2: the 65536x1024 headline problem; c3: the 2^20x4096 precision "
+                    help="c5 (default): learned+BF16 against plain FP32 on the 2^21x8192 "
+                         "evaluation problem; c2: the 65536x1024 problem; c3: the 2^20x4096 precision "
                          "form; c4a: 64 nu^2 on one 2^18x2048 problem; c4b: 256 uneven "
                          "problems, batched; path: the warm-started regularization path "
                          "nu = 10^0..10^-4 on one 65536x1024 problem; dual: the "
@@ -112,7 +120,8 @@ def plain_in_child(args):
     process after the learned regions it measures 25-50% slower (more warm-up does
     not change that), an effect of that process's history, not of the method."""
     import subprocess
-    cmd = [sys.executable, os.path.abspath(__file__), "--mode", "plain", "--steps",
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "c2", "--mode", "plain",
+           "--steps",
            str(args.steps), "--warmup", str(args.warmup), "--no-cpu-baseline", "--variant",
            args.variant, "--check-every", str(args.check_every)]
     print("[bench] plain FP32 comparison in its own process", file=sys.stderr, flush=True)
@@ -166,6 +175,13 @@ def main():
         return run_refreshed(args)
     if args.workload == "sparse":
         return run_sparse(args)
+    return run_c2(args)
+
+
+def run_c2(args):
+    """The 65536 x 1024 problem (sigma_i = 1/i) at nu^2 = 1e-2 and 1e-4: the learned
+    form's two solves per step batched over two worker streams (the value), the
+    same solves one at a time, and the plain method in a process of its own."""
     import torch
 
     from paper_2006_05874_amd import rs
@@ -488,87 +504,206 @@ def oracle_gradient_bound(A_dev, b_dev, x, nu2, rows=32768):
     return float(bound), float(np.linalg.norm(g) / np.linalg.norm(atb))
 
 
+C5_N, C5_D = 1 << 21, 8192
+C5_NU2S = (1e-2, 1e-4)
+C5_SEED = 5
+
+
+def c5_certify(A_dev, b_dev, X, nu2s, rows=32768, k=256):
+    """The oracle's streamed certificate of every solution (columns of X, with
+    their nu^2): row blocks of the stored A and b read back from the device; per
+    point an upper bound on delta(x) / delta(0).  Identical points are judged once."""
+    from oracle.certify import StreamedCertificate
+    n, d = A_dev.shape
+    keys = [(nu, x.tobytes()) for nu, x in zip(nu2s, X.T)]
+    uniq = {}
+    for key in keys:
+        uniq.setdefault(key, len(uniq))
+    cols = [None] * len(uniq)
+    for (nu, xb), j in uniq.items():
+        cols[j] = (nu, np.frombuffer(xb, dtype=np.float64))
+    C = StreamedCertificate(d, np.stack([c[1] for c in cols], axis=1), k=k)
+    t0 = time.perf_counter()
+    for r0 in range(0, n, rows):
+        C.add(A_dev[r0:r0 + rows].cpu().numpy(), b_dev[r0:r0 + rows].cpu().numpy())
+        if (r0 // rows) % 8 == 0:
+            print(f"[oracle] certificate rows {min(n, r0 + rows)}/{n} "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    res = C.bounds(np.array([c[0] for c in cols]))
+    return [res[uniq[key]] for key in keys], len(uniq), k
+
+
 def run_c5(args):
-    """Learned form on the 2^21 x 8192 FP32 problem (64 GiB; sigma_i = 1/i,
-    nu^2 = 1e-3, noise 0.1), outside the sizes the predictor was trained on: the
-    learned start with BF16 SRHT sketches against the plain method (FP32 sketch,
-    m from 1).  Each solution is checked by the oracle's FP64 gradient bound; that
-    bound is loose by about (|A|_F^2 + nu^2) / nu^2 (about 1600 here), so both
-    forms stop at tol = 1e-10 on the decrement to be certified at 1e-6."""
+    """The metric's configuration: the learned form with BF16 SRHT sketches against
+    the plain method (FP32 sketch, m from 1) on the 2^21 x 8192 FP32 evaluation
+    problem (64 GiB; sigma_i = 1/i, G ~ N(0, 1/n), V Haar, b = A x_pl + 0.1 xi,
+    seed 5).  One step = the solve at nu^2 = 1e-2 and the solve at nu^2 = 1e-4
+    (nominal effective dimensions 15.2 and 155), each to the default decrement
+    tolerance, one after another on one stream.  Every timed solve is judged
+    afterwards by the oracle's streamed certificate (an upper bound on
+    delta(x) / delta(0) from one FP64 pass over the stored A)."""
     import torch
     from paper_2006_05874_amd import learned, rs
     from synth import make_problem_torch, spectrum
-    n, d, nu2 = 1 << 21, 8192, 1e-3
+    n, d = C5_N, C5_D
     torch.cuda.set_device(0)
-    A0, b, _ = make_problem_torch(n, d, spectrum("poly", d, 1.0), 0.1, 5, "cuda")
-    A = rs.padded(n, d, dtype=torch.float32)
-    A.copy_(A0)
-    del A0
+    print(f"[c5] generating the {n}x{d} problem on the device", file=sys.stderr, flush=True)
+    A, b, _ = make_problem_torch(n, d, spectrum("poly", d, 1.0), 0.1, C5_SEED, "cuda")
     torch.cuda.empty_cache()
     torch.cuda.synchronize()
-    for k in (1, 2):
-        rs.rs_gradient_autotune(A, b, k=k)
-    print("[c5] problem ready", file=sys.stderr, flush=True)
-    params, mu, sd, _ = learned.load_model(args.model or learned.MODEL_PATH)
-    out, last_x = {}, {}
-    for mode in ("learned_bf16", "plain_f32"):
-        def solve():
-            if mode == "plain_f32":
-                return rs.rs_adaptive_solve(A, b, nu2, sketch_dtype="f32", tol=1e-10,
-                                            raise_on_error=False)
-            return rs.rs_learned_solve(A, b, nu2, params, mu, sd, sketch_dtype="bf16",
-                                       tol=1e-10, raise_on_error=False)
-        solve()
+    plans = {k: rs.rs_gradient_autotune(A, b, k=k) for k in (1, 2)}
+    print(f"[c5] problem ready; gradient plans {plans}", file=sys.stderr, flush=True)
+    path = args.model or learned.MODEL_PATH
+    params, mu, sd, _ = learned.load_model(path)
+
+    def solve(nu2, mode):
+        if mode == "plain":
+            return rs.rs_adaptive_solve(A, b, nu2, kind="srht", variant=args.variant,
+                                        sketch_dtype="f32", check_every=args.check_every,
+                                        raise_on_error=False)
+        return rs.rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant=args.variant,
+                                   sketch_dtype="bf16", check_every=args.check_every,
+                                   raise_on_error=False)
+
+    def timed(mode, steps, warmup):
+        for _ in range(warmup):
+            for nu2 in C5_NU2S:
+                solve(nu2, mode)
         torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            x, info = solve()
+        out = []
+        for s in range(steps):
+            for nu2 in C5_NU2S:
+                x, info = solve(nu2, mode)
+                out.append((nu2, x, info))
+        ev1.record()
         torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / args.steps
-        last_x[mode] = x
-        out[mode] = {"solves_per_s": round(1.0 / sec, 3), "s_per_solve": round(sec, 4),
-                     "status": info["status"], "m_init": info.get("m_init", 1),
-                     "m_final": info["m_final"], "doublings": info["doublings"],
-                     "grad_passes": info["grad_passes"]}
-        print(f"[c5] {mode}: {out[mode]}", file=sys.stderr, flush=True)
-    roof = gradient_roofline(
-        rs, lambda: rs.rs_learned_solve(A, b, nu2, params, mu, sd, sketch_dtype="bf16",
-                                        tol=1e-10, raise_on_error=False),
-        n * d * 4 + n * 4, "k_grad_partial (A^T(AX-b) pass, 64 GiB)", "one more learned solve")
-    # the oracle's gradient bound, after every timed region
-    for mode, x in last_x.items():
-        bound, gr = oracle_gradient_bound(A, b, x, nu2)
-        out[mode]["rel_pred_err_bound"] = bound
-        out[mode]["grad_norm_ratio"] = gr
-    # the oracle's direct solve on a bounded sample: the first 2^15 rows (its Gram
-    # costs 2 rows d^2 flops, so the full problem's rate is 2^15 / n of the sample's)
+        wall = time.perf_counter() - t0
+        print(f"[c5] {mode}: {steps} steps in {wall:.2f} s", file=sys.stderr, flush=True)
+        return out, ev0.elapsed_time(ev1), wall
+
+    main_mode = "plain" if args.mode == "plain" else "learned"
+    results, ms_total, wall = timed(main_mode, args.steps, args.warmup)
+    solves = args.steps * len(C5_NU2S)
+    value = solves / (ms_total / 1e3)
+    plain = None
+    if main_mode == "learned" and not args.skip_plain:
+        # the comparison: fewer steps (each plain solve walks the doubling ladder)
+        psteps = max(1, min(args.steps, args.plain_steps))
+        pres, pms, _ = timed("plain", psteps, 1)
+        plain = {"steps": psteps, "warmup": 1, "ms_per_step": pms / psteps,
+                 "value": psteps * len(C5_NU2S) / (pms / 1e3), "res": pres}
+
+    # roofline of the dominant kernel: one more step with every gradient pass timed
+    # by HIP events on its stream
+    grad_bytes = n * d * 4 + n * 4
+    roof = gradient_roofline(rs, lambda: [solve(nu2, main_mode) for nu2 in C5_NU2S], grad_bytes,
+                             "k_grad_partial (A^T(AX-b) pass over 64 GiB)", "one more step")
+    # the SRHT at the sketch size each learned solve started from (BF16 output),
+    # timed by events around the call on its stream
+    srht = {}
+    for nu2, _, info in results[:len(C5_NU2S)]:
+        m = int(info.get("m_init", info["m_final"]))
+        sdt = "bf16" if main_mode == "learned" else "f32"
+        rs.rs_sketch_srht(A, m, sa_dtype=sdt)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for r in range(reps):
+            rs.rs_sketch_srht(A, m, sketch_id=r + 1, sa_dtype=sdt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = n * d * 4 + m * d * (2 if sdt == "bf16" else 4)
+        ach = alg / (ms / 1e3) / 1e9
+        srht[str(nu2)] = {"bound": "hbm", "m": m, "sa_dtype": sdt, "ms_per_sketch": round(ms, 3),
+                          "algorithmic_bytes": alg, "achieved": round(ach, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(ach / HBM_PEAK_GBS, 4),
+                          "region": f"{reps} calls of rs_sketch_srht (selection, both passes), "
+                                    "HIP events around them on the stream"}
+
+    # the oracle's certificate of every timed solve, after the timed work
+    pts = [(nu2, x, info, "main") for nu2, x, info in results]
+    if plain is not None:
+        pts += [(nu2, x, info, "plain") for nu2, x, info in plain["res"]]
+    X = np.stack([x.cpu().numpy().astype(np.float64) for _, x, _, _ in pts], axis=1)
+    bounds, nuniq, kny = c5_certify(A, b, X, [p[0] for p in pts])
+
+    def summary(which):
+        rel, infos = {}, {}
+        ok = True
+        for (nu2, x, info, w), (up, lo, ratio) in zip(pts, bounds):
+            if w != which:
+                continue
+            rel[str(nu2)] = max(rel.get(str(nu2), 0.0), ratio)
+            infos[str(nu2)] = info
+            ok = ok and ratio <= 1e-6 and info["status"] == "ok"
+        keys = ("m_final", "doublings", "steps", "grad_passes", "accepted_polyak", "accepted_gd")
+        sol = {k: {kk: v[kk] for kk in keys} for k, v in infos.items()}
+        for k, v in infos.items():
+            if "m_init" in v:
+                sol[k]["m_init"] = v["m_init"]
+        return ok, rel, sol
+
+    ok, rel, sol = summary("main")
+
+    # the oracle's direct solve on a bounded sample: the FP64 Gram of the first 2^15
+    # rows (linear in the rows: scaled by n / 2^15) and the d x d Cholesky solve
     from oracle import ridge
     rows = 1 << 15
     As = A[:rows].cpu().numpy().astype(np.float64)
     bs = b[:rows].cpu().numpy().astype(np.float64)
     t0 = time.perf_counter()
-    ridge.solve_direct(As, bs, nu2)
-    samp_s = time.perf_counter() - t0
-    del As, bs
-    cpu = {"value": round(rows / n / samp_s, 6), "unit": "solves/s", "cores": blas_threads(),
+    Gs = As.T @ As
+    cs = As.T @ bs
+    t_gram = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ridge.solve_direct_from_gram(Gs, cs, C5_NU2S[0])
+    t_solve = time.perf_counter() - t0
+    del As, bs, Gs
+    t_full = t_gram * n / rows + t_solve
+    cpu = {"value": round(1.0 / t_full, 6), "unit": "solves/s", "cores": blas_threads(),
            "kind": "oracle",
-           "sample": f"one oracle direct FP64 solve of the first {rows} rows ({samp_s:.1f} s), "
-                     f"scaled by {rows}/{n} to the full problem (the Gram dominates and is "
-                     "linear in the rows)"}
-    line = {"metric": "ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32",
-            "value": out["learned_bf16"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": 1,
-            "ms_per_step": round(out["learned_bf16"]["s_per_solve"] * 1e3, 3),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "bf16 sketch / f32 gradient / f64 factor", "data": "synthetic",
-            "config": {"workload": f"{n}x{d} FP32 (64 GiB), sigma_i=1/i, nu^2=1e-3, SRHT, "
-                                   "decrement tol 1e-10",
-                       "n": n, "d": d},
-            "verified_bound": all(v["rel_pred_err_bound"] <= 1e-6 and v["status"] == "ok"
-                                  for v in out.values()),
-            "modes": out, "roofline": roof, "cpu_baseline": cpu,
-            "speedup_vs_plain_f32": round(out["learned_bf16"]["solves_per_s"] /
-                                          out["plain_f32"]["solves_per_s"], 3)}
+           "sample": f"the oracle's direct FP64 solve on the first {rows} rows: Gram "
+                     f"{t_gram:.1f} s (scaled by {n}/{rows}) + Cholesky solve {t_solve:.1f} s"}
+    dtype = "bf16 sketch / f32 gradient / f64 factor" if main_mode == "learned" else "f32"
+    line = {
+        "metric": "ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32; HBM GB/s",
+        "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic (seeded low-rank-decay A = G diag(1/i) V^T, generated on the device)",
+        "config": {"workload": f"{n}x{d} FP32 (64 GiB), sigma_i=1/i, nu^2 in {list(C5_NU2S)}, "
+                               "SRHT rho=0.1, "
+                               + ("learned m_init, BF16 sketch" if main_mode == "learned"
+                                  else "m_init=1, FP32 sketch")
+                               + f", {args.variant}, 2 solves per step, one stream",
+                   "mode": main_mode, "n": n, "d": d,
+                   "gradient_plan_k2": list(plans[2]), "parallelism": "single GPU"},
+        "verified": ok,
+        "rel_pred_err_bound": rel,
+        "rel_pred_err_bound_sqrt": {k: math.sqrt(v) for k, v in rel.items()},
+        "certificate": f"oracle/certify.py: upper bound on delta(x)/delta(0) from one FP64 pass "
+                       f"over the stored A (Nystrom k={kny}); {nuniq} distinct solutions judged",
+        "solve": sol, "wall_s": round(wall, 3),
+        "roofline": roof, "srht_roofline": srht,
+    }
+    if plain is not None:
+        pok, prel, psol = summary("plain")
+        line["plain_fp32"] = {"value": round(plain["value"], 4), "unit": "solves/s",
+                              "steps": plain["steps"], "warmup": plain["warmup"],
+                              "ms_per_step": round(plain["ms_per_step"], 3), "verified": pok,
+                              "rel_pred_err_bound": prel, "solve": psol,
+                              "dtype": "f32 sketch", "m_init": 1, "process": "same"}
+        line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line))
 
 

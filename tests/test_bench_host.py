@@ -53,3 +53,34 @@ def test_roofline_and_oracle_rate_arithmetic(monkeypatch):
     rate = bench.oracle_rate([lambda: time.sleep(0.01)], "sleep", budget_s=0.05)
     assert rate["kind"] == "oracle" and rate["unit"] == "solves/s" and rate["cores"] >= 1
     assert 0 < rate["value"] <= 100
+
+
+def test_headline_certificate_maps_every_solution(monkeypatch):
+    """c5_certify judges each distinct (nu^2, x) once and hands every timed solve its
+    own bound, the same as the oracle's certificate called directly."""
+    import importlib
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    bench = importlib.import_module("bench")
+    from oracle import ridge
+    from oracle.certify import StreamedCertificate
+    rng = np.random.default_rng(4)
+    n, d = 500, 24
+    A = rng.standard_normal((n, d)).astype(np.float32) / np.sqrt(n)
+    b = rng.standard_normal(n).astype(np.float32)
+    A64, b64 = A.astype(np.float64), b.astype(np.float64)
+    nus = [1e-2, 1e-4, 1e-2, 1e-4, 1e-2]
+    xs = [ridge.solve_svd(A64, b64, nu) for nu in (1e-2, 1e-4)]
+    far = rng.standard_normal(d)
+    X = np.stack([xs[0], xs[1], xs[0], xs[1], far], axis=1)
+    got, nuniq, k = bench.c5_certify(torch.from_numpy(A), torch.from_numpy(b), X, nus, rows=64,
+                                     k=d)
+    assert nuniq == 3 and k == d and len(got) == 5
+    assert got[0] == got[2] and got[1] == got[3]
+    C = StreamedCertificate(d, np.stack([xs[0], xs[1], far], axis=1), k=d)
+    C.add(A, b)
+    want = C.bounds(np.array([1e-2, 1e-4, 1e-2]))
+    for g, w in zip((got[0], got[1], got[4]), want):
+        np.testing.assert_allclose(g, w, rtol=1e-9, atol=1e-25)
+    assert got[0][2] < 1e-12 and got[4][2] > 1e-3
