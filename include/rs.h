@@ -166,6 +166,23 @@ rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
                       const void* b, double nu2, const double* X, int64_t k, double* G,
                       hipStream_t stream);
 
+/* rs_gradient for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same kernels
+ * and the same result as rs_gradient (bit for bit when the grid is the same), with
+ * the per-block FP64 partial sums in a fixed array of 8 Mi doubles (64 MiB) that
+ * the library holds on each device it runs on until the process ends; the call
+ * itself allocates nothing.  The array's device address is looked up once per
+ * device (first call with that device current).  Arguments, layout and limits as
+ * rs_gradient; RS_ERR_SHAPE when k * d exceeds the array (it cannot for the built
+ * d <= 8192, k <= 4), and the grid is capped at 8 Mi / (k d) blocks.  Every call
+ * on one device shares the array: calls that overlap on a device (two host threads,
+ * or two streams with no ordering between them) race on it and must be
+ * serialized by the caller.  Each call overwrites every partial sum it reads, so
+ * nothing needs clearing between calls.  Asynchronous. */
+rs_status rs_gradient_noalloc(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t lda,
+                              const void* b, double nu2, const double* X, int64_t k, double* G,
+                              hipStream_t stream);
+
 /* ------------------------------------------------------------------ iteration */
 
 typedef struct {

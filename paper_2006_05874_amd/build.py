@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "librs.so")
 
 SOURCES = ["rs_api.hip", "k_gradient.hip", "k_srht.hip", "k_factor.hip", "k_apply.hip",
            "k_control.hip", "k_gauss.hip", "k_quant.hip", "k_learned.hip", "k_grid.hip",
-           "k_dual.hip", "k_sparse.hip"]
+           "k_dual.hip", "k_sparse.hip", "rs_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-result",

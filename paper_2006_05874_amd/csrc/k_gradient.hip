@@ -260,10 +260,11 @@ constexpr int default_rows(int nv) { return nv >= 8 ? 2 : (nv >= 4 ? 4 : 8); }
 
 template <typename T, int TPR, int NV, int K, int R>
 void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
-                    double* partial, int grid, int64_t rpb, const int* status, hipStream_t s) {
+                    double* partial, int grid, int64_t rpb, const int* status, hipStream_t s,
+                    bool prof) {
   constexpr int GPB = 256 / TPR;
   const int iters = (int)((rpb + GPB * R - 1) / (GPB * R));
-  const ProfSlot ps = prof_begin();
+  const ProfSlot ps = prof ? prof_begin() : ProfSlot();
   launch_timed(k_grad_partial<T, TPR, NV, K, R>, dim3(grid), dim3(256), s, ps.begin, ps.end, A, n,
                d, lda, b, X, rpb, iters, partial, status, ps.ran);
 }
@@ -271,10 +272,10 @@ void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, c
 template <typename T, int K>
 bool dispatch_k(GradShape sh, const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
                 const double* X, double* partial, int grid, int64_t rpb, const int* status,
-                hipStream_t s) {
+                hipStream_t s, bool prof = true) {
 #define RS_GCASE(TP, NVV, RR)                                                                \
   if (sh.tpr == TP && sh.nv == NVV && (sh.r == RR || (sh.r == 0 && RR == default_rows(NVV)))) { \
-    launch_partial<T, TP, NVV, K, RR>(A, n, d, lda, b, X, partial, grid, rpb, status, s);    \
+    launch_partial<T, TP, NVV, K, RR>(A, n, d, lda, b, X, partial, grid, rpb, status, s, prof); \
     return true;                                                                             \
   }
   RS_GCASE(16, 1, 8) RS_GCASE(64, 1, 8) RS_GCASE(64, 2, 8) RS_GCASE(64, 4, 4) RS_GCASE(128, 4, 4)
@@ -339,14 +340,14 @@ GradPlan grad_plan(int64_t n, int64_t d, int k) {
 template <typename T>
 static bool launch_plan(const GradPlan& pl, const T* A, int64_t n, int64_t d, int64_t lda,
                         const T* b, const double* X, int k, double* partial, const int* status,
-                        hipStream_t s) {
+                        hipStream_t s, bool prof = true) {
   const GradShape sh{pl.tpr, pl.nv, pl.r};
   const int64_t rpb = (n + pl.grid - 1) / pl.grid;
   switch (k) {
-    case 1: return dispatch_k<T, 1>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
-    case 2: return dispatch_k<T, 2>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
-    case 3: return dispatch_k<T, 3>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
-    case 4: return dispatch_k<T, 4>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s);
+    case 1: return dispatch_k<T, 1>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s, prof);
+    case 2: return dispatch_k<T, 2>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s, prof);
+    case 3: return dispatch_k<T, 3>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s, prof);
+    case 4: return dispatch_k<T, 4>(sh, A, n, d, lda, b, X, partial, pl.grid, rpb, status, s, prof);
   }
   return false;
 }
@@ -354,12 +355,12 @@ static bool launch_plan(const GradPlan& pl, const T* A, int64_t n, int64_t d, in
 template <typename T>
 rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
                           const double* X, int k, double* G, double* partial, int grid_cap,
-                          const int* status, hipStream_t s, const double* c) {
+                          const int* status, hipStream_t s, const double* c, bool prof) {
   if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "gradient: k must be in 1..4");
   GradPlan pl = grad_plan<T>(n, d, k);
   if (pl.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
   if (pl.grid > grid_cap) pl.grid = grid_cap;
-  if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s))
+  if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s, prof))
     return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
   const int64_t kd = (int64_t)k * d;
   hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
@@ -458,9 +459,9 @@ template rs_status gradient_autotune<double>(const double*, int64_t, int64_t, in
                                              int, hipStream_t, GradPlan*);
 template rs_status gradient_launch<float>(const float*, int64_t, int64_t, int64_t, const float*,
                                           double, const double*, int, double*, double*, int,
-                                          const int*, hipStream_t, const double*);
+                                          const int*, hipStream_t, const double*, bool);
 template rs_status gradient_launch<double>(const double*, int64_t, int64_t, int64_t, const double*,
                                            double, const double*, int, double*, double*, int,
-                                           const int*, hipStream_t, const double*);
+                                           const int*, hipStream_t, const double*, bool);
 
 }  // namespace rs

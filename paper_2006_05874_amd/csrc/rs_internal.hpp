@@ -130,7 +130,8 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
 template <typename T>
 rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, double nu2,
                           const double* X, int k, double* G, double* partial, int grid,
-                          const int* status, hipStream_t s, const double* c = nullptr);
+                          const int* status, hipStream_t s, const double* c = nullptr,
+                          bool prof = true);  // prof: false keeps the launch out of the profiler
 
 // ---------------------------------------------------------------- sparse A (CSR)
 struct GrowBuf {  // grow-only device buffer released with its owner

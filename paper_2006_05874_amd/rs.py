@@ -85,7 +85,8 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
            "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs",
-           "rs_adaptive_solve_csr", "rs_step_rule", "rs_start_rule", "rs_gradient_set_plan"]
+           "rs_adaptive_solve_csr", "rs_step_rule", "rs_start_rule", "rs_gradient_set_plan",
+           "rs_gradient_noalloc"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -120,6 +121,7 @@ def load(path=LIB_PATH):
     L.rs_factor_destroy.argtypes = [vp]
     L.rs_factor_destroy.restype = None
     L.rs_gradient.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, i64, vp, vp]
+    L.rs_gradient_noalloc.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, i64, vp, vp]
     L.rs_ihs_step.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, ctypes.POINTER(IhsParams),
                               c_int, ctypes.POINTER(IhsState), ctypes.POINTER(StepResult), vp]
     L.rs_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -168,7 +170,8 @@ def load(path=LIB_PATH):
                  "rs_mlp_backward", "rs_mlp_adam_step", "rs_learned_solve", "rs_solve_batch",
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
                  "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual",
-                 "rs_refreshed_ihs", "rs_adaptive_solve_csr", "rs_gradient_set_plan"]:
+                 "rs_refreshed_ihs", "rs_adaptive_solve_csr", "rs_gradient_set_plan",
+                 "rs_gradient_noalloc"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -356,6 +359,29 @@ def rs_gradient(A, b, nu2, X):
     st = load().rs_gradient(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2, _ptr(X),
                             X.shape[0], _ptr(G), _stream())
     _check(st, "rs_gradient")
+    return G
+
+
+def rs_gradient_noalloc(A, b, nu2, X, G=None):
+    """rs_gradient through the entry point that allocates no device memory (its
+    partial sums live in the library's fixed device array).  X: (k, d) float64 on
+    the device; G: None or a (k, d) float64 device tensor to write into."""
+    a_t = _mat(A, "rs_gradient_noalloc")
+    n, d = A.shape
+    if X.dim() != 2 or X.shape[1] != d:
+        raise ValueError(f"rs_gradient_noalloc: X must be (k, {d})")
+    X = _dev(X, "rs_gradient_noalloc", "X")
+    if X.dtype != torch.float64 or not X.is_contiguous():
+        raise ValueError("rs_gradient_noalloc: X must be contiguous float64")
+    if G is None:
+        G = torch.empty_like(X)
+    elif G.shape != X.shape or G.dtype != torch.float64 or not G.is_contiguous():
+        raise ValueError("rs_gradient_noalloc: G must be a contiguous float64 tensor shaped as X")
+    G = _dev(G, "rs_gradient_noalloc", "G")
+    bc = _rhs(b, A, "rs_gradient_noalloc")
+    st = load().rs_gradient_noalloc(_ptr(A), a_t, n, d, A.stride(0), _ptr(bc), nu2, _ptr(X),
+                                    X.shape[0], _ptr(G), _stream())
+    _check(st, "rs_gradient_noalloc")
     return G
 
 
