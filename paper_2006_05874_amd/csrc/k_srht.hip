@@ -346,6 +346,30 @@ __device__ __forceinline__ void reg_fwht(V (&v)[J], int bit_lo, int lb) {
 // 16 lanes served together over 16 different bank groups in both directions.
 __device__ __forceinline__ int lds_slot(int r, int c) { return (r * 4 + c) ^ (((r >> 5) & 15) << 2); }
 
+// The transform of one 1024-row tile held as v[j] = row g + 32 j by thread (g, c):
+// stage A (row bits 5..9 in registers), an LDS transpose in two halves (vectors
+// 0-3, then 4-7, so a block needs half the LDS and two blocks share a CU), stage B
+// (row bits 0..4).  On return thread (g, c) holds rows 32 g + j.  Only row bits
+// below lb take part.
+template <typename V, int J>
+__device__ __forceinline__ void tile_fwht(V (&v)[J], V* lds, int g, int c, int lb) {
+  const int half = c >> 2;
+  reg_fwht<V, J>(v, 5, lb);
+  for (int h = 0; h < 2; ++h) {
+    if (half == h) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) lds[lds_slot(g + 32 * j, c & 3)] = v[j];
+    }
+    __syncthreads();
+    if (half == h) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = lds[lds_slot(32 * g + j, c & 3)];
+    }
+    __syncthreads();
+  }
+  reg_fwht<V, J>(v, 0, lb);
+}
+
 // Row segment store: one 16-byte (8-byte for BF16) vector store when the segment
 // lies inside the row and the destination is aligned (vec_ok, uniform), else
 // element by element.
@@ -411,7 +435,6 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
   // blocks fit a CU: one loads while the other computes
   const int c = t & 7;
   const int g = t >> 3;
-  const int half = c >> 2;
   const int64_t col0 = ((int64_t)blockIdx.y * TT::CW + c) * VEC;
   const bool cvec = col0 < d;
 
@@ -490,20 +513,7 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
       set(v[j], e, (okr[j] && col0 + e < d) ? xe : (T)0);
     }
   }
-  reg_fwht<V, J>(v, 5, lb);
-for (int h = 0; h < 2; ++h) {
-    if (half == h) {
-#pragma unroll
-      for (int j = 0; j < J; ++j) lds[lds_slot(g + 32 * j, c & 3)] = v[j];
-    }
-    __syncthreads();
-    if (half == h) {
-#pragma unroll
-      for (int j = 0; j < J; ++j) v[j] = lds[lds_slot(32 * g + j, c & 3)];
-    }
-    __syncthreads();
-  }
-  reg_fwht<V, J>(v, 0, lb);
+  tile_fwht<V, J>(v, lds, g, c, lb);
 
   // vector stores need the row pitch and base aligned to the store width
   constexpr uintptr_t kAlign = sizeof(OutT) == 2 ? 8 : 16;
@@ -522,6 +532,241 @@ for (int h = 0; h < 2; ++h) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------- FP32 two-pass form
+// For FP32 A with 1 < n1 <= 2048 the intermediate Z (the tile transforms along i2,
+// kept at the Q low indices some sampled row uses) is stored panel-major:
+// Z[((p * Qmax + q) * n1 + i1) * 16 + c], p a 16-column panel.  Pass 2 then reads
+// each (panel, q) as n1 contiguous 64-byte rows and transforms all of i1 (up to 11
+// bits) in one tile, so Z is read exactly once.
+constexpr int kP2Rows = 2048;  // rows of a pass-2 tile
+constexpr int kP2J = 64;       // rows per thread
+
+// Pass 1: block (x = 32-column panel, y = pair of 1024-row tiles).  The panel is the
+// fastest grid index, so the blocks in flight read whole row ranges of A rather
+// than one column offset of many rows at the row pitch.  The two tiles 2y, 2y+1 of
+// a block write the two 64-byte halves of the same 128-byte lines of Z.
+// A raw buffer descriptor over `bytes` bytes at `base` (untyped loads; the loads
+// below keep every offset inside the region, they do not rely on its range check).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// Block (x = 32-column panel, y = 1024-row tile i1 - tile0).  The panel is the
+// fastest grid index, so the blocks in flight read whole row ranges of A rather
+// than one column offset of many rows at the row pitch, and tiles i1 and i1 + 1 of
+// a panel (whose 64-byte pieces share 128-byte lines of Z) run on the same XCD
+// when the panel count is a multiple of 8.
+// EDGE = false: tiles whose 1024 rows all lie below n (and n2 = 1024), loaded with
+// buffer loads (tile base in scalar registers, one 32-bit lane offset, the row
+// group's offset as the scalar offset), so 32 loads in flight cost no address
+// registers.  EDGE = true: rows clamped below n.
+template <bool EDGE>
+__global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, int64_t n,
+                                                 int64_t d, int64_t lda,
+                                                 const int8_t* __restrict__ signs, int lb,
+                                                 int64_t n2, int64_t n1, int64_t Qmax,
+                                                 const int32_t* __restrict__ qmap,
+                                                 float* __restrict__ Z, int64_t tile0) {
+  using TT = Tile<float>;
+  constexpr int J = TT::J;
+  __shared__ float4 lds[TT::RT * TT::CW / 2];
+  __shared__ int32_t dest[TT::RT];
+  __shared__ float sgn[TT::RT];
+  const int t = threadIdx.x;
+  const int c = t & 7;
+  const int g = t >> 3;
+  const int64_t tile = tile0 + (int64_t)blockIdx.y;
+  const int64_t row0 = tile * n2;
+  const int64_t col0 = ((int64_t)blockIdx.x * TT::CW + c) * 4;
+  // columns past d read column 0 and are zeroed (the last panel only)
+  const int64_t colr = col0 < d ? col0 : 0;
+  // the kept low indices, and the signs (zero for tile rows past n2 or n, which
+  // then add nothing)
+  for (int r = t; r < TT::RT; r += 256) {
+    const int32_t q = qmap[r < n2 ? r : 0];
+    dest[r] = r < n2 ? q : -1;
+    const int64_t i = row0 + r;
+    sgn[r] = (r < n2 && i < n) ? (float)signs[i < n ? i : 0] : 0.0f;
+  }
+  float4 v[J];
+  if constexpr (!EDGE) {
+    const uint32_t rowb = (uint32_t)(lda * 4);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(A + row0 * lda, rowb * TT::RT);
+    const uint32_t voff = (uint32_t)g * rowb + (uint32_t)colr * 4u;
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      v[j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                            rs, voff, (uint32_t)j * 32u * rowb, 0));
+  } else {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      int64_t i = row0 + g + 32 * j;
+      i = i < n ? i : n - 1;
+      v[j] = *reinterpret_cast<const float4*>(A + i * lda + colr);
+    }
+  }
+  __syncthreads();  // sgn and dest written
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const float sg = sgn[g + 32 * j];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) set(v[j], e, get(v[j], e) * (col0 + e < d ? sg : 0.0f));
+  }
+  tile_fwht<float4, J>(v, lds, g, c, lb);
+  // stores through a buffer descriptor over this block's two 16-column panels of Z
+  // (panel 2 x + (c >> 2); at most 2 * 1024 * 2048 rows of 64 bytes, inside 32-bit
+  // offsets)
+  const uint32_t pbytes = (uint32_t)(Qmax * n1 * 64);
+  const __amdgpu_buffer_rsrc_t zs = buf_rsrc(Z + (int64_t)blockIdx.x * 2 * Qmax * n1 * 16,
+                                             2u * pbytes);
+  const uint32_t lane_off =
+      (uint32_t)(c >> 2) * pbytes + (uint32_t)tile * 64u + (uint32_t)(c & 3) * 16u;
+  using U4 = __attribute__((ext_vector_type(4))) unsigned int;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int32_t q = dest[32 * g + j];
+    if (q >= 0)
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v[j]), zs,
+                                             lane_off + (uint32_t)q * (uint32_t)n1 * 64u, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void bfly2(float2& u, float2& v) {
+  const float2 a = u, b = v;
+  u = make_float2(a.x + b.x, a.y + b.y);
+  v = make_float2(a.x - b.x, a.y - b.y);
+}
+
+// Butterflies over register-index bits s < ns; register bit s <-> row bit bit_lo + s.
+template <int J, int NS>
+__device__ __forceinline__ void reg_fwht2(float2 (&v)[J], int bit_lo, int lb) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (bit_lo + s < lb) {
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+        if ((j & (1 << s)) == 0) bfly2(v[j], v[j | (1 << s)]);
+    }
+  }
+}
+
+// Transpose slot of (row r, lane c < 4) in float2 units: the row-bit-6..8 XOR
+// spreads the 8 row groups a wave reads together over different banks; the rows a
+// wave writes together share those bits, so the write stays contiguous.
+__device__ __forceinline__ int p2_slot(int r, int c) { return (r * 4 + c) ^ (((r >> 6) & 7) << 2); }
+
+// Pass 2: block (x = 16-column panel, y = tile of 2048 rows r = qq n1 + i1, i.e.
+// 2048 / n1 consecutive q).  Thread (g, c) first holds rows g + 32 j (j < 64: row
+// bits 5..10 in registers), then after the LDS transpose rows 64 g + j (bits 0..4),
+// two columns each.  Row r = (q, r1) of the result goes to SA row kmap[r1 n2 +
+// qlist[q]] when that row is sampled, scaled.
+template <typename OutT, bool EDGE>
+__global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, int64_t Qmax,
+                                                 int lb1, int64_t n2, int64_t d,
+                                                 const int32_t* __restrict__ qlist,
+                                                 const int32_t* __restrict__ kmap,
+                                                 const int32_t* __restrict__ qcount,
+                                                 OutT* __restrict__ out, int64_t ldo,
+                                                 float scale, int64_t ytile0) {
+  constexpr int RT = kP2Rows;
+  constexpr int J = kP2J;
+  __shared__ float2 lds[RT * 4];
+  __shared__ int32_t dest[RT];
+  const int64_t n1 = (int64_t)1 << lb1;
+  const int64_t Q = *qcount;
+  const int64_t q0 = (ytile0 + (int64_t)blockIdx.y) * (RT >> lb1);
+  if (q0 >= Q) return;  // uniform: no sampled low index in this tile
+  const int64_t valid = (Q - q0) * n1 < RT ? (Q - q0) * n1 : RT;
+  const int t = threadIdx.x;
+  const int c = t & 7;
+  const int g = t >> 3;
+  const int half = c >> 2;
+  for (int r = t; r < RT; r += 256) {
+    const int64_t q = q0 + (r >> lb1);
+    const int64_t r1 = r & (n1 - 1);
+    const bool ok = r < valid;
+    const int32_t i2 = qlist[ok ? q : 0];
+    const int32_t k = kmap[ok ? r1 * n2 + i2 : 0];
+    dest[r] = ok ? k : -1;
+  }
+  // rows of q >= Q (whole groups of n1) carry whatever Z holds there: the transform
+  // never mixes them with other q and they are not stored, so only the addresses
+  // are kept inside this panel's Qmax * n1 rows (EDGE: the tile that reaches past
+  // them)
+  const float* base = Z + (((int64_t)blockIdx.x * Qmax + q0) * n1 << 4);
+  float2 v[J];
+  if constexpr (!EDGE) {
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, RT * 64u);
+    const uint32_t voff = ((uint32_t)g * 16u + 2u * c) * 4u;
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      v[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                            rs, voff, (uint32_t)j * 32u * 64u, 0));
+  } else {
+    const int rmax = (int)((Qmax - q0) * n1) - 1;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int r = g + 32 * j;
+      v[j] = *reinterpret_cast<const float2*>(base + ((int64_t)(r < rmax ? r : rmax) << 4) + 2 * c);
+    }
+  }
+  reg_fwht2<J, 6>(v, 5, lb1);
+  for (int h = 0; h < 2; ++h) {
+    if (half == h) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) lds[p2_slot(g + 32 * j, c & 3)] = v[j];
+    }
+    __syncthreads();
+    if (half == h) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = lds[p2_slot(64 * g + j, c & 3)];
+    }
+    __syncthreads();
+  }
+  reg_fwht2<J, 5>(v, 0, lb1);
+  const int64_t col = (int64_t)blockIdx.x * 16 + 2 * c;
+  if (col >= d) return;
+  const bool pair = col + 1 < d;
+  constexpr uintptr_t kAlign = sizeof(OutT) == 2 ? 4 : 8;
+  const bool vec_ok = pair && ((reinterpret_cast<uintptr_t>(out) |
+                                (uintptr_t)(ldo * (int64_t)sizeof(OutT))) & (kAlign - 1)) == 0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int32_t k = dest[64 * g + j];
+    if (k < 0) continue;
+    OutT* o = out + (int64_t)k * ldo + col;
+    const float a = v[j].x * scale, b = v[j].y * scale;
+    if constexpr (sizeof(OutT) == 2) {
+      if (vec_ok) {
+        *reinterpret_cast<uint32_t*>(o) =
+            (uint32_t)f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
+      } else {
+        o[0] = f32_to_bf16_rne(a);
+        if (pair) o[1] = f32_to_bf16_rne(b);
+      }
+    } else {
+      if (vec_ok) {
+        *reinterpret_cast<float2*>(o) = make_float2(a, b);
+      } else {
+        o[0] = a;
+        if (pair) o[1] = b;
+      }
+    }
+  }
+}
+
+size_t srht_zbuf_bytes(rs_dtype a_t, int64_t npad, int64_t d, int64_t Qmax) {
+  const int64_t n2 = npad < 1024 ? npad : 1024;
+  const int64_t n1 = npad / n2;
+  if (n1 <= 1) return 0;
+  if (a_t == RS_F32 && n1 <= kP2Rows)  // panel-major, 32-column multiple
+    return (size_t)n1 * Qmax * ((d + 31) / 32 * 32) * sizeof(float);
+  const int64_t es = a_t == RS_F64 ? 8 : 4;
+  const int64_t vec = 16 / es;
+  return (size_t)n1 * Qmax * ((d + vec - 1) / vec * vec) * es;
 }
 
 // ---------------------------------------------------------------- driver
@@ -600,6 +845,44 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
   }
   // Q (distinct low indices) lives on the device; the intermediate is laid out
   // with the host bound Qmax >= Q and pass 2 reads the device count.
+  if constexpr (sizeof(T) == 4) {
+    // the panel form addresses a tile of A with 32-bit offsets (1024 rows of lda
+    // floats below 2^31 bytes); its intermediate is never smaller than the old
+    // layout's, so wider rows fall back to that form in the same buffer
+    if (n1 <= kP2Rows && lda < ((int64_t)1 << 19)) {
+      const int64_t np16 = (d + 15) / 16;
+      float* Zw = reinterpret_cast<float*>(B.zbuf);
+      const float* Af = reinterpret_cast<const float*>(A);
+      // full tiles (all 1024 rows below n), then the rest row-clamped
+      const int64_t full = n2 == 1024 ? std::min<int64_t>(n / 1024, n1) : 0;
+      if (full > 0)
+        hipLaunchKernelGGL(k_srht_p1<false>, dim3(panels, (unsigned)full), dim3(256), 0, s, Af, n,
+                           d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, (int64_t)0);
+      if (full < n1)
+        hipLaunchKernelGGL(k_srht_p1<true>, dim3(panels, (unsigned)(n1 - full)), dim3(256), 0, s,
+                           Af, n, d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, full);
+      const int64_t t2 = (Qmax * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
+      const int64_t t2full = Qmax * n1 / kP2Rows;
+      const float* Z = Zw;
+      auto p2 = [&](auto out_tag) {
+        using OutT = decltype(out_tag);
+        OutT* o = reinterpret_cast<OutT*>(SA);
+        if (t2full > 0)
+          hipLaunchKernelGGL((k_srht_p2<OutT, false>), dim3((unsigned)np16, (unsigned)t2full),
+                             dim3(256), 0, s, Z, Qmax, lb1, n2, d, B.qlist, B.kmap, B.qcount, o,
+                             ldsa, (float)scale, (int64_t)0);
+        if (t2 > t2full)
+          hipLaunchKernelGGL((k_srht_p2<OutT, true>), dim3((unsigned)np16, 1u), dim3(256), 0, s, Z,
+                             Qmax, lb1, n2, d, B.qlist, B.kmap, B.qcount, o, ldsa, (float)scale,
+                             t2full);
+      };
+      if (bf16)
+        p2(uint16_t{});
+      else
+        p2(float{});
+      return check_launch("srht two pass");
+    }
+  }
   const int64_t ldz = ((d + TT::VEC - 1) / TT::VEC) * TT::VEC;
   launch_tile<T, T, 0>(dim3((unsigned)n1, panels), s, A, n, lda, d, B, lb2, n2, Qmax, B.zbuf, ldz,
                        1.0);

@@ -337,12 +337,8 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
                           int8_t* signs_out, hipStream_t s) {
   const int64_t npad = next_pow2(n);
   const int64_t n2 = std::min<int64_t>(npad, 1024);
-  const int64_t n1 = npad / n2;
   const int64_t Qmax = std::min<int64_t>(m, n2);
-  const int64_t es = (int64_t)dtype_size(a_t);
-  const int64_t vec = 16 / es;
-  const int64_t ldz = (d + vec - 1) / vec * vec;
-  const int64_t zbytes = n1 > 1 ? n1 * Qmax * ldz * es : 0;
+  const size_t zbytes = srht_zbuf_bytes(a_t, npad, d, Qmax);
   SrhtBuffers B;
   RS_TRY(ensure_srht(S, npad, zbytes, B));
   int64_t* rows = rows_out;
@@ -428,8 +424,7 @@ static rs_status nested_sketch(DeviceScratch& S, NestedCache& C, bool srht, cons
     SrhtBuffers B;
     RS_TRY(S.rows.ensure((size_t)npad * sizeof(int64_t)));
     if (!C.hda_ready) {
-      const int64_t n1 = npad / n2;
-      RS_TRY(ensure_srht(S, npad, n1 > 1 ? n1 * n2 * ldh * es : 0, B));
+      RS_TRY(ensure_srht(S, npad, (int64_t)srht_zbuf_bytes(a_t, npad, d, n2), B));
       RS_TRY(S.hda.ensure((size_t)npad * ldh * es));
       RS_TRY(srht_select(B, seed, sid, npad, npad, n2, S.rows.as<int64_t>(), s));
       if (a_t == RS_F32)

@@ -62,6 +62,8 @@ rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* r
                       int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
                       hipStream_t s);
 size_t srht_state_bytes();
+// bytes of the intermediate (zbuf) of srht_transform for this shape
+size_t srht_zbuf_bytes(rs_dtype a_t, int64_t npad, int64_t d, int64_t Qmax);
 int srht_cand_cap();
 int srht_compact_block();
 
