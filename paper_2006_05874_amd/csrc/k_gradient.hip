@@ -209,6 +209,150 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
   }
 }
 
+// Wide rows (FP32, up to 512 * NV * 4 columns): one row group per block of 512
+// threads, thread lt holding the 16-byte vectors lt + 512 v (v < NV) of every row,
+// R rows per step.  The rows of step s + 1 are loaded into a second register set
+// while step s is reduced and accumulated, so the pass keeps a step of A in flight
+// at all times.  Loads go through a buffer descriptor over the block's rows (row
+// offset as the scalar offset, column offset as the 32-bit lane offset).  Row dots
+// are reduced over the 8 waves through LDS (two buffers, one barrier per step); the
+// A^T r products of a step's R rows are summed in FP32 and added to FP64
+// accumulators, as in k_grad_partial.
+template <int K, int NV, int R>
+__global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, int64_t n,
+                                                   int64_t d, int64_t lda,
+                                                   const float* __restrict__ b,
+                                                   const double* __restrict__ X,
+                                                   int64_t rows_per_block, int iters,
+                                                   double* __restrict__ partial,
+                                                   const int* __restrict__ status,
+                                                   int* __restrict__ ran) {
+  if (status && *status != 0) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  constexpr int NW = 8;  // waves per block
+  __shared__ float red[2][NW][R * K];
+  const int lt = threadIdx.x;
+  const int w = lt >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t row1 = row0 + rows_per_block < n ? row0 + rows_per_block : n;
+  if (row0 >= row1) {  // an empty block still writes its (zero) partial
+    for (int k = 0; k < K; ++k)
+      for (int v = 0; v < NV; ++v)
+        for (int e = 0; e < 4; ++e) {
+          const int64_t c = (int64_t)(lt + 512 * v) * 4 + e;
+          if (c < d) partial[((int64_t)blockIdx.x * K + k) * d + c] = 0.0;
+        }
+    return;
+  }
+  // x in registers; columns past d get x = 0 and their A values are zeroed
+  float xv[K][NV][4];
+  uint32_t coff[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t c0 = (int64_t)(lt + 512 * v) * 4;
+    coff[v] = (uint32_t)((c0 < d ? c0 : 0) * 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t c = c0 + e;
+#pragma unroll
+      for (int k = 0; k < K; ++k) xv[k][v][e] = c < d ? (float)X[k * d + c] : 0.0f;
+    }
+  }
+  double acc[K][NV][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[k][v][e] = 0.0;
+  const uint32_t rowb = (uint32_t)(lda * 4);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), (short)0, (int)(rowb * (uint32_t)(row1 - row0)),
+      0x00020000);
+  const int64_t nrows = row1 - row0;
+  // rows of a step past the block's range repeat its last row (uniform) and count 0
+  auto load = [&](float4 (&a)[R][NV], int step) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      int64_t r = (int64_t)step * R + i;
+      r = r < nrows ? r : nrows - 1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        a[i][v] = __builtin_bit_cast(
+            float4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[v], (uint32_t)r * rowb, 0));
+    }
+  };
+  auto process = [&](float4 (&a)[R][NV], int step) {
+    const int buf = step & 1;
+    // zero A values past d (padding columns may hold anything)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = (int64_t)(lt + 512 * v) * 4 + e < d;
+#pragma unroll
+        for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
+      }
+    float s[R][K];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float t = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) t = fmaf(get(a[i][v], e), xv[k][v][e], t);
+        t = wave_sum(t);
+        if ((lt & 63) == 0) red[buf][w][i * K + k] = t;
+      }
+    __syncthreads();
+    float res[K][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int64_t r = (int64_t)step * R + i;
+      const bool live = r < nrows;
+      const float bi = b[row0 + (live ? r : 0)];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float t = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) t += red[buf][ww][i * K + k];
+        res[k][i] = live ? t - bi : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float t = 0.0f;
+#pragma unroll
+          for (int i = 0; i < R; ++i) t = fmaf(get(a[i][v], e), res[k][i], t);
+          acc[k][v][e] += (double)t;
+        }
+  };
+  float4 a0[R][NV], a1[R][NV];
+  load(a0, 0);
+  for (int it = 0; it < iters; it += 2) {
+    if (it + 1 < iters) load(a1, it + 1);
+    process(a0, it);
+    if (it + 1 >= iters) break;
+    if (it + 2 < iters) load(a0, it + 2);
+    process(a1, it + 1);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t c = (int64_t)(lt + 512 * v) * 4 + e;
+        if (c < d) partial[((int64_t)blockIdx.x * K + k) * d + c] = acc[k][v][e];
+      }
+}
+
 // G[k][j] = sum over blocks of partial[b][k][j] (fixed order) + nu2 X[k][j] - sub[j]
 // (sub null: 0; the dual problem's gradient carries -b there).
 // Block: 8 columns x 32 block-strides; LDS tree over the 32 strides.
@@ -269,6 +413,16 @@ void launch_partial(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, c
                d, lda, b, X, rpb, iters, partial, status, ps.ran);
 }
 
+template <int K, int NV, int R>
+void launch_wide(const float* A, int64_t n, int64_t d, int64_t lda, const float* b,
+                 const double* X, double* partial, int grid, int64_t rpb, const int* status,
+                 hipStream_t s, bool prof) {
+  const int iters = (int)((rpb + R - 1) / R);
+  const ProfSlot ps = prof ? prof_begin() : ProfSlot();
+  launch_timed(k_grad_wide<K, NV, R>, dim3(grid), dim3(512), s, ps.begin, ps.end, A, n, d, lda,
+               b, X, rpb, iters, partial, status, ps.ran);
+}
+
 template <typename T, int K>
 bool dispatch_k(GradShape sh, const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
                 const double* X, double* partial, int grid, int64_t rpb, const int* status,
@@ -283,6 +437,18 @@ bool dispatch_k(GradShape sh, const T* A, int64_t n, int64_t d, int64_t lda, con
   // deeper row batches (more loads in flight per step), offered to the autotuner
   RS_GCASE(64, 4, 8) RS_GCASE(128, 4, 8) RS_GCASE(256, 4, 8) RS_GCASE(256, 8, 4)
 #undef RS_GCASE
+  // 512 threads per row (FP32 only; the block's rows addressed with 32-bit offsets)
+  if constexpr (sizeof(T) == 4) {
+    if (sh.tpr == 512 && rpb * lda * 4 < ((int64_t)1 << 31)) {
+#define RS_WCASE(NVV, RR)                                                                   \
+  if (sh.nv == NVV && sh.r == RR) {                                                        \
+    launch_wide<K, NVV, RR>(A, n, d, lda, b, X, partial, grid, rpb, status, s, prof);       \
+    return true;                                                                           \
+  }
+      RS_WCASE(4, 2) RS_WCASE(2, 4)
+#undef RS_WCASE
+    }
+  }
   return false;
 }
 
@@ -322,7 +488,8 @@ int64_t pow2_ceil(int64_t v) {
 
 const GradShape kShapes[] = {{16, 1, 8},  {64, 1, 8},  {64, 2, 8},  {64, 4, 4},
                              {128, 4, 4}, {256, 4, 4}, {256, 8, 2}, {64, 4, 8},
-                             {128, 4, 8}, {256, 4, 8}, {256, 8, 4}};
+                             {128, 4, 8}, {256, 4, 8}, {256, 8, 4}, {512, 4, 2},
+                             {512, 2, 4}};
 
 }  // namespace
 
@@ -360,8 +527,14 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
   GradPlan pl = grad_plan<T>(n, d, k);
   if (pl.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
   if (pl.grid > grid_cap) pl.grid = grid_cap;
-  if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s, prof))
-    return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
+  if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s, prof)) {
+    // a plan this call cannot use (e.g. the wide kernel's 32-bit row offsets for a
+    // larger leading dimension): the default shape for d
+    const GradShape sh = pick_shape<T>(d);
+    pl = GradPlan{sh.tpr, sh.nv, std::min(grad_partial_blocks(n), grid_cap), default_rows(sh.nv)};
+    if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s, prof))
+      return set_error(RS_ERR_UNSUPPORTED, "gradient: no kernel for this shape");
+  }
   const int64_t kd = (int64_t)k * d;
   hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
                      pl.grid, kd, nu2, X, G, status, c, d);
@@ -379,9 +552,11 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
   for (const GradShape& sh : kShapes) {
     const int64_t cover = (int64_t)sh.tpr * sh.nv;
     if (cover < row || cover > 4 * std::max<int64_t>(row, 16)) continue;
+    if (sh.tpr == 512 && sizeof(T) != 4) continue;  // the wide kernel is FP32 only
     for (int f : {1, 2, 4}) {
       int g = (int)std::min<int64_t>((int64_t)device_cus() * f, std::max<int64_t>(n / 64, 1));
       g = std::min(g, grid_cap);
+      if (sh.tpr == 512 && (n + g - 1) / g * lda * 4 >= ((int64_t)1 << 31)) continue;
       bool dup = false;
       for (const GradPlan& c : cand)
         dup |= (c.tpr == sh.tpr && c.nv == sh.nv && c.grid == g && c.r == sh.r);
@@ -436,7 +611,8 @@ rs_status gradient_set_plan(int64_t n, int64_t d, int k, const GradPlan& pl) {
   bool built = false;
   for (const GradShape& sh : kShapes)
     built |= sh.tpr == pl.tpr && sh.nv == pl.nv && sh.r == pl.r;
-  if (!built) return set_error(RS_ERR_UNSUPPORTED, "gradient plan: shape not built");
+  if (!built || (pl.tpr == 512 && sizeof(T) != 4))
+    return set_error(RS_ERR_UNSUPPORTED, "gradient plan: shape not built");
   const int64_t cover = (int64_t)pl.tpr * pl.nv;
   if (cover < row || cover > 4 * std::max<int64_t>(row, 16))
     return set_error(RS_ERR_SHAPE, "gradient plan: shape does not fit this d");

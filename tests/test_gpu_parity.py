@@ -229,7 +229,7 @@ def _fp32_grad_check(A, b, X, G, nu2):
         assert np.all(np.abs(G[c] - want) <= tol + 1e-12)
 
 
-WIDE_SHAPES = [(tpr, nv, r) for tpr in (16, 64, 128, 256) for nv in (1, 2, 4, 8)
+WIDE_SHAPES = [(tpr, nv, r) for tpr in (16, 64, 128, 256, 512) for nv in (1, 2, 4, 8)
                for r in (2, 4, 8)]
 
 
