@@ -541,6 +541,12 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
 // each (panel, q) as n1 contiguous 64-byte rows and transforms all of i1 (up to 11
 // bits) in one tile, so Z is read exactly once.
 constexpr int kP2Rows = 2048;  // rows of a pass-2 tile
+// panels per group in the first pass's work order: 16 when the pass mostly reads
+// (few kept low indices), 4 when it also writes an intermediate as large as A
+// (the blocks of one XCD then store to 16 different tiles at a time); measured on
+// 2^21 x 8192: 21.7 against 24.5 ms at m = 128, 59.0 against 50.9 ms at m = 4096
+constexpr int kP1GroupRead = 16;
+constexpr int kP1GroupWrite = 4;
 constexpr int kP2J = 64;       // rows per thread
 
 // Pass 1: block (x = 32-column panel, y = pair of 1024-row tiles).  The panel is the
@@ -554,22 +560,40 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uin
                                            0x00020000);
 }
 
-// Block (x = 32-column panel, y = 1024-row tile i1 - tile0).  The panel is the
-// fastest grid index, so the blocks in flight read whole row ranges of A rather
-// than one column offset of many rows at the row pitch, and tiles i1 and i1 + 1 of
-// a panel (whose 64-byte pieces share 128-byte lines of Z) run on the same XCD
-// when the panel count is a multiple of 8.
+// Block: one (32-column panel, 1024-row tile i1 = tile0 + ...) work item in the
+// order of p1_work.
 // EDGE = false: tiles whose 1024 rows all lie below n (and n2 = 1024), loaded with
 // buffer loads (tile base in scalar registers, one 32-bit lane offset, the row
 // group's offset as the scalar offset), so 32 loads in flight cost no address
 // registers.  EDGE = true: rows clamped below n.
+// Work order: blocks are dispatched to the 8 XCDs in turn, so block L runs on XCD
+// L % 8.  XCD j takes the j-th eighth of the work items w (in order), and w runs
+// over groups of `pgroup` consecutive panels, all tiles of a group before the next
+// (panel fastest inside a group): the blocks one XCD runs together cover pgroup
+// column offsets of a few neighbouring tiles.
+__device__ __forceinline__ void p1_work(int64_t L, int64_t panels, int64_t ntiles, int pgroup,
+                                        int64_t& panel, int64_t& tile) {
+  const int64_t W = panels * ntiles;
+  const int64_t W8 = W / 8;
+  const int64_t w = L < 8 * W8 ? (L % 8) * W8 + L / 8 : L;
+  const int64_t G = pgroup;
+  const int64_t gsize = G * ntiles;  // items of a full group
+  const int64_t grp = w / gsize;
+  const int64_t first = grp * G;
+  const int64_t gw = panels - first < G ? panels - first : G;  // panels in this group
+  const int64_t u = w - grp * gsize;
+  tile = u / gw;
+  panel = first + u % gw;
+}
+
 template <bool EDGE>
 __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, int64_t n,
                                                  int64_t d, int64_t lda,
                                                  const int8_t* __restrict__ signs, int lb,
                                                  int64_t n2, int64_t n1, int64_t Qmax,
                                                  const int32_t* __restrict__ qmap,
-                                                 float* __restrict__ Z, int64_t tile0) {
+                                                 float* __restrict__ Z, int64_t tile0,
+                                                 int64_t ntiles, int64_t panels, int pgroup) {
   using TT = Tile<float>;
   constexpr int J = TT::J;
   __shared__ float4 lds[TT::RT * TT::CW / 2];
@@ -578,9 +602,11 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
   const int t = threadIdx.x;
   const int c = t & 7;
   const int g = t >> 3;
-  const int64_t tile = tile0 + (int64_t)blockIdx.y;
+  int64_t panel, tloc;
+  p1_work(blockIdx.x, panels, ntiles, pgroup, panel, tloc);
+  const int64_t tile = tile0 + tloc;
   const int64_t row0 = tile * n2;
-  const int64_t col0 = ((int64_t)blockIdx.x * TT::CW + c) * 4;
+  const int64_t col0 = (panel * TT::CW + c) * 4;
   // columns past d read column 0 and are zeroed (the last panel only)
   const int64_t colr = col0 < d ? col0 : 0;
   // the kept low indices, and the signs (zero for tile rows past n2 or n, which
@@ -620,8 +646,7 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
   // (panel 2 x + (c >> 2); at most 2 * 1024 * 2048 rows of 64 bytes, inside 32-bit
   // offsets)
   const uint32_t pbytes = (uint32_t)(Qmax * n1 * 64);
-  const __amdgpu_buffer_rsrc_t zs = buf_rsrc(Z + (int64_t)blockIdx.x * 2 * Qmax * n1 * 16,
-                                             2u * pbytes);
+  const __amdgpu_buffer_rsrc_t zs = buf_rsrc(Z + panel * 2 * Qmax * n1 * 16, 2u * pbytes);
   const uint32_t lane_off =
       (uint32_t)(c >> 2) * pbytes + (uint32_t)tile * 64u + (uint32_t)(c & 3) * 16u;
   using U4 = __attribute__((ext_vector_type(4))) unsigned int;
@@ -663,11 +688,27 @@ __device__ __forceinline__ int p2_slot(int r, int c) { return (r * 4 + c) ^ (((r
 // bits 5..10 in registers), then after the LDS transpose rows 64 g + j (bits 0..4),
 // two columns each.  Row r = (q, r1) of the result goes to SA row kmap[r1 n2 +
 // qlist[q]] when that row is sampled, scaled.
+// The SA row of every pass-2 tile row (q, r1): kmap[r1 n2 + qlist[q]] for q < Q,
+// else -1, stored q-major (q n1 + r1) like the tiles, so pass 2 reads its block's
+// destinations as one contiguous run instead of a gather from kmap.
+__global__ __launch_bounds__(256) void k_p2_dest(const int32_t* __restrict__ qlist,
+                                                 const int32_t* __restrict__ kmap,
+                                                 const int32_t* __restrict__ qcount,
+                                                 int64_t Qmax, int64_t n1, int64_t n2,
+                                                 int32_t* __restrict__ dest2) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;  // q fastest
+  if (idx >= Qmax * n1) return;
+  const int64_t q = idx % Qmax;
+  const int64_t r1 = idx / Qmax;
+  int32_t v = -1;
+  if (q < (int64_t)*qcount) v = kmap[r1 * n2 + qlist[q]];
+  dest2[q * n1 + r1] = v;
+}
+
 template <typename OutT, bool EDGE>
 __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, int64_t Qmax,
                                                  int lb1, int64_t n2, int64_t d,
-                                                 const int32_t* __restrict__ qlist,
-                                                 const int32_t* __restrict__ kmap,
+                                                 const int32_t* __restrict__ dest2,
                                                  const int32_t* __restrict__ qcount,
                                                  OutT* __restrict__ out, int64_t ldo,
                                                  float scale, int64_t ytile0) {
@@ -684,14 +725,7 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
   const int c = t & 7;
   const int g = t >> 3;
   const int half = c >> 2;
-  for (int r = t; r < RT; r += 256) {
-    const int64_t q = q0 + (r >> lb1);
-    const int64_t r1 = r & (n1 - 1);
-    const bool ok = r < valid;
-    const int32_t i2 = qlist[ok ? q : 0];
-    const int32_t k = kmap[ok ? r1 * n2 + i2 : 0];
-    dest[r] = ok ? k : -1;
-  }
+  for (int r = t; r < RT; r += 256) dest[r] = r < valid ? dest2[q0 * n1 + r] : -1;
   // rows of q >= Q (whole groups of n1) carry whatever Z holds there: the transform
   // never mixes them with other q and they are not stored, so only the addresses
   // are kept inside this panel's Qmax * n1 rows (EDGE: the tile that reaches past
@@ -855,12 +889,18 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       const float* Af = reinterpret_cast<const float*>(A);
       // full tiles (all 1024 rows below n), then the rest row-clamped
       const int64_t full = n2 == 1024 ? std::min<int64_t>(n / 1024, n1) : 0;
+      const int64_t P = panels;
+      const int kP1Group = Qmax >= 512 ? kP1GroupWrite : kP1GroupRead;
       if (full > 0)
-        hipLaunchKernelGGL(k_srht_p1<false>, dim3(panels, (unsigned)full), dim3(256), 0, s, Af, n,
-                           d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, (int64_t)0);
+        hipLaunchKernelGGL(k_srht_p1<false>, dim3((unsigned)(P * full)), dim3(256), 0, s, Af, n, d,
+                           lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, (int64_t)0, full, P,
+                           kP1Group);
       if (full < n1)
-        hipLaunchKernelGGL(k_srht_p1<true>, dim3(panels, (unsigned)(n1 - full)), dim3(256), 0, s,
-                           Af, n, d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, full);
+        hipLaunchKernelGGL(k_srht_p1<true>, dim3((unsigned)(P * (n1 - full))), dim3(256), 0, s,
+                           Af, n, d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, full, n1 - full,
+                           P, kP1Group);
+      hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((Qmax * n1 + 255) / 256)), dim3(256), 0, s,
+                         B.qlist, B.kmap, B.qcount, Qmax, n1, n2, B.dest2);
       const int64_t t2 = (Qmax * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
       const int64_t t2full = Qmax * n1 / kP2Rows;
       const float* Z = Zw;
@@ -869,12 +909,11 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
         OutT* o = reinterpret_cast<OutT*>(SA);
         if (t2full > 0)
           hipLaunchKernelGGL((k_srht_p2<OutT, false>), dim3((unsigned)np16, (unsigned)t2full),
-                             dim3(256), 0, s, Z, Qmax, lb1, n2, d, B.qlist, B.kmap, B.qcount, o,
-                             ldsa, (float)scale, (int64_t)0);
+                             dim3(256), 0, s, Z, Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa,
+                             (float)scale, (int64_t)0);
         if (t2 > t2full)
           hipLaunchKernelGGL((k_srht_p2<OutT, true>), dim3((unsigned)np16, 1u), dim3(256), 0, s, Z,
-                             Qmax, lb1, n2, d, B.qlist, B.kmap, B.qcount, o, ldsa, (float)scale,
-                             t2full);
+                             Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full);
       };
       if (bf16)
         p2(uint16_t{});

@@ -156,7 +156,8 @@ struct DevBuf {
 struct DeviceScratch {
   std::mutex mu;
   // SRHT
-  DevBuf hist, signs, kmap, state, cand_key, cand_idx, blk_less, used, qmap, qlist, qcount, zbuf, rows;
+  DevBuf hist, signs, kmap, state, cand_key, cand_idx, blk_less, used, qmap, qlist, qcount, zbuf, rows,
+      dest2;
   // gradient partials, vectors, control
   DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
   // solver-owned sketch and factor
@@ -323,10 +324,11 @@ static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, Srh
   RS_TRY(S.qlist.ensure(1024 * sizeof(int32_t)));
   RS_TRY(S.qcount.ensure(sizeof(int32_t)));
   RS_TRY(S.zbuf.ensure((size_t)std::max<int64_t>(zbytes, 256)));
+  RS_TRY(S.dest2.ensure((size_t)npad * sizeof(int32_t)));
   B = SrhtBuffers{S.hist.as<uint32_t>(), S.signs.as<int8_t>(),   S.kmap.as<int32_t>(),
                   S.state.p,             S.cand_key.as<uint64_t>(), S.cand_idx.as<int64_t>(),
                   S.blk_less.as<uint32_t>(), S.used.as<int32_t>(), S.qmap.as<int32_t>(),
-                  S.qlist.as<int32_t>(), S.qcount.as<int32_t>(), S.zbuf.p};
+                  S.qlist.as<int32_t>(), S.qcount.as<int32_t>(), S.zbuf.p, S.dest2.as<int32_t>()};
   return RS_OK;
 }
 

@@ -51,6 +51,7 @@ struct SrhtBuffers {
   int32_t* qlist;      // 1024
   int32_t* qcount;     // 1
   void* zbuf;          // pass-1 output: n1 * Qmax rows of ldz elements
+  int32_t* dest2;      // npad: SA row of each second-pass row (q n1 + r1), or -1
 };
 rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t npad, int64_t m,
                       int64_t n2, int64_t* rows, hipStream_t s);
