@@ -3,12 +3,14 @@ and kernel-trace summaries under profiles/ are taken from).
 
   python -m paper_2006_05874_amd.kernel_bench gradient --n N --d D --k K --reps R
   python -m paper_2006_05874_amd.kernel_bench srht --n N --d D --m M --sa bf16 --reps R
+  python -m paper_2006_05874_amd.kernel_bench gaussian --n N --d D --m M --sa bf16 --reps R
 
 A is N x D FP32 with i.i.d. N(0, 1/N) entries and b N(0, 1), drawn on the device
 (the values do not change the traffic of either pass).  Each call is timed by HIP
 events on the stream; the line printed per call gives milliseconds and the
 algorithmic bytes over that time (gradient: N D 4 + N 4 per pass, A and b read
-once; SRHT: N D 4 + M D s, A read once and SA written).  --copy-calibration first
+once; SRHT: N D 4 + M D s, A read once and SA written; Gaussian: also 2 M N D flops,
+printed as TFLOP/s).  --copy-calibration first
 runs one 256 MiB device-to-device copy, the reference for HBM counters.
 """
 import argparse
@@ -21,7 +23,7 @@ from . import rs
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["gradient", "srht"])
+    ap.add_argument("what", choices=["gradient", "srht", "gaussian"])
     ap.add_argument("--n", type=int, default=1 << 21)
     ap.add_argument("--d", type=int, default=8192)
     ap.add_argument("--k", type=int, default=2)
@@ -55,10 +57,11 @@ def main(argv=None):
     else:
         es = {"f32": 4, "bf16": 2, "fp8": 1}[a.sa]
         sid = [0]
+        sketch = rs.rs_sketch_srht if a.what == "srht" else rs.rs_sketch_gaussian
 
         def call():
             sid[0] += 1
-            return rs.rs_sketch_srht(A, a.m, sketch_id=sid[0], sa_dtype=a.sa)
+            return sketch(A, a.m, sketch_id=sid[0], sa_dtype=a.sa)
         alg = n * d * 4 + a.m * d * es
     call()
     torch.cuda.synchronize()
@@ -70,8 +73,9 @@ def main(argv=None):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        print(f"{a.what} n={n} d={d} rep {r}: {ms:.3f} ms, {alg / ms / 1e6:.1f} GB/s algorithmic",
-              flush=True)
+        extra = (f", {2.0 * a.m * n * d / ms / 1e9:.1f} TFLOP/s" if a.what == "gaussian" else "")
+        print(f"{a.what} n={n} d={d} rep {r}: {ms:.3f} ms, {alg / ms / 1e6:.1f} GB/s algorithmic"
+              + extra, flush=True)
     return 0
 
 

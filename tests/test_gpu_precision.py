@@ -55,13 +55,35 @@ def test_srht_fp8_codes_and_scales(rs, n, d, m):
                                rtol=0, atol=1e-4 * np.abs(S32).max())
 
 
-def test_gaussian_bf16_and_fp8(rs):
+@pytest.mark.parametrize("n,d,m", [(2048, 72, 40), (3001, 300, 130), (65536, 40, 16)])
+def test_gaussian_bf16_matrix_core_product(rs, n, d, m):
+    """The BF16 Gaussian sketch is the product of BF16-rounded inputs on the matrix
+    cores: SA = bf16(S) bf16(A) / sqrt(m) with FP32 accumulation, stored in BF16.
+    Against the oracle's FP64 product of the same rounded inputs; the bound adds
+    the FP32 accumulation of n products, the final BF16 rounding and one BF16 step
+    of one entry of S per row (the device's FP32 Box-Muller value and the
+    oracle's FP64 one can round to neighbouring BF16 values when they straddle a
+    rounding midpoint).  Ragged d and n, and n = 65536 with m = 16 (the split over
+    A's rows)."""
+    rng = np.random.default_rng(n + d + m)
+    A = rng.standard_normal((n, d)).astype(np.float32)
+    Ad = dev_padded(A, rs)
+    S16 = host(rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2, sa_dtype="bf16").float())
+    z = sketch.gaussian_matrix(3, 2, m, n, precision="f32") * np.sqrt(m)
+    Sq = lowprec.bf16_round(z)
+    Aq = lowprec.bf16_round(A.astype(np.float64))
+    want = Sq @ Aq / np.sqrt(m)
+    absprod = np.abs(Sq) @ np.abs(Aq) / np.sqrt(m)
+    flip = 2.0 ** -8 * np.abs(Sq).max(axis=1)[:, None] * np.abs(Aq).max(axis=0)[None, :] / np.sqrt(m)
+    tol = 2.0 ** -8 * np.abs(want) + n * 2.0 ** -24 * absprod + flip + 1e-30
+    assert np.all(np.abs(S16.astype(np.float64) - want) <= tol)
+
+
+def test_gaussian_fp8(rs):
     n, d, m = 2048, 72, 40
     A = np.random.default_rng(9).standard_normal((n, d)).astype(np.float32)
     Ad = dev_padded(A, rs)
     S32 = host(rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2)).astype(np.float64)
-    S16 = host(rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2, sa_dtype="bf16").float())
-    np.testing.assert_array_equal(S16.astype(np.float64), lowprec.bf16_round(S32))
     codes, scale = rs.rs_sketch_gaussian(Ad, m, seed=3, sketch_id=2, sa_dtype="fp8")
     want_codes, want_scale, _ = lowprec.fp8_quantize(S32)
     np.testing.assert_array_equal(host(scale).astype(np.float64), want_scale)
