@@ -136,11 +136,13 @@ typedef struct rs_factor rs_factor;
 
 /* Factor the sketched Hessian H_S = (SA)^T SA + nu^2 I (eq. (3))
  * for repeated solves.  m < d: Woodbury identity through the m x m matrix
- * nu^2 I_m + SA SA^T (proof of Theorem 7); m >= d: the d x d matrix itself.  The
- * Gram is accumulated in FP32 (FP64 for F64 SA) on the matrix cores, the
- * Cholesky factor and its triangular inverse are FP64.
- *   SA    : m x d device array (borrowed: it must stay valid and unchanged while
- *           *out is used; the Woodbury branch reads it on every apply).
+ * nu^2 I_m + SA SA^T = L L^T (proof of Theorem 7); the handle keeps the whitened
+ * sketch C = L^-1 SA (m x d, FP64) and applies H_S^-1 g = (g - C^T (C g)) / nu^2,
+ * O(m d) per apply and m d doubles of memory (no d x d inverse).  m >= d: the
+ * d x d matrix itself, applied through its explicit FP64 inverse.  The Gram is
+ * accumulated in FP32 (FP64 for F64 SA) on the matrix cores, the Cholesky factor
+ * and its triangular inverse are FP64.
+ *   SA    : m x d device array, read during this call only.
  *   nu2   : > 0.
  *   out   : host pointer receiving a handle; release with rs_factor_destroy.
  * Synchronizes the stream (checks the pivots); RS_ERR_NOT_SPD on a failed pivot. */

@@ -1377,8 +1377,9 @@ rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
     hipLaunchKernelGGL(k_chol_step, dim3((unsigned)(nfac + nupd), 1, Bz), dim3(256), 0, s, F.M,
                        pp, k, nblk, F.Linv, F.info, p, zb);
   }
-  // 3. explicit inverse (skipped when the caller only needs L and L^-1)
-  if (!F.Hinv) return check_launch("factor");
+  // 3. explicit inverse (skipped when the caller only needs L and L^-1; the
+  //    Woodbury route with cw_only stops at the whitened sketch)
+  if (!F.Hinv && !(wood && F.cw_only)) return check_launch("factor");
   const int64_t dp = pad64(d);
   if (!wood) {
     const int ch = lauum_chunk(nblk);
@@ -1412,6 +1413,7 @@ rs_status factor_finish(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
       hipLaunchKernelGGL((k_whiten<QOpnd>), g2, dim3(256), 0, s, F.Linv, pp, Bo, d, F.Cw, dp,
                          zb);
     }
+    if (F.cw_only) return check_launch("factor");
     const int dblk = (int)(dp / NB);
     hipLaunchKernelGGL(k_woodbury_inv, dim3((unsigned)(dblk * (dblk + 1) / 2), 1, Bz), dim3(256),
                        0, s, F.Cw, dp, pp, 1.0 / nu2, dp, F.Hinv, dp, zb);

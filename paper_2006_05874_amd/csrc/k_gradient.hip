@@ -293,7 +293,6 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
 #pragma unroll
         for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
       }
-    float s[R][K];
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll

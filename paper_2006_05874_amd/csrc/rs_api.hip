@@ -160,8 +160,8 @@ struct DeviceScratch {
       dest2;
   // gradient partials, vectors, control
   DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
-  // solver-owned sketch and factor
-  DevBuf sa, fM, fLinv, fHinv, fCw, fGram;
+  // solver-owned sketch and factor (wbuf: scratch of the Woodbury-form apply)
+  DevBuf sa, fM, fLinv, fHinv, fCw, fGram, wbuf;
   // FP8 staging: FP32 sketch, column maxima, per-column scales
   DevBuf sa_tmp, colmax, sa_scale;
   // nested resampling: H D A of the whole padded A, and the unscaled Gaussian rows
@@ -465,10 +465,20 @@ using namespace rs;
 struct rs_factor {
   int64_t m, d, p, pp, dp;
   double nu2;
-  bool wood;
-  DevBuf M, Linv, Hinv, Cw, info, rpart, gram;
+  bool wood;  // m < d: applied through Cw = L^-1 SA, no d x d inverse
+  DevBuf M, Linv, Hinv, Cw, info, rpart, gram, wbuf;
   rs_dtype sa_t;
 };
+
+// gtilde = H_S^-1 G of a factor handle (either route), partial sums into rpart
+// (apply_blocks(d) blocks).
+static rs_status factor_apply_any(const rs_factor* F, const double* G, int k, double* GT,
+                                  double* rpart, const int* status, hipStream_t s) {
+  if (F->wood)
+    return wapply_launch(F->Cw.as<double>(), F->dp, F->m, F->d, F->nu2, G, k, GT, rpart,
+                         apply_blocks(F->d), F->wbuf.as<double>(), status, s);
+  return apply_launch(F->Hinv.as<double>(), F->dp, F->d, G, k, GT, rpart, status, s);
+}
 
 extern "C" {
 
@@ -606,8 +616,9 @@ static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
   F->nu2 = nu2;
   RS_TRY(F->M.ensure(factor_bytes_M(m, d)));
   RS_TRY(F->Linv.ensure(factor_bytes_M(m, d)));
-  RS_TRY(F->Hinv.ensure(factor_bytes_Hinv(d)));
+  if (!F->wood) RS_TRY(F->Hinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(F->Cw.ensure(factor_bytes_Cw(m, d)));
+  if (F->wood) RS_TRY(F->wbuf.ensure(wapply_scratch_doubles(m, d) * sizeof(double)));
   RS_TRY(F->info.ensure(sizeof(int), true));
   RS_TRY(F->rpart.ensure((size_t)apply_blocks(d) * 4 * sizeof(double)));
   RS_TRY(F->gram.ensure(factor_bytes_gram(m, d, F->sa_t)));
@@ -630,9 +641,10 @@ rs_status rs_factor_woodbury(const void* SA, rs_dtype sa_t, const float* sa_col_
   F->sa_t = sa_t;
   rs_status st = factor_alloc(F, m, d, nu2);
   if (st == RS_OK) {
-    FactorBuffers B{F->M.as<double>(), F->Linv.as<double>(), F->Hinv.as<double>(),
-                    F->Cw.as<double>(), F->info.as<int>(), F->gram.p, F->gram.bytes,
-                    F->Cw.bytes};
+    FactorBuffers B{F->M.as<double>(), F->Linv.as<double>(),
+                    F->wood ? nullptr : F->Hinv.as<double>(), F->Cw.as<double>(),
+                    F->info.as<int>(), F->gram.p, F->gram.bytes, F->Cw.bytes};
+    B.cw_only = F->wood;
     hipError_t e = hipMemsetAsync(B.info, 0, sizeof(int), stream);
     if (e != hipSuccess) st = set_error(RS_ERR_HIP, "hipMemsetAsync failed");
     if (st == RS_OK) st = factor_build(B, SA, sa_t, sa_col_scale, m, d, ldsa, nu2, stream);
@@ -656,8 +668,7 @@ rs_status rs_factor_apply(const rs_factor* F, const double* g, double* gtilde, d
                           hipStream_t stream) {
   if (!F || !g || !gtilde || !r) return set_error(RS_ERR_ARG, "rs_factor_apply: null argument");
   if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "rs_factor_apply: k must be in 1..4");
-  RS_TRY(apply_launch(F->Hinv.as<double>(), F->dp, F->d, g, (int)k, gtilde,
-                      F->rpart.as<double>(), nullptr, stream));
+  RS_TRY(factor_apply_any(F, g, (int)k, gtilde, F->rpart.as<double>(), nullptr, stream));
   return rsum_launch(F->rpart.as<double>(), apply_blocks(F->d), (int)k, r, stream);
 }
 
@@ -791,8 +802,7 @@ rs_status rs_ihs_step(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
   RS_TRY(candidates_launch(K, d, st->x, st->x_prev, st->gtilde, X, p->mu_p, p->beta_p, p->mu_gd,
                            status, stream));
   RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, X, K, G, status, stream));
-  RS_TRY(apply_launch(F->Hinv.as<double>(), F->dp, d, G, K, GT, S->rpart.as<double>(), status,
-                      stream));
+  RS_TRY(factor_apply_any(F, G, K, GT, S->rpart.as<double>(), status, stream));
   RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, st->x, st->x_prev,
                        st->g, st->gtilde, S->ev.as<int32_t>(), 0, stream));
   RS_HIP(hipMemcpyAsync(&h, dctl, sizeof(DevCtl), hipMemcpyDeviceToHost, stream));
@@ -996,7 +1006,9 @@ struct SolveJob {
   DevCtl* dctl = nullptr;
   int* finfo = nullptr;
   const int* status = nullptr;
-  const double* Hinv = nullptr;
+  const double* Hinv = nullptr;  // m >= d: explicit inverse of the d x d factor
+  bool wood = false;             // m < d: apply through Cw = L^-1 SA
+  const double* Cw = nullptr;
   std::vector<int32_t> dbl_t;  // step index of each doubling
   std::vector<int64_t> dbl_m;  // m after it
   DevCtl h{};
@@ -1011,8 +1023,8 @@ struct SolveJob {
   int phase = 1;
   int64_t m_init_used = 0;
   // queued steps replayed from HIP graphs (one for a single step, one for
-  // check_every steps), captured on first use: every pointer they touch is fixed
-  // for the job's lifetime
+  // check_every steps), captured on first use under the current factor and
+  // dropped when the job refactors (the apply's route and buffers follow m)
   bool use_graph = false;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   NestedCache ncache;
@@ -1036,13 +1048,21 @@ struct SolveJob {
     return grad_any(*S, A, a_t, n, d, lda, b, nu2, Xin, k, Gout, st, s, cvec);
   }
 
+  // gtilde = H_S^-1 G under the current factor (either route)
+  rs_status apply(const double* Gin, int k, double* GTout, const int* st) {
+    if (wood)
+      return wapply_launch(Cw, dp, m, d, nu2, Gin, k, GTout, S->rpart.as<double>(), nrp,
+                           S->wbuf.as<double>(), st, stream);
+    return apply_launch(Hinv, dp, d, Gin, k, GTout, S->rpart.as<double>(), st, stream);
+  }
+
   // one step = the gradient pass over the candidates (left in X by the previous
   // decision, or by the start / resample kernels), the apply, and the decision,
   // which also writes the next step's candidates
   rs_status enqueue_steps(int q) {
     for (int it = 0; it < q; ++it) {
       RS_TRY(grad(X, K, G, status, stream));
-      RS_TRY(apply_launch(Hinv, dp, d, G, K, GT, S->rpart.as<double>(), status, stream));
+      RS_TRY(apply(G, K, GT, status));
       RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
                            gt, S->ev.as<int32_t>(), ev_cap, stream, true, snap()));
     }
@@ -1129,19 +1149,35 @@ struct SolveJob {
                       nullptr, stream));
     else
       RS_TRY(gauss_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, stream));
+    // step graphs captured under the previous factor hold its route, sizes and
+    // buffers: they are captured again on next use (the job's queued work has
+    // finished whenever it refactors)
+    for (hipGraphExec_t& gxe : gx)
+      if (gxe) {
+        (void)hipGraphExecDestroy(gxe);
+        gxe = nullptr;
+      }
+    // m < d: the Woodbury route keeps the whitened sketch Cw = L^-1 SA and applies
+    // H_S^-1 through it (O(m d) per apply); m >= d: the explicit d x d inverse
+    const bool w = mm < d;
     RS_TRY(S->fM.ensure(factor_bytes_M(mm, d)));
     RS_TRY(S->fLinv.ensure(factor_bytes_M(mm, d)));
-    RS_TRY(S->fHinv.ensure(factor_bytes_Hinv(d)));
+    if (!w) RS_TRY(S->fHinv.ensure(factor_bytes_Hinv(d)));
     RS_TRY(S->fCw.ensure(factor_bytes_Cw(mm, d)));
     RS_TRY(S->fGram.ensure(factor_bytes_gram(mm, d, sa_t)));
-    FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(), S->fHinv.as<double>(),
-                     S->fCw.as<double>(), finfo, S->fGram.p, S->fGram.bytes, S->fCw.bytes};
+    if (w) RS_TRY(S->wbuf.ensure(wapply_scratch_doubles(mm, d) * sizeof(double)));
+    FactorBuffers FB{S->fM.as<double>(), S->fLinv.as<double>(),
+                     w ? nullptr : S->fHinv.as<double>(), S->fCw.as<double>(), finfo,
+                     S->fGram.p, S->fGram.bytes, S->fCw.bytes};
+    FB.cw_only = w;
     if (reuse)
       RS_TRY(factor_finish(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, 1, FactorBatch{}, stream));
     else
       RS_TRY(factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream));
     if (nc_shared) nc_shared->gram_m = mm;
-    Hinv = S->fHinv.as<double>();
+    wood = w;
+    Hinv = w ? nullptr : S->fHinv.as<double>();
+    Cw = S->fCw.as<double>();
     return RS_OK;
   }
 
@@ -1191,7 +1227,7 @@ struct SolveJob {
     RS_TRY(sketch_and_factor(m, sid));
     RS_HIP(hipStreamWaitEvent(stream, S->join_ev, 0));
     // gtilde_1, r_1 (and r_ref from g(0))
-    RS_TRY(apply_launch(Hinv, dp, d, G, cols, GT, S->rpart.as<double>(), nullptr, stream));
+    RS_TRY(apply(G, cols, GT, nullptr));
     RS_TRY(init_state_launch(dctl, S->rpart.as<double>(), nrp, o.tol, o.max_iter, d, G, GT, x,
                              x_prev, g, gt, gref, m == m_cap ? 1 : 0, stream, next_cand(),
                              snap(), cols));
@@ -1267,7 +1303,7 @@ struct SolveJob {
       dbl_m.push_back(m);
       RS_TRY(sketch_and_factor(m, sid));
       RS_TRY(pack2_launch(d, g, gref, X, stream));
-      RS_TRY(apply_launch(Hinv, dp, d, X, 2, GT, S->rpart.as<double>(), nullptr, stream));
+      RS_TRY(apply(X, 2, GT, nullptr));
       RS_TRY(post_resample_launch(dctl, S->rpart.as<double>(), nrp, o.tol, d, GT, gt,
                                   m == m_cap ? 1 : 0, stream, next_cand(), x, x_prev, snap()));
       applies += 1;
@@ -1407,7 +1443,7 @@ rs_status rs_refreshed_ihs(const void* A, rs_dtype a_t, int64_t n, int64_t d, in
     // a new sketch (sketch_id t - 1) and factor every step, then one step
     RS_TRY(J.sketch_and_factor(m, (uint32_t)(h.t - 1)));
     RS_TRY(grad_any(*S, A, a_t, n, d, lda, b, nu2, x, 1, G, nullptr, stream));
-    RS_TRY(apply_launch(J.Hinv, J.dp, d, G, 1, GT, S->rpart.as<double>(), nullptr, stream));
+    RS_TRY(J.apply(G, 1, GT, nullptr));
     RS_TRY(refresh_step_launch(dctl, S->rpart.as<double>(), J.nrp, d, GT, x, xp, mu, beta,
                                J.o.tol, J.o.max_iter, rhist, rcap, stream));
     int fbad = 0;

@@ -89,6 +89,9 @@ struct FactorBuffers {
   void* gram;    // split-K partial Grams
   size_t gram_bytes;
   size_t cw_bytes = 0;  // bytes at Cw (m >= d: scratch of the split inverse product)
+  // m < d: stop at the whitened sketch Cw = L^-1 SA (applied by wapply_launch) and
+  // leave Hinv unwritten
+  bool cw_only = false;
 };
 rs_status factor_build(const FactorBuffers& F, const void* SA, rs_dtype sa_t,
                        const float* colscale, int64_t m, int64_t d, int64_t ldsa, double nu2,
@@ -189,6 +192,13 @@ int apply_blocks(int64_t d);
 rs_status apply_launch(const double* Hinv, int64_t ldh, int64_t d, const double* G, int k,
                        double* Y, double* rpart, const int* status, hipStream_t s);
 rs_status rsum_launch(const double* rpart, int nblk, int k, double* r, hipStream_t s);
+// The Woodbury form for m < d: gtilde = (G - C^T (C G)) / nu^2 with C = L^-1 SA
+// (m x d at leading dimension ldc), the same rpart layout (nrp >= ceil(d / 256)
+// blocks) as apply_launch; scratch: wapply_scratch_doubles(m, d) doubles.
+size_t wapply_scratch_doubles(int64_t m, int64_t d);
+rs_status wapply_launch(const double* C, int64_t ldc, int64_t m, int64_t d, double nu2,
+                        const double* G, int k, double* GT, double* rpart, int nrp,
+                        double* scratch, const int* status, hipStream_t s);
 
 // ---------------------------------------------------------------- control
 enum {
