@@ -83,26 +83,42 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_partial_65536x1024_f32_traffic.txt")
-GRAD_SOURCES = [os.path.join(ROOT, "paper_2006_05874_amd", "csrc", f)
-                for f in ("k_gradient.hip", "rs_device.hpp")]
+TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "k_grad_wide_2p21x8192_f32_traffic.txt")
+SRHT_TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "k_srht_2p21x8192_m2048_bf16_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_2006_05874_amd", "csrc")
+GRAD_SOURCES = [os.path.join(CSRC, f) for f in ("k_gradient.hip", "rs_device.hpp")]
+SRHT_SOURCES = [os.path.join(CSRC, f) for f in ("k_srht.hip", "rs_device.hpp")]
 
 
-def recorded_traffic():
-    """HBM bytes per gradient launch from the committed counter summary, or None
-    when the kernel sources changed since the counters were taken."""
+def recorded_traffic_all(path, sources):
+    """HBM bytes per launch of each kernel of a committed counter summary
+    ({kernel: bytes}), or None when the kernel sources changed since the counters
+    were taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
-        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in GRAD_SOURCES)).hexdigest()
+        text = open(path).read()
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()
     except OSError:
         return None
-    kv = {}
+    out, kernel, src_sha = {}, None, None
     for line in text.splitlines():
-        if ": " in line and not line.startswith("#"):
-            k, v = line.split(": ", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != sha:
+        if ": " not in line or line.startswith("#"):
+            continue
+        k, v = (x.strip() for x in line.split(": ", 1))
+        if k == "kernel_source_sha256":
+            src_sha = v
+        elif k == "kernel":
+            kernel = v
+        elif k == "traffic_bytes_per_launch" and kernel:
+            out[kernel] = float(v)
+    if src_sha != sha or not out:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return out
+
+
+def recorded_traffic(path=TRAFFIC_FILE, sources=GRAD_SOURCES):
+    """HBM bytes per gradient launch from a committed counter summary, or None."""
+    t = recorded_traffic_all(path, sources)
+    return next(iter(t.values())) if t else None
 
 
 def blas_threads():
@@ -601,7 +617,13 @@ def run_c5(args):
     # by HIP events on its stream
     grad_bytes = n * d * 4 + n * 4
     roof = gradient_roofline(rs, lambda: [solve(nu2, main_mode) for nu2 in C5_NU2S], grad_bytes,
-                             "k_grad_partial (A^T(AX-b) pass over 64 GiB)", "one more step")
+                             "k_grad_wide / k_grad_partial (A^T(AX-b) pass over 64 GiB, tuned "
+                             "plan)", "one more step")
+    traffic = recorded_traffic(TRAFFIC_FILE_C5, GRAD_SOURCES)
+    if traffic and list(plans[2])[0] == 512:
+        roof["traffic"] = round(traffic)
+        roof["traffic_source"] = ("profiles/k_grad_wide_2p21x8192_f32_traffic.txt (k = 2 pass, "
+                                  "FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB copy)")
     # the SRHT at the sketch size each learned solve started from (BF16 output),
     # timed by events around the call on its stream
     srht = {}
@@ -624,9 +646,14 @@ def run_c5(args):
         srht[str(nu2)] = {"bound": "hbm", "m": m, "sa_dtype": sdt, "ms_per_sketch": round(ms, 3),
                           "algorithmic_bytes": alg, "achieved": round(ach, 1),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(ach / HBM_PEAK_GBS, 4),
+                          "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                           "region": f"{reps} calls of rs_sketch_srht (selection, both passes), "
                                     "HIP events around them on the stream"}
+        st = recorded_traffic_all(SRHT_TRAFFIC_FILE_C5, SRHT_SOURCES)
+        if st and m == 2048 and sdt == "bf16":
+            srht[str(nu2)]["traffic"] = round(sum(st.values()))
+            srht[str(nu2)]["traffic_source"] = ("profiles/k_srht_2p21x8192_m2048_bf16_traffic.txt "
+                                                "(both passes, counters at m = 2048)")
 
     # the oracle's certificate of every timed solve, after the timed work
     pts = [(nu2, x, info, "main") for nu2, x, info in results]

@@ -84,3 +84,23 @@ def test_headline_certificate_maps_every_solution(monkeypatch):
     for g, w in zip((got[0], got[1], got[4]), want):
         np.testing.assert_allclose(g, w, rtol=1e-9, atol=1e-25)
     assert got[0][2] < 1e-12 and got[4][2] > 1e-3
+
+
+def test_recorded_traffic_needs_the_current_kernel_source(tmp_path):
+    """Counter summaries count only while the kernel sources are the ones they were
+    taken with; every kernel section of a summary is read."""
+    import hashlib
+    import importlib
+    sys.path.insert(0, ROOT)
+    bench = importlib.import_module("bench")
+    src = tmp_path / "k.hip"
+    src.write_text("kernel source\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    summ = tmp_path / "t.txt"
+    summ.write_text("# header: not data\nkernel_source_sha256: " + sha + "\nkernel: a<1>\n"
+                    "traffic_bytes_per_launch: 10.5\nkernel: b<2, 3>\n"
+                    "traffic_bytes_per_launch: 20\n")
+    assert bench.recorded_traffic_all(str(summ), [str(src)]) == {"a<1>": 10.5, "b<2, 3>": 20.0}
+    assert bench.recorded_traffic(str(summ), [str(src)]) == 10.5
+    src.write_text("kernel source, changed\n")
+    assert bench.recorded_traffic_all(str(summ), [str(src)]) is None
