@@ -210,7 +210,14 @@ static DeviceScratch* scratch_for_current() {
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   std::lock_guard<std::mutex> g(mu);
   if ((int)all.size() <= dev) all.resize(dev + 1, nullptr);
-  if (!all[dev]) all[dev] = new DeviceScratch();
+  if (!all[dev]) {
+    all[dev] = new DeviceScratch();
+    // the side stream of single solves is created with the scratch, before any
+    // batch creates its worker streams: streams share the device's few hardware
+    // queues in creation order, and a side stream created later can land on the
+    // caller's queue, which serializes the work meant to overlap
+    (void)all[dev]->ensure_aux();
+  }
   return all[dev];
 }
 
