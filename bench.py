@@ -42,6 +42,28 @@ NU2S = (1e-2, 1e-4)
 HBM_PEAK_GBS = 8000.0
 
 
+def with_error_roots(obj):
+    """Every relative prediction error field (delta(x)/delta(0), a squared norm
+    ratio) gets its square root beside it as <key>_sqrt, at any depth."""
+    if isinstance(obj, dict):
+        out = {}
+        for k, v in obj.items():
+            out[k] = with_error_roots(v)
+            if "rel_pred_err" in k and not k.endswith("_sqrt") and k + "_sqrt" not in obj:
+                if isinstance(v, (int, float)):
+                    out[k + "_sqrt"] = math.sqrt(max(v, 0.0))
+                elif isinstance(v, dict) and all(isinstance(x, (int, float)) for x in v.values()):
+                    out[k + "_sqrt"] = {kk: math.sqrt(max(x, 0.0)) for kk, x in v.items()}
+        return out
+    if isinstance(obj, list):
+        return [with_error_roots(v) for v in obj]
+    return obj
+
+
+def emit(line):
+    print(json.dumps(with_error_roots(line)))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,7 +432,7 @@ def run_c2(args):
         line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p0.A, p0.b)
-    print(json.dumps(line))
+    emit(line)
 
 
 def oracle_gram_chunks(A_dev, b_dev, rows=65536):
@@ -506,7 +528,7 @@ def run_c3(args):
                              "sample": f"one oracle direct FP64 solve of the full {n}x{d} "
                                        f"problem (Gram accumulated from row blocks read back "
                                        f"from the device, Cholesky): {oracle_s:.1f} s"}}
-    print(json.dumps(line))
+    emit(line)
 
 
 def oracle_gradient_bound(A_dev, b_dev, x, nu2, rows=32768):
@@ -667,6 +689,19 @@ def run_c5(args):
             srht[str(nu2)]["traffic_source"] = ("profiles/k_srht_2p21x8192_m2048_bf16_traffic.txt "
                                                 "(both passes, counters at m = 2048)")
 
+    # where a solve's GPU time goes: one more step per mode with the phases timed by
+    # HIP events inside the library (sketches, Grams and factors, the rest)
+    phases = {}
+    rs.set_phase_timing(True)
+    for mode in ([main_mode] + (["plain"] if plain is not None else [])):
+        for nu2 in C5_NU2S:
+            _, inf = solve(nu2, mode)
+            phases.setdefault(mode, {})[str(nu2)] = {
+                "ms_sketch": round(inf["ms_sketch"], 2), "ms_factor": round(inf["ms_factor"], 2),
+                "ms_iterate": round(inf["ms_iterate"], 2), "m_final": inf["m_final"],
+                "doublings": inf["doublings"], "grad_passes": inf["grad_passes"]}
+    rs.set_phase_timing(False)
+
     # the oracle's certificate of every timed solve, after the timed work
     pts = [(nu2, x, info, "main") for nu2, x, info in results]
     if plain is not None:
@@ -732,6 +767,7 @@ def run_c5(args):
                        f"over the stored A (Nystrom k={kny}); {nuniq} distinct solutions judged",
         "solve": sol, "wall_s": round(wall, 3),
         "roofline": roof, "srht_roofline": srht,
+        "phases_ms": phases,
     }
     if plain is not None:
         pok, prel, psol = summary("plain")
@@ -743,7 +779,7 @@ def run_c5(args):
         line["speedup_vs_plain_fp32"] = round(value / plain["value"], 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu
-    print(json.dumps(line))
+    emit(line)
 
 
 def run_c4a(args):
@@ -842,7 +878,7 @@ def run_c4a(args):
                                        f"device, Cholesky): {oracle_s:.1f} s"},
             "speedup_vs_sequential_plain_f32": round(
                 out["grid_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
-    print(json.dumps(line))
+    emit(line)
 
 
 def run_path(args):
@@ -930,7 +966,7 @@ def run_path(args):
     if "cold_f32" in out:
         line["speedup_vs_cold_f32"] = round(out[best]["solves_per_s"]
                                             / out["cold_f32"]["solves_per_s"], 3)
-    print(json.dumps(line))
+    emit(line)
 
 
 def run_dual(args):
@@ -1007,7 +1043,7 @@ def run_dual(args):
                             for v in out.values()),
             "roofline": roof, "cpu_baseline": cpu,
             "modes": out}
-    print(json.dumps(line))
+    emit(line)
 
 
 def gradient_roofline(rs, fn, alg_bytes, kernel, region):
@@ -1115,7 +1151,7 @@ def run_refreshed(args):
                             for v in out.values()),
             "roofline": roof, "cpu_baseline": cpu,
             "modes": out}
-    print(json.dumps(line))
+    emit(line)
 
 
 def run_sparse(args):
@@ -1195,7 +1231,7 @@ def run_sparse(args):
             "modes": out,
             "speedup_vs_dense_srht_f32": round(out[best]["solves_per_s"]
                                                / out["dense_srht_f32"]["solves_per_s"], 3)}
-    print(json.dumps(line))
+    emit(line)
 
 
 def run_c4b(args):
@@ -1310,7 +1346,7 @@ def run_c4b(args):
             "speedup_vs_sequential_plain_f32": round(
                 out["learned_bf16_batched"]["solves_per_s"] /
                 out["sequential_plain_f32"]["solves_per_s"], 3)}
-    print(json.dumps(line))
+    emit(line)
 
 
 if __name__ == "__main__":

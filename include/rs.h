@@ -269,6 +269,15 @@ typedef struct {
  * warm starts along a regularization path).  g(0) is one more column of the
  * first gradient pass.  A start at the origin is unchanged by the flag. */
 #define RS_SOLVE_REF_AT_ZERO 2
+/* rs_solve_opts.flags: time the solve's phases on its stream with HIP events
+ * (rs_adaptive_solve and its CSR, dual and learned forms, the batch forms,
+ * rs_refreshed_ihs and rs_solve_path; rs_solve_nu_grid leaves the fields 0)
+ * into rs_solve_info.ms_sketch (every sketch the run
+ * forms), ms_factor (every Gram and factor) and ms_iterate (the rest of the
+ * run's GPU time line: gradients, applies, decisions, the learned start's
+ * features, and the waits between them), in milliseconds.  Off by default (the
+ * events add packets to the stream). */
+#define RS_SOLVE_TIMING 4
 
 /* Event kinds recorded in rs_solve_info. */
 #define RS_EVENT_POLYAK 0
@@ -285,7 +294,7 @@ typedef struct {
   int32_t event_kind[RS_MAX_EVENTS];    /* RS_EVENT_* in order */
   int32_t event_t[RS_MAX_EVENTS];       /* step index t of each event */
   int64_t event_m[RS_MAX_EVENTS];       /* sketch size after the event */
-  double ms_sketch, ms_factor, ms_iterate; /* reserved (written as 0) */
+  double ms_sketch, ms_factor, ms_iterate; /* phase times under RS_SOLVE_TIMING, else 0 */
 } rs_solve_info;
 
 /* Fill opts with the defaults listed above. */

@@ -1056,6 +1056,16 @@ struct SolveJob {
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   NestedCache ncache;
   NestedCache* nc_shared = nullptr;  // a path's cache, kept across its solves
+  // phase timing (RS_SOLVE_TIMING): events around every sketch and factor, and
+  // the first and last work of the run
+  std::vector<hipEvent_t> tev;  // triples: before sketch, after sketch, after factor
+  hipEvent_t tbeg = nullptr, tend = nullptr;
+  bool timing() const { return (o.flags & RS_SOLVE_TIMING) != 0; }
+  rs_status tmark(hipEvent_t* e) {
+    if (!*e) RS_HIP(hipEventCreate(e));
+    RS_HIP(hipEventRecord(*e, stream));
+    return RS_OK;
+  }
   // the dual problem: A holds the data matrix A^T of the dual, b a zero vector,
   // and the gradient subtracts cvec (the primal b, FP64)
   const double* cvec = nullptr;
@@ -1068,6 +1078,9 @@ struct SolveJob {
   ~SolveJob() {
     for (hipGraphExec_t& g : gx)
       if (g) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+    if (tbeg) (void)hipEventDestroy(tbeg);
+    if (tend) (void)hipEventDestroy(tend);
   }
 
   rs_status grad(const double* Xin, int k, double* Gout, const int* st, hipStream_t s) {
@@ -1164,6 +1177,11 @@ struct SolveJob {
     RS_TRY(S->sa.ensure((size_t)mm * ldsa * sa_es));
     RS_TRY(S->sa_scale.ensure((size_t)d * sizeof(float)));
     float* scl = sa_t == RS_FP8E4M3 ? S->sa_scale.as<float>() : nullptr;
+    const size_t tk = tev.size();
+    if (timing()) {
+      tev.resize(tk + 3, nullptr);
+      RS_TRY(tmark(&tev[tk]));
+    }
     if (reuse)
       ;  // SA (and its FP8 column scales) already hold this sketch
     else if (sp)  // nested: the same hash at 2m splits every bucket in two
@@ -1201,10 +1219,12 @@ struct SolveJob {
                      w ? nullptr : S->fHinv.as<double>(), S->fCw.as<double>(), finfo,
                      S->fGram.p, S->fGram.bytes, S->fCw.bytes};
     FB.cw_only = w;
+    if (timing()) RS_TRY(tmark(&tev[tk + 1]));
     if (reuse)
       RS_TRY(factor_finish(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, 1, FactorBatch{}, stream));
     else
       RS_TRY(factor_build(FB, S->sa.p, sa_t, scl, mm, d, ldsa, nu2, stream));
+    if (timing()) RS_TRY(tmark(&tev[tk + 2]));
     if (nc_shared) nc_shared->gram_m = mm;
     wood = w;
     Hinv = w ? nullptr : S->fHinv.as<double>();
@@ -1276,6 +1296,7 @@ struct SolveJob {
 
   // first work of the job: the learned prediction if a model is given, else start()
   rs_status begin() {
+    if (timing()) RS_TRY(tmark(&tbeg));
     if (!lp_params) {
       m_init_used = m;
       return start();
@@ -1356,6 +1377,20 @@ struct SolveJob {
 
   rs_status conclude() {
     done = true;
+    double ms_sk = 0.0, ms_fa = 0.0, ms_all = 0.0;
+    if (timing() && tbeg) {
+      RS_TRY(tmark(&tend));
+      RS_HIP(hipEventSynchronize(tend));
+      float v = 0.0f;
+      RS_HIP(hipEventElapsedTime(&v, tbeg, tend));
+      ms_all = v;
+      for (size_t i = 0; i + 2 < tev.size(); i += 3) {
+        RS_HIP(hipEventElapsedTime(&v, tev[i], tev[i + 1]));
+        ms_sk += v;
+        RS_HIP(hipEventElapsedTime(&v, tev[i + 1], tev[i + 2]));
+        ms_fa += v;
+      }
+    }
     const int64_t tfin = h.t;
     std::vector<int32_t> kinds((size_t)std::max<int64_t>(tfin, 1), -1);
     if (tfin > 1) {
@@ -1366,6 +1401,9 @@ struct SolveJob {
     }
     fill_info(info, result, h, kinds.data(), (int64_t)kinds.size(), dbl_t, dbl_m,
               std::min<int64_t>(std::max<int64_t>(o.m_init, 1), m_cap), m, applies);
+    info->ms_sketch = ms_sk;
+    info->ms_factor = ms_fa;
+    info->ms_iterate = ms_all > 0.0 ? std::max(0.0, ms_all - ms_sk - ms_fa) : 0.0;
     return result;
   }
 };

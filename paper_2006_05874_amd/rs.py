@@ -402,6 +402,16 @@ def rs_ihs_step(A, b, nu2, F, params, variant, state):
     return {"accepted": out.accepted, "r_p": out.r_p, "r_gd": out.r_gd}
 
 
+RS_SOLVE_TIMING = 4
+_TIMING = [False]
+
+
+def set_phase_timing(on=True):
+    """Solves started after this call time their phases (RS_SOLVE_TIMING): their
+    info dicts carry ms_sketch, ms_factor and ms_iterate."""
+    _TIMING[0] = bool(on)
+
+
 def _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
           seed, check_every):
     o = SolveOpts()
@@ -410,6 +420,8 @@ def _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, t
     o.sketch_dtype = DTYPES[sketch_dtype or ("f64" if a_t == 0 else "f32")]
     o.rho, o.eta, o.m_init, o.m_max, o.tol = rho, eta, m_init, m_max, tol
     o.max_iter, o.seed, o.check_every = max_iter, seed, check_every
+    if _TIMING[0]:
+        o.flags |= RS_SOLVE_TIMING
     return o
 
 
@@ -423,7 +435,7 @@ def rs_adaptive_solve(A, b, nu2, kind="srht", variant="polyak", resample="fresh"
     n, d = A.shape
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
-    o.flags = RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
+    o.flags |= RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
     x = _start(x0, d, A.device, "rs_adaptive_solve")
     bc = _rhs(b, A, "rs_adaptive_solve")
     info = SolveInfo()
@@ -464,7 +476,7 @@ def rs_solve_batch(problems, kind="srht", variant="polyak", resample="fresh",
     a_ts, P, xs, bs = _batch_problems(problems, "rs_solve_batch")
     o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol,
               max_iter, seed, check_every)
-    o.flags = RS_SOLVE_GRAPH_STEPS if graph_steps else 0
+    o.flags |= RS_SOLVE_GRAPH_STEPS if graph_steps else 0
     infos = (SolveInfo * len(problems))()
     st = load().rs_solve_batch(P, len(problems), ctypes.byref(o), infos, workers, _stream())
     if st != RS_OK and raise_on_error and st != RS_ERR_NO_CONVERGENCE:
@@ -484,7 +496,7 @@ def rs_learned_solve_batch(problems, params, mu, sd, kind="srht", variant="polya
     a_ts, P, xs, bs = _batch_problems(problems, "rs_learned_solve_batch")
     o = _opts(a_ts[0], kind, variant, resample, sketch_dtype, rho, eta, 1, m_max, tol,
               max_iter, seed, check_every)
-    o.flags = RS_SOLVE_GRAPH_STEPS if graph_steps else 0
+    o.flags |= RS_SOLVE_GRAPH_STEPS if graph_steps else 0
     infos = (SolveInfo * len(problems))()
     used = (ctypes.c_int64 * len(problems))()
     st = load().rs_learned_solve_batch(P, len(problems), ctypes.byref(o), _ptr(params), _ptr(mu),
@@ -534,7 +546,7 @@ def rs_adaptive_solve_dual(A, b, nu2, kind="srht", variant="polyak", resample="f
     n, d = A.shape
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
-    o.flags = RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
+    o.flags |= RS_SOLVE_REF_AT_ZERO if ref_at_zero else 0
     z = _start(z0, n, A.device, "rs_adaptive_solve_dual", "z0")
     bc = _rhs(b, A, "rs_adaptive_solve_dual")
     x = torch.zeros(d, dtype=torch.float64, device=A.device)
@@ -620,6 +632,8 @@ def _info(info, st, raise_on_error, where):
         "grad_passes": info.grad_passes, "applies": info.applies,
         "accepted_polyak": info.accepted_polyak, "accepted_gd": info.accepted_gd,
         "r_final": info.r_final, "r_ref": info.r_ref,
+        "ms_sketch": info.ms_sketch, "ms_factor": info.ms_factor,
+        "ms_iterate": info.ms_iterate,
         "events": [(int(info.event_t[i]), EVENT_NAMES[int(info.event_kind[i])],
                     int(info.event_m[i])) for i in range(info.n_events)],
     }

@@ -104,3 +104,18 @@ def test_recorded_traffic_needs_the_current_kernel_source(tmp_path):
     assert bench.recorded_traffic(str(summ), [str(src)]) == 10.5
     src.write_text("kernel source, changed\n")
     assert bench.recorded_traffic_all(str(summ), [str(src)]) is None
+
+
+def test_every_error_field_gets_its_square_root():
+    import importlib
+    import math
+    sys.path.insert(0, ROOT)
+    bench = importlib.import_module("bench")
+    line = {"rel_pred_err": {"0.01": 1e-8, "0.0001": 4e-10}, "modes": {
+        "a": {"worst_rel_pred_err": 2.5e-9, "x": 1}, "b": {"rel_pred_err_bound": 1e-10}},
+        "rel_pred_err_bound_sqrt": {"0.01": 1e-4}, "rel_pred_err_bound": {"0.01": 1e-8}}
+    out = bench.with_error_roots(line)
+    assert out["rel_pred_err_sqrt"] == {"0.01": 1e-4, "0.0001": 2e-5}
+    assert math.isclose(out["modes"]["a"]["worst_rel_pred_err_sqrt"], 5e-5)
+    assert math.isclose(out["modes"]["b"]["rel_pred_err_bound_sqrt"], 1e-5)
+    assert out["rel_pred_err_bound_sqrt"] == {"0.01": 1e-4}    # kept as given
