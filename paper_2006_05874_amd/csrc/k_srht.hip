@@ -549,10 +549,6 @@ constexpr int kP1GroupRead = 16;
 constexpr int kP1GroupWrite = 4;
 constexpr int kP2J = 64;       // rows per thread
 
-// Pass 1: block (x = 32-column panel, y = pair of 1024-row tiles).  The panel is the
-// fastest grid index, so the blocks in flight read whole row ranges of A rather
-// than one column offset of many rows at the row pitch.  The two tiles 2y, 2y+1 of
-// a block write the two 64-byte halves of the same 128-byte lines of Z.
 // A raw buffer descriptor over `bytes` bytes at `base` (untyped loads; the loads
 // below keep every offset inside the region, they do not rely on its range check).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
