@@ -278,6 +278,13 @@ typedef struct {
  * features, and the waits between them), in milliseconds.  Off by default (the
  * events add packets to the stream). */
 #define RS_SOLVE_TIMING 4
+/* rs_solve_opts.flags, rs_solve_nu_grid only: run each window of check_every
+ * steps of all nu (candidates, the multi-right-hand-side gradient, the apply,
+ * the decision) as one cooperative persistent launch with grid-wide barriers
+ * between the phases, instead of four launches per step (batching form; the
+ * results are the same bit for bit).  The host still resamples and factors
+ * between windows. */
+#define RS_SOLVE_PERSISTENT 8
 
 /* Event kinds recorded in rs_solve_info. */
 #define RS_EVENT_POLYAK 0

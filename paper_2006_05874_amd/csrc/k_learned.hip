@@ -27,15 +27,19 @@ constexpr int kWork = 2 * kHid + 1;            // dz1, dz2, dy per sample
 
 // ------------------------------------------------------------------ features
 // Column sums over a chunk of rows: part[chunk][k][j] = sum_i w_k(i) A[i][j] for
-// the 8 probes and part[chunk][8][j] = sum_i A[i][j]^2, FP64.  Block: 64 lanes x
+// the 8 probes, part[chunk][8][j] = sum_i A[i][j]^2 and, when b is given,
+// part[chunk][9][j] = sum_i b_i A[i][j] (A^T b, the gradient at the origin up to
+// its sign, so a solve started at 0 needs no gradient pass of its own), FP64.  Block: 64 lanes x
 // VEC columns (one 16-byte vector per lane and row), 4 waves taking every 4th
 // row of the chunk, 4 rows per wave in flight; the probe signs of the chunk's
 // rows are drawn once into LDS.  The waves' sums meet in LDS in a fixed order.
 constexpr int kProbeChunkMax = 4096;
+constexpr int kPCols = kProbes + 2;  // the probes, the squared norms, A^T b
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, int64_t n,
-                                                       int64_t d, int64_t lda, uint64_t seed,
+                                                       int64_t d, int64_t lda,
+                                                       const T* __restrict__ b, uint64_t seed,
                                                        int64_t rows_per_chunk,
                                                        double* __restrict__ part) {
   using V = typename VecOf<T>::type;
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, 
   constexpr int COLS = 64 * VEC;
   constexpr int U = 4;
   __shared__ uint8_t sgn[kProbeChunkMax];
-  __shared__ double red[kProbes + 1][COLS];
+  __shared__ double red[kPCols][COLS];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * COLS + lane * VEC;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
@@ -63,9 +67,9 @@ __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, 
 #pragma unroll
   for (int e = 0; e < VEC; ++e) cok[e] = c0 + e < d;
   const int64_t cc = c0 < d ? c0 : 0;
-  double acc[kProbes + 1][VEC];
+  double acc[kPCols][VEC];
 #pragma unroll
-  for (int k = 0; k <= kProbes; ++k)
+  for (int k = 0; k < kPCols; ++k)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[k][e] = 0.0;
   for (int i0 = w; i0 < cnt; i0 += 4 * U) {
@@ -81,12 +85,14 @@ __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, 
       const int i = i0 + 4 * u;
       const bool rok = i < cnt;
       const uint8_t bits = sgn[rok ? i : 0];
+      const double bi = b ? (double)b[r0 + (rok ? i : 0)] : 0.0;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const double x = (rok && cok[e]) ? (double)get(a[u], e) : 0.0;
 #pragma unroll
         for (int k = 0; k < kProbes; ++k) acc[k][e] += ((bits >> k) & 1) ? -x : x;
         acc[kProbes][e] = fma(x, x, acc[kProbes][e]);
+        acc[kProbes + 1][e] = fma(bi, x, acc[kProbes + 1][e]);
       }
     }
   }
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, 
   for (int ww = 0; ww < 4; ++ww) {
     if (w == ww) {
 #pragma unroll
-      for (int k = 0; k <= kProbes; ++k)
+      for (int k = 0; k < kPCols; ++k)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           const int col = lane * VEC + e;
@@ -103,20 +109,20 @@ __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, 
     }
     __syncthreads();
   }
-  for (int e = t; e < (kProbes + 1) * COLS; e += 256) {
+  for (int e = t; e < kPCols * COLS; e += 256) {
     const int k = e / COLS, col = e % COLS;
     const int64_t j = (int64_t)blockIdx.x * COLS + col;
-    if (j < d) part[((int64_t)blockIdx.y * (kProbes + 1) + k) * d + j] = red[k][col];
+    if (j < d) part[((int64_t)blockIdx.y * kPCols + k) * d + j] = red[k][col];
   }
 }
 
-// U[k][j] = sum over chunks (fixed order), k = 0..8.  Block: 8 consecutive
+// U[k][j] = sum over chunks (fixed order), k = 0..9.  Block: 8 consecutive
 // elements x 32 chunk strides, then a tree over the strides in LDS.
 __global__ __launch_bounds__(256) void k_probe_finish(const double* __restrict__ part, int nchunk,
                                                       int64_t d, double* __restrict__ U) {
   __shared__ double sh[32][8];
   const int cl = threadIdx.x & 7, st = threadIdx.x >> 3;
-  const int64_t tot = (int64_t)(kProbes + 1) * d;
+  const int64_t tot = (int64_t)kPCols * d;
   const int64_t e = (int64_t)blockIdx.x * 8 + cl;
   double v = 0.0;
   if (e < tot)
@@ -262,23 +268,47 @@ int feature_chunks(int64_t n, int64_t d, int vec) {
 }
 
 template <typename T>
-rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
-                        double* part, double* U, hipStream_t s) {
+rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
+                        uint64_t seed, double* part, double* U, hipStream_t s) {
   constexpr int VEC = VecOf<T>::n;
   const int64_t rpc = probe_rows_per_chunk(n, d, VEC);
   const int nch = (int)((n + rpc - 1) / rpc);
   const unsigned colblocks = (unsigned)((d + 64 * VEC - 1) / (64 * VEC));
   hipLaunchKernelGGL(k_probe_partial<T>, dim3(colblocks, (unsigned)nch), dim3(256), 0, s, A, n, d,
-                     lda, seed, rpc, part);
-  const int64_t tot = (int64_t)(kProbes + 1) * d;
+                     lda, b, seed, rpc, part);
+  const int64_t tot = (int64_t)kPCols * d;
   hipLaunchKernelGGL(k_probe_finish, dim3((unsigned)((tot + 7) / 8)), dim3(256), 0, s, part, nch,
                      d, U);
   return check_launch("features pass");
 }
-template rs_status features_pass<float>(const float*, int64_t, int64_t, int64_t, uint64_t, double*,
-                                        double*, hipStream_t);
-template rs_status features_pass<double>(const double*, int64_t, int64_t, int64_t, uint64_t,
-                                         double*, double*, hipStream_t);
+// The gradient at a start x = 0 from the features pass: grad f(0) = -A^T b (eq. (1)
+// with x = 0).  One block: if any x_j != 0 the flag stays 0 (the solve's own
+// gradient pass runs); otherwise G = -A^T b and the flag tells that pass to skip.
+__global__ __launch_bounds__(256) void k_start_from_atb(const double* __restrict__ x,
+                                                        const double* __restrict__ atb,
+                                                        int64_t d, double* __restrict__ G,
+                                                        int* __restrict__ skip) {
+  int nz = 0;
+  for (int64_t j = threadIdx.x; j < d; j += 256) nz |= x[j] != 0.0;
+  const int any = __syncthreads_or(nz);
+  if (any) {
+    if (threadIdx.x == 0) *skip = 0;
+    return;
+  }
+  for (int64_t j = threadIdx.x; j < d; j += 256) G[j] = -atb[j];
+  if (threadIdx.x == 0) *skip = 1;
+}
+
+rs_status start_from_atb(const double* x, const double* atb, int64_t d, double* G, int* skip,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_start_from_atb, dim3(1), dim3(256), 0, s, x, atb, d, G, skip);
+  return check_launch("start from A^T b");
+}
+
+template rs_status features_pass<float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                        uint64_t, double*, double*, hipStream_t);
+template rs_status features_pass<double>(const double*, int64_t, int64_t, int64_t, const double*,
+                                         uint64_t, double*, double*, hipStream_t);
 
 rs_status features_final(const double* U, int64_t d, const double* rprobe, int64_t n, double nu2,
                          float* feat, hipStream_t s) {

@@ -871,9 +871,11 @@ void rs_solve_opts_default(rs_solve_opts* o) {
 namespace rs {
 
 // The 16 features of (A, nu^2) into feat (device), on stream; no argument checks.
+// With b (device, n values of a_t; may be null) the same pass over A also leaves
+// A^T b in column kFeatAtbCol of S.pU.
 static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
-                              int64_t d, int64_t lda, double nu2, uint64_t seed, float* feat,
-                              hipStream_t stream) {
+                              int64_t d, int64_t lda, const void* b, double nu2, uint64_t seed,
+                              float* feat, hipStream_t stream) {
   const int64_t npad = next_pow2(n);
   const int64_t m0 = std::min<int64_t>(256, npad);
   const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
@@ -888,19 +890,21 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
   RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
   RS_TRY(S.pinfo.ensure(sizeof(int), true));
   const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
-  RS_TRY(S.ppart.ensure((size_t)nch * 9 * d * sizeof(double)));
-  RS_TRY(S.pU.ensure((size_t)9 * d * sizeof(double)));
-  // 2. (on the side stream, beside 1) one pass over A: the 8 probes A^T w_k and
-  //    the squared column norms; it does not depend on the probe sketch
+  RS_TRY(S.ppart.ensure((size_t)nch * (kFeatAtbCol + 1) * d * sizeof(double)));
+  RS_TRY(S.pU.ensure((size_t)(kFeatAtbCol + 1) * d * sizeof(double)));
+  // 2. (on the side stream, beside 1) one pass over A: the 8 probes A^T w_k, the
+  //    squared column norms and A^T b; it does not depend on the probe sketch
   RS_TRY(S.ensure_aux());
   RS_HIP(hipEventRecord(S.fork_ev, stream));
   RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
   if (a_t == RS_F32)
-    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda, seed,
-                                S.ppart.as<double>(), S.pU.as<double>(), S.aux));
+    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda,
+                                reinterpret_cast<const float*>(b), seed, S.ppart.as<double>(),
+                                S.pU.as<double>(), S.aux));
   else
-    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda, seed,
-                                 S.ppart.as<double>(), S.pU.as<double>(), S.aux));
+    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda,
+                                 reinterpret_cast<const double*>(b), seed, S.ppart.as<double>(),
+                                 S.pU.as<double>(), S.aux));
   RS_HIP(hipEventRecord(S.join_ev, S.aux));
   RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
                   nullptr, nullptr, stream));
@@ -1049,6 +1053,7 @@ struct SolveJob {
   const float* lp_sd = nullptr;
   int phase = 1;
   int64_t m_init_used = 0;
+  bool atb_ready = false;  // the features pass left A^T b in S->pU
   // queued steps replayed from HIP graphs (one for a single step, one for
   // check_every steps), captured on first use under the current factor and
   // dropped when the job refactors (the apply's route and buffers follow m)
@@ -1273,7 +1278,15 @@ struct SolveJob {
       RS_HIP(hipMemsetAsync(X + d, 0, (size_t)d * sizeof(double), S->aux));
       gin = X;
     }
-    RS_TRY(grad(gin, cols, G, nullptr, S->aux));
+    // after a learned prediction, a start at the origin takes g_1 = -A^T b from the
+    // features pass (the same read of A) and its own gradient pass returns at once
+    const int* gskip = nullptr;
+    if (atb_ready && cols == 1 && !cvec) {
+      int* fl = reinterpret_cast<int*>(S->ctl.as<char>() + kSnapFlagOff + 8);
+      RS_TRY(start_from_atb(x, S->pU.as<double>() + (int64_t)kFeatAtbCol * d, d, G, fl, S->aux));
+      gskip = fl;
+    }
+    RS_TRY(grad(gin, cols, G, gskip, S->aux));
     RS_HIP(hipEventRecord(S->join_ev, S->aux));
     RS_TRY(sketch_and_factor(m, sid));
     RS_HIP(hipStreamWaitEvent(stream, S->join_ev, 0));
@@ -1305,7 +1318,9 @@ struct SolveJob {
     if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocCoherent));
     if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
     RS_TRY(S->pfeat.ensure(16 * sizeof(float)));
-    RS_TRY(features_run(*S, A, a_t, n, d, lda, nu2, o.seed, S->pfeat.as<float>(), stream));
+    RS_TRY(features_run(*S, A, a_t, n, d, lda, sp ? nullptr : b, nu2, o.seed,
+                        S->pfeat.as<float>(), stream));
+    atb_ready = !sp;
     // the prediction goes straight to pinned host memory
     RS_TRY(mlp_forward(lp_params, S->pfeat.as<float>(), 1, lp_mu, lp_sd,
                        reinterpret_cast<float*>((char*)S->host_pinned + 1024), nullptr, stream));
@@ -1905,6 +1920,23 @@ struct NuGrid {
   }
   int64_t ldr() const { return (2 * count + 3) / 4 * 4; }
 
+  // check_every steps of the listed nu in one cooperative launch
+  rs_status steps_persistent(const GridPtrs& Q, int nl, int K) {
+    const DecideParams dpar{base.prm.mu_p, base.prm.beta_p, base.prm.mu_gd, base.prm.cbar_p,
+                            base.prm.cbar_gd, base.o.tol, base.o.max_iter};
+    if (base.a_t == RS_F32)
+      return grid_steps<float>(Q, nl, K, reinterpret_cast<const float*>(base.A), base.n, base.d,
+                               base.lda, reinterpret_cast<const float*>(base.b),
+                               S->g_nu2.as<double>(), S->g_R.as<float>(), ldr(),
+                               S->g_Gp.as<double>(), S->g_xt.as<float>(), base.prm.mu_p,
+                               base.prm.beta_p, base.prm.mu_gd, dpar, base.check_every, s);
+    return grid_steps<double>(Q, nl, K, reinterpret_cast<const double*>(base.A), base.n, base.d,
+                              base.lda, reinterpret_cast<const double*>(base.b),
+                              S->g_nu2.as<double>(), S->g_R.as<double>(), ldr(),
+                              S->g_Gp.as<double>(), S->g_xt.as<double>(), base.prm.mu_p,
+                              base.prm.beta_p, base.prm.mu_gd, dpar, base.check_every, s);
+  }
+
   rs_status read_ctl() {
     RS_HIP(hipMemcpyAsync(S->g_pinned, S->g_ctl.p, (size_t)count * sizeof(DevCtl),
                           hipMemcpyDeviceToHost, s));
@@ -2044,6 +2076,10 @@ struct NuGrid {
       GridPtrs Q = P;
       Q.zl = sz;
       const int nl = (int)lst.size();
+      if (base.o.flags & RS_SOLVE_PERSISTENT) {
+        RS_TRY(steps_persistent(Q, nl, K));
+        continue;
+      }
       for (int it = 0; it < base.check_every; ++it) {
         RS_TRY(grid_candidates(Q, nl, K, d, base.prm.mu_p, base.prm.beta_p, base.prm.mu_gd, s));
         RS_TRY(gradient(Q.Xc, (int64_t)nl * K, K, sz));
@@ -2113,7 +2149,7 @@ rs_status rs_features(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
   if (npad > (int64_t)1 << 22) return set_error(RS_ERR_SHAPE, "rs_features: padded n above 2^22");
   DeviceScratch* S = scratch_for_current();
   std::lock_guard<std::mutex> g(S->mu);
-  return features_run(*S, A, a_t, n, d, lda, nu2, seed, feat, stream);
+  return features_run(*S, A, a_t, n, d, lda, nullptr, nu2, seed, feat, stream);
 }
 
 rs_status rs_mlp_forward(const float* params, const float* X, int64_t B, const float* mu,

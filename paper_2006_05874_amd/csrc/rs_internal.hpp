@@ -334,6 +334,15 @@ template <typename T>
 rs_status mr_gradient(const T* A, int64_t n, int64_t d, int64_t lda, const T* b, const double* X,
                       int64_t Kc, int kper, const double* nu2, const int* zl, T* R, int64_t ldr,
                       double* Gp, double* G, T* XT, hipStream_t s);
+// Up to iters steps of every listed nu in one cooperative (persistent) launch:
+// candidates, the multi-RHS gradient, the apply and the decision, separated by
+// grid barriers; returns early once no listed nu is running.  Same results as
+// the separate launches (grid_candidates, mr_gradient, grid_apply, grid_decide).
+template <typename T>
+rs_status grid_steps(const GridPtrs& P, int nl, int K, const T* A, int64_t n, int64_t d,
+                     int64_t lda, const T* b, const double* nu2, T* R, int64_t ldr, double* Gp,
+                     T* XT, double mu_p, double beta_p, double mu_gd, const DecideParams& dp,
+                     int iters, hipStream_t s);
 rs_status grid_candidates(const GridPtrs& P, int nl, int K, int64_t d, double mu_p, double beta_p,
                           double mu_gd, hipStream_t s);
 rs_status grid_pack(const GridPtrs& P, int nl, int64_t d, int what, hipStream_t s);
@@ -349,8 +358,15 @@ rs_status grid_post_resample(const GridPtrs& P, int nl, double tol, int64_t d, c
 // ---------------------------------------------------------------- learned form
 int feature_chunks(int64_t n, int64_t d, int vec);
 template <typename T>
-rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, uint64_t seed,
-                        double* part, double* U, hipStream_t s);
+rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, const T* b,
+                        uint64_t seed, double* part, double* U, hipStream_t s);
+// U column of A^T b in the features pass's output (after the 8 probes and the
+// squared column norms)
+constexpr int kFeatAtbCol = 9;
+// G = -A^T b and *skip = 1 when every x_j is 0 (the gradient at the origin), else
+// *skip = 0 and G untouched; one block
+rs_status start_from_atb(const double* x, const double* atb, int64_t d, double* G, int* skip,
+                         hipStream_t s);
 rs_status probe_quads(const void* SA, rs_dtype sa_t, int64_t m, int64_t d, int64_t ldsa,
                       const double* Linv, int64_t ldl, const double* U, double nu2, double* V,
                       double* r, hipStream_t s);

@@ -5,14 +5,20 @@
   python -m paper_2006_05874_amd.learned evaluate --model MODEL --count N --out FILE
 
 Training problems (problem p uses seed 10^6 + p):
-  n = 2^U{12..18}, d = U{64..2048}; singular values either exponential
-  sigma_i = r^i, r ~ U[0.9, 0.999], or power law sigma_i = i^-alpha,
+  with odds 4:1 either n = 2^U{12..18}, d = U{64..2048} or the wide family
+  d = U{2049..8192}, n = 2^U{14..17} (n >= 2d); a third, tall family
+  (problem p uses seed 2 10^6 + p) has n = 2^U{19..21}, d = U{64..1024}.
+  Singular values either
+  exponential sigma_i = r^i, r ~ U[0.9, 0.999], or power law sigma_i = i^-alpha,
   alpha ~ U[0.5, 2] (even odds); nu^2 = sigma_1^2 * 10^U[-6, 0]; b = A x_pl +
   0.1 xi.  A is generated on the device (synth.make_problem_torch).
 Label: log2 of the final sketch size of a plain run (fresh SRHT, FP32 sketch,
 m from 1).  Features: rs_features with the same seed.  Training runs on the GPU
 with rs_mlp_forward / rs_mlp_backward / rs_mlp_adam_step (MSE, Adam, batch 256,
-80/20 split).  Every number the model sees comes from the library's kernels.
+80/20 split); the parameters kept are those of the epoch with the lowest
+validation error.  The output offset (m_init = 2^floor(y + offset)) is then
+chosen on separate held-out problems (p >= 10^5) by total solve time.  Every
+number the model sees comes from the library's kernels.
 """
 import argparse
 import json
@@ -33,8 +39,12 @@ MODEL_PATH = os.path.join(HERE, "models", "m_init_mlp.npz")
 
 def problem_spec(p, seed_base=10 ** 6):
     rng = np.random.default_rng(seed_base + p)
-    n = 2 ** int(rng.integers(12, 19))
-    d = int(rng.integers(64, 2049))
+    if rng.random() < 0.8:
+        n = 2 ** int(rng.integers(12, 19))
+        d = int(rng.integers(64, 2049))
+    else:
+        n = 2 ** int(rng.integers(14, 18))
+        d = int(rng.integers(2049, 8193))
     if rng.random() < 0.5:
         kind, rate = "geom", float(rng.uniform(0.9, 0.999))
     else:
@@ -42,6 +52,23 @@ def problem_spec(p, seed_base=10 ** 6):
     nu2_rel = 10.0 ** float(rng.uniform(-6.0, 0.0))
     return {"p": p, "seed": seed_base + p, "n": n, "d": d, "kind": kind, "rate": rate,
             "nu2": nu2_rel}   # sigma_1 = 1 for both families
+
+
+def tall_spec(p, seed_base=2 * 10 ** 6):
+    """The tall family: n = 2^U{19..21}, d = U{64..1024}, the same spectra and nu^2."""
+    rng = np.random.default_rng(seed_base + p)
+    n = 2 ** int(rng.integers(19, 22))
+    d = int(rng.integers(64, 1025))
+    if rng.random() < 0.5:
+        kind, rate = "geom", float(rng.uniform(0.9, 0.999))
+    else:
+        kind, rate = "poly", float(rng.uniform(0.5, 2.0))
+    nu2_rel = 10.0 ** float(rng.uniform(-6.0, 0.0))
+    return {"p": p, "seed": seed_base + p, "n": n, "d": d, "kind": kind, "rate": rate,
+            "nu2": nu2_rel, "family": "tall"}
+
+
+FAMILIES = {"mixed": problem_spec, "tall": tall_spec}
 
 
 def make_device_problem(spec, device="cuda"):
@@ -57,13 +84,19 @@ def make_device_problem(spec, device="cuda"):
     return A, b
 
 
-def generate(count, first, out, log_every=100):
+def generate(count, first, out, log_every=100, max_seconds=None, family="mixed"):
+    """Features and labels of problems first .. first + count - 1 of a family,
+    saved to out every log_every problems; stops early (after a whole problem)
+    once max_seconds have passed."""
     import torch
     from . import rs
     rows = []
     t0 = time.time()
     for p in range(first, first + count):
-        spec = problem_spec(p)
+        if max_seconds is not None and time.time() - t0 > max_seconds:
+            print(f"[generate] time budget reached after {p - first} problems", flush=True)
+            break
+        spec = FAMILIES[family](p)
         A, b = make_device_problem(spec)
         f = rs.rs_features(A, spec["nu2"], seed=spec["seed"])
         t1 = time.time()
@@ -109,8 +142,12 @@ def _he_init(seed):
     return th
 
 
-def train(F, L, epochs=300, batch=256, lr=1e-3, seed=0, log_every=25, val_frac=0.2):
-    """Train on the GPU with the library's kernels.  Returns (params, mu, sd, history)."""
+def train(F, L, epochs=300, batch=256, lr=1e-3, seed=0, log_every=25, val_frac=0.2,
+          select_every=5):
+    """Train on the GPU with the library's kernels.  The validation error is taken
+    every select_every epochs and the parameters of the lowest one are kept.
+    Returns (params, mu, sd, history, selected) with selected = {"epoch",
+    "val_mse", "train_mse"} of the kept parameters."""
     import torch
     from . import rs
     rng = np.random.default_rng(seed)
@@ -128,6 +165,7 @@ def train(F, L, epochs=300, batch=256, lr=1e-3, seed=0, log_every=25, val_frac=0
     Fva, Lva = dev(F[val].astype(np.float32)), dev(L[val].astype(np.float32))
     hist = []
     step = 0
+    best, best_p = None, P.clone()
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(len(tr))).cuda()
         for b0 in range(0, len(tr) - batch + 1, batch):
@@ -136,14 +174,20 @@ def train(F, L, epochs=300, batch=256, lr=1e-3, seed=0, log_every=25, val_frac=0
             _, C = rs.rs_mlp_forward(P, Ftr[sel], mud, sdd, cache=True)
             G, loss = rs.rs_mlp_backward(P, C, Ltr[sel])
             rs.rs_mlp_adam_step(P, G, M, V, step, lr=lr)
-        if (ep + 1) % log_every == 0 or ep == epochs - 1:
+        last = ep == epochs - 1
+        if (ep + 1) % select_every == 0 or (ep + 1) % log_every == 0 or last:
             ytr = rs.rs_mlp_forward(P, Ftr, mud, sdd)
             yva = rs.rs_mlp_forward(P, Fva, mud, sdd)
             mtr = float(torch.mean((ytr - Ltr) ** 2))
             mva = float(torch.mean((yva - Lva) ** 2))
-            hist.append({"epoch": ep + 1, "train_mse": mtr, "val_mse": mva})
-            print(f"[train] epoch {ep + 1} train mse {mtr:.4f} val mse {mva:.4f}", flush=True)
-    return P.cpu().numpy(), mu, sd, hist
+            if best is None or mva < best["val_mse"]:
+                best = {"epoch": ep + 1, "val_mse": mva, "train_mse": mtr}
+                best_p.copy_(P)
+            if (ep + 1) % log_every == 0 or last:
+                hist.append({"epoch": ep + 1, "train_mse": mtr, "val_mse": mva})
+                print(f"[train] epoch {ep + 1} train mse {mtr:.4f} val mse {mva:.4f}", flush=True)
+    print(f"[train] kept epoch {best['epoch']} (val mse {best['val_mse']:.4f})", flush=True)
+    return best_p.cpu().numpy(), mu, sd, hist, best
 
 
 def save_model(path, params, mu, sd, meta):
@@ -158,7 +202,7 @@ def load_model(path=MODEL_PATH):
     return dev(z["params"]), dev(z["mu"]), dev(z["sd"]), json.loads(str(z["meta"]))
 
 
-def evaluate(model_path, count, first, out, offsets=(0.0,), log_every=50):
+def evaluate(model_path, count, first, out, offsets=(0.0,), log_every=50, family="mixed"):
     """Held-out problems: plain (m from 1, FP32 sketch) against the learned start
     with each bias offset (added to the output bias: m_init = 2^floor(y + off)).
     Records each solve's time, final m, passes and status."""
@@ -167,7 +211,7 @@ def evaluate(model_path, count, first, out, offsets=(0.0,), log_every=50):
     params, mu, sd, _ = load_model(model_path)
     rows = []
     for p in range(first, first + count):
-        spec = problem_spec(p)
+        spec = FAMILIES[family](p)
         A, b = make_device_problem(spec)
         res = {**spec}
         for mode in ["plain"] + [f"learned{o:+.2f}" for o in offsets]:
@@ -222,6 +266,9 @@ def main():
     g.add_argument("--count", type=int, required=True)
     g.add_argument("--first", type=int, default=0)
     g.add_argument("--out", required=True)
+    g.add_argument("--max-seconds", type=float, default=None)
+    g.add_argument("--log-every", type=int, default=100)
+    g.add_argument("--family", default="mixed", choices=sorted(FAMILIES))
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--out", default=MODEL_PATH)
@@ -232,21 +279,25 @@ def main():
     e.add_argument("--first", type=int, default=10 ** 5)
     e.add_argument("--offsets", type=float, nargs="+", default=[0.0])
     e.add_argument("--out", required=True)
+    e.add_argument("--family", default="mixed", choices=sorted(FAMILIES))
     f = sub.add_parser("finalize", help="fold the chosen offset into the output bias")
     f.add_argument("--model", required=True)
     f.add_argument("--eval", required=True)
     f.add_argument("--out", default=MODEL_PATH)
     a = ap.parse_args()
     if a.cmd == "generate":
-        generate(a.count, a.first, a.out)
+        generate(a.count, a.first, a.out, log_every=a.log_every, max_seconds=a.max_seconds,
+                 family=a.family)
     elif a.cmd == "train":
         F, L = load_data(a.data)
-        params, mu, sd, hist = train(F, L, epochs=a.epochs)
+        params, mu, sd, hist, sel = train(F, L, epochs=a.epochs)
         save_model(a.out, params, mu, sd, {"problems": int(len(L)), "history": hist,
+                                           "selected": sel,
                                            "data": [os.path.basename(x) for x in a.data]})
         print(f"saved {a.out}", flush=True)
     elif a.cmd == "evaluate":
-        _, summary = evaluate(a.model, a.count, a.first, a.out, offsets=a.offsets)
+        _, summary = evaluate(a.model, a.count, a.first, a.out, offsets=a.offsets,
+                              family=a.family)
         print(json.dumps(summary, indent=1), flush=True)
     else:
         summary = json.load(open(a.eval))["summary"]

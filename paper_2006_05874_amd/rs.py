@@ -511,16 +511,22 @@ def rs_learned_solve_batch(problems, params, mu, sd, kind="srht", variant="polya
     return out
 
 
+RS_SOLVE_PERSISTENT = 8
+
+
 def rs_solve_nu_grid(A, b, nu2s, kind="srht", variant="polyak", resample="fresh",
                      sketch_dtype=None, rho=0.1, eta=0.01, m_init=1, m_max=0, tol=1e-7,
-                     max_iter=200, seed=0, check_every=4, X0=None, raise_on_error=True):
+                     max_iter=200, seed=0, check_every=4, X0=None, raise_on_error=True,
+                     persistent=False):
     """Solve for every nu^2 in ``nu2s`` on one (A, b).  Returns (X, infos) with X
-    a (len(nu2s), d) float64 tensor of solutions."""
+    a (len(nu2s), d) float64 tensor of solutions.  ``persistent`` runs each window
+    of check_every steps as one cooperative launch (RS_SOLVE_PERSISTENT)."""
     a_t = _mat(A, "rs_solve_nu_grid")
     n, d = A.shape
     k = len(nu2s)
     o = _opts(a_t, kind, variant, resample, sketch_dtype, rho, eta, m_init, m_max, tol, max_iter,
               seed, check_every)
+    o.flags |= RS_SOLVE_PERSISTENT if persistent else 0
     if X0 is not None and tuple(X0.shape) != (k, d):
         raise ValueError(f"rs_solve_nu_grid: X0 must be ({k}, {d})")
     X = (torch.zeros(k, d, dtype=torch.float64, device=A.device) if X0 is None

@@ -138,6 +138,32 @@ def test_learned_solve_falls_back_to_the_adaptive_rule(rs, bias):
     assert ridge.relative_error(ridge.hessian(p.A, p.nu2), host(x), xs) <= 1e-6
 
 
+@pytest.mark.parametrize("bias", [3.0, 6.0])
+def test_learned_start_at_origin_reuses_the_features_pass(rs, bias):
+    # started at 0, a learned solve takes g_1 = -A^T b from the features pass
+    # (eq. (1) at x = 0) instead of a gradient pass of its own: in FP64 it follows
+    # the event trajectory of the plain solve started at the same m and lands on
+    # the same x; a nonzero start still runs its own gradient pass and converges
+    p = config_c1()
+    th = np.zeros(18817, dtype=np.float32)
+    th[-1] = bias
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    A, b = dev_padded(p.A, rs), d(p.b)
+    mu, sd = d(np.zeros(16, np.float32)), d(np.ones(16, np.float32))
+    x, il = rs.rs_learned_solve(A, b, p.nu2, d(th), mu, sd, seed=3)
+    xp, ip = rs.rs_adaptive_solve(A, b, p.nu2, seed=3, m_init=il["m_init"])
+    assert il["events"] == ip["events"] and il["steps"] == ip["steps"]
+    np.testing.assert_allclose(host(x), host(xp), rtol=1e-9, atol=1e-12)
+    xs = ridge.solve_direct(p.A, p.b, p.nu2)
+    x0 = np.full(p.A.shape[1], 0.01)
+    xw, iw = rs.rs_learned_solve(A, b, p.nu2, d(th), mu, sd, seed=3, x0=d(x0))
+    xpw, ipw = rs.rs_adaptive_solve(A, b, p.nu2, seed=3, m_init=iw["m_init"], x0=d(x0))
+    assert iw["events"] == ipw["events"]
+    np.testing.assert_allclose(host(xw), host(xpw), rtol=1e-9, atol=1e-12)
+    for xx in (x, xw):
+        assert ridge.relative_error(ridge.hessian(p.A, p.nu2), host(xx), xs) <= 1e-6
+
+
 def test_trained_model_gains_over_plain(rs):
     # held-out problems of the training distribution (indices never generated for
     # training): the committed predictor must skip most of the doubling ladder and
