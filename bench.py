@@ -801,8 +801,9 @@ def run_c4a(args):
     torch.cuda.synchronize()
     print("[c4a] problem ready", file=sys.stderr, flush=True)
 
-    def grid():
-        X, infos = rs.rs_solve_nu_grid(A, b, nus, sketch_dtype="bf16", raise_on_error=False)
+    def grid(persistent=False):
+        X, infos = rs.rs_solve_nu_grid(A, b, nus, sketch_dtype="bf16", raise_on_error=False,
+                                       persistent=persistent)
         return [(X[k], infos[k]) for k in range(len(nus))]
 
     def seq():
@@ -810,7 +811,11 @@ def run_c4a(args):
                 for nu in nus]
 
     out = {}
-    for name, fn in (("grid_bf16", grid), ("sequential_plain_f32", seq)):
+    # the grid's persistent form (each window of steps one cooperative launch) runs
+    # the same arithmetic: its solutions must equal the default form's bit for bit
+    modes = [("grid_bf16", grid), ("grid_bf16_persistent", lambda: grid(True)),
+             ("sequential_plain_f32", seq)]
+    for name, fn in modes:
         fn()
         torch.cuda.synchronize()
         rs.rs_profile_enable(name == "grid_bf16")
@@ -831,6 +836,8 @@ def run_c4a(args):
     # the multi-RHS gradient passes of the timed grid solves (timed by HIP events):
     # each running nu adds its candidates as columns, 4 n d flops per column
     gres = out["grid_bf16"]["res"]
+    same = all(torch.equal(x0, x1) and i0["events"] == i1["events"]
+               for (x0, i0), (x1, i1) in zip(gres, out["grid_bf16_persistent"]["res"]))
     cols = sum(2 * i["grad_passes"] - 1 for _, i in gres) * args.steps
     gms = out["grid_bf16"]["mr_gradient_ms_total"]
     tfl = 4.0 * n * d * cols / (gms / 1e3) / 1e12 if gms > 0 else 0.0
@@ -877,7 +884,8 @@ def run_c4a(args):
                                        f"problem (Gram from row blocks read back from the "
                                        f"device, Cholesky): {oracle_s:.1f} s"},
             "speedup_vs_sequential_plain_f32": round(
-                out["grid_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3)}
+                out["grid_bf16"]["solves_per_s"] / out["sequential_plain_f32"]["solves_per_s"], 3),
+            "persistent_identical_to_launches": same}
     emit(line)
 
 
