@@ -33,6 +33,19 @@ __device__ __forceinline__ Acc4<T> mfma4(T a, T b, Acc4<T> c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Eight consecutive elements at p (16-byte aligned) as 16-byte loads.
+template <typename T>
+__device__ __forceinline__ void load8(const T* __restrict__ p, T (&v)[8]) {
+  using V = typename VecOf<T>::type;
+  constexpr int VEC = VecOf<T>::n;
+#pragma unroll
+  for (int q = 0; q < 8 / VEC; ++q) {
+    const V x = reinterpret_cast<const V*>(p)[q];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[q * VEC + e] = get(x, e);
+  }
+}
+
 // ---------------------------------------------------------------- R = A X^T - b
 // Block: 128 rows x TC columns of R (TC = 32, 64 or 128, the narrowest that holds
 // Kc), 8 waves of 32 rows x TC/2 columns (two waves per SIMD); k (the d dimension)
@@ -64,11 +77,34 @@ __device__ __forceinline__ void mr_resid_tile(int64_t bx, const T* __restrict__ 
   const bool rok = arow < n, cok = lrow < TC && xcol < Kc;
   const T* asrc = A + (rok ? arow : 0) * lda;
   const T* xsrc = XT + (cok ? xcol : 0) * d;
+  // rows of A are 16-byte aligned (lda a multiple of 16 bytes); rows of XT when d is
+  constexpr int VEC = VecOf<T>::n;
+  const bool xvec = d % VEC == 0;
   T va[8], vx[8];
   auto fetch = [&](int64_t k0) {
+    const int64_t kb = k0 + lk;
+    if (kb + 8 <= d) {
+      // a whole segment: 16-byte loads (the same values as the element loads)
+      if (rok) {
+        load8<T>(asrc + kb, va);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) va[e] = (T)0;
+      }
+      if (cok && xvec) {
+        load8<T>(xsrc + kb, vx);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const T y = xsrc[cok ? kb + e : 0];
+          vx[e] = cok ? y : (T)0;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int64_t k = k0 + lk + e;
+      const int64_t k = kb + e;
       const bool okk = k < d;
       const T x = asrc[(rok && okk) ? k : 0];
       const T y = xsrc[(cok && okk) ? k : 0];
@@ -165,6 +201,24 @@ __device__ __forceinline__ void mr_atr_tile(int64_t bx, int64_t by, const T* __r
     const bool rok = row < row_hi;
     const T* as = A + (rok ? row : 0) * lda;
     const T* rsrc = R + (rok ? row : 0) * ldr;
+    // whole 8-element segments as 16-byte loads (A rows and R rows, ldr a multiple
+    // of 4 elements, are 16-byte aligned): the same values as the element loads
+    const bool wa = j0 + lc + 8 <= d, wr = lc < TC && c0 + lc + 8 <= Kc;
+    if (wa && (wr || !(lc < TC))) {
+      if (rok) {
+        load8<T>(as + j0 + lc, va);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) va[e] = (T)0;
+      }
+      if (rok && wr) {
+        load8<T>(rsrc + c0 + lc, vr);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) vr[e] = (T)0;
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int64_t j = j0 + lc + e, c = c0 + lc + e;

@@ -438,8 +438,8 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
   const int64_t col0 = ((int64_t)blockIdx.y * TT::CW + c) * VEC;
   const bool cvec = col0 < d;
 
-  // destination of each tile row (index loads clamped in bounds, then masked)
   const int64_t tile = blockIdx.x;
+  // destination of each tile row (index loads clamped in bounds, then masked)
   for (int r = t; r < TT::RT; r += 256) {
     int32_t dst = -1;
     if (MODE == 0) {
@@ -460,6 +460,7 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     }
     dest[r] = dst;
   }
+
 
   // load (stage A mapping): every load is issued unconditionally from a clamped
   // in-bounds address and masked afterwards, so all 32 stay in flight
@@ -605,14 +606,6 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
   const int64_t col0 = (panel * TT::CW + c) * 4;
   // columns past d read column 0 and are zeroed (the last panel only)
   const int64_t colr = col0 < d ? col0 : 0;
-  // the kept low indices, and the signs (zero for tile rows past n2 or n, which
-  // then add nothing)
-  for (int r = t; r < TT::RT; r += 256) {
-    const int32_t q = qmap[r < n2 ? r : 0];
-    dest[r] = r < n2 ? q : -1;
-    const int64_t i = row0 + r;
-    sgn[r] = (r < n2 && i < n) ? (float)signs[i < n ? i : 0] : 0.0f;
-  }
   float4 v[J];
   if constexpr (!EDGE) {
     const uint32_t rowb = (uint32_t)(lda * 4);
@@ -629,6 +622,25 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
       i = i < n ? i : n - 1;
       v[j] = *reinterpret_cast<const float4*>(A + i * lda + colr);
     }
+  }
+  // the kept low indices and the signs (zero for tile rows past n2 or n, which then
+  // add nothing), loaded behind the tile so that one memory round trip serves both
+  static_assert(TT::RT == 4 * 256, "four tile rows per thread");
+  int32_t qv[4];
+  int8_t sv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = t + 256 * u;
+    const int64_t i = row0 + r;
+    qv[u] = qmap[r < n2 ? r : 0];
+    sv[u] = signs[(r < n2 && i < n) ? i : 0];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = t + 256 * u;
+    const int64_t i = row0 + r;
+    dest[r] = r < n2 ? qv[u] : -1;
+    sgn[r] = (r < n2 && i < n) ? (float)sv[u] : 0.0f;
   }
   __syncthreads();  // sgn and dest written
 #pragma unroll
@@ -721,7 +733,6 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
   const int c = t & 7;
   const int g = t >> 3;
   const int half = c >> 2;
-  for (int r = t; r < RT; r += 256) dest[r] = r < valid ? dest2[q0 * n1 + r] : -1;
   // rows of q >= Q (whole groups of n1) carry whatever Z holds there: the transform
   // never mixes them with other q and they are not stored, so only the addresses
   // are kept inside this panel's Qmax * n1 rows (EDGE: the tile that reaches past
@@ -742,6 +753,19 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
       const int r = g + 32 * j;
       v[j] = *reinterpret_cast<const float2*>(base + ((int64_t)(r < rmax ? r : rmax) << 4) + 2 * c);
     }
+  }
+  // the SA row of each tile row, loaded behind the tile (one memory round trip)
+  static_assert(RT == 8 * 256, "eight tile rows per thread");
+  int32_t dv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int r = t + 256 * u;
+    dv[u] = dest2[q0 * n1 + (r < valid ? r : 0)];
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int r = t + 256 * u;
+    dest[r] = r < valid ? dv[u] : -1;
   }
   reg_fwht2<J, 6>(v, 5, lb1);
   for (int h = 0; h < 2; ++h) {
