@@ -109,7 +109,9 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_partial_65536x1024_f32_traffic.txt")
 TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "k_grad_wide_2p21x8192_f32_traffic.txt")
-SRHT_TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "k_srht_2p21x8192_m2048_bf16_traffic.txt")
+# counter summaries of the BF16 SRHT at 2^21 x 8192, per sketch size
+SRHT_TRAFFIC_FILES_C5 = {m: os.path.join(ROOT, "profiles", f"k_srht_2p21x8192_m{m}_bf16_traffic.txt")
+                         for m in (512, 4096)}
 CSRC = os.path.join(ROOT, "paper_2006_05874_amd", "csrc")
 GRAD_SOURCES = [os.path.join(CSRC, f) for f in ("k_gradient.hip", "rs_device.hpp")]
 SRHT_SOURCES = [os.path.join(CSRC, f) for f in ("k_srht.hip", "rs_device.hpp")]
@@ -683,11 +685,13 @@ def run_c5(args):
                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                           "region": f"{reps} calls of rs_sketch_srht (selection, both passes), "
                                     "HIP events around them on the stream"}
-        st = recorded_traffic_all(SRHT_TRAFFIC_FILE_C5, SRHT_SOURCES)
-        if st and m == 2048 and sdt == "bf16":
+        tf = SRHT_TRAFFIC_FILES_C5.get(m) if sdt == "bf16" else None
+        st = recorded_traffic_all(tf, SRHT_SOURCES) if tf else None
+        if st:
             srht[str(nu2)]["traffic"] = round(sum(st.values()))
-            srht[str(nu2)]["traffic_source"] = ("profiles/k_srht_2p21x8192_m2048_bf16_traffic.txt "
-                                                "(both passes, counters at m = 2048)")
+            srht[str(nu2)]["traffic_source"] = (os.path.relpath(tf, ROOT) + " (both passes, "
+                                                "FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB "
+                                                "copy)")
 
     # where a solve's GPU time goes: one more step per mode with the phases timed by
     # HIP events inside the library (sketches, Grams and factors, the rest)

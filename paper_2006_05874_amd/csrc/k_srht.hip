@@ -538,9 +538,13 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
 // ---------------------------------------------------------------- FP32 two-pass form
 // For FP32 A with 1 < n1 <= 2048 the intermediate Z (the tile transforms along i2,
 // kept at the Q low indices some sampled row uses) is stored panel-major:
-// Z[((p * Qmax + q) * n1 + i1) * 16 + c], p a 16-column panel.  Pass 2 then reads
-// each (panel, q) as n1 contiguous 64-byte rows and transforms all of i1 (up to 11
-// bits) in one tile, so Z is read exactly once.
+// Z[((p * Qmax + q) * n1 + i1) * 32 + c], p a 32-column panel, so every row a
+// first-pass block stores is one whole 128-byte line (64-byte half lines written by
+// different blocks moved 3.5 TB/s in a store probe at this size, whole lines 4.7,
+// a device copy's rate).  Pass 2 reads each (16-column half of a panel, q) as n1
+// rows of 64 bytes at a 128-byte pitch and transforms all of i1 (up to 11 bits) in
+// one tile, so Z is read exactly once; the two halves of a panel run on the same
+// XCD at the same time, so each line comes from HBM once.
 constexpr int kP2Rows = 2048;  // rows of a pass-2 tile
 // panels per group in the first pass's work order: 16 when the pass mostly reads
 // (few kept low indices), 4 when it also writes an intermediate as large as A
@@ -650,20 +654,19 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
     for (int e = 0; e < 4; ++e) set(v[j], e, get(v[j], e) * (col0 + e < d ? sg : 0.0f));
   }
   tile_fwht<float4, J>(v, lds, g, c, lb);
-  // stores through a buffer descriptor over this block's two 16-column panels of Z
-  // (panel 2 x + (c >> 2); at most 2 * 1024 * 2048 rows of 64 bytes, inside 32-bit
-  // offsets)
-  const uint32_t pbytes = (uint32_t)(Qmax * n1 * 64);
-  const __amdgpu_buffer_rsrc_t zs = buf_rsrc(Z + panel * 2 * Qmax * n1 * 16, 2u * pbytes);
-  const uint32_t lane_off =
-      (uint32_t)(c >> 2) * pbytes + (uint32_t)tile * 64u + (uint32_t)(c & 3) * 16u;
+  // stores through a buffer descriptor over this block's 32-column panel of Z (at
+  // most 1024 * 2048 rows of 128 bytes, inside 32-bit offsets): the 8 lanes of a
+  // tile row write one whole 128-byte line
+  const uint32_t pbytes = (uint32_t)(Qmax * n1 * 128);
+  const __amdgpu_buffer_rsrc_t zs = buf_rsrc(Z + panel * Qmax * n1 * 32, pbytes);
+  const uint32_t lane_off = (uint32_t)tile * 128u + (uint32_t)c * 16u;
   using U4 = __attribute__((ext_vector_type(4))) unsigned int;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int32_t q = dest[32 * g + j];
     if (q >= 0)
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v[j]), zs,
-                                             lane_off + (uint32_t)q * (uint32_t)n1 * 64u, 0, 0);
+                                             lane_off + (uint32_t)q * (uint32_t)n1 * 128u, 0, 0);
   }
 }
 
@@ -691,8 +694,12 @@ __device__ __forceinline__ void reg_fwht2(float2 (&v)[J], int bit_lo, int lb) {
 // wave writes together share those bits, so the write stays contiguous.
 __device__ __forceinline__ int p2_slot(int r, int c) { return (r * 4 + c) ^ (((r >> 6) & 7) << 2); }
 
-// Pass 2: block (x = 16-column panel, y = tile of 2048 rows r = qq n1 + i1, i.e.
-// 2048 / n1 consecutive q).  Thread (g, c) first holds rows g + 32 j (j < 64: row
+// Pass 2: block (16-column half of a 32-column panel, tile of 2048 rows
+// r = qq n1 + i1, i.e. 2048 / n1 consecutive q).  Blocks are dispatched to the 8
+// XCDs in turn (block L on XCD L % 8): blocks 16 k + x and 16 k + 8 + x take the
+// two halves of the same (panel, tile), work item 8 k + x, so both halves of
+// every 128-byte row of Z are read on one XCD at about the same time.
+// Thread (g, c) first holds rows g + 32 j (j < 64: row
 // bits 5..10 in registers), then after the LDS transpose rows 64 g + j (bits 0..4),
 // two columns each.  Row r = (q, r1) of the result goes to SA row kmap[r1 n2 +
 // qlist[q]] when that row is sampled, scaled.
@@ -719,14 +726,20 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
                                                  const int32_t* __restrict__ dest2,
                                                  const int32_t* __restrict__ qcount,
                                                  OutT* __restrict__ out, int64_t ldo,
-                                                 float scale, int64_t ytile0) {
+                                                 float scale, int64_t ytile0, int64_t np32,
+                                                 int64_t ntile) {
   constexpr int RT = kP2Rows;
   constexpr int J = kP2J;
   __shared__ float2 lds[RT * 4];
   __shared__ int32_t dest[RT];
+  const int64_t slot = blockIdx.x >> 3;
+  const int64_t item = (slot >> 1) * 8 + (blockIdx.x & 7);
+  if (item >= np32 * ntile) return;  // uniform: the grid is rounded up to 16 blocks
+  const int64_t p32 = item % np32;
+  const int hsel = (int)(slot & 1);
   const int64_t n1 = (int64_t)1 << lb1;
   const int64_t Q = *qcount;
-  const int64_t q0 = (ytile0 + (int64_t)blockIdx.y) * (RT >> lb1);
+  const int64_t q0 = (ytile0 + item / np32) * (RT >> lb1);
   if (q0 >= Q) return;  // uniform: no sampled low index in this tile
   const int64_t valid = (Q - q0) * n1 < RT ? (Q - q0) * n1 : RT;
   const int t = threadIdx.x;
@@ -737,21 +750,21 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
   // never mixes them with other q and they are not stored, so only the addresses
   // are kept inside this panel's Qmax * n1 rows (EDGE: the tile that reaches past
   // them)
-  const float* base = Z + (((int64_t)blockIdx.x * Qmax + q0) * n1 << 4);
+  const float* base = Z + ((p32 * Qmax + q0) * n1 << 5) + 16 * hsel;
   float2 v[J];
   if constexpr (!EDGE) {
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, RT * 64u);
-    const uint32_t voff = ((uint32_t)g * 16u + 2u * c) * 4u;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, RT * 128u);
+    const uint32_t voff = ((uint32_t)g * 32u + 2u * c) * 4u;
 #pragma unroll
     for (int j = 0; j < J; ++j)
       v[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
-                                            rs, voff, (uint32_t)j * 32u * 64u, 0));
+                                            rs, voff, (uint32_t)j * 32u * 128u, 0));
   } else {
     const int rmax = (int)((Qmax - q0) * n1) - 1;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int r = g + 32 * j;
-      v[j] = *reinterpret_cast<const float2*>(base + ((int64_t)(r < rmax ? r : rmax) << 4) + 2 * c);
+      v[j] = *reinterpret_cast<const float2*>(base + ((int64_t)(r < rmax ? r : rmax) << 5) + 2 * c);
     }
   }
   // the SA row of each tile row, loaded behind the tile (one memory round trip)
@@ -781,7 +794,7 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
     __syncthreads();
   }
   reg_fwht2<J, 5>(v, 0, lb1);
-  const int64_t col = (int64_t)blockIdx.x * 16 + 2 * c;
+  const int64_t col = (2 * p32 + hsel) * 16 + 2 * c;
   if (col >= d) return;
   const bool pair = col + 1 < d;
   constexpr uintptr_t kAlign = sizeof(OutT) == 2 ? 4 : 8;
@@ -904,7 +917,6 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
     // floats below 2^31 bytes); its intermediate is never smaller than the old
     // layout's, so wider rows fall back to that form in the same buffer
     if (n1 <= kP2Rows && lda < ((int64_t)1 << 19)) {
-      const int64_t np16 = (d + 15) / 16;
       float* Zw = reinterpret_cast<float*>(B.zbuf);
       const float* Af = reinterpret_cast<const float*>(A);
       // full tiles (all 1024 rows below n), then the rest row-clamped
@@ -924,16 +936,22 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       const int64_t t2 = (Qmax * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
       const int64_t t2full = Qmax * n1 / kP2Rows;
       const float* Z = Zw;
+      // two blocks (the halves of a 32-column panel) per work item, 16 blocks per
+      // 8 work items (see k_srht_p2)
+      auto p2_grid = [&](int64_t ntile) {
+        return dim3((unsigned)((P * ntile + 7) / 8 * 16));
+      };
       auto p2 = [&](auto out_tag) {
         using OutT = decltype(out_tag);
         OutT* o = reinterpret_cast<OutT*>(SA);
         if (t2full > 0)
-          hipLaunchKernelGGL((k_srht_p2<OutT, false>), dim3((unsigned)np16, (unsigned)t2full),
-                             dim3(256), 0, s, Z, Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa,
-                             (float)scale, (int64_t)0);
+          hipLaunchKernelGGL((k_srht_p2<OutT, false>), p2_grid(t2full), dim3(256), 0, s, Z, Qmax,
+                             lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, (int64_t)0, P,
+                             t2full);
         if (t2 > t2full)
-          hipLaunchKernelGGL((k_srht_p2<OutT, true>), dim3((unsigned)np16, 1u), dim3(256), 0, s, Z,
-                             Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full);
+          hipLaunchKernelGGL((k_srht_p2<OutT, true>), p2_grid(1), dim3(256), 0, s, Z, Qmax, lb1,
+                             n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full, P,
+                             (int64_t)1);
       };
       if (bf16)
         p2(uint16_t{});
