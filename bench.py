@@ -101,6 +101,8 @@ def parse():
                          "sparse: 2^20x1024 CSR (1.5%% dense) with the CountSketch")
     ap.add_argument("--path-modes", default="path_warm_f32,path_warm_bf16,cold_f32",
                     help="path workload: the modes to time (the first listed is the value)")
+    ap.add_argument("--skip-persistent", action="store_true",
+                    help="c4a: do not time the grid's persistent form (its cooperative launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a counter "
                          "reference for HBM traffic measurements)")
@@ -819,6 +821,8 @@ def run_c4a(args):
     # the same arithmetic: its solutions must equal the default form's bit for bit
     modes = [("grid_bf16", grid), ("grid_bf16_persistent", lambda: grid(True)),
              ("sequential_plain_f32", seq)]
+    if args.skip_persistent:
+        modes.pop(1)
     for name, fn in modes:
         fn()
         torch.cuda.synchronize()
@@ -840,8 +844,9 @@ def run_c4a(args):
     # the multi-RHS gradient passes of the timed grid solves (timed by HIP events):
     # each running nu adds its candidates as columns, 4 n d flops per column
     gres = out["grid_bf16"]["res"]
-    same = all(torch.equal(x0, x1) and i0["events"] == i1["events"]
-               for (x0, i0), (x1, i1) in zip(gres, out["grid_bf16_persistent"]["res"]))
+    same = None if args.skip_persistent else all(
+        torch.equal(x0, x1) and i0["events"] == i1["events"]
+        for (x0, i0), (x1, i1) in zip(gres, out["grid_bf16_persistent"]["res"]))
     cols = sum(2 * i["grad_passes"] - 1 for _, i in gres) * args.steps
     gms = out["grid_bf16"]["mr_gradient_ms_total"]
     tfl = 4.0 * n * d * cols / (gms / 1e3) / 1e12 if gms > 0 else 0.0

@@ -1,10 +1,9 @@
 // Sparse A (CSR) with the CountSketch, the O(nnz) embedding named for sparse data
 // matrices: S has one signed nonzero per column, S[h_i, i] = s_i.  Every sum has a
 // fixed order (no floating-point atomics): rows are grouped by bucket with a
-// stable radix sort, the gradient's A^T r pass runs over a column-major (CSC) copy
-// formed once per solve by the same kind of sort.
-#include <hipcub/hipcub.hpp>
-
+// stable radix sort (written here: digit counts, a scan, an order-keeping
+// scatter), the gradient's A^T r pass runs over a column-major (CSC) copy formed
+// once per solve by the same sort.
 #include "rs_internal.hpp"
 
 namespace rs {
@@ -360,19 +359,186 @@ static int bits_for(uint64_t v) {  // bits to hold values 0..v
   return b;
 }
 
-// stable sort of (key, value) pairs, scratch grown in place
+// ------------------------------------------------------------ scan and sort
+// Exclusive prefix sums of int64 values: blocks of 1024 (256 threads x 4) scan
+// their part in LDS and leave their totals, which are scanned the same way (one
+// level per factor of 1024), then added back.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_block(const int64_t* __restrict__ in, int64_t n,
+                                                    int64_t* __restrict__ out,
+                                                    int64_t* __restrict__ totals) {
+  __shared__ int64_t sh[256];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + 4 * t;
+  int64_t v[4], run = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    v[e] = base + e < n ? in[base + e] : 0;
+    run += v[e];
+  }
+  sh[t] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the thread sums
+    const int64_t x = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  int64_t acc = sh[t] - run;  // exclusive start of this thread
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (base + e < n) out[base + e] = acc;
+    acc += v[e];
+  }
+  if (t == 255 && totals) totals[blockIdx.x] = sh[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ out, int64_t n,
+                                                  const int64_t* __restrict__ starts) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] += starts[i / kScanBlock];
+}
+
+// Scratch int64 values needed by excl_scan for n values (every level's totals).
+static int64_t scan_scratch(int64_t n) {
+  int64_t need = 0;
+  for (int64_t m = (n + kScanBlock - 1) / kScanBlock; m > 1; m = (m + kScanBlock - 1) / kScanBlock)
+    need += 2 * m;
+  return need + 2;
+}
+
+// out = exclusive prefix sums of in (n values); work holds scan_scratch(n) values.
+static rs_status excl_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* work,
+                           hipStream_t s) {
+  if (n <= 0) return RS_OK;
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(256), 0, s, in, n, out, (int64_t*)nullptr);
+    return check_launch("scan");
+  }
+  int64_t* totals = work;
+  int64_t* starts = work + nb;
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(256), 0, s, in, n, out, totals);
+  SP_TRY(excl_scan(totals, starts, nb, work + 2 * nb, s));
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n,
+                     (const int64_t*)starts);
+  return check_launch("scan");
+}
+
+// Stable LSD radix sort of (key, value) pairs on the low end_bit key bits, 8 bits a
+// pass.  A pass: every block counts the digits of its chunk of kSortChunk pairs
+// (hist[digit][block]); one exclusive scan over that digit-major table gives each
+// (digit, block) its first output slot; every block then walks its chunk in order,
+// 256 pairs at a time, and places each pair after the equal digits before it (its
+// rank in the wave from 8 ballots, the waves before it from LDS counts), so equal
+// keys keep their input order.
+constexpr int kSortChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ key, int64_t n,
+                                                   int shift, int nblk,
+                                                   int64_t* __restrict__ hist) {
+  __shared__ int cnt[256];
+  const int t = threadIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+  for (int i = t; i < kSortChunk; i += 256)
+    if (c0 + i < n) atomicAdd(&cnt[(key[c0 + i] >> shift) & 255u], 1);
+  __syncthreads();
+  hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict__ kin,
+                                                      const V* __restrict__ vin, int64_t n,
+                                                      int shift, int nblk,
+                                                      const int64_t* __restrict__ start,
+                                                      uint32_t* __restrict__ kout,
+                                                      V* __restrict__ vout) {
+  __shared__ int64_t base[256];
+  __shared__ int wcnt[4][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  base[t] = start[(int64_t)t * nblk + blockIdx.x];
+#pragma unroll
+  for (int ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+  for (int tile = 0; tile < kSortChunk; tile += 256) {
+    const int64_t i = c0 + tile + t;
+    const bool ok = i < n;
+    const uint32_t k = ok ? kin[i] : 0u;
+    const V v = ok ? vin[i] : V(0);
+    const int dg = (int)((k >> shift) & 255u);
+    // lanes of this wave holding the same digit
+    uint64_t same = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bits = __ballot((dg >> b) & 1);
+      same &= ((dg >> b) & 1) ? bits : ~bits;
+    }
+    const int rank = __popcll(same & lt);
+    if (ok && lane == 63 - __clzll(same)) wcnt[w][dg] = __popcll(same);
+    __syncthreads();
+    if (ok) {
+      int64_t pos = base[dg] + rank;
+      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][dg];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
+    __syncthreads();
+  }
+}
+
+// Scratch bytes of radix_pairs for n pairs of value type V.
+template <typename V>
+static size_t sort_scratch(int64_t n) {
+  const int64_t nblk = (n + kSortChunk - 1) / kSortChunk;
+  return (size_t)n * (sizeof(uint32_t) + sizeof(V)) + 64 +  // + two 16-byte alignments
+         (size_t)(2 * 256 * nblk + scan_scratch(256 * nblk)) * sizeof(int64_t);
+}
+
+// Stable sort of (key, value) pairs by the low end_bit key bits into kout / vout (kin
+// and vin unchanged), scratch grown in place.
 template <typename V>
 static rs_status radix_pairs(const uint32_t* kin, uint32_t* kout, const V* vin, V* vout, int64_t n,
                              int end_bit, GrowBuf& tmp, hipStream_t s) {
-  size_t need = 0;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, 0, end_bit,
-                                         s) != hipSuccess)
-    return set_error(RS_ERR_HIP, "sparse: radix sort sizing failed");
-  SP_TRY(tmp.ensure(need));
-  size_t have = tmp.bytes;
-  SP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, have, kin, kout, vin, vout, (int)n, 0, end_bit,
-                                            s));
-  return RS_OK;
+  if (n <= 0) return RS_OK;
+  if (n > ((int64_t)1 << 31)) return set_error(RS_ERR_SHAPE, "sparse: more than 2^31 pairs");
+  SP_TRY(tmp.ensure(sort_scratch<V>(n)));
+  const int nblk = (int)((n + kSortChunk - 1) / kSortChunk);
+  char* p = tmp.as<char>();
+  uint32_t* kalt = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)n * sizeof(uint32_t);
+  p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+  V* valt = reinterpret_cast<V*>(p);
+  p += (size_t)n * sizeof(V);
+  p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+  int64_t* hist = reinterpret_cast<int64_t*>(p);
+  int64_t* start = hist + (int64_t)256 * nblk;
+  int64_t* work = start + (int64_t)256 * nblk;
+  const int passes = (end_bit + 7) / 8;
+  const uint32_t* ksrc = kin;
+  const V* vsrc = vin;
+  for (int ps = 0; ps < passes; ++ps) {
+    // the last pass writes kout / vout
+    const bool to_out = ((passes - 1 - ps) & 1) == 0;
+    uint32_t* kdst = to_out ? kout : kalt;
+    V* vdst = to_out ? vout : valt;
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)nblk), dim3(256), 0, s, ksrc, n, 8 * ps, nblk,
+                       hist);
+    SP_TRY(excl_scan(hist, start, (int64_t)256 * nblk, work, s));
+    hipLaunchKernelGGL(k_sort_scatter<V>, dim3((unsigned)nblk), dim3(256), 0, s, ksrc, vsrc, n,
+                       8 * ps, nblk, (const int64_t*)start, kdst, vdst);
+    ksrc = kdst;
+    vsrc = vdst;
+  }
+  return check_launch("radix sort");
 }
 
 // cst = exclusive prefix sum of the chunk counts of the nseg segments given by off
@@ -383,14 +549,8 @@ static rs_status chunk_starts(const int64_t* off, int64_t nseg, int64_t per, Gro
   SP_TRY(cst.ensure((size_t)(nseg + 1) * sizeof(int64_t)));
   hipLaunchKernelGGL(k_chunk_counts, dim3(grid_for(nseg + 1)), dim3(256), 0, s, off, nseg, per,
                      nch.as<int64_t>());
-  size_t need = 0;
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, nch.as<int64_t>(), cst.as<int64_t>(),
-                                       (int)(nseg + 1), s) != hipSuccess)
-    return set_error(RS_ERR_HIP, "sparse: scan sizing failed");
-  SP_TRY(tmp.ensure(need));
-  size_t have = tmp.bytes;
-  SP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, have, nch.as<int64_t>(), cst.as<int64_t>(),
-                                          (int)(nseg + 1), s));
+  SP_TRY(tmp.ensure((size_t)scan_scratch(nseg + 1) * sizeof(int64_t)));
+  SP_TRY(excl_scan(nch.as<int64_t>(), cst.as<int64_t>(), nseg + 1, tmp.as<int64_t>(), s));
   return check_launch("sparse chunks");
 }
 
