@@ -35,6 +35,7 @@ constexpr int kWork = 2 * kHid + 1;            // dz1, dz2, dy per sample
 // rows are drawn once into LDS.  The waves' sums meet in LDS in a fixed order.
 constexpr int kProbeChunkMax = 4096;
 constexpr int kPCols = kProbes + 2;  // the probes, the squared norms, A^T b
+static_assert(kPCols == kProbeCols, "one layout for both forms of the probe sums");
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_probe_partial(const T* __restrict__ A, int64_t n,
@@ -281,6 +282,46 @@ rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, const T* 
                      d, U);
   return check_launch("features pass");
 }
+// The probe signs of every row as one byte (bit k: w_k(i) = -1), for the first pass
+// of the probe sketch that takes the probe sums along (ProbeArgs).
+__global__ __launch_bounds__(256) void k_probe_bits(uint64_t seed, int64_t n,
+                                                    uint8_t* __restrict__ bits) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint8_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kProbes; ++k) {
+      const uint4 wd = draw(seed, kStreamProbe, (uint32_t)k, (uint64_t)i);
+      v |= (uint8_t)((wd.x & 1u) << k);
+    }
+    bits[i] = v;
+  }
+}
+
+rs_status probe_bits(uint64_t seed, int64_t n, uint8_t* bits, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_probe_bits, dim3(g), dim3(256), 0, s, seed, n, bits);
+  return check_launch("probe bits");
+}
+
+// U[k][j] = sum over the tiles (in order) of the first pass's per-tile sums.
+__global__ __launch_bounds__(256) void k_probe_tiles_finish(const double* __restrict__ part,
+                                                            int64_t ntiles, int64_t d, int64_t dp,
+                                                            double* __restrict__ U) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)kProbeCols * d) return;
+  const int64_t k = e / d, j = e - k * d;
+  double v = 0.0;
+  for (int64_t t = 0; t < ntiles; ++t) v += part[(t * kProbeCols + k) * dp + j];
+  U[e] = v;
+}
+
+rs_status probe_tiles_finish(const double* part, int64_t ntiles, int64_t d, int64_t dp, double* U,
+                             hipStream_t s) {
+  const unsigned g = (unsigned)(((int64_t)kProbeCols * d + 255) / 256);
+  hipLaunchKernelGGL(k_probe_tiles_finish, dim3(g), dim3(256), 0, s, part, ntiles, d, dp, U);
+  return check_launch("probe sums");
+}
+
 // The gradient at a start x = 0 from the features pass: grad f(0) = -A^T b (eq. (1)
 // with x = 0).  One block: if any x_j != 0 the flag stays 0 (the solve's own
 // gradient pass runs); otherwise G = -A^T b and the flag tells that pass to skip.

@@ -587,19 +587,25 @@ __device__ __forceinline__ void p1_work(int64_t L, int64_t panels, int64_t ntile
   panel = first + u % gw;
 }
 
-template <bool EDGE>
+// PROBE: also the learned start's column sums of this tile (ProbeArgs), taken from
+// the loaded rows before the sign flip, reduced over the block's 32 row groups in
+// the (still unused) transpose buffer.
+template <bool EDGE, bool PROBE>
 __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, int64_t n,
                                                  int64_t d, int64_t lda,
                                                  const int8_t* __restrict__ signs, int lb,
                                                  int64_t n2, int64_t n1, int64_t Qmax,
                                                  const int32_t* __restrict__ qmap,
                                                  float* __restrict__ Z, int64_t tile0,
-                                                 int64_t ntiles, int64_t panels, int pgroup) {
+                                                 int64_t ntiles, int64_t panels, int pgroup,
+                                                 ProbeArgs pa) {
   using TT = Tile<float>;
   constexpr int J = TT::J;
   __shared__ float4 lds[TT::RT * TT::CW / 2];
   __shared__ int32_t dest[TT::RT];
   __shared__ float sgn[TT::RT];
+  __shared__ uint8_t pbit[PROBE ? TT::RT : 1];
+  __shared__ float bvl[PROBE ? TT::RT : 1];
   const int t = threadIdx.x;
   const int c = t & 7;
   const int g = t >> 3;
@@ -639,6 +645,16 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
     qv[u] = qmap[r < n2 ? r : 0];
     sv[u] = signs[(r < n2 && i < n) ? i : 0];
   }
+  if constexpr (PROBE) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = t + 256 * u;
+      const int64_t i = row0 + r;
+      const bool ok = r < n2 && i < n;
+      pbit[r] = ok ? pa.bits[i] : (uint8_t)0;
+      bvl[r] = (ok && pa.b) ? pa.b[i] : 0.0f;
+    }
+  }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int r = t + 256 * u;
@@ -647,6 +663,43 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
     sgn[r] = (r < n2 && i < n) ? (float)sv[u] : 0.0f;
   }
   __syncthreads();  // sgn and dest written
+  if constexpr (PROBE) {
+    // rows past n2 or n have sign 0 and add nothing; columns past d are masked
+    float acc[kProbeCols][4];
+#pragma unroll
+    for (int k = 0; k < kProbeCols; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[k][e] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int r = g + 32 * j;
+      const bool rv = sgn[r] != 0.0f;
+      const uint32_t bits = pbit[r];
+      const float bv = bvl[r];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = (rv && col0 + e < d) ? get(v[j], e) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k][e] += ((bits >> k) & 1u) ? -x : x;
+        acc[8][e] = fmaf(x, x, acc[8][e]);
+        acc[9][e] = fmaf(bv, x, acc[9][e]);
+      }
+    }
+    float* red = reinterpret_cast<float*>(lds);  // [32 row groups][10][32 columns]
+#pragma unroll
+    for (int k = 0; k < kProbeCols; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[(g * kProbeCols + k) * 32 + c * 4 + e] = acc[k][e];
+    __syncthreads();
+    for (int q = t; q < kProbeCols * 32; q += 256) {
+      const int k = q >> 5, col = q & 31;
+      double sum = 0.0;
+      for (int gg = 0; gg < 32; ++gg) sum += (double)red[(gg * kProbeCols + k) * 32 + col];
+      const int64_t jc = panel * TT::W + col;
+      if (jc < d) pa.part[(tile * kProbeCols + k) * pa.dp + jc] = sum;
+    }
+    __syncthreads();  // the transpose below reuses the buffer
+  }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const float sg = sgn[g + 32 * j];
@@ -878,10 +931,19 @@ static void launch_tile(dim3 grid, hipStream_t s, const T* src, int64_t nsrc, in
                        reinterpret_cast<OutT*>(out), ldo, scale, hb);
 }
 
+bool srht_panel_path(int64_t npad, int64_t lda) {
+  const int64_t n2 = npad < 1024 ? npad : 1024;
+  const int64_t n1 = npad / n2;
+  return n1 > 1 && n1 <= kP2Rows && lda < ((int64_t)1 << 19);
+}
+
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
-                         int64_t Qmax, hipStream_t s, double scale_override) {
+                         int64_t Qmax, hipStream_t s, double scale_override,
+                         const ProbeArgs* probe) {
+  if (probe && (sizeof(T) != 4 || !srht_panel_path(npad, lda)))
+    return set_error(RS_ERR_ARG, "srht: the probe sums ride on the panel-major path only");
   using TT = Tile<T>;
   const int64_t n2 = npad < TT::RT ? npad : TT::RT;
   const int64_t n1 = npad / n2;
@@ -923,14 +985,23 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       const int64_t full = n2 == 1024 ? std::min<int64_t>(n / 1024, n1) : 0;
       const int64_t P = panels;
       const int kP1Group = Qmax >= 512 ? kP1GroupWrite : kP1GroupRead;
-      if (full > 0)
-        hipLaunchKernelGGL(k_srht_p1<false>, dim3((unsigned)(P * full)), dim3(256), 0, s, Af, n, d,
-                           lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, (int64_t)0, full, P,
-                           kP1Group);
-      if (full < n1)
-        hipLaunchKernelGGL(k_srht_p1<true>, dim3((unsigned)(P * (n1 - full))), dim3(256), 0, s,
-                           Af, n, d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, full, n1 - full,
-                           P, kP1Group);
+      const ProbeArgs pa = probe ? *probe : ProbeArgs{nullptr, nullptr, nullptr, 0};
+      auto p1 = [&](auto edge, auto withp, int64_t t0, int64_t nt) {
+        constexpr bool E = decltype(edge)::value, PR = decltype(withp)::value;
+        hipLaunchKernelGGL((k_srht_p1<E, PR>), dim3((unsigned)(P * nt)), dim3(256), 0, s, Af, n,
+                           d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, t0, nt, P, kP1Group,
+                           pa);
+      };
+      using F_ = std::false_type;
+      using T_ = std::true_type;
+      if (full > 0) {
+        if (probe) p1(F_{}, T_{}, (int64_t)0, full);
+        else p1(F_{}, F_{}, (int64_t)0, full);
+      }
+      if (full < n1) {
+        if (probe) p1(T_{}, T_{}, full, n1 - full);
+        else p1(T_{}, F_{}, full, n1 - full);
+      }
       hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((Qmax * n1 + 255) / 256)), dim3(256), 0, s,
                          B.qlist, B.kmap, B.qcount, Qmax, n1, n2, B.dest2);
       const int64_t t2 = (Qmax * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
@@ -979,10 +1050,10 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
 
 template rs_status srht_transform<float>(const SrhtBuffers&, const float*, int64_t, int64_t,
                                          int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
-                                         int64_t, hipStream_t, double);
+                                         int64_t, hipStream_t, double, const ProbeArgs*);
 template rs_status srht_transform<double>(const SrhtBuffers&, const double*, int64_t, int64_t,
                                           int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
-                                          int64_t, hipStream_t, double);
+                                          int64_t, hipStream_t, double, const ProbeArgs*);
 
 // ---------------------------------------------------------------- nested gather
 // SA[k] = scale * HDA[rows[k]] for the cached transform of the whole padded A

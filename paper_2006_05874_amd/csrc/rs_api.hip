@@ -193,7 +193,7 @@ struct DeviceScratch {
   // sparse A: its column-major copy, the gradient's residuals, the sketch's sort
   SparseWork spw;
   // learned form: probe sketch and its factor, probe sums, features
-  DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py;
+  DevBuf psa, pM, pLinv, pHinv, pCw, pGram, pinfo, ppart, pU, pY, prp, pr, pfeat, py, pbits;
   // nu grid: per-slot state, candidate blocks, multi-RHS products, batched
   // factors, uploads, and the per-level sketch / Gram cache
   DevBuf g_vec, g_ctl, g_ev, g_hinv, g_rpart, g_xc, g_gc, g_gtc, g_nu2, g_up, g_R, g_Gp, g_M, g_L,
@@ -363,7 +363,7 @@ static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, Srh
 static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                           int64_t lda, int64_t m, uint64_t seed, uint32_t sid, void* SA,
                           rs_dtype sa_t, int64_t ldsa, float* scale_out, int64_t* rows_out,
-                          int8_t* signs_out, hipStream_t s) {
+                          int8_t* signs_out, hipStream_t s, const ProbeArgs* probe = nullptr) {
   const int64_t npad = next_pow2(n);
   const int64_t n2 = std::min<int64_t>(npad, 1024);
   const int64_t Qmax = std::min<int64_t>(m, n2);
@@ -385,7 +385,7 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
                         reinterpret_cast<uint8_t*>(SA), ldsa, s));
   } else if (a_t == RS_F32)
     RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, m, SA, sa_t,
-                                 ldsa, Qmax, s));
+                                 ldsa, Qmax, s, 0.0, probe));
   else
     RS_TRY(srht_transform<double>(B, reinterpret_cast<const double*>(A), n, d, lda, npad, m, SA,
                                   sa_t, ldsa, Qmax, s));
@@ -889,29 +889,45 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
   if (!wood) RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
   RS_TRY(S.pinfo.ensure(sizeof(int), true));
-  const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
-  RS_TRY(S.ppart.ensure((size_t)nch * (kFeatAtbCol + 1) * d * sizeof(double)));
   RS_TRY(S.pU.ensure((size_t)(kFeatAtbCol + 1) * d * sizeof(double)));
-  // 2. (on the side stream, beside 1) one pass over A: the 8 probes A^T w_k, the
-  //    squared column norms and A^T b; it does not depend on the probe sketch
-  RS_TRY(S.ensure_aux());
-  RS_HIP(hipEventRecord(S.fork_ev, stream));
-  RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
-  if (a_t == RS_F32)
-    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda,
-                                reinterpret_cast<const float*>(b), seed, S.ppart.as<double>(),
-                                S.pU.as<double>(), S.aux));
-  else
-    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda,
-                                 reinterpret_cast<const double*>(b), seed, S.ppart.as<double>(),
-                                 S.pU.as<double>(), S.aux));
-  RS_HIP(hipEventRecord(S.join_ev, S.aux));
-  RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
-                  nullptr, nullptr, stream));
+  // 2. one pass over A for the 8 probes A^T w_k, the squared column norms and A^T b
+  //    (they do not depend on the probe sketch).  FP32 A on the panel-major SRHT
+  //    path: the probe sketch's first pass takes these sums from the tiles it reads
+  //    anyway (one read of A for both).  Otherwise a pass of its own on the side
+  //    stream, beside the sketch.
+  const bool fused = a_t == RS_F32 && srht_panel_path(npad, lda);
+  if (fused) {
+    const int64_t ntiles = npad / 1024, dp = (d + 31) / 32 * 32;
+    RS_TRY(S.pbits.ensure((size_t)n));
+    RS_TRY(S.ppart.ensure((size_t)ntiles * kProbeCols * dp * sizeof(double)));
+    RS_TRY(probe_bits(seed, n, S.pbits.as<uint8_t>(), stream));
+    const ProbeArgs pa{S.pbits.as<uint8_t>(), reinterpret_cast<const float*>(b),
+                       S.ppart.as<double>(), dp};
+    RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
+                    nullptr, nullptr, stream, &pa));
+    RS_TRY(probe_tiles_finish(S.ppart.as<double>(), ntiles, d, dp, S.pU.as<double>(), stream));
+  } else {
+    const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
+    RS_TRY(S.ppart.ensure((size_t)nch * (kFeatAtbCol + 1) * d * sizeof(double)));
+    RS_TRY(S.ensure_aux());
+    RS_HIP(hipEventRecord(S.fork_ev, stream));
+    RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
+    if (a_t == RS_F32)
+      RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda,
+                                  reinterpret_cast<const float*>(b), seed, S.ppart.as<double>(),
+                                  S.pU.as<double>(), S.aux));
+    else
+      RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda,
+                                   reinterpret_cast<const double*>(b), seed, S.ppart.as<double>(),
+                                   S.pU.as<double>(), S.aux));
+    RS_HIP(hipEventRecord(S.join_ev, S.aux));
+    RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
+                    nullptr, nullptr, stream));
+  }
   FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), wood ? nullptr : S.pHinv.as<double>(),
                    nullptr, S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
   RS_TRY(factor_build(FB, S.psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
-  RS_HIP(hipStreamWaitEvent(stream, S.join_ev, 0));
+  if (!fused) RS_HIP(hipStreamWaitEvent(stream, S.join_ev, 0));
   // 3. r_k = q_k / 2 with q_k = u_k^T H_S0^-1 u_k
   RS_TRY(S.pr.ensure(8 * sizeof(double)));
   if (wood) {

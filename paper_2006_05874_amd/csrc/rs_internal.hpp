@@ -55,10 +55,26 @@ struct SrhtBuffers {
 };
 rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t npad, int64_t m,
                       int64_t n2, int64_t* rows, hipStream_t s);
+// The learned start's column sums taken by the first pass of its probe sketch from
+// the tiles it loads anyway (one read of A for both): for every 1024-row tile and
+// column j, part[(tile * kProbeCols + k) * dp + j] = sum over the tile's rows of
+// w_k(i) A_ij (k < 8, w_k(i) = -1 where bit k of bits[i] is set), A_ij^2 (k = 8) and
+// b_i A_ij (k = 9, 0 without b).  FP32 A on the panel-major path only.
+constexpr int kProbeCols = 10;
+struct ProbeArgs {
+  const uint8_t* bits;  // n probe sign bytes
+  const float* b;       // n values or null
+  double* part;         // n1 * kProbeCols * dp
+  int64_t dp;           // column pitch of part (d rounded up to 32)
+};
+// Whether srht_transform takes the panel-major two-pass path (the one that can
+// carry ProbeArgs) for FP32 A of padded size npad and leading dimension lda.
+bool srht_panel_path(int64_t npad, int64_t lda);
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
-                         int64_t Qmax, hipStream_t s, double scale_override = 0.0);
+                         int64_t Qmax, hipStream_t s, double scale_override = 0.0,
+                         const ProbeArgs* probe = nullptr);
 rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* rows, int64_t m,
                       int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
                       hipStream_t s);
@@ -363,6 +379,12 @@ rs_status features_pass(const T* A, int64_t n, int64_t d, int64_t lda, const T* 
 // U column of A^T b in the features pass's output (after the 8 probes and the
 // squared column norms)
 constexpr int kFeatAtbCol = 9;
+// bits[i] = the 8 probe signs of row i (bit k set: w_k(i) = -1), Philox stream 7
+rs_status probe_bits(uint64_t seed, int64_t n, uint8_t* bits, hipStream_t s);
+// U[k * d + j] = sum over the ntiles tiles of part[(tile * kProbeCols + k) * dp + j]
+// (fixed order), k < kProbeCols
+rs_status probe_tiles_finish(const double* part, int64_t ntiles, int64_t d, int64_t dp, double* U,
+                             hipStream_t s);
 // G = -A^T b and *skip = 1 when every x_j is 0 (the gradient at the origin), else
 // *skip = 0 and G untouched; one block
 rs_status start_from_atb(const double* x, const double* atb, int64_t d, double* G, int* skip,
