@@ -593,8 +593,10 @@ def run_c5(args):
     problem (64 GiB; sigma_i = 1/i, G ~ N(0, 1/n), V Haar, b = A x_pl + 0.1 xi,
     seed 5).  One step = the solve at nu^2 = 1e-2 and the solve at nu^2 = 1e-4
     (nominal effective dimensions 15.2 and 155), each to the default decrement
-    tolerance, one after another on one stream.  Every timed solve is judged
-    afterwards by the oracle's streamed certificate (an upper bound on
+    tolerance.  The value is the learned form with the step's two solves batched
+    (rs_learned_solve_batch, two worker streams); the same solves one at a time on
+    one stream and the plain method are timed beside it.  Every timed solve is
+    judged afterwards by the oracle's streamed certificate (an upper bound on
     delta(x) / delta(0) from one FP64 pass over the stored A)."""
     import torch
     from paper_2006_05874_amd import learned, rs
@@ -619,10 +621,20 @@ def run_c5(args):
                                    sketch_dtype="bf16", check_every=args.check_every,
                                    raise_on_error=False)
 
+    def batch():
+        return rs.rs_learned_solve_batch([(A, b, nu2) for nu2 in C5_NU2S], params, mu, sd,
+                                         kind="srht", variant=args.variant, sketch_dtype="bf16",
+                                         check_every=args.check_every, workers=len(C5_NU2S),
+                                         raise_on_error=False)
+
+    def one_step(mode):
+        if mode == "batched":
+            return [(nu2, x, info) for nu2, (x, info) in zip(C5_NU2S, batch())]
+        return [(nu2,) + tuple(solve(nu2, mode)) for nu2 in C5_NU2S]
+
     def timed(mode, steps, warmup):
         for _ in range(warmup):
-            for nu2 in C5_NU2S:
-                solve(nu2, mode)
+            one_step(mode)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -630,21 +642,28 @@ def run_c5(args):
         t0 = time.perf_counter()
         out = []
         for s in range(steps):
-            for nu2 in C5_NU2S:
-                x, info = solve(nu2, mode)
-                out.append((nu2, x, info))
+            out += one_step(mode)
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         print(f"[c5] {mode}: {steps} steps in {wall:.2f} s", file=sys.stderr, flush=True)
         return out, ev0.elapsed_time(ev1), wall
 
-    main_mode = "plain" if args.mode == "plain" else "learned"
+    main_mode = {"plain": "plain", "learned-single": "learned"}.get(args.mode, "batched")
+    single = None
+    if main_mode == "batched":
+        # the same solves one at a time on one stream, timed first
+        sres, sms, _ = timed("learned", args.steps, args.warmup)
+        single = {"steps": args.steps, "warmup": args.warmup, "ms_per_step": sms / args.steps,
+                  "value": args.steps * len(C5_NU2S) / (sms / 1e3), "res": sres}
     results, ms_total, wall = timed(main_mode, args.steps, args.warmup)
     solves = args.steps * len(C5_NU2S)
     value = solves / (ms_total / 1e3)
+    free_b, total_b = torch.cuda.mem_get_info()
+    print(f"[c5] device memory in use {(total_b - free_b) / 2 ** 30:.1f} of "
+          f"{total_b / 2 ** 30:.1f} GiB", file=sys.stderr, flush=True)
     plain = None
-    if main_mode == "learned" and not args.skip_plain:
+    if main_mode != "plain" and not args.skip_plain:
         # the comparison: fewer steps (each plain solve walks the doubling ladder)
         psteps = max(1, min(args.steps, args.plain_steps))
         pres, pms, _ = timed("plain", psteps, 1)
@@ -654,9 +673,16 @@ def run_c5(args):
     # roofline of the dominant kernel: one more step with every gradient pass timed
     # by HIP events on its stream
     grad_bytes = n * d * 4 + n * 4
-    roof = gradient_roofline(rs, lambda: [solve(nu2, main_mode) for nu2 in C5_NU2S], grad_bytes,
-                             "k_grad_wide / k_grad_partial (A^T(AX-b) pass over 64 GiB, tuned "
-                             "plan)", "one more step")
+    kname = "k_grad_wide / k_grad_partial (A^T(AX-b) pass over 64 GiB, tuned plan)"
+    rmode = "learned" if main_mode == "batched" else main_mode
+    roof = gradient_roofline(rs, lambda: one_step(rmode), grad_bytes, kname,
+                             "one more step" + (", its solves one at a time"
+                                                if main_mode == "batched" else ""))
+    roof_over = None
+    if main_mode == "batched":
+        # the batched step: the two streams' passes share HBM, so a launch takes longer
+        roof_over = gradient_roofline(rs, lambda: one_step("batched"), grad_bytes, kname,
+                                      "one more batched step (two worker streams)")
     traffic = recorded_traffic(TRAFFIC_FILE_C5, GRAD_SOURCES)
     if traffic and list(plans[2])[0] == 512:
         roof["traffic"] = round(traffic)
@@ -699,7 +725,8 @@ def run_c5(args):
     # HIP events inside the library (sketches, Grams and factors, the rest)
     phases = {}
     rs.set_phase_timing(True)
-    for mode in ([main_mode] + (["plain"] if plain is not None else [])):
+    for mode in (["learned" if main_mode == "batched" else main_mode]
+                 + (["plain"] if plain is not None else [])):
         for nu2 in C5_NU2S:
             _, inf = solve(nu2, mode)
             phases.setdefault(mode, {})[str(nu2)] = {
@@ -710,6 +737,8 @@ def run_c5(args):
 
     # the oracle's certificate of every timed solve, after the timed work
     pts = [(nu2, x, info, "main") for nu2, x, info in results]
+    if single is not None:
+        pts += [(nu2, x, info, "single") for nu2, x, info in single["res"]]
     if plain is not None:
         pts += [(nu2, x, info, "plain") for nu2, x, info in plain["res"]]
     X = np.stack([x.cpu().numpy().astype(np.float64) for _, x, _, _ in pts], axis=1)
@@ -752,7 +781,8 @@ def run_c5(args):
            "kind": "oracle",
            "sample": f"the oracle's direct FP64 solve on the first {rows} rows: Gram "
                      f"{t_gram:.1f} s (scaled by {n}/{rows}) + Cholesky solve {t_solve:.1f} s"}
-    dtype = "bf16 sketch / f32 gradient / f64 factor" if main_mode == "learned" else "f32"
+    learned_form = main_mode in ("learned", "batched")
+    dtype = "bf16 sketch / f32 gradient / f64 factor" if learned_form else "f32"
     line = {
         "metric": "ridge solves/s to 1e-6 rel. pred. error, learned+BF16 vs plain FP32; HBM GB/s",
         "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -761,9 +791,11 @@ def run_c5(args):
         "data": "synthetic (seeded low-rank-decay A = G diag(1/i) V^T, generated on the device)",
         "config": {"workload": f"{n}x{d} FP32 (64 GiB), sigma_i=1/i, nu^2 in {list(C5_NU2S)}, "
                                "SRHT rho=0.1, "
-                               + ("learned m_init, BF16 sketch" if main_mode == "learned"
+                               + ("learned m_init, BF16 sketch" if learned_form
                                   else "m_init=1, FP32 sketch")
-                               + f", {args.variant}, 2 solves per step, one stream",
+                               + f", {args.variant}, 2 solves per step, "
+                               + ("batched over 2 worker streams" if main_mode == "batched"
+                                  else "one stream"),
                    "mode": main_mode, "n": n, "d": d,
                    "gradient_plan_k2": list(plans[2]), "parallelism": "single GPU"},
         "verified": ok,
@@ -775,6 +807,14 @@ def run_c5(args):
         "roofline": roof, "srht_roofline": srht,
         "phases_ms": phases,
     }
+    if roof_over is not None:
+        line["roofline_overlapped"] = roof_over
+    if single is not None:
+        sok, srel, ssol = summary("single")
+        line["learned_bf16_one_at_a_time"] = {
+            "value": round(single["value"], 4), "unit": "solves/s", "steps": single["steps"],
+            "warmup": single["warmup"], "ms_per_step": round(single["ms_per_step"], 3),
+            "verified": sok, "rel_pred_err_bound": srel, "solve": ssol}
     if plain is not None:
         pok, prel, psol = summary("plain")
         line["plain_fp32"] = {"value": round(plain["value"], 4), "unit": "solves/s",
