@@ -19,8 +19,12 @@
  *     exception crosses the ABI.
  *   - Internal scratch (histograms, transform intermediates, partial sums) is
  *     owned by the library, allocated once per device and grown on demand.
- *     Calls that overlap on one device (e.g. from two host threads or two
- *     streams) race on it: serialize them.
+ *     Every call holds a per-device lock while it queues its work, so calls
+ *     from several host threads keep the library's host state consistent; the
+ *     device work of two calls queued on different streams can still overlap
+ *     and race on that scratch: queue them on one stream or serialize them.
+ *     The batched solvers run their jobs on worker streams with scratch of
+ *     their own (a per-device worker pool, locked for the whole call).
  */
 #ifndef RS_H_
 #define RS_H_
@@ -341,7 +345,8 @@ typedef struct rs_problem {
  * private scratch; the host advances a job whenever its last queued work has
  * finished, so small solves run concurrently and fill the device.  The worker
  * streams wait for work already queued on `stream`, and `stream` waits for all of
- * them on return.  infos: count host records.  Synchronizes.  Returns RS_OK when
+ * them on return.  Workers past the first run on host threads that the library
+ * starts on first use and keeps until the process ends.  infos: count host records.  Synchronizes.  Returns RS_OK when
  * every job ended RS_OK or RS_ERR_NO_CONVERGENCE (see infos[i].status), else the
  * first other error; an argument error in any problem is reported before any
  * work is queued. */

@@ -444,7 +444,9 @@ __global__ __launch_bounds__(256) void k_fwht_tile(
     int32_t dst = -1;
     if (MODE == 0) {
       const int32_t q = qmap[r < n2 ? r : 0];
-      dst = (r < n2 && q >= 0) ? (int32_t)(tile * Q + q) : -1;
+      // q < Q holds for every kept index (the selection keeps at most Q of them);
+      // the test keeps a tile's writes inside its Q rows regardless
+      dst = (r < n2 && q >= 0 && q < Q) ? (int32_t)(tile * Q + q) : -1;
     } else if (MODE == 1) {
       const int32_t kk = kmap[r < n2 ? r : 0];
       dst = r < n2 ? kk : -1;
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
   for (int u = 0; u < 4; ++u) {
     const int r = t + 256 * u;
     const int64_t i = row0 + r;
-    dest[r] = r < n2 ? qv[u] : -1;
+    dest[r] = (r < n2 && qv[u] < Qmax) ? qv[u] : -1;
     sgn[r] = (r < n2 && i < n) ? (float)sv[u] : 0.0f;
   }
   __syncthreads();  // sgn and dest written
@@ -670,21 +672,33 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
     for (int k = 0; k < kProbeCols; ++k)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[k][e] = 0.0f;
+    // every row and column of a full tile's panel is inside A except in the last
+    // panel: only those blocks and the ragged tiles mask
+    auto sums = [&](auto masked) {
+      constexpr bool MASK = decltype(masked)::value;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int r = g + 32 * j;
-      const bool rv = sgn[r] != 0.0f;
-      const uint32_t bits = pbit[r];
-      const float bv = bvl[r];
+      for (int j = 0; j < J; ++j) {
+        const int r = g + 32 * j;
+        const bool rv = !MASK || sgn[r] != 0.0f;
+        const uint32_t bits = pbit[r];
+        const float bv = bvl[r];
+        // the row's 8 probe signs as +-1.0f (bit k moved to the sign bit of 1.0f),
+        // so that each column takes one multiply-add per probe
+        float sk[8];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float x = (rv && col0 + e < d) ? get(v[j], e) : 0.0f;
+        for (int k = 0; k < 8; ++k) sk[k] = __uint_as_float(((bits >> k) << 31) | 0x3f800000u);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k][e] += ((bits >> k) & 1u) ? -x : x;
-        acc[8][e] = fmaf(x, x, acc[8][e]);
-        acc[9][e] = fmaf(bv, x, acc[9][e]);
+        for (int e = 0; e < 4; ++e) {
+          const float x = (!MASK || (rv && col0 + e < d)) ? get(v[j], e) : 0.0f;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc[k][e] = fmaf(sk[k], x, acc[k][e]);
+          acc[8][e] = fmaf(x, x, acc[8][e]);
+          acc[9][e] = fmaf(bv, x, acc[9][e]);
+        }
       }
-    }
+    };
+    if (!EDGE && n2 == TT::RT && col0 + 3 < d) sums(std::false_type{});
+    else sums(std::true_type{});
     float* red = reinterpret_cast<float*>(lds);  // [32 row groups][10][32 columns]
 #pragma unroll
     for (int k = 0; k < kProbeCols; ++k)

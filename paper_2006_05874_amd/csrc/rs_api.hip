@@ -112,8 +112,8 @@ static void release_block(void* p) {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  // grow-only; zero-fills fresh memory when `zero` is set
-  rs_status ensure(size_t want, bool zero = false) {
+  // grow-only
+  rs_status ensure(size_t want) {
     if (want <= bytes && p) return RS_OK;
     size_t sz = want ? want : 256;
     if (t_retire && p) sz = std::max(sz, bytes + bytes / 2);
@@ -128,11 +128,17 @@ struct DevBuf {
       g_err = std::string("hipMalloc: ") + hipGetErrorString(e);
       return e == hipErrorOutOfMemory ? RS_ERR_OOM : RS_ERR_HIP;
     }
-    if (zero) {
-      e = hipMemset(p, 0, sz);
-      if (e != hipSuccess) return set_error(RS_ERR_HIP, "hipMemset failed");
-    }
     bytes = sz;
+    return RS_OK;
+  }
+  // grow-only; fresh memory is zero-filled on stream s, the stream whose kernels
+  // read it (a plain hipMemset runs on the null stream, which the library's
+  // non-blocking streams do not wait for: their kernels could read the block
+  // before the fill lands)
+  rs_status ensure_zeroed(size_t want, hipStream_t s) {
+    if (want <= bytes && p) return RS_OK;
+    RS_TRY(ensure(want));
+    RS_HIP(hipMemsetAsync(p, 0, bytes, s));
     return RS_OK;
   }
   // grow-only, keeping the first `keep` bytes (copied on the stream, which is
@@ -337,8 +343,11 @@ static rs_status check_matrix(const void* A, rs_dtype a_t, int64_t n, int64_t d,
   return RS_OK;
 }
 
-static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, SrhtBuffers& B) {
-  RS_TRY(S.hist.ensure(4096 * sizeof(uint32_t), true));
+// hist and used must be zero on entry to the selection (its kernels leave them
+// zero): fresh blocks are cleared on s, the selection's stream
+static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, SrhtBuffers& B,
+                             hipStream_t s) {
+  RS_TRY(S.hist.ensure_zeroed(4096 * sizeof(uint32_t), s));
   RS_TRY(S.signs.ensure((size_t)npad));
   RS_TRY(S.kmap.ensure((size_t)npad * sizeof(int32_t)));
   RS_TRY(S.state.ensure(srht_state_bytes()));
@@ -346,7 +355,7 @@ static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, Srh
   RS_TRY(S.cand_idx.ensure((size_t)srht_cand_cap() * sizeof(int64_t)));
   RS_TRY(S.blk_less.ensure((size_t)((npad + srht_compact_block() - 1) / srht_compact_block()) *
                            sizeof(uint32_t)));
-  RS_TRY(S.used.ensure(1024 * sizeof(int32_t), true));
+  RS_TRY(S.used.ensure_zeroed(1024 * sizeof(int32_t), s));
   RS_TRY(S.qmap.ensure(1024 * sizeof(int32_t)));
   RS_TRY(S.qlist.ensure(1024 * sizeof(int32_t)));
   RS_TRY(S.qcount.ensure(sizeof(int32_t)));
@@ -369,7 +378,7 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
   const int64_t Qmax = std::min<int64_t>(m, n2);
   const size_t zbytes = srht_zbuf_bytes(a_t, npad, d, Qmax);
   SrhtBuffers B;
-  RS_TRY(ensure_srht(S, npad, zbytes, B));
+  RS_TRY(ensure_srht(S, npad, zbytes, B, s));
   int64_t* rows = rows_out;
   if (!rows) {
     RS_TRY(S.rows.ensure((size_t)m * sizeof(int64_t)));
@@ -453,7 +462,7 @@ static rs_status nested_sketch(DeviceScratch& S, NestedCache& C, bool srht, cons
     SrhtBuffers B;
     RS_TRY(S.rows.ensure((size_t)npad * sizeof(int64_t)));
     if (!C.hda_ready) {
-      RS_TRY(ensure_srht(S, npad, (int64_t)srht_zbuf_bytes(a_t, npad, d, n2), B));
+      RS_TRY(ensure_srht(S, npad, (int64_t)srht_zbuf_bytes(a_t, npad, d, n2), B, s));
       RS_TRY(S.hda.ensure((size_t)npad * ldh * es));
       RS_TRY(srht_select(B, seed, sid, npad, npad, n2, S.rows.as<int64_t>(), s));
       if (a_t == RS_F32)
@@ -464,7 +473,7 @@ static rs_status nested_sketch(DeviceScratch& S, NestedCache& C, bool srht, cons
                                       npad, S.hda.p, RS_F64, ldh, n2, s, 1.0));
       C.hda_ready = true;
     } else {
-      RS_TRY(ensure_srht(S, npad, 0, B));
+      RS_TRY(ensure_srht(S, npad, 0, B, s));
     }
     RS_TRY(srht_select(B, seed, sid, npad, m, n2, S.rows.as<int64_t>(), s));
     RS_TRY(srht_gather(S.hda.p, a_t, ldh, S.rows.as<int64_t>(), m, d, scale, dst, dst_t, ldd, s));
@@ -517,6 +526,9 @@ rs_status rs_profile_enable(int on) {
   if (on && !g_prof_ran) {
     RS_HIP(hipMalloc(&g_prof_ran, kProfCap * sizeof(int)));
     RS_HIP(hipMemset(g_prof_ran, 0, kProfCap * sizeof(int)));
+    // the launches that set these flags run on streams that do not wait for the
+    // null stream's fill
+    RS_HIP(hipDeviceSynchronize());
   }
   g_prof_on = on != 0;
   return RS_OK;
@@ -533,6 +545,7 @@ rs_status rs_profile_read(int64_t* launches, double* total_ms) {
     RS_HIP(hipDeviceSynchronize());
     RS_HIP(hipMemcpy(ran.data(), g_prof_ran, pairs * sizeof(int), hipMemcpyDeviceToHost));
     RS_HIP(hipMemset(g_prof_ran, 0, kProfCap * sizeof(int)));
+    RS_HIP(hipDeviceSynchronize());
   }
   for (size_t i = 0; i < pairs; ++i) {
     RS_HIP(hipEventSynchronize(g_prof_ev[2 * i + 1]));
@@ -646,7 +659,7 @@ static rs_status factor_alloc(rs_factor* F, int64_t m, int64_t d, double nu2) {
   if (!F->wood) RS_TRY(F->Hinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(F->Cw.ensure(factor_bytes_Cw(m, d)));
   if (F->wood) RS_TRY(F->wbuf.ensure(wapply_scratch_doubles(m, d) * sizeof(double)));
-  RS_TRY(F->info.ensure(sizeof(int), true));
+  RS_TRY(F->info.ensure(sizeof(int)));  // cleared on the stream before each use
   RS_TRY(F->rpart.ensure((size_t)apply_blocks(d) * 4 * sizeof(double)));
   RS_TRY(F->gram.ensure(factor_bytes_gram(m, d, F->sa_t)));
   return RS_OK;
@@ -888,7 +901,7 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
   RS_TRY(S.pLinv.ensure(factor_bytes_M(m0, d)));
   if (!wood) RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
-  RS_TRY(S.pinfo.ensure(sizeof(int), true));
+  RS_TRY(S.pinfo.ensure_zeroed(sizeof(int), stream));
   RS_TRY(S.pU.ensure((size_t)(kFeatAtbCol + 1) * d * sizeof(double)));
   // 2. one pass over A for the 8 probes A^T w_k, the squared column norms and A^T b
   //    (they do not depend on the probe sketch).  FP32 A on the panel-major SRHT
@@ -1985,7 +1998,7 @@ struct NuGrid {
     int64_t rps = 0;
     const int ns = mr_splits(base.n, d, 1, rps);
     RS_TRY(S->g_Gp.ensure((size_t)ns * d * ldr() * 8));
-    RS_TRY(S->info.ensure(sizeof(int), true));
+    RS_TRY(S->info.ensure(sizeof(int)));  // cleared on the stream before each use
     up_cap = (size_t)64 * count + 65536;
     RS_TRY(S->g_up.ensure(up_cap));
     const size_t pin = (size_t)count * sizeof(DevCtl) + 256 + up_cap;

@@ -65,6 +65,24 @@ def test_batch_equals_single_solves_fp64(rs, workers, graph_steps):
         assert ridge.relative_error(ridge.hessian(p.A, p.nu2), host(x), xs) <= 1e-6
 
 
+def test_batch_new_workers_on_reused_memory(rs):
+    # workers created inside a batch allocate their scratch there, possibly on
+    # memory that held other data (here a released GiB of 0xff bytes): the row
+    # selection's zero-on-entry flags are cleared on the worker's own stream, so
+    # every job still gives exactly what it gives alone
+    junk = torch.full((1 << 28,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    probs = small_uneven(12, np.float64, seed=4)
+    dev_probs = [(dev_padded(p.A, rs), torch.from_numpy(p.b).cuda(), p.nu2) for p in probs]
+    res = rs.rs_solve_batch(dev_probs, seed=5, workers=12)
+    for (A, b, nu2), (x, info) in zip(dev_probs, res):
+        xs1, i1 = rs.rs_adaptive_solve(A, b, nu2, seed=5)
+        assert info["status"] == i1["status"] == "ok"
+        assert info["events"] == i1["events"] and torch.equal(x, xs1)
+
+
 @pytest.mark.parametrize("sketch_dtype", ["f32", "bf16", "fp8"])
 def test_batch_low_precision_sketches_reach_tolerance(rs, sketch_dtype):
     probs = small_uneven(12, np.float32, seed=1)
