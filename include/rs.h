@@ -172,6 +172,22 @@ rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
                       const void* b, double nu2, const double* X, int64_t k, double* G,
                       hipStream_t stream);
 
+/* The gradients of two problems that share A and b (two nu, or two starting
+ * points), each with a block of two iterates, in one read of A:
+ * G_j = A^T (A X_j - b) + nu2[j] X_j for j = 0, 1.  The proof of Theorem 7 prices
+ * an iteration at these products; two solves on the same data share them.  Each
+ * G_j equals rs_gradient(A, F32, ..., nu2[j], X_j, k = 2) bit for bit.  FP32 A
+ * only, and only where the k = 2 gradient plan of (n, d) runs on the 512-thread
+ * kernel (a plan rs_gradient_autotune picks for wide rows, or one set with
+ * rs_gradient_set_plan); otherwise RS_ERR_UNSUPPORTED and nothing is queued.
+ *   nu2    : host, 2 values.
+ *   X0, X1 : device, 2 x d FP64 each (column after column).
+ *   G0, G1 : device, 2 x d FP64 out.
+ * Asynchronous. */
+rs_status rs_gradient_two(const float* A, int64_t n, int64_t d, int64_t lda, const float* b,
+                          const double* nu2, const double* X0, const double* X1, double* G0,
+                          double* G1, hipStream_t stream);
+
 /* rs_gradient for callers that cannot allocate device memory (code under HIP
  * graph capture, serving loops, harnesses that forbid hipMalloc): the same kernels
  * and the same result as rs_gradient (bit for bit when the grid is the same), with

@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "rs_internal.hpp"
@@ -352,6 +353,189 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
       }
 }
 
+// wave_sum's butterfly (xor 32, 16, 8, 4, 2, 1, in that order) with the four
+// in-row stages as DPP moves instead of LDS permutes.  xor 8 is row_ror:8 and xor
+// 2, xor 1 are quad permutes (the same partners); row_ror:4 takes lane p +- 4 in
+// place of p ^ 4, and after the xor-8 stage lanes 8 apart hold the same bits, so
+// the operands, and every lane's result, are wave_sum's bit for bit.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += __shfl_xor(v, 32, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
+                                                              0xF, 0xF, false));  // row_ror:8
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
+                                                              0xF, 0xF, false));  // row_ror:4
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E,
+                                                              0xF, 0xF, false));  // [2,3,0,1]
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1,
+                                                              0xF, 0xF, false));  // [1,0,3,2]
+  return v;
+}
+
+// Two problems that share A and b (two nu, or two starts), each with two columns:
+// one read of A serves both.  Each job's columns get exactly the arithmetic of
+// k_grad_wide<2, NV, R> on the same grid (the same products in the same order, wave
+// and block sums, FP64 accumulation), so its partial sums are those of its own pass.
+// Four columns of x in registers would not fit beside the FP64 sums, so x sits in
+// LDS: thread lt keeps its columns there and reads back only its own entries (no
+// barrier needed for them).  A job whose status flag is raised gets no partial sums
+// written (its finish returns at once too); both raised: the block returns.
+template <int NV, int R>
+__global__ __launch_bounds__(512) void k_grad_wide_two(
+    const float* __restrict__ A, int64_t n, int64_t d, int64_t lda, const float* __restrict__ b,
+    const double* __restrict__ X0, const double* __restrict__ X1, int64_t rows_per_block,
+    int iters, double* __restrict__ partial0, double* __restrict__ partial1,
+    const int* __restrict__ status0, const int* __restrict__ status1, int* __restrict__ ran) {
+  constexpr int K = 4;  // job 0: columns 0, 1; job 1: columns 2, 3
+  const bool live0 = !status0 || *status0 == 0;
+  const bool live1 = !status1 || *status1 == 0;
+  if (!live0 && !live1) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  constexpr int NW = 8;
+  __shared__ float red[2][NW][R * K];
+  __shared__ float4 xs[K][NV][512];
+  const int lt = threadIdx.x;
+  const int w = lt >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t row1 = row0 + rows_per_block < n ? row0 + rows_per_block : n;
+  auto put = [&](int k, int v, int e, double val) {
+    const int64_t c = (int64_t)(lt + 512 * v) * 4 + e;
+    if (c >= d) return;
+    if (k < 2) {
+      if (live0) partial0[((int64_t)blockIdx.x * 2 + k) * d + c] = val;
+    } else if (live1) {
+      partial1[((int64_t)blockIdx.x * 2 + (k - 2)) * d + c] = val;
+    }
+  };
+  if (row0 >= row1) {
+    for (int k = 0; k < K; ++k)
+      for (int v = 0; v < NV; ++v)
+        for (int e = 0; e < 4; ++e) put(k, v, e, 0.0);
+    return;
+  }
+  uint32_t coff[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t c0 = (int64_t)(lt + 512 * v) * 4;
+    coff[v] = (uint32_t)((c0 < d ? c0 : 0) * 4);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double* X = k < 2 ? X0 + (int64_t)k * d : X1 + (int64_t)(k - 2) * d;
+      float4 xv;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) set(xv, e, c0 + e < d ? (float)X[c0 + e] : 0.0f);
+      xs[k][v][lt] = xv;
+    }
+  }
+  double acc[K][NV][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[k][v][e] = 0.0;
+  const uint32_t rowb = (uint32_t)(lda * 4);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(A + row0 * lda), (short)0, (int)(rowb * (uint32_t)(row1 - row0)),
+      0x00020000);
+  const int64_t nrows = row1 - row0;
+  auto load = [&](float4 (&a)[R][NV], int step) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      int64_t r = (int64_t)step * R + i;
+      r = r < nrows ? r : nrows - 1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        a[i][v] = __builtin_bit_cast(
+            float4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[v], (uint32_t)r * rowb, 0));
+    }
+  };
+  // MASK: some of the thread's columns lie past d (zeroed); a d that fills every
+  // thread's columns runs the loop without the selects
+  auto process = [&](float4 (&a)[R][NV], int step, auto mask) {
+    const int buf = step & 1;
+    if constexpr (decltype(mask)::value) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = (int64_t)(lt + 512 * v) * 4 + e < d;
+#pragma unroll
+          for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      float4 xk[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) xk[v] = xs[k][v][lt];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        float t = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) t = fmaf(get(a[i][v], e), get(xk[v], e), t);
+        t = wave_sum_dpp(t);
+        if ((lt & 63) == 0) red[buf][w][i * K + k] = t;
+      }
+    }
+    __syncthreads();
+    // lane q < R K of each wave adds the NW wave partials of dot q (in wave order,
+    // as every lane does in k_grad_wide); readlane hands the sums to the whole wave
+    float mine = 0.0f;
+    if ((lt & 63) < R * K) {
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) mine += red[buf][ww][lt & 63];
+    }
+    float res[K][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int64_t r = (int64_t)step * R + i;
+      const bool live = r < nrows;
+      const float bi = b[row0 + (live ? r : 0)];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float t = __builtin_bit_cast(
+            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine), i * K + k));
+        res[k][i] = live ? t - bi : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float t = 0.0f;
+#pragma unroll
+          for (int i = 0; i < R; ++i) t = fmaf(get(a[i][v], e), res[k][i], t);
+          acc[k][v][e] += (double)t;
+        }
+  };
+  auto run = [&](auto mask) {
+    float4 a0[R][NV], a1[R][NV];
+    load(a0, 0);
+    for (int it = 0; it < iters; it += 2) {
+      if (it + 1 < iters) load(a1, it + 1);
+      process(a0, it, mask);
+      if (it + 1 >= iters) break;
+      if (it + 2 < iters) load(a0, it + 2);
+      process(a1, it + 1, mask);
+    }
+  };
+  if (d >= (int64_t)2048 * NV)
+    run(std::false_type{});
+  else
+    run(std::true_type{});
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) put(k, v, e, acc[k][v][e]);
+}
+
 // G[k][j] = sum over blocks of partial[b][k][j] (fixed order) + nu2 X[k][j] - sub[j]
 // (sub null: 0; the dual problem's gradient carries -b there).
 // Block: 8 columns x 32 block-strides; LDS tree over the 32 strides.
@@ -538,6 +722,40 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
   hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial,
                      pl.grid, kd, nu2, X, G, status, c, d);
   return check_launch("gradient");
+}
+
+bool gradient_two_fits(int64_t n, int64_t d, int64_t lda, int grid_cap) {
+  GradPlan pl = grad_plan<float>(n, d, 2);
+  if (pl.grid > grid_cap) pl.grid = grid_cap;
+  const int64_t rpb = (n + pl.grid - 1) / pl.grid;
+  return pl.tpr == 512 && ((pl.nv == 4 && pl.r == 2) || (pl.nv == 2 && pl.r == 4)) &&
+         rpb * lda * 4 < ((int64_t)1 << 31);
+}
+
+rs_status gradient_two_launch(const float* A, int64_t n, int64_t d, int64_t lda, const float* b,
+                              const double* nu2, const double* const* X, double* const* G,
+                              double* const* partial, int grid_cap, const int* const* status,
+                              hipStream_t s) {
+  if (!gradient_two_fits(n, d, lda, grid_cap))
+    return set_error(RS_ERR_UNSUPPORTED, "gradient: no two-job kernel for this plan");
+  GradPlan pl = grad_plan<float>(n, d, 2);
+  if (pl.grid > grid_cap) pl.grid = grid_cap;
+  const int64_t rpb = (n + pl.grid - 1) / pl.grid;
+  const int iters = (int)((rpb + pl.r - 1) / pl.r);
+  const ProfSlot ps = prof_begin();
+  if (pl.nv == 4)
+    launch_timed(k_grad_wide_two<4, 2>, dim3(pl.grid), dim3(512), s, ps.begin, ps.end, A, n, d,
+                 lda, b, X[0], X[1], rpb, iters, partial[0], partial[1], status[0], status[1],
+                 ps.ran);
+  else
+    launch_timed(k_grad_wide_two<2, 4>, dim3(pl.grid), dim3(512), s, ps.begin, ps.end, A, n, d,
+                 lda, b, X[0], X[1], rpb, iters, partial[0], partial[1], status[0], status[1],
+                 ps.ran);
+  const int64_t kd = 2 * d;
+  for (int j = 0; j < 2; ++j)
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((kd + 7) / 8)), dim3(256), 0, s, partial[j],
+                       pl.grid, kd, nu2[j], X[j], G[j], status[j], (const double*)nullptr, d);
+  return check_launch("gradient (two jobs)");
 }
 
 template <typename T>

@@ -734,6 +734,27 @@ rs_status rs_gradient(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64_t
                                  S->partial.as<double>(), grid, nullptr, stream);
 }
 
+rs_status rs_gradient_two(const float* A, int64_t n, int64_t d, int64_t lda, const float* b,
+                          const double* nu2, const double* X0, const double* X1, double* G0,
+                          double* G1, hipStream_t stream) {
+  RS_TRY(check_matrix(A, RS_F32, n, d, lda, "rs_gradient_two"));
+  if (!b || !nu2 || !X0 || !X1 || !G0 || !G1)
+    return set_error(RS_ERR_ARG, "rs_gradient_two: null argument");
+  DeviceScratch* S = scratch_for_current();
+  std::lock_guard<std::mutex> g(S->mu);
+  const int grid = grad_partial_blocks_max(n);
+  if (!gradient_two_fits(n, d, lda, grid))
+    return set_error(RS_ERR_UNSUPPORTED,
+                     "rs_gradient_two: the k = 2 plan for this shape is not on the 512-thread kernel");
+  RS_TRY(S->partial.ensure((size_t)grid * 4 * d * sizeof(double)));
+  double* p0 = S->partial.as<double>();
+  const double* X[2] = {X0, X1};
+  double* G[2] = {G0, G1};
+  double* P[2] = {p0, p0 + (size_t)grid * 2 * d};
+  const int* st[2] = {nullptr, nullptr};
+  return gradient_two_launch(A, n, d, lda, b, nu2, X, G, P, grid, st, stream);
+}
+
 static rs_status grad_any(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                           int64_t lda, const void* b, double nu2, const double* X, int k, double* G,
                           const int* status, hipStream_t s, const double* c = nullptr) {

@@ -154,6 +154,15 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
                           const double* X, int k, double* G, double* partial, int grid,
                           const int* status, hipStream_t s, const double* c = nullptr,
                           bool prof = true);  // prof: false keeps the launch out of the profiler
+// Two jobs on the same FP32 A and b, k = 2 columns each (X[j], G[j], partial[j],
+// status[j], nu2[j]): one pass over A whose per-job results are those of
+// gradient_launch with k = 2 (same plan, same arithmetic).  Only for plans on the
+// 512-thread kernel (gradient_two_fits); partial[j] as for gradient_launch.
+bool gradient_two_fits(int64_t n, int64_t d, int64_t lda, int grid_cap);
+rs_status gradient_two_launch(const float* A, int64_t n, int64_t d, int64_t lda, const float* b,
+                              const double* nu2, const double* const* X, double* const* G,
+                              double* const* partial, int grid_cap, const int* const* status,
+                              hipStream_t s);
 
 // ---------------------------------------------------------------- sparse A (CSR)
 struct GrowBuf {  // grow-only device buffer released with its owner

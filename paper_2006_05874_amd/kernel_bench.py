@@ -23,7 +23,7 @@ from . import rs
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["gradient", "srht", "gaussian"])
+    ap.add_argument("what", choices=["gradient", "gradient2", "srht", "gaussian"])
     ap.add_argument("--n", type=int, default=1 << 21)
     ap.add_argument("--d", type=int, default=8192)
     ap.add_argument("--k", type=int, default=2)
@@ -53,6 +53,14 @@ def main(argv=None):
         if not a.no_tune:
             print("plan", rs.rs_gradient_autotune(A, b, k=a.k), flush=True)
         call = lambda: rs.rs_gradient(A, b, 0.01, X)
+        alg = n * d * 4 + n * 4
+    elif a.what == "gradient2":
+        # two problems on the same A and b, two columns each, in one read of A
+        X0 = torch.randn(2, d, dtype=torch.float64, device="cuda", generator=gen)
+        X1 = torch.randn(2, d, dtype=torch.float64, device="cuda", generator=gen)
+        if not a.no_tune:
+            print("plan", rs.rs_gradient_autotune(A, b, k=2), flush=True)
+        call = lambda: rs.rs_gradient_two(A, b, (0.01, 0.0001), X0, X1)
         alg = n * d * 4 + n * 4
     else:
         es = {"f32": 4, "bf16": 2, "fp8": 1}[a.sa]

@@ -86,7 +86,7 @@ EXPORTS = ["rs_params", "rs_sketch_srht", "rs_sketch_gaussian", "rs_factor_woodb
            "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
            "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual", "rs_refreshed_ihs",
            "rs_adaptive_solve_csr", "rs_step_rule", "rs_start_rule", "rs_gradient_set_plan",
-           "rs_gradient_noalloc"]
+           "rs_gradient_noalloc", "rs_gradient_two"]
 MLP_PARAMS = 18817
 MLP_CACHE = 273
 MLP_WORK = 257
@@ -122,6 +122,7 @@ def load(path=LIB_PATH):
     L.rs_factor_destroy.restype = None
     L.rs_gradient.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, i64, vp, vp]
     L.rs_gradient_noalloc.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, i64, vp, vp]
+    L.rs_gradient_two.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, vp]
     L.rs_ihs_step.argtypes = [vp, c_int, i64, i64, i64, vp, dbl, vp, ctypes.POINTER(IhsParams),
                               c_int, ctypes.POINTER(IhsState), ctypes.POINTER(StepResult), vp]
     L.rs_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -171,7 +172,7 @@ def load(path=LIB_PATH):
                  "rs_solve_nu_grid", "rs_learned_solve_batch", "rs_gradient_autotune",
                  "rs_gradient_plan", "rs_solve_path", "rs_adaptive_solve_dual",
                  "rs_refreshed_ihs", "rs_adaptive_solve_csr", "rs_gradient_set_plan",
-                 "rs_gradient_noalloc"]:
+                 "rs_gradient_noalloc", "rs_gradient_two"]:
         getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -702,6 +703,27 @@ def rs_learned_solve(A, b, nu2, params, mu, sd, kind="srht", variant="polyak", r
     res = _info(info, st, raise_on_error, "rs_learned_solve")
     res["m_init"] = used.value
     return x, res
+
+
+def rs_gradient_two(A, b, nu2s, X0, X1):
+    """(G0, G1) for two problems sharing FP32 A and b, X_j of shape (2, d) float64, in
+    one read of A; each equals rs_gradient(A, b, nu2s[j], X_j)."""
+    if _mat(A, "rs_gradient_two") != DTYPES["f32"]:
+        raise ValueError("rs_gradient_two: A must be float32")
+    n, d = A.shape
+    Xs = []
+    for X in (X0, X1):
+        if X.dim() != 2 or tuple(X.shape) != (2, d):
+            raise ValueError(f"rs_gradient_two: X must be (2, {d})")
+        Xs.append(_dev(X, "rs_gradient_two", "X").to(torch.float64).contiguous())
+    G0, G1 = torch.empty_like(Xs[0]), torch.empty_like(Xs[1])
+    bc = _rhs(b, A, "rs_gradient_two")
+    nu = (ctypes.c_double * 2)(float(nu2s[0]), float(nu2s[1]))
+    st = load().rs_gradient_two(_ptr(A), n, d, A.stride(0), _ptr(bc),
+                                ctypes.cast(nu, ctypes.c_void_p), _ptr(Xs[0]), _ptr(Xs[1]),
+                                _ptr(G0), _ptr(G1), _stream())
+    _check(st, "rs_gradient_two")
+    return G0, G1
 
 
 def rs_gradient_autotune(A, b, k=2):

@@ -260,6 +260,39 @@ def test_gradient_every_built_shape_at_wide_d(rs, d, k):
     assert tried >= 4          # (256, 8, 2) and (256, 8, 4) at d = 8192, two grids each
 
 
+@pytest.mark.parametrize("n,d,plan", [(3001, 8192, (512, 4, 7, 2)), (4099, 8190, (512, 4, 64, 2)),
+                                      (2500, 4093, (512, 2, 39, 4)), (1, 5000, (512, 4, 1, 2))])
+def test_gradient_two_equals_two_single_passes(rs, n, d, plan):
+    """Two problems on one A and b in one read: each job's G bit for bit what its own
+    k = 2 pass gives under the same plan (ragged n and d, a grid that leaves the
+    last block short, one row), and within the FP32 bound of the exact gradient."""
+    rng = np.random.default_rng(n + d)
+    A = (rng.standard_normal((n, d)) / np.sqrt(max(n, 2))).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    X0, X1 = rng.standard_normal((2, d)), rng.standard_normal((2, d))
+    Ad, bd = dev_padded(A, rs), dev(b)
+    rs.rs_gradient_set_plan("f32", n, d, 2, plan)
+    G0, G1 = rs.rs_gradient_two(Ad, bd, (0.37, 1e-4), dev(X0), dev(X1))
+    assert torch.equal(G0, rs.rs_gradient(Ad, bd, 0.37, dev(X0)))
+    assert torch.equal(G1, rs.rs_gradient(Ad, bd, 1e-4, dev(X1)))
+    _fp32_grad_check(A, b, X0, host(G0), 0.37)
+    _fp32_grad_check(A, b, X1, host(G1), 1e-4)
+
+
+def test_gradient_two_needs_the_512_thread_plan(rs):
+    n, d = 3001, 4096
+    Ad = rs.padded(n, d, dtype=torch.float32)
+    Ad.zero_()
+    bd = torch.zeros(n, device="cuda", dtype=torch.float32)
+    X = torch.zeros(2, d, dtype=torch.float64, device="cuda")
+    rs.rs_gradient_set_plan("f32", n, d, 2, (256, 4, 16, 4))
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_gradient_two(Ad, bd, (1.0, 1.0), X, X)
+    assert e.value.name == "unsupported"
+    with pytest.raises(ValueError):
+        rs.rs_gradient_two(Ad.double(), bd.double(), (1.0, 1.0), X, X)
+
+
 def test_gradient_set_plan_rejects_bad_plans(rs):
     with pytest.raises(rs.RsError) as e:
         rs.rs_gradient_set_plan("f32", 4096, 8192, 2, (64, 1, 16, 8))     # does not cover d
