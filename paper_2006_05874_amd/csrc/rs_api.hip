@@ -1,5 +1,6 @@
 // C ABI of librs: argument checks, per-device scratch, and the host side of the
 // adaptive controller (Algorithm 1).  Every numeric step runs in the kernels.
+#include <array>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -255,6 +256,7 @@ struct BatchWorker {
   DeviceScratch S;
   hipStream_t s = nullptr;
   hipEvent_t join = nullptr;
+  hipEvent_t step_ev = nullptr;  // a pair's shared steps (drive_pair)
   std::thread th;
   std::mutex m;
   std::condition_variable cv;
@@ -907,29 +909,42 @@ namespace rs {
 // The 16 features of (A, nu^2) into feat (device), on stream; no argument checks.
 // With b (device, n values of a_t; may be null) the same pass over A also leaves
 // A^T b in column kFeatAtbCol of S.pU.
-static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
-                              int64_t d, int64_t lda, const void* b, double nu2, uint64_t seed,
-                              float* feat, hipStream_t stream) {
-  const int64_t npad = next_pow2(n);
-  const int64_t m0 = std::min<int64_t>(256, npad);
+// The learned start's features (Section 5's predictor inputs) come in two parts.
+// The head is one pass over A: the 256-row probe sketch and the probe sums A^T w_k,
+// the squared column norms and A^T b (none of them depends on nu).  The tail
+// factors the probe sketch at nu, forms the probe quadratic forms and the final
+// features.  Jobs on the same A and b can share one head (features_copy_head).
+static int64_t features_m0(int64_t n) { return std::min<int64_t>(256, next_pow2(n)); }
+
+static rs_status features_buffers(DeviceScratch& S, rs_dtype a_t, int64_t n, int64_t d,
+                                  hipStream_t stream) {
+  const int64_t m0 = features_m0(n);
   const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
   const int64_t es = a_t == RS_F64 ? 8 : 4;
-  // 1. the probe sketch and its factor (when m0 < d only L and L^-1 of the m0 x m0
-  //    Woodbury matrix are needed)
-  const bool wood = m0 < d;
   RS_TRY(S.psa.ensure((size_t)m0 * d * es));
   RS_TRY(S.pM.ensure(factor_bytes_M(m0, d)));
   RS_TRY(S.pLinv.ensure(factor_bytes_M(m0, d)));
-  if (!wood) RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
+  if (!(m0 < d)) RS_TRY(S.pHinv.ensure(factor_bytes_Hinv(d)));
   RS_TRY(S.pGram.ensure(factor_bytes_gram(m0, d, sa_t)));
   RS_TRY(S.pinfo.ensure_zeroed(sizeof(int), stream));
   RS_TRY(S.pU.ensure((size_t)(kFeatAtbCol + 1) * d * sizeof(double)));
-  // 2. one pass over A for the 8 probes A^T w_k, the squared column norms and A^T b
-  //    (they do not depend on the probe sketch).  FP32 A on the panel-major SRHT
-  //    path: the probe sketch's first pass takes these sums from the tiles it reads
-  //    anyway (one read of A for both).  Otherwise a pass of its own on the side
-  //    stream, beside the sketch.
+  return RS_OK;
+}
+
+// The head; *join: the tail must wait for S.join_ev (the sums on the side stream).
+static rs_status features_head(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
+                               int64_t d, int64_t lda, const void* b, uint64_t seed,
+                               hipStream_t stream, bool* join) {
+  const int64_t npad = next_pow2(n);
+  const int64_t m0 = features_m0(n);
+  const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
+  // one pass over A for the 8 probes A^T w_k, the squared column norms and A^T b
+  // (they do not depend on the probe sketch).  FP32 A on the panel-major SRHT
+  // path: the probe sketch's first pass takes these sums from the tiles it reads
+  // anyway (one read of A for both).  Otherwise a pass of its own on the side
+  // stream, beside the sketch.
   const bool fused = a_t == RS_F32 && srht_panel_path(npad, lda);
+  *join = !fused;
   if (fused) {
     const int64_t ntiles = npad / 1024, dp = (d + 31) / 32 * 32;
     RS_TRY(S.pbits.ensure((size_t)n));
@@ -939,30 +954,50 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
                        S.ppart.as<double>(), dp};
     RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
                     nullptr, nullptr, stream, &pa));
-    RS_TRY(probe_tiles_finish(S.ppart.as<double>(), ntiles, d, dp, S.pU.as<double>(), stream));
-  } else {
-    const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
-    RS_TRY(S.ppart.ensure((size_t)nch * (kFeatAtbCol + 1) * d * sizeof(double)));
-    RS_TRY(S.ensure_aux());
-    RS_HIP(hipEventRecord(S.fork_ev, stream));
-    RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
-    if (a_t == RS_F32)
-      RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda,
-                                  reinterpret_cast<const float*>(b), seed, S.ppart.as<double>(),
-                                  S.pU.as<double>(), S.aux));
-    else
-      RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda,
-                                   reinterpret_cast<const double*>(b), seed, S.ppart.as<double>(),
-                                   S.pU.as<double>(), S.aux));
-    RS_HIP(hipEventRecord(S.join_ev, S.aux));
-    RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
-                    nullptr, nullptr, stream));
+    return probe_tiles_finish(S.ppart.as<double>(), ntiles, d, dp, S.pU.as<double>(), stream);
   }
+  const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
+  RS_TRY(S.ppart.ensure((size_t)nch * (kFeatAtbCol + 1) * d * sizeof(double)));
+  RS_TRY(S.ensure_aux());
+  RS_HIP(hipEventRecord(S.fork_ev, stream));
+  RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
+  if (a_t == RS_F32)
+    RS_TRY(features_pass<float>(reinterpret_cast<const float*>(A), n, d, lda,
+                                reinterpret_cast<const float*>(b), seed, S.ppart.as<double>(),
+                                S.pU.as<double>(), S.aux));
+  else
+    RS_TRY(features_pass<double>(reinterpret_cast<const double*>(A), n, d, lda,
+                                 reinterpret_cast<const double*>(b), seed, S.ppart.as<double>(),
+                                 S.pU.as<double>(), S.aux));
+  RS_HIP(hipEventRecord(S.join_ev, S.aux));
+  return srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
+                  nullptr, nullptr, stream);
+}
+
+// Another job's head (same A, b and seed) into S: the probe sketch and the sums
+// copied on `stream`, which must already wait for the head's work.
+static rs_status features_copy_head(DeviceScratch& S, const DeviceScratch& from, rs_dtype a_t,
+                                    int64_t n, int64_t d, hipStream_t stream) {
+  const int64_t es = a_t == RS_F64 ? 8 : 4;
+  RS_HIP(hipMemcpyAsync(S.psa.p, from.psa.p, (size_t)features_m0(n) * d * es,
+                        hipMemcpyDeviceToDevice, stream));
+  RS_HIP(hipMemcpyAsync(S.pU.p, from.pU.p, (size_t)(kFeatAtbCol + 1) * d * sizeof(double),
+                        hipMemcpyDeviceToDevice, stream));
+  return RS_OK;
+}
+
+static rs_status features_tail(DeviceScratch& S, rs_dtype a_t, int64_t n, int64_t d, double nu2,
+                               float* feat, bool join, hipStream_t stream) {
+  const int64_t m0 = features_m0(n);
+  const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
+  // the probe sketch's factor (when m0 < d only L and L^-1 of the m0 x m0 Woodbury
+  // matrix are needed)
+  const bool wood = m0 < d;
   FactorBuffers FB{S.pM.as<double>(), S.pLinv.as<double>(), wood ? nullptr : S.pHinv.as<double>(),
                    nullptr, S.pinfo.as<int>(), S.pGram.p, S.pGram.bytes};
   RS_TRY(factor_build(FB, S.psa.p, sa_t, nullptr, m0, d, d, nu2, stream));
-  if (!fused) RS_HIP(hipStreamWaitEvent(stream, S.join_ev, 0));
-  // 3. r_k = q_k / 2 with q_k = u_k^T H_S0^-1 u_k
+  if (join) RS_HIP(hipStreamWaitEvent(stream, S.join_ev, 0));
+  // r_k = q_k / 2 with q_k = u_k^T H_S0^-1 u_k
   RS_TRY(S.pr.ensure(8 * sizeof(double)));
   if (wood) {
     RS_TRY(S.pY.ensure((size_t)8 * m0 * sizeof(double)));
@@ -981,6 +1016,15 @@ static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int
     }
   }
   return features_final(S.pU.as<double>(), d, S.pr.as<double>(), n, nu2, feat, stream);
+}
+
+static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
+                              int64_t d, int64_t lda, const void* b, double nu2, uint64_t seed,
+                              float* feat, hipStream_t stream) {
+  RS_TRY(features_buffers(S, a_t, n, d, stream));
+  bool join = false;
+  RS_TRY(features_head(S, A, a_t, n, d, lda, b, seed, stream, &join));
+  return features_tail(S, a_t, n, d, nu2, feat, join, stream);
 }
 
 // m_init from the predicted log2 m: 2^floor(pred), clamped to [1, m_max].
@@ -1104,6 +1148,13 @@ struct SolveJob {
   int phase = 1;
   int64_t m_init_used = 0;
   bool atb_ready = false;  // the features pass left A^T b in S->pU
+  bool defer = false;      // steps and reads left to a pair driver
+  // the learned features' head taken from a partner's scratch (feat_wait: recorded
+  // on the partner's stream after it)
+  const DeviceScratch* feat_from = nullptr;
+  hipEvent_t feat_wait = nullptr;
+  int pend_q = 0;
+  bool pend_read = false;
   // queued steps replayed from HIP graphs (one for a single step, one for
   // check_every steps), captured on first use under the current factor and
   // dropped when the job refactors (the apply's route and buffers follow m)
@@ -1154,12 +1205,15 @@ struct SolveJob {
   // one step = the gradient pass over the candidates (left in X by the previous
   // decision, or by the start / resample kernels), the apply, and the decision,
   // which also writes the next step's candidates
+  rs_status after_grad() {
+    RS_TRY(apply(G, K, GT, status));
+    return decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g, gt,
+                         S->ev.as<int32_t>(), ev_cap, stream, true, snap());
+  }
   rs_status enqueue_steps(int q) {
     for (int it = 0; it < q; ++it) {
       RS_TRY(grad(X, K, G, status, stream));
-      RS_TRY(apply(G, K, GT, status));
-      RS_TRY(decide_launch(K, dctl, S->rpart.as<double>(), nrp, cp, d, X, G, GT, x, x_prev, g,
-                           gt, S->ev.as<int32_t>(), ev_cap, stream, true, snap()));
+      RS_TRY(after_grad());
     }
     return RS_OK;
   }
@@ -1167,6 +1221,10 @@ struct SolveJob {
   NextCand next_cand() { return NextCand{X, prm.mu_p, prm.beta_p, prm.mu_gd, K}; }
 
   rs_status steps(int q) {
+    if (defer) {
+      pend_q = q;
+      return RS_OK;
+    }
     if (!use_graph || g_prof_on || (q != 1 && q != check_every)) return enqueue_steps(q);
     hipGraphExec_t& ex = gx[q == 1 ? 0 : 1];
     if (!ex) {
@@ -1290,6 +1348,20 @@ struct SolveJob {
   // the control record and the factor's pivot flag reach pinned host memory from
   // the kernels that change them (CtlSnap); the host waits for this event
   rs_status enqueue_read() {
+    if (defer) {
+      pend_read = true;
+      return RS_OK;
+    }
+    RS_HIP(hipEventRecord(S->done_ev, stream));
+    return RS_OK;
+  }
+  // deferred mode (a pair of jobs driven together): the steps and the read a
+  // decision asks for are left to the driver, which queues them after the partner's
+  // decision (the steps both jobs have share their gradient passes)
+  rs_status flush_read() {
+    pend_q = 0;
+    if (!pend_read) return RS_OK;
+    pend_read = false;
     RS_HIP(hipEventRecord(S->done_ev, stream));
     return RS_OK;
   }
@@ -1368,8 +1440,17 @@ struct SolveJob {
     if (!S->host_pinned) RS_HIP(hipHostMalloc(&S->host_pinned, 4096, hipHostMallocCoherent));
     if (!S->done_ev) RS_HIP(hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming));
     RS_TRY(S->pfeat.ensure(16 * sizeof(float)));
-    RS_TRY(features_run(*S, A, a_t, n, d, lda, sp ? nullptr : b, nu2, o.seed,
-                        S->pfeat.as<float>(), stream));
+    if (feat_from) {
+      // a partner on the same A, b and seed formed the features' head: copy it and
+      // finish at this job's nu
+      RS_TRY(features_buffers(*S, a_t, n, d, stream));
+      RS_HIP(hipStreamWaitEvent(stream, feat_wait, 0));
+      RS_TRY(features_copy_head(*S, *feat_from, a_t, n, d, stream));
+      RS_TRY(features_tail(*S, a_t, n, d, nu2, S->pfeat.as<float>(), false, stream));
+    } else {
+      RS_TRY(features_run(*S, A, a_t, n, d, lda, sp ? nullptr : b, nu2, o.seed,
+                          S->pfeat.as<float>(), stream));
+    }
     atb_ready = !sp;
     // the prediction goes straight to pinned host memory
     RS_TRY(mlp_forward(lp_params, S->pfeat.as<float>(), 1, lp_mu, lp_sd,
@@ -1702,6 +1783,100 @@ rs_status rs_solve_path(const void* A, rs_dtype a_t, int64_t n, int64_t d, int64
 
 namespace rs {
 
+// Whether two jobs of a batch can run as a pair: the same FP32 A and b (pointers,
+// shape, leading dimension), two candidates per step, no step graphs, and a k = 2
+// gradient plan on the kernel that has a two-job form.
+static bool pairable(const SolveJob& a, const SolveJob& b) {
+  return a.A == b.A && a.b == b.b && a.a_t == RS_F32 && b.a_t == RS_F32 && a.n == b.n &&
+         a.d == b.d && a.lda == b.lda && a.K == 2 && b.K == 2 && !a.use_graph && !b.use_graph &&
+         !a.sp && !b.sp && !a.cvec && !b.cvec &&
+         gradient_two_fits(a.n, a.d, a.lda, grad_partial_blocks_max(a.n));
+}
+
+// Two jobs on the same A and b, each on its own stream and scratch, driven by one
+// host thread in rounds.  A round waits for both jobs' control records, lets each
+// decide its next work (resample, steps, or the end) with its steps and read held
+// back, then queues the steps both have as shared steps: one gradient pass for the
+// two (gradient_two_launch, each job's result bit for bit its own pass) on job 0's
+// stream once job 1's last decision is in, then each job's apply and decision on its
+// own stream.  A job's extra steps run alone, and each read follows its job's last
+// step.  The device decides every step as in a solve alone (queued steps past a
+// rejection or the stop are no-ops), so trajectories and solutions are the jobs' own.
+// With learned starts the features' head (its pass over A) is formed once, by job 0.
+static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
+  auto fail = [](SolveJob& j, rs_status st) {
+    if (!j.done) {
+      j.done = true;
+      j.result = st;
+      j.info->status = st;
+    }
+  };
+  // learned starts: job 1 takes the features' head (one pass over A, independent
+  // of nu) from job 0's scratch and finishes them at its own nu
+  const bool share_head = J[0]->lp_params && J[1]->lp_params && !J[0]->sp && !J[1]->sp &&
+                          J[0]->o.seed == J[1]->o.seed;
+  for (int k = 0; k < 2; ++k) {
+    J[k]->defer = true;
+    if (k == 1 && share_head && !J[0]->done) {
+      const hipError_t e = hipEventRecord(ev[0], J[0]->stream);
+      if (e != hipSuccess) {
+        fail(*J[1], set_error(RS_ERR_HIP, hipGetErrorString(e)));
+        continue;
+      }
+      J[1]->feat_from = J[0]->S;
+      J[1]->feat_wait = ev[0];
+    }
+    const rs_status st = J[k]->begin();
+    if (st != RS_OK) fail(*J[k], st);
+  }
+  const int grid = grad_partial_blocks_max(J[0]->n);
+  auto issue = [&]() -> rs_status {
+    const bool both = !J[0]->done && !J[1]->done;
+    const int common = both ? std::min(J[0]->pend_q, J[1]->pend_q) : 0;
+    if (common > 0) {
+      const size_t pbytes = (size_t)grid * 4 * J[0]->d * sizeof(double);
+      RS_TRY(J[0]->S->partial.ensure(pbytes));
+      RS_TRY(J[1]->S->partial.ensure(pbytes));
+      const double nu2[2] = {J[0]->nu2, J[1]->nu2};
+      const double* X[2] = {J[0]->X, J[1]->X};
+      double* G[2] = {J[0]->G, J[1]->G};
+      double* P[2] = {J[0]->S->partial.as<double>(), J[1]->S->partial.as<double>()};
+      const int* stt[2] = {J[0]->status, J[1]->status};
+      for (int it = 0; it < common; ++it) {
+        RS_HIP(hipEventRecord(ev[1], J[1]->stream));
+        RS_HIP(hipStreamWaitEvent(J[0]->stream, ev[1], 0));
+        RS_TRY(gradient_two_launch(reinterpret_cast<const float*>(J[0]->A), J[0]->n, J[0]->d,
+                                   J[0]->lda, reinterpret_cast<const float*>(J[0]->b), nu2, X, G,
+                                   P, grid, stt, J[0]->stream));
+        RS_HIP(hipEventRecord(ev[0], J[0]->stream));
+        RS_HIP(hipStreamWaitEvent(J[1]->stream, ev[0], 0));
+        RS_TRY(J[0]->after_grad());
+        RS_TRY(J[1]->after_grad());
+      }
+    }
+    for (int k = 0; k < 2; ++k) {
+      if (J[k]->done) continue;
+      if (J[k]->pend_q > common) RS_TRY(J[k]->enqueue_steps(J[k]->pend_q - common));
+      RS_TRY(J[k]->flush_read());
+    }
+    return RS_OK;
+  };
+  for (;;) {
+    const rs_status st = issue();
+    if (st != RS_OK) {
+      for (int k = 0; k < 2; ++k) fail(*J[k], st);
+      return;
+    }
+    if (J[0]->done && J[1]->done) return;
+    for (int k = 0; k < 2; ++k) {
+      if (J[k]->done) continue;
+      const hipError_t e = hipEventSynchronize(J[k]->S->done_ev);
+      rs_status r = e == hipSuccess ? J[k]->advance() : set_error(RS_ERR_HIP, hipGetErrorString(e));
+      if (r != RS_OK) fail(*J[k], r);
+    }
+  }
+}
+
 static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const rs_solve_opts* opts,
                                   rs_solve_info* infos, int32_t workers, hipStream_t stream,
                                   const float* params, const float* mu, const float* sd,
@@ -1753,6 +1928,33 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
       first_msg = rs_last_error();
     }
   };
+  // Jobs on the same FP32 A and b form pairs (pairable); a pair shares its
+  // gradient passes (drive_pair) and takes two workers' streams and scratch:
+  // worker 2t drives the pairs of team t one after another while worker 2t + 1
+  // lends its set, then both take single jobs.
+  std::vector<char> in_pair((size_t)count, 0);
+  std::vector<std::array<int64_t, 2>> pairs;
+  if (W >= 2)
+    for (int64_t i = 0; i < count; ++i) {
+      if (in_pair[i]) continue;
+      for (int64_t j = i + 1; j < count; ++j)
+        if (!in_pair[j] && pairable(jobs[i], jobs[j])) {
+          pairs.push_back({i, j});
+          in_pair[i] = in_pair[j] = 1;
+          break;
+        }
+    }
+  std::vector<int64_t> singles;
+  for (int64_t i = 0; i < count; ++i)
+    if (!in_pair[i]) singles.push_back(i);
+  const int teams = (int)std::min<int64_t>(W / 2, (int64_t)pairs.size());
+  for (int t = 0; t < 2 * teams; ++t)
+    if (!pool->w[t]->step_ev)
+      RS_HIP(hipEventCreateWithFlags(&pool->w[t]->step_ev, hipEventDisableTiming));
+  std::atomic<int64_t> next_pair{0};
+  std::mutex tmu;
+  std::condition_variable tcv;
+  std::vector<char> team_done((size_t)teams, 0);
   std::vector<std::vector<void*>> retired((size_t)W);
   auto run = [&](int wi) {
     BatchWorker& w = *pool->w[wi];
@@ -1760,10 +1962,37 @@ static rs_status solve_batch_impl(const rs_problem* probs, int64_t count, const 
     struct Reset {
       ~Reset() { t_retire = nullptr; }
     } reset;
+    if (wi < 2 * teams) {
+      const int t = wi / 2;
+      if (wi % 2 == 0) {
+        BatchWorker& w1 = *pool->w[wi + 1];
+        for (;;) {
+          const int64_t pid = next_pair.fetch_add(1);
+          if (pid >= (int64_t)pairs.size()) break;
+          SolveJob* J[2] = {&jobs[pairs[pid][0]], &jobs[pairs[pid][1]]};
+          J[0]->S = &w.S;
+          J[0]->stream = w.s;
+          J[1]->S = &w1.S;
+          J[1]->stream = w1.s;
+          hipEvent_t ev[2] = {w.step_ev, w1.step_ev};
+          drive_pair(J, ev);
+          for (SolveJob* j : J)
+            if (j->result != RS_OK && j->result != RS_ERR_NO_CONVERGENCE) note(j->result);
+        }
+        {
+          std::lock_guard<std::mutex> g(tmu);
+          team_done[t] = 1;
+        }
+        tcv.notify_all();
+      } else {
+        std::unique_lock<std::mutex> lk(tmu);
+        tcv.wait(lk, [&] { return team_done[t] != 0; });
+      }
+    }
     for (;;) {
-      const int64_t id = next.fetch_add(1);
-      if (id >= count) return;
-      SolveJob& J = jobs[id];
+      const int64_t sid_ = next.fetch_add(1);
+      if (sid_ >= (int64_t)singles.size()) return;
+      SolveJob& J = jobs[singles[sid_]];
       J.S = &w.S;
       J.stream = w.s;
       rs_status st = J.begin();

@@ -1,0 +1,137 @@
+"""Batches whose jobs share A and b run as pairs: one gradient pass per shared step
+serves both jobs (the two-job pass), and every job still gives exactly what it gives
+alone (trajectory and solution), for plain and learned starts, FP32 and BF16
+sketches, one job resampling while the other steps, pairs beside other problems,
+and more pairs than worker teams."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ridge  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N, D = 12000, 4096
+PLAN = (512, 2, 128, 4)          # the 512-thread kernel with two vectors per thread
+
+
+@pytest.fixture(scope="module")
+def rs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_05874_amd import rs as _rs
+    _rs.load()
+    return _rs
+
+
+def shared_problem(seed=0, n=N, d=D):
+    """A = G diag(i^-1) / sqrt(n) with Gaussian G (nominal spectrum 1/i), b = A x + noise."""
+    rng = np.random.default_rng(seed)
+    sigma = 1.0 / np.arange(1, d + 1)
+    A = (rng.standard_normal((n, d)) * (sigma / np.sqrt(n))[None, :]).astype(np.float32)
+    b = (A.astype(np.float64) @ rng.standard_normal(d) + 0.1 * rng.standard_normal(n))
+    return A, b.astype(np.float32)
+
+
+def upload(A, b, rs):
+    T = rs.padded(A.shape[0], A.shape[1], dtype=torch.float32)
+    T.copy_(torch.from_numpy(A))
+    return T, torch.from_numpy(b).cuda()
+
+
+def grad_launches(rs, fn):
+    rs.rs_profile_read()        # clears the counters
+    rs.rs_profile_enable(True)
+    try:
+        out = fn()
+        torch.cuda.synchronize()
+        launches, _ = rs.rs_profile_read()
+    finally:
+        rs.rs_profile_enable(False)
+    return out, launches
+
+
+def same(a, b):
+    (x, i), (y, j) = a, b
+    assert i["status"] == j["status"] == "ok"
+    assert i["events"] == j["events"] and i["m_final"] == j["m_final"]
+    assert i["grad_passes"] == j["grad_passes"]
+    assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("sketch_dtype", [None, "bf16"])
+def test_pair_equals_single_solves_and_shares_passes(rs, sketch_dtype):
+    A, b = shared_problem(1)
+    Ad, bd = upload(A, b, rs)
+    rs.rs_gradient_set_plan("f32", N, D, 2, PLAN)
+    nus = (1e-2, 1e-4)
+    batch, lb = grad_launches(rs, lambda: rs.rs_solve_batch(
+        [(Ad, bd, nu) for nu in nus], sketch_dtype=sketch_dtype, workers=2))
+    singles, ls = [], 0
+    for nu in nus:
+        r, l = grad_launches(rs, lambda: rs.rs_adaptive_solve(Ad, bd, nu,
+                                                              sketch_dtype=sketch_dtype))
+        singles.append(r)
+        ls += l
+    for r, s in zip(batch, singles):
+        same(r, s)
+    # the pair ran its common steps as shared passes: fewer gradient launches
+    assert lb < ls, (lb, ls)
+    # and the solutions are the ridge solutions
+    A64 = A.astype(np.float64)
+    G = A64.T @ A64
+    Atb = A64.T @ b.astype(np.float64)
+    for nu, (x, _) in zip(nus, batch):
+        xs = ridge.solve_direct_from_gram(G, Atb, nu)
+        assert ridge.relative_error(G + nu * np.eye(D), x.cpu().numpy(), xs) <= 1e-6
+
+
+@pytest.mark.parametrize("workers", [2, 5])
+def test_pairs_beside_other_problems(rs, workers):
+    # four jobs on one (A, b) form two pairs, a fifth problem runs alone; with two
+    # workers one team drives both pairs in turn
+    A, b = shared_problem(2)
+    Ad, bd = upload(A, b, rs)
+    rs.rs_gradient_set_plan("f32", N, D, 2, PLAN)
+    A2, b2 = shared_problem(3, n=3000, d=200)
+    A2d, b2d = upload(A2, b2, rs)
+    probs = [(Ad, bd, 1e-1), (Ad, bd, 1e-2), (A2d, b2d, 1e-3), (Ad, bd, 1e-3), (Ad, bd, 1e-5)]
+    batch = rs.rs_solve_batch(probs, seed=3, workers=workers)
+    for (Ax, bx, nu), r in zip(probs, batch):
+        same(r, rs.rs_adaptive_solve(Ax, bx, nu, seed=3))
+
+
+def test_learned_pair_equals_single_learned_solves(rs):
+    from paper_2006_05874_amd import learned as L
+    params, mu, sd, _ = L.load_model()
+    A, b = shared_problem(4)
+    Ad, bd = upload(A, b, rs)
+    rs.rs_gradient_set_plan("f32", N, D, 2, PLAN)
+    nus = (1e-2, 1e-4)
+    batch, lb = grad_launches(rs, lambda: rs.rs_learned_solve_batch(
+        [(Ad, bd, nu) for nu in nus], params, mu, sd, sketch_dtype="bf16", workers=2))
+    ls = 0
+    for nu, r in zip(nus, batch):
+        s, l = grad_launches(rs, lambda: rs.rs_learned_solve(Ad, bd, nu, params, mu, sd,
+                                                             sketch_dtype="bf16"))
+        assert r[1]["m_init"] == s[1]["m_init"]
+        same(r, s)
+        ls += l
+    assert lb < ls, (lb, ls)
+
+
+def test_no_pair_without_the_two_job_plan(rs):
+    # a plan off the 512-thread kernel: the jobs run alone, with the same results
+    A, b = shared_problem(5, n=6000, d=1000)
+    Ad, bd = upload(A, b, rs)
+    rs.rs_gradient_set_plan("f32", 6000, 1000, 2, (64, 4, 64, 4))
+    nus = (1e-2, 1e-3)
+    batch, lb = grad_launches(rs, lambda: rs.rs_solve_batch([(Ad, bd, nu) for nu in nus],
+                                                            workers=2))
+    ls = 0
+    for nu, r in zip(nus, batch):
+        s, l = grad_launches(rs, lambda: rs.rs_adaptive_solve(Ad, bd, nu))
+        same(r, s)
+        ls += l
+    assert lb == ls
