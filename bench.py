@@ -111,6 +111,9 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_partial_65536x1024_f32_traffic.txt")
 TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "k_grad_wide_2p21x8192_f32_traffic.txt")
+# the two-job pass (a pair's shared gradient) at 2^21 x 8192
+TRAFFIC_FILE_C5_TWO = os.path.join(ROOT, "profiles",
+                                   "k_grad_wide_two_2p21x8192_f32_traffic.txt")
 # counter summaries of the BF16 SRHT at 2^21 x 8192, per sketch size
 SRHT_TRAFFIC_FILES_C5 = {m: os.path.join(ROOT, "profiles", f"k_srht_2p21x8192_m{m}_bf16_traffic.txt")
                          for m in (512, 4096)}
@@ -594,8 +597,10 @@ def run_c5(args):
     seed 5).  One step = the solve at nu^2 = 1e-2 and the solve at nu^2 = 1e-4
     (nominal effective dimensions 15.2 and 155), each to the default decrement
     tolerance.  The value is the learned form with the step's two solves batched
-    (rs_learned_solve_batch, two worker streams); the same solves one at a time on
-    one stream and the plain method are timed beside it.  Every timed solve is
+    (rs_learned_solve_batch: the two jobs share A and b, so they run as a pair on
+    two worker streams, with one features pass and one gradient pass per common
+    step for both); the same solves one at a time on one stream and the plain
+    method are timed beside it.  Every timed solve is
     judged afterwards by the oracle's streamed certificate (an upper bound on
     delta(x) / delta(0) from one FP64 pass over the stored A)."""
     import torch
@@ -670,24 +675,34 @@ def run_c5(args):
         plain = {"steps": psteps, "warmup": 1, "ms_per_step": pms / psteps,
                  "value": psteps * len(C5_NU2S) / (pms / 1e3), "res": pres}
 
-    # roofline of the dominant kernel: one more step with every gradient pass timed
-    # by HIP events on its stream
+    # roofline of the dominant kernel: one more step of the timed form with every
+    # gradient pass timed by HIP events on its stream (algorithmic bytes per launch:
+    # A and b once, also for a pair's shared pass)
     grad_bytes = n * d * 4 + n * 4
     kname = "k_grad_wide / k_grad_partial (A^T(AX-b) pass over 64 GiB, tuned plan)"
-    rmode = "learned" if main_mode == "batched" else main_mode
-    roof = gradient_roofline(rs, lambda: one_step(rmode), grad_bytes, kname,
-                             "one more step" + (", its solves one at a time"
-                                                if main_mode == "batched" else ""))
-    roof_over = None
+    kname_two = ("k_grad_wide_two (a pair's shared A^T(AX-b) pass: both solves' two "
+                 "candidates in one read of the 64 GiB A)")
+    roof_single = None
     if main_mode == "batched":
-        # the batched step: the two streams' passes share HBM, so a launch takes longer
-        roof_over = gradient_roofline(rs, lambda: one_step("batched"), grad_bytes, kname,
-                                      "one more batched step (two worker streams)")
+        roof = gradient_roofline(rs, lambda: one_step("batched"), grad_bytes, kname_two,
+                                 "one more batched step (the pair's passes; a pass after "
+                                 "one job has stopped runs alone)")
+        tt = recorded_traffic(TRAFFIC_FILE_C5_TWO, GRAD_SOURCES)
+        if tt and list(plans[2])[0] == 512:
+            roof["traffic"] = round(tt)
+            roof["traffic_source"] = (os.path.relpath(TRAFFIC_FILE_C5_TWO, ROOT) + " (two-job "
+                                      "pass, FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB copy)")
+        roof_single = gradient_roofline(rs, lambda: one_step("learned"), grad_bytes, kname,
+                                        "one more step, its solves one at a time")
+    else:
+        roof = gradient_roofline(rs, lambda: one_step(main_mode), grad_bytes, kname,
+                                 "one more step")
     traffic = recorded_traffic(TRAFFIC_FILE_C5, GRAD_SOURCES)
+    rk2 = roof_single if roof_single is not None else roof
     if traffic and list(plans[2])[0] == 512:
-        roof["traffic"] = round(traffic)
-        roof["traffic_source"] = ("profiles/k_grad_wide_2p21x8192_f32_traffic.txt (k = 2 pass, "
-                                  "FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB copy)")
+        rk2["traffic"] = round(traffic)
+        rk2["traffic_source"] = ("profiles/k_grad_wide_2p21x8192_f32_traffic.txt (k = 2 pass, "
+                                 "FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB copy)")
     # the SRHT at the sketch size each learned solve started from (BF16 output),
     # timed by events around the call on its stream
     srht = {}
@@ -794,7 +809,8 @@ def run_c5(args):
                                + ("learned m_init, BF16 sketch" if learned_form
                                   else "m_init=1, FP32 sketch")
                                + f", {args.variant}, 2 solves per step, "
-                               + ("batched over 2 worker streams" if main_mode == "batched"
+                               + ("batched as a pair on 2 worker streams (shared features "
+                                  "and gradient passes)" if main_mode == "batched"
                                   else "one stream"),
                    "mode": main_mode, "n": n, "d": d,
                    "gradient_plan_k2": list(plans[2]), "parallelism": "single GPU"},
@@ -807,8 +823,8 @@ def run_c5(args):
         "roofline": roof, "srht_roofline": srht,
         "phases_ms": phases,
     }
-    if roof_over is not None:
-        line["roofline_overlapped"] = roof_over
+    if roof_single is not None:
+        line["roofline_one_at_a_time"] = roof_single
     if single is not None:
         sok, srel, ssol = summary("single")
         line["learned_bf16_one_at_a_time"] = {
