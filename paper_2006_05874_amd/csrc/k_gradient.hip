@@ -210,6 +210,25 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
   }
 }
 
+// wave_sum's butterfly (xor 32, 16, 8, 4, 2, 1, in that order) with the four
+// in-row stages as DPP moves instead of LDS permutes.  xor 8 is row_ror:8 and xor
+// 2, xor 1 are quad permutes (the same partners); row_ror:4 takes lane p +- 4 in
+// place of p ^ 4, and after the xor-8 stage lanes 8 apart hold the same bits, so
+// the operands, and every lane's result, are wave_sum's bit for bit.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += __shfl_xor(v, 32, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
+                                                              0xF, 0xF, false));  // row_ror:8
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
+                                                              0xF, 0xF, false));  // row_ror:4
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E,
+                                                              0xF, 0xF, false));  // [2,3,0,1]
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1,
+                                                              0xF, 0xF, false));  // [1,0,3,2]
+  return v;
+}
+
 // Wide rows (FP32, up to 512 * NV * 4 columns): one row group per block of 512
 // threads, thread lt holding the 16-byte vectors lt + 512 v (v < NV) of every row,
 // R rows per step.  The rows of step s + 1 are loaded into a second register set
@@ -283,17 +302,20 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
             float4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[v], (uint32_t)r * rowb, 0));
     }
   };
-  auto process = [&](float4 (&a)[R][NV], int step) {
+  // MASK: zero A values past d (padding columns may hold anything); a d that fills
+  // every thread's columns runs the loop without the selects
+  auto process = [&](float4 (&a)[R][NV], int step, auto mask) {
     const int buf = step & 1;
-    // zero A values past d (padding columns may hold anything)
+    if constexpr (decltype(mask)::value) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const bool ok = (int64_t)(lt + 512 * v) * 4 + e < d;
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = (int64_t)(lt + 512 * v) * 4 + e < d;
 #pragma unroll
-        for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
-      }
+          for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -303,10 +325,17 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
         for (int v = 0; v < NV; ++v)
 #pragma unroll
           for (int e = 0; e < 4; ++e) t = fmaf(get(a[i][v], e), xv[k][v][e], t);
-        t = wave_sum(t);
+        t = wave_sum_dpp(t);
         if ((lt & 63) == 0) red[buf][w][i * K + k] = t;
       }
     __syncthreads();
+    // lane q < R K of each wave adds the NW wave partials of dot q in wave order;
+    // readlane hands the sums to the whole wave
+    float mine = 0.0f;
+    if ((lt & 63) < R * K) {
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) mine += red[buf][ww][lt & 63];
+    }
     float res[K][R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -315,9 +344,8 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
       const float bi = b[row0 + (live ? r : 0)];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        float t = 0.0f;
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww) t += red[buf][ww][i * K + k];
+        const float t = __builtin_bit_cast(
+            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine), i * K + k));
         res[k][i] = live ? t - bi : 0.0f;
       }
     }
@@ -333,15 +361,21 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
           acc[k][v][e] += (double)t;
         }
   };
-  float4 a0[R][NV], a1[R][NV];
-  load(a0, 0);
-  for (int it = 0; it < iters; it += 2) {
-    if (it + 1 < iters) load(a1, it + 1);
-    process(a0, it);
-    if (it + 1 >= iters) break;
-    if (it + 2 < iters) load(a0, it + 2);
-    process(a1, it + 1);
-  }
+  auto run = [&](auto mask) {
+    float4 a0[R][NV], a1[R][NV];
+    load(a0, 0);
+    for (int it = 0; it < iters; it += 2) {
+      if (it + 1 < iters) load(a1, it + 1);
+      process(a0, it, mask);
+      if (it + 1 >= iters) break;
+      if (it + 2 < iters) load(a0, it + 2);
+      process(a1, it + 1, mask);
+    }
+  };
+  if (d >= (int64_t)2048 * NV)
+    run(std::false_type{});
+  else
+    run(std::true_type{});
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -351,25 +385,6 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
         const int64_t c = (int64_t)(lt + 512 * v) * 4 + e;
         if (c < d) partial[((int64_t)blockIdx.x * K + k) * d + c] = acc[k][v][e];
       }
-}
-
-// wave_sum's butterfly (xor 32, 16, 8, 4, 2, 1, in that order) with the four
-// in-row stages as DPP moves instead of LDS permutes.  xor 8 is row_ror:8 and xor
-// 2, xor 1 are quad permutes (the same partners); row_ror:4 takes lane p +- 4 in
-// place of p ^ 4, and after the xor-8 stage lanes 8 apart hold the same bits, so
-// the operands, and every lane's result, are wave_sum's bit for bit.
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-  v += __shfl_xor(v, 32, 64);
-  v += __shfl_xor(v, 16, 64);
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
-                                                              0xF, 0xF, false));  // row_ror:8
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
-                                                              0xF, 0xF, false));  // row_ror:4
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E,
-                                                              0xF, 0xF, false));  // [2,3,0,1]
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1,
-                                                              0xF, 0xF, false));  // [1,0,3,2]
-  return v;
 }
 
 // Two problems that share A and b (two nu, or two starts), each with two columns:

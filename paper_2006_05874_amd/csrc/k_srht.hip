@@ -787,18 +787,29 @@ __global__ __launch_bounds__(256) void k_p2_dest(const int32_t* __restrict__ qli
   dest2[q * n1 + r1] = v;
 }
 
-template <typename OutT, bool EDGE>
+// DUAL: a second, smaller sketch of the same seed and sketch_id (its rows are a
+// subset of this one's) written from the same transformed rows: destination rows
+// dest2b (-1: not in it), its own output, leading dimension and scale.
+struct P2Dual {
+  const int32_t* dest2b;
+  void* out;
+  int64_t ldo;
+  float scale;
+};
+
+template <typename OutT, bool EDGE, bool DUAL>
 __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, int64_t Qmax,
                                                  int lb1, int64_t n2, int64_t d,
                                                  const int32_t* __restrict__ dest2,
                                                  const int32_t* __restrict__ qcount,
                                                  OutT* __restrict__ out, int64_t ldo,
                                                  float scale, int64_t ytile0, int64_t np32,
-                                                 int64_t ntile) {
+                                                 int64_t ntile, P2Dual du) {
   constexpr int RT = kP2Rows;
   constexpr int J = kP2J;
   __shared__ float2 lds[RT * 4];
   __shared__ int32_t dest[RT];
+  __shared__ int32_t destb[DUAL ? RT : 1];
   const int64_t slot = blockIdx.x >> 3;
   const int64_t item = (slot >> 1) * 8 + (blockIdx.x & 7);
   if (item >= np32 * ntile) return;  // uniform: the grid is rounded up to 16 blocks
@@ -847,6 +858,18 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
     const int r = t + 256 * u;
     dest[r] = r < valid ? dv[u] : -1;
   }
+  if constexpr (DUAL) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = t + 256 * u;
+      dv[u] = du.dest2b[q0 * n1 + (r < valid ? r : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = t + 256 * u;
+      destb[r] = r < valid ? dv[u] : -1;
+    }
+  }
   reg_fwht2<J, 6>(v, 5, lb1);
   for (int h = 0; h < 2; ++h) {
     if (half == h) {
@@ -865,14 +888,12 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
   if (col >= d) return;
   const bool pair = col + 1 < d;
   constexpr uintptr_t kAlign = sizeof(OutT) == 2 ? 4 : 8;
-  const bool vec_ok = pair && ((reinterpret_cast<uintptr_t>(out) |
-                                (uintptr_t)(ldo * (int64_t)sizeof(OutT))) & (kAlign - 1)) == 0;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int32_t k = dest[64 * g + j];
-    if (k < 0) continue;
-    OutT* o = out + (int64_t)k * ldo + col;
-    const float a = v[j].x * scale, b = v[j].y * scale;
+  // one output row: the two columns scaled, rounded to OutT, stored
+  auto put = [&](OutT* base, int64_t ld, int64_t k, float sc, float2 val) {
+    const bool vec_ok = pair && ((reinterpret_cast<uintptr_t>(base) |
+                                  (uintptr_t)(ld * (int64_t)sizeof(OutT))) & (kAlign - 1)) == 0;
+    OutT* o = base + k * ld + col;
+    const float a = val.x * sc, b = val.y * sc;
     if constexpr (sizeof(OutT) == 2) {
       if (vec_ok) {
         *reinterpret_cast<uint32_t*>(o) =
@@ -888,6 +909,15 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
         o[0] = a;
         if (pair) o[1] = b;
       }
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int32_t k = dest[64 * g + j];
+    if (k >= 0) put(out, ldo, k, scale, v[j]);
+    if constexpr (DUAL) {
+      const int32_t k2 = destb[64 * g + j];
+      if (k2 >= 0) put(reinterpret_cast<OutT*>(du.out), du.ldo, k2, du.scale, v[j]);
     }
   }
 }
@@ -955,9 +985,11 @@ template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
                          int64_t Qmax, hipStream_t s, double scale_override,
-                         const ProbeArgs* probe) {
+                         const ProbeArgs* probe, const SrhtDual* dual) {
   if (probe && (sizeof(T) != 4 || !srht_panel_path(npad, lda)))
     return set_error(RS_ERR_ARG, "srht: the probe sums ride on the panel-major path only");
+  if (dual && !(sizeof(T) == 4 && srht_panel_path(npad, lda)))
+    return set_error(RS_ERR_ARG, "srht: a second output rides on the panel-major path only");
   using TT = Tile<T>;
   const int64_t n2 = npad < TT::RT ? npad : TT::RT;
   const int64_t n1 = npad / n2;
@@ -1018,6 +1050,13 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       }
       hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((Qmax * n1 + 255) / 256)), dim3(256), 0, s,
                          B.qlist, B.kmap, B.qcount, Qmax, n1, n2, B.dest2);
+      // the second sketch's rows among this one's transformed rows (its low indices
+      // are among this selection's, so this Z holds them all)
+      if (dual)
+        hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((Qmax * n1 + 255) / 256)), dim3(256), 0,
+                           s, B.qlist, dual->kmap2, B.qcount, Qmax, n1, n2, dual->dest2b);
+      const P2Dual du = dual ? P2Dual{dual->dest2b, dual->SA2, dual->ldsa2, (float)dual->scale2}
+                             : P2Dual{nullptr, nullptr, 0, 0.0f};
       const int64_t t2 = (Qmax * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
       const int64_t t2full = Qmax * n1 / kP2Rows;
       const float* Z = Zw;
@@ -1026,22 +1065,26 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       auto p2_grid = [&](int64_t ntile) {
         return dim3((unsigned)((P * ntile + 7) / 8 * 16));
       };
-      auto p2 = [&](auto out_tag) {
+      auto p2 = [&](auto out_tag, auto dual_tag) {
         using OutT = decltype(out_tag);
+        constexpr bool DU = decltype(dual_tag)::value;
         OutT* o = reinterpret_cast<OutT*>(SA);
         if (t2full > 0)
-          hipLaunchKernelGGL((k_srht_p2<OutT, false>), p2_grid(t2full), dim3(256), 0, s, Z, Qmax,
-                             lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, (int64_t)0, P,
-                             t2full);
+          hipLaunchKernelGGL((k_srht_p2<OutT, false, DU>), p2_grid(t2full), dim3(256), 0, s, Z,
+                             Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale,
+                             (int64_t)0, P, t2full, du);
         if (t2 > t2full)
-          hipLaunchKernelGGL((k_srht_p2<OutT, true>), p2_grid(1), dim3(256), 0, s, Z, Qmax, lb1,
-                             n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full, P,
-                             (int64_t)1);
+          hipLaunchKernelGGL((k_srht_p2<OutT, true, DU>), p2_grid(1), dim3(256), 0, s, Z, Qmax,
+                             lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full, P,
+                             (int64_t)1, du);
       };
-      if (bf16)
-        p2(uint16_t{});
-      else
-        p2(float{});
+      if (bf16) {
+        if (dual) p2(uint16_t{}, std::true_type{});
+        else p2(uint16_t{}, std::false_type{});
+      } else {
+        if (dual) p2(float{}, std::true_type{});
+        else p2(float{}, std::false_type{});
+      }
       return check_launch("srht two pass");
     }
   }
@@ -1064,10 +1107,12 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
 
 template rs_status srht_transform<float>(const SrhtBuffers&, const float*, int64_t, int64_t,
                                          int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
-                                         int64_t, hipStream_t, double, const ProbeArgs*);
+                                         int64_t, hipStream_t, double, const ProbeArgs*,
+                                         const SrhtDual*);
 template rs_status srht_transform<double>(const SrhtBuffers&, const double*, int64_t, int64_t,
                                           int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
-                                          int64_t, hipStream_t, double, const ProbeArgs*);
+                                          int64_t, hipStream_t, double, const ProbeArgs*,
+                                          const SrhtDual*);
 
 // ---------------------------------------------------------------- nested gather
 // SA[k] = scale * HDA[rows[k]] for the cached transform of the whole padded A

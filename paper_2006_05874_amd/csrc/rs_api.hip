@@ -185,6 +185,9 @@ struct DeviceScratch {
   // SRHT
   DevBuf hist, signs, kmap, state, cand_key, cand_idx, blk_less, used, qmap, qlist, qcount, zbuf, rows,
       dest2;
+  // a second, smaller sketch formed by the same transform (srht_run's dual output):
+  // its own selection's row map and low-index lists, and its pass-2 destinations
+  DevBuf kmap2, qmap2, qlist2, qcount2, rows2, dest2b;
   // gradient partials, vectors, control
   DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
   // solver-owned sketch and factor (wbuf: scratch of the Woodbury-form apply)
@@ -371,10 +374,25 @@ static rs_status ensure_srht(DeviceScratch& S, int64_t npad, int64_t zbytes, Srh
 }
 
 // SRHT into SA (no argument checks).
+// A second SRHT of the same seed and sketch_id with m2 <= m rows (its rows are
+// among this one's) written by the same transform: SA2 (ldsa2, the dtype of SA).
+struct SrhtSecond {
+  int64_t m2;
+  void* SA2;
+  int64_t ldsa2;
+};
+
+// Whether srht_run can carry a SrhtSecond for this problem and sketch dtype.
+static bool srht_second_ok(rs_dtype a_t, int64_t n, int64_t lda, rs_dtype sa_t) {
+  return a_t == RS_F32 && (sa_t == RS_F32 || sa_t == RS_BF16) &&
+         srht_panel_path(next_pow2(n), lda);
+}
+
 static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n, int64_t d,
                           int64_t lda, int64_t m, uint64_t seed, uint32_t sid, void* SA,
                           rs_dtype sa_t, int64_t ldsa, float* scale_out, int64_t* rows_out,
-                          int8_t* signs_out, hipStream_t s, const ProbeArgs* probe = nullptr) {
+                          int8_t* signs_out, hipStream_t s, const ProbeArgs* probe = nullptr,
+                          const SrhtSecond* second = nullptr) {
   const int64_t npad = next_pow2(n);
   const int64_t n2 = std::min<int64_t>(npad, 1024);
   const int64_t Qmax = std::min<int64_t>(m, n2);
@@ -386,6 +404,28 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
     RS_TRY(S.rows.ensure((size_t)m * sizeof(int64_t)));
     rows = S.rows.as<int64_t>();
   }
+  SrhtDual dual{};
+  if (second) {
+    if (!srht_second_ok(a_t, n, lda, sa_t) || second->m2 < 1 || second->m2 > m)
+      return set_error(RS_ERR_ARG, "srht: no second output for this shape");
+    // the second sketch's own selection first (its row map and low-index lists in
+    // buffers of their own; the shared histogram and flags are left zero), then
+    // this one's, whose lists the transform uses
+    RS_TRY(S.kmap2.ensure((size_t)npad * sizeof(int32_t)));
+    RS_TRY(S.qmap2.ensure(1024 * sizeof(int32_t)));
+    RS_TRY(S.qlist2.ensure(1024 * sizeof(int32_t)));
+    RS_TRY(S.qcount2.ensure(sizeof(int32_t)));
+    RS_TRY(S.rows2.ensure((size_t)second->m2 * sizeof(int64_t)));
+    RS_TRY(S.dest2b.ensure((size_t)Qmax * (npad / n2) * sizeof(int32_t)));
+    SrhtBuffers B2 = B;
+    B2.kmap = S.kmap2.as<int32_t>();
+    B2.qmap = S.qmap2.as<int32_t>();
+    B2.qlist = S.qlist2.as<int32_t>();
+    B2.qcount = S.qcount2.as<int32_t>();
+    RS_TRY(srht_select(B2, seed, sid, npad, second->m2, n2, S.rows2.as<int64_t>(), s));
+    dual = SrhtDual{S.kmap2.as<int32_t>(), S.dest2b.as<int32_t>(), second->SA2, second->ldsa2,
+                    1.0 / std::sqrt((double)second->m2)};
+  }
   RS_TRY(srht_select(B, seed, sid, npad, m, n2, rows, s));
   if (a_t == RS_F32 && sa_t == RS_FP8E4M3) {
     RS_TRY(S.sa_tmp.ensure((size_t)m * d * sizeof(float)));
@@ -396,7 +436,7 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
                         reinterpret_cast<uint8_t*>(SA), ldsa, s));
   } else if (a_t == RS_F32)
     RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, m, SA, sa_t,
-                                 ldsa, Qmax, s, 0.0, probe));
+                                 ldsa, Qmax, s, 0.0, probe, second ? &dual : nullptr));
   else
     RS_TRY(srht_transform<double>(B, reinterpret_cast<const double*>(A), n, d, lda, npad, m, SA,
                                   sa_t, ldsa, Qmax, s));
@@ -1153,6 +1193,15 @@ struct SolveJob {
   // on the partner's stream after it)
   const DeviceScratch* feat_from = nullptr;
   hipEvent_t feat_wait = nullptr;
+  // the first sketch shared within a pair (same seed and sketch_id, m2 <= m): the
+  // job with the larger m forms both (sa_for: the partner, sa_done: recorded on
+  // this stream after the transform); the partner's SA is then given (sa_given,
+  // its stream waits for sa_wait) and it only factors
+  SolveJob* sa_for = nullptr;
+  int64_t sa_m2 = 0;
+  hipEvent_t sa_done = nullptr;
+  bool sa_given = false;
+  hipEvent_t sa_wait = nullptr;
   int pend_q = 0;
   bool pend_read = false;
   // queued steps replayed from HIP graphs (one for a single step, one for
@@ -1295,9 +1344,19 @@ struct SolveJob {
       tev.resize(tk + 3, nullptr);
       RS_TRY(tmark(&tev[tk]));
     }
-    if (reuse)
+    if (sa_given) {
+      // a partner's transform wrote this sketch into S->sa
+      RS_HIP(hipStreamWaitEvent(stream, sa_wait, 0));
+      sa_given = false;
+    } else if (reuse)
       ;  // SA (and its FP8 column scales) already hold this sketch
-    else if (sp)  // nested: the same hash at 2m splits every bucket in two
+    else if (sa_for) {
+      const SrhtSecond sec{sa_m2, sa_for->S->sa.p, sa_for->ldsa};
+      RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, nullptr,
+                      nullptr, stream, nullptr, &sec));
+      RS_HIP(hipEventRecord(sa_done, stream));
+      sa_for = nullptr;
+    } else if (sp)  // nested: the same hash at 2m splits every bucket in two
       RS_TRY(count_sketch_run(S->spw, *sp, mm, o.seed, id, S->sa.p, sa_t, ldsa, stream));
     else if (o.resample == RS_RESAMPLE_NESTED)
       RS_TRY(nested_sketch(*S, nc_shared ? *nc_shared : ncache, srht, A, a_t, n, d, lda, mm,
@@ -1457,6 +1516,13 @@ struct SolveJob {
                        reinterpret_cast<float*>((char*)S->host_pinned + 1024), nullptr, stream));
     RS_HIP(hipEventRecord(S->done_ev, stream));
     return RS_OK;
+  }
+
+  // the starting m of a learned job whose prediction has reached host memory
+  int64_t predicted_m() const {
+    float pred = 0.0f;
+    std::memcpy(&pred, (char*)S->host_pinned + 1024, sizeof(float));
+    return std::min<int64_t>(std::max<int64_t>(learned_m_init(pred, o, n), 1), m_cap);
   }
 
   // the previous batch has finished: decide what to enqueue next
@@ -1871,8 +1937,38 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
     for (int k = 0; k < 2; ++k) {
       if (J[k]->done) continue;
       const hipError_t e = hipEventSynchronize(J[k]->S->done_ev);
-      rs_status r = e == hipSuccess ? J[k]->advance() : set_error(RS_ERR_HIP, hipGetErrorString(e));
+      if (e != hipSuccess) fail(*J[k], set_error(RS_ERR_HIP, hipGetErrorString(e)));
+    }
+    // both learned predictions in: their first sketches have the same seed and
+    // sketch_id, so the job with the larger m forms both in one transform
+    int order[2] = {0, 1};
+    int prod = -1;
+    if (!J[0]->done && !J[1]->done && J[0]->phase == 0 && J[1]->phase == 0 && J[0]->srht &&
+        !J[0]->sp && J[0]->o.resample == RS_RESAMPLE_FRESH && J[0]->sid == J[1]->sid &&
+        J[0]->sa_t == J[1]->sa_t && srht_second_ok(J[0]->a_t, J[0]->n, J[0]->lda, J[0]->sa_t)) {
+      const int64_t mk[2] = {J[0]->predicted_m(), J[1]->predicted_m()};
+      const int p = mk[0] >= mk[1] ? 0 : 1, c = 1 - p;
+      if (J[c]->S->sa.ensure((size_t)mk[c] * J[c]->ldsa * J[c]->sa_es) == RS_OK) {
+        J[p]->sa_for = J[c];
+        J[p]->sa_m2 = mk[c];
+        J[p]->sa_done = ev[p];
+        J[c]->sa_given = true;
+        J[c]->sa_wait = ev[p];
+        order[0] = p;
+        order[1] = c;
+        prod = p;
+      }
+    }
+    for (int i = 0; i < 2; ++i) {
+      const int k = order[i];
+      if (J[k]->done) continue;
+      const rs_status r = J[k]->advance();
       if (r != RS_OK) fail(*J[k], r);
+      if (k == prod && J[k]->sa_for) {
+        // the transform was not queued: the partner forms its own sketch
+        J[k]->sa_for = nullptr;
+        J[1 - k]->sa_given = false;
+      }
     }
   }
 }

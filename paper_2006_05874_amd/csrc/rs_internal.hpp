@@ -70,11 +70,24 @@ struct ProbeArgs {
 // Whether srht_transform takes the panel-major two-pass path (the one that can
 // carry ProbeArgs) for FP32 A of padded size npad and leading dimension lda.
 bool srht_panel_path(int64_t npad, int64_t lda);
+// A second, smaller SRHT of the same seed and sketch_id formed by the same pass:
+// the m2 smallest keys are among the m smallest, so its rows are rows of this
+// transform.  kmap2: row -> its sample index or -1 (its own selection); dest2b:
+// scratch of Qmax * n1 int32; SA2 (ldsa2, sa_t of the first output) scaled by
+// scale2 = 1/sqrt(m2).  Values bit for bit those of its own transform.  FP32 A on
+// the panel-major path only.
+struct SrhtDual {
+  const int32_t* kmap2;
+  int32_t* dest2b;
+  void* SA2;
+  int64_t ldsa2;
+  double scale2;
+};
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
                          int64_t Qmax, hipStream_t s, double scale_override = 0.0,
-                         const ProbeArgs* probe = nullptr);
+                         const ProbeArgs* probe = nullptr, const SrhtDual* dual = nullptr);
 rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* rows, int64_t m,
                       int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
                       hipStream_t s);
