@@ -229,6 +229,42 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return v;
 }
 
+// S wave sums at once (S a power of two, at least 4) with wave_sum's pairings: the
+// xor-32 and xor-16 stages are transposed (a lane keeps half of its values and hands
+// the other half to its partner, which keeps the mirror half), so they take S/2 + S/4
+// permutes instead of 2 S; the in-row stages then run on the S/4 values left, as in
+// wave_sum_dpp.  Every sum adds the same lane pairs in the same order as wave_sum,
+// so its bits are wave_sum's.  On return v[u] (u < S/4) of lane L holds the sum of
+// value (L >> 4) * (S/4) + u, the same bits in all 16 lanes of L's row.
+template <int S>
+__device__ __forceinline__ void wave_sums_t(float (&v)[S]) {
+  static_assert(S >= 4 && (S & (S - 1)) == 0, "S: a power of two >= 4");
+  const int lane = threadIdx.x & 63;
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
+  float a[S / 2];
+#pragma unroll
+  for (int u = 0; u < S / 2; ++u) {
+    const float send = h5 ? v[u] : v[u + S / 2];
+    const float keep = h5 ? v[u + S / 2] : v[u];
+    a[u] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int u = 0; u < S / 4; ++u) {
+    const float send = h4 ? a[u] : a[u + S / 4];
+    const float keep = h4 ? a[u + S / 4] : a[u];
+    float c = keep + __shfl_xor(send, 16, 64);
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0x128, 0xF, 0xF, false));
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0x124, 0xF, 0xF, false));
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0x4E, 0xF, 0xF, false));
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0xB1, 0xF, 0xF, false));
+    v[u] = c;
+  }
+}
+
 // Wide rows (FP32, up to 512 * NV * 4 columns): one row group per block of 512
 // threads, thread lt holding the 16-byte vectors lt + 512 v (v < NV) of every row,
 // R rows per step.  The rows of step s + 1 are loaded into a second register set
@@ -316,6 +352,7 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
           for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
         }
     }
+    float dots[R * K];  // dot i * K + k
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -325,9 +362,22 @@ __global__ __launch_bounds__(512) void k_grad_wide(const float* __restrict__ A, 
         for (int v = 0; v < NV; ++v)
 #pragma unroll
           for (int e = 0; e < 4; ++e) t = fmaf(get(a[i][v], e), xv[k][v][e], t);
-        t = wave_sum_dpp(t);
-        if ((lt & 63) == 0) red[buf][w][i * K + k] = t;
+        dots[i * K + k] = t;
       }
+    if constexpr (R * K >= 4 && (R * K & (R * K - 1)) == 0) {
+      wave_sums_t<R * K>(dots);
+      if ((lt & 15) == 0) {
+#pragma unroll
+        for (int u = 0; u < R * K / 4; ++u)
+          red[buf][w][((lt & 63) >> 4) * (R * K / 4) + u] = dots[u];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < R * K; ++q) {
+        const float t = wave_sum_dpp(dots[q]);
+        if ((lt & 63) == 0) red[buf][w][q] = t;
+      }
+    }
     __syncthreads();
     // lane q < R K of each wave adds the NW wave partials of dot q in wave order;
     // readlane hands the sums to the whole wave
@@ -479,6 +529,7 @@ __global__ __launch_bounds__(512) void k_grad_wide_two(
           for (int i = 0; i < R; ++i) set(a[i][v], e, ok ? get(a[i][v], e) : 0.0f);
         }
     }
+    float dots[R * K];  // dot i * K + k
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       float4 xk[NV];
@@ -491,9 +542,13 @@ __global__ __launch_bounds__(512) void k_grad_wide_two(
         for (int v = 0; v < NV; ++v)
 #pragma unroll
           for (int e = 0; e < 4; ++e) t = fmaf(get(a[i][v], e), get(xk[v], e), t);
-        t = wave_sum_dpp(t);
-        if ((lt & 63) == 0) red[buf][w][i * K + k] = t;
+        dots[i * K + k] = t;
       }
+    }
+    wave_sums_t<R * K>(dots);
+    if ((lt & 15) == 0) {
+#pragma unroll
+      for (int u = 0; u < R * K / 4; ++u) red[buf][w][((lt & 63) >> 4) * (R * K / 4) + u] = dots[u];
     }
     __syncthreads();
     // lane q < R K of each wave adds the NW wave partials of dot q (in wave order,
