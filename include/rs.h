@@ -362,7 +362,13 @@ typedef struct rs_problem {
  * finished, so small solves run concurrently and fill the device.  The worker
  * streams wait for work already queued on `stream`, and `stream` waits for all of
  * them on return.  Workers past the first run on host threads that the library
- * starts on first use and keeps until the process ends.  infos: count host records.  Synchronizes.  Returns RS_OK when
+ * starts on first use and keeps until the process ends.  Jobs on the same FP32 A
+ * and b (the same pointers, shape and lda; e.g. several nu of one data set) run as
+ * pairs when the k = 2 gradient plan of (n, d) is on the 512-thread kernel: one host
+ * thread drives both on two worker streams, each step the two jobs have in common
+ * takes one gradient pass for both (rs_gradient_two), a learned start forms the
+ * features' pass over A once, and the two first sketches come from one transform;
+ * the results are those of the jobs alone, bit for bit.  infos: count host records.  Synchronizes.  Returns RS_OK when
  * every job ended RS_OK or RS_ERR_NO_CONVERGENCE (see infos[i].status), else the
  * first other error; an argument error in any problem is reported before any
  * work is queued. */

@@ -789,7 +789,10 @@ __global__ __launch_bounds__(256) void k_p2_dest(const int32_t* __restrict__ qli
 
 // DUAL: a second, smaller sketch of the same seed and sketch_id (its rows are a
 // subset of this one's) written from the same transformed rows: destination rows
-// dest2b (-1: not in it), its own output, leading dimension and scale.
+// dest2b (q-major like dest2, -1: not in it), its own output, leading dimension and
+// scale.  Both outputs then take their two columns with one store (the host checks
+// that each output is aligned for it and has a padding column when d is odd), which
+// keeps the kernel's code inside the instruction cache.
 struct P2Dual {
   const int32_t* dest2b;
   void* out;
@@ -797,7 +800,10 @@ struct P2Dual {
   float scale;
 };
 
-template <typename OutT, bool EDGE, bool DUAL>
+// PST: every output row takes its two columns with one store (the host has checked
+// alignment and the padding column); otherwise a row's columns are stored by the
+// general path (vector or single stores as alignment and d allow).  DUAL implies PST.
+template <typename OutT, bool EDGE, bool DUAL, bool PST>
 __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, int64_t Qmax,
                                                  int lb1, int64_t n2, int64_t d,
                                                  const int32_t* __restrict__ dest2,
@@ -809,7 +815,6 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
   constexpr int J = kP2J;
   __shared__ float2 lds[RT * 4];
   __shared__ int32_t dest[RT];
-  __shared__ int32_t destb[DUAL ? RT : 1];
   const int64_t slot = blockIdx.x >> 3;
   const int64_t item = (slot >> 1) * 8 + (blockIdx.x & 7);
   if (item >= np32 * ntile) return;  // uniform: the grid is rounded up to 16 blocks
@@ -858,18 +863,7 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
     const int r = t + 256 * u;
     dest[r] = r < valid ? dv[u] : -1;
   }
-  if constexpr (DUAL) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = t + 256 * u;
-      dv[u] = du.dest2b[q0 * n1 + (r < valid ? r : 0)];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = t + 256 * u;
-      destb[r] = r < valid ? dv[u] : -1;
-    }
-  }
+
   reg_fwht2<J, 6>(v, 5, lb1);
   for (int h = 0; h < 2; ++h) {
     if (half == h) {
@@ -911,13 +905,57 @@ __global__ __launch_bounds__(256) void k_srht_p2(const float* __restrict__ Z, in
       }
     }
   };
+  static_assert(PST || !DUAL, "the dual pass stores paired columns");
+  // one store for both columns (alignment and padding checked by the host)
+  auto put2 = [&](OutT* base, int64_t ld, int64_t k, float sc, float2 val) {
+    OutT* o = base + k * ld + col;
+    const float a = val.x * sc, b = val.y * sc;
+    if constexpr (sizeof(OutT) == 2)
+      *reinterpret_cast<uint32_t*>(o) =
+          (uint32_t)f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
+    else
+      *reinterpret_cast<float2*>(o) = make_float2(a, b);
+  };
+  if constexpr (!PST) {
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int32_t k = dest[64 * g + j];
-    if (k >= 0) put(out, ldo, k, scale, v[j]);
-    if constexpr (DUAL) {
-      const int32_t k2 = destb[64 * g + j];
-      if (k2 >= 0) put(reinterpret_cast<OutT*>(du.out), du.ldo, k2, du.scale, v[j]);
+    for (int j = 0; j < J; ++j) {
+      const int32_t k = dest[64 * g + j];
+      if (k >= 0) put(out, ldo, k, scale, v[j]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int32_t k = dest[64 * g + j];
+      if (k >= 0) put2(out, ldo, k, scale, v[j]);
+    }
+  }
+  if constexpr (DUAL) {
+    // the second sketch's rows: destinations read from global memory (the 8 lanes
+    // of a row group share each address), no LDS of their own, 16 at a time with
+    // 16-byte loads so that one wait covers them (a full tile's 2048 rows lie inside
+    // dest2b's Qmax n1 entries; the edge tile reads only rows below valid)
+    const int32_t* db = du.dest2b + q0 * n1 + 64 * g;
+#pragma unroll
+    for (int j0 = 0; j0 < J; j0 += 16) {
+      int32_t kb[16];
+      if constexpr (!EDGE) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int4 w4 = *reinterpret_cast<const int4*>(db + j0 + 4 * h);
+          kb[4 * h] = w4.x;
+          kb[4 * h + 1] = w4.y;
+          kb[4 * h + 2] = w4.z;
+          kb[4 * h + 3] = w4.w;
+        }
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) kb[jj] = 64 * g + j0 + jj < valid ? db[j0 + jj] : -1;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int32_t k2 = 64 * g + j0 + jj < valid ? kb[jj] : -1;
+        if (k2 >= 0) put2(reinterpret_cast<OutT*>(du.out), du.ldo, k2, du.scale, v[j0 + jj]);
+      }
     }
   }
 }
@@ -981,6 +1019,14 @@ bool srht_panel_path(int64_t npad, int64_t lda) {
   return n1 > 1 && n1 <= kP2Rows && lda < ((int64_t)1 << 19);
 }
 
+// Whether pass 2 may store each row's two columns (col, col + 1; col even) with one
+// store into SA: a base aligned to two elements, an even leading dimension, and a
+// padding column to take the write past d when d is odd.
+static bool pair_store_ok(const void* SA, int64_t ldsa, int64_t d, int es) {
+  return (reinterpret_cast<uintptr_t>(SA) % (uintptr_t)(2 * es)) == 0 && ldsa % 2 == 0 &&
+         (d % 2 == 0 || ldsa > d);
+}
+
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
@@ -990,6 +1036,12 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
     return set_error(RS_ERR_ARG, "srht: the probe sums ride on the panel-major path only");
   if (dual && !(sizeof(T) == 4 && srht_panel_path(npad, lda)))
     return set_error(RS_ERR_ARG, "srht: a second output rides on the panel-major path only");
+  if (dual) {
+    // the dual pass stores two columns at once in both outputs
+    const int es = sa_t == RS_BF16 ? 2 : 4;
+    if (!pair_store_ok(SA, ldsa, d, es) || !pair_store_ok(dual->SA2, dual->ldsa2, d, es))
+      return set_error(RS_ERR_ARG, "srht: a second output needs paired-column stores");
+  }
   using TT = Tile<T>;
   const int64_t n2 = npad < TT::RT ? npad : TT::RT;
   const int64_t n1 = npad / n2;
@@ -1065,25 +1117,30 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       auto p2_grid = [&](int64_t ntile) {
         return dim3((unsigned)((P * ntile + 7) / 8 * 16));
       };
-      auto p2 = [&](auto out_tag, auto dual_tag) {
+      auto p2 = [&](auto out_tag, auto dual_tag, auto pst_tag) {
         using OutT = decltype(out_tag);
-        constexpr bool DU = decltype(dual_tag)::value;
+        constexpr bool DU = decltype(dual_tag)::value, PS = decltype(pst_tag)::value;
         OutT* o = reinterpret_cast<OutT*>(SA);
         if (t2full > 0)
-          hipLaunchKernelGGL((k_srht_p2<OutT, false, DU>), p2_grid(t2full), dim3(256), 0, s, Z,
-                             Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale,
+          hipLaunchKernelGGL((k_srht_p2<OutT, false, DU, PS>), p2_grid(t2full), dim3(256), 0, s,
+                             Z, Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale,
                              (int64_t)0, P, t2full, du);
         if (t2 > t2full)
-          hipLaunchKernelGGL((k_srht_p2<OutT, true, DU>), p2_grid(1), dim3(256), 0, s, Z, Qmax,
-                             lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full, P,
-                             (int64_t)1, du);
+          hipLaunchKernelGGL((k_srht_p2<OutT, true, DU, PS>), p2_grid(1), dim3(256), 0, s, Z,
+                             Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full,
+                             P, (int64_t)1, du);
       };
+      using F_ = std::false_type;
+      using T_ = std::true_type;
+      const bool pst = pair_store_ok(SA, ldsa, d, bf16 ? 2 : 4);
       if (bf16) {
-        if (dual) p2(uint16_t{}, std::true_type{});
-        else p2(uint16_t{}, std::false_type{});
+        if (dual) p2(uint16_t{}, T_{}, T_{});
+        else if (pst) p2(uint16_t{}, F_{}, T_{});
+        else p2(uint16_t{}, F_{}, F_{});
       } else {
-        if (dual) p2(float{}, std::true_type{});
-        else p2(float{}, std::false_type{});
+        if (dual) p2(float{}, T_{}, T_{});
+        else if (pst) p2(float{}, F_{}, T_{});
+        else p2(float{}, F_{}, F_{});
       }
       return check_launch("srht two pass");
     }
