@@ -708,7 +708,7 @@ def run_c5(args):
     srht = {}
     for nu2, _, info in results[:len(C5_NU2S)]:
         m = int(info.get("m_init", info["m_final"]))
-        sdt = "bf16" if main_mode == "learned" else "f32"
+        sdt = "bf16" if main_mode in ("learned", "batched") else "f32"
         rs.rs_sketch_srht(A, m, sa_dtype=sdt)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
