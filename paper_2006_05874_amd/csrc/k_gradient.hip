@@ -21,6 +21,78 @@
 
 namespace rs {
 
+// wave_sum's butterfly (xor 32, 16, 8, 4, 2, 1, in that order) with the four
+// in-row stages as DPP moves instead of LDS permutes.  xor 8 is row_ror:8 and xor
+// 2, xor 1 are quad permutes (the same partners); row_ror:4 takes lane p +- 4 in
+// place of p ^ 4, and after the xor-8 stage lanes 8 apart hold the same bits, so
+// the operands, and every lane's result, are wave_sum's bit for bit.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += __shfl_xor(v, 32, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
+                                                              0xF, 0xF, false));  // row_ror:8
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
+                                                              0xF, 0xF, false));  // row_ror:4
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E,
+                                                              0xF, 0xF, false));  // [2,3,0,1]
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1,
+                                                              0xF, 0xF, false));  // [1,0,3,2]
+  return v;
+}
+
+// S wave sums at once (S a power of two, at least 4) with wave_sum's pairings: the
+// xor-32 and xor-16 stages are transposed (a lane keeps half of its values and hands
+// the other half to its partner, which keeps the mirror half), so they take S/2 + S/4
+// permutes instead of 2 S; the in-row stages then run on the S/4 values left, as in
+// wave_sum_dpp.  Every sum adds the same lane pairs in the same order as wave_sum,
+// so its bits are wave_sum's.  On return v[u] (u < S/4) of lane L holds the sum of
+// value (L >> 4) * (S/4) + u, the same bits in all 16 lanes of L's row.
+template <int S>
+__device__ __forceinline__ void wave_sums_t(float (&v)[S]) {
+  static_assert(S >= 4 && (S & (S - 1)) == 0, "S: a power of two >= 4");
+  const int lane = threadIdx.x & 63;
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
+  float a[S / 2];
+#pragma unroll
+  for (int u = 0; u < S / 2; ++u) {
+    const float send = h5 ? v[u] : v[u + S / 2];
+    const float keep = h5 ? v[u + S / 2] : v[u];
+    a[u] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int u = 0; u < S / 4; ++u) {
+    const float send = h4 ? a[u] : a[u + S / 4];
+    const float keep = h4 ? a[u + S / 4] : a[u];
+    float c = keep + __shfl_xor(send, 16, 64);
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0x128, 0xF, 0xF, false));
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0x124, 0xF, 0xF, false));
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0x4E, 0xF, 0xF, false));
+    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
+                                                                0xB1, 0xF, 0xF, false));
+    v[u] = c;
+  }
+}
+
+// group_sum<W> (W = 16 or 32) with its in-row stages as DPP moves, as in
+// wave_sum_dpp: the same lane pairs, the same bits in every lane of the group.
+template <int W>
+__device__ __forceinline__ float group_sum_dpp(float v) {
+  static_assert(W == 16 || W == 32, "W: 16 or 32");
+  if constexpr (W == 32) v += __shfl_xor(v, 16, 64);
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
+                                                              0xF, 0xF, false));  // row_ror:8
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
+                                                              0xF, 0xF, false));  // row_ror:4
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E,
+                                                              0xF, 0xF, false));  // [2,3,0,1]
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1,
+                                                              0xF, 0xF, false));  // [1,0,3,2]
+  return v;
+}
+
 template <typename T, int TPR, int NV, int K, int R>
 __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, int64_t n, int64_t d,
                                                       int64_t lda, const T* __restrict__ b,
@@ -113,22 +185,69 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
           for (int e = 0; e < VEC; ++e) t = fma(get(a[i][v], e), xv[k][v][e], t);
         s[i][k] = t;
       }
-    // reduce the row dots over the TPR threads of the group
+    // reduce the row dots over the TPR threads of the group.  FP32: DPP for the
+    // in-row stages, and where the R K dots of a wave form a power of two of at
+    // least 4 they are reduced together (wave_sums_t); the lane pairs are those of
+    // group_sum / wave_sum, so the bits are too
+    constexpr int S = R * K;
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    // (k <= 2: with four right-hand sides the wider shapes have no registers to spare)
+    constexpr bool kTrans = kF32 && K <= 2 && S >= 4 && (S & (S - 1)) == 0;
     if constexpr (TPR <= 64) {
+      if constexpr (kF32 && TPR == 64 && kTrans) {
+        float dots[S];
 #pragma unroll
-      for (int i = 0; i < R; ++i)
+        for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int k = 0; k < K; ++k) s[i][k] = group_sum<TPR>(s[i][k]);
+          for (int k = 0; k < K; ++k) dots[i * K + k] = s[i][k];
+        wave_sums_t<S>(dots);
+        // lane 16 h holds dots h S/4 .. h S/4 + S/4 - 1: every lane takes all of them
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+          s[q / K][q % K] = __builtin_bit_cast(
+              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dots[q % (S / 4)]),
+                                               (q / (S / 4)) * 16));
+      } else if constexpr (kF32 && TPR == 64) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int k = 0; k < K; ++k) s[i][k] = wave_sum_dpp(s[i][k]);
+      } else if constexpr (kF32 && (TPR == 16 || TPR == 32)) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int k = 0; k < K; ++k) s[i][k] = group_sum_dpp<TPR>(s[i][k]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int k = 0; k < K; ++k) s[i][k] = group_sum<TPR>(s[i][k]);
+      }
     } else {
       const int w = lt / 64;
       const int buf = it & 1;
+      if constexpr (kTrans) {
+        float dots[S];
 #pragma unroll
-      for (int i = 0; i < R; ++i)
+        for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          T t = wave_sum(s[i][k]);
-          if ((lt & 63) == 0) red_dot[buf][grp][w][i * K + k] = t;
+          for (int k = 0; k < K; ++k) dots[i * K + k] = s[i][k];
+        wave_sums_t<S>(dots);
+        if ((lt & 15) == 0) {
+#pragma unroll
+          for (int u = 0; u < S / 4; ++u) red_dot[buf][grp][w][((lt & 63) >> 4) * (S / 4) + u] = dots[u];
         }
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            T t;
+            if constexpr (kF32) t = wave_sum_dpp(s[i][k]);
+            else t = wave_sum(s[i][k]);
+            if ((lt & 63) == 0) red_dot[buf][grp][w][i * K + k] = t;
+          }
+      }
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < R; ++i)
@@ -207,61 +326,6 @@ __global__ __launch_bounds__(256) void k_grad_partial(const T* __restrict__ A, i
           }
       }
     }
-  }
-}
-
-// wave_sum's butterfly (xor 32, 16, 8, 4, 2, 1, in that order) with the four
-// in-row stages as DPP moves instead of LDS permutes.  xor 8 is row_ror:8 and xor
-// 2, xor 1 are quad permutes (the same partners); row_ror:4 takes lane p +- 4 in
-// place of p ^ 4, and after the xor-8 stage lanes 8 apart hold the same bits, so
-// the operands, and every lane's result, are wave_sum's bit for bit.
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-  v += __shfl_xor(v, 32, 64);
-  v += __shfl_xor(v, 16, 64);
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
-                                                              0xF, 0xF, false));  // row_ror:8
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
-                                                              0xF, 0xF, false));  // row_ror:4
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E,
-                                                              0xF, 0xF, false));  // [2,3,0,1]
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1,
-                                                              0xF, 0xF, false));  // [1,0,3,2]
-  return v;
-}
-
-// S wave sums at once (S a power of two, at least 4) with wave_sum's pairings: the
-// xor-32 and xor-16 stages are transposed (a lane keeps half of its values and hands
-// the other half to its partner, which keeps the mirror half), so they take S/2 + S/4
-// permutes instead of 2 S; the in-row stages then run on the S/4 values left, as in
-// wave_sum_dpp.  Every sum adds the same lane pairs in the same order as wave_sum,
-// so its bits are wave_sum's.  On return v[u] (u < S/4) of lane L holds the sum of
-// value (L >> 4) * (S/4) + u, the same bits in all 16 lanes of L's row.
-template <int S>
-__device__ __forceinline__ void wave_sums_t(float (&v)[S]) {
-  static_assert(S >= 4 && (S & (S - 1)) == 0, "S: a power of two >= 4");
-  const int lane = threadIdx.x & 63;
-  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
-  float a[S / 2];
-#pragma unroll
-  for (int u = 0; u < S / 2; ++u) {
-    const float send = h5 ? v[u] : v[u + S / 2];
-    const float keep = h5 ? v[u + S / 2] : v[u];
-    a[u] = keep + __shfl_xor(send, 32, 64);
-  }
-#pragma unroll
-  for (int u = 0; u < S / 4; ++u) {
-    const float send = h4 ? a[u] : a[u + S / 4];
-    const float keep = h4 ? a[u + S / 4] : a[u];
-    float c = keep + __shfl_xor(send, 16, 64);
-    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
-                                                                0x128, 0xF, 0xF, false));
-    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
-                                                                0x124, 0xF, 0xF, false));
-    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
-                                                                0x4E, 0xF, 0xF, false));
-    c += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, c),
-                                                                0xB1, 0xF, 0xF, false));
-    v[u] = c;
   }
 }
 
