@@ -995,6 +995,53 @@ rs_status srht_select(const SrhtBuffers& B, uint64_t seed, uint32_t sid, int64_t
   return check_launch("srht select");
 }
 
+// The signs of (seed, sid) alone (k_keys_hist writes them with the histogram,
+// which must then be consumed by a selection).
+__global__ __launch_bounds__(256) void k_signs(uint64_t seed, uint32_t sid, int64_t npad,
+                                               int8_t* __restrict__ signs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad;
+       i += (int64_t)gridDim.x * blockDim.x)
+    signs[i] = (int8_t)sign_of(seed, sid, (uint64_t)i);
+}
+
+// Every low index kept, in order: qmap = qlist = identity over n2, qcount = n2.
+__global__ __launch_bounds__(1024) void k_iota_q(int32_t* __restrict__ qmap,
+                                                 int32_t* __restrict__ qlist,
+                                                 int32_t* __restrict__ qcount, int n2) {
+  const int i = threadIdx.x;
+  if (i < n2) {
+    qmap[i] = i;
+    qlist[i] = i;
+  }
+  if (i == 0) *qcount = n2;
+}
+
+rs_status srht_pass1_full(const SrhtBuffers& B, const float* A, int64_t n, int64_t d, int64_t lda,
+                          int64_t npad, uint64_t seed, uint32_t sid, hipStream_t s) {
+  if (!srht_panel_path(npad, lda))
+    return set_error(RS_ERR_ARG, "srht: the full first pass runs on the panel-major path only");
+  const int64_t n2 = npad < 1024 ? npad : 1024;
+  const int64_t n1 = npad / n2;
+  int lb2 = 0;
+  while (((int64_t)1 << lb2) < n2) ++lb2;
+  const int hist_grid = (int)std::min<int64_t>((npad + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_signs, dim3(hist_grid), dim3(256), 0, s, seed, sid, npad, B.signs);
+  hipLaunchKernelGGL(k_iota_q, dim3(1), dim3(1024), 0, s, B.qmap, B.qlist, B.qcount, (int)n2);
+  const int64_t P = (d + 31) / 32;
+  const int64_t full = n2 == 1024 ? std::min<int64_t>(n / 1024, n1) : 0;
+  const ProbeArgs pa{nullptr, nullptr, nullptr, 0};
+  float* Zw = reinterpret_cast<float*>(B.zbuf);
+  if (full > 0)
+    hipLaunchKernelGGL((k_srht_p1<false, false>), dim3((unsigned)(P * full)), dim3(256), 0, s, A,
+                       n, d, lda, B.signs, lb2, n2, n1, n2, B.qmap, Zw, (int64_t)0, full, P,
+                       kP1GroupWrite, pa);
+  if (full < n1)
+    hipLaunchKernelGGL((k_srht_p1<true, false>), dim3((unsigned)(P * (n1 - full))), dim3(256), 0,
+                       s, A, n, d, lda, B.signs, lb2, n2, n1, n2, B.qmap, Zw, full, n1 - full, P,
+                       kP1GroupWrite, pa);
+  return check_launch("srht full first pass");
+}
+
 size_t srht_state_bytes() { return sizeof(SelectState); }
 int srht_cand_cap() { return kCandCap; }
 int srht_compact_block() { return kCompactBlock; }
@@ -1031,7 +1078,9 @@ template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
                          int64_t Qmax, hipStream_t s, double scale_override,
-                         const ProbeArgs* probe, const SrhtDual* dual) {
+                         const ProbeArgs* probe, const SrhtDual* dual, const SrhtPre* pre) {
+  if (pre && (sizeof(T) != 4 || !srht_panel_path(npad, lda) || probe))
+    return set_error(RS_ERR_ARG, "srht: a done first pass rides on the panel-major path only");
   if (probe && (sizeof(T) != 4 || !srht_panel_path(npad, lda)))
     return set_error(RS_ERR_ARG, "srht: the probe sums ride on the panel-major path only");
   if (dual && !(sizeof(T) == 4 && srht_panel_path(npad, lda)))
@@ -1077,7 +1126,13 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
     // floats below 2^31 bytes); its intermediate is never smaller than the old
     // layout's, so wider rows fall back to that form in the same buffer
     if (n1 <= kP2Rows && lda < ((int64_t)1 << 19)) {
-      float* Zw = reinterpret_cast<float*>(B.zbuf);
+      // pre: pass 1 already ran with every low index kept (srht_pass1_full): its
+      // intermediate, q = i2 over all n2 low indices
+      // (pass 1 writes Zw only without pre; with it pass 2 only reads)
+      float* Zw = reinterpret_cast<float*>(pre ? const_cast<void*>(pre->Z) : B.zbuf);
+      const int64_t QM = pre ? n2 : Qmax;
+      const int32_t* ql = pre ? pre->qlist : B.qlist;
+      const int32_t* qc = pre ? pre->qcount : B.qcount;
       const float* Af = reinterpret_cast<const float*>(A);
       // full tiles (all 1024 rows below n), then the rest row-clamped
       const int64_t full = n2 == 1024 ? std::min<int64_t>(n / 1024, n1) : 0;
@@ -1092,25 +1147,25 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       };
       using F_ = std::false_type;
       using T_ = std::true_type;
-      if (full > 0) {
+      if (full > 0 && !pre) {
         if (probe) p1(F_{}, T_{}, (int64_t)0, full);
         else p1(F_{}, F_{}, (int64_t)0, full);
       }
-      if (full < n1) {
+      if (full < n1 && !pre) {
         if (probe) p1(T_{}, T_{}, full, n1 - full);
         else p1(T_{}, F_{}, full, n1 - full);
       }
-      hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((Qmax * n1 + 255) / 256)), dim3(256), 0, s,
-                         B.qlist, B.kmap, B.qcount, Qmax, n1, n2, B.dest2);
+      hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((QM * n1 + 255) / 256)), dim3(256), 0, s,
+                         ql, B.kmap, qc, QM, n1, n2, B.dest2);
       // the second sketch's rows among this one's transformed rows (its low indices
       // are among this selection's, so this Z holds them all)
       if (dual)
-        hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((Qmax * n1 + 255) / 256)), dim3(256), 0,
-                           s, B.qlist, dual->kmap2, B.qcount, Qmax, n1, n2, dual->dest2b);
+        hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((QM * n1 + 255) / 256)), dim3(256), 0,
+                           s, ql, dual->kmap2, qc, QM, n1, n2, dual->dest2b);
       const P2Dual du = dual ? P2Dual{dual->dest2b, dual->SA2, dual->ldsa2, (float)dual->scale2}
                              : P2Dual{nullptr, nullptr, 0, 0.0f};
-      const int64_t t2 = (Qmax * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
-      const int64_t t2full = Qmax * n1 / kP2Rows;
+      const int64_t t2 = (QM * n1 + kP2Rows - 1) / kP2Rows;  // tiles of 2048 rows
+      const int64_t t2full = QM * n1 / kP2Rows;
       const float* Z = Zw;
       // two blocks (the halves of a 32-column panel) per work item, 16 blocks per
       // 8 work items (see k_srht_p2)
@@ -1123,11 +1178,11 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
         OutT* o = reinterpret_cast<OutT*>(SA);
         if (t2full > 0)
           hipLaunchKernelGGL((k_srht_p2<OutT, false, DU, PS>), p2_grid(t2full), dim3(256), 0, s,
-                             Z, Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale,
+                             Z, QM, lb1, n2, d, B.dest2, qc, o, ldsa, (float)scale,
                              (int64_t)0, P, t2full, du);
         if (t2 > t2full)
           hipLaunchKernelGGL((k_srht_p2<OutT, true, DU, PS>), p2_grid(1), dim3(256), 0, s, Z,
-                             Qmax, lb1, n2, d, B.dest2, B.qcount, o, ldsa, (float)scale, t2full,
+                             QM, lb1, n2, d, B.dest2, qc, o, ldsa, (float)scale, t2full,
                              P, (int64_t)1, du);
       };
       using F_ = std::false_type;
@@ -1165,11 +1220,11 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
 template rs_status srht_transform<float>(const SrhtBuffers&, const float*, int64_t, int64_t,
                                          int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
                                          int64_t, hipStream_t, double, const ProbeArgs*,
-                                         const SrhtDual*);
+                                         const SrhtDual*, const SrhtPre*);
 template rs_status srht_transform<double>(const SrhtBuffers&, const double*, int64_t, int64_t,
                                           int64_t, int64_t, int64_t, void*, rs_dtype, int64_t,
                                           int64_t, hipStream_t, double, const ProbeArgs*,
-                                          const SrhtDual*);
+                                          const SrhtDual*, const SrhtPre*);
 
 // ---------------------------------------------------------------- nested gather
 // SA[k] = scale * HDA[rows[k]] for the cached transform of the whole padded A

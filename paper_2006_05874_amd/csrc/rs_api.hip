@@ -188,6 +188,9 @@ struct DeviceScratch {
   // a second, smaller sketch formed by the same transform (srht_run's dual output):
   // its own selection's row map and low-index lists, and its pass-2 destinations
   DevBuf kmap2, qmap2, qlist2, qcount2, rows2, dest2b;
+  // identity low-index lists of a full first pass run ahead of its selection
+  // (srht_pretransform): qmap, qlist (1024 each) and the count
+  DevBuf qid;
   // gradient partials, vectors, control
   DevBuf partial, vecs, rpart, ctl, ev, info, rvec;
   // solver-owned sketch and factor (wbuf: scratch of the Woodbury-form apply)
@@ -380,6 +383,7 @@ struct SrhtSecond {
   int64_t m2;
   void* SA2;
   int64_t ldsa2;
+  const SrhtPre* pre = nullptr;  // pass 1 already run with every low index kept
 };
 
 // Whether srht_run can carry a SrhtSecond for this problem and sketch dtype.
@@ -416,7 +420,7 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
     RS_TRY(S.qlist2.ensure(1024 * sizeof(int32_t)));
     RS_TRY(S.qcount2.ensure(sizeof(int32_t)));
     RS_TRY(S.rows2.ensure((size_t)second->m2 * sizeof(int64_t)));
-    RS_TRY(S.dest2b.ensure((size_t)Qmax * (npad / n2) * sizeof(int32_t)));
+    RS_TRY(S.dest2b.ensure((size_t)(second->pre ? n2 : Qmax) * (npad / n2) * sizeof(int32_t)));
     SrhtBuffers B2 = B;
     B2.kmap = S.kmap2.as<int32_t>();
     B2.qmap = S.qmap2.as<int32_t>();
@@ -436,11 +440,34 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
                         reinterpret_cast<uint8_t*>(SA), ldsa, s));
   } else if (a_t == RS_F32)
     RS_TRY(srht_transform<float>(B, reinterpret_cast<const float*>(A), n, d, lda, npad, m, SA, sa_t,
-                                 ldsa, Qmax, s, 0.0, probe, second ? &dual : nullptr));
+                                 ldsa, Qmax, s, 0.0, probe, second ? &dual : nullptr,
+                                 second ? second->pre : nullptr));
   else
     RS_TRY(srht_transform<double>(B, reinterpret_cast<const double*>(A), n, d, lda, npad, m, SA,
                                   sa_t, ldsa, Qmax, s));
   if (signs_out) RS_HIP(hipMemcpyAsync(signs_out, B.signs, (size_t)npad, hipMemcpyDeviceToDevice, s));
+  return RS_OK;
+}
+
+// Pass 1 of the SRHT of (seed, sid) with every low index kept, ahead of any
+// selection, into S's intermediate; *pre then describes it for srht_run (a pair's
+// first sketches: the pass needs only A and the signs, so it can run beside the
+// learned features' pass over A).
+static rs_status srht_pretransform(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
+                                   int64_t d, int64_t lda, uint64_t seed, uint32_t sid,
+                                   hipStream_t s, SrhtPre* pre) {
+  const int64_t npad = next_pow2(n);
+  const int64_t n2 = std::min<int64_t>(npad, 1024);
+  if (a_t != RS_F32 || !srht_panel_path(npad, lda))
+    return set_error(RS_ERR_ARG, "srht: no full first pass for this shape");
+  SrhtBuffers B;
+  RS_TRY(ensure_srht(S, npad, (int64_t)srht_zbuf_bytes(a_t, npad, d, n2), B, s));
+  RS_TRY(S.qid.ensure((2 * 1024 + 1) * sizeof(int32_t)));
+  B.qmap = S.qid.as<int32_t>();
+  B.qlist = B.qmap + 1024;
+  B.qcount = B.qmap + 2048;
+  RS_TRY(srht_pass1_full(B, reinterpret_cast<const float*>(A), n, d, lda, npad, seed, sid, s));
+  *pre = SrhtPre{S.zbuf.p, B.qlist, B.qcount};
   return RS_OK;
 }
 
@@ -1199,6 +1226,7 @@ struct SolveJob {
   // its stream waits for sa_wait) and it only factors
   SolveJob* sa_for = nullptr;
   int64_t sa_m2 = 0;
+  const SrhtPre* sa_pre = nullptr;  // its first pass, already run (or null)
   hipEvent_t sa_done = nullptr;
   bool sa_given = false;
   hipEvent_t sa_wait = nullptr;
@@ -1351,11 +1379,12 @@ struct SolveJob {
     } else if (reuse)
       ;  // SA (and its FP8 column scales) already hold this sketch
     else if (sa_for) {
-      const SrhtSecond sec{sa_m2, sa_for->S->sa.p, sa_for->ldsa};
+      const SrhtSecond sec{sa_m2, sa_for->S->sa.p, sa_for->ldsa, sa_pre};
       RS_TRY(srht_run(*S, A, a_t, n, d, lda, mm, o.seed, id, S->sa.p, sa_t, ldsa, scl, nullptr,
                       nullptr, stream, nullptr, &sec));
       RS_HIP(hipEventRecord(sa_done, stream));
       sa_for = nullptr;
+      sa_pre = nullptr;
     } else if (sp)  // nested: the same hash at 2m splits every bucket in two
       RS_TRY(count_sketch_run(S->spw, *sp, mm, o.seed, id, S->sa.p, sa_t, ldsa, stream));
     else if (o.resample == RS_RESAMPLE_NESTED)
@@ -1881,6 +1910,16 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
   // of nu) from job 0's scratch and finishes them at its own nu
   const bool share_head = J[0]->lp_params && J[1]->lp_params && !J[0]->sp && !J[1]->sp &&
                           J[0]->o.seed == J[1]->o.seed;
+  // and the first sketches' pass 1 (sketch_id 0, every low index kept) runs on job 1's
+  // stream beside job 0's features pass: it needs only A and the signs
+  const bool pre_first = share_head && J[0]->srht && J[0]->o.resample == RS_RESAMPLE_FRESH &&
+                         J[0]->sid == J[1]->sid && J[0]->sa_t == J[1]->sa_t &&
+                         srht_second_ok(J[0]->a_t, J[0]->n, J[0]->lda, J[0]->sa_t);
+  SrhtPre pre{};
+  bool pre_ok = false;
+  if (pre_first)
+    pre_ok = srht_pretransform(*J[1]->S, J[1]->A, J[1]->a_t, J[1]->n, J[1]->d, J[1]->lda,
+                               J[1]->o.seed, J[1]->sid, J[1]->stream, &pre) == RS_OK;
   for (int k = 0; k < 2; ++k) {
     J[k]->defer = true;
     if (k == 1 && share_head && !J[0]->done) {
@@ -1951,6 +1990,9 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
       if (J[c]->S->sa.ensure((size_t)mk[c] * J[c]->ldsa * J[c]->sa_es) == RS_OK) {
         J[p]->sa_for = J[c];
         J[p]->sa_m2 = mk[c];
+        // the full first pass ran on job 1's stream, which the host has seen finish
+        // (its prediction came after it)
+        J[p]->sa_pre = pre_ok ? &pre : nullptr;
         J[p]->sa_done = ev[p];
         J[c]->sa_given = true;
         J[c]->sa_wait = ev[p];
@@ -1967,6 +2009,7 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
       if (k == prod && J[k]->sa_for) {
         // the transform was not queued: the partner forms its own sketch
         J[k]->sa_for = nullptr;
+        J[k]->sa_pre = nullptr;
         J[1 - k]->sa_given = false;
       }
     }

@@ -83,11 +83,26 @@ struct SrhtDual {
   int64_t ldsa2;
   double scale2;
 };
+// Pass 1 already run with every low index kept (srht_pass1_full, same seed and
+// sketch_id): its intermediate Z (Qmax = n2, q = i2) and the identity list and count
+// it was run with.  The transform then runs the selection's pass 2 only, over every
+// low index (rows outside the selection are not stored).
+struct SrhtPre {
+  const void* Z;
+  const int32_t* qlist;
+  const int32_t* qcount;
+};
 template <typename T>
 rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d, int64_t lda,
                          int64_t npad, int64_t m, void* SA, rs_dtype sa_t, int64_t ldsa,
                          int64_t Qmax, hipStream_t s, double scale_override = 0.0,
-                         const ProbeArgs* probe = nullptr, const SrhtDual* dual = nullptr);
+                         const ProbeArgs* probe = nullptr, const SrhtDual* dual = nullptr,
+                         const SrhtPre* pre = nullptr);
+// Pass 1 of the SRHT of (seed, sid) with every low index kept, before any selection:
+// writes B.signs, an identity B.qmap / B.qlist / B.qcount and the full intermediate
+// in B.zbuf (srht_zbuf_bytes with Qmax = n2).  FP32 A on the panel-major path.
+rs_status srht_pass1_full(const SrhtBuffers& B, const float* A, int64_t n, int64_t d, int64_t lda,
+                          int64_t npad, uint64_t seed, uint32_t sid, hipStream_t s);
 rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* rows, int64_t m,
                       int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
                       hipStream_t s);
