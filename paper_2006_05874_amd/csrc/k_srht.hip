@@ -589,31 +589,23 @@ __device__ __forceinline__ void p1_work(int64_t L, int64_t panels, int64_t ntile
   panel = first + u % gw;
 }
 
-// PROBE: also the learned start's column sums of this tile (ProbeArgs), taken from
-// the loaded rows before the sign flip, reduced over the block's 32 row groups in
-// the (still unused) transpose buffer.
-template <bool EDGE, bool PROBE>
-__global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, int64_t n,
-                                                 int64_t d, int64_t lda,
-                                                 const int8_t* __restrict__ signs, int lb,
-                                                 int64_t n2, int64_t n1, int64_t Qmax,
-                                                 const int32_t* __restrict__ qmap,
-                                                 float* __restrict__ Z, int64_t tile0,
-                                                 int64_t ntiles, int64_t panels, int pgroup,
-                                                 ProbeArgs pa) {
+// One work item (32-column panel, tile) of the first pass, in LDS buffers the caller
+// owns.  PROBE: also the learned start's column sums of this tile (ProbeArgs), taken
+// from the loaded rows before the sign flip, reduced over the block's 32 row groups
+// in the (still unused) transpose buffer.  IDQ: every low index kept in order (q = r,
+// Qmax = n2, no qmap read).
+template <bool EDGE, bool PROBE, bool IDQ>
+__device__ __forceinline__ void p1_item(const float* __restrict__ A, int64_t n, int64_t d,
+                                        int64_t lda, const int8_t* __restrict__ signs, int lb,
+                                        int64_t n2, int64_t n1, int64_t Qmax,
+                                        const int32_t* __restrict__ qmap, float* __restrict__ Z,
+                                        int64_t panel, int64_t tile, const ProbeArgs& pa,
+                                        float4* lds, int32_t* dest, float* sgn, uint8_t* pbit,
+                                        float* bvl, int t) {
   using TT = Tile<float>;
   constexpr int J = TT::J;
-  __shared__ float4 lds[TT::RT * TT::CW / 2];
-  __shared__ int32_t dest[TT::RT];
-  __shared__ float sgn[TT::RT];
-  __shared__ uint8_t pbit[PROBE ? TT::RT : 1];
-  __shared__ float bvl[PROBE ? TT::RT : 1];
-  const int t = threadIdx.x;
   const int c = t & 7;
   const int g = t >> 3;
-  int64_t panel, tloc;
-  p1_work(blockIdx.x, panels, ntiles, pgroup, panel, tloc);
-  const int64_t tile = tile0 + tloc;
   const int64_t row0 = tile * n2;
   const int64_t col0 = (panel * TT::CW + c) * 4;
   // columns past d read column 0 and are zeroed (the last panel only)
@@ -644,7 +636,7 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
   for (int u = 0; u < 4; ++u) {
     const int r = t + 256 * u;
     const int64_t i = row0 + r;
-    qv[u] = qmap[r < n2 ? r : 0];
+    qv[u] = IDQ ? r : qmap[r < n2 ? r : 0];
     sv[u] = signs[(r < n2 && i < n) ? i : 0];
   }
   if constexpr (PROBE) {
@@ -735,6 +727,62 @@ __global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, in
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v[j]), zs,
                                              lane_off + (uint32_t)q * (uint32_t)n1 * 128u, 0, 0);
   }
+}
+
+template <bool EDGE, bool PROBE>
+__global__ __launch_bounds__(256) void k_srht_p1(const float* __restrict__ A, int64_t n,
+                                                 int64_t d, int64_t lda,
+                                                 const int8_t* __restrict__ signs, int lb,
+                                                 int64_t n2, int64_t n1, int64_t Qmax,
+                                                 const int32_t* __restrict__ qmap,
+                                                 float* __restrict__ Z, int64_t tile0,
+                                                 int64_t ntiles, int64_t panels, int pgroup,
+                                                 ProbeArgs pa) {
+  using TT = Tile<float>;
+  __shared__ float4 lds[TT::RT * TT::CW / 2];
+  __shared__ int32_t dest[TT::RT];
+  __shared__ float sgn[TT::RT];
+  __shared__ uint8_t pbit[PROBE ? TT::RT : 1];
+  __shared__ float bvl[PROBE ? TT::RT : 1];
+  int64_t panel, tloc;
+  p1_work(blockIdx.x, panels, ntiles, pgroup, panel, tloc);
+  p1_item<EDGE, PROBE, false>(A, n, d, lda, signs, lb, n2, n1, Qmax, qmap, Z, panel,
+                              tile0 + tloc, pa, lds, dest, sgn, pbit, bvl, (int)threadIdx.x);
+}
+
+// The probe sketch's first pass (with the sums) and, from the same tile read again
+// right after it (then mostly a cache hit, not HBM), the first pass of a second
+// SRHT of the same A with its own signs (pa.signs2) and every low index kept, into
+// pa.Z2 (the layout of a Qmax = n2 intermediate): a pair's features head and its
+// first sketches' transform from one read of A.  Each item is computed exactly as
+// k_srht_p1 computes it.
+template <bool EDGE>
+__global__ __launch_bounds__(256) void k_srht_p1_two(const float* __restrict__ A, int64_t n,
+                                                     int64_t d, int64_t lda,
+                                                     const int8_t* __restrict__ signs, int lb,
+                                                     int64_t n2, int64_t n1, int64_t Qmax,
+                                                     const int32_t* __restrict__ qmap,
+                                                     float* __restrict__ Z, int64_t tile0,
+                                                     int64_t ntiles, int64_t panels, int pgroup,
+                                                     ProbeArgs pa) {
+  using TT = Tile<float>;
+  __shared__ float4 lds[TT::RT * TT::CW / 2];
+  __shared__ int32_t dest[TT::RT];
+  __shared__ float sgn[TT::RT];
+  __shared__ uint8_t pbit[TT::RT];
+  __shared__ float bvl[TT::RT];
+  int64_t panel, tloc;
+  p1_work(blockIdx.x, panels, ntiles, pgroup, panel, tloc);
+  const int64_t tile = tile0 + tloc;
+  p1_item<EDGE, true, false>(A, n, d, lda, signs, lb, n2, n1, Qmax, qmap, Z, panel, tile, pa,
+                             lds, dest, sgn, pbit, bvl, (int)threadIdx.x);
+  __syncthreads();  // the first item's stores have read dest
+  // the thread index through an empty asm: the second item derives its addresses
+  // anew instead of keeping the first item's live across it (they would not fit)
+  int t2 = (int)threadIdx.x;
+  asm volatile("" : "+v"(t2));
+  p1_item<EDGE, false, true>(A, n, d, lda, pa.signs2, lb, n2, n1, n2, nullptr, pa.Z2, panel,
+                             tile, pa, lds, dest, sgn, pbit, bvl, t2);
 }
 
 __device__ __forceinline__ void bfly2(float2& u, float2& v) {
@@ -1016,30 +1064,15 @@ __global__ __launch_bounds__(1024) void k_iota_q(int32_t* __restrict__ qmap,
   if (i == 0) *qcount = n2;
 }
 
-rs_status srht_pass1_full(const SrhtBuffers& B, const float* A, int64_t n, int64_t d, int64_t lda,
-                          int64_t npad, uint64_t seed, uint32_t sid, hipStream_t s) {
+rs_status srht_pass1_prep(const SrhtBuffers& B, int64_t npad, int64_t lda, uint64_t seed,
+                          uint32_t sid, hipStream_t s) {
   if (!srht_panel_path(npad, lda))
     return set_error(RS_ERR_ARG, "srht: the full first pass runs on the panel-major path only");
   const int64_t n2 = npad < 1024 ? npad : 1024;
-  const int64_t n1 = npad / n2;
-  int lb2 = 0;
-  while (((int64_t)1 << lb2) < n2) ++lb2;
   const int hist_grid = (int)std::min<int64_t>((npad + 255) / 256, 1024);
   hipLaunchKernelGGL(k_signs, dim3(hist_grid), dim3(256), 0, s, seed, sid, npad, B.signs);
   hipLaunchKernelGGL(k_iota_q, dim3(1), dim3(1024), 0, s, B.qmap, B.qlist, B.qcount, (int)n2);
-  const int64_t P = (d + 31) / 32;
-  const int64_t full = n2 == 1024 ? std::min<int64_t>(n / 1024, n1) : 0;
-  const ProbeArgs pa{nullptr, nullptr, nullptr, 0};
-  float* Zw = reinterpret_cast<float*>(B.zbuf);
-  if (full > 0)
-    hipLaunchKernelGGL((k_srht_p1<false, false>), dim3((unsigned)(P * full)), dim3(256), 0, s, A,
-                       n, d, lda, B.signs, lb2, n2, n1, n2, B.qmap, Zw, (int64_t)0, full, P,
-                       kP1GroupWrite, pa);
-  if (full < n1)
-    hipLaunchKernelGGL((k_srht_p1<true, false>), dim3((unsigned)(P * (n1 - full))), dim3(256), 0,
-                       s, A, n, d, lda, B.signs, lb2, n2, n1, n2, B.qmap, Zw, full, n1 - full, P,
-                       kP1GroupWrite, pa);
-  return check_launch("srht full first pass");
+  return check_launch("srht full first pass set-up");
 }
 
 size_t srht_state_bytes() { return sizeof(SelectState); }
@@ -1126,7 +1159,7 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
     // floats below 2^31 bytes); its intermediate is never smaller than the old
     // layout's, so wider rows fall back to that form in the same buffer
     if (n1 <= kP2Rows && lda < ((int64_t)1 << 19)) {
-      // pre: pass 1 already ran with every low index kept (srht_pass1_full): its
+      // pre: pass 1 already ran with every low index kept (k_srht_p1_two): its
       // intermediate, q = i2 over all n2 low indices
       // (pass 1 writes Zw only without pre; with it pass 2 only reads)
       float* Zw = reinterpret_cast<float*>(pre ? const_cast<void*>(pre->Z) : B.zbuf);
@@ -1141,6 +1174,14 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
       const ProbeArgs pa = probe ? *probe : ProbeArgs{nullptr, nullptr, nullptr, 0};
       auto p1 = [&](auto edge, auto withp, int64_t t0, int64_t nt) {
         constexpr bool E = decltype(edge)::value, PR = decltype(withp)::value;
+        if constexpr (PR) {
+          if (pa.Z2) {  // the second transform writes an intermediate as large as A
+            hipLaunchKernelGGL((k_srht_p1_two<E>), dim3((unsigned)(P * nt)), dim3(256), 0, s,
+                               Af, n, d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, t0, nt, P,
+                               kP1GroupWrite, pa);
+            return;
+          }
+        }
         hipLaunchKernelGGL((k_srht_p1<E, PR>), dim3((unsigned)(P * nt)), dim3(256), 0, s, Af, n,
                            d, lda, B.signs, lb2, n2, n1, Qmax, B.qmap, Zw, t0, nt, P, kP1Group,
                            pa);

@@ -449,13 +449,14 @@ static rs_status srht_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t
   return RS_OK;
 }
 
-// Pass 1 of the SRHT of (seed, sid) with every low index kept, ahead of any
-// selection, into S's intermediate; *pre then describes it for srht_run (a pair's
-// first sketches: the pass needs only A and the signs, so it can run beside the
-// learned features' pass over A).
-static rs_status srht_pretransform(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
-                                   int64_t d, int64_t lda, uint64_t seed, uint32_t sid,
-                                   hipStream_t s, SrhtPre* pre) {
+// Set-up of the SRHT of (seed, sid) whose first pass, with every low index kept,
+// rides in another job's probe sketch pass (ProbeArgs::signs2 / Z2, *two): its
+// signs and identity lists in S, on stream s; *pre then describes the intermediate
+// for srht_run (a pair's first sketches: that pass needs only A and the signs, so it
+// shares the learned features' read of A).
+static rs_status srht_pretransform(DeviceScratch& S, rs_dtype a_t, int64_t n, int64_t d,
+                                   int64_t lda, uint64_t seed, uint32_t sid, hipStream_t s,
+                                   SrhtPre* pre, ProbeArgs* two) {
   const int64_t npad = next_pow2(n);
   const int64_t n2 = std::min<int64_t>(npad, 1024);
   if (a_t != RS_F32 || !srht_panel_path(npad, lda))
@@ -466,8 +467,10 @@ static rs_status srht_pretransform(DeviceScratch& S, const void* A, rs_dtype a_t
   B.qmap = S.qid.as<int32_t>();
   B.qlist = B.qmap + 1024;
   B.qcount = B.qmap + 2048;
-  RS_TRY(srht_pass1_full(B, reinterpret_cast<const float*>(A), n, d, lda, npad, seed, sid, s));
+  RS_TRY(srht_pass1_prep(B, npad, lda, seed, sid, s));
   *pre = SrhtPre{S.zbuf.p, B.qlist, B.qcount};
+  two->signs2 = B.signs;
+  two->Z2 = reinterpret_cast<float*>(S.zbuf.p);
   return RS_OK;
 }
 
@@ -999,9 +1002,10 @@ static rs_status features_buffers(DeviceScratch& S, rs_dtype a_t, int64_t n, int
 }
 
 // The head; *join: the tail must wait for S.join_ev (the sums on the side stream).
+// two: the first pass of another SRHT to run in the probe sketch's read of A (or null).
 static rs_status features_head(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
                                int64_t d, int64_t lda, const void* b, uint64_t seed,
-                               hipStream_t stream, bool* join) {
+                               hipStream_t stream, bool* join, const ProbeArgs* two = nullptr) {
   const int64_t npad = next_pow2(n);
   const int64_t m0 = features_m0(n);
   const rs_dtype sa_t = a_t == RS_F64 ? RS_F64 : RS_F32;
@@ -1011,6 +1015,7 @@ static rs_status features_head(DeviceScratch& S, const void* A, rs_dtype a_t, in
   // anyway (one read of A for both).  Otherwise a pass of its own on the side
   // stream, beside the sketch.
   const bool fused = a_t == RS_F32 && srht_panel_path(npad, lda);
+  if (two && !fused) return set_error(RS_ERR_ARG, "features: no shared first pass for this shape");
   *join = !fused;
   if (fused) {
     const int64_t ntiles = npad / 1024, dp = (d + 31) / 32 * 32;
@@ -1018,7 +1023,8 @@ static rs_status features_head(DeviceScratch& S, const void* A, rs_dtype a_t, in
     RS_TRY(S.ppart.ensure((size_t)ntiles * kProbeCols * dp * sizeof(double)));
     RS_TRY(probe_bits(seed, n, S.pbits.as<uint8_t>(), stream));
     const ProbeArgs pa{S.pbits.as<uint8_t>(), reinterpret_cast<const float*>(b),
-                       S.ppart.as<double>(), dp};
+                       S.ppart.as<double>(), dp, two ? two->signs2 : nullptr,
+                       two ? two->Z2 : nullptr};
     RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
                     nullptr, nullptr, stream, &pa));
     return probe_tiles_finish(S.ppart.as<double>(), ntiles, d, dp, S.pU.as<double>(), stream);
@@ -1087,10 +1093,10 @@ static rs_status features_tail(DeviceScratch& S, rs_dtype a_t, int64_t n, int64_
 
 static rs_status features_run(DeviceScratch& S, const void* A, rs_dtype a_t, int64_t n,
                               int64_t d, int64_t lda, const void* b, double nu2, uint64_t seed,
-                              float* feat, hipStream_t stream) {
+                              float* feat, hipStream_t stream, const ProbeArgs* two = nullptr) {
   RS_TRY(features_buffers(S, a_t, n, d, stream));
   bool join = false;
-  RS_TRY(features_head(S, A, a_t, n, d, lda, b, seed, stream, &join));
+  RS_TRY(features_head(S, A, a_t, n, d, lda, b, seed, stream, &join, two));
   return features_tail(S, a_t, n, d, nu2, feat, join, stream);
 }
 
@@ -1220,6 +1226,8 @@ struct SolveJob {
   // on the partner's stream after it)
   const DeviceScratch* feat_from = nullptr;
   hipEvent_t feat_wait = nullptr;
+  // a partner's first pass to run in this job's probe sketch pass (or null)
+  const ProbeArgs* feat_two = nullptr;
   // the first sketch shared within a pair (same seed and sketch_id, m2 <= m): the
   // job with the larger m forms both (sa_for: the partner, sa_done: recorded on
   // this stream after the transform); the partner's SA is then given (sa_given,
@@ -1537,7 +1545,7 @@ struct SolveJob {
       RS_TRY(features_tail(*S, a_t, n, d, nu2, S->pfeat.as<float>(), false, stream));
     } else {
       RS_TRY(features_run(*S, A, a_t, n, d, lda, sp ? nullptr : b, nu2, o.seed,
-                          S->pfeat.as<float>(), stream));
+                          S->pfeat.as<float>(), stream, feat_two));
     }
     atb_ready = !sp;
     // the prediction goes straight to pinned host memory
@@ -1910,16 +1918,23 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
   // of nu) from job 0's scratch and finishes them at its own nu
   const bool share_head = J[0]->lp_params && J[1]->lp_params && !J[0]->sp && !J[1]->sp &&
                           J[0]->o.seed == J[1]->o.seed;
-  // and the first sketches' pass 1 (sketch_id 0, every low index kept) runs on job 1's
-  // stream beside job 0's features pass: it needs only A and the signs
+  // and the first sketches' pass 1 (sketch_id 0, every low index kept, into job 1's
+  // scratch) runs in job 0's probe sketch pass: it needs only A and the signs, so one
+  // read of A serves both
   const bool pre_first = share_head && J[0]->srht && J[0]->o.resample == RS_RESAMPLE_FRESH &&
                          J[0]->sid == J[1]->sid && J[0]->sa_t == J[1]->sa_t &&
                          srht_second_ok(J[0]->a_t, J[0]->n, J[0]->lda, J[0]->sa_t);
   SrhtPre pre{};
+  ProbeArgs two{};
   bool pre_ok = false;
-  if (pre_first)
-    pre_ok = srht_pretransform(*J[1]->S, J[1]->A, J[1]->a_t, J[1]->n, J[1]->d, J[1]->lda,
-                               J[1]->o.seed, J[1]->sid, J[1]->stream, &pre) == RS_OK;
+  if (pre_first) {
+    // job 1's scratch is written on job 0's stream: after job 1's earlier work on it
+    pre_ok = hipEventRecord(ev[1], J[1]->stream) == hipSuccess &&
+             hipStreamWaitEvent(J[0]->stream, ev[1], 0) == hipSuccess &&
+             srht_pretransform(*J[1]->S, J[1]->a_t, J[1]->n, J[1]->d, J[1]->lda, J[1]->o.seed,
+                               J[1]->sid, J[0]->stream, &pre, &two) == RS_OK;
+    if (pre_ok) J[0]->feat_two = &two;
+  }
   for (int k = 0; k < 2; ++k) {
     J[k]->defer = true;
     if (k == 1 && share_head && !J[0]->done) {
@@ -1932,6 +1947,7 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
       J[1]->feat_wait = ev[0];
     }
     const rs_status st = J[k]->begin();
+    J[k]->feat_two = nullptr;  // (points into this frame)
     if (st != RS_OK) fail(*J[k], st);
   }
   const int grid = grad_partial_blocks_max(J[0]->n);
@@ -1990,8 +2006,8 @@ static void drive_pair(SolveJob* J[2], hipEvent_t ev[2]) {
       if (J[c]->S->sa.ensure((size_t)mk[c] * J[c]->ldsa * J[c]->sa_es) == RS_OK) {
         J[p]->sa_for = J[c];
         J[p]->sa_m2 = mk[c];
-        // the full first pass ran on job 1's stream, which the host has seen finish
-        // (its prediction came after it)
+        // the full first pass ran in job 0's features pass, which the host has seen
+        // finish (its prediction came after it)
         J[p]->sa_pre = pre_ok ? &pre : nullptr;
         J[p]->sa_done = ev[p];
         J[c]->sa_given = true;

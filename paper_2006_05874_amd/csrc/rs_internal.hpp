@@ -66,6 +66,10 @@ struct ProbeArgs {
   const float* b;       // n values or null
   double* part;         // n1 * kProbeCols * dp
   int64_t dp;           // column pitch of part (d rounded up to 32)
+  // optional: the same read of A also runs the first pass of another SRHT with
+  // these signs and every low index kept, into Z2 (srht_pass1_prep set them up)
+  const int8_t* signs2 = nullptr;
+  float* Z2 = nullptr;
 };
 // Whether srht_transform takes the panel-major two-pass path (the one that can
 // carry ProbeArgs) for FP32 A of padded size npad and leading dimension lda.
@@ -83,7 +87,7 @@ struct SrhtDual {
   int64_t ldsa2;
   double scale2;
 };
-// Pass 1 already run with every low index kept (srht_pass1_full, same seed and
+// Pass 1 already run with every low index kept (k_srht_p1_two, same seed and
 // sketch_id): its intermediate Z (Qmax = n2, q = i2) and the identity list and count
 // it was run with.  The transform then runs the selection's pass 2 only, over every
 // low index (rows outside the selection are not stored).
@@ -98,11 +102,12 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
                          int64_t Qmax, hipStream_t s, double scale_override = 0.0,
                          const ProbeArgs* probe = nullptr, const SrhtDual* dual = nullptr,
                          const SrhtPre* pre = nullptr);
-// Pass 1 of the SRHT of (seed, sid) with every low index kept, before any selection:
-// writes B.signs, an identity B.qmap / B.qlist / B.qcount and the full intermediate
-// in B.zbuf (srht_zbuf_bytes with Qmax = n2).  FP32 A on the panel-major path.
-rs_status srht_pass1_full(const SrhtBuffers& B, const float* A, int64_t n, int64_t d, int64_t lda,
-                          int64_t npad, uint64_t seed, uint32_t sid, hipStream_t s);
+// Set-up of a first pass of the SRHT of (seed, sid) that keeps every low index, run
+// by a probe sketch's pass (ProbeArgs::signs2 = B.signs, Z2 = B.zbuf, which must hold
+// srht_zbuf_bytes with Qmax = n2): writes B.signs and an identity B.qmap / B.qlist /
+// B.qcount.  FP32 A on the panel-major path.
+rs_status srht_pass1_prep(const SrhtBuffers& B, int64_t npad, int64_t lda, uint64_t seed,
+                          uint32_t sid, hipStream_t s);
 rs_status srht_gather(const void* H, rs_dtype h_t, int64_t ldh, const int64_t* rows, int64_t m,
                       int64_t d, double scale, void* SA, rs_dtype sa_t, int64_t ldsa,
                       hipStream_t s);
