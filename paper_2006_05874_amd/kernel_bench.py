@@ -4,6 +4,11 @@ and kernel-trace summaries under profiles/ are taken from).
   python -m paper_2006_05874_amd.kernel_bench gradient --n N --d D --k K --reps R
   python -m paper_2006_05874_amd.kernel_bench srht --n N --d D --m M --sa bf16 --reps R
   python -m paper_2006_05874_amd.kernel_bench gaussian --n N --d D --m M --sa bf16 --reps R
+  python -m paper_2006_05874_amd.kernel_bench pair --n N --d D --reps R
+
+pair: one learned + BF16 batch of two solves on A, b (nu^2 = 1e-2 and 1e-4), which
+runs as a pair: its features pass (k_srht_p1_two) also forms the first sketches'
+first pass; the line gives the whole batch and N D 4 bytes.
 
 A is N x D FP32 with i.i.d. N(0, 1/N) entries and b N(0, 1), drawn on the device
 (the values do not change the traffic of either pass).  Each call is timed by HIP
@@ -23,7 +28,7 @@ from . import rs
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["gradient", "gradient2", "srht", "gaussian"])
+    ap.add_argument("what", choices=["gradient", "gradient2", "srht", "gaussian", "pair"])
     ap.add_argument("--n", type=int, default=1 << 21)
     ap.add_argument("--d", type=int, default=8192)
     ap.add_argument("--k", type=int, default=2)
@@ -62,6 +67,14 @@ def main(argv=None):
             print("plan", rs.rs_gradient_autotune(A, b, k=2), flush=True)
         call = lambda: rs.rs_gradient_two(A, b, (0.01, 0.0001), X0, X1)
         alg = n * d * 4 + n * 4
+    elif a.what == "pair":
+        from . import learned
+        for k in (1, 2):
+            print("plan", k, rs.rs_gradient_autotune(A, b, k=k), flush=True)
+        params, mu, sd, _ = learned.load_model(learned.MODEL_PATH)
+        call = lambda: rs.rs_learned_solve_batch([(A, b, 1e-2), (A, b, 1e-4)], params, mu, sd,
+                                                 sketch_dtype="bf16", workers=2)
+        alg = n * d * 4
     else:
         es = {"f32": 4, "bf16": 2, "fp8": 1}[a.sa]
         sid = [0]
