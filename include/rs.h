@@ -367,8 +367,10 @@ typedef struct rs_problem {
  * pairs when the k = 2 gradient plan of (n, d) is on the 512-thread kernel: one host
  * thread drives both on two worker streams, each step the two jobs have in common
  * takes one gradient pass for both (rs_gradient_two), a learned start forms the
- * features' pass over A once, and the two first sketches come from one transform;
- * the results are those of the jobs alone, bit for bit.  infos: count host records.  Synchronizes.  Returns RS_OK when
+ * features' pass over A once (with learned starts and the SRHT, that pass also runs
+ * the first pass of the two first sketches' transform), and the two first sketches
+ * come from one transform; the results are those of the jobs alone, bit for bit.
+ * infos: count host records.  Synchronizes.  Returns RS_OK when
  * every job ended RS_OK or RS_ERR_NO_CONVERGENCE (see infos[i].status), else the
  * first other error; an argument error in any problem is reported before any
  * work is queued. */
