@@ -135,3 +135,25 @@ def test_no_pair_without_the_two_job_plan(rs):
         same(r, s)
         ls += l
     assert lb == ls
+
+
+def test_learned_pair_with_ragged_columns(rs):
+    # d = 4093: the last 32-column panel of the features pass (probe sums and the first
+    # sketches' pass 1 from one kernel) and of the shared pass 2 is partial; n = 12000
+    # leaves ragged row tiles too
+    from paper_2006_05874_amd import learned as L
+    params, mu, sd, _ = L.load_model()
+    n, d = 12000, 4093
+    A, b = shared_problem(6, n=n, d=d)
+    Ad, bd = upload(A, b, rs)
+    rs.rs_gradient_set_plan("f32", n, d, 2, PLAN)
+    nus = (1e-2, 1e-4)
+    batch, lb = grad_launches(rs, lambda: rs.rs_learned_solve_batch(
+        [(Ad, bd, nu) for nu in nus], params, mu, sd, sketch_dtype="bf16", workers=2))
+    ls = 0
+    for nu, r in zip(nus, batch):
+        s, l = grad_launches(rs, lambda: rs.rs_learned_solve(Ad, bd, nu, params, mu, sd,
+                                                             sketch_dtype="bf16"))
+        same(r, s)
+        ls += l
+    assert lb < ls, (lb, ls)
