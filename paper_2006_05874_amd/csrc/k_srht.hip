@@ -1196,6 +1196,10 @@ rs_status srht_transform(const SrhtBuffers& B, const T* A, int64_t n, int64_t d,
         if (probe) p1(T_{}, T_{}, full, n1 - full);
         else p1(T_{}, F_{}, full, n1 - full);
       }
+      if (probe && pa.p1_done) {
+        const hipError_t e = hipEventRecord(pa.p1_done, s);
+        if (e != hipSuccess) return set_error(RS_ERR_HIP, hipGetErrorString(e));
+      }
       hipLaunchKernelGGL(k_p2_dest, dim3((unsigned)((QM * n1 + 255) / 256)), dim3(256), 0, s,
                          ql, B.kmap, qc, QM, n1, n2, B.dest2);
       // the second sketch's rows among this one's transformed rows (its low indices

@@ -1016,22 +1016,27 @@ static rs_status features_head(DeviceScratch& S, const void* A, rs_dtype a_t, in
   // stream, beside the sketch.
   const bool fused = a_t == RS_F32 && srht_panel_path(npad, lda);
   if (two && !fused) return set_error(RS_ERR_ARG, "features: no shared first pass for this shape");
-  *join = !fused;
+  *join = true;  // either way the side stream finishes the sums
+  RS_TRY(S.ensure_aux());
   if (fused) {
     const int64_t ntiles = npad / 1024, dp = (d + 31) / 32 * 32;
     RS_TRY(S.pbits.ensure((size_t)n));
     RS_TRY(S.ppart.ensure((size_t)ntiles * kProbeCols * dp * sizeof(double)));
     RS_TRY(probe_bits(seed, n, S.pbits.as<uint8_t>(), stream));
+    // the per-tile sums are complete after the first pass: the side stream adds them
+    // up while the probe sketch's second pass runs
     const ProbeArgs pa{S.pbits.as<uint8_t>(), reinterpret_cast<const float*>(b),
                        S.ppart.as<double>(), dp, two ? two->signs2 : nullptr,
-                       two ? two->Z2 : nullptr};
+                       two ? two->Z2 : nullptr, S.fork_ev};
     RS_TRY(srht_run(S, A, a_t, n, d, lda, m0, seed, 0x7FFF0000u, S.psa.p, sa_t, d, nullptr,
                     nullptr, nullptr, stream, &pa));
-    return probe_tiles_finish(S.ppart.as<double>(), ntiles, d, dp, S.pU.as<double>(), stream);
+    RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
+    RS_TRY(probe_tiles_finish(S.ppart.as<double>(), ntiles, d, dp, S.pU.as<double>(), S.aux));
+    RS_HIP(hipEventRecord(S.join_ev, S.aux));
+    return RS_OK;
   }
   const int nch = feature_chunks(n, d, a_t == RS_F32 ? 4 : 2);
   RS_TRY(S.ppart.ensure((size_t)nch * (kFeatAtbCol + 1) * d * sizeof(double)));
-  RS_TRY(S.ensure_aux());
   RS_HIP(hipEventRecord(S.fork_ev, stream));
   RS_HIP(hipStreamWaitEvent(S.aux, S.fork_ev, 0));
   if (a_t == RS_F32)

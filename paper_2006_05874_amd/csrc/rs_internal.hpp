@@ -70,6 +70,9 @@ struct ProbeArgs {
   // these signs and every low index kept, into Z2 (srht_pass1_prep set them up)
   const int8_t* signs2 = nullptr;
   float* Z2 = nullptr;
+  // optional: recorded on the stream right after the first pass (the sums are then
+  // complete and can be finished beside the second pass)
+  hipEvent_t p1_done = nullptr;
 };
 // Whether srht_transform takes the panel-major two-pass path (the one that can
 // carry ProbeArgs) for FP32 A of padded size npad and leading dimension lda.
