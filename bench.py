@@ -204,7 +204,7 @@ def cpu_baseline(A, b):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "c3":
         return run_c3(args)

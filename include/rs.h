@@ -46,7 +46,7 @@ typedef enum {
   RS_ERR_NO_CONVERGENCE = 6,  /* tolerance not met within max_iter, or stuck at m_max */
   RS_ERR_OOM = 7,
   RS_ERR_HIP = 8,             /* a HIP runtime call failed */
-  RS_ERR_UNSUPPORTED = 9      /* valid request outside what this build implements */
+  RS_ERR_UNSUPPORTED = 9      /* valid request outside what the library implements */
 } rs_status;
 
 typedef enum { RS_F64 = 0, RS_F32 = 1, RS_BF16 = 2, RS_FP8E4M3 = 3 } rs_dtype;

@@ -842,7 +842,7 @@ rs_status gradient_launch(const T* A, int64_t n, int64_t d, int64_t lda, const T
                           const int* status, hipStream_t s, const double* c, bool prof) {
   if (k < 1 || k > 4) return set_error(RS_ERR_ARG, "gradient: k must be in 1..4");
   GradPlan pl = grad_plan<T>(n, d, k);
-  if (pl.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d too large for this build");
+  if (pl.tpr == 0) return set_error(RS_ERR_UNSUPPORTED, "gradient: d above the widest gradient kernel");
   if (pl.grid > grid_cap) pl.grid = grid_cap;
   if (!launch_plan<T>(pl, A, n, d, lda, b, X, k, partial, status, s, prof)) {
     // a plan this call cannot use (e.g. the wide kernel's 32-bit row offsets for a
@@ -914,7 +914,7 @@ rs_status gradient_autotune(const T* A, int64_t n, int64_t d, int64_t lda, const
       if (!dup) cand.push_back(GradPlan{sh.tpr, sh.nv, g, sh.r});
     }
   }
-  if (cand.empty()) return set_error(RS_ERR_UNSUPPORTED, "autotune: d too large for this build");
+  if (cand.empty()) return set_error(RS_ERR_UNSUPPORTED, "autotune: d above the widest gradient kernel");
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return set_error(RS_ERR_HIP, "autotune: event creation failed");
